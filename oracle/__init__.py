@@ -1,0 +1,314 @@
+"""FP64 CPU reference for the gas-kinetic scheme -- test infrastructure only.
+
+This package wraps ``gks_oracle.c``, a plain single-threaded FP64 C
+implementation of the third-order WENO gas-kinetic scheme written from the
+paper (Yang, Pan & Xu, arXiv 2203.09047).  Only the test suite, the smoke check
+and the CPU-baseline leg of the benchmark may import it; the GPU library never
+does, and the two share no code.  Inputs come from the seeded generators in
+``paper_2203_09047_amd.inputs``, which hold none of the method's arithmetic.
+
+Parity unpinned (readings only, checked by oracle == GPU under a shared
+reading): the ring rule of enlarged sub-stencils when a neighbour is not a
+tetrahedron, the rank fallback of the least-squares fits, the nonlinear-weight
+exponent and epsilon, the time-step formula, the Prandtl-number fix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCE = os.path.join(_HERE, "gks_oracle.c")
+LIB_PATH = os.path.join(_HERE, "libgks_oracle.so")
+
+_lib = None
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (no fast-math, FP64)."""
+    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", "-o", LIB_PATH,
+           SOURCE, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    return LIB_PATH
+
+
+class Params(ctypes.Structure):
+    """Scheme parameters (gamma, CFL, viscosity, Prandtl number, WENO and collision-time constants)."""
+
+    _fields_ = [
+        ("gamma", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("Pr", ctypes.c_double),
+        ("weno_eps", ctypes.c_double),
+        ("weno_gamma_m", ctypes.c_double),
+        ("weno_p", ctypes.c_double),
+        ("tau_eps", ctypes.c_double),
+        ("tau_C", ctypes.c_double),
+        ("viscous", ctypes.c_int),
+        ("force_linear", ctypes.c_int),
+    ]
+
+
+def params(gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, weno_eps=1e-6, weno_gamma_m=0.0125, weno_p=1.0, tau_eps=0.01,
+           tau_C=1.0, viscous=False, force_linear=False) -> Params:
+    return Params(gamma, cfl, mu, Pr, weno_eps, weno_gamma_m, weno_p, tau_eps, tau_C, int(viscous), int(force_linear))
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+OP_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SOURCE):
+            build()
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, dbl, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+        pp = ctypes.POINTER(Params)
+        lib.orc_create.argtypes = [i64, vp, i64, vp, vp, vp, i32]
+        lib.orc_create.restype = vp
+        lib.orc_destroy.argtypes = [vp]
+        lib.orc_last_error.restype = ctypes.c_char_p
+        lib.orc_n_faces.argtypes = [vp]
+        lib.orc_n_faces.restype = i64
+        lib.orc_cell_geometry.argtypes = [vp, vp, vp, vp, vp]
+        lib.orc_face_info.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        lib.orc_stencil_info.argtypes = [vp, i64, vp, vp, vp]
+        lib.orc_weno_eval.argtypes = [vp, pp, vp, i64, i32, vp, vp, vp]
+        lib.orc_weno_weights.argtypes = [vp, pp, vp, i64, vp]
+        lib.orc_gp_flux.argtypes = [pp, vp, vp, vp, vp, dbl, vp, vp]
+        lib.orc_gp_flux.restype = i32
+        lib.orc_face_flux.argtypes = [vp, pp, vp, dbl, vp]
+        lib.orc_face_flux.restype = i32
+        lib.orc_residual.argtypes = [vp, pp, vp, dbl, vp, vp]
+        lib.orc_residual.restype = i32
+        lib.orc_timestep.argtypes = [vp, pp, vp]
+        lib.orc_timestep.restype = dbl
+        lib.orc_s2o4.argtypes = [i64, vp, dbl, OP_CB, vp]
+        lib.orc_s2o4.restype = i32
+        lib.orc_step.argtypes = [vp, pp, vp, dbl]
+        lib.orc_step.restype = i32
+        lib.orc_run.argtypes = [vp, pp, vp, i32, dbl, dbl, vp, vp, vp]
+        lib.orc_run.restype = i32
+        lib.orc_cell_moments_raw.argtypes = [i32, vp, vp, vp, vp]
+        lib.orc_face_gauss_raw.argtypes = [vp, vp, vp]
+        lib.orc_maxwell_moments.argtypes = [dbl, dbl, dbl, vp, vp, vp, vp]
+        lib.orc_stencil_members.argtypes = [vp, i64, vp, vp]
+        lib.orc_stencil_members.restype = i32
+        lib.orc_substencil_members.argtypes = [vp, i64, i32, vp, vp]
+        lib.orc_substencil_members.restype = i32
+        lib.orc_cell_faces.argtypes = [vp, i64, vp, vp]
+        lib.orc_cell_faces.restype = i32
+        lib.orc_stencil_grown.argtypes = [vp, i64]
+        lib.orc_stencil_grown.restype = i32
+        _lib = lib
+    return _lib
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class Oracle:
+    """Reference solver on one mesh (mesh records as produced by the input generators)."""
+
+    def __init__(self, mesh, prm: Params | None = None):
+        lib = _load()
+        self.mesh = mesh
+        self.n = mesh.n_cells
+        self.P = prm if prm is not None else params()
+        self._nodes = np.ascontiguousarray(mesh.nodes, np.float64)
+        self._types = np.ascontiguousarray(mesh.types, np.int8)
+        self._cells = np.ascontiguousarray(mesh.cells, np.int64)
+        box = np.asarray(mesh.box, np.float64)
+        h = lib.orc_create(self._nodes.shape[0], _p(self._nodes), self.n, _p(self._types), _p(self._cells), _p(box),
+                           int(mesh.periodic))
+        if not h:
+            raise OracleError(lib.orc_last_error().decode())
+        self.h = h
+        self.n_faces = int(lib.orc_n_faces(h))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _load().orc_destroy(self.h)
+            self.h = None
+
+    # geometry -----------------------------------------------------------
+    def cell_geometry(self):
+        vol = np.zeros(self.n)
+        xc = np.zeros((self.n, 3))
+        m2 = np.zeros((self.n, 6))
+        area = np.zeros(self.n)
+        _load().orc_cell_geometry(self.h, _p(vol), _p(xc), _p(m2), _p(area))
+        return vol, xc, m2, area
+
+    def face_info(self):
+        F = self.n_faces
+        owner = np.zeros(F, np.int64)
+        nbr = np.zeros(F, np.int64)
+        key = np.zeros((F, 4), np.int64)
+        gp = np.zeros((F, 4, 3))
+        va = np.zeros((F, 4, 3))
+        sh = np.zeros((F, 3), np.int32)
+        _load().orc_face_info(self.h, _p(owner), _p(nbr), _p(key), _p(gp), _p(va), _p(sh))
+        return dict(owner=owner, nbr=nbr, key=key, gp=gp, va=va, sh=sh)
+
+    def stencil(self, c):
+        ids = np.zeros(96, np.int64)
+        sh = np.zeros((96, 3), np.int32)
+        k = _load().orc_stencil_members(self.h, c, _p(ids), _p(sh))
+        return ids[:k].copy(), sh[:k].copy()
+
+    def substencil(self, c, m):
+        ids = np.zeros(16, np.int64)
+        sh = np.zeros((16, 3), np.int32)
+        k = _load().orc_substencil_members(self.h, c, m, _p(ids), _p(sh))
+        return ids[:k].copy(), sh[:k].copy()
+
+    def stencil_sizes(self, c):
+        K = ctypes.c_int()
+        M = ctypes.c_int()
+        subn = np.zeros(8, np.int32)
+        _load().orc_stencil_info(self.h, c, ctypes.byref(K), ctypes.byref(M), _p(subn))
+        return K.value, M.value, subn[:M.value].copy()
+
+    def grown(self, c):
+        """Members appended to cell c's stencils to make the fits well posed."""
+        return int(_load().orc_stencil_grown(self.h, c))
+
+    def cell_faces(self, c):
+        faces = np.zeros(6, np.int64)
+        side = np.zeros(6, np.int32)
+        k = _load().orc_cell_faces(self.h, c, _p(faces), _p(side))
+        return faces[:k].copy(), side[:k].copy()
+
+    # reconstruction -----------------------------------------------------
+    def weno_eval(self, Q, c, x, m=-1):
+        """Value [5] and gradient [5,3] at x of Eq. weno (m=-1) or of candidate polynomial P_m."""
+        Q = np.ascontiguousarray(Q, np.float64)
+        x = np.ascontiguousarray(x, np.float64)
+        val = np.zeros(5)
+        grad = np.zeros((5, 3))
+        _load().orc_weno_eval(self.h, ctypes.byref(self.P), _p(Q), c, m, _p(x), _p(val), _p(grad))
+        return val, grad
+
+    def weno_weights(self, Q, c):
+        Q = np.ascontiguousarray(Q, np.float64)
+        w = np.zeros((5, 9))
+        _load().orc_weno_weights(self.h, ctypes.byref(self.P), _p(Q), c, _p(w))
+        return w
+
+    # operators ----------------------------------------------------------
+    def face_flux(self, Q, dt):
+        """Area-integrated (Fbar0, Fbar1) per face, [F, 10], oriented owner -> neighbour."""
+        Q = np.ascontiguousarray(Q, np.float64)
+        out = np.zeros((self.n_faces, 10))
+        e = _load().orc_face_flux(self.h, ctypes.byref(self.P), _p(Q), dt, _p(out))
+        if e:
+            raise OracleError(f"non-physical state in flux (code {e})")
+        return out
+
+    def residual(self, Q, dt):
+        Q = np.ascontiguousarray(Q, np.float64)
+        L = np.zeros((5, self.n))
+        D = np.zeros((5, self.n))
+        e = _load().orc_residual(self.h, ctypes.byref(self.P), _p(Q), dt, _p(L), _p(D))
+        if e:
+            raise OracleError(f"non-physical state in flux (code {e})")
+        return L, D
+
+    def timestep(self, Q):
+        Q = np.ascontiguousarray(Q, np.float64)
+        return float(_load().orc_timestep(self.h, ctypes.byref(self.P), _p(Q)))
+
+    def step(self, Q, dt):
+        Q = np.array(Q, np.float64, copy=True, order="C")
+        e = _load().orc_step(self.h, ctypes.byref(self.P), _p(Q), dt)
+        if e:
+            raise OracleError(f"step failed (code {e})")
+        return Q
+
+    def run(self, Q, nsteps=0, t_end=0.0, dt_fixed=0.0):
+        """Advance; returns (Q, dts)."""
+        Q = np.array(Q, np.float64, copy=True, order="C")
+        cap = max(nsteps, 1) if t_end <= 0 else 100000
+        dts = np.zeros(cap)
+        k = ctypes.c_int()
+        t = ctypes.c_double()
+        e = _load().orc_run(self.h, ctypes.byref(self.P), _p(Q), nsteps, t_end, dt_fixed, _p(dts), ctypes.byref(k),
+                            ctypes.byref(t))
+        if e:
+            raise OracleError(f"run failed (code {e})")
+        return Q, dts[:k.value].copy()
+
+
+# ---------------------------------------------------------------------------
+# raw helpers for the pin tests
+# ---------------------------------------------------------------------------
+def cell_moments(cell_type: int, verts: np.ndarray):
+    v = np.zeros((8, 3))
+    v[: len(verts)] = verts
+    vol = ctypes.c_double()
+    xc = np.zeros(3)
+    m2 = np.zeros(6)
+    _load().orc_cell_moments_raw(cell_type, _p(v), ctypes.byref(vol), _p(xc), _p(m2))
+    return vol.value, xc, m2
+
+
+def face_gauss(quad: np.ndarray):
+    q = np.ascontiguousarray(quad, np.float64)
+    gp = np.zeros((4, 3))
+    va = np.zeros((4, 3))
+    _load().orc_face_gauss_raw(_p(q), _p(gp), _p(va))
+    return gp, va
+
+
+def maxwell_moments(U, lam, K):
+    full = np.zeros(14)
+    pos = np.zeros(14)
+    neg = np.zeros(14)
+    s = np.zeros(6)
+    _load().orc_maxwell_moments(U, lam, K, _p(full), _p(pos), _p(neg), _p(s))
+    return full, pos, neg, s
+
+
+def gp_flux(prm: Params, ql, dql, qr, dqr, dt):
+    """Single Gauss-point flux in the local frame: returns (Fbar [10], debug [80])."""
+    ql, qr = np.ascontiguousarray(ql, np.float64), np.ascontiguousarray(qr, np.float64)
+    dql, dqr = np.ascontiguousarray(dql, np.float64), np.ascontiguousarray(dqr, np.float64)
+    out = np.zeros(10)
+    dbg = np.zeros(80)
+    e = _load().orc_gp_flux(ctypes.byref(prm), _p(ql), _p(dql), _p(qr), _p(dqr), dt, _p(out), _p(dbg))
+    if e:
+        raise OracleError(f"gp flux failed (code {e})")
+    return out, dbg
+
+
+def s2o4(Q: np.ndarray, dt: float, op) -> np.ndarray:
+    """Generic two-stage fourth-order step with a Python operator op(Q) -> (L, dL)."""
+    Q = np.array(Q, np.float64, copy=True)
+    n = Q.size
+
+    def cb(ctx, q, L, D):
+        qa = np.ctypeslib.as_array(q, shape=(n,))
+        l, d = op(qa.copy())
+        np.ctypeslib.as_array(L, shape=(n,))[:] = l
+        np.ctypeslib.as_array(D, shape=(n,))[:] = d
+        return 0
+
+    f = OP_CB(cb)
+    e = _load().orc_s2o4(n, _p(Q), dt, f, None)
+    if e:
+        raise OracleError("s2o4 failed")
+    return Q

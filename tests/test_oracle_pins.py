@@ -1,0 +1,614 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks one part of the oracle against something other than itself:
+closed forms, exact reproduction properties, brute-force quadrature of the
+kinetic moments, symmetries of the flux, the exact Taylor polynomial of the
+two-stage fourth-order step, free-stream preservation, conservation, the
+convergence order and the paper's own accuracy table.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_09047_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TET, PYR, PRISM, HEX = 0, 1, 2, 3
+
+# tetrahedral splits (local vertex slots) of the flat-faced element types
+SPLITS = {
+    TET: [(0, 1, 2, 3)],
+    PYR: [(0, 1, 2, 4), (0, 2, 3, 4)],
+    PRISM: [(0, 1, 2, 3), (1, 2, 3, 4), (2, 3, 4, 5)],
+    HEX: [(0, 1, 2, 4), (1, 2, 4, 5), (2, 4, 5, 6), (0, 2, 3, 4), (2, 3, 4, 6), (3, 4, 6, 7)],
+}
+NV = {TET: 4, PYR: 5, PRISM: 6, HEX: 8}
+
+
+def tet_integrals(v):
+    """Volume, first and second moments of a tetrahedron from the vertex closed forms."""
+    v = np.asarray(v, float)
+    vol = abs(np.linalg.det(np.stack([v[1] - v[0], v[2] - v[0], v[3] - v[0]]))) / 6.0
+    s = v.sum(axis=0)
+    first = vol * s / 4.0
+    second = vol / 20.0 * (v.T @ v + np.outer(s, s))
+    return vol, first, second
+
+
+def flat_cell_integrals(ctype, verts):
+    vol, first, second = 0.0, np.zeros(3), np.zeros((3, 3))
+    for t in SPLITS[ctype]:
+        a, b, c = tet_integrals([verts[i] for i in t])
+        vol += a
+        first += b
+        second += c
+    return vol, first, second
+
+
+def m2_matrix(m2):
+    return np.array([[m2[0], m2[1], m2[2]], [m2[1], m2[3], m2[4]], [m2[2], m2[4], m2[5]]])
+
+
+REF = {
+    TET: np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float),
+    PYR: np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0], [0.5, 0.5, 1]], float),
+    PRISM: np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 0, 1], [0, 1, 1]], float),
+    HEX: np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0], [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]], float),
+}
+
+
+# ---------------------------------------------------------------------------
+# geometry: 3x3x3 Gauss on the trilinear map (Section 2, Eq. trilinear)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("ctype", [TET, PYR, PRISM, HEX])
+def test_cell_moments_affine_images(ctype):
+    rng = np.random.default_rng(11 + ctype)
+    for _ in range(5):
+        A = np.eye(3) + 0.3 * rng.standard_normal((3, 3))
+        if np.linalg.det(A) < 0:
+            A[:, 0] *= -1
+        b = rng.standard_normal(3)
+        verts = REF[ctype] @ A.T + b
+        vol, xc, m2 = oracle.cell_moments(ctype, verts)
+        V, first, second = flat_cell_integrals(ctype, verts)
+        assert vol == pytest.approx(V, rel=1e-13)
+        np.testing.assert_allclose(xc, first / V, rtol=0, atol=1e-13)
+        central = second / V - np.outer(first / V, first / V)
+        np.testing.assert_allclose(m2_matrix(m2), central, rtol=0, atol=1e-13)
+
+
+def test_cell_moments_truncated_pyramid_hex():
+    """A flat-faced but non-affine hexahedron (frustum): the trilinear map is exact for it."""
+    bot = np.array([[0, 0, 0], [2, 0, 0], [2, 2, 0], [0, 2, 0]], float)
+    top = np.array([[0.5, 0.5, 1], [1.5, 0.5, 1], [1.5, 1.5, 1], [0.5, 1.5, 1]], float)
+    verts = np.vstack([bot, top])
+    vol, xc, m2 = oracle.cell_moments(HEX, verts)
+    # frustum volume h/3 (A1 + A2 + sqrt(A1 A2))
+    assert vol == pytest.approx((4 + 1 + 2) / 3.0, rel=1e-14)
+    V, first, second = flat_cell_integrals(HEX, verts)
+    np.testing.assert_allclose(xc, first / V, atol=1e-14)
+    np.testing.assert_allclose(m2_matrix(m2), second / V - np.outer(first / V, first / V), atol=1e-14)
+
+
+def test_pyramid_volume_base_height():
+    verts = np.array([[0, 0, 0], [3, 0, 0], [3, 2, 0], [0, 2, 0], [0.7, 1.9, 1.5]], float)
+    vol, xc, _ = oracle.cell_moments(PYR, verts)
+    assert vol == pytest.approx(3 * 2 * 1.5 / 3, rel=1e-14)
+    assert xc[2] == pytest.approx(1.5 / 4, rel=1e-14)
+
+
+@pytest.mark.parametrize("kind", ["hex", "tet", "pyr", "prism", "hybrid"])
+def test_mesh_volumes_tile_the_box(kind):
+    m = inputs.lattice(3 if kind != "hybrid" else 4, kind)
+    o = oracle.Oracle(m)
+    vol, xc, m2, area = o.cell_geometry()
+    assert vol.sum() == pytest.approx(1.0, rel=1e-14)
+    assert (vol > 0).all()
+    for c in range(m.n_cells):
+        V, first, second = flat_cell_integrals(int(m.types[c]), m.nodes[m.cells[c][: NV[int(m.types[c])]]])
+        assert vol[c] == pytest.approx(V, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# face quadrature (Eq. flux-qud)
+# ---------------------------------------------------------------------------
+def test_face_gauss_planar_quad_and_triangle():
+    quad = np.array([[0, 0, 0], [2, 0, 0], [2.5, 1, 0], [-0.5, 1.5, 0]], float)
+    gp, va = oracle.face_gauss(quad)
+    shoelace = 0.5 * abs(sum(quad[i, 0] * quad[(i + 1) % 4, 1] - quad[(i + 1) % 4, 0] * quad[i, 1] for i in range(4)))
+    assert np.linalg.norm(va, axis=1).sum() == pytest.approx(shoelace, rel=1e-14)
+    assert np.allclose(gp[:, 2], 0)
+    tri = np.array([[0, 0, 0], [1, 0, 0], [0.2, 0.9, 0], [0.2, 0.9, 0]], float)
+    gp, va = oracle.face_gauss(tri)
+    assert np.linalg.norm(va, axis=1).sum() == pytest.approx(0.5 * 0.9, rel=1e-14)
+    # 2x2 Gauss is exact for the linear function x over the triangle: centroid x = 0.4
+    w = np.linalg.norm(va, axis=1)
+    assert (w * gp[:, 0]).sum() / w.sum() == pytest.approx(0.4, rel=1e-14)
+
+
+def test_face_gauss_nonplanar_quad_quadratic_exact():
+    """The 2x2 rule on [-1/2,1/2]^2 integrates the bilinear area element times a linear function exactly."""
+    quad = np.array([[0, 0, 0], [1, 0, 0.2], [1, 1, 0], [0, 1, 0.3]], float)
+    gp, va = oracle.face_gauss(quad)
+    # brute force with a fine midpoint rule on the bilinear patch
+    n = 400
+    s = (np.arange(n) + 0.5) / n - 0.5
+    E, Z = np.meshgrid(s, s, indexing="ij")
+    f = lambda e, z: (quad[0] * ((0.5 - e) * (0.5 - z))[..., None] + quad[1] * ((0.5 + e) * (0.5 - z))[..., None]
+                      + quad[2] * ((0.5 + e) * (0.5 + z))[..., None] + quad[3] * ((0.5 - e) * (0.5 + z))[..., None])
+    Xe = (-quad[0][None, None] * (0.5 - Z)[..., None] + quad[1] * (0.5 - Z)[..., None] + quad[2] * (0.5 + Z)[..., None]
+          - quad[3] * (0.5 + Z)[..., None])
+    Xz = (-quad[0] * (0.5 - E)[..., None] - quad[1] * (0.5 + E)[..., None] + quad[2] * (0.5 + E)[..., None]
+          + quad[3] * (0.5 - E)[..., None])
+    cr = np.cross(Xe, Xz)
+    vec_area = cr.sum(axis=(0, 1)) / n / n
+    np.testing.assert_allclose(va.sum(axis=0), vec_area, rtol=1e-10, atol=1e-12)
+    # every Gauss point lies on the patch
+    X = f(E, Z)
+    for k in range(4):
+        assert np.min(np.linalg.norm(X - gp[k], axis=-1)) < 2e-3
+
+
+@pytest.mark.parametrize("kind", ["hex", "tet", "pyr", "prism", "hybrid"])
+def test_closed_cells_vector_area_sums_to_zero(kind):
+    m = inputs.lattice(3, kind)
+    o = oracle.Oracle(m)
+    fi = o.face_info()
+    for c in range(m.n_cells):
+        faces, side = o.cell_faces(c)
+        s = np.zeros(3)
+        for f, sd in zip(faces, side):
+            s += (1 if sd == 0 else -1) * fi["va"][f].sum(axis=0)
+        assert np.abs(s).max() < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# stencils (Section 2)
+# ---------------------------------------------------------------------------
+def test_hex_stencil_and_substencils_follow_face_labels():
+    m = inputs.lattice(5, "hex")
+    o = oracle.Oracle(m)
+    vol, xc, _, _ = o.cell_geometry()
+    c = 62  # any cell: the mesh is periodic
+    ids, sh = o.stencil(c)
+    assert len(ids) == 24
+    L = np.array(m.box)
+    off = xc[ids] + sh * L - xc[c]
+    steps = np.round(off * 5).astype(int)
+    assert sorted(np.abs(steps).sum(axis=1).tolist()) == [1] * 6 + [2] * 18
+    # hexahedron faces: F1 bottom (-z), F2 (-y), F3 (+x), F4 (+y), F5 (-x), F6 top (+z)
+    dirs = {1: (0, 0, -1), 2: (0, -1, 0), 3: (1, 0, 0), 4: (0, 1, 0), 5: (-1, 0, 0), 6: (0, 0, 1)}
+    table = [(1, 2, 3), (1, 3, 4), (1, 4, 5), (1, 5, 2), (6, 2, 3), (6, 3, 4), (6, 4, 5), (6, 5, 2)]
+    for mm, labs in enumerate(table):
+        sid, ssh = o.substencil(c, mm)
+        got = sorted(tuple(np.round((xc[s] + h * L - xc[c]) * 5).astype(int)) for s, h in zip(sid, ssh))
+        assert got == sorted(dirs[l] for l in labs)
+
+
+def test_tet_substencils_have_three_neighbours_and_one_ring():
+    m = inputs.lattice(3, "tet")
+    o = oracle.Oracle(m)
+    for c in range(0, m.n_cells, 7):
+        K, M, subn = o.stencil_sizes(c)
+        assert M == 4
+        faces, _ = o.cell_faces(c)
+        for mm in range(4):
+            sid, _ = o.substencil(c, mm)
+            assert len(sid) == 6  # three neighbours + the three other neighbours of one of them
+            assert c not in sid.tolist()
+
+
+# ---------------------------------------------------------------------------
+# reconstruction (Section 2, Eq. weno, Eq. indicator)
+# ---------------------------------------------------------------------------
+def _interior_cells(o, lo=0.3, hi=0.7):
+    _, xc, _, _ = o.cell_geometry()
+    return [c for c in range(len(xc)) if np.all(xc[c] > lo) and np.all(xc[c] < hi)]
+
+
+def _quadratic_averages(m, coef):
+    """Cell averages of q(x) = c0 + g.x + x^T H x from tetrahedral closed forms (no oracle geometry)."""
+    c0, g, H = coef
+    out = np.zeros(m.n_cells)
+    for c in range(m.n_cells):
+        t = int(m.types[c])
+        V, first, second = flat_cell_integrals(t, m.nodes[m.cells[c][: NV[t]]])
+        out[c] = c0 + g @ first / V + np.sum(H * second) / V
+    return out
+
+
+@pytest.mark.parametrize("kind", ["hex", "tet", "pyr", "prism", "hybrid"])
+def test_linear_fields_reproduced_by_every_polynomial(kind):
+    m = inputs.lattice(8 if kind == "hybrid" else 6, kind)
+    o = oracle.Oracle(m)
+    g = np.array([0.3, -0.7, 0.45])
+    q = _quadratic_averages(m, (2.0, g, np.zeros((3, 3))))
+    Q = np.vstack([q, 2 * q, -q, 0.5 * q, 3 * q])
+    scale = np.array([1, 2, -1, 0.5, 3])
+    rng = np.random.default_rng(3)
+    cells = _interior_cells(o)
+    assert cells
+    vol, xc, _, _ = o.cell_geometry()
+    for c in cells[:: max(1, len(cells) // 25)]:
+        K, M, _ = o.stencil_sizes(c)
+        x = xc[c] + 0.02 * rng.standard_normal(3)
+        exact = 2.0 + g @ x
+        for mm in range(-1, M + 1):
+            val, grad = o.weno_eval(Q, c, x, mm)
+            np.testing.assert_allclose(val, scale * exact, rtol=1e-12, atol=1e-12)
+            np.testing.assert_allclose(grad, np.outer(scale, g), rtol=1e-10, atol=1e-11)
+        w = o.weno_weights(Q, c)
+        lin = np.r_[1 - 0.0125 * M, np.full(M, 0.0125)]
+        np.testing.assert_allclose(w[:, : M + 1], np.tile(lin, (5, 1)), rtol=1e-6)
+
+
+@pytest.mark.parametrize("kind", ["hex", "tet", "hybrid"])
+def test_quadratic_fields_reproduced_by_big_stencil(kind):
+    m = inputs.lattice(8, kind)
+    o = oracle.Oracle(m, oracle.params(force_linear=True))
+    g = np.array([0.3, -0.7, 0.45])
+    H = np.array([[1.0, 0.2, -0.3], [0.2, -0.5, 0.4], [-0.3, 0.4, 0.8]])
+    q = _quadratic_averages(m, (1.5, g, H))
+    Q = np.vstack([q, q, q, q, q])
+    rng = np.random.default_rng(5)
+    _, xc, _, _ = o.cell_geometry()
+    cells = _interior_cells(o)
+    for c in cells[:: max(1, len(cells) // 20)]:
+        x = xc[c] + 0.03 * rng.standard_normal(3)
+        exact = 1.5 + g @ x + x @ H @ x
+        for mm in (0, -1):  # P_0 alone, and Eq. weno with linear weights
+            val, grad = o.weno_eval(Q, c, x, mm)
+            np.testing.assert_allclose(val, exact, rtol=1e-11)
+            np.testing.assert_allclose(grad, np.tile(g + 2 * H @ x, (5, 1)), rtol=1e-9, atol=1e-10)
+
+
+def _tet_quadrature_points(verts, ctype):
+    """Degree-2 exact points/weights on a flat-faced cell via its tetrahedral split."""
+    a, b = 0.5854101966249685, 0.1381966011250105
+    bary = np.array([[a, b, b, b], [b, a, b, b], [b, b, a, b], [b, b, b, a]])
+    pts, wts = [], []
+    for t in SPLITS[ctype]:
+        v = verts[list(t)]
+        vol = abs(np.linalg.det(np.stack([v[1] - v[0], v[2] - v[0], v[3] - v[0]]))) / 6
+        pts.append(bary @ v)
+        wts.append(np.full(4, vol / 4))
+    return np.vstack(pts), np.concatenate(wts)
+
+
+def test_smoothness_indicators_and_weights_by_brute_force():
+    """beta_m from direct quadrature of (d^l P_m)^2 over the cell (Eq. indicator), then the weights."""
+    m = inputs.lattice(8, "hybrid")
+    o = oracle.Oracle(m)
+    Q = inputs.cell_averages(m, inputs.riemann(normal=(1.0, 0.3, 0.2), c=0.6))
+    Q += 0.05 * inputs.cell_averages(m, inputs.wave())
+    vol, xc, _, _ = o.cell_geometry()
+    checked = 0
+    for c in range(0, m.n_cells, 97):
+        t = int(m.types[c])
+        K, M, _ = o.stencil_sizes(c)
+        pts, wts = _tet_quadrature_points(m.nodes[m.cells[c][: NV[t]]], t)
+        V = vol[c]
+        betas = []
+        for mm in range(0, M + 1):
+            b = np.zeros(5)
+            for p, wq in zip(pts, wts):
+                _, gr = o.weno_eval(Q, c, p, mm)
+                b += wq * (gr ** 2).sum(axis=1) * V ** (2 / 3 - 1)
+            if mm == 0:
+                # second derivatives are constant: difference the (linear) gradient
+                h = 1e-3 * V ** (1 / 3)
+                sec = np.zeros(5)
+                for d in range(3):
+                    e = np.zeros(3)
+                    e[d] = h
+                    _, gp = o.weno_eval(Q, c, xc[c] + e, 0)
+                    _, gm = o.weno_eval(Q, c, xc[c] - e, 0)
+                    H = (gp - gm) / (2 * h)  # [5, 3]: d/dx_d of each gradient component
+                    for k in range(3):
+                        if k >= d:  # each multi-index once: xx yy zz xy xz yz
+                            sec += H[:, k] ** 2
+                b += V * sec * V ** (4 / 3 - 1)
+            betas.append(b)
+        betas = np.array(betas)  # [M+1, 5]
+        tau = np.abs(betas[0] - betas[1:]).mean(axis=0)
+        gam = np.r_[1 - 0.0125 * M, np.full(M, 0.0125)]
+        om = gam[:, None] * (1 + tau[None, :] / (betas + 1e-6))
+        om /= om.sum(axis=0)
+        w = o.weno_weights(Q, c)
+        np.testing.assert_allclose(w[:, : M + 1], om.T, rtol=2e-5, atol=1e-9)
+        checked += 1
+    assert checked >= 20
+
+
+# ---------------------------------------------------------------------------
+# Maxwellian moments (Eq. bgk-3d, Eq. compatibility)
+# ---------------------------------------------------------------------------
+def _half_line(U, lam, n, sign):
+    """Brute-force normalised moments of u^n over a half line (Gauss-Legendre on a truncated interval)."""
+    sd = 1 / math.sqrt(2 * lam)
+    lo, hi = (0.0, U + 14 * sd) if sign > 0 else (U - 14 * sd, 0.0)
+    if sign > 0 and hi <= 0 or sign < 0 and lo >= 0:
+        return 0.0
+    x, w = np.polynomial.legendre.leggauss(400)
+    u = 0.5 * (hi - lo) * x + 0.5 * (hi + lo)
+    wt = 0.5 * (hi - lo) * w
+    g = math.sqrt(lam / math.pi) * np.exp(-lam * (u - U) ** 2)
+    return float((wt * g * u ** n).sum())
+
+
+@pytest.mark.parametrize("U,lam", [(0.3, 0.7), (-1.2, 2.5), (2.0, 0.4), (0.0, 1.0)])
+def test_maxwellian_moments_brute_force(U, lam):
+    K = 2.0
+    full, pos, neg, s = oracle.maxwell_moments(U, lam, K)
+    for n in range(9):
+        bp, bn = _half_line(U, lam, n, +1), _half_line(U, lam, n, -1)
+        assert pos[n] == pytest.approx(bp, rel=1e-12, abs=1e-14)
+        assert neg[n] == pytest.approx(bn, rel=1e-12, abs=1e-14)
+        assert full[n] == pytest.approx(bp + bn, rel=1e-12, abs=1e-14)
+    # internal degrees of freedom: K = 2 Gaussian variables with the same temperature
+    x, w = np.polynomial.hermite.hermgauss(30)
+    r = x[:, None] ** 2 + x[None, :] ** 2
+    W = (w[:, None] * w[None, :]) / math.pi
+    for d in range(4):
+        assert s[d] == pytest.approx(float((W * (r / lam) ** d).sum()), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# gas-kinetic flux at one Gauss point (Section 3.2, Eq. flux-1)
+# ---------------------------------------------------------------------------
+GAMMA = 1.4
+
+
+def prim_to_cons(rho, U, p):
+    U = np.asarray(U, float)
+    return np.r_[rho, rho * U, p / (GAMMA - 1) + 0.5 * rho * U @ U]
+
+
+def test_uniform_equilibrium_gives_euler_flux():
+    prm = oracle.params()
+    for rho, U, p in [(1.0, (0.3, -0.2, 0.5), 1.0), (0.4, (-1.5, 0.1, 0.0), 0.3), (2.0, (0.0, 0.0, 0.0), 5.0)]:
+        q = prim_to_cons(rho, U, p)
+        F, _ = oracle.gp_flux(prm, q, np.zeros((3, 5)), q, np.zeros((3, 5)), 0.01)
+        E = q[4]
+        euler = np.array([rho * U[0], rho * U[0] ** 2 + p, rho * U[0] * U[1], rho * U[0] * U[2], U[0] * (E + p)])
+        np.testing.assert_allclose(F[:5], euler, rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(F[5:], 0.0, atol=1e-10)
+
+
+class Quad5:
+    """Tensor quadrature over (u, v, w, s1, s2) for moments of (half-space) Maxwellians with K = 2."""
+
+    def __init__(self, rho, U, lam, half=0):
+        sd = 1 / math.sqrt(2 * lam)
+        if half == 0:
+            xu, wu = np.polynomial.hermite.hermgauss(40)
+            u = U[0] + xu / math.sqrt(lam)
+            wu = wu / math.sqrt(math.pi)
+        else:
+            lo, hi = (0.0, max(U[0], 0) + 14 * sd) if half > 0 else (min(U[0], 0) - 14 * sd, 0.0)
+            x, w = np.polynomial.legendre.leggauss(120)
+            u = 0.5 * (hi - lo) * x + 0.5 * (hi + lo)
+            wu = 0.5 * (hi - lo) * w * math.sqrt(lam / math.pi) * np.exp(-lam * (u - U[0]) ** 2)
+        xh, wh = np.polynomial.hermite.hermgauss(8)
+        v = U[1] + xh / math.sqrt(lam)
+        w_ = U[2] + xh / math.sqrt(lam)
+        s = xh / math.sqrt(lam)
+        wh = wh / math.sqrt(math.pi)
+        G = np.meshgrid(u, v, w_, s, s, indexing="ij")
+        W = np.einsum("a,b,c,d,e->abcde", wu, wh, wh, wh, wh)
+        self.u, self.v, self.w, self.s1, self.s2 = (g.ravel() for g in G)
+        self.W = rho * W.ravel()
+
+    def psi(self):
+        return np.stack([np.ones_like(self.u), self.u, self.v, self.w,
+                         0.5 * (self.u ** 2 + self.v ** 2 + self.w ** 2 + self.s1 ** 2 + self.s2 ** 2)])
+
+    def moment(self, f):
+        """int psi f g dXi for a per-node weight f."""
+        return self.psi() @ (self.W * f)
+
+    def slope(self, a):
+        return self.psi().T @ a
+
+
+def test_flux_pieces_and_time_integrals_by_brute_force():
+    """Slopes, interface equilibrium and the time-integrated flux of Eq. flux-1, by quadrature in u and t."""
+    prm = oracle.params()
+    rng = np.random.default_rng(7)
+    for trial in range(2):
+        ql = prim_to_cons(1.0 + 0.3 * rng.random(), 0.4 * rng.standard_normal(3), 1.0 + 0.3 * rng.random())
+        qr = prim_to_cons(0.6 + 0.3 * rng.random(), 0.4 * rng.standard_normal(3), 0.7 + 0.3 * rng.random())
+        dql = 0.2 * rng.standard_normal((3, 5))
+        dqr = 0.2 * rng.standard_normal((3, 5))
+        dt = 0.03
+        F, dbg = oracle.gp_flux(prm, ql, dql, qr, dqr, dt)
+        rho0, U0, lam0 = dbg[0], dbg[1:4], dbg[4]
+        al, ar, ab = dbg[5:20].reshape(3, 5), dbg[20:35].reshape(3, 5), dbg[35:50].reshape(3, 5)
+        Al, Ar, Ab, tau = dbg[50:55], dbg[55:60], dbg[60:65], dbg[65]
+        Fh, Ff = dbg[66:71], dbg[71:76]
+
+        def prim(q):
+            rho = q[0]
+            U = q[1:4] / rho
+            p = (GAMMA - 1) * (q[4] - 0.5 * rho * U @ U)
+            return rho, U, rho / (2 * p), p
+
+        rl, Ul, laml, pl = prim(ql)
+        rr, Ur, lamr, pr = prim(qr)
+        assert tau == pytest.approx(0.01 * dt + abs(pl - pr) / (pl + pr) * dt, rel=1e-14)
+        Gl, Gr = Quad5(rl, Ul, laml), Quad5(rr, Ur, lamr)
+        Hl, Hr = Quad5(rl, Ul, laml, +1), Quad5(rr, Ur, lamr, -1)
+        # interface equilibrium from the two half spaces
+        q0 = Hl.moment(1.0) + Hr.moment(1.0)
+        r0, U0b, lam0b, _ = prim(q0)
+        assert rho0 == pytest.approx(r0, rel=1e-11)
+        np.testing.assert_allclose(U0, U0b, rtol=1e-10, atol=1e-12)
+        assert lam0 == pytest.approx(lam0b, rel=1e-10)
+        G0 = Quad5(rho0, U0, lam0)
+        for mdir in range(3):
+            np.testing.assert_allclose(Gl.moment(Gl.slope(al[mdir])), dql[mdir], rtol=1e-9, atol=1e-11)
+            np.testing.assert_allclose(Gr.moment(Gr.slope(ar[mdir])), dqr[mdir], rtol=1e-9, atol=1e-11)
+            target = Hl.moment(Hl.slope(al[mdir])) + Hr.moment(Hr.slope(ar[mdir]))
+            np.testing.assert_allclose(G0.moment(G0.slope(ab[mdir])), target, rtol=1e-9, atol=1e-11)
+
+        def adv(Gq, a):
+            return Gq.slope(a[0]) * Gq.u + Gq.slope(a[1]) * Gq.v + Gq.slope(a[2]) * Gq.w
+
+        np.testing.assert_allclose(Gl.moment(adv(Gl, al) + Gl.slope(Al)), 0, atol=1e-11)
+        np.testing.assert_allclose(Gr.moment(adv(Gr, ar) + Gr.slope(Ar)), 0, atol=1e-11)
+        np.testing.assert_allclose(G0.moment(adv(G0, ab) + G0.slope(Ab)), 0, atol=1e-11)
+
+        # F(delta) = int_0^delta int u psi f(t) dXi dt with f from Eq. flux-1: the velocity moments
+        # of each term by quadrature, the time integral of the term coefficients by Gauss-Legendre
+        M0, Ma, MA = G0.moment(G0.u), G0.moment(G0.u * adv(G0, ab)), G0.moment(G0.u * G0.slope(Ab))
+        Mh = Hl.moment(Hl.u) + Hr.moment(Hr.u)
+        Mha = Hl.moment(Hl.u * adv(Hl, al)) + Hr.moment(Hr.u * adv(Hr, ar))
+        MhA = Hl.moment(Hl.u * Hl.slope(Al)) + Hr.moment(Hr.u * Hr.slope(Ar))
+
+        def F_of(delta):
+            xt, wt = np.polynomial.legendre.leggauss(40)
+            out = np.zeros(5)
+            for t, w in zip(0.5 * delta * (xt + 1), 0.5 * delta * wt):
+                e = math.exp(-t / tau)
+                out += w * ((1 - e) * M0 + ((t + tau) * e - tau) * Ma + (t - tau + tau * e) * MA
+                            + e * (Mh - (tau + t) * Mha - tau * MhA))
+            return out
+
+        np.testing.assert_allclose(Fh, F_of(0.5 * dt), rtol=1e-9, atol=1e-13)
+        np.testing.assert_allclose(Ff, F_of(dt), rtol=1e-9, atol=1e-13)
+        np.testing.assert_allclose(F[:5], (4 * Fh - Ff) / dt, rtol=1e-12)
+        np.testing.assert_allclose(F[5:], 4 * (Ff - 2 * Fh) / dt ** 2, rtol=1e-12)
+
+
+def _mirror(q):
+    q = np.array(q, float)
+    q[..., 1] = -q[..., 1]
+    return q
+
+
+def test_flux_mirror_symmetry():
+    prm = oracle.params()
+    rng = np.random.default_rng(9)
+    for _ in range(5):
+        ql = prim_to_cons(1.0 + 0.2 * rng.random(), 0.5 * rng.standard_normal(3), 1.0 + 0.2 * rng.random())
+        qr = prim_to_cons(0.5 + 0.2 * rng.random(), 0.5 * rng.standard_normal(3), 0.6 + 0.2 * rng.random())
+        dql, dqr = 0.3 * rng.standard_normal((3, 5)), 0.3 * rng.standard_normal((3, 5))
+        F, _ = oracle.gp_flux(prm, ql, dql, qr, dqr, 0.02)
+        # reflect x1 -> -x1: swap sides, negate normal momentum and the n1-derivatives
+        dl2, dr2 = _mirror(dqr), _mirror(dql)
+        dl2[0] *= -1
+        dr2[0] *= -1
+        G, _ = oracle.gp_flux(prm, _mirror(qr), dl2, _mirror(ql), dr2, 0.02)
+        sgn = np.array([-1, 1, -1, -1, -1, -1, 1, -1, -1, -1])
+        np.testing.assert_allclose(G, sgn * F, rtol=1e-11, atol=1e-12)
+
+
+def test_flux_tangential_rotation_invariance():
+    prm = oracle.params(viscous=True, mu=1e-3, Pr=0.72)
+    rng = np.random.default_rng(13)
+    th = 0.7
+    R = np.array([[1, 0, 0], [0, math.cos(th), -math.sin(th)], [0, math.sin(th), math.cos(th)]])
+
+    def rot(q):
+        q = np.array(q, float)
+        q[..., 1:4] = q[..., 1:4] @ R.T
+        return q
+
+    for _ in range(4):
+        ql = prim_to_cons(1.0, 0.5 * rng.standard_normal(3), 1.0)
+        qr = prim_to_cons(0.7, 0.5 * rng.standard_normal(3), 0.8)
+        dql, dqr = 0.3 * rng.standard_normal((3, 5)), 0.3 * rng.standard_normal((3, 5))
+        F, _ = oracle.gp_flux(prm, ql, dql, qr, dqr, 0.02)
+        # derivative directions rotate with the frame as well
+        G, _ = oracle.gp_flux(prm, rot(ql), R @ rot(dql), rot(qr), R @ rot(dqr), 0.02)
+        np.testing.assert_allclose(G[:5], rot(F[:5]), rtol=1e-11, atol=1e-12)
+        np.testing.assert_allclose(G[5:], rot(F[5:]), rtol=1e-10, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# two-stage fourth-order time stepping
+# ---------------------------------------------------------------------------
+def test_s2o4_matches_fourth_order_taylor_polynomial():
+    rng = np.random.default_rng(21)
+    A = rng.standard_normal((4, 4))
+    u0 = rng.standard_normal(4)
+    dt = 0.1
+    out = oracle.s2o4(u0, dt, lambda u: (A @ u, A @ (A @ u)))
+    T = np.eye(4)
+    P = np.eye(4)
+    for k in range(1, 5):
+        P = P @ (dt * A) / k
+        T = T + P
+    np.testing.assert_allclose(out, T @ u0, rtol=1e-14, atol=1e-14)
+    out = oracle.s2o4(np.array([1.0]), dt, lambda u: (-u, u))
+    assert out[0] == pytest.approx(1 - dt + dt ** 2 / 2 - dt ** 3 / 6 + dt ** 4 / 24, rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# the whole scheme
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["hex", "tet", "pyr", "prism", "hybrid"])
+def test_free_stream_preserved(kind):
+    m = inputs.lattice(3 if kind != "hybrid" else 4, kind)
+    o = oracle.Oracle(m)
+    Q = inputs.cell_averages(m, inputs.uniform(1.3, 0.3, -0.2, 0.5, 0.9))
+    Q1 = o.step(Q, o.timestep(Q))
+    np.testing.assert_allclose(Q1, Q, rtol=0, atol=5e-15 * np.abs(Q).max())
+
+
+def test_conservation_on_hybrid_mesh():
+    m = inputs.lattice(5, "hybrid")
+    o = oracle.Oracle(m)
+    Q = inputs.cell_averages(m, inputs.perturbed_wave(amp=0.5, kmax=1, rms=0.2))
+    vol, _, _, _ = o.cell_geometry()
+    Q1, _ = o.run(Q, nsteps=2)
+    tot0 = (Q * vol).sum(axis=1)
+    tot1 = (Q1 * vol).sum(axis=1)
+    np.testing.assert_allclose(tot1, tot0, rtol=1e-14, atol=1e-15)
+
+
+def test_timestep_is_cfl_h_over_signal_speed_on_cubes():
+    m = inputs.lattice(4, "hex")
+    o = oracle.Oracle(m)
+    Q = inputs.cell_averages(m, inputs.uniform(1.0, 1.0, 1.0, 1.0, 1.0))
+    assert o.timestep(Q) == pytest.approx(0.5 * 0.25 / (math.sqrt(3) + math.sqrt(1.4)), rel=1e-14)
+
+
+def _errors(m, o, Q, t):
+    vol, _, _, _ = o.cell_geometry()
+    ex = inputs.cell_averages(m, inputs.wave(t=t))[0]
+    e = Q[0] - ex
+    return float((np.abs(e) * vol).sum()), float(np.abs(e).max())
+
+
+@pytest.mark.slow
+def test_third_order_convergence_on_hexahedra():
+    errs = []
+    for N in (8, 16):
+        m = inputs.lattice(N, "hex")
+        o = oracle.Oracle(m)
+        Q, _ = o.run(inputs.cell_averages(m, inputs.wave()), t_end=0.1)
+        errs.append(_errors(m, o, Q, 0.1))
+    order = math.log2(errs[0][0] / errs[1][0])
+    assert order > 2.5, (errs, order)
+
+
+@pytest.mark.slow
+def test_paper_hex_accuracy_table_first_row():
+    """Table tab-3d-1 (N = 10): the paper's domain [0,2]^3 and wave pi(x+y+z) scale to the unit cube.
+
+    The paper's L1 error integrates |e| over a volume of 8, so the unit-cube value is 1/8 of it.  The
+    paper's smooth-flow flux (tau = 0) differs from the collision time used here, so the pin is a factor
+    of 2.5 either way.
+    """
+    ref = json.load(open(os.path.join(GOLDEN, "paper_accuracy_tables.json")))["hex"]
+    m = inputs.lattice(10, "hex")
+    o = oracle.Oracle(m)
+    Q, _ = o.run(inputs.cell_averages(m, inputs.wave()), t_end=1.0)
+    l1, _ = _errors(m, o, Q, 1.0)
+    paper = ref["L1"][0] / 8.0
+    assert paper / 2.5 < l1 < paper * 2.5, (l1, paper)
