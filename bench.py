@@ -1,0 +1,185 @@
+"""Throughput of the explicit WENO gas-kinetic S2O4 step on one MI355X.
+
+Workload: hybrid tetrahedron/pyramid/prism/hexahedron lattice mesh of the
+periodic box [0, 2 pi]^3 with N = 64 lattice cells per side (about 1.47 M
+cells), compressible Navier-Stokes Taylor-Green vortex at Mach 0.1,
+Re = 1600, Pr = 0.72.  A step is one full two-stage fourth-order step: CFL
+time step, then twice WENO reconstruction -> face GKS flux -> stage update.
+Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: FP64 cell-updates/s as ``value``, with the FP32-mixed
+throughput, the per-kernel breakdown, the roofline of the dominant kernel and
+the oracle's CPU rate on a bounded sample beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# FP64 operations of one Gauss-point flux evaluation of the flux kernel (state
+# evaluation from the two quadratics, frame, BGK flux with both time integrals,
+# rotation back and weighting), counted from the kernel source by executing it
+# on the host with an operation-counting number type; see the design doc.
+FLUX_FLOPS_PER_GP_INVISCID = None
+FLUX_FLOPS_PER_GP_VISCOUS = None
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(host, es):
+    """Compulsory HBM bytes per launch of each kernel (es = bytes of the reduced-precision type)."""
+    n, nf, ns = host.n, host.n_faces, host.n_stencil
+    nsc = host.n_subcoef
+    ncf = host.n_cellfaces
+    recon = 40 * n + 8 * n + 4 * ns + ns + 9 * es * ns + 3 * es * nsc + n + 8 * n + 48 * n + 50 * es * n
+    flux = 8 * nf + 9 * 4 * 8 * nf + 50 * es * n + 10 * es * nf + (40 * n if es == 4 else 0)
+    stage1 = 4 * n + 4 * ncf + 10 * es * nf + 8 * n + 40 * n + 40 * n + 40 * n
+    stage2 = 4 * n + 4 * ncf + 10 * es * nf + 8 * n + 40 * n + 40 * n
+    timestep = 48 * n
+    return dict(reconstruct=recon, flux=flux, stage1=stage1, stage2=stage2, timestep=timestep)
+
+
+def run_gpu(args, mesh, Q0, precision):
+    import torch
+
+    from paper_2203_09047_amd import gks
+
+    host = gks.HostMesh(mesh) if not hasattr(run_gpu, "host") else run_gpu.host
+    run_gpu.host = host
+    prm = gks.params(precision=precision, viscous=True, mu=1.0 / 1600.0, Pr=0.72, cfl=0.5)
+    sol = gks.Solver(host, prm)
+    Q = sol.upload(host.to_internal(Q0))
+    for _ in range(args.warmup):
+        sol.step(Q)
+    torch.cuda.synchronize()
+    sol.poll()
+    sol.profile(True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        sol.step(Q)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = sol.profile_read()
+    sol.profile(False)
+    sol.poll()
+    q = Q.cpu().numpy()
+    assert np.isfinite(q).all()
+    return host, sol, ms, prof
+
+
+def cpu_baseline(N_sample=16):
+    import oracle
+    from paper_2203_09047_amd import inputs
+
+    mesh = inputs.lattice(N_sample, "hybrid", box=(2 * math.pi,) * 3)
+    Q0 = inputs.cell_averages(mesh, inputs.tgv())
+    prm = oracle.params(viscous=True, mu=1.0 / 1600.0, Pr=0.72, cfl=0.5)
+    o = oracle.Oracle(mesh, prm)
+    dt = o.timestep(Q0)
+    t = time.perf_counter()
+    o.step(Q0, dt)
+    el = time.perf_counter() - t
+    return dict(value=mesh.n_cells / el, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=f"hybrid lattice N={N_sample} ({mesh.n_cells} cells), Taylor-Green Mach 0.1 NS, "
+                       f"1 S2O4 step, single-threaded FP64 C oracle, {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--N", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2203_09047_amd import gks, inputs
+
+    gks.load()
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU")
+    t = time.perf_counter()
+    mesh = inputs.lattice(args.N, "hybrid", box=(2 * math.pi,) * 3)
+    Q0 = inputs.cell_averages(mesh, inputs.tgv())
+    log(f"mesh N={args.N}: {mesh.n_cells} cells {mesh.hist} ({time.perf_counter() - t:.1f} s)")
+    t = time.perf_counter()
+    host, sol, ms64, prof64 = run_gpu(args, mesh, Q0, gks.FP64)
+    log(f"fp64: {args.steps} steps {ms64:.2f} ms (setup+run {time.perf_counter() - t:.1f} s) {prof64}")
+    n = host.n
+    value = n * args.steps / (ms64 * 1e-3)
+    res = {
+        "metric": "cell-updates/s per S2O4 step (FP64 vs FP32-mixed) + adjoint/forward time ratio",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"hybrid-lattice N={args.N} periodic [0,2pi]^3 Taylor-Green Ma0.1 Re1600 Pr0.72 NS",
+                   "cells": n, "faces": host.n_faces, "hist": mesh.hist},
+    }
+    kern = {k: dict(avg_ms=v[0] / max(v[1], 1), launches=v[1]) for k, v in prof64.items() if v[1]}
+    res["kernels_fp64"] = kern
+    bytes64 = algorithmic_bytes(host, 8)
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+    avg_s = kern[dom]["avg_ms"] * 1e-3
+    if dom == "flux" and FLUX_FLOPS_PER_GP_VISCOUS:
+        fl = FLUX_FLOPS_PER_GP_VISCOUS * 4 * host.n_faces
+        achieved = fl / avg_s / 1e12
+        res["roofline"] = dict(kernel=dom, bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS,
+                               unit="TFLOP/s", frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=None)
+    else:
+        b = bytes64[dom]
+        achieved = b / avg_s / 1e9
+        res["roofline"] = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                               frac=achieved / HBM_PEAK_GBS, traffic=None)
+    res["hbm_fraction_of_step_fp64"] = sum(bytes64[k] * kern[k]["launches"] for k in kern) / args.steps / (
+        ms64 / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS
+    if not args.no_fp32:
+        del sol
+        torch.cuda.empty_cache()
+        _, sol32, ms32, prof32 = run_gpu(args, mesh, Q0, gks.FP32_MIXED)
+        log(f"fp32-mixed: {ms32:.2f} ms {prof32}")
+        res["fp32_mixed"] = dict(value=n * args.steps / (ms32 * 1e-3), ms_per_step=ms32 / args.steps,
+                                 speedup_vs_fp64=ms64 / ms32,
+                                 kernels={k: dict(avg_ms=v[0] / max(v[1], 1), launches=v[1])
+                                          for k, v in prof32.items() if v[1]})
+    if not args.no_cpu:
+        t = time.perf_counter()
+        res["cpu_baseline"] = cpu_baseline()
+        log(f"cpu baseline {time.perf_counter() - t:.1f} s")
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * gks.h -- C ABI of the MI355X third-order gas-kinetic scheme on hybrid
+ * unstructured meshes (Yang, Pan & Xu, arXiv 2203.09047).
+ *
+ * The library computes the explicit hot path of the method on one gfx950 GPU:
+ *   WENO reconstruction per cell (Section 2: least-squares quadratic on the
+ *   big stencil, linear polynomials on the sub-stencils, linear weights,
+ *   smoothness indicators of Eq. indicator, nonlinear combination Eq. weno),
+ *   the BGK time-dependent flux at the four Gauss points of every face
+ *   (Section 3.2, Eq. flux-1, integrated over the face with Eq. flux-qud),
+ *   and the two-stage fourth-order time step (Section 3.3, applied to the
+ *   semi-discrete operator of Eq. semi / Eq. finite).
+ *
+ * Conventions shared by every entry point:
+ *   - Cell indices are the library's internal order (cells sorted along a
+ *     Morton space-filling curve of their centroids).  gks_host_mesh_perm()
+ *     maps internal index -> index in the caller's mesh records.
+ *   - Conserved variables Q are structure-of-arrays FP64 [5][n_cells]:
+ *     rho, rho U, rho V, rho W, rho E.
+ *   - Every device pointer is owned by the caller.  The library never
+ *     allocates device memory in a compute call; the mesh arena and the work
+ *     buffer are sized by gks_mesh_sizes() and passed in.  Host objects
+ *     (gks_host_mesh, gks_mesh handles) are allocated with malloc/new and
+ *     released by their destroy calls.
+ *   - Compute calls are asynchronous on the given stream (NULL = default
+ *     stream of the current device) and only enqueue kernels.
+ *   - Errors are status codes; no call aborts or throws across the ABI.
+ *     gks_last_error() returns a thread-local message for the last failure.
+ *   - Non-physical states (rho <= 0 or p <= 0 at a cell or a Gauss point,
+ *     or a NaN) set a sticky flag in the work buffer; gks_poll_status()
+ *     synchronises the stream and reports GKS_ENONPHYS.  Nothing is
+ *     repaired silently.
+ */
+#ifndef GKS_H
+#define GKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *gks_stream_t; /* a hipStream_t */
+
+typedef enum {
+    GKS_OK = 0,
+    GKS_EINVAL = 1,     /* bad pointer, size or parameter */
+    GKS_EDEVICE = 2,    /* HIP runtime error (see gks_last_error) */
+    GKS_ESINGULAR = 3,  /* a least-squares fit stayed rank deficient after growing its stencil */
+    GKS_ENONPHYS = 4,   /* sticky: non-physical state met in a kernel */
+    GKS_EMESH = 5       /* mesh records are not a conforming (periodic) mesh */
+} gks_status;
+
+typedef enum { GKS_FP64 = 0, GKS_FP32_MIXED = 1 } gks_precision;
+
+/*
+ * Scheme parameters.  Defaults (gks_default_params) follow the paper:
+ * gamma = 1.4; linear weights gamma_m = 0.0125 for every sub-stencil and
+ * gamma_0 = 1 - 0.0125 M (Section 2); nonlinear weights
+ * w_m = gamma_m (1 + (tau_w / (beta_m + weno_eps))^weno_p) with weno_p = 1
+ * and weno_eps = 1e-6 (the paper leaves epsilon unspecified); collision time
+ * tau = tau_eps dt + tau_C |p_l - p_r| / (p_l + p_r) dt for inviscid flow and
+ * mu / p_0 + tau_C |p_l - p_r| / (p_l + p_r) dt for viscous flow with
+ * tau_eps = 0.01, tau_C = 1 (Section 4); CFL time step
+ * dt = cfl min_i h_i / (|U_i| + c_i) with h_i = 6 |Omega_i| / (sum of face areas).
+ * Pr != 1 adds (1/Pr - 1) q to the energy flux, q being the heat flux of the
+ * time-integrated distribution about the interface velocity.
+ */
+typedef struct {
+    double gamma;
+    double cfl;
+    double mu;
+    double Pr;
+    double weno_eps;
+    double weno_gamma_m;
+    double weno_p;
+    double tau_eps;
+    double tau_C;
+    int viscous;      /* 0: Euler, 1: Navier-Stokes collision time */
+    int precision;    /* gks_precision */
+    int force_linear; /* 1: use the linear weights (testing of the quadratic reproduction) */
+    int dt_given;     /* 1: gks_s2o4_step uses *dt_dev as given instead of computing the CFL step */
+} gks_params;
+
+typedef struct gks_host_mesh gks_host_mesh;
+typedef struct gks_mesh gks_mesh;
+
+void gks_default_params(gks_params *p);
+
+/*
+ * Build the host-side preprocessed mesh (Section 2: face labels of the four
+ * cell types, degenerate-hexahedron trilinear maps, 3x3x3 volume Gauss rule,
+ * bilinear faces with 2x2 Gauss points, big stencil and sub-stencils, FP64
+ * least-squares pseudo-inverses; plus the Morton reorder of the cells).
+ *   nodes  [n_nodes][3] FP64 coordinates;
+ *   types  [n_cells] int8: 0 tetrahedron, 1 pyramid, 2 prism, 3 hexahedron;
+ *   cells  [n_cells][8] int64 node ids in the paper's vertex order, -1 padded;
+ *   box    [3] periodic box lengths (the domain is [0,box_x] x [0,box_y] x [0,box_z]);
+ *   periodic must be 1 (every face is then shared by exactly two cells).
+ * All arrays are read only during the call.  Returns GKS_EMESH for a
+ * non-conforming mesh and GKS_ESINGULAR when a fit cannot be made well posed.
+ */
+gks_status gks_preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, const int8_t *types,
+                          const int64_t *cells, const double *box, int periodic, gks_host_mesh **out);
+void gks_host_mesh_free(gks_host_mesh *h);
+
+/*
+ * n_cells, n_faces, stencil entries (members of all cells), sub-stencil
+ * coefficient triples, and the number of members appended by rank growth.
+ * Any pointer may be NULL.
+ */
+gks_status gks_host_mesh_counts(const gks_host_mesh *h, int64_t *n_cells, int64_t *n_faces, int64_t *n_stencil,
+                                int64_t *n_subcoef, int64_t *n_grown);
+/* perm[n_cells]: internal index -> caller's cell index */
+gks_status gks_host_mesh_perm(const gks_host_mesh *h, int64_t *perm);
+/* per cell (internal order): volume, centroid [n][3]; either pointer may be NULL */
+gks_status gks_host_mesh_geometry(const gks_host_mesh *h, double *vol, double *xc);
+/* per face: owner and neighbour (internal indices) */
+gks_status gks_host_mesh_faces(const gks_host_mesh *h, int32_t *owner, int32_t *nbr);
+
+/*
+ * Bytes of the device mesh arena and of the work buffer for a precision.
+ * The work buffer holds the stage state, reconstruction coefficients, face
+ * fluxes, time-step partials and the status word.
+ */
+gks_status gks_mesh_sizes(const gks_host_mesh *h, int precision, size_t *mesh_bytes, size_t *work_bytes);
+
+/*
+ * Upload the mesh into the caller's device arena (mesh_bytes from
+ * gks_mesh_sizes, 256-byte aligned) on the stream and synchronise it.
+ * The returned handle refers to the arena; it does not own it.
+ */
+gks_status gks_init_mesh(const gks_host_mesh *h, int precision, void *mesh_arena, size_t mesh_bytes,
+                         gks_stream_t stream, gks_mesh **out);
+void gks_destroy_mesh(gks_mesh *m);
+
+/* Clear the sticky status word of a work buffer (enqueued on the stream). */
+gks_status gks_reset_status(gks_mesh *m, void *work, gks_stream_t stream);
+
+/*
+ * CFL time step (reading of the paper's time-step step of its solution
+ * algorithm, which gives no formula): *dt_dev = cfl min_i h_i / (|U_i| + c_i),
+ * computed in FP64 with a deterministic two-pass minimum.
+ */
+gks_status gks_timestep(gks_mesh *m, const double *Q, const gks_params *p, double *dt_dev, void *work,
+                        gks_stream_t stream);
+
+/*
+ * WENO reconstruction (Section 2, Eq. weno).  Every candidate polynomial is a
+ * polynomial in the same zero-mean basis, so the nonlinear combination of
+ * Eq. weno is itself one quadratic per cell and component.  Output coeff
+ * [n_cells][5][10] (FP64, or FP32 for GKS_FP32_MIXED): for component c,
+ * entry 0 is the constant term and entries 1..9 the coefficients of the
+ * monomials x y z xx xy xz yy yz zz of (x - x_c), so that the reconstructed
+ * value at x is coeff[0] + sum_n coeff[n] (x - x_c)^n; in FP32_MIXED mode
+ * entry 0 excludes the cell average, which is added back in FP64.
+ */
+gks_status gks_reconstruct(gks_mesh *m, const double *Q, void *coeff, const gks_params *p, void *work,
+                           gks_stream_t stream);
+
+/*
+ * Face fluxes (Section 3.2, Eq. flux-1 at each Gauss point, Eq. flux-qud over
+ * the face).  For each face the time integrals F(dt/2) and F(dt) of the
+ * area-integrated flux give Fbar0 = (4 F(dt/2) - F(dt)) / dt (flux at the
+ * start of the step) and Fbar1 = 4 (F(dt) - 2 F(dt/2)) / dt^2 (its time
+ * derivative).  face_flux is [n_faces][10] (FP64, or FP32 for
+ * GKS_FP32_MIXED), oriented owner -> neighbour.  dt_dev is read on the device.
+ */
+gks_status gks_flux(gks_mesh *m, const void *coeff, const double *Q, const double *dt_dev, void *face_flux,
+                    const gks_params *p, void *work, gks_stream_t stream);
+
+/*
+ * Semi-discrete operator (Eq. finite) and its time derivative:
+ * L_i = -(1/|Omega_i|) sum_p s_p Fbar0_p, dL_i = -(1/|Omega_i|) sum_p s_p Fbar1_p,
+ * each [5][n_cells] FP64, gathered per cell in a fixed face order.
+ */
+gks_status gks_residual(gks_mesh *m, const void *face_flux, double *L, double *dL, const gks_params *p,
+                        gks_stream_t stream);
+
+/*
+ * One two-stage fourth-order step (Section 3.3):
+ *   Q* = Q + dt/2 L(Q) + dt^2/8 dL(Q),
+ *   Q <- Q + dt L(Q) + dt^2/6 (dL(Q) + 2 dL(Q*)),
+ * with the same dt in both stages.  Q is updated in place.  If p->dt_given
+ * is 0 the CFL step is computed first into *dt_dev; otherwise *dt_dev is
+ * used as given.  Q_star (optional, may be NULL) receives Q* [5][n_cells].
+ */
+gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_params *p, void *work, double *Q_star,
+                         gks_stream_t stream);
+
+/* Synchronise the stream and report GKS_ENONPHYS if the sticky flag is set. */
+gks_status gks_poll_status(gks_mesh *m, void *work, gks_stream_t stream);
+
+/*
+ * Gauss-point flux in the local frame for a batch (kernel-level testing of the
+ * flux of Section 3.2).  ql, qr [n][5]: conserved states with the momentum in
+ * the (n1, n2, n3) frame; dql, dqr [n][3][5]: their derivatives along n1, n2,
+ * n3; dt [n]; out [n][10]: (Fbar0, Fbar1) per unit area.  Device pointers;
+ * FP64, or FP32 arithmetic for GKS_FP32_MIXED (inputs and outputs stay FP64).
+ */
+gks_status gks_gp_flux_batch(int64_t n, const double *ql, const double *dql, const double *qr, const double *dqr,
+                             const double *dt, double *out, const gks_params *p, gks_stream_t stream);
+
+/*
+ * Optional per-kernel timing with HIP events recorded on the launch stream
+ * around every kernel the library enqueues (host-side events owned by the
+ * mesh handle; no device memory).  gks_profile_read synchronises on the last
+ * event, returns the summed milliseconds and launch counts per kernel id
+ * (arrays of GKS_K_COUNT) and clears the record.
+ */
+enum {
+    GKS_K_TIMESTEP = 0,
+    GKS_K_RECONSTRUCT = 1,
+    GKS_K_FLUX = 2,
+    GKS_K_STAGE1 = 3,
+    GKS_K_STAGE2 = 4,
+    GKS_K_RESIDUAL = 5,
+    GKS_K_COUNT = 6
+};
+gks_status gks_profile(gks_mesh *m, int enable);
+gks_status gks_profile_read(gks_mesh *m, double *total_ms, int64_t *launches);
+
+const char *gks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GKS_H */

@@ -1,0 +1,982 @@
+// Device library of the gas-kinetic solver for gfx950 (MI355X): kernels and C ABI.
+//
+// Kernels (one stage of the two-stage fourth-order step runs K1 -> K2 -> K3):
+//   K0 timestep  : CFL time step, FP64 two-pass deterministic minimum.
+//   K1 reconstruct: one lane per (cell, conserved component).  Streams the
+//                  cell's stencil once: differences Q_k - Q_0, the quadratic
+//                  fit a = A^+ (Q_k - Q_0) and the linear sub-stencil fits
+//                  b^m; smoothness indicators (Eq. indicator), nonlinear
+//                  weights, and Eq. weno collapsed into one quadratic.
+//   K2 flux      : one lane per (face, Gauss point); reconstructed states on
+//                  both sides, local frame, BGK flux of Eq. flux-1 with both
+//                  time integrals, rotated back and weighted (Eq. flux-qud);
+//                  the four Gauss points of a face are summed across lanes in
+//                  a fixed butterfly order.
+//   K3 update    : one lane per cell; gathers its face fluxes in F_p order
+//                  (no atomics, so results are bitwise reproducible), forms
+//                  L and dL/dt (Eq. finite) in FP64 and applies a stage of
+//                  the two-stage fourth-order step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gks_flux.h"
+#include "gks_internal.h"
+
+namespace gks {
+
+static thread_local std::string g_err;
+
+gks_status fail(gks_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+static gks_status hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return GKS_OK;
+    return fail(GKS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// device mesh
+// ---------------------------------------------------------------------------
+struct DevMesh {
+    int n, nf;
+    int precision;
+    // cells
+    const int8_t *M;        // number of sub-stencils
+    const double *vol;      // |Omega|
+    const double *vol23;    // |Omega|^(2/3)
+    const double *m2;       // [6][n] centred second moments (means)
+    const double *hcfl;     // 6 |Omega| / sum of face areas
+    const int32_t *st_ptr;  // [n+1]
+    const int32_t *sc_ptr;  // [n+1] (units of 3 coefficients)
+    const int32_t *st_idx;  // members
+    const uint8_t *st_mask;
+    const void *pinv;       // [nnz][9], FP64 or FP32
+    const void *sc;         // [nsc][3], FP64 or FP32
+    // faces
+    const int32_t *owner, *nbr;
+    const double *fgeo;     // [9][4 nf]
+    const int32_t *cf_ptr, *cf_idx;
+};
+
+// work buffer: status word, time-step partials, Q*, coefficients, face fluxes
+struct Work {
+    int *status;
+    double *dtpart;
+    double *Qs;
+    void *coeff;
+    void *ff;
+};
+
+constexpr int kBlock = 256;
+constexpr int kDtBlocks = 1024;
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t work_layout(int64_t n, int64_t nf, int precision, Work *w, char *base)
+{
+    const size_t es = precision == GKS_FP32_MIXED ? 4 : 8;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return base ? (void *)(base + o) : nullptr;
+    };
+    void *st = take(256);
+    void *dp = take(sizeof(double) * (kDtBlocks + 1));
+    void *qs = take(sizeof(double) * 5 * n);
+    void *co = take(es * 50 * n);
+    void *ff = take(es * 10 * nf);
+    if (w) {
+        w->status = (int *)st;
+        w->dtpart = (double *)dp;
+        w->Qs = (double *)qs;
+        w->coeff = co;
+        w->ff = ff;
+    }
+    return off;
+}
+
+// ---------------------------------------------------------------------------
+// K0: time step
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_dt_partial(int n, const double *__restrict__ Q, const double *__restrict__ hcfl,
+                                                       double gam, double cfl, double *__restrict__ part, int *status)
+{
+    __shared__ double red[kBlock];
+    double best = INFINITY;
+    bool bad = false;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double r = Q[i], mx = Q[n + i], my = Q[2 * n + i], mz = Q[3 * n + i], E = Q[4 * n + i];
+        const double ir = 1.0 / r;
+        const double ke = 0.5 * (mx * mx + my * my + mz * mz) * ir;
+        const double p = (gam - 1.0) * (E - ke);
+        if (!(r > 0.0) || !(p > 0.0)) {
+            bad = true;
+            continue;
+        }
+        const double s = sqrt((mx * mx + my * my + mz * mz)) * ir + sqrt(gam * p * ir);
+        best = fmin(best, cfl * hcfl[i] / s);
+    }
+    if (bad) status[0] = 1;
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_dt_final(int nb, const double *__restrict__ part, double *dt)
+{
+    __shared__ double red[kBlock];
+    double best = INFINITY;
+    for (int i = threadIdx.x; i < nb; i += kBlock) best = fmin(best, part[i]);
+    red[threadIdx.x] = best;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dt[0] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// K1: WENO reconstruction, one lane per (cell, component)
+// ---------------------------------------------------------------------------
+struct WenoParams {
+    double eps, gm, p;
+    int force_linear;
+};
+
+template <typename T>
+__device__ __forceinline__ T wpow(T x, T p)
+{
+    if (p == T(1)) return x;
+    if (p == T(2)) return x * x;
+    return (T)pow((double)x, (double)p);
+}
+
+constexpr int kK1Block = 320;  // 64 cells x 5 components
+
+template <typename T>
+__global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff,
+                                                          WenoParams wp)
+{
+    const int t = blockIdx.x * kK1Block + threadIdx.x;
+    const int i = t / 5;
+    const int comp = t - 5 * i;
+    if (i >= m.n) return;
+    const int n = m.n;
+    const double q0 = Q[comp * n + i];
+    const double *Qc = Q + (size_t)comp * n;
+    const T *pinv = (const T *)m.pinv;
+    const T *sc = (const T *)m.sc;
+    const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
+    int e = m.sc_ptr[i];
+    T a[9], b[8][3];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) a[j] = T(0);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) b[s][0] = b[s][1] = b[s][2] = T(0);
+    for (int k = k0; k < k1; ++k) {
+        const T d = (T)(Qc[m.st_idx[k]] - q0);
+        const T *row = pinv + (size_t)9 * k;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) a[j] += row[j] * d;
+        const unsigned mask = m.st_mask[k];
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            if (mask & (1u << s)) {
+                const T *c = sc + (size_t)3 * e;
+                b[s][0] += c[0] * d;
+                b[s][1] += c[1] * d;
+                b[s][2] += c[2] * d;
+                ++e;
+            }
+    }
+    const int M = m.M[i];
+    const T v23 = (T)m.vol23[i];
+    const T S00 = (T)m.m2[i], S01 = (T)m.m2[n + i], S02 = (T)m.m2[2 * n + i], S11 = (T)m.m2[3 * n + i],
+            S12 = (T)m.m2[4 * n + i], S22 = (T)m.m2[5 * n + i];
+    // a: x y z xx xy xz yy yz zz
+    const T H[3][3] = {{T(2) * a[3], a[4], a[5]}, {a[4], T(2) * a[6], a[7]}, {a[5], a[7], T(2) * a[8]}};
+    T beta0 = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T h0 = H[d][0], h1 = H[d][1], h2 = H[d][2];
+        const T quad = h0 * (S00 * h0 + S01 * h1 + S02 * h2) + h1 * (S01 * h0 + S11 * h1 + S12 * h2) +
+                       h2 * (S02 * h0 + S12 * h1 + S22 * h2);
+        beta0 += a[d] * a[d] + quad;
+    }
+    const T sec = T(4) * (a[3] * a[3] + a[6] * a[6] + a[8] * a[8]) + a[4] * a[4] + a[5] * a[5] + a[7] * a[7];
+    beta0 = v23 * beta0 + v23 * v23 * sec;
+    const T gm = (T)wp.gm, g0 = T(1) - gm * T(M), eps = (T)wp.eps, pw = (T)wp.p;
+    T beta[8];
+    T tw = T(0);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        beta[s] = v23 * (b[s][0] * b[s][0] + b[s][1] * b[s][1] + b[s][2] * b[s][2]);
+        if (s < M) tw += fabs(beta0 - beta[s]);
+    }
+    tw /= T(M);
+    T w0, ws[8];
+    if (wp.force_linear) {
+        w0 = g0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) ws[s] = gm;
+    } else {
+        w0 = g0 * (T(1) + wpow(tw / (beta0 + eps), pw));
+#pragma unroll
+        for (int s = 0; s < 8; ++s) ws[s] = gm * (T(1) + wpow(tw / (beta[s] + eps), pw));
+    }
+    T sum = w0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+        if (s < M) sum += ws[s];
+    const T isum = T(1) / sum;
+    const T f0 = w0 * isum / g0;  // factor of P_0
+    T c[10];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) c[1 + j] = f0 * a[j];
+    const T sub0 = f0 * gm;  // omega_0 gamma_m / gamma_0
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+        if (s < M) {
+            const T fs = ws[s] * isum - sub0;
+            c[1] += fs * b[s][0];
+            c[2] += fs * b[s][1];
+            c[3] += fs * b[s][2];
+        }
+    // constant term: cell average minus the means of the quadratic monomials
+    const T corr = -(c[4] * S00 + c[5] * S01 + c[6] * S02 + c[7] * S11 + c[8] * S12 + c[9] * S22);
+    if constexpr (sizeof(T) == 8)
+        c[0] = (T)q0 + corr;
+    else
+        c[0] = corr;
+    T *out = coeff + (size_t)50 * i + 10 * comp;
+#pragma unroll
+    for (int j = 0; j < 10; ++j) out[j] = c[j];
+}
+
+// ---------------------------------------------------------------------------
+// K2: face flux, one lane per (face, Gauss point)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void local_frame(T vx, T vy, T vz, T n[3][3], T &area)
+{
+    area = sqrt_t(vx * vx + vy * vy + vz * vz);
+    const T ia = T(1) / area;
+    n[0][0] = vx * ia;
+    n[0][1] = vy * ia;
+    n[0][2] = vz * ia;
+    const T ax = n[0][0] < T(0) ? -n[0][0] : n[0][0];
+    const T ay = n[0][1] < T(0) ? -n[0][1] : n[0][1];
+    const T az = n[0][2] < T(0) ? -n[0][2] : n[0][2];
+    int e = 0;
+    T best = ax;
+    if (ay < best) {
+        e = 1;
+        best = ay;
+    }
+    if (az < best) e = 2;
+    T t[3] = {T(0), T(0), T(0)};
+    t[e] = T(1);
+    const T d = n[0][e];
+    t[0] -= d * n[0][0];
+    t[1] -= d * n[0][1];
+    t[2] -= d * n[0][2];
+    const T it = T(1) / sqrt_t(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    n[1][0] = t[0] * it;
+    n[1][1] = t[1] * it;
+    n[1][2] = t[2] * it;
+    n[2][0] = n[0][1] * n[1][2] - n[0][2] * n[1][1];
+    n[2][1] = n[0][2] * n[1][0] - n[0][0] * n[1][2];
+    n[2][2] = n[0][0] * n[1][1] - n[0][1] * n[1][0];
+}
+
+template <typename T>
+__device__ __forceinline__ void rotate_in(const T n[3][3], const T v[5], const T g[5][3], T q[5], T dq[3][5])
+{
+    q[0] = v[0];
+    q[4] = v[4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) q[1 + k] = v[1] * n[k][0] + v[2] * n[k][1] + v[3] * n[k][2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        T dn[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) dn[c] = g[c][0] * n[m][0] + g[c][1] * n[m][1] + g[c][2] * n[m][2];
+        dq[m][0] = dn[0];
+        dq[m][4] = dn[4];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dq[m][1 + k] = dn[1] * n[k][0] + dn[2] * n[k][1] + dn[3] * n[k][2];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor_t(T v, int mask)
+{
+    return __shfl_xor(v, mask, 64);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict__ coeff, const double *__restrict__ Q,
+                                                 const double *__restrict__ dt_dev, T *__restrict__ ff, FluxParams<T> fp,
+                                                 int *status)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int f = t >> 2;
+    const bool live = f < m.nf;
+    const int fs = live ? f : m.nf - 1;  // tail lanes compute a valid face and write nothing
+    const int nf4 = 4 * m.nf;
+    const int tt = 4 * fs + (t & 3);
+    const int o = m.owner[fs], nb = m.nbr[fs];
+    const double *G = m.fgeo;
+    const T dLx = (T)G[tt], dLy = (T)G[nf4 + tt], dLz = (T)G[2 * nf4 + tt];
+    const T dRx = (T)G[3 * nf4 + tt], dRy = (T)G[4 * nf4 + tt], dRz = (T)G[5 * nf4 + tt];
+    const T vx = (T)G[6 * nf4 + tt], vy = (T)G[7 * nf4 + tt], vz = (T)G[8 * nf4 + tt];
+    T n3[3][3], area;
+    local_frame(vx, vy, vz, n3, area);
+    T ql[5], qr[5], dql[3][5], dqr[3][5];
+    // left (owner)
+    {
+        T cc[50];
+        const T *src = coeff + (size_t)50 * o;
+#pragma unroll
+        for (int j = 0; j < 50; ++j) cc[j] = src[j];
+        T vv[5], gg[5][3];
+#pragma unroll
+        for (int comp = 0; comp < 5; ++comp) {
+            const double q0 = sizeof(T) == 8 ? 0.0 : Q[(size_t)comp * m.n + o];
+            const T *c = cc + 10 * comp;
+            const T X = dLx, Y = dLy, Z = dLz;
+            const T lin = c[1] * X + c[2] * Y + c[3] * Z;
+            const T qua = c[4] * X * X + c[5] * X * Y + c[6] * X * Z + c[7] * Y * Y + c[8] * Y * Z + c[9] * Z * Z;
+            if constexpr (sizeof(T) == 8)
+                vv[comp] = c[0] + lin + qua;
+            else
+                vv[comp] = (T)(q0 + (double)(c[0] + lin + qua));
+            gg[comp][0] = c[1] + T(2) * c[4] * X + c[5] * Y + c[6] * Z;
+            gg[comp][1] = c[2] + c[5] * X + T(2) * c[7] * Y + c[8] * Z;
+            gg[comp][2] = c[3] + c[6] * X + c[8] * Y + T(2) * c[9] * Z;
+        }
+        rotate_in(n3, vv, gg, ql, dql);
+    }
+    {
+        T cc[50];
+        const T *src = coeff + (size_t)50 * nb;
+#pragma unroll
+        for (int j = 0; j < 50; ++j) cc[j] = src[j];
+        T vv[5], gg[5][3];
+#pragma unroll
+        for (int comp = 0; comp < 5; ++comp) {
+            const double q0 = sizeof(T) == 8 ? 0.0 : Q[(size_t)comp * m.n + nb];
+            const T *c = cc + 10 * comp;
+            const T X = dRx, Y = dRy, Z = dRz;
+            const T lin = c[1] * X + c[2] * Y + c[3] * Z;
+            const T qua = c[4] * X * X + c[5] * X * Y + c[6] * X * Z + c[7] * Y * Y + c[8] * Y * Z + c[9] * Z * Z;
+            if constexpr (sizeof(T) == 8)
+                vv[comp] = c[0] + lin + qua;
+            else
+                vv[comp] = (T)(q0 + (double)(c[0] + lin + qua));
+            gg[comp][0] = c[1] + T(2) * c[4] * X + c[5] * Y + c[6] * Z;
+            gg[comp][1] = c[2] + c[5] * X + T(2) * c[7] * Y + c[8] * Z;
+            gg[comp][2] = c[3] + c[6] * X + c[8] * Y + T(2) * c[9] * Z;
+        }
+        rotate_in(n3, vv, gg, qr, dqr);
+    }
+    const T dt = (T)dt_dev[0];
+    T F[10];
+    const bool ok = gp_flux<T>(ql, dql, qr, dqr, dt, fp, F);
+    if (live && !ok) status[0] = 1;
+    // rotate back, weight by the Gauss point's area, sum over the face's four lanes
+    T out[10];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const T *Fl = F + 5 * s;
+        out[5 * s] = area * Fl[0];
+        out[5 * s + 4] = area * Fl[4];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) out[5 * s + 1 + q] = area * (Fl[1] * n3[0][q] + Fl[2] * n3[1][q] + Fl[3] * n3[2][q]);
+    }
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+        out[j] += shfl_xor_t(out[j], 1);
+        out[j] += shfl_xor_t(out[j], 2);
+    }
+    if (live) {
+        const int g4 = t & 3;
+        T *dst = ff + (size_t)10 * f;
+#pragma unroll
+        for (int j = 0; j < 10; ++j)
+            if ((j & 3) == g4) dst[j] = out[j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K3: per-cell gather of face fluxes and stage updates
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void gather(const DevMesh &m, const T *__restrict__ ff, int i, double L[5], double D[5])
+{
+#pragma unroll
+    for (int c = 0; c < 5; ++c) L[c] = D[c] = 0.0;
+    const int p0 = m.cf_ptr[i], p1 = m.cf_ptr[i + 1];
+    for (int p = p0; p < p1; ++p) {
+        const int code = m.cf_idx[p];
+        const double s = (code & 1) ? 1.0 : -1.0;  // owner: -F, neighbour: +F (L = -sum outward / vol)
+        const T *src = ff + (size_t)10 * (code >> 1);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            L[c] += s * (double)src[c];
+            D[c] += s * (double)src[5 + c];
+        }
+    }
+    const double iv = 1.0 / m.vol[i];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        L[c] *= iv;
+        D[c] *= iv;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_residual(DevMesh m, const T *__restrict__ ff, double *__restrict__ Lout,
+                                                     double *__restrict__ Dout)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m.n) return;
+    double L[5], D[5];
+    gather(m, ff, i, L, D);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        Lout[(size_t)c * m.n + i] = L[c];
+        Dout[(size_t)c * m.n + i] = D[c];
+    }
+}
+
+// stage 1: Q* = Q + dt/2 L + dt^2/8 D into Qs;  Q <- Q + dt L + dt^2/6 D (partial update)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_stage1(DevMesh m, const T *__restrict__ ff, double *__restrict__ Q,
+                                                   double *__restrict__ Qs, const double *__restrict__ dt_dev)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m.n) return;
+    const double dt = dt_dev[0];
+    double L[5], D[5];
+    gather(m, ff, i, L, D);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        const double q = Q[(size_t)c * m.n + i];
+        Qs[(size_t)c * m.n + i] = q + 0.5 * dt * L[c] + 0.125 * dt * dt * D[c];
+        Q[(size_t)c * m.n + i] = q + dt * L[c] + dt * dt / 6.0 * D[c];
+    }
+}
+
+// stage 2: Q <- Q + dt^2/3 D(Q*)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_stage2(DevMesh m, const T *__restrict__ ff, double *__restrict__ Q,
+                                                   const double *__restrict__ dt_dev)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m.n) return;
+    const double dt = dt_dev[0];
+    double L[5], D[5];
+    gather(m, ff, i, L, D);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Q[(size_t)c * m.n + i] += dt * dt / 3.0 * D[c];
+}
+
+// batch of single Gauss-point fluxes (kernel-level tests)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gp_batch(int64_t n, const double *__restrict__ ql, const double *__restrict__ dql,
+                                                     const double *__restrict__ qr, const double *__restrict__ dqr,
+                                                     const double *__restrict__ dt, double *__restrict__ out,
+                                                     FluxParams<T> fp)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    T a[5], b[5], da[3][5], db[3][5], F[10];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        a[j] = (T)ql[5 * i + j];
+        b[j] = (T)qr[5 * i + j];
+    }
+#pragma unroll
+    for (int mm = 0; mm < 3; ++mm)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            da[mm][j] = (T)dql[15 * i + 5 * mm + j];
+            db[mm][j] = (T)dqr[15 * i + 5 * mm + j];
+        }
+    gp_flux<T>(a, da, b, db, (T)dt[i], fp, F);
+#pragma unroll
+    for (int j = 0; j < 10; ++j) out[10 * i + j] = (double)F[j];
+}
+
+template <typename T>
+static FluxParams<T> flux_params(const gks_params *p)
+{
+    FluxParams<T> f;
+    f.gamma = (T)p->gamma;
+    f.K = (T)((5.0 - 3.0 * p->gamma) / (p->gamma - 1.0));
+    f.mu = (T)p->mu;
+    f.Pr = (T)p->Pr;
+    f.tau_eps = (T)p->tau_eps;
+    f.tau_C = (T)p->tau_C;
+    f.viscous = p->viscous;
+    return f;
+}
+
+}  // namespace gks
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace gks;
+
+struct gks_mesh {
+    DevMesh d;
+    int64_t n, nf;
+    int precision;
+    // optional per-kernel HIP-event timing (gks_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<int, size_t>> rec;  // kernel id, index of its start event
+};
+
+namespace {
+// records a start event before and a stop event after one launch when profiling is on
+struct ProfScope {
+    gks_mesh *m;
+    hipStream_t st;
+    size_t idx = (size_t)-1;
+    ProfScope(gks_mesh *m_, int id, hipStream_t s) : m(m_), st(s)
+    {
+        if (!m->prof) return;
+        while (m->pool.size() < m->used + 2) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            m->pool.push_back(e);
+        }
+        idx = m->used;
+        m->used += 2;
+        m->rec.push_back({id, idx});
+        (void)hipEventRecord(m->pool[idx], st);
+    }
+    ~ProfScope()
+    {
+        if (idx != (size_t)-1) (void)hipEventRecord(m->pool[idx + 1], st);
+    }
+};
+}  // namespace
+
+static hipStream_t S(gks_stream_t s) { return (hipStream_t)s; }
+
+static unsigned grid_for(int64_t threads, int block) { return (unsigned)((threads + block - 1) / block); }
+
+extern "C" {
+
+void gks_default_params(gks_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->gamma = 1.4;
+    p->cfl = 0.5;
+    p->mu = 0.0;
+    p->Pr = 1.0;
+    p->weno_eps = 1e-6;
+    p->weno_gamma_m = 0.0125;
+    p->weno_p = 1.0;
+    p->tau_eps = 0.01;
+    p->tau_C = 1.0;
+}
+
+const char *gks_last_error(void) { return g_err.c_str(); }
+
+gks_status gks_preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, const int8_t *types,
+                          const int64_t *cells, const double *box, int periodic, gks_host_mesh **out)
+{
+    if (!out) return fail(GKS_EINVAL, "null output");
+    *out = nullptr;
+    gks_host_mesh *h = new (std::nothrow) gks_host_mesh;
+    if (!h) return fail(GKS_EINVAL, "out of host memory");
+    gks_status s;
+    try {
+        s = preprocess(n_nodes, nodes, n_cells, types, cells, box, periodic, h->h);
+    } catch (const std::exception &e) {
+        s = fail(GKS_EINVAL, std::string("preprocessing failed: ") + e.what());
+    }
+    if (s != GKS_OK) {
+        delete h;
+        return s;
+    }
+    *out = h;
+    return GKS_OK;
+}
+
+void gks_host_mesh_free(gks_host_mesh *h) { delete h; }
+
+gks_status gks_host_mesh_counts(const gks_host_mesh *h, int64_t *n_cells, int64_t *n_faces, int64_t *n_stencil,
+                                int64_t *n_subcoef, int64_t *n_grown)
+{
+    if (!h) return fail(GKS_EINVAL, "null mesh");
+    if (n_cells) *n_cells = h->h.n;
+    if (n_faces) *n_faces = h->h.nf;
+    if (n_stencil) *n_stencil = (int64_t)h->h.st_idx.size();
+    if (n_subcoef) *n_subcoef = (int64_t)h->h.sc.size() / 3;
+    if (n_grown) *n_grown = h->h.n_grown;
+    return GKS_OK;
+}
+
+gks_status gks_host_mesh_perm(const gks_host_mesh *h, int64_t *perm)
+{
+    if (!h || !perm) return fail(GKS_EINVAL, "null argument");
+    std::memcpy(perm, h->h.perm.data(), sizeof(int64_t) * h->h.n);
+    return GKS_OK;
+}
+
+gks_status gks_host_mesh_geometry(const gks_host_mesh *h, double *vol, double *xc)
+{
+    if (!h) return fail(GKS_EINVAL, "null mesh");
+    if (vol) std::memcpy(vol, h->h.vol.data(), sizeof(double) * h->h.n);
+    if (xc) std::memcpy(xc, h->h.xc.data(), sizeof(double) * 3 * h->h.n);
+    return GKS_OK;
+}
+
+gks_status gks_host_mesh_faces(const gks_host_mesh *h, int32_t *owner, int32_t *nbr)
+{
+    if (!h) return fail(GKS_EINVAL, "null mesh");
+    if (owner) std::memcpy(owner, h->h.owner.data(), sizeof(int32_t) * h->h.nf);
+    if (nbr) std::memcpy(nbr, h->h.nbr.data(), sizeof(int32_t) * h->h.nf);
+    return GKS_OK;
+}
+
+// mesh arena layout (offsets only when base == nullptr)
+static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *base,
+                          std::vector<std::pair<size_t, std::pair<const void *, size_t>>> *copies,
+                          std::vector<std::vector<char>> *owned)
+{
+    const size_t es = precision == GKS_FP32_MIXED ? 4 : 8;
+    size_t off = 0;
+    auto put = [&](const void *src, size_t bytes) -> void * {
+        size_t o = off;
+        off = align256(off + (bytes ? bytes : 1));
+        if (copies && bytes) copies->push_back({o, {src, bytes}});
+        return base ? (void *)(base + o) : nullptr;
+    };
+    auto put_vec = [&](std::vector<char> &&v) -> void * {
+        if (!owned) return put(nullptr, v.size());
+        owned->push_back(std::move(v));
+        return put(owned->back().data(), owned->back().size());
+    };
+    const int64_t n = H.n, nf = H.nf;
+    std::vector<char> M(n), v23(8 * n), m2t(8 * 6 * n);
+    if (owned) {
+        for (int64_t i = 0; i < n; ++i) {
+            const int t = H.type[i];
+            M[i] = (char)(t == 3 ? 8 : t == 2 ? 6 : t == 0 ? 4 : 8);
+            double v = std::cbrt(H.vol[i]);
+            v = v * v;
+            std::memcpy(&v23[8 * i], &v, 8);
+            for (int q = 0; q < 6; ++q) std::memcpy(&m2t[8 * (q * n + i)], &H.m2[6 * i + q], 8);
+        }
+    }
+    auto convert = [&](const std::vector<double> &v) {
+        std::vector<char> out(v.size() * es);
+        if (owned) {
+            if (es == 8)
+                std::memcpy(out.data(), v.data(), out.size());
+            else
+                for (size_t k = 0; k < v.size(); ++k) {
+                    float f = (float)v[k];
+                    std::memcpy(&out[4 * k], &f, 4);
+                }
+        }
+        return out;
+    };
+    DevMesh dm{};
+    dm.n = (int)n;
+    dm.nf = (int)nf;
+    dm.precision = precision;
+    dm.M = (const int8_t *)put_vec(std::move(M));
+    dm.vol = (const double *)put(H.vol.data(), 8 * n);
+    dm.vol23 = (const double *)put_vec(std::move(v23));
+    dm.m2 = (const double *)put_vec(std::move(m2t));
+    dm.hcfl = (const double *)put(H.hcfl.data(), 8 * n);
+    dm.st_ptr = (const int32_t *)put(H.st_ptr.data(), 4 * (n + 1));
+    dm.sc_ptr = (const int32_t *)put(H.sc_ptr.data(), 4 * (n + 1));
+    dm.st_idx = (const int32_t *)put(H.st_idx.data(), 4 * H.st_idx.size());
+    dm.st_mask = (const uint8_t *)put(H.st_mask.data(), H.st_mask.size());
+    dm.pinv = put_vec(convert(H.pinv));
+    dm.sc = put_vec(convert(H.sc));
+    dm.owner = (const int32_t *)put(H.owner.data(), 4 * nf);
+    dm.nbr = (const int32_t *)put(H.nbr.data(), 4 * nf);
+    dm.fgeo = (const double *)put(H.fgeo.data(), 8 * H.fgeo.size());
+    dm.cf_ptr = (const int32_t *)put(H.cf_ptr.data(), 4 * (n + 1));
+    dm.cf_idx = (const int32_t *)put(H.cf_idx.data(), 4 * H.cf_idx.size());
+    if (d) *d = dm;
+    return off;
+}
+
+gks_status gks_mesh_sizes(const gks_host_mesh *h, int precision, size_t *mesh_bytes, size_t *work_bytes)
+{
+    if (!h || (precision != GKS_FP64 && precision != GKS_FP32_MIXED)) return fail(GKS_EINVAL, "bad argument");
+    if (mesh_bytes) *mesh_bytes = mesh_layout(h->h, precision, nullptr, nullptr, nullptr, nullptr);
+    if (work_bytes) *work_bytes = work_layout(h->h.n, h->h.nf, precision, nullptr, nullptr);
+    return GKS_OK;
+}
+
+gks_status gks_init_mesh(const gks_host_mesh *h, int precision, void *mesh_arena, size_t mesh_bytes,
+                         gks_stream_t stream, gks_mesh **out)
+{
+    if (!h || !mesh_arena || !out || (precision != GKS_FP64 && precision != GKS_FP32_MIXED))
+        return fail(GKS_EINVAL, "bad argument");
+    if (((uintptr_t)mesh_arena & 255) != 0) return fail(GKS_EINVAL, "mesh arena must be 256-byte aligned");
+    const size_t need = mesh_layout(h->h, precision, nullptr, nullptr, nullptr, nullptr);
+    if (mesh_bytes < need) return fail(GKS_EINVAL, "mesh arena too small");
+    std::vector<std::pair<size_t, std::pair<const void *, size_t>>> copies;
+    std::vector<std::vector<char>> owned;
+    owned.reserve(16);
+    DevMesh d;
+    mesh_layout(h->h, precision, &d, (char *)mesh_arena, &copies, &owned);
+    for (auto &c : copies) {
+        gks_status s = hip_check(hipMemcpyAsync((char *)mesh_arena + c.first, c.second.first, c.second.second,
+                                                hipMemcpyHostToDevice, S(stream)),
+                                 "mesh upload");
+        if (s) return s;
+    }
+    gks_status s = hip_check(hipStreamSynchronize(S(stream)), "mesh upload sync");
+    if (s) return s;
+    gks_mesh *m = new (std::nothrow) gks_mesh;
+    if (!m) return fail(GKS_EINVAL, "out of host memory");
+    m->d = d;
+    m->n = h->h.n;
+    m->nf = h->h.nf;
+    m->precision = precision;
+    *out = m;
+    return GKS_OK;
+}
+
+void gks_destroy_mesh(gks_mesh *m)
+{
+    if (!m) return;
+    for (hipEvent_t e : m->pool) (void)hipEventDestroy(e);
+    delete m;
+}
+
+gks_status gks_profile(gks_mesh *m, int enable)
+{
+    if (!m) return fail(GKS_EINVAL, "null mesh");
+    m->prof = enable != 0;
+    return GKS_OK;
+}
+
+gks_status gks_profile_read(gks_mesh *m, double *total_ms, int64_t *launches)
+{
+    if (!m || !total_ms || !launches) return fail(GKS_EINVAL, "null argument");
+    for (int k = 0; k < GKS_K_COUNT; ++k) {
+        total_ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    if (!m->rec.empty()) {
+        gks_status s = hip_check(hipEventSynchronize(m->pool[m->rec.back().second + 1]), "profile sync");
+        if (s) return s;
+    }
+    for (auto &r : m->rec) {
+        float ms = 0.0f;
+        gks_status s = hip_check(hipEventElapsedTime(&ms, m->pool[r.second], m->pool[r.second + 1]), "profile read");
+        if (s) return s;
+        total_ms[r.first] += ms;
+        launches[r.first] += 1;
+    }
+    m->rec.clear();
+    m->used = 0;
+    return GKS_OK;
+}
+
+static gks_status check_params(const gks_mesh *m, const gks_params *p)
+{
+    if (!m || !p) return fail(GKS_EINVAL, "null mesh or params");
+    if (p->precision != m->precision) return fail(GKS_EINVAL, "params precision differs from the mesh precision");
+    if (!(p->gamma > 1.0) || !(p->cfl > 0.0)) return fail(GKS_EINVAL, "bad gamma or cfl");
+    if (p->viscous && !(p->mu >= 0.0)) return fail(GKS_EINVAL, "bad viscosity");
+    if (!(p->Pr > 0.0)) return fail(GKS_EINVAL, "bad Prandtl number");
+    return GKS_OK;
+}
+
+static Work work_of(const gks_mesh *m, void *work)
+{
+    Work w;
+    work_layout(m->n, m->nf, m->precision, &w, (char *)work);
+    return w;
+}
+
+gks_status gks_reset_status(gks_mesh *m, void *work, gks_stream_t stream)
+{
+    if (!m || !work) return fail(GKS_EINVAL, "null argument");
+    Work w = work_of(m, work);
+    return hip_check(hipMemsetAsync(w.status, 0, sizeof(int), S(stream)), "status reset");
+}
+
+static gks_status launch_timestep(gks_mesh *m, const double *Q, const gks_params *p, double *dt_dev, Work &w,
+                                  hipStream_t st)
+{
+    ProfScope ps(m, GKS_K_TIMESTEP, st);
+    int nb = (int)std::min<int64_t>(kDtBlocks, grid_for(m->n, kBlock));
+    k_dt_partial<<<nb, kBlock, 0, st>>>((int)m->n, Q, m->d.hcfl, p->gamma, p->cfl, w.dtpart, w.status);
+    k_dt_final<<<1, kBlock, 0, st>>>(nb, w.dtpart, dt_dev);
+    return hip_check(hipGetLastError(), "timestep launch");
+}
+
+gks_status gks_timestep(gks_mesh *m, const double *Q, const gks_params *p, double *dt_dev, void *work,
+                        gks_stream_t stream)
+{
+    gks_status s = check_params(m, p);
+    if (s) return s;
+    if (!Q || !dt_dev || !work) return fail(GKS_EINVAL, "null argument");
+    Work w = work_of(m, work);
+    return launch_timestep(m, Q, p, dt_dev, w, S(stream));
+}
+
+static WenoParams weno_params(const gks_params *p)
+{
+    return WenoParams{p->weno_eps, p->weno_gamma_m, p->weno_p, p->force_linear};
+}
+
+static gks_status launch_reconstruct(gks_mesh *m, const double *Q, void *coeff, const gks_params *p, hipStream_t st)
+{
+    const unsigned grid = grid_for(5 * m->n, kK1Block);
+    ProfScope ps(m, GKS_K_RECONSTRUCT, st);
+    if (m->precision == GKS_FP64)
+        k_reconstruct<double><<<grid, kK1Block, 0, st>>>(m->d, Q, (double *)coeff, weno_params(p));
+    else
+        k_reconstruct<float><<<grid, kK1Block, 0, st>>>(m->d, Q, (float *)coeff, weno_params(p));
+    return hip_check(hipGetLastError(), "reconstruct launch");
+}
+
+static gks_status launch_flux(gks_mesh *m, const void *coeff, const double *Q, const double *dt_dev, void *ff,
+                              const gks_params *p, Work &w, hipStream_t st)
+{
+    const unsigned grid = grid_for(4 * m->nf, kBlock);
+    ProfScope ps(m, GKS_K_FLUX, st);
+    if (m->precision == GKS_FP64)
+        k_flux<double><<<grid, kBlock, 0, st>>>(m->d, (const double *)coeff, Q, dt_dev, (double *)ff,
+                                                flux_params<double>(p), w.status);
+    else
+        k_flux<float><<<grid, kBlock, 0, st>>>(m->d, (const float *)coeff, Q, dt_dev, (float *)ff,
+                                               flux_params<float>(p), w.status);
+    return hip_check(hipGetLastError(), "flux launch");
+}
+
+gks_status gks_reconstruct(gks_mesh *m, const double *Q, void *coeff, const gks_params *p, void *work,
+                           gks_stream_t stream)
+{
+    gks_status s = check_params(m, p);
+    if (s) return s;
+    if (!Q || !coeff) return fail(GKS_EINVAL, "null argument");
+    (void)work;
+    return launch_reconstruct(m, Q, coeff, p, S(stream));
+}
+
+gks_status gks_flux(gks_mesh *m, const void *coeff, const double *Q, const double *dt_dev, void *face_flux,
+                    const gks_params *p, void *work, gks_stream_t stream)
+{
+    gks_status s = check_params(m, p);
+    if (s) return s;
+    if (!coeff || !Q || !dt_dev || !face_flux || !work) return fail(GKS_EINVAL, "null argument");
+    Work w = work_of(m, work);
+    return launch_flux(m, coeff, Q, dt_dev, face_flux, p, w, S(stream));
+}
+
+gks_status gks_residual(gks_mesh *m, const void *face_flux, double *L, double *dL, const gks_params *p,
+                        gks_stream_t stream)
+{
+    gks_status s = check_params(m, p);
+    if (s) return s;
+    if (!face_flux || !L || !dL) return fail(GKS_EINVAL, "null argument");
+    const unsigned grid = grid_for(m->n, kBlock);
+    ProfScope ps(m, GKS_K_RESIDUAL, S(stream));
+    if (m->precision == GKS_FP64)
+        k_residual<double><<<grid, kBlock, 0, S(stream)>>>(m->d, (const double *)face_flux, L, dL);
+    else
+        k_residual<float><<<grid, kBlock, 0, S(stream)>>>(m->d, (const float *)face_flux, L, dL);
+    return hip_check(hipGetLastError(), "residual launch");
+}
+
+gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_params *p, void *work, double *Q_star,
+                         gks_stream_t stream)
+{
+    gks_status s = check_params(m, p);
+    if (s) return s;
+    if (!Q || !dt_dev || !work) return fail(GKS_EINVAL, "null argument");
+    hipStream_t st = S(stream);
+    Work w = work_of(m, work);
+    if (!p->dt_given && (s = launch_timestep(m, Q, p, dt_dev, w, st))) return s;
+    const unsigned gc = grid_for(m->n, kBlock);
+    // stage 1
+    if ((s = launch_reconstruct(m, Q, w.coeff, p, st))) return s;
+    if ((s = launch_flux(m, w.coeff, Q, dt_dev, w.ff, p, w, st))) return s;
+    {
+    ProfScope ps(m, GKS_K_STAGE1, st);
+    if (m->precision == GKS_FP64)
+        k_stage1<double><<<gc, kBlock, 0, st>>>(m->d, (const double *)w.ff, Q, w.Qs, dt_dev);
+    else
+        k_stage1<float><<<gc, kBlock, 0, st>>>(m->d, (const float *)w.ff, Q, w.Qs, dt_dev);
+    }
+    if ((s = hip_check(hipGetLastError(), "stage-1 launch"))) return s;
+    // stage 2
+    if ((s = launch_reconstruct(m, w.Qs, w.coeff, p, st))) return s;
+    if ((s = launch_flux(m, w.coeff, w.Qs, dt_dev, w.ff, p, w, st))) return s;
+    {
+    ProfScope ps(m, GKS_K_STAGE2, st);
+    if (m->precision == GKS_FP64)
+        k_stage2<double><<<gc, kBlock, 0, st>>>(m->d, (const double *)w.ff, Q, dt_dev);
+    else
+        k_stage2<float><<<gc, kBlock, 0, st>>>(m->d, (const float *)w.ff, Q, dt_dev);
+    }
+    if ((s = hip_check(hipGetLastError(), "stage-2 launch"))) return s;
+    if (Q_star)
+        return hip_check(hipMemcpyAsync(Q_star, w.Qs, sizeof(double) * 5 * m->n, hipMemcpyDeviceToDevice, st),
+                         "Q* copy");
+    return GKS_OK;
+}
+
+gks_status gks_poll_status(gks_mesh *m, void *work, gks_stream_t stream)
+{
+    if (!m || !work) return fail(GKS_EINVAL, "null argument");
+    Work w = work_of(m, work);
+    int flag = 0;
+    gks_status s = hip_check(hipMemcpyAsync(&flag, w.status, sizeof(int), hipMemcpyDeviceToHost, S(stream)), "status read");
+    if (s) return s;
+    if ((s = hip_check(hipStreamSynchronize(S(stream)), "status sync"))) return s;
+    if (flag) return fail(GKS_ENONPHYS, "non-physical state (rho <= 0 or p <= 0) met in a kernel");
+    return GKS_OK;
+}
+
+gks_status gks_gp_flux_batch(int64_t n, const double *ql, const double *dql, const double *qr, const double *dqr,
+                             const double *dt, double *out, const gks_params *p, gks_stream_t stream)
+{
+    if (n < 0 || !p || (n > 0 && (!ql || !dql || !qr || !dqr || !dt || !out))) return fail(GKS_EINVAL, "bad argument");
+    if (n == 0) return GKS_OK;
+    const unsigned grid = grid_for(n, kBlock);
+    if (p->precision == GKS_FP32_MIXED)
+        k_gp_batch<float><<<grid, kBlock, 0, S(stream)>>>(n, ql, dql, qr, dqr, dt, out, flux_params<float>(p));
+    else
+        k_gp_batch<double><<<grid, kBlock, 0, S(stream)>>>(n, ql, dql, qr, dqr, dt, out, flux_params<double>(p));
+    return hip_check(hipGetLastError(), "gp flux launch");
+}
+
+}  // extern "C"

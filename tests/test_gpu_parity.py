@@ -1,0 +1,273 @@
+"""GPU parity of the HIP path against the FP64 oracle (needs an MI355X).
+
+Every comparison runs the HIP kernels through the C ABI (via the ctypes
+binding) and the oracle on the same seeded inputs.  FP64 parity bar: relative
+L-infinity per conserved component <= 1e-12 (max_i |dQ_ci| / max_i |Q_ci|).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_09047_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def rel_linf(got, ref):
+    got, ref = np.asarray(got), np.asarray(ref)
+    scale = np.abs(ref).max(axis=-1)
+    scale = np.where(scale == 0, 1.0, scale)
+    return np.abs(got - ref).max(axis=-1) / scale
+
+
+@pytest.fixture(scope="module")
+def gks():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2203_09047_amd import gks as g
+
+    g.load()
+    return g
+
+
+def _states(rng, n, jump=0.3):
+    def prim_to_cons(rho, U, p):
+        return np.c_[rho, rho[:, None] * U, p / 0.4 + 0.5 * rho * (U ** 2).sum(1)]
+
+    ql = prim_to_cons(1 + jump * rng.random(n), 0.5 * rng.standard_normal((n, 3)), 1 + jump * rng.random(n))
+    qr = prim_to_cons(0.6 + jump * rng.random(n), 0.5 * rng.standard_normal((n, 3)), 0.7 + jump * rng.random(n))
+    dql = 0.3 * rng.standard_normal((n, 3, 5))
+    dqr = 0.3 * rng.standard_normal((n, 3, 5))
+    dt = 0.005 + 0.03 * rng.random(n)
+    return ql, dql, qr, dqr, dt
+
+
+@pytest.mark.parametrize("viscous", [False, True])
+def test_gauss_point_flux_matches_oracle(gks, viscous):
+    rng = np.random.default_rng(100 + viscous)
+    n = 1000
+    ql, dql, qr, dqr, dt = _states(rng, n)
+    kw = dict(viscous=viscous, mu=2e-3, Pr=0.72) if viscous else {}
+    print("case: gp flux batch n=%d viscous=%d" % (n, viscous), flush=True)
+    got = gks.gp_flux_batch(ql, dql, qr, dqr, dt, **kw)
+    prm = oracle.params(**kw)
+    ref = np.array([oracle.gp_flux(prm, ql[i], dql[i], qr[i], dqr[i], dt[i])[0] for i in range(n)])
+    err = np.abs(got - ref) / (np.abs(ref).max(axis=0) + 1e-300)
+    assert err.max() < 1e-12, err.max(axis=0)
+
+
+def test_gauss_point_flux_fp32_error_is_small(gks):
+    rng = np.random.default_rng(7)
+    n = 500
+    ql, dql, qr, dqr, dt = _states(rng, n)
+    got = gks.gp_flux_batch(ql, dql, qr, dqr, dt, precision=gks.FP32_MIXED)
+    prm = oracle.params()
+    ref = np.array([oracle.gp_flux(prm, ql[i], dql[i], qr[i], dqr[i], dt[i])[0] for i in range(n)])
+    err = np.abs(got - ref) / (np.abs(ref).max(axis=0) + 1e-300)
+    print("fp32 gp flux relative error per output:", err.max(axis=0))
+    assert err[:, :5].max() < 1e-4
+    assert err[:, 5:].max() < 1e-2
+
+
+def test_gp_flux_batch_empty_and_single(gks):
+    z = np.zeros((0, 5))
+    out = gks.gp_flux_batch(z, np.zeros((0, 3, 5)), z, np.zeros((0, 3, 5)), np.zeros(0))
+    assert out.shape == (0, 10)
+    rng = np.random.default_rng(1)
+    ql, dql, qr, dqr, dt = _states(rng, 1)
+    got = gks.gp_flux_batch(ql, dql, qr, dqr, dt)
+    ref, _ = oracle.gp_flux(oracle.params(), ql[0], dql[0], qr[0], dqr[0], dt[0])
+    assert np.abs(got[0] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _poly_eval(c, X):
+    """Value and gradient of the per-cell quadratic [5,10] at offset X from the centroid."""
+    x, y, z = X
+    mono = np.array([1, x, y, z, x * x, x * y, x * z, y * y, y * z, z * z])
+    dm = np.array([[0, 1, 0, 0, 2 * x, y, z, 0, 0, 0], [0, 0, 1, 0, 0, x, 0, 2 * y, z, 0],
+                   [0, 0, 0, 1, 0, 0, x, 0, y, 2 * z]])
+    return c @ mono, c @ dm.T
+
+
+@pytest.mark.parametrize("kind,N", [("hex", 6), ("tet", 4), ("pyr", 4), ("prism", 4), ("hybrid", 6)])
+def test_reconstruction_matches_oracle(gks, kind, N):
+    import torch
+
+    print(f"case: reconstruct {kind} N={N}", flush=True)
+    mesh = inputs.lattice(N, kind)
+    Q0 = inputs.cell_averages(mesh, inputs.perturbed_wave(amp=0.3, kmax=2, rms=0.1))
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host)
+    Q = sol.upload(host.to_internal(Q0))
+    coeff = sol.reconstruct(Q).cpu().numpy()
+    torch.cuda.synchronize()
+    o = oracle.Oracle(mesh)
+    vol, xc, _, _ = o.cell_geometry()
+    rng = np.random.default_rng(3)
+    worst = 0.0
+    for i in range(0, host.n, max(1, host.n // 150)):
+        ext = host.perm[i]
+        X = 0.3 * vol[ext] ** (1 / 3) * rng.standard_normal(3)
+        v, g = _poly_eval(coeff[i], X)
+        rv, rg = o.weno_eval(Q0, ext, xc[ext] + X)
+        worst = max(worst, (np.abs(v - rv) / np.abs(Q0).max(axis=1)).max())
+        np.testing.assert_allclose(v, rv, rtol=0, atol=TOL * np.abs(Q0).max())
+        np.testing.assert_allclose(g, rg, rtol=0, atol=1e-10 * np.abs(rg).max() + 1e-13)
+    print("max relative value error", worst)
+
+
+@pytest.mark.parametrize("kind,N", [("hex", 5), ("hybrid", 5)])
+def test_residual_matches_oracle(gks, kind, N):
+    import torch
+
+    print(f"case: residual {kind} N={N}", flush=True)
+    mesh = inputs.lattice(N, kind)
+    Q0 = inputs.cell_averages(mesh, inputs.perturbed_wave(amp=0.3, kmax=1, rms=0.1))
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host)
+    Q = sol.upload(host.to_internal(Q0))
+    dt = 3e-3
+    ff = sol.flux(sol.reconstruct(Q), Q, dt)
+    L, D = sol.residual(ff)
+    sol.poll()
+    L = host.to_external(L.cpu().numpy())
+    D = host.to_external(D.cpu().numpy())
+    rL, rD = oracle.Oracle(mesh).residual(Q0, dt)
+    assert (rel_linf(L, rL) < 1e-11).all(), rel_linf(L, rL)
+    assert (rel_linf(D, rD) < 1e-10).all(), rel_linf(D, rD)
+
+
+def _run_both(gks, mesh, Q0, nsteps=0, t_end=0.0, precision=0):
+    import torch
+
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host, gks.params(precision=precision))
+    Q = sol.upload(host.to_internal(Q0))
+    dts = sol.run(Q, nsteps=nsteps, t_end=t_end)
+    sol.poll()
+    torch.cuda.synchronize()
+    got = host.to_external(Q.cpu().numpy())
+    o = oracle.Oracle(mesh)
+    if t_end > 0:
+        ref, rdts = o.run(Q0, t_end=t_end)
+    else:
+        ref, rdts = o.run(Q0, nsteps=nsteps)
+    return got, ref, host, sol, o
+
+
+def test_config1_hex_8cubed_ten_steps_fp64_parity(gks):
+    """Uniform 8^3 hexahedra, density wave, CFL 0.5, 10 steps: relative Linf <= 1e-12 per component."""
+    print("case: config1 hex 8^3 x 10 steps", flush=True)
+    mesh = inputs.lattice(8, "hex")
+    Q0 = inputs.cell_averages(mesh, inputs.wave())
+    got, ref, *_ = _run_both(gks, mesh, Q0, nsteps=10)
+    err = rel_linf(got, ref)
+    print("config1 relative Linf per component:", err)
+    assert (err <= TOL).all(), err
+
+
+@pytest.mark.parametrize("kind,N,steps", [("hybrid", 8, 4), ("tet", 5, 3), ("pyr", 5, 3), ("prism", 6, 3)])
+def test_hybrid_steps_fp64_parity(gks, kind, N, steps):
+    print(f"case: {kind} N={N} x {steps} steps", flush=True)
+    mesh = inputs.lattice(N, kind)
+    Q0 = inputs.cell_averages(mesh, inputs.wave())
+    got, ref, *_ = _run_both(gks, mesh, Q0, nsteps=steps)
+    err = rel_linf(got, ref)
+    print(kind, "relative Linf per component:", err)
+    assert (err <= TOL).all(), err
+
+
+def test_fp32_mixed_error_against_oracle(gks):
+    print("case: fp32-mixed hybrid N=6 x 3 steps", flush=True)
+    mesh = inputs.lattice(6, "hybrid")
+    Q0 = inputs.cell_averages(mesh, inputs.wave())
+    got, ref, host, sol, o = _run_both(gks, mesh, Q0, nsteps=3, precision=1)
+    vol, _, _, _ = o.cell_geometry()
+    err = rel_linf(got, ref)
+    l1 = (np.abs(got - ref) * vol).sum(axis=1)
+    print("fp32-mixed relative Linf:", err, "L1:", l1)
+    assert (err < 1e-5).all(), err
+
+
+def test_free_stream_and_conservation_on_gpu(gks):
+    import torch
+
+    mesh = inputs.lattice(10, "hybrid")
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host)
+    vol, _ = host.geometry()
+    U = host.to_internal(inputs.cell_averages(mesh, inputs.uniform(1.3, 0.3, -0.2, 0.5, 0.9)))
+    Q = sol.upload(U)
+    sol.run(Q, nsteps=2)
+    sol.poll()
+    np.testing.assert_allclose(Q.cpu().numpy(), U, rtol=0, atol=5e-15 * np.abs(U).max())
+    W = host.to_internal(inputs.cell_averages(mesh, inputs.perturbed_wave(amp=0.4, kmax=2, rms=0.1)))
+    Q = sol.upload(W)
+    sol.run(Q, nsteps=2)
+    torch.cuda.synchronize()
+    tot0 = (W * vol).sum(axis=1)
+    tot1 = (Q.cpu().numpy() * vol).sum(axis=1)
+    np.testing.assert_allclose(tot1, tot0, rtol=1e-14, atol=1e-15)
+
+
+def test_bitwise_deterministic(gks):
+    mesh = inputs.lattice(8, "hybrid")
+    host = gks.HostMesh(mesh)
+    W = host.to_internal(inputs.cell_averages(mesh, inputs.wave()))
+    outs = []
+    for _ in range(2):
+        sol = gks.Solver(host)
+        Q = sol.upload(W)
+        sol.run(Q, nsteps=3)
+        outs.append(Q.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_non_physical_state_is_reported(gks):
+    mesh = inputs.lattice(4, "hex")
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host)
+    W = host.to_internal(inputs.cell_averages(mesh, inputs.wave()))
+    W[0, 7] = -0.5  # negative density planted on the host
+    Q = sol.upload(W)
+    sol.step(Q, 1e-3)
+    with pytest.raises(gks.GksError) as e:
+        sol.poll()
+    assert e.value.code == gks.GKS_ENONPHYS
+
+
+def test_bad_arguments_rejected(gks):
+    mesh = inputs.lattice(3, "hex")
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host)
+    p = gks.params(precision=gks.FP32_MIXED)  # differs from the mesh precision
+    import ctypes
+
+    code = gks.load().gks_timestep(sol.m, ctypes.c_void_p(sol.dt.data_ptr()), ctypes.byref(p),
+                                   ctypes.c_void_p(sol.dt.data_ptr()), sol._work_ptr, sol._s())
+    assert code == gks.GKS_EINVAL
+
+
+@pytest.mark.slow
+def test_convergence_order_on_gpu(gks):
+    """Hybrid lattice, density wave to t = 0.1: third-order convergence between N = 16 and 32."""
+    errs = []
+    for N in (16, 32):
+        mesh = inputs.lattice(N, "hybrid")
+        host = gks.HostMesh(mesh)
+        sol = gks.Solver(host)
+        Q = sol.upload(host.to_internal(inputs.cell_averages(mesh, inputs.wave())))
+        sol.run(Q, t_end=0.1)
+        vol, _ = host.geometry()
+        ex = host.to_internal(inputs.cell_averages(mesh, inputs.wave(t=0.1)))
+        e = Q.cpu().numpy()[0] - ex[0]
+        errs.append(((np.abs(e) * vol).sum(), np.abs(e).max()))
+        print(f"N={N} cells={host.n} L1={errs[-1][0]:.4e} Linf={errs[-1][1]:.4e}", flush=True)
+    order = math.log2(errs[0][0] / errs[1][0])
+    print("order", order)
+    assert order > 2.5

@@ -1,0 +1,88 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library loads, exports every entry point declared in include/gks.h, and
+its host preprocessor (connectivity, geometry, stencils) agrees with the
+oracle's independent construction.  No compute entry point is called here.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_09047_amd import gks, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "gks.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gks_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = gks.load()
+    names = declared_symbols()
+    assert "gks_s2o4_step" in names and "gks_flux" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(gks.SYMBOLS) <= set(names)
+
+
+def test_default_params_follow_the_paper():
+    p = gks.params()
+    assert p.gamma == 1.4 and p.weno_gamma_m == 0.0125 and p.tau_eps == 0.01 and p.tau_C == 1.0
+
+
+@pytest.mark.parametrize("kind,N", [("hex", 4), ("tet", 3), ("pyr", 3), ("prism", 3), ("hybrid", 6)])
+def test_preprocessor_matches_oracle_construction(kind, N):
+    mesh = inputs.lattice(N, kind)
+    host = gks.HostMesh(mesh)
+    o = oracle.Oracle(mesh)
+    assert host.n == mesh.n_cells
+    assert host.n_faces == o.n_faces
+    assert sorted(host.perm.tolist()) == list(range(host.n))
+    assert host.n_grown == sum(o.grown(c) for c in range(mesh.n_cells))
+    vol, xc = host.geometry()
+    ovol, oxc, _, _ = o.cell_geometry()
+    np.testing.assert_allclose(vol, ovol[host.perm], rtol=1e-14, atol=0)
+    np.testing.assert_allclose(xc, oxc[host.perm], rtol=0, atol=1e-15)
+    owner, nbr = host.faces()
+    assert (owner < nbr).all() or kind == "hex" and N < 3
+    # same set of neighbouring cell pairs
+    fi = o.face_info()
+    pairs = sorted(tuple(sorted((host.perm[a], host.perm[b]))) for a, b in zip(owner, nbr))
+    opairs = sorted(tuple(sorted((a, b))) for a, b in zip(fi["owner"], fi["nbr"]))
+    assert pairs == opairs
+
+
+def test_preprocessor_rejects_bad_meshes():
+    mesh = inputs.lattice(3, "hex")
+    bad_types = mesh.types.copy()
+    bad_types[0] = 7
+    h = ctypes.c_void_p()
+    lib = gks.load()
+    nodes = np.ascontiguousarray(mesh.nodes)
+    cells = np.ascontiguousarray(mesh.cells)
+    box = np.asarray(mesh.box, float)
+    code = lib.gks_preprocess(nodes.shape[0], gks._np(nodes), len(bad_types), gks._np(bad_types), gks._np(cells),
+                              gks._np(box), 1, ctypes.byref(h))
+    assert code == gks.GKS_EINVAL
+    # drop one cell: the mesh is no longer closed
+    code = lib.gks_preprocess(nodes.shape[0], gks._np(nodes), len(mesh.types) - 1, gks._np(mesh.types),
+                              gks._np(cells), gks._np(box), 1, ctypes.byref(h))
+    assert code == gks.GKS_EMESH
+    assert b"face" in lib.gks_last_error()
+
+
+def test_solver_refuses_to_run_without_gpu():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    host = gks.HostMesh(inputs.lattice(3, "hex"))
+    with pytest.raises(gks.GksError):
+        gks.Solver(host)
