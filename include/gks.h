@@ -221,6 +221,16 @@ enum {
 gks_status gks_profile(gks_mesh *m, int enable);
 gks_status gks_profile_read(gks_mesh *m, double *total_ms, int64_t *launches);
 
+/*
+ * Floating-point operations of one face Gauss point of the flux kernel
+ * (two-sided state evaluation, frame, BGK flux with both time integrals,
+ * rotation back), counted by executing the kernel's templated body on the
+ * host with an operation-counting number type: additions/subtractions,
+ * multiplications, divisions, and transcendental calls (erfc, exp, expm1,
+ * sqrt).  viscous/Pr select the collision-time and Prandtl branches.
+ */
+gks_status gks_gp_op_count(int viscous, double Pr, int64_t *adds, int64_t *muls, int64_t *divs, int64_t *transc);
+
 const char *gks_last_error(void);
 
 #ifdef __cplusplus

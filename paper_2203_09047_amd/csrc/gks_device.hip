@@ -27,6 +27,7 @@
 
 #include "gks_flux.h"
 #include "gks_internal.h"
+#include "gks_opcount.h"
 
 namespace gks {
 
@@ -58,8 +59,7 @@ struct DevMesh {
     const double *hcfl;     // 6 |Omega| / sum of face areas
     const int32_t *st_ptr;  // [n+1]
     const int32_t *sc_ptr;  // [n+1] (units of 3 coefficients)
-    const int32_t *st_idx;  // members
-    const uint8_t *st_mask;
+    const int2 *st_rec;     // members: {cell, mask | (relative coefficient offset << 8)}
     const void *pinv;       // [nnz][9], FP64 or FP32
     const void *sc;         // [nsc][3], FP64 or FP32
     // faces
@@ -183,18 +183,21 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
     const T *pinv = (const T *)m.pinv;
     const T *sc = (const T *)m.sc;
     const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
-    int e = m.sc_ptr[i];
+    const int e0 = m.sc_ptr[i];
     T a[9], b[8][3];
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = T(0);
 #pragma unroll
     for (int s = 0; s < 8; ++s) b[s][0] = b[s][1] = b[s][2] = T(0);
+#pragma unroll 2
     for (int k = k0; k < k1; ++k) {
-        const T d = (T)(Qc[m.st_idx[k]] - q0);
+        const int2 rec = m.st_rec[k];
+        const T d = (T)(Qc[rec.x] - q0);
         const T *row = pinv + (size_t)9 * k;
 #pragma unroll
         for (int j = 0; j < 9; ++j) a[j] += row[j] * d;
-        const unsigned mask = m.st_mask[k];
+        const unsigned mask = (unsigned)rec.y & 255u;
+        int e = e0 + (rec.y >> 8);
 #pragma unroll
         for (int s = 0; s < 8; ++s)
             if (mask & (1u << s)) {
@@ -273,64 +276,12 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
 // K2: face flux, one lane per (face, Gauss point)
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void local_frame(T vx, T vy, T vz, T n[3][3], T &area)
-{
-    area = sqrt_t(vx * vx + vy * vy + vz * vz);
-    const T ia = T(1) / area;
-    n[0][0] = vx * ia;
-    n[0][1] = vy * ia;
-    n[0][2] = vz * ia;
-    const T ax = n[0][0] < T(0) ? -n[0][0] : n[0][0];
-    const T ay = n[0][1] < T(0) ? -n[0][1] : n[0][1];
-    const T az = n[0][2] < T(0) ? -n[0][2] : n[0][2];
-    int e = 0;
-    T best = ax;
-    if (ay < best) {
-        e = 1;
-        best = ay;
-    }
-    if (az < best) e = 2;
-    T t[3] = {T(0), T(0), T(0)};
-    t[e] = T(1);
-    const T d = n[0][e];
-    t[0] -= d * n[0][0];
-    t[1] -= d * n[0][1];
-    t[2] -= d * n[0][2];
-    const T it = T(1) / sqrt_t(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
-    n[1][0] = t[0] * it;
-    n[1][1] = t[1] * it;
-    n[1][2] = t[2] * it;
-    n[2][0] = n[0][1] * n[1][2] - n[0][2] * n[1][1];
-    n[2][1] = n[0][2] * n[1][0] - n[0][0] * n[1][2];
-    n[2][2] = n[0][0] * n[1][1] - n[0][1] * n[1][0];
-}
-
-template <typename T>
-__device__ __forceinline__ void rotate_in(const T n[3][3], const T v[5], const T g[5][3], T q[5], T dq[3][5])
-{
-    q[0] = v[0];
-    q[4] = v[4];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) q[1 + k] = v[1] * n[k][0] + v[2] * n[k][1] + v[3] * n[k][2];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        T dn[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) dn[c] = g[c][0] * n[m][0] + g[c][1] * n[m][1] + g[c][2] * n[m][2];
-        dq[m][0] = dn[0];
-        dq[m][4] = dn[4];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) dq[m][1 + k] = dn[1] * n[k][0] + dn[2] * n[k][1] + dn[3] * n[k][2];
-    }
-}
-
-template <typename T>
 __device__ __forceinline__ T shfl_xor_t(T v, int mask)
 {
     return __shfl_xor(v, mask, 64);
 }
 
-template <typename T>
+template <typename T, bool PR>
 __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict__ coeff, const double *__restrict__ Q,
                                                  const double *__restrict__ dt_dev, T *__restrict__ ff, FluxParams<T> fp,
                                                  int *status)
@@ -342,74 +293,21 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict_
     const int nf4 = 4 * m.nf;
     const int tt = 4 * fs + (t & 3);
     const int o = m.owner[fs], nb = m.nbr[fs];
-    const double *G = m.fgeo;
-    const T dLx = (T)G[tt], dLy = (T)G[nf4 + tt], dLz = (T)G[2 * nf4 + tt];
-    const T dRx = (T)G[3 * nf4 + tt], dRy = (T)G[4 * nf4 + tt], dRz = (T)G[5 * nf4 + tt];
-    const T vx = (T)G[6 * nf4 + tt], vy = (T)G[7 * nf4 + tt], vz = (T)G[8 * nf4 + tt];
-    T n3[3][3], area;
-    local_frame(vx, vy, vz, n3, area);
-    T ql[5], qr[5], dql[3][5], dqr[3][5];
-    // left (owner)
-    {
-        T cc[50];
-        const T *src = coeff + (size_t)50 * o;
+    T geo[9];
 #pragma unroll
-        for (int j = 0; j < 50; ++j) cc[j] = src[j];
-        T vv[5], gg[5][3];
+    for (int q = 0; q < 9; ++q) geo[q] = (T)m.fgeo[(size_t)q * nf4 + tt];
+    double ql0[5], qr0[5];
+    if constexpr (sizeof(T) == 4) {
 #pragma unroll
-        for (int comp = 0; comp < 5; ++comp) {
-            const double q0 = sizeof(T) == 8 ? 0.0 : Q[(size_t)comp * m.n + o];
-            const T *c = cc + 10 * comp;
-            const T X = dLx, Y = dLy, Z = dLz;
-            const T lin = c[1] * X + c[2] * Y + c[3] * Z;
-            const T qua = c[4] * X * X + c[5] * X * Y + c[6] * X * Z + c[7] * Y * Y + c[8] * Y * Z + c[9] * Z * Z;
-            if constexpr (sizeof(T) == 8)
-                vv[comp] = c[0] + lin + qua;
-            else
-                vv[comp] = (T)(q0 + (double)(c[0] + lin + qua));
-            gg[comp][0] = c[1] + T(2) * c[4] * X + c[5] * Y + c[6] * Z;
-            gg[comp][1] = c[2] + c[5] * X + T(2) * c[7] * Y + c[8] * Z;
-            gg[comp][2] = c[3] + c[6] * X + c[8] * Y + T(2) * c[9] * Z;
+        for (int c = 0; c < 5; ++c) {
+            ql0[c] = Q[(size_t)c * m.n + o];
+            qr0[c] = Q[(size_t)c * m.n + nb];
         }
-        rotate_in(n3, vv, gg, ql, dql);
-    }
-    {
-        T cc[50];
-        const T *src = coeff + (size_t)50 * nb;
-#pragma unroll
-        for (int j = 0; j < 50; ++j) cc[j] = src[j];
-        T vv[5], gg[5][3];
-#pragma unroll
-        for (int comp = 0; comp < 5; ++comp) {
-            const double q0 = sizeof(T) == 8 ? 0.0 : Q[(size_t)comp * m.n + nb];
-            const T *c = cc + 10 * comp;
-            const T X = dRx, Y = dRy, Z = dRz;
-            const T lin = c[1] * X + c[2] * Y + c[3] * Z;
-            const T qua = c[4] * X * X + c[5] * X * Y + c[6] * X * Z + c[7] * Y * Y + c[8] * Y * Z + c[9] * Z * Z;
-            if constexpr (sizeof(T) == 8)
-                vv[comp] = c[0] + lin + qua;
-            else
-                vv[comp] = (T)(q0 + (double)(c[0] + lin + qua));
-            gg[comp][0] = c[1] + T(2) * c[4] * X + c[5] * Y + c[6] * Z;
-            gg[comp][1] = c[2] + c[5] * X + T(2) * c[7] * Y + c[8] * Z;
-            gg[comp][2] = c[3] + c[6] * X + c[8] * Y + T(2) * c[9] * Z;
-        }
-        rotate_in(n3, vv, gg, qr, dqr);
     }
     const T dt = (T)dt_dev[0];
-    T F[10];
-    const bool ok = gp_flux<T>(ql, dql, qr, dqr, dt, fp, F);
-    if (live && !ok) status[0] = 1;
-    // rotate back, weight by the Gauss point's area, sum over the face's four lanes
     T out[10];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        const T *Fl = F + 5 * s;
-        out[5 * s] = area * Fl[0];
-        out[5 * s + 4] = area * Fl[4];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) out[5 * s + 1 + q] = area * (Fl[1] * n3[0][q] + Fl[2] * n3[1][q] + Fl[3] * n3[2][q]);
-    }
+    const bool ok = face_gp<T, PR>(coeff + (size_t)50 * o, coeff + (size_t)50 * nb, ql0, qr0, geo, dt, fp, out);
+    if (live && !ok) status[0] = 1;
 #pragma unroll
     for (int j = 0; j < 10; ++j) {
         out[j] += shfl_xor_t(out[j], 1);
@@ -499,7 +397,7 @@ __global__ void __launch_bounds__(kBlock) k_stage2(DevMesh m, const T *__restric
 }
 
 // batch of single Gauss-point fluxes (kernel-level tests)
-template <typename T>
+template <typename T, bool PR>
 __global__ void __launch_bounds__(kBlock) k_gp_batch(int64_t n, const double *__restrict__ ql, const double *__restrict__ dql,
                                                      const double *__restrict__ qr, const double *__restrict__ dqr,
                                                      const double *__restrict__ dt, double *__restrict__ out,
@@ -520,7 +418,7 @@ __global__ void __launch_bounds__(kBlock) k_gp_batch(int64_t n, const double *__
             da[mm][j] = (T)dql[15 * i + 5 * mm + j];
             db[mm][j] = (T)dqr[15 * i + 5 * mm + j];
         }
-    gp_flux<T>(a, da, b, db, (T)dt[i], fp, F);
+    gp_flux<T, PR>(a, da, b, db, (T)dt[i], fp, F);
 #pragma unroll
     for (int j = 0; j < 10; ++j) out[10 * i + j] = (double)F[j];
 }
@@ -718,8 +616,15 @@ static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *ba
     dm.hcfl = (const double *)put(H.hcfl.data(), 8 * n);
     dm.st_ptr = (const int32_t *)put(H.st_ptr.data(), 4 * (n + 1));
     dm.sc_ptr = (const int32_t *)put(H.sc_ptr.data(), 4 * (n + 1));
-    dm.st_idx = (const int32_t *)put(H.st_idx.data(), 4 * H.st_idx.size());
-    dm.st_mask = (const uint8_t *)put(H.st_mask.data(), H.st_mask.size());
+    {
+        std::vector<char> rec(owned ? 8 * H.st_idx.size() : 0);
+        if (owned)
+            for (size_t k = 0; k < H.st_idx.size(); ++k) {
+                std::memcpy(&rec[8 * k], &H.st_idx[k], 4);
+                std::memcpy(&rec[8 * k + 4], &H.st_meta[k], 4);
+            }
+        dm.st_rec = owned ? (const int2 *)put_vec(std::move(rec)) : (const int2 *)put(nullptr, 8 * H.st_idx.size());
+    }
     dm.pinv = put_vec(convert(H.pinv));
     dm.sc = put_vec(convert(H.sc));
     dm.owner = (const int32_t *)put(H.owner.data(), 4 * nf);
@@ -872,12 +777,20 @@ static gks_status launch_flux(gks_mesh *m, const void *coeff, const double *Q, c
 {
     const unsigned grid = grid_for(4 * m->nf, kBlock);
     ProfScope ps(m, GKS_K_FLUX, st);
-    if (m->precision == GKS_FP64)
-        k_flux<double><<<grid, kBlock, 0, st>>>(m->d, (const double *)coeff, Q, dt_dev, (double *)ff,
-                                                flux_params<double>(p), w.status);
-    else
-        k_flux<float><<<grid, kBlock, 0, st>>>(m->d, (const float *)coeff, Q, dt_dev, (float *)ff,
-                                               flux_params<float>(p), w.status);
+    const bool pr = p->viscous && p->Pr != 1.0;
+    if (m->precision == GKS_FP64) {
+        auto fp = flux_params<double>(p);
+        if (pr)
+            k_flux<double, true><<<grid, kBlock, 0, st>>>(m->d, (const double *)coeff, Q, dt_dev, (double *)ff, fp, w.status);
+        else
+            k_flux<double, false><<<grid, kBlock, 0, st>>>(m->d, (const double *)coeff, Q, dt_dev, (double *)ff, fp, w.status);
+    } else {
+        auto fp = flux_params<float>(p);
+        if (pr)
+            k_flux<float, true><<<grid, kBlock, 0, st>>>(m->d, (const float *)coeff, Q, dt_dev, (float *)ff, fp, w.status);
+        else
+            k_flux<float, false><<<grid, kBlock, 0, st>>>(m->d, (const float *)coeff, Q, dt_dev, (float *)ff, fp, w.status);
+    }
     return hip_check(hipGetLastError(), "flux launch");
 }
 
@@ -972,11 +885,58 @@ gks_status gks_gp_flux_batch(int64_t n, const double *ql, const double *dql, con
     if (n < 0 || !p || (n > 0 && (!ql || !dql || !qr || !dqr || !dt || !out))) return fail(GKS_EINVAL, "bad argument");
     if (n == 0) return GKS_OK;
     const unsigned grid = grid_for(n, kBlock);
-    if (p->precision == GKS_FP32_MIXED)
-        k_gp_batch<float><<<grid, kBlock, 0, S(stream)>>>(n, ql, dql, qr, dqr, dt, out, flux_params<float>(p));
-    else
-        k_gp_batch<double><<<grid, kBlock, 0, S(stream)>>>(n, ql, dql, qr, dqr, dt, out, flux_params<double>(p));
+    const bool pr = p->viscous && p->Pr != 1.0;
+    hipStream_t st = S(stream);
+    if (p->precision == GKS_FP32_MIXED) {
+        if (pr)
+            k_gp_batch<float, true><<<grid, kBlock, 0, st>>>(n, ql, dql, qr, dqr, dt, out, flux_params<float>(p));
+        else
+            k_gp_batch<float, false><<<grid, kBlock, 0, st>>>(n, ql, dql, qr, dqr, dt, out, flux_params<float>(p));
+    } else {
+        if (pr)
+            k_gp_batch<double, true><<<grid, kBlock, 0, st>>>(n, ql, dql, qr, dqr, dt, out, flux_params<double>(p));
+        else
+            k_gp_batch<double, false><<<grid, kBlock, 0, st>>>(n, ql, dql, qr, dqr, dt, out, flux_params<double>(p));
+    }
     return hip_check(hipGetLastError(), "gp flux launch");
+}
+
+gks_status gks_gp_op_count(int viscous, double Pr, int64_t *adds, int64_t *muls, int64_t *divs, int64_t *transc)
+{
+    if (!adds || !muls || !divs || !transc) return fail(GKS_EINVAL, "null argument");
+    // one Gauss point of the flux kernel on a generic smooth state, executed on the host
+    Cnt cl[50], cr[50], geo[9];
+    const double base[5] = {1.1, 0.3, -0.2, 0.1, 2.9};
+    for (int c = 0; c < 5; ++c)
+        for (int j = 0; j < 10; ++j) {
+            cl[10 * c + j] = Cnt(j == 0 ? base[c] : 0.01 * (j + c));
+            cr[10 * c + j] = Cnt(j == 0 ? 0.95 * base[c] : -0.01 * (j + 2 * c));
+        }
+    const double g[9] = {0.02, 0.01, -0.015, -0.03, 0.012, 0.011, 0.002, 0.0012, -0.0007};
+    for (int q = 0; q < 9; ++q) geo[q] = Cnt(g[q]);
+    gks_params p;
+    gks_default_params(&p);
+    p.viscous = viscous;
+    p.mu = viscous ? 1e-3 : 0.0;
+    p.Pr = Pr;
+    FluxParams<Cnt> fp;
+    fp.gamma = Cnt(p.gamma);
+    fp.K = Cnt((5.0 - 3.0 * p.gamma) / (p.gamma - 1.0));
+    fp.mu = Cnt(p.mu);
+    fp.Pr = Cnt(p.Pr);
+    fp.tau_eps = Cnt(p.tau_eps);
+    fp.tau_C = Cnt(p.tau_C);
+    fp.viscous = p.viscous;
+    op_counts() = OpCounts();
+    Cnt out[10];
+    const bool ok = (viscous && Pr != 1.0) ? face_gp<Cnt, true>(cl, cr, nullptr, nullptr, geo, Cnt(0.01), fp, out)
+                                           : face_gp<Cnt, false>(cl, cr, nullptr, nullptr, geo, Cnt(0.01), fp, out);
+    const OpCounts c = op_counts();
+    *adds = c.add;
+    *muls = c.mul;
+    *divs = c.div;
+    *transc = c.transc;
+    return ok ? GKS_OK : fail(GKS_EINVAL, "counting state was non-physical");
 }
 
 }  // extern "C"

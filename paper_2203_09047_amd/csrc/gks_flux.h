@@ -33,47 +33,47 @@ struct Mom {
 };
 
 template <typename T>
-__device__ __forceinline__ void recur7(T *m, T U, T h)  // h = 1 / (2 lambda)
+__host__ __device__ __forceinline__ void recur7(T *m, T U, T h)  // h = 1 / (2 lambda)
 {
 #pragma unroll
     for (int k = 0; k + 2 < 7; ++k) m[k + 2] = U * m[k + 1] + T(k + 1) * h * m[k];
 }
 
 template <typename T>
-__device__ __forceinline__ void recur6(T *m, T U, T h)
+__host__ __device__ __forceinline__ void recur6(T *m, T U, T h)
 {
 #pragma unroll
     for (int k = 0; k + 2 < 6; ++k) m[k + 2] = U * m[k + 1] + T(k + 1) * h * m[k];
 }
 
 template <typename T>
-__device__ __forceinline__ T erfc_t(T x);
+__host__ __device__ __forceinline__ T erfc_t(T x);
 template <>
-__device__ __forceinline__ double erfc_t<double>(double x) { return erfc(x); }
+__host__ __device__ __forceinline__ double erfc_t<double>(double x) { return erfc(x); }
 template <>
-__device__ __forceinline__ float erfc_t<float>(float x) { return erfcf(x); }
+__host__ __device__ __forceinline__ float erfc_t<float>(float x) { return erfcf(x); }
 template <typename T>
-__device__ __forceinline__ T exp_t(T x);
+__host__ __device__ __forceinline__ T exp_t(T x);
 template <>
-__device__ __forceinline__ double exp_t<double>(double x) { return exp(x); }
+__host__ __device__ __forceinline__ double exp_t<double>(double x) { return exp(x); }
 template <>
-__device__ __forceinline__ float exp_t<float>(float x) { return expf(x); }
+__host__ __device__ __forceinline__ float exp_t<float>(float x) { return expf(x); }
 template <typename T>
-__device__ __forceinline__ T expm1_t(T x);
+__host__ __device__ __forceinline__ T expm1_t(T x);
 template <>
-__device__ __forceinline__ double expm1_t<double>(double x) { return expm1(x); }
+__host__ __device__ __forceinline__ double expm1_t<double>(double x) { return expm1(x); }
 template <>
-__device__ __forceinline__ float expm1_t<float>(float x) { return expm1f(x); }
+__host__ __device__ __forceinline__ float expm1_t<float>(float x) { return expm1f(x); }
 template <typename T>
-__device__ __forceinline__ T sqrt_t(T x);
+__host__ __device__ __forceinline__ T sqrt_t(T x);
 template <>
-__device__ __forceinline__ double sqrt_t<double>(double x) { return sqrt(x); }
+__host__ __device__ __forceinline__ double sqrt_t<double>(double x) { return sqrt(x); }
 template <>
-__device__ __forceinline__ float sqrt_t<float>(float x) { return sqrtf(x); }
+__host__ __device__ __forceinline__ float sqrt_t<float>(float x) { return sqrtf(x); }
 
 // Full-space v, w, internal moments (shared by full and half-space sets of one state).
 template <typename T>
-__device__ __forceinline__ void mom_common(Mom<T> &m, T V, T W, T lam, T K)
+__host__ __device__ __forceinline__ void mom_common(Mom<T> &m, T V, T W, T lam, T K)
 {
     const T h = T(0.5) / lam;
     m.v[0] = T(1);
@@ -87,7 +87,7 @@ __device__ __forceinline__ void mom_common(Mom<T> &m, T V, T W, T lam, T K)
 }
 
 template <typename T>
-__device__ __forceinline__ void mom_full_u(Mom<T> &m, T U, T lam)
+__host__ __device__ __forceinline__ void mom_full_u(Mom<T> &m, T U, T lam)
 {
     m.u[0] = T(1);
     m.u[1] = U;
@@ -96,7 +96,7 @@ __device__ __forceinline__ void mom_full_u(Mom<T> &m, T U, T lam)
 
 // sign = +1: u > 0, -1: u < 0
 template <typename T>
-__device__ __forceinline__ void mom_half_u(Mom<T> &m, T U, T lam, T sign)
+__host__ __device__ __forceinline__ void mom_half_u(Mom<T> &m, T U, T lam, T sign)
 {
     const T sl = sqrt_t(lam);
     const T e = exp_t(-lam * U * U) / (T(2) * sqrt_t(T(M_PI) * lam));
@@ -107,7 +107,7 @@ __device__ __forceinline__ void mom_half_u(Mom<T> &m, T U, T lam, T sign)
 
 // <u^k v^l w^m psi>
 template <int k, int l, int n, typename T>
-__device__ __forceinline__ void P(const Mom<T> &M, T o[5])
+__host__ __device__ __forceinline__ void P(const Mom<T> &M, T o[5])
 {
     const T vw = M.v[l] * M.w[n];
     const T base = M.u[k] * vw;
@@ -120,7 +120,7 @@ __device__ __forceinline__ void P(const Mom<T> &M, T o[5])
 
 // <u^k v^l w^m s^2 psi>
 template <int k, int l, int n, typename T>
-__device__ __forceinline__ void Ps(const Mom<T> &M, T o[5])
+__host__ __device__ __forceinline__ void Ps(const Mom<T> &M, T o[5])
 {
     const T vw = M.v[l] * M.w[n];
     const T base = M.u[k] * vw;
@@ -134,7 +134,7 @@ __device__ __forceinline__ void Ps(const Mom<T> &M, T o[5])
 
 // <u^k v^l w^m (a . psi) psi> for a slope a = (a1, a2, a3, a4, a5)
 template <int k, int l, int n, typename T>
-__device__ __forceinline__ void Pa(const Mom<T> &M, const T a[5], T o[5])
+__host__ __device__ __forceinline__ void Pa(const Mom<T> &M, const T a[5], T o[5])
 {
     T t[5];
     P<k, l, n>(M, t);
@@ -164,7 +164,7 @@ __device__ __forceinline__ void Pa(const Mom<T> &M, const T a[5], T o[5])
 
 // <u^k (a1.psi u + a2.psi v + a3.psi w) psi> for k = 0 (compatibility) or 1 (flux)
 template <int k, typename T>
-__device__ __forceinline__ void Padv(const Mom<T> &M, const T a[3][5], T o[5])
+__host__ __device__ __forceinline__ void Padv(const Mom<T> &M, const T a[3][5], T o[5])
 {
     T t[5];
     Pa<k + 1, 0, 0>(M, a[0], o);
@@ -178,7 +178,7 @@ __device__ __forceinline__ void Padv(const Mom<T> &M, const T a[3][5], T o[5])
 
 // Closed-form solution of <psi psi^T> a = b for a Maxwellian (U, V, W, lambda).
 template <typename T>
-__device__ __forceinline__ void slope_solve(const T b[5], T U, T V, T W, T lam, T K, T a[5])
+__host__ __device__ __forceinline__ void slope_solve(const T b[5], T U, T V, T W, T lam, T K, T a[5])
 {
     const T q = U * U + V * V + W * W + (K + T(3)) / (T(2) * lam);
     const T R2 = b[1] - U * b[0], R3 = b[2] - V * b[0], R4 = b[3] - W * b[0];
@@ -192,7 +192,7 @@ __device__ __forceinline__ void slope_solve(const T b[5], T U, T V, T W, T lam, 
 
 // primitive variables; returns false for a non-physical state
 template <typename T>
-__device__ __forceinline__ bool to_prim(const T q[5], T gam, T &rho, T &U, T &V, T &W, T &lam, T &p)
+__host__ __device__ __forceinline__ bool to_prim(const T q[5], T gam, T &rho, T &U, T &V, T &W, T &lam, T &p)
 {
     rho = q[0];
     const T ir = T(1) / rho;
@@ -205,80 +205,119 @@ __device__ __forceinline__ bool to_prim(const T q[5], T gam, T &rho, T &U, T &V,
 }
 
 /*
- * out[0..4]: flux per unit area at the start of the step, out[5..9]: its time
- * derivative.  Returns false if a state (left, right or interface) is non-physical.
+ * The Gauss-point flux is assembled in three passes so that only one side's
+ * moments and slopes are live at a time: side_pass() for the left state
+ * (half space u > 0) and for the right state (u < 0) accumulates every
+ * half-space moment the flux needs; finish_flux() builds g_0 from them, its
+ * slopes, the collision time and both time integrals.  PR selects the
+ * Prandtl-number correction, which needs the conserved moments of the
+ * time-integrated distribution as well.
  */
+template <typename T, bool PR>
+struct FluxAcc {
+    T q0[5];      // sum_s rho_s <psi>_half            (conserved variables of g_0)
+    T bab[3][5];  // sum_s rho_s <a^s_m psi psi>_half   (right-hand sides of the g_0 slopes)
+    T Mh[5];      // sum_s rho_s <u psi>_half
+    T Mha[5];     // sum_s rho_s <u (a^s . u) psi>_half
+    T MhA[5];     // sum_s rho_s <u A^s psi>_half
+    T Wha[PR ? 5 : 1];  // sum_s rho_s <(a^s . u) psi>_half
+    T WhA[PR ? 5 : 1];  // sum_s rho_s <A^s psi>_half
+    T p[2];       // side pressures
+};
+
+template <typename T, bool PR>
+__host__ __device__ __forceinline__ void acc_zero(FluxAcc<T, PR> &A)
+{
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        A.q0[j] = A.Mh[j] = A.Mha[j] = A.MhA[j] = T(0);
+        A.bab[0][j] = A.bab[1][j] = A.bab[2][j] = T(0);
+        if constexpr (PR) A.Wha[j] = A.WhA[j] = T(0);
+    }
+}
+
 template <typename T>
-__device__ bool gp_flux(const T ql[5], const T dql[3][5], const T qr[5], const T dqr[3][5], T dt,
-                        const FluxParams<T> &fp, T out[10])
+__host__ __device__ __forceinline__ void axpy5(T *y, T a, const T *x)
+{
+#pragma unroll
+    for (int j = 0; j < 5; ++j) y[j] += a * x[j];
+}
+
+// One side of the interface: sign = +1 for the left state (u > 0), -1 for the right (u < 0).
+template <typename T, bool PR>
+__host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5], T sign, const FluxParams<T> &fp,
+                                                   FluxAcc<T, PR> &A, int side)
 {
     const T K = fp.K;
-    T rl, Ul, Vl, Wl, laml, pl, rr, Ur, Vr, Wr, lamr, pr;
-    bool ok = to_prim(ql, fp.gamma, rl, Ul, Vl, Wl, laml, pl);
-    ok = to_prim(qr, fp.gamma, rr, Ur, Vr, Wr, lamr, pr) && ok;
-    if (!ok) {
-#pragma unroll
-        for (int j = 0; j < 10; ++j) out[j] = T(0);
-        return false;
-    }
-    Mom<T> Lf, Lh, Rf, Rh;
-    mom_common(Lf, Vl, Wl, laml, K);
-    mom_full_u(Lf, Ul, laml);
-    Lh = Lf;
-    mom_half_u(Lh, Ul, laml, T(1));
-    mom_common(Rf, Vr, Wr, lamr, K);
-    mom_full_u(Rf, Ur, lamr);
-    Rh = Rf;
-    mom_half_u(Rh, Ur, lamr, T(-1));
-
-    // interface equilibrium
-    T q0[5], t5[5];
-    P<0, 0, 0>(Lh, q0);
-    P<0, 0, 0>(Rh, t5);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) q0[j] = rl * q0[j] + rr * t5[j];
-    T r0, U0, V0, W0, lam0, p0;
-    ok = to_prim(q0, fp.gamma, r0, U0, V0, W0, lam0, p0);
-    Mom<T> G;
-    mom_common(G, V0, W0, lam0, K);
-    mom_full_u(G, U0, lam0);
-
-    // spatial slopes on both sides
-    T al[3][5], ar[3][5];
-    const T irl = T(1) / rl, irr = T(1) / rr;
+    T rho, U, V, W, lam, p;
+    const bool ok = to_prim(q, fp.gamma, rho, U, V, W, lam, p);
+    A.p[side] = p;
+    if (!ok) return false;
+    Mom<T> M;
+    mom_common(M, V, W, lam, K);
+    mom_full_u(M, U, lam);
+    // spatial slopes <a_m> = dQ/dn_m / rho, time slope from <a_1 u + a_2 v + a_3 w + A> = 0
+    T a[3][5], Ab[5];
+    const T ir = T(1) / rho;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         T b[5];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) b[j] = dql[m][j] * irl;
-        slope_solve(b, Ul, Vl, Wl, laml, K, al[m]);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) b[j] = dqr[m][j] * irr;
-        slope_solve(b, Ur, Vr, Wr, lamr, K, ar[m]);
+        for (int j = 0; j < 5; ++j) b[j] = dq[m][j] * ir;
+        slope_solve(b, U, V, W, lam, K, a[m]);
     }
-    // time slopes from compatibility
-    T Al[5], Ar[5];
     {
         T b[5];
-        Padv<0>(Lf, al, b);
+        Padv<0>(M, a, b);
 #pragma unroll
         for (int j = 0; j < 5; ++j) b[j] = -b[j];
-        slope_solve(b, Ul, Vl, Wl, laml, K, Al);
-        Padv<0>(Rf, ar, b);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) b[j] = -b[j];
-        slope_solve(b, Ur, Vr, Wr, lamr, K, Ar);
+        slope_solve(b, U, V, W, lam, K, Ab);
     }
-    // equilibrium slopes
+    // half-space moments of u replace the full ones
+    mom_half_u(M, U, lam, sign);
+    T t[5];
+    P<0, 0, 0>(M, t);
+    axpy5(A.q0, rho, t);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        Pa<0, 0, 0>(M, a[m], t);
+        axpy5(A.bab[m], rho, t);
+    }
+    P<1, 0, 0>(M, t);
+    axpy5(A.Mh, rho, t);
+    Padv<1>(M, a, t);
+    axpy5(A.Mha, rho, t);
+    Pa<1, 0, 0>(M, Ab, t);
+    axpy5(A.MhA, rho, t);
+    if constexpr (PR) {
+        Padv<0>(M, a, t);
+        axpy5(A.Wha, rho, t);
+        Pa<0, 0, 0>(M, Ab, t);
+        axpy5(A.WhA, rho, t);
+    }
+    return true;
+}
+
+/*
+ * out[0..4]: flux per unit area at the start of the step, out[5..9]: its time
+ * derivative.  Returns false if the interface state is non-physical.
+ */
+template <typename T, bool PR>
+__host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T dt, const FluxParams<T> &fp, T out[10])
+{
+    const T K = fp.K;
+    T r0, U0, V0, W0, lam0, p0;
+    const bool ok = to_prim(A.q0, fp.gamma, r0, U0, V0, W0, lam0, p0);
+    Mom<T> G;
+    mom_common(G, V0, W0, lam0, K);
+    mom_full_u(G, U0, lam0);
     T ab[3][5], Ab[5];
     const T ir0 = T(1) / r0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        T b[5], c[5];
-        Pa<0, 0, 0>(Lh, al[m], b);
-        Pa<0, 0, 0>(Rh, ar[m], c);
+        T b[5];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) b[j] = (rl * b[j] + rr * c[j]) * ir0;
+        for (int j = 0; j < 5; ++j) b[j] = A.bab[m][j] * ir0;
         slope_solve(b, U0, V0, W0, lam0, K, ab[m]);
     }
     {
@@ -289,49 +328,18 @@ __device__ bool gp_flux(const T ql[5], const T dql[3][5], const T qr[5], const T
         slope_solve(b, U0, V0, W0, lam0, K, Ab);
     }
     // collision time
-    const T dp = (pl - pr) / (pl + pr);
+    const T dp = (A.p[0] - A.p[1]) / (A.p[0] + A.p[1]);
     const T jump = (dp < T(0) ? -dp : dp) * dt;
     const T tau = fp.viscous ? fp.mu / p0 + fp.tau_C * jump : fp.tau_eps * dt + fp.tau_C * jump;
-
-    // flux moments of every term (shared by both time integrals)
-    T M0[5], Ma[5], MA[5], Mh[5], Mha[5], MhA[5];
-    {
-        T x[5], y[5];
-        P<1, 0, 0>(G, M0);
-        Padv<1>(G, ab, Ma);
-        Pa<1, 0, 0>(G, Ab, MA);
-        P<1, 0, 0>(Lh, x);
-        P<1, 0, 0>(Rh, y);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) Mh[j] = rl * x[j] + rr * y[j];
-        Padv<1>(Lh, al, x);
-        Padv<1>(Rh, ar, y);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) Mha[j] = rl * x[j] + rr * y[j];
-        Pa<1, 0, 0>(Lh, Al, x);
-        Pa<1, 0, 0>(Rh, Ar, y);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) MhA[j] = rl * x[j] + rr * y[j];
-    }
-    const bool prandtl = fp.viscous && fp.Pr != T(1);
-    T W0m[5], Wam[5], WAm[5], Whm[5], Wham[5], WhAm[5];
-    if (prandtl) {
-        T x[5], y[5];
+    T M0[5], Ma[5], MA[5];
+    P<1, 0, 0>(G, M0);
+    Padv<1>(G, ab, Ma);
+    Pa<1, 0, 0>(G, Ab, MA);
+    T W0m[PR ? 5 : 1], Wam[PR ? 5 : 1], WAm[PR ? 5 : 1];
+    if constexpr (PR) {
         P<0, 0, 0>(G, W0m);
         Padv<0>(G, ab, Wam);
         Pa<0, 0, 0>(G, Ab, WAm);
-        P<0, 0, 0>(Lh, x);
-        P<0, 0, 0>(Rh, y);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) Whm[j] = rl * x[j] + rr * y[j];
-        Padv<0>(Lh, al, x);
-        Padv<0>(Rh, ar, y);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) Wham[j] = rl * x[j] + rr * y[j];
-        Pa<0, 0, 0>(Lh, Al, x);
-        Pa<0, 0, 0>(Rh, Ar, y);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) WhAm[j] = rl * x[j] + rr * y[j];
     }
     T Fd[2][5];
 #pragma unroll
@@ -346,13 +354,13 @@ __device__ bool gp_flux(const T ql[5], const T dql[3][5], const T qr[5], const T
         const T T5 = T(2) * tau * tau * om - tau * d * eta;
 #pragma unroll
         for (int j = 0; j < 5; ++j)
-            Fd[s][j] = r0 * (T1 * M0[j] + T2 * Ma[j] + T3 * MA[j]) + T4 * Mh[j] - T5 * Mha[j] - tau * T4 * MhA[j];
-        if (prandtl) {
+            Fd[s][j] = r0 * (T1 * M0[j] + T2 * Ma[j] + T3 * MA[j]) + T4 * A.Mh[j] - T5 * A.Mha[j] - tau * T4 * A.MhA[j];
+        if constexpr (PR) {
             T Wv[5];
 #pragma unroll
             for (int j = 0; j < 5; ++j)
-                Wv[j] = r0 * (T1 * W0m[j] + T2 * Wam[j] + T3 * WAm[j]) + T4 * Whm[j] - T5 * Wham[j] -
-                        tau * T4 * WhAm[j];
+                Wv[j] = r0 * (T1 * W0m[j] + T2 * Wam[j] + T3 * WAm[j]) + T4 * A.q0[j] - T5 * A.Wha[j] -
+                        tau * T4 * A.WhA[j];
             const T *F = Fd[s];
             const T U2 = U0 * U0 + V0 * V0 + W0 * W0;
             // heat flux about the interface velocity of the time-integrated distribution (times 2)
@@ -366,6 +374,147 @@ __device__ bool gp_flux(const T ql[5], const T dql[3][5], const T qr[5], const T
     for (int j = 0; j < 5; ++j) {
         out[j] = (T(4) * Fd[0][j] - Fd[1][j]) * idt;
         out[5 + j] = T(4) * (Fd[1][j] - T(2) * Fd[0][j]) * idt * idt;
+    }
+    return ok;
+}
+
+/*
+ * Gauss-point flux from the two local-frame states and their n1, n2, n3
+ * derivatives.  Returns false if a state (left, right or interface) is
+ * non-physical; the output is then zero.
+ */
+template <typename T, bool PR>
+__host__ __device__ bool gp_flux(const T ql[5], const T dql[3][5], const T qr[5], const T dqr[3][5], T dt,
+                                 const FluxParams<T> &fp, T out[10])
+{
+    FluxAcc<T, PR> A;
+    acc_zero(A);
+    bool ok = side_pass<T, PR>(ql, dql, T(1), fp, A, 0);
+    ok = side_pass<T, PR>(qr, dqr, T(-1), fp, A, 1) && ok;
+    if (!ok) {
+#pragma unroll
+        for (int j = 0; j < 10; ++j) out[j] = T(0);
+        return false;
+    }
+    return finish_flux<T, PR>(A, dt, fp, out);
+}
+
+// Local frame at a Gauss point: n1 = unit weighted vector area; e = the coordinate
+// axis with the smallest |n1 . e| (lowest index on ties), n2 = unit(e - (e.n1) n1),
+// n3 = n1 x n2.  Returns |vector area|.
+template <typename T>
+__host__ __device__ __forceinline__ T local_frame(T vx, T vy, T vz, T n[3][3])
+{
+    const T area = sqrt_t(vx * vx + vy * vy + vz * vz);
+    const T ia = T(1) / area;
+    n[0][0] = vx * ia;
+    n[0][1] = vy * ia;
+    n[0][2] = vz * ia;
+    const T ax = n[0][0] < T(0) ? -n[0][0] : n[0][0];
+    const T ay = n[0][1] < T(0) ? -n[0][1] : n[0][1];
+    const T az = n[0][2] < T(0) ? -n[0][2] : n[0][2];
+    int e = 0;
+    T best = ax;
+    if (ay < best) {
+        e = 1;
+        best = ay;
+    }
+    if (az < best) e = 2;
+    T t[3] = {T(0), T(0), T(0)};
+    t[e] = T(1);
+    const T d = n[0][e];
+    t[0] = t[0] - d * n[0][0];
+    t[1] = t[1] - d * n[0][1];
+    t[2] = t[2] - d * n[0][2];
+    const T it = T(1) / sqrt_t(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    n[1][0] = t[0] * it;
+    n[1][1] = t[1] * it;
+    n[1][2] = t[2] * it;
+    n[2][0] = n[0][1] * n[1][2] - n[0][2] * n[1][1];
+    n[2][1] = n[0][2] * n[1][0] - n[0][0] * n[1][2];
+    n[2][2] = n[0][0] * n[1][1] - n[0][1] * n[1][0];
+    return area;
+}
+
+// Value and gradient at offset (X, Y, Z) of one cell's per-component quadratic, rotated
+// into the local frame (momentum components and derivative directions).
+template <typename T>
+__host__ __device__ __forceinline__ void side_state(const T *__restrict__ c, const double *q0, T X, T Y, T Z,
+                                                    const T n[3][3], T q[5], T dq[3][5])
+{
+    T v[5], g[5][3];
+    const T XX = X * X, XY = X * Y, XZ = X * Z, YY = Y * Y, YZ = Y * Z, ZZ = Z * Z;
+#pragma unroll
+    for (int comp = 0; comp < 5; ++comp) {
+        const T *cc = c + 10 * comp;
+        const T lin = cc[1] * X + cc[2] * Y + cc[3] * Z;
+        const T qua = cc[4] * XX + cc[5] * XY + cc[6] * XZ + cc[7] * YY + cc[8] * YZ + cc[9] * ZZ;
+        if constexpr (sizeof(T) == 8)
+            v[comp] = cc[0] + lin + qua;
+        else
+            v[comp] = (T)(q0[comp] + (double)(cc[0] + lin + qua));
+        g[comp][0] = cc[1] + T(2) * cc[4] * X + cc[5] * Y + cc[6] * Z;
+        g[comp][1] = cc[2] + cc[5] * X + T(2) * cc[7] * Y + cc[8] * Z;
+        g[comp][2] = cc[3] + cc[6] * X + cc[8] * Y + T(2) * cc[9] * Z;
+    }
+    q[0] = v[0];
+    q[4] = v[4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) q[1 + k] = v[1] * n[k][0] + v[2] * n[k][1] + v[3] * n[k][2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        T dn[5];
+#pragma unroll
+        for (int cc = 0; cc < 5; ++cc) dn[cc] = g[cc][0] * n[m][0] + g[cc][1] * n[m][1] + g[cc][2] * n[m][2];
+        dq[m][0] = dn[0];
+        dq[m][4] = dn[4];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dq[m][1 + k] = dn[1] * n[k][0] + dn[2] * n[k][1] + dn[3] * n[k][2];
+    }
+}
+
+/*
+ * All the work of one face Gauss point: states on both sides from their
+ * quadratics (cl, cr: [5][10]) at offsets geo[0..2] (owner) and geo[3..5]
+ * (neighbour), frame from the weighted vector area geo[6..8], the BGK flux,
+ * rotation back to global axes and weighting (Eq. flux-qud).  out: the Gauss
+ * point's (Fbar0, Fbar1) contribution to the face, owner -> neighbour.
+ * ql0, qr0: FP64 cell averages (used by the FP32 variant only).
+ */
+template <typename T, bool PR>
+__host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl, const T *__restrict__ cr, const double *ql0,
+                                                 const double *qr0, const T geo[9], T dt, const FluxParams<T> &fp,
+                                                 T out[10])
+{
+    T n3[3][3];
+    const T area = local_frame(geo[6], geo[7], geo[8], n3);
+    FluxAcc<T, PR> A;
+    acc_zero(A);
+    bool ok;
+    {
+        T q[5], dq[3][5];
+        side_state(cl, ql0, geo[0], geo[1], geo[2], n3, q, dq);
+        ok = side_pass<T, PR>(q, dq, T(1), fp, A, 0);
+    }
+    {
+        T q[5], dq[3][5];
+        side_state(cr, qr0, geo[3], geo[4], geo[5], n3, q, dq);
+        ok = side_pass<T, PR>(q, dq, T(-1), fp, A, 1) && ok;
+    }
+    T F[10];
+    if (ok) {
+        ok = finish_flux<T, PR>(A, dt, fp, F);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 10; ++j) F[j] = T(0);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const T *Fl = F + 5 * s;
+        out[5 * s] = area * Fl[0];
+        out[5 * s + 4] = area * Fl[4];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) out[5 * s + 1 + q] = area * (Fl[1] * n3[0][q] + Fl[2] * n3[1][q] + Fl[3] * n3[2][q]);
     }
     return ok;
 }

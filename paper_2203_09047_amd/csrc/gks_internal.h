@@ -24,6 +24,7 @@ struct HostMesh {
     // for each sub-stencil in its mask (stored consecutively from sc_ptr[i])
     std::vector<int32_t> st_ptr, st_idx, sc_ptr;
     std::vector<uint8_t> st_mask;
+    std::vector<int32_t> st_meta;  // per member: mask | (offset of its first coefficient triple - sc_ptr[i]) << 8
     std::vector<double> pinv, sc;
     // faces
     std::vector<int32_t> owner, nbr;

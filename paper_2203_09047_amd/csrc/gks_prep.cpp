@@ -398,6 +398,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
     H.sc_ptr.assign(n + 1, 0);
     H.st_idx.clear();
     H.st_mask.clear();
+    H.st_meta.clear();
     H.pinv.clear();
     H.sc.clear();
     H.n_grown = 0;
@@ -449,7 +450,15 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         }
     };
 
-    for (int64_t i = 0; i < n; ++i) {
+    struct CellOut {
+        std::vector<int32_t> idx;
+        std::vector<uint8_t> mask;
+        std::vector<double> pinv, sc;
+        int grown = 0;
+        int err = 0;  // 0 ok, 1 big fit singular, 2 sub fit singular, 3 too large
+    };
+    std::vector<CellOut> outs(n);
+    auto process = [&](int64_t i, CellOut &out) {
         const int64_t c = perm[i];
         const int t = types[c];
         const CellGeom &g = geo[c];
@@ -496,14 +505,20 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         const double h = std::cbrt(g.vol);
         std::vector<double> P0;
         int gr = fit(c, big, 9, h, P0);
-        if (gr < 0) return fail(GKS_ESINGULAR, "big-stencil fit stays rank deficient at cell " + std::to_string(c));
-        H.n_grown += gr;
+        if (gr < 0) {
+            out.err = 1;
+            return;
+        }
+        out.grown += gr;
         const int nls = (int)big.size();
         std::vector<std::vector<double>> Pm(M);
         for (int m = 0; m < M; ++m) {
             int gm = fit(c, subs[m], 3, h, Pm[m]);
-            if (gm < 0) return fail(GKS_ESINGULAR, "sub-stencil fit stays rank deficient at cell " + std::to_string(c));
-            H.n_grown += gm;
+            if (gm < 0) {
+                out.err = 2;
+                return;
+            }
+            out.grown += gm;
         }
         // member list = big stencil, then members only a sub-stencil uses
         std::vector<Member> members = big;
@@ -515,25 +530,54 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
                 if (it == members.end()) members.push_back(s);
                 slot[m].push_back(k);
             }
-        if (members.size() > 255) return fail(GKS_EINVAL, "stencil too large");
-        H.st_ptr[i + 1] = H.st_ptr[i] + (int32_t)members.size();
+        if (members.size() > 255) {
+            out.err = 3;
+            return;
+        }
         for (size_t k = 0; k < members.size(); ++k) {
             uint8_t mask = 0;
             for (int m = 0; m < M; ++m)
                 for (size_t e = 0; e < slot[m].size(); ++e)
                     if (slot[m][e] == (int)k) mask |= (uint8_t)(1u << m);
-            H.st_idx.push_back((int32_t)members[k].cell);  // external for now
-            H.st_mask.push_back(mask);
+            out.idx.push_back((int32_t)members[k].cell);  // external for now
+            out.mask.push_back(mask);
             for (int j = 0; j < 9; ++j)
-                H.pinv.push_back((int)k < nls ? P0[(size_t)j * nls + k] : 0.0);
+                out.pinv.push_back((int)k < nls ? P0[(size_t)j * nls + k] : 0.0);
             for (int m = 0; m < M; ++m)
                 if (mask & (1u << m)) {
                     const int rows = (int)subs[m].size();
                     int e = (int)(std::find(slot[m].begin(), slot[m].end(), (int)k) - slot[m].begin());
-                    for (int j = 0; j < 3; ++j) H.sc.push_back(Pm[m][(size_t)j * rows + e]);
+                    for (int j = 0; j < 3; ++j) out.sc.push_back(Pm[m][(size_t)j * rows + e]);
                 }
         }
+    };
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) process(i, outs[i]);
+    for (int64_t i = 0; i < n; ++i) {
+        CellOut &o = outs[i];
+        if (o.err == 1) return fail(GKS_ESINGULAR, "big-stencil fit stays rank deficient at cell " + std::to_string(perm[i]));
+        if (o.err == 2) return fail(GKS_ESINGULAR, "sub-stencil fit stays rank deficient at cell " + std::to_string(perm[i]));
+        if (o.err == 3) return fail(GKS_EINVAL, "stencil too large at cell " + std::to_string(perm[i]));
+        H.n_grown += o.grown;
+        H.st_ptr[i + 1] = H.st_ptr[i] + (int32_t)o.idx.size();
+        H.st_idx.insert(H.st_idx.end(), o.idx.begin(), o.idx.end());
+        {
+            // member record: sub-stencil mask in the low byte, offset of the member's first
+            // sub-stencil coefficient triple (relative to the cell's first) above it
+            int32_t rel = 0;
+            for (uint8_t mk : o.mask) {
+                H.st_mask.push_back(mk);
+                H.st_meta.push_back((int32_t)mk | (rel << 8));
+                rel += __builtin_popcount(mk);
+            }
+        }
+        H.pinv.insert(H.pinv.end(), o.pinv.begin(), o.pinv.end());
+        H.sc.insert(H.sc.end(), o.sc.begin(), o.sc.end());
         H.sc_ptr[i + 1] = (int32_t)(H.sc.size() / 3);
+        CellOut().idx.swap(o.idx);
+        std::vector<double>().swap(o.pinv);
+        std::vector<double>().swap(o.sc);
+        std::vector<uint8_t>().swap(o.mask);
     }
     for (auto &v : H.st_idx) v = (int32_t)inv[v];
 

@@ -23,7 +23,8 @@ SYMBOLS = [
     "gks_default_params", "gks_preprocess", "gks_host_mesh_free", "gks_host_mesh_counts", "gks_host_mesh_perm",
     "gks_host_mesh_geometry", "gks_host_mesh_faces", "gks_mesh_sizes", "gks_init_mesh", "gks_destroy_mesh",
     "gks_reset_status", "gks_timestep", "gks_reconstruct", "gks_flux", "gks_residual", "gks_s2o4_step",
-    "gks_poll_status", "gks_gp_flux_batch", "gks_profile", "gks_profile_read", "gks_last_error",
+    "gks_poll_status", "gks_gp_flux_batch", "gks_profile", "gks_profile_read", "gks_gp_op_count",
+    "gks_last_error",
 ]
 KERNELS = ("timestep", "reconstruct", "flux", "stage1", "stage2", "residual")
 
@@ -98,6 +99,8 @@ def load():
         lib.gks_profile.restype = st
         lib.gks_profile_read.argtypes = [vp, vp, vp]
         lib.gks_profile_read.restype = st
+        lib.gks_gp_op_count.argtypes = [i32, ctypes.c_double, vp, vp, vp, vp]
+        lib.gks_gp_op_count.restype = st
         lib.gks_last_error.argtypes = []
         lib.gks_last_error.restype = ctypes.c_char_p
         _lib = lib
@@ -301,6 +304,13 @@ class Solver:
             if dt is not None:
                 t += dt
         return dts
+
+
+def gp_op_count(viscous=False, Pr=1.0):
+    """Operations of one Gauss point of the flux kernel: dict(add, mul, div, transc)."""
+    v = [ctypes.c_int64() for _ in range(4)]
+    _check(load().gks_gp_op_count(int(viscous), Pr, *(ctypes.byref(x) for x in v)))
+    return dict(add=v[0].value, mul=v[1].value, div=v[2].value, transc=v[3].value)
 
 
 def gp_flux_batch(ql, dql, qr, dqr, dt, precision=FP64, **kw):
