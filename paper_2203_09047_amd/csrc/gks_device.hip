@@ -60,8 +60,9 @@ struct DevMesh {
     const int32_t *st_ptr;  // [n+1]
     const int32_t *sc_ptr;  // [n+1] (units of 3 coefficients)
     const int2 *st_rec;     // members: {cell, mask | (relative coefficient offset << 8)}
-    const void *pinv;       // [nnz][9], FP64 or FP32
-    const void *sc;         // [nsc][3], FP64 or FP32
+    int nnz, nsc;           // stencil members, sub-stencil coefficient triples
+    const void *pinv;       // [9][nnz] (coefficient-major), FP64 or FP32
+    const void *sc;         // [3][nsc] (coefficient-major), FP64 or FP32
     // faces
     const int32_t *owner, *nbr;
     const double *fgeo;     // [9][4 nf]
@@ -167,109 +168,176 @@ __device__ __forceinline__ T wpow(T x, T p)
     return (T)pow((double)x, (double)p);
 }
 
-constexpr int kK1Block = 320;  // 64 cells x 5 components
+// 8 lanes cooperate on one cell: lane l streams members l, l+8, ... of the cell's
+// stencil (consecutive lanes read consecutive pseudo-inverse rows), then the
+// partial fits are summed across the 8 lanes with a fixed butterfly, so every
+// lane holds identical totals (deterministic, no atomics).
+constexpr int kK1Lanes = 8;
+constexpr int kK1Block = 256;  // 32 cells per block
+
+// DPP lane permutations (VALU, no LDS traffic) of a 32-bit value within groups of 8 lanes
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_t(float v) { return dpp_f32<CTRL>(v); }
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double v) { return dpp_f64<CTRL>(v); }
+
+constexpr int kDppHalfMirror = 0x141;  // lane i <- lane 7 - i within each group of 8
+constexpr int kDppQuadXor1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2,3,0,1]
+
+// Sum over a group of 8 lanes; every lane gets the bitwise-identical total
+// (each step adds the same two partial sums, only in swapped order).
+template <typename T>
+__device__ __forceinline__ T bfly_sum8(T v)
+{
+    v += dpp_t<kDppHalfMirror>(v);
+    v += dpp_t<kDppQuadXor1>(v);
+    v += dpp_t<kDppQuadXor2>(v);
+    return v;
+}
+
+// Block index remap so that each of the 8 XCDs (which receive blocks round-robin)
+// works through one contiguous range of blocks, keeping neighbour gathers in its L2.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, j = b >> 3;
+    return x * q + (x < r ? x : r) + j;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff,
                                                           WenoParams wp)
 {
-    const int t = blockIdx.x * kK1Block + threadIdx.x;
-    const int i = t / 5;
-    const int comp = t - 5 * i;
-    if (i >= m.n) return;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kK1Block + threadIdx.x;
     const int n = m.n;
-    const double q0 = Q[comp * n + i];
-    const double *Qc = Q + (size_t)comp * n;
+    const int ic = t / kK1Lanes;
+    const int l = t - kK1Lanes * ic;
+    const bool valid = ic < n;
+    const int i = valid ? ic : n - 1;  // tail lanes shadow the last cell and write nothing
     const T *pinv = (const T *)m.pinv;
     const T *sc = (const T *)m.sc;
+    const int nnz = m.nnz, nsc = m.nsc;
     const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
     const int e0 = m.sc_ptr[i];
-    T a[9], b[8][3];
-#pragma unroll
-    for (int j = 0; j < 9; ++j) a[j] = T(0);
-#pragma unroll
-    for (int s = 0; s < 8; ++s) b[s][0] = b[s][1] = b[s][2] = T(0);
-#pragma unroll 2
-    for (int k = k0; k < k1; ++k) {
-        const int2 rec = m.st_rec[k];
-        const T d = (T)(Qc[rec.x] - q0);
-        const T *row = pinv + (size_t)9 * k;
-#pragma unroll
-        for (int j = 0; j < 9; ++j) a[j] += row[j] * d;
-        const unsigned mask = (unsigned)rec.y & 255u;
-        int e = e0 + (rec.y >> 8);
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-            if (mask & (1u << s)) {
-                const T *c = sc + (size_t)3 * e;
-                b[s][0] += c[0] * d;
-                b[s][1] += c[1] * d;
-                b[s][2] += c[2] * d;
-                ++e;
-            }
-    }
     const int M = m.M[i];
     const T v23 = (T)m.vol23[i];
     const T S00 = (T)m.m2[i], S01 = (T)m.m2[n + i], S02 = (T)m.m2[2 * n + i], S11 = (T)m.m2[3 * n + i],
             S12 = (T)m.m2[4 * n + i], S22 = (T)m.m2[5 * n + i];
-    // a: x y z xx xy xz yy yz zz
-    const T H[3][3] = {{T(2) * a[3], a[4], a[5]}, {a[4], T(2) * a[6], a[7]}, {a[5], a[7], T(2) * a[8]}};
-    T beta0 = T(0);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const T h0 = H[d][0], h1 = H[d][1], h2 = H[d][2];
-        const T quad = h0 * (S00 * h0 + S01 * h1 + S02 * h2) + h1 * (S01 * h0 + S11 * h1 + S12 * h2) +
-                       h2 * (S02 * h0 + S12 * h1 + S22 * h2);
-        beta0 += a[d] * a[d] + quad;
-    }
-    const T sec = T(4) * (a[3] * a[3] + a[6] * a[6] + a[8] * a[8]) + a[4] * a[4] + a[5] * a[5] + a[7] * a[7];
-    beta0 = v23 * beta0 + v23 * v23 * sec;
     const T gm = (T)wp.gm, g0 = T(1) - gm * T(M), eps = (T)wp.eps, pw = (T)wp.p;
-    T beta[8];
-    T tw = T(0);
+    T *outc = coeff + (size_t)50 * i;
+#pragma unroll 1
+    for (int comp = 0; comp < 5; ++comp) {
+        const double *Qc = Q + (size_t)comp * n;
+        const double q0 = Qc[i];
+        T a[9], b[8][3];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        beta[s] = v23 * (b[s][0] * b[s][0] + b[s][1] * b[s][1] + b[s][2] * b[s][2]);
-        if (s < M) tw += fabs(beta0 - beta[s]);
-    }
-    tw /= T(M);
-    T w0, ws[8];
-    if (wp.force_linear) {
-        w0 = g0;
+        for (int j = 0; j < 9; ++j) a[j] = T(0);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) ws[s] = gm;
-    } else {
-        w0 = g0 * (T(1) + wpow(tw / (beta0 + eps), pw));
+        for (int s = 0; s < 8; ++s) b[s][0] = b[s][1] = b[s][2] = T(0);
+        for (int k = k0 + l; k < k1; k += kK1Lanes) {
+            const int2 rec = m.st_rec[k];
+            const T d = (T)(Qc[rec.x] - q0);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) ws[s] = gm * (T(1) + wpow(tw / (beta[s] + eps), pw));
-    }
-    T sum = w0;
+            for (int j = 0; j < 9; ++j) a[j] += pinv[(size_t)j * nnz + k] * d;
+            const unsigned mask = (unsigned)rec.y & 255u;
+            int e = e0 + (rec.y >> 8);
 #pragma unroll
-    for (int s = 0; s < 8; ++s)
-        if (s < M) sum += ws[s];
-    const T isum = T(1) / sum;
-    const T f0 = w0 * isum / g0;  // factor of P_0
-    T c[10];
-#pragma unroll
-    for (int j = 0; j < 9; ++j) c[1 + j] = f0 * a[j];
-    const T sub0 = f0 * gm;  // omega_0 gamma_m / gamma_0
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-        if (s < M) {
-            const T fs = ws[s] * isum - sub0;
-            c[1] += fs * b[s][0];
-            c[2] += fs * b[s][1];
-            c[3] += fs * b[s][2];
+            for (int s = 0; s < 8; ++s)
+                if (mask & (1u << s)) {
+                    b[s][0] += sc[e] * d;
+                    b[s][1] += sc[(size_t)nsc + e] * d;
+                    b[s][2] += sc[(size_t)2 * nsc + e] * d;
+                    ++e;
+                }
         }
-    // constant term: cell average minus the means of the quadratic monomials
-    const T corr = -(c[4] * S00 + c[5] * S01 + c[6] * S02 + c[7] * S11 + c[8] * S12 + c[9] * S22);
-    if constexpr (sizeof(T) == 8)
-        c[0] = (T)q0 + corr;
-    else
-        c[0] = corr;
-    T *out = coeff + (size_t)50 * i + 10 * comp;
 #pragma unroll
-    for (int j = 0; j < 10; ++j) out[j] = c[j];
+        for (int j = 0; j < 9; ++j) a[j] = bfly_sum8(a[j]);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            b[s][0] = bfly_sum8(b[s][0]);
+            b[s][1] = bfly_sum8(b[s][1]);
+            b[s][2] = bfly_sum8(b[s][2]);
+        }
+        // smoothness indicators (Eq. indicator) over the cell: a = x y z xx xy xz yy yz zz
+        const T H[3][3] = {{T(2) * a[3], a[4], a[5]}, {a[4], T(2) * a[6], a[7]}, {a[5], a[7], T(2) * a[8]}};
+        T beta0 = T(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T h0 = H[d][0], h1 = H[d][1], h2 = H[d][2];
+            const T quad = h0 * (S00 * h0 + S01 * h1 + S02 * h2) + h1 * (S01 * h0 + S11 * h1 + S12 * h2) +
+                           h2 * (S02 * h0 + S12 * h1 + S22 * h2);
+            beta0 += a[d] * a[d] + quad;
+        }
+        const T sec = T(4) * (a[3] * a[3] + a[6] * a[6] + a[8] * a[8]) + a[4] * a[4] + a[5] * a[5] + a[7] * a[7];
+        beta0 = v23 * beta0 + v23 * v23 * sec;
+        T beta[8];
+        T tw = T(0);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            beta[s] = v23 * (b[s][0] * b[s][0] + b[s][1] * b[s][1] + b[s][2] * b[s][2]);
+            if (s < M) tw += fabs(beta0 - beta[s]);
+        }
+        tw /= T(M);
+        // nonlinear weights and Eq. weno folded into one quadratic
+        T w0, ws[8];
+        if (wp.force_linear) {
+            w0 = g0;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) ws[s] = gm;
+        } else {
+            w0 = g0 * (T(1) + wpow(tw / (beta0 + eps), pw));
+#pragma unroll
+            for (int s = 0; s < 8; ++s) ws[s] = gm * (T(1) + wpow(tw / (beta[s] + eps), pw));
+        }
+        T sum = w0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            if (s < M) sum += ws[s];
+        const T isum = T(1) / sum;
+        const T f0 = w0 * isum / g0;
+        T c[10];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) c[1 + j] = f0 * a[j];
+        const T sub0 = f0 * gm;
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            if (s < M) {
+                const T fs = ws[s] * isum - sub0;
+                c[1] += fs * b[s][0];
+                c[2] += fs * b[s][1];
+                c[3] += fs * b[s][2];
+            }
+        // constant term: cell average minus the means of the quadratic monomials
+        const T corr = -(c[4] * S00 + c[5] * S01 + c[6] * S02 + c[7] * S11 + c[8] * S12 + c[9] * S22);
+        if constexpr (sizeof(T) == 8)
+            c[0] = (T)q0 + corr;
+        else
+            c[0] = corr;
+        // lane l writes entries l and l + 8 of this component
+        T v0 = c[0], v1 = c[8];
+#pragma unroll
+        for (int j = 1; j < 8; ++j)
+            if (l == j) v0 = c[j];
+        if (l == 1) v1 = c[9];
+        if (valid) {
+            outc[10 * comp + l] = v0;
+            if (l < 2) outc[10 * comp + 8 + l] = v1;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -286,7 +354,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict_
                                                  const double *__restrict__ dt_dev, T *__restrict__ ff, FluxParams<T> fp,
                                                  int *status)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int f = t >> 2;
     const bool live = f < m.nf;
     const int fs = live ? f : m.nf - 1;  // tail lanes compute a valid face and write nothing
@@ -353,7 +421,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_residual(DevMesh m, const T *__restrict__ ff, double *__restrict__ Lout,
                                                      double *__restrict__ Dout)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= m.n) return;
     double L[5], D[5];
     gather(m, ff, i, L, D);
@@ -369,7 +437,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_stage1(DevMesh m, const T *__restrict__ ff, double *__restrict__ Q,
                                                    double *__restrict__ Qs, const double *__restrict__ dt_dev)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= m.n) return;
     const double dt = dt_dev[0];
     double L[5], D[5];
@@ -387,7 +455,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_stage2(DevMesh m, const T *__restrict__ ff, double *__restrict__ Q,
                                                    const double *__restrict__ dt_dev)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= m.n) return;
     const double dt = dt_dev[0];
     double L[5], D[5];
@@ -592,15 +660,21 @@ static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *ba
             for (int q = 0; q < 6; ++q) std::memcpy(&m2t[8 * (q * n + i)], &H.m2[6 * i + q], 8);
         }
     }
-    auto convert = [&](const std::vector<double> &v) {
+    // [rows][width] row-major host data -> [width][rows] on the device, FP64 or FP32
+    auto convert_t = [&](const std::vector<double> &v, size_t width) {
         std::vector<char> out(v.size() * es);
         if (owned) {
-            if (es == 8)
-                std::memcpy(out.data(), v.data(), out.size());
-            else
-                for (size_t k = 0; k < v.size(); ++k) {
-                    float f = (float)v[k];
-                    std::memcpy(&out[4 * k], &f, 4);
+            const size_t rows = v.size() / width;
+            for (size_t r = 0; r < rows; ++r)
+                for (size_t j = 0; j < width; ++j) {
+                    const double x = v[r * width + j];
+                    const size_t o = j * rows + r;
+                    if (es == 8)
+                        std::memcpy(&out[8 * o], &x, 8);
+                    else {
+                        const float f = (float)x;
+                        std::memcpy(&out[4 * o], &f, 4);
+                    }
                 }
         }
         return out;
@@ -625,8 +699,10 @@ static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *ba
             }
         dm.st_rec = owned ? (const int2 *)put_vec(std::move(rec)) : (const int2 *)put(nullptr, 8 * H.st_idx.size());
     }
-    dm.pinv = put_vec(convert(H.pinv));
-    dm.sc = put_vec(convert(H.sc));
+    dm.nnz = (int)H.st_idx.size();
+    dm.nsc = (int)(H.sc.size() / 3);
+    dm.pinv = put_vec(convert_t(H.pinv, 9));
+    dm.sc = put_vec(convert_t(H.sc, 3));
     dm.owner = (const int32_t *)put(H.owner.data(), 4 * nf);
     dm.nbr = (const int32_t *)put(H.nbr.data(), 4 * nf);
     dm.fgeo = (const double *)put(H.fgeo.data(), 8 * H.fgeo.size());
@@ -763,7 +839,7 @@ static WenoParams weno_params(const gks_params *p)
 
 static gks_status launch_reconstruct(gks_mesh *m, const double *Q, void *coeff, const gks_params *p, hipStream_t st)
 {
-    const unsigned grid = grid_for(5 * m->n, kK1Block);
+    const unsigned grid = grid_for((int64_t)kK1Lanes * m->n, kK1Block);
     ProfScope ps(m, GKS_K_RECONSTRUCT, st);
     if (m->precision == GKS_FP64)
         k_reconstruct<double><<<grid, kK1Block, 0, st>>>(m->d, Q, (double *)coeff, weno_params(p));

@@ -481,8 +481,35 @@ __host__ __device__ __forceinline__ void side_state(const T *__restrict__ c, con
  * point's (Fbar0, Fbar1) contribution to the face, owner -> neighbour.
  * ql0, qr0: FP64 cell averages (used by the FP32 variant only).
  */
+// Copy one cell's 50 coefficients with 16-byte loads (the per-cell block is 16-byte aligned).
+template <typename T>
+__host__ __device__ __forceinline__ void load_cell(const T *__restrict__ src, T dst[50])
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (sizeof(T) == 8) {
+        const double2 *s2 = reinterpret_cast<const double2 *>(src);
+#pragma unroll
+        for (int q = 0; q < 25; ++q) {
+            const double2 v = s2[q];
+            dst[2 * q] = v.x;
+            dst[2 * q + 1] = v.y;
+        }
+    } else {
+        const float2 *s2 = reinterpret_cast<const float2 *>(src);  // 200-byte blocks: 8-byte alignment
+#pragma unroll
+        for (int q = 0; q < 25; ++q) {
+            const float2 v = s2[q];
+            dst[2 * q] = v.x;
+            dst[2 * q + 1] = v.y;
+        }
+    }
+#else
+    for (int q = 0; q < 50; ++q) dst[q] = src[q];
+#endif
+}
+
 template <typename T, bool PR>
-__host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl, const T *__restrict__ cr, const double *ql0,
+__host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, const T *__restrict__ cr_g, const double *ql0,
                                                  const double *qr0, const T geo[9], T dt, const FluxParams<T> &fp,
                                                  T out[10])
 {
@@ -492,12 +519,14 @@ __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl, const
     acc_zero(A);
     bool ok;
     {
-        T q[5], dq[3][5];
+        T q[5], dq[3][5], cl[50];
+        load_cell(cl_g, cl);
         side_state(cl, ql0, geo[0], geo[1], geo[2], n3, q, dq);
         ok = side_pass<T, PR>(q, dq, T(1), fp, A, 0);
     }
     {
-        T q[5], dq[3][5];
+        T q[5], dq[3][5], cr[50];
+        load_cell(cr_g, cr);
         side_state(cr, qr0, geo[3], geo[4], geo[5], n3, q, dq);
         ok = side_pass<T, PR>(q, dq, T(-1), fp, A, 1) && ok;
     }
