@@ -29,12 +29,6 @@ HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
-# FP64 operations of one Gauss-point flux evaluation of the flux kernel (state
-# evaluation from the two quadratics, frame, BGK flux with both time integrals,
-# rotation back and weighting), counted from the kernel source by executing it
-# on the host with an operation-counting number type; see the design doc.
-FLUX_FLOPS_PER_GP_INVISCID = None
-FLUX_FLOPS_PER_GP_VISCOUS = None
 
 
 def log(*a):
@@ -46,7 +40,7 @@ def algorithmic_bytes(host, es):
     n, nf, ns = host.n, host.n_faces, host.n_stencil
     nsc = host.n_subcoef
     ncf = host.n_cellfaces
-    recon = 40 * n + 8 * n + 4 * ns + ns + 9 * es * ns + 3 * es * nsc + n + 8 * n + 48 * n + 50 * es * n
+    recon = 40 * n + 4 * n + 8 * ns + 9 * es * ns + 3 * es * ns + 6 * es * nsc + n + 8 * n + 48 * n + 50 * es * n
     flux = 8 * nf + 9 * 4 * 8 * nf + 50 * es * n + 10 * es * nf + (40 * n if es == 4 else 0)
     stage1 = 4 * n + 4 * ncf + 10 * es * nf + 8 * n + 40 * n + 40 * n + 40 * n
     stage2 = 4 * n + 4 * ncf + 10 * es * nf + 8 * n + 40 * n + 40 * n
@@ -111,6 +105,8 @@ def main():
     ap.add_argument("--N", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
@@ -123,6 +119,14 @@ def main():
     gks.load()
     if not torch.cuda.is_available():
         raise SystemExit("no GPU")
+    if args.copy_calibration:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 1 GiB (read 1 GiB + write 1 GiB each)")
+        del x, y
     t = time.perf_counter()
     mesh = inputs.lattice(args.N, "hybrid", box=(2 * math.pi,) * 3)
     Q0 = inputs.cell_averages(mesh, inputs.tgv())
@@ -153,8 +157,13 @@ def main():
     bytes64 = algorithmic_bytes(host, 8)
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
     avg_s = kern[dom]["avg_ms"] * 1e-3
-    if dom == "flux" and FLUX_FLOPS_PER_GP_VISCOUS:
-        fl = FLUX_FLOPS_PER_GP_VISCOUS * 4 * host.n_faces
+    # FP64 operations of one Gauss point of the flux kernel (both sides' states, frame, BGK flux with
+    # both time integrals, rotation back), counted by the library from the kernel's own templated body
+    ops = gks.gp_op_count(viscous=True, Pr=0.72)
+    flops_gp = ops["add"] + ops["mul"] + ops["div"]
+    res["flux_ops_per_gauss_point"] = ops
+    if dom == "flux":
+        fl = flops_gp * 4 * host.n_faces
         achieved = fl / avg_s / 1e12
         res["roofline"] = dict(kernel=dom, bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS,
                                unit="TFLOP/s", frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=None)

@@ -58,11 +58,11 @@ struct DevMesh {
     const double *m2;       // [6][n] centred second moments (means)
     const double *hcfl;     // 6 |Omega| / sum of face areas
     const int32_t *st_ptr;  // [n+1]
-    const int32_t *sc_ptr;  // [n+1] (units of 3 coefficients)
-    const int2 *st_rec;     // members: {cell, mask | (relative coefficient offset << 8)}
-    int nnz, nsc;           // stencil members, sub-stencil coefficient triples
+    const int2 *st_rec;     // members: {cell, sub-stencil membership mask}
+    int nnz;                // stencil members
     const void *pinv;       // [9][nnz] (coefficient-major), FP64 or FP32
-    const void *sc;         // [3][nsc] (coefficient-major), FP64 or FP32
+    const void *dsc;        // [3][nnz] scaled member centroid offsets, FP64 or FP32
+    const void *ginv;       // [48][n] inverses of the sub-stencil normal matrices / h, FP64 or FP32
     // faces
     const int32_t *owner, *nbr;
     const double *fgeo;     // [9][4 nf]
@@ -168,14 +168,16 @@ __device__ __forceinline__ T wpow(T x, T p)
     return (T)pow((double)x, (double)p);
 }
 
-// 8 lanes cooperate on one cell: lane l streams members l, l+8, ... of the cell's
-// stencil (consecutive lanes read consecutive pseudo-inverse rows), then the
-// partial fits are summed across the 8 lanes with a fixed butterfly, so every
-// lane holds identical totals (deterministic, no atomics).
-constexpr int kK1Lanes = 8;
-constexpr int kK1Block = 256;  // 32 cells per block
+// Four lanes cooperate on one (cell, conserved component): lane l streams
+// members l, l+4, ... of the cell's stencil, so a cell's 20 lanes read
+// consecutive operator entries and each lane's chain of dependent loads is short;
+// the partial fits are summed over the quad with DPP lane permutations, so every
+// lane of the quad holds bitwise-identical totals (deterministic, no atomics).
+constexpr int kK1Lanes = 4;
+constexpr int kK1CellLanes = 5 * kK1Lanes;
+constexpr int kK1Block = 16 * kK1CellLanes;  // 16 cells, 5 waves
 
-// DPP lane permutations (VALU, no LDS traffic) of a 32-bit value within groups of 8 lanes
+// DPP lane permutations (VALU, no LDS traffic) of a 32-bit value within a quad of lanes
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v)
 {
@@ -194,16 +196,14 @@ __device__ __forceinline__ float dpp_t(float v) { return dpp_f32<CTRL>(v); }
 template <int CTRL>
 __device__ __forceinline__ double dpp_t(double v) { return dpp_f64<CTRL>(v); }
 
-constexpr int kDppHalfMirror = 0x141;  // lane i <- lane 7 - i within each group of 8
-constexpr int kDppQuadXor1 = 0xB1;     // quad_perm [1,0,3,2]
-constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
 
-// Sum over a group of 8 lanes; every lane gets the bitwise-identical total
+// Sum over a quad of lanes; every lane gets the bitwise-identical total
 // (each step adds the same two partial sums, only in swapped order).
 template <typename T>
-__device__ __forceinline__ T bfly_sum8(T v)
+__device__ __forceinline__ T quad_sum(T v)
 {
-    v += dpp_t<kDppHalfMirror>(v);
     v += dpp_t<kDppQuadXor1>(v);
     v += dpp_t<kDppQuadXor2>(v);
     return v;
@@ -217,126 +217,134 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     const int x = b & 7, j = b >> 3;
     return x * q + (x < r ? x : r) + j;
 }
-
 template <typename T>
 __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff,
                                                           WenoParams wp)
 {
     const int t = xcd_block(blockIdx.x, gridDim.x) * kK1Block + threadIdx.x;
     const int n = m.n;
-    const int ic = t / kK1Lanes;
-    const int l = t - kK1Lanes * ic;
+    const int ic = t / kK1CellLanes;
+    const int lane = t - kK1CellLanes * ic;
+    const int comp = lane >> 2;
+    const int l = lane & 3;
     const bool valid = ic < n;
     const int i = valid ? ic : n - 1;  // tail lanes shadow the last cell and write nothing
     const T *pinv = (const T *)m.pinv;
-    const T *sc = (const T *)m.sc;
-    const int nnz = m.nnz, nsc = m.nsc;
+    const T *dsc = (const T *)m.dsc;
+    const int nnz = m.nnz;
     const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
-    const int e0 = m.sc_ptr[i];
+    const double *Qc = Q + (size_t)comp * n;
+    const double q0 = Qc[i];
+    T a[9], r[8][3];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) a[j] = T(0);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) r[s][0] = r[s][1] = r[s][2] = T(0);
+#pragma unroll 2
+    for (int k = k0 + l; k < k1; k += kK1Lanes) {
+        const int2 rec = m.st_rec[k];
+        const T d = (T)(Qc[rec.x] - q0);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) a[j] += pinv[(size_t)j * nnz + k] * d;
+        const T dx = dsc[k] * d, dy = dsc[(size_t)nnz + k] * d, dz = dsc[(size_t)2 * nnz + k] * d;
+        const unsigned mask = (unsigned)rec.y;
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            if (mask & (1u << s)) {
+                r[s][0] += dx;
+                r[s][1] += dy;
+                r[s][2] += dz;
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) a[j] = quad_sum(a[j]);
+    // linear sub-stencil fits: b^m = G_m^{-1} r_m / h (normal equations of the scaled offsets)
+    const T *gi = (const T *)m.ginv;
+    T b[8][3];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const T r0 = quad_sum(r[s][0]), r1 = quad_sum(r[s][1]), r2 = quad_sum(r[s][2]);
+        const T g00 = gi[(size_t)(6 * s + 0) * n + i], g01 = gi[(size_t)(6 * s + 1) * n + i],
+                g02 = gi[(size_t)(6 * s + 2) * n + i], g11 = gi[(size_t)(6 * s + 3) * n + i],
+                g12 = gi[(size_t)(6 * s + 4) * n + i], g22 = gi[(size_t)(6 * s + 5) * n + i];
+        b[s][0] = g00 * r0 + g01 * r1 + g02 * r2;
+        b[s][1] = g01 * r0 + g11 * r1 + g12 * r2;
+        b[s][2] = g02 * r0 + g12 * r1 + g22 * r2;
+    }
     const int M = m.M[i];
     const T v23 = (T)m.vol23[i];
     const T S00 = (T)m.m2[i], S01 = (T)m.m2[n + i], S02 = (T)m.m2[2 * n + i], S11 = (T)m.m2[3 * n + i],
             S12 = (T)m.m2[4 * n + i], S22 = (T)m.m2[5 * n + i];
     const T gm = (T)wp.gm, g0 = T(1) - gm * T(M), eps = (T)wp.eps, pw = (T)wp.p;
-    T *outc = coeff + (size_t)50 * i;
-#pragma unroll 1
-    for (int comp = 0; comp < 5; ++comp) {
-        const double *Qc = Q + (size_t)comp * n;
-        const double q0 = Qc[i];
-        T a[9], b[8][3];
+    // smoothness indicators (Eq. indicator) over the cell: a = x y z xx xy xz yy yz zz
+    const T H[3][3] = {{T(2) * a[3], a[4], a[5]}, {a[4], T(2) * a[6], a[7]}, {a[5], a[7], T(2) * a[8]}};
+    T beta0 = T(0);
 #pragma unroll
-        for (int j = 0; j < 9; ++j) a[j] = T(0);
+    for (int d = 0; d < 3; ++d) {
+        const T h0 = H[d][0], h1 = H[d][1], h2 = H[d][2];
+        const T quad = h0 * (S00 * h0 + S01 * h1 + S02 * h2) + h1 * (S01 * h0 + S11 * h1 + S12 * h2) +
+                       h2 * (S02 * h0 + S12 * h1 + S22 * h2);
+        beta0 += a[d] * a[d] + quad;
+    }
+    const T sec = T(4) * (a[3] * a[3] + a[6] * a[6] + a[8] * a[8]) + a[4] * a[4] + a[5] * a[5] + a[7] * a[7];
+    beta0 = v23 * beta0 + v23 * v23 * sec;
+    T beta[8];
+    T tw = T(0);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) b[s][0] = b[s][1] = b[s][2] = T(0);
-        for (int k = k0 + l; k < k1; k += kK1Lanes) {
-            const int2 rec = m.st_rec[k];
-            const T d = (T)(Qc[rec.x] - q0);
+    for (int s = 0; s < 8; ++s) {
+        beta[s] = v23 * (b[s][0] * b[s][0] + b[s][1] * b[s][1] + b[s][2] * b[s][2]);
+        if (s < M) tw += fabs(beta0 - beta[s]);
+    }
+    tw /= T(M);
+    // nonlinear weights and Eq. weno folded into one quadratic
+    T w0, ws[8];
+    if (wp.force_linear) {
+        w0 = g0;
 #pragma unroll
-            for (int j = 0; j < 9; ++j) a[j] += pinv[(size_t)j * nnz + k] * d;
-            const unsigned mask = (unsigned)rec.y & 255u;
-            int e = e0 + (rec.y >> 8);
+        for (int s = 0; s < 8; ++s) ws[s] = gm;
+    } else {
+        w0 = g0 * (T(1) + wpow(tw / (beta0 + eps), pw));
 #pragma unroll
-            for (int s = 0; s < 8; ++s)
-                if (mask & (1u << s)) {
-                    b[s][0] += sc[e] * d;
-                    b[s][1] += sc[(size_t)nsc + e] * d;
-                    b[s][2] += sc[(size_t)2 * nsc + e] * d;
-                    ++e;
-                }
+        for (int s = 0; s < 8; ++s) ws[s] = gm * (T(1) + wpow(tw / (beta[s] + eps), pw));
+    }
+    T sum = w0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+        if (s < M) sum += ws[s];
+    const T isum = T(1) / sum;
+    const T f0 = w0 * isum / g0;
+    T c[10];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) c[1 + j] = f0 * a[j];
+    const T sub0 = f0 * gm;
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+        if (s < M) {
+            const T fs = ws[s] * isum - sub0;
+            c[1] += fs * b[s][0];
+            c[2] += fs * b[s][1];
+            c[3] += fs * b[s][2];
         }
+    // constant term: cell average minus the means of the quadratic monomials
+    const T corr = -(c[4] * S00 + c[5] * S01 + c[6] * S02 + c[7] * S11 + c[8] * S12 + c[9] * S22);
+    if constexpr (sizeof(T) == 8)
+        c[0] = (T)q0 + corr;
+    else
+        c[0] = corr;
+    // lane l writes entries l, l + 4 and (lanes 0, 1) l + 8 of this component
+    T v0 = c[0], v1 = c[4], v2 = c[8];
 #pragma unroll
-        for (int j = 0; j < 9; ++j) a[j] = bfly_sum8(a[j]);
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            b[s][0] = bfly_sum8(b[s][0]);
-            b[s][1] = bfly_sum8(b[s][1]);
-            b[s][2] = bfly_sum8(b[s][2]);
+    for (int j = 1; j < 4; ++j)
+        if (l == j) {
+            v0 = c[j];
+            v1 = c[4 + j];
         }
-        // smoothness indicators (Eq. indicator) over the cell: a = x y z xx xy xz yy yz zz
-        const T H[3][3] = {{T(2) * a[3], a[4], a[5]}, {a[4], T(2) * a[6], a[7]}, {a[5], a[7], T(2) * a[8]}};
-        T beta0 = T(0);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const T h0 = H[d][0], h1 = H[d][1], h2 = H[d][2];
-            const T quad = h0 * (S00 * h0 + S01 * h1 + S02 * h2) + h1 * (S01 * h0 + S11 * h1 + S12 * h2) +
-                           h2 * (S02 * h0 + S12 * h1 + S22 * h2);
-            beta0 += a[d] * a[d] + quad;
-        }
-        const T sec = T(4) * (a[3] * a[3] + a[6] * a[6] + a[8] * a[8]) + a[4] * a[4] + a[5] * a[5] + a[7] * a[7];
-        beta0 = v23 * beta0 + v23 * v23 * sec;
-        T beta[8];
-        T tw = T(0);
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            beta[s] = v23 * (b[s][0] * b[s][0] + b[s][1] * b[s][1] + b[s][2] * b[s][2]);
-            if (s < M) tw += fabs(beta0 - beta[s]);
-        }
-        tw /= T(M);
-        // nonlinear weights and Eq. weno folded into one quadratic
-        T w0, ws[8];
-        if (wp.force_linear) {
-            w0 = g0;
-#pragma unroll
-            for (int s = 0; s < 8; ++s) ws[s] = gm;
-        } else {
-            w0 = g0 * (T(1) + wpow(tw / (beta0 + eps), pw));
-#pragma unroll
-            for (int s = 0; s < 8; ++s) ws[s] = gm * (T(1) + wpow(tw / (beta[s] + eps), pw));
-        }
-        T sum = w0;
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-            if (s < M) sum += ws[s];
-        const T isum = T(1) / sum;
-        const T f0 = w0 * isum / g0;
-        T c[10];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) c[1 + j] = f0 * a[j];
-        const T sub0 = f0 * gm;
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-            if (s < M) {
-                const T fs = ws[s] * isum - sub0;
-                c[1] += fs * b[s][0];
-                c[2] += fs * b[s][1];
-                c[3] += fs * b[s][2];
-            }
-        // constant term: cell average minus the means of the quadratic monomials
-        const T corr = -(c[4] * S00 + c[5] * S01 + c[6] * S02 + c[7] * S11 + c[8] * S12 + c[9] * S22);
-        if constexpr (sizeof(T) == 8)
-            c[0] = (T)q0 + corr;
-        else
-            c[0] = corr;
-        // lane l writes entries l and l + 8 of this component
-        T v0 = c[0], v1 = c[8];
-#pragma unroll
-        for (int j = 1; j < 8; ++j)
-            if (l == j) v0 = c[j];
-        if (l == 1) v1 = c[9];
-        if (valid) {
-            outc[10 * comp + l] = v0;
-            if (l < 2) outc[10 * comp + 8 + l] = v1;
-        }
+    if (l == 1) v2 = c[9];
+    if (valid) {
+        T *out = coeff + (size_t)50 * i + 10 * comp;
+        out[l] = v0;
+        out[4 + l] = v1;
+        if (l < 2) out[8 + l] = v2;
     }
 }
 
@@ -602,7 +610,7 @@ gks_status gks_host_mesh_counts(const gks_host_mesh *h, int64_t *n_cells, int64_
     if (n_cells) *n_cells = h->h.n;
     if (n_faces) *n_faces = h->h.nf;
     if (n_stencil) *n_stencil = (int64_t)h->h.st_idx.size();
-    if (n_subcoef) *n_subcoef = (int64_t)h->h.sc.size() / 3;
+    if (n_subcoef) *n_subcoef = (int64_t)h->h.ginv.size() / 6;
     if (n_grown) *n_grown = h->h.n_grown;
     return GKS_OK;
 }
@@ -689,20 +697,20 @@ static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *ba
     dm.m2 = (const double *)put_vec(std::move(m2t));
     dm.hcfl = (const double *)put(H.hcfl.data(), 8 * n);
     dm.st_ptr = (const int32_t *)put(H.st_ptr.data(), 4 * (n + 1));
-    dm.sc_ptr = (const int32_t *)put(H.sc_ptr.data(), 4 * (n + 1));
     {
         std::vector<char> rec(owned ? 8 * H.st_idx.size() : 0);
         if (owned)
             for (size_t k = 0; k < H.st_idx.size(); ++k) {
                 std::memcpy(&rec[8 * k], &H.st_idx[k], 4);
-                std::memcpy(&rec[8 * k + 4], &H.st_meta[k], 4);
+                const int32_t mk = H.st_mask[k];
+                std::memcpy(&rec[8 * k + 4], &mk, 4);
             }
         dm.st_rec = owned ? (const int2 *)put_vec(std::move(rec)) : (const int2 *)put(nullptr, 8 * H.st_idx.size());
     }
     dm.nnz = (int)H.st_idx.size();
-    dm.nsc = (int)(H.sc.size() / 3);
     dm.pinv = put_vec(convert_t(H.pinv, 9));
-    dm.sc = put_vec(convert_t(H.sc, 3));
+    dm.dsc = put_vec(convert_t(H.dsc, 3));
+    dm.ginv = put_vec(convert_t(H.ginv, 48));
     dm.owner = (const int32_t *)put(H.owner.data(), 4 * nf);
     dm.nbr = (const int32_t *)put(H.nbr.data(), 4 * nf);
     dm.fgeo = (const double *)put(H.fgeo.data(), 8 * H.fgeo.size());
@@ -839,7 +847,7 @@ static WenoParams weno_params(const gks_params *p)
 
 static gks_status launch_reconstruct(gks_mesh *m, const double *Q, void *coeff, const gks_params *p, hipStream_t st)
 {
-    const unsigned grid = grid_for((int64_t)kK1Lanes * m->n, kK1Block);
+    const unsigned grid = grid_for((int64_t)kK1CellLanes * m->n, kK1Block);
     ProfScope ps(m, GKS_K_RECONSTRUCT, st);
     if (m->precision == GKS_FP64)
         k_reconstruct<double><<<grid, kK1Block, 0, st>>>(m->d, Q, (double *)coeff, weno_params(p));

@@ -20,12 +20,13 @@ struct HostMesh {
     std::vector<int8_t> type;
     std::vector<double> vol, xc, m2, hcfl;  // m2: [n][6] xx xy xz yy yz zz (centred means)
     // stencil: members of cell i are st_idx[st_ptr[i] .. st_ptr[i+1]); per member a
-    // sub-stencil mask, a row of the quadratic pseudo-inverse (9), and 3 coefficients
-    // for each sub-stencil in its mask (stored consecutively from sc_ptr[i])
-    std::vector<int32_t> st_ptr, st_idx, sc_ptr;
+    // sub-stencil membership mask, a row of the quadratic pseudo-inverse (9, zero for
+    // members only a sub-stencil uses) and its centroid offset scaled by h = |Omega_i|^(1/3)
+    // (3); per cell the inverses G_m^{-1}/h of the sub-stencil normal matrices
+    // (6 unique entries xx xy xz yy yz zz for each of 8 slots)
+    std::vector<int32_t> st_ptr, st_idx;
     std::vector<uint8_t> st_mask;
-    std::vector<int32_t> st_meta;  // per member: mask | (offset of its first coefficient triple - sc_ptr[i]) << 8
-    std::vector<double> pinv, sc;
+    std::vector<double> pinv, dsc, ginv;
     // faces
     std::vector<int32_t> owner, nbr;
     std::vector<double> fgeo;  // [9][4 nf]: d_owner(3), d_neighbour(3), weighted vector area(3) per Gauss point

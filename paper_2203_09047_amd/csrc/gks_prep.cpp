@@ -395,12 +395,11 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
     H.m2.resize(6 * n);
     H.hcfl.resize(n);
     H.st_ptr.assign(n + 1, 0);
-    H.sc_ptr.assign(n + 1, 0);
     H.st_idx.clear();
     H.st_mask.clear();
-    H.st_meta.clear();
     H.pinv.clear();
-    H.sc.clear();
+    H.dsc.clear();
+    H.ginv.clear();
     H.n_grown = 0;
 
     auto member_row = [&](const CellGeom &g0, const Member &m, int k, double h, double *row) {
@@ -453,7 +452,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
     struct CellOut {
         std::vector<int32_t> idx;
         std::vector<uint8_t> mask;
-        std::vector<double> pinv, sc;
+        std::vector<double> pinv, dsc, ginv;
         int grown = 0;
         int err = 0;  // 0 ok, 1 big fit singular, 2 sub fit singular, 3 too large
     };
@@ -534,6 +533,30 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
             out.err = 3;
             return;
         }
+        // scaled centroid offsets of the members: the linear sub-stencil fits are
+        // b^m = (1/h) G_m^{-1} sum_{k in S_m} D_k (Q_k - Q_0), G_m = sum_{k in S_m} D_k D_k^T
+        std::vector<std::array<double, 3>> Ds(members.size());
+        for (size_t k = 0; k < members.size(); ++k)
+            for (int d = 0; d < 3; ++d)
+                Ds[k][d] = (geo[members[k].cell].xc[d] + members[k].sh[d] * box[d] - g.xc[d]) / h;
+        out.ginv.assign(48, 0.0);
+        for (int m = 0; m < M; ++m) {
+            double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            for (int k : slot[m])
+                for (int p = 0; p < 3; ++p)
+                    for (int q = 0; q < 3; ++q) G[p][q] += Ds[k][p] * Ds[k][q];
+            const double c00 = G[1][1] * G[2][2] - G[1][2] * G[2][1];
+            const double c01 = G[0][2] * G[2][1] - G[0][1] * G[2][2];
+            const double c02 = G[0][1] * G[1][2] - G[0][2] * G[1][1];
+            const double c11 = G[0][0] * G[2][2] - G[0][2] * G[2][0];
+            const double c12 = G[0][2] * G[1][0] - G[0][0] * G[1][2];
+            const double c22 = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+            const double det = G[0][0] * c00 + G[0][1] * (G[1][2] * G[2][0] - G[1][0] * G[2][2]) +
+                               G[0][2] * (G[1][0] * G[2][1] - G[1][1] * G[2][0]);
+            const double s = 1.0 / (det * h);
+            const double inv6[6] = {c00 * s, c01 * s, c02 * s, c11 * s, c12 * s, c22 * s};
+            for (int q = 0; q < 6; ++q) out.ginv[6 * m + q] = inv6[q];
+        }
         for (size_t k = 0; k < members.size(); ++k) {
             uint8_t mask = 0;
             for (int m = 0; m < M; ++m)
@@ -543,12 +566,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
             out.mask.push_back(mask);
             for (int j = 0; j < 9; ++j)
                 out.pinv.push_back((int)k < nls ? P0[(size_t)j * nls + k] : 0.0);
-            for (int m = 0; m < M; ++m)
-                if (mask & (1u << m)) {
-                    const int rows = (int)subs[m].size();
-                    int e = (int)(std::find(slot[m].begin(), slot[m].end(), (int)k) - slot[m].begin());
-                    for (int j = 0; j < 3; ++j) out.sc.push_back(Pm[m][(size_t)j * rows + e]);
-                }
+            for (int d = 0; d < 3; ++d) out.dsc.push_back(Ds[k][d]);
         }
     };
 #pragma omp parallel for schedule(dynamic, 256)
@@ -561,22 +579,14 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         H.n_grown += o.grown;
         H.st_ptr[i + 1] = H.st_ptr[i] + (int32_t)o.idx.size();
         H.st_idx.insert(H.st_idx.end(), o.idx.begin(), o.idx.end());
-        {
-            // member record: sub-stencil mask in the low byte, offset of the member's first
-            // sub-stencil coefficient triple (relative to the cell's first) above it
-            int32_t rel = 0;
-            for (uint8_t mk : o.mask) {
-                H.st_mask.push_back(mk);
-                H.st_meta.push_back((int32_t)mk | (rel << 8));
-                rel += __builtin_popcount(mk);
-            }
-        }
+        H.st_mask.insert(H.st_mask.end(), o.mask.begin(), o.mask.end());
         H.pinv.insert(H.pinv.end(), o.pinv.begin(), o.pinv.end());
-        H.sc.insert(H.sc.end(), o.sc.begin(), o.sc.end());
-        H.sc_ptr[i + 1] = (int32_t)(H.sc.size() / 3);
+        H.dsc.insert(H.dsc.end(), o.dsc.begin(), o.dsc.end());
+        H.ginv.insert(H.ginv.end(), o.ginv.begin(), o.ginv.end());
         CellOut().idx.swap(o.idx);
         std::vector<double>().swap(o.pinv);
-        std::vector<double>().swap(o.sc);
+        std::vector<double>().swap(o.dsc);
+        std::vector<double>().swap(o.ginv);
         std::vector<uint8_t>().swap(o.mask);
     }
     for (auto &v : H.st_idx) v = (int32_t)inv[v];
