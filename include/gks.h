@@ -190,6 +190,34 @@ gks_status gks_residual(gks_mesh *m, const void *face_flux, double *L, double *d
 gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_params *p, void *work, double *Q_star,
                          gks_stream_t stream);
 
+/*
+ * Discrete adjoint of one S2O4 step (FP64 meshes only), the dt of the step
+ * being a constant.  With the step written as
+ *   Q* = Q + dt/2 L(Q) + dt^2/8 D(Q),  Q' = Q + dt L(Q) + dt^2/6 (D(Q) + 2 D(Q*)),
+ * and lam' = dJ/dQ' [5][n_cells] (device), it computes
+ *   lam* = dt^2/3 J_D(Q*)^T lam',
+ *   lam  = lam' + lam* + J_L(Q)^T (dt lam' + dt/2 lam*) + J_D(Q)^T (dt^2/6 lam' + dt^2/8 lam*)
+ * into lam_n, where J_L, J_D are the Jacobians of the reconstruction -> flux ->
+ * Eq. finite operator (including the nonlinear WENO weights and the collision
+ * time; |x| is differentiated as sign(x), sign(0) = 0).  Qn and Qstar are the
+ * step's start state and stage state (as produced by gks_s2o4_step), dt_dev
+ * the step's dt.  adj_work: caller-owned device buffer of
+ * gks_adjoint_work_bytes(), 256-byte aligned.  Every gather runs in a fixed
+ * order (no atomics): the result is bitwise reproducible.
+ */
+gks_status gks_adjoint_work_bytes(const gks_host_mesh *h, size_t *bytes);
+gks_status gks_adjoint_step(gks_mesh *m, const double *Qn, const double *Qstar, const double *dt_dev,
+                            const double *lam_np1, double *lam_n, const gks_params *p, void *adj_work,
+                            gks_stream_t stream);
+
+/*
+ * Flow functional J = sum_i |Omega_i| |rho U_i|^2 / (2 rho_i) (kinetic energy)
+ * into *J_dev (deterministic two-pass sum), and its gradient dJ/dQ [5][n]
+ * into dJdQ when not NULL.  Uses the time-step partials of the work buffer.
+ */
+gks_status gks_kinetic_energy(gks_mesh *m, const double *Q, double *J_dev, double *dJdQ, void *work,
+                              gks_stream_t stream);
+
 /* Synchronise the stream and report GKS_ENONPHYS if the sticky flag is set. */
 gks_status gks_poll_status(gks_mesh *m, void *work, gks_stream_t stream);
 
@@ -217,10 +245,41 @@ enum {
     GKS_K_STAGE1 = 3,
     GKS_K_STAGE2 = 4,
     GKS_K_RESIDUAL = 5,
-    GKS_K_COUNT = 6
+    GKS_K_FLUX_ADJ = 6,
+    GKS_K_RECONSTRUCT_ADJ = 7,
+    GKS_K_GATHER_ADJ = 8,
+    GKS_K_COUNT = 9
 };
 gks_status gks_profile(gks_mesh *m, int enable);
 gks_status gks_profile_read(gks_mesh *m, double *total_ms, int64_t *launches);
+
+/*
+ * Host (CPU) execution of the same templated Gauss-point flux and of its
+ * hand-written reverse (vector-Jacobian product), FP64, for testing the
+ * adjoint against finite differences.  Arguments as gks_gp_flux_batch for
+ * one point (host pointers); outb [10] is the cotangent of (Fbar0, Fbar1),
+ * qlb, qrb [5] and dqlb, dqrb [3][5] receive the input cotangents.
+ */
+gks_status gks_gp_flux_host(const double *ql, const double *dql, const double *qr, const double *dqr, double dt,
+                            const gks_params *p, double *out);
+gks_status gks_gp_flux_vjp_host(const double *ql, const double *dql, const double *qr, const double *dqr, double dt,
+                                const gks_params *p, const double *outb, double *qlb, double *dqlb, double *qrb,
+                                double *dqrb);
+
+/*
+ * Host execution of the WENO combination of one cell and component (after the
+ * stencil sums) and of its reverse, FP64, for testing the adjoint:
+ * a [9] quadratic coefficients, r [8][3] sub-stencil sums sum_k D_k (Q_k - Q_0),
+ * gi [8][6] inverses of the sub-stencil normal matrices (divided by h),
+ * M sub-stencils, v23 = |Omega|^(2/3), S [6] centred second moments, q0 the cell
+ * average; c [10] the combined quadratic.  The reverse maps cb [10] to
+ * ab [9], rb [8][3] and the direct cotangent of q0.
+ */
+gks_status gks_weno_combine_host(const double *a, const double *r, const double *gi, int M, double v23,
+                                 const double *S, double q0, const gks_params *p, double *c);
+gks_status gks_weno_combine_vjp_host(const double *a, const double *r, const double *gi, int M, double v23,
+                                     const double *S, const gks_params *p, const double *cb, double *ab, double *rb,
+                                     double *q0b);
 
 /*
  * Floating-point operations of one face Gauss point of the flux kernel

@@ -9,6 +9,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgks.so")
 SOURCES = [os.path.join(HERE, "csrc", "gks_device.hip"), os.path.join(HERE, "csrc", "gks_prep.cpp")]
 DEPS = SOURCES + [os.path.join(HERE, "csrc", "gks_flux.h"), os.path.join(HERE, "csrc", "gks_internal.h"),
+                  os.path.join(HERE, "csrc", "gks_flux_adj.h"), os.path.join(HERE, "csrc", "gks_opcount.h"),
                   os.path.join(ROOT, "include", "gks.h")]
 
 HIPCC_FLAGS = [

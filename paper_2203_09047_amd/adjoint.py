@@ -1,0 +1,57 @@
+"""Checkpointed discrete adjoint of an S2O4 rollout behind torch.autograd.
+
+``Rollout.apply(Q0, solver, nsteps, ckpt_every)`` advances Q0 by nsteps CFL
+steps on the GPU and returns the final state; its backward propagates the
+cotangent of the final state to Q0 with the library's hand-written adjoint
+(``gks_adjoint_step``), recomputing each segment of ``ckpt_every`` steps from
+its checkpoint.  The step sizes chosen in the forward pass are frozen.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, Q0, solver, nsteps, ckpt_every=10):
+        Q = Q0.detach().clone()
+        dts = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=Q.device)
+        ckpts = {}
+        for k in range(nsteps):
+            if k % ckpt_every == 0:
+                ckpts[k] = Q.clone()
+            solver.step(Q)                       # CFL dt computed on the device into solver.dt
+            dts[k:k + 1].copy_(solver.dt)        # frozen for the adjoint
+        ctx.solver, ctx.nsteps, ctx.ckpt_every = solver, nsteps, ckpt_every
+        ctx.ckpts, ctx.dts = ckpts, dts
+        return Q
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        solver, nsteps, every = ctx.solver, ctx.nsteps, ctx.ckpt_every
+        lam = grad_out.detach().contiguous().clone()
+        lam_tmp = torch.empty_like(lam)
+        for seg in reversed(range(0, nsteps, every)):
+            last = min(seg + every, nsteps)
+            # recompute the segment, keeping each step's start state and stage state
+            Q = ctx.ckpts[seg].clone()
+            states = []
+            for k in range(seg, last):
+                Qn = Q.clone()
+                Qs = torch.empty_like(Q)
+                solver.step_to(Q, ctx.dts[k:k + 1], Q_star=Qs)
+                states.append((Qn, Qs))
+            for k in reversed(range(seg, last)):
+                Qn, Qs = states[k - seg]
+                solver.adjoint_step(Qn, Qs, ctx.dts[k:k + 1], lam, lam_tmp)
+                lam, lam_tmp = lam_tmp, lam
+        return lam, None, None, None
+
+
+def kinetic_energy_gradient(solver, Q0, nsteps, ckpt_every=10):
+    """(J, dJ/dQ0) of the kinetic energy after nsteps steps from Q0."""
+    Q0 = Q0.detach().clone().requires_grad_(True)
+    QT = Rollout.apply(Q0, solver, nsteps, ckpt_every)
+    J, g = solver.kinetic_energy(QT.detach(), grad=True)
+    QT.backward(g)
+    return J, Q0.grad

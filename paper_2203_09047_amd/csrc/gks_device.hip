@@ -26,6 +26,8 @@
 #include <vector>
 
 #include "gks_flux.h"
+#include "gks_flux_adj.h"
+#include "gks_weno.h"
 #include "gks_internal.h"
 #include "gks_opcount.h"
 
@@ -67,6 +69,7 @@ struct DevMesh {
     const int32_t *owner, *nbr;
     const double *fgeo;     // [9][4 nf]
     const int32_t *cf_ptr, *cf_idx;
+    const int32_t *tr_ptr, *tr_idx;  // transposed stencil (adjoint gathers)
 };
 
 // work buffer: status word, time-step partials, Q*, coefficients, face fluxes
@@ -155,19 +158,6 @@ __global__ void __launch_bounds__(kBlock) k_dt_final(int nb, const double *__res
 // ---------------------------------------------------------------------------
 // K1: WENO reconstruction, one lane per (cell, component)
 // ---------------------------------------------------------------------------
-struct WenoParams {
-    double eps, gm, p;
-    int force_linear;
-};
-
-template <typename T>
-__device__ __forceinline__ T wpow(T x, T p)
-{
-    if (p == T(1)) return x;
-    if (p == T(2)) return x * x;
-    return (T)pow((double)x, (double)p);
-}
-
 // Four lanes cooperate on one (cell, conserved component): lane l streams
 // members l, l+4, ... of the cell's stencil, so a cell's 20 lanes read
 // consecutive operator entries and each lane's chain of dependent loads is short;
@@ -258,79 +248,22 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
     }
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = quad_sum(a[j]);
-    // linear sub-stencil fits: b^m = G_m^{-1} r_m / h (normal equations of the scaled offsets)
-    const T *gi = (const T *)m.ginv;
-    T b[8][3];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-        const T r0 = quad_sum(r[s][0]), r1 = quad_sum(r[s][1]), r2 = quad_sum(r[s][2]);
-        const T g00 = gi[(size_t)(6 * s + 0) * n + i], g01 = gi[(size_t)(6 * s + 1) * n + i],
-                g02 = gi[(size_t)(6 * s + 2) * n + i], g11 = gi[(size_t)(6 * s + 3) * n + i],
-                g12 = gi[(size_t)(6 * s + 4) * n + i], g22 = gi[(size_t)(6 * s + 5) * n + i];
-        b[s][0] = g00 * r0 + g01 * r1 + g02 * r2;
-        b[s][1] = g01 * r0 + g11 * r1 + g12 * r2;
-        b[s][2] = g02 * r0 + g12 * r1 + g22 * r2;
+        r[s][0] = quad_sum(r[s][0]);
+        r[s][1] = quad_sum(r[s][1]);
+        r[s][2] = quad_sum(r[s][2]);
     }
-    const int M = m.M[i];
-    const T v23 = (T)m.vol23[i];
-    const T S00 = (T)m.m2[i], S01 = (T)m.m2[n + i], S02 = (T)m.m2[2 * n + i], S11 = (T)m.m2[3 * n + i],
-            S12 = (T)m.m2[4 * n + i], S22 = (T)m.m2[5 * n + i];
-    const T gm = (T)wp.gm, g0 = T(1) - gm * T(M), eps = (T)wp.eps, pw = (T)wp.p;
-    // smoothness indicators (Eq. indicator) over the cell: a = x y z xx xy xz yy yz zz
-    const T H[3][3] = {{T(2) * a[3], a[4], a[5]}, {a[4], T(2) * a[6], a[7]}, {a[5], a[7], T(2) * a[8]}};
-    T beta0 = T(0);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const T h0 = H[d][0], h1 = H[d][1], h2 = H[d][2];
-        const T quad = h0 * (S00 * h0 + S01 * h1 + S02 * h2) + h1 * (S01 * h0 + S11 * h1 + S12 * h2) +
-                       h2 * (S02 * h0 + S12 * h1 + S22 * h2);
-        beta0 += a[d] * a[d] + quad;
-    }
-    const T sec = T(4) * (a[3] * a[3] + a[6] * a[6] + a[8] * a[8]) + a[4] * a[4] + a[5] * a[5] + a[7] * a[7];
-    beta0 = v23 * beta0 + v23 * v23 * sec;
-    T beta[8];
-    T tw = T(0);
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        beta[s] = v23 * (b[s][0] * b[s][0] + b[s][1] * b[s][1] + b[s][2] * b[s][2]);
-        if (s < M) tw += fabs(beta0 - beta[s]);
-    }
-    tw /= T(M);
-    // nonlinear weights and Eq. weno folded into one quadratic
-    T w0, ws[8];
-    if (wp.force_linear) {
-        w0 = g0;
-#pragma unroll
-        for (int s = 0; s < 8; ++s) ws[s] = gm;
-    } else {
-        w0 = g0 * (T(1) + wpow(tw / (beta0 + eps), pw));
-#pragma unroll
-        for (int s = 0; s < 8; ++s) ws[s] = gm * (T(1) + wpow(tw / (beta[s] + eps), pw));
-    }
-    T sum = w0;
+    const T *gip = (const T *)m.ginv;
+    T gi[8][6];
 #pragma unroll
     for (int s = 0; s < 8; ++s)
-        if (s < M) sum += ws[s];
-    const T isum = T(1) / sum;
-    const T f0 = w0 * isum / g0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) gi[s][q] = gip[(size_t)(6 * s + q) * n + i];
+    const T S[6] = {(T)m.m2[i], (T)m.m2[n + i], (T)m.m2[2 * n + i], (T)m.m2[3 * n + i], (T)m.m2[4 * n + i],
+                    (T)m.m2[5 * n + i]};
     T c[10];
-#pragma unroll
-    for (int j = 0; j < 9; ++j) c[1 + j] = f0 * a[j];
-    const T sub0 = f0 * gm;
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-        if (s < M) {
-            const T fs = ws[s] * isum - sub0;
-            c[1] += fs * b[s][0];
-            c[2] += fs * b[s][1];
-            c[3] += fs * b[s][2];
-        }
-    // constant term: cell average minus the means of the quadratic monomials
-    const T corr = -(c[4] * S00 + c[5] * S01 + c[6] * S02 + c[7] * S11 + c[8] * S12 + c[9] * S22);
-    if constexpr (sizeof(T) == 8)
-        c[0] = (T)q0 + corr;
-    else
-        c[0] = corr;
+    weno_combine<T>(a, r, gi, m.M[i], (T)m.vol23[i], S, q0, sizeof(T) == 8, wp, c);
     // lane l writes entries l, l + 4 and (lanes 0, 1) l + 8 of this component
     T v0 = c[0], v1 = c[4], v2 = c[8];
 #pragma unroll
@@ -470,6 +403,266 @@ __global__ void __launch_bounds__(kBlock) k_stage2(DevMesh m, const T *__restric
     gather(m, ff, i, L, D);
 #pragma unroll
     for (int c = 0; c < 5; ++c) Q[(size_t)c * m.n + i] += dt * dt / 3.0 * D[c];
+}
+
+
+// ===========================================================================
+// Discrete adjoint of one S2O4 step (FP64)
+// ===========================================================================
+//
+// The step is Q* = Q + dt/2 L(Q) + dt^2/8 D(Q),
+//             Q' = Q + dt L(Q) + dt^2/6 (D(Q) + 2 D(Q*)), dt frozen.
+// Given lam' = dJ/dQ', the step's reverse is
+//   lam* = dt^2/3 J_D(Q*)^T lam',
+//   lam  = lam' + lam* + J_L(Q)^T (dt lam' + dt/2 lam*) + J_D(Q)^T (dt^2/6 lam' + dt^2/8 lam*).
+// Each J^T product is one vector-Jacobian product of the operator Q -> (L, D):
+// face-flux cotangents from the cell cotangents (reverse of Eq. finite), the
+// reverse of every Gauss-point flux (recomputed in registers), a per-cell
+// gather of the coefficient cotangents, the reverse of the reconstruction
+// per (cell, component), and a gather over the transposed stencil.  All
+// gathers run in a fixed order: no atomics, bitwise reproducible.
+
+struct AdjWork {
+    double *cbf;    // [F][2][50] coefficient cotangents per face side
+    double *cbc;    // [N][50]    per cell
+    double *dbar;   // [5][nnz]   cotangents of the stencil differences Q_k - Q_0
+    double *own;    // [5][N]     direct cotangent of each cell's own average
+    double *lstar;  // [5][N]     lam*
+    double *vjp;    // [5][N]     result of the latest vector-Jacobian product
+    double *coeff;  // [N][50]    recomputed reconstruction
+};
+
+static size_t adj_layout(int64_t n, int64_t nf, int64_t nnz, AdjWork *w, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return base ? (double *)(base + o) : nullptr;
+    };
+    double *cbf = take(8 * 100 * nf), *cbc = take(8 * 50 * n), *dbar = take(8 * 5 * nnz), *own = take(8 * 5 * n),
+           *ls = take(8 * 5 * n), *vj = take(8 * 5 * n), *co = take(8 * 50 * n);
+    if (w) *w = AdjWork{cbf, cbc, dbar, own, ls, vj, co};
+    return off;
+}
+
+// reverse of the flux: lane per (face, Gauss point)
+template <bool PR>
+__global__ void __launch_bounds__(kBlock) k_flux_adj(DevMesh m, const double *__restrict__ coeff,
+                                                     const double *__restrict__ dt_dev, const double *__restrict__ lp,
+                                                     const double *__restrict__ ls, double cL1, double cL2, double cD1,
+                                                     double cD2, FluxParams<double> fp, double *__restrict__ cbf)
+{
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int f = t >> 2;
+    const bool live = f < m.nf;
+    const int fs = live ? f : m.nf - 1;
+    const int nf4 = 4 * m.nf;
+    const int tt = 4 * fs + (t & 3);
+    const int o = m.owner[fs], nb = m.nbr[fs];
+    const int n = m.n;
+    const double dt = dt_dev[0];
+    // face cotangents from L = -(1/V) sum s F0, D = -(1/V) sum s F1 (owner s = +1, neighbour s = -1)
+    const double io = 1.0 / m.vol[o], inb = 1.0 / m.vol[nb];
+    double outb[10];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        double Lo = cL1 * lp[(size_t)c * n + o], Ln = cL1 * lp[(size_t)c * n + nb];
+        double Do = cD1 * lp[(size_t)c * n + o], Dn = cD1 * lp[(size_t)c * n + nb];
+        if (ls) {
+            Lo += cL2 * ls[(size_t)c * n + o];
+            Ln += cL2 * ls[(size_t)c * n + nb];
+            Do += cD2 * ls[(size_t)c * n + o];
+            Dn += cD2 * ls[(size_t)c * n + nb];
+        }
+        outb[c] = dt * (-Lo * io + Ln * inb);
+        outb[5 + c] = dt * dt * (-Do * io + Dn * inb);
+    }
+    double geo[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) geo[q] = m.fgeo[(size_t)q * nf4 + tt];
+    double cl[50], cr[50], clb[50], crb[50];
+    load_cell(coeff + (size_t)50 * o, cl);
+    load_cell(coeff + (size_t)50 * nb, cr);
+#pragma unroll
+    for (int j = 0; j < 50; ++j) clb[j] = crb[j] = 0.0;
+    face_gp_b<double, PR>(cl, cr, geo, dt, fp, outb, clb, crb);
+    // sum over the face's four Gauss points (a quad of lanes)
+#pragma unroll
+    for (int j = 0; j < 50; ++j) {
+        clb[j] = quad_sum(clb[j]);
+        crb[j] = quad_sum(crb[j]);
+    }
+    if (live) {
+        const int g4 = t & 3;
+        double *dst = cbf + (size_t)100 * f;
+#pragma unroll
+        for (int j = 0; j < 50; ++j)
+            if ((j & 3) == g4) {
+                dst[j] = clb[j];
+                dst[50 + j] = crb[j];
+            }
+    }
+}
+
+// per cell: sum of its face sides' coefficient cotangents, F_p order
+__global__ void __launch_bounds__(kBlock) k_cbar_gather(DevMesh m, const double *__restrict__ cbf, double *__restrict__ cbc)
+{
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int i = t / 50, j = t - 50 * (t / 50);
+    if (i >= m.n) return;
+    double s = 0.0;
+    for (int p = m.cf_ptr[i]; p < m.cf_ptr[i + 1]; ++p) {
+        const int code = m.cf_idx[p];
+        s += cbf[(size_t)100 * (code >> 1) + 50 * (code & 1) + j];
+    }
+    cbc[(size_t)50 * i + j] = s;
+}
+
+// reverse of the reconstruction: quad of lanes per (cell, component)
+__global__ void __launch_bounds__(kK1Block) k_reconstruct_adj(DevMesh m, const double *__restrict__ Q,
+                                                              const double *__restrict__ cbc, WenoParams wp,
+                                                              double *__restrict__ dbar, double *__restrict__ own)
+{
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kK1Block + threadIdx.x;
+    const int n = m.n;
+    const int ic = t / kK1CellLanes;
+    const int lane = t - kK1CellLanes * ic;
+    const int comp = lane >> 2;
+    const int l = lane & 3;
+    const bool valid = ic < n;
+    const int i = valid ? ic : n - 1;
+    const double *pinv = (const double *)m.pinv;
+    const double *dsc = (const double *)m.dsc;
+    const int nnz = m.nnz;
+    const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
+    const double *Qc = Q + (size_t)comp * n;
+    const double q0 = Qc[i];
+    double a[9], r[8][3];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) a[j] = 0.0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) r[s][0] = r[s][1] = r[s][2] = 0.0;
+    for (int k = k0 + l; k < k1; k += kK1Lanes) {
+        const int2 rec = m.st_rec[k];
+        const double d = Qc[rec.x] - q0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) a[j] += pinv[(size_t)j * nnz + k] * d;
+        const double dx = dsc[k] * d, dy = dsc[(size_t)nnz + k] * d, dz = dsc[(size_t)2 * nnz + k] * d;
+        const unsigned mask = (unsigned)rec.y;
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            if (mask & (1u << s)) {
+                r[s][0] += dx;
+                r[s][1] += dy;
+                r[s][2] += dz;
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) a[j] = quad_sum(a[j]);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        r[s][0] = quad_sum(r[s][0]);
+        r[s][1] = quad_sum(r[s][1]);
+        r[s][2] = quad_sum(r[s][2]);
+    }
+    const double *gip = (const double *)m.ginv;
+    double gi[8][6];
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) gi[s][q] = gip[(size_t)(6 * s + q) * n + i];
+    const double S[6] = {m.m2[i], m.m2[n + i], m.m2[2 * n + i], m.m2[3 * n + i], m.m2[4 * n + i], m.m2[5 * n + i]};
+    double cb[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) cb[j] = cbc[(size_t)50 * i + 10 * comp + j];
+    double ab[9], rb[8][3], q0b = 0.0;
+    weno_combine_b<double>(a, r, gi, m.M[i], m.vol23[i], S, wp, cb, ab, rb, q0b);
+    // members: dbar_k = sum_j A+[j][k] ab_j + D_k . sum_{m in mask} rb_m
+    double sumk = 0.0;
+    for (int k = k0 + l; k < k1; k += kK1Lanes) {
+        const int2 rec = m.st_rec[k];
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) v += pinv[(size_t)j * nnz + k] * ab[j];
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        const unsigned mask = (unsigned)rec.y;
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            if (mask & (1u << s)) {
+                sx += rb[s][0];
+                sy += rb[s][1];
+                sz += rb[s][2];
+            }
+        v += dsc[k] * sx + dsc[(size_t)nnz + k] * sy + dsc[(size_t)2 * nnz + k] * sz;
+        if (valid) dbar[(size_t)comp * nnz + k] = v;
+        sumk += v;
+    }
+    sumk = quad_sum(sumk);
+    if (valid && l == 0) own[(size_t)comp * n + i] = q0b - sumk;
+}
+
+// per cell: own cotangent plus every stencil entry that names the cell; out = scale * that (+ add)
+__global__ void __launch_bounds__(kBlock) k_transpose_gather(DevMesh m, const double *__restrict__ dbar,
+                                                             const double *__restrict__ own, double *__restrict__ out)
+{
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int i = t / 5, c = t - 5 * (t / 5);
+    if (i >= m.n) return;
+    double s = own[(size_t)c * m.n + i];
+    const double *dc = dbar + (size_t)c * m.nnz;
+    for (int p = m.tr_ptr[i]; p < m.tr_ptr[i + 1]; ++p) s += dc[m.tr_idx[p]];
+    out[(size_t)c * m.n + i] = s;
+}
+
+// lam = lam' + lam* + vjp
+__global__ void __launch_bounds__(kBlock) k_adj_combine(int len, const double *__restrict__ lp,
+                                                        const double *__restrict__ ls, const double *__restrict__ v,
+                                                        double *__restrict__ out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) out[i] = lp[i] + ls[i] + v[i];
+}
+
+// kinetic energy J = sum_i |Omega_i| |m_i|^2 / (2 rho_i): per-block partial sums, then one block
+__global__ void __launch_bounds__(kBlock) k_ke_partial(int n, const double *__restrict__ Q, const double *__restrict__ vol,
+                                                       double *__restrict__ part, double *__restrict__ grad)
+{
+    __shared__ double red[kBlock];
+    double acc = 0.0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double r = Q[i], mx = Q[n + i], my = Q[2 * n + i], mz = Q[3 * n + i];
+        const double ir = 1.0 / r, m2 = mx * mx + my * my + mz * mz;
+        acc += 0.5 * vol[i] * m2 * ir;
+        if (grad) {
+            grad[i] = -0.5 * vol[i] * m2 * ir * ir;
+            grad[n + i] = vol[i] * mx * ir;
+            grad[2 * n + i] = vol[i] * my * ir;
+            grad[3 * n + i] = vol[i] * mz * ir;
+            grad[4 * n + i] = 0.0;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kBlock) k_sum_final(int nb, const double *__restrict__ part, double *out)
+{
+    __shared__ double red[kBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kBlock) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
 }
 
 // batch of single Gauss-point fluxes (kernel-level tests)
@@ -716,6 +909,8 @@ static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *ba
     dm.fgeo = (const double *)put(H.fgeo.data(), 8 * H.fgeo.size());
     dm.cf_ptr = (const int32_t *)put(H.cf_ptr.data(), 4 * (n + 1));
     dm.cf_idx = (const int32_t *)put(H.cf_idx.data(), 4 * H.cf_idx.size());
+    dm.tr_ptr = (const int32_t *)put(H.tr_ptr.data(), 4 * (n + 1));
+    dm.tr_idx = (const int32_t *)put(H.tr_idx.data(), 4 * H.tr_idx.size());
     if (d) *d = dm;
     return off;
 }
@@ -951,6 +1146,77 @@ gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_param
     return GKS_OK;
 }
 
+gks_status gks_adjoint_work_bytes(const gks_host_mesh *h, size_t *bytes)
+{
+    if (!h || !bytes) return fail(GKS_EINVAL, "null argument");
+    *bytes = adj_layout(h->h.n, h->h.nf, (int64_t)h->h.st_idx.size(), nullptr, nullptr);
+    return GKS_OK;
+}
+
+static gks_status launch_vjp(gks_mesh *m, const double *Qe, const double *dt_dev, const double *lp, const double *ls,
+                             double cL1, double cL2, double cD1, double cD2, const gks_params *p, AdjWork &aw,
+                             hipStream_t st, double *out)
+{
+    gks_status s;
+    if ((s = launch_reconstruct(m, Qe, aw.coeff, p, st))) return s;
+    const bool pr = p->viscous && p->Pr != 1.0;
+    const FluxParams<double> fp = flux_params<double>(p);
+    {
+        ProfScope ps(m, GKS_K_FLUX_ADJ, st);
+        const unsigned g = grid_for(4 * m->nf, kBlock);
+        if (pr)
+            k_flux_adj<true><<<g, kBlock, 0, st>>>(m->d, aw.coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.cbf);
+        else
+            k_flux_adj<false><<<g, kBlock, 0, st>>>(m->d, aw.coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.cbf);
+    }
+    {
+        ProfScope ps(m, GKS_K_GATHER_ADJ, st);
+        k_cbar_gather<<<grid_for(50 * m->n, kBlock), kBlock, 0, st>>>(m->d, aw.cbf, aw.cbc);
+    }
+    {
+        ProfScope ps(m, GKS_K_RECONSTRUCT_ADJ, st);
+        k_reconstruct_adj<<<grid_for((int64_t)kK1CellLanes * m->n, kK1Block), kK1Block, 0, st>>>(
+            m->d, Qe, aw.cbc, weno_params(p), aw.dbar, aw.own);
+    }
+    {
+        ProfScope ps(m, GKS_K_GATHER_ADJ, st);
+        k_transpose_gather<<<grid_for(5 * m->n, kBlock), kBlock, 0, st>>>(m->d, aw.dbar, aw.own, out);
+    }
+    return hip_check(hipGetLastError(), "adjoint launch");
+}
+
+gks_status gks_adjoint_step(gks_mesh *m, const double *Qn, const double *Qstar, const double *dt_dev,
+                            const double *lam_np1, double *lam_n, const gks_params *p, void *adj_work,
+                            gks_stream_t stream)
+{
+    gks_status s = check_params(m, p);
+    if (s) return s;
+    if (m->precision != GKS_FP64) return fail(GKS_EINVAL, "the adjoint runs on an FP64 mesh");
+    if (!Qn || !Qstar || !dt_dev || !lam_np1 || !lam_n || !adj_work) return fail(GKS_EINVAL, "null argument");
+    if (((uintptr_t)adj_work & 255) != 0) return fail(GKS_EINVAL, "adjoint work buffer must be 256-byte aligned");
+    AdjWork aw;
+    adj_layout(m->n, m->nf, m->d.nnz, &aw, (char *)adj_work);
+    hipStream_t st = S(stream);
+    // lam* = dt^2/3 J_D(Q*)^T lam'
+    if ((s = launch_vjp(m, Qstar, dt_dev, lam_np1, nullptr, 0.0, 0.0, 1.0 / 3.0, 0.0, p, aw, st, aw.lstar))) return s;
+    // J_L(Q)^T (dt lam' + dt/2 lam*) + J_D(Q)^T (dt^2/6 lam' + dt^2/8 lam*)
+    if ((s = launch_vjp(m, Qn, dt_dev, lam_np1, aw.lstar, 1.0, 0.5, 1.0 / 6.0, 0.125, p, aw, st, aw.vjp))) return s;
+    const int len = (int)(5 * m->n);
+    k_adj_combine<<<grid_for(len, kBlock), kBlock, 0, st>>>(len, lam_np1, aw.lstar, aw.vjp, lam_n);
+    return hip_check(hipGetLastError(), "adjoint combine launch");
+}
+
+gks_status gks_kinetic_energy(gks_mesh *m, const double *Q, double *J_dev, double *dJdQ, void *work, gks_stream_t stream)
+{
+    if (!m || !Q || !J_dev || !work) return fail(GKS_EINVAL, "null argument");
+    Work w = work_of(m, work);
+    hipStream_t st = S(stream);
+    const int nb = (int)std::min<int64_t>(kDtBlocks, grid_for(m->n, kBlock));
+    k_ke_partial<<<nb, kBlock, 0, st>>>((int)m->n, Q, m->d.vol, w.dtpart, dJdQ);
+    k_sum_final<<<1, kBlock, 0, st>>>(nb, w.dtpart, J_dev);
+    return hip_check(hipGetLastError(), "kinetic energy launch");
+}
+
 gks_status gks_poll_status(gks_mesh *m, void *work, gks_stream_t stream)
 {
     if (!m || !work) return fail(GKS_EINVAL, "null argument");
@@ -983,6 +1249,83 @@ gks_status gks_gp_flux_batch(int64_t n, const double *ql, const double *dql, con
             k_gp_batch<double, false><<<grid, kBlock, 0, st>>>(n, ql, dql, qr, dqr, dt, out, flux_params<double>(p));
     }
     return hip_check(hipGetLastError(), "gp flux launch");
+}
+
+gks_status gks_gp_flux_host(const double *ql, const double *dql, const double *qr, const double *dqr, double dt,
+                            const gks_params *p, double *out)
+{
+    if (!ql || !dql || !qr || !dqr || !p || !out) return fail(GKS_EINVAL, "null argument");
+    const FluxParams<double> fp = flux_params<double>(p);
+    double dl[3][5], dr[3][5];
+    for (int m = 0; m < 3; ++m)
+        for (int j = 0; j < 5; ++j) {
+            dl[m][j] = dql[5 * m + j];
+            dr[m][j] = dqr[5 * m + j];
+        }
+    const bool ok = (p->viscous && p->Pr != 1.0) ? gp_flux<double, true>(ql, dl, qr, dr, dt, fp, out)
+                                                 : gp_flux<double, false>(ql, dl, qr, dr, dt, fp, out);
+    return ok ? GKS_OK : fail(GKS_ENONPHYS, "non-physical state");
+}
+
+gks_status gks_gp_flux_vjp_host(const double *ql, const double *dql, const double *qr, const double *dqr, double dt,
+                                const gks_params *p, const double *outb, double *qlb, double *dqlb, double *qrb,
+                                double *dqrb)
+{
+    if (!ql || !dql || !qr || !dqr || !p || !outb || !qlb || !dqlb || !qrb || !dqrb)
+        return fail(GKS_EINVAL, "null argument");
+    const FluxParams<double> fp = flux_params<double>(p);
+    double dl[3][5], dr[3][5], dlb[3][5] = {}, drb[3][5] = {};
+    double a[5] = {}, b[5] = {};
+    for (int m = 0; m < 3; ++m)
+        for (int j = 0; j < 5; ++j) {
+            dl[m][j] = dql[5 * m + j];
+            dr[m][j] = dqr[5 * m + j];
+        }
+    if (p->viscous && p->Pr != 1.0)
+        gp_flux_b<double, true>(ql, dl, qr, dr, dt, fp, outb, a, dlb, b, drb);
+    else
+        gp_flux_b<double, false>(ql, dl, qr, dr, dt, fp, outb, a, dlb, b, drb);
+    for (int j = 0; j < 5; ++j) {
+        qlb[j] = a[j];
+        qrb[j] = b[j];
+    }
+    for (int m = 0; m < 3; ++m)
+        for (int j = 0; j < 5; ++j) {
+            dqlb[5 * m + j] = dlb[m][j];
+            dqrb[5 * m + j] = drb[m][j];
+        }
+    return GKS_OK;
+}
+
+gks_status gks_weno_combine_host(const double *a, const double *r, const double *gi, int M, double v23,
+                                 const double *S, double q0, const gks_params *p, double *c)
+{
+    if (!a || !r || !gi || !S || !p || !c || M < 1 || M > 8) return fail(GKS_EINVAL, "bad argument");
+    double rr[8][3], gg[8][6];
+    for (int s = 0; s < 8; ++s) {
+        for (int q = 0; q < 3; ++q) rr[s][q] = r[3 * s + q];
+        for (int q = 0; q < 6; ++q) gg[s][q] = gi[6 * s + q];
+    }
+    weno_combine<double>(a, rr, gg, M, v23, S, q0, true, weno_params(p), c);
+    return GKS_OK;
+}
+
+gks_status gks_weno_combine_vjp_host(const double *a, const double *r, const double *gi, int M, double v23,
+                                     const double *S, const gks_params *p, const double *cb, double *ab, double *rb,
+                                     double *q0b)
+{
+    if (!a || !r || !gi || !S || !p || !cb || !ab || !rb || !q0b || M < 1 || M > 8) return fail(GKS_EINVAL, "bad argument");
+    double rr[8][3], gg[8][6], rrb[8][3];
+    for (int s = 0; s < 8; ++s) {
+        for (int q = 0; q < 3; ++q) rr[s][q] = r[3 * s + q];
+        for (int q = 0; q < 6; ++q) gg[s][q] = gi[6 * s + q];
+    }
+    double qb = 0.0;
+    weno_combine_b<double>(a, rr, gg, M, v23, S, weno_params(p), cb, ab, rrb, qb);
+    for (int s = 0; s < 8; ++s)
+        for (int q = 0; q < 3; ++q) rb[3 * s + q] = rrb[s][q];
+    *q0b = qb;
+    return GKS_OK;
 }
 
 gks_status gks_gp_op_count(int viscous, double Pr, int64_t *adds, int64_t *muls, int64_t *divs, int64_t *transc)

@@ -1,0 +1,731 @@
+// Reverse mode (vector-Jacobian products) of the Gauss-point gas-kinetic flux.
+//
+// Each function below is the hand-written adjoint of the forward function of
+// the same name in gks_flux.h: given the cotangent of the forward outputs it
+// accumulates the cotangents of the forward inputs ("x_b" is the cotangent of
+// x).  Forward intermediates are recomputed, never stored.  The time step is a
+// constant of the step (frozen), and |x| has derivative sign(x) with sign(0) = 0.
+#pragma once
+
+#include "gks_flux.h"
+
+namespace gks {
+
+template <typename T>
+__host__ __device__ __forceinline__ T sgn_t(T x)
+{
+    return x > T(0) ? T(1) : (x < T(0) ? T(-1) : T(0));
+}
+
+// cotangents of one set of normalised Maxwellian moments
+template <typename T>
+struct MomB {
+    T u[7], v[6], w[6], s1, s2;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ void momb_zero(MomB<T> &B)
+{
+#pragma unroll
+    for (int k = 0; k < 7; ++k) B.u[k] = T(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) B.v[k] = B.w[k] = T(0);
+    B.s1 = B.s2 = T(0);
+}
+
+// reverse of m[k+2] = U m[k+1] + (k+1) h m[k] for k = NK-3 .. 0
+template <int NK, typename T>
+__host__ __device__ __forceinline__ void recur_b(const T *m, T *mb, T U, T h, T &Ub, T &hb)
+{
+#pragma unroll
+    for (int k = NK - 3; k >= 0; --k) {
+        const T g = mb[k + 2];
+        mb[k + 1] += U * g;
+        Ub += m[k + 1] * g;
+        mb[k] += T(k + 1) * h * g;
+        hb += T(k + 1) * m[k] * g;
+    }
+}
+
+// reverse of mom_common: v, w, s moments -> V, W, lambda
+template <typename T>
+__host__ __device__ __forceinline__ void mom_common_b(const Mom<T> &M, MomB<T> &B, T V, T W, T lam, T K, T &Vb, T &Wb,
+                                                      T &lamb)
+{
+    const T h = T(0.5) / lam;
+    T hb = K * B.s1 + T(2) * K * (K + T(2)) * h * B.s2;
+    recur_b<6>(M.v, B.v, V, h, Vb, hb);
+    Vb += B.v[1];
+    recur_b<6>(M.w, B.w, W, h, Wb, hb);
+    Wb += B.w[1];
+    lamb += -hb * h / lam;
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void mom_full_u_b(const Mom<T> &M, MomB<T> &B, T U, T lam, T &Ub, T &lamb)
+{
+    const T h = T(0.5) / lam;
+    T hb = T(0);
+    recur_b<7>(M.u, B.u, U, h, Ub, hb);
+    Ub += B.u[1];
+    lamb += -hb * h / lam;
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ void mom_half_u_b(const Mom<T> &M, MomB<T> &B, T U, T lam, T sign, T &Ub, T &lamb)
+{
+    const T h = T(0.5) / lam;
+    T hb = T(0);
+    recur_b<7>(M.u, B.u, U, h, Ub, hb);
+    lamb += -hb * h / lam;
+    const T sl = sqrt_t(lam);
+    const T g = exp_t(-lam * U * U);
+    const T e = g / (T(2) * sqrt_t(T(M_PI) * lam));
+    // u1 = U u0 + sign e
+    Ub += M.u[0] * B.u[1];
+    const T u0b = B.u[0] + U * B.u[1];
+    const T eb = sign * B.u[1];
+    Ub += eb * e * (T(-2) * lam * U);
+    lamb += eb * e * (-U * U - T(0.5) / lam);
+    // u0 = erfc(-sign sqrt(lam) U) / 2
+    const T ip = T(1) / sqrt_t(T(M_PI));
+    Ub += u0b * sign * sl * g * ip;
+    lamb += u0b * sign * U * g * ip / (T(2) * sl);
+}
+
+// reverse of P<k,l,n>: o_b -> moment cotangents
+template <int k, int l, int n, typename T>
+__host__ __device__ __forceinline__ void P_b(const Mom<T> &M, const T ob[5], MomB<T> &B)
+{
+    const T uk = M.u[k], vl = M.v[l], wn = M.w[n];
+    // o0 = uk vl wn
+    B.u[k] += ob[0] * vl * wn;
+    B.v[l] += ob[0] * uk * wn;
+    B.w[n] += ob[0] * uk * vl;
+    // o1 = u[k+1] vl wn
+    B.u[k + 1] += ob[1] * vl * wn;
+    B.v[l] += ob[1] * M.u[k + 1] * wn;
+    B.w[n] += ob[1] * M.u[k + 1] * vl;
+    // o2 = uk v[l+1] wn
+    B.u[k] += ob[2] * M.v[l + 1] * wn;
+    B.v[l + 1] += ob[2] * uk * wn;
+    B.w[n] += ob[2] * uk * M.v[l + 1];
+    // o3 = uk vl w[n+1]
+    B.u[k] += ob[3] * vl * M.w[n + 1];
+    B.v[l] += ob[3] * uk * M.w[n + 1];
+    B.w[n + 1] += ob[3] * uk * vl;
+    // o4 = (u[k+2] vl wn + uk v[l+2] wn + uk vl w[n+2] + uk vl wn s1) / 2
+    const T h4 = T(0.5) * ob[4];
+    B.u[k + 2] += h4 * vl * wn;
+    B.v[l] += h4 * M.u[k + 2] * wn;
+    B.w[n] += h4 * M.u[k + 2] * vl;
+    B.u[k] += h4 * M.v[l + 2] * wn;
+    B.v[l + 2] += h4 * uk * wn;
+    B.w[n] += h4 * uk * M.v[l + 2];
+    B.u[k] += h4 * vl * M.w[n + 2];
+    B.v[l] += h4 * uk * M.w[n + 2];
+    B.w[n + 2] += h4 * uk * vl;
+    B.u[k] += h4 * vl * wn * M.s1;
+    B.v[l] += h4 * uk * wn * M.s1;
+    B.w[n] += h4 * uk * vl * M.s1;
+    B.s1 += h4 * uk * vl * wn;
+}
+
+// reverse of Ps<k,l,n>
+template <int k, int l, int n, typename T>
+__host__ __device__ __forceinline__ void Ps_b(const Mom<T> &M, const T ob[5], MomB<T> &B)
+{
+    // o_j (j < 4) = P_j * s1; o4 = (sum of three) s1 / 2 + base s2 / 2
+    T pb[5];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) pb[j] = ob[j] * M.s1;
+    T t[5];
+    P<k, l, n>(M, t);
+    // P<>'s o4 includes base*s1/2, which Ps does not have in that form: handle the three
+    // squared-velocity terms through P_b with o0..o3 zeroed, then the base terms directly
+    const T uk = M.u[k], vl = M.v[l], wn = M.w[n];
+    const T base = uk * vl * wn;
+    const T three = T(2) * t[4] - base * M.s1;  // u[k+2] vl wn + uk v[l+2] wn + uk vl w[n+2]
+    B.s1 += ob[0] * t[0] + ob[1] * t[1] + ob[2] * t[2] + ob[3] * t[3] + T(0.5) * ob[4] * three;
+    B.s2 += T(0.5) * ob[4] * base;
+    // base s2 / 2
+    const T bb = T(0.5) * ob[4] * M.s2;
+    B.u[k] += bb * vl * wn;
+    B.v[l] += bb * uk * wn;
+    B.w[n] += bb * uk * vl;
+    // three * s1 / 2: same as P's o4 without its s1 term, scaled by s1
+    const T h4 = T(0.5) * ob[4] * M.s1;
+    B.u[k + 2] += h4 * vl * wn;
+    B.v[l] += h4 * M.u[k + 2] * wn;
+    B.w[n] += h4 * M.u[k + 2] * vl;
+    B.u[k] += h4 * M.v[l + 2] * wn;
+    B.v[l + 2] += h4 * uk * wn;
+    B.w[n] += h4 * uk * M.v[l + 2];
+    B.u[k] += h4 * vl * M.w[n + 2];
+    B.v[l] += h4 * uk * M.w[n + 2];
+    B.w[n + 2] += h4 * uk * vl;
+    // o0..o3 = P0..P3 * s1
+    T ob4[5] = {pb[0], pb[1], pb[2], pb[3], T(0)};
+    P_b<k, l, n>(M, ob4, B);
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ T dot5(const T *a, const T *b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4];
+}
+
+// reverse of Pa<k,l,n>(M, a): o_b -> moment cotangents and a_b
+template <int k, int l, int n, typename T>
+__host__ __device__ __forceinline__ void Pa_b(const Mom<T> &M, const T a[5], const T ob[5], MomB<T> &B, T ab[5])
+{
+    T t[5], s[5];
+    P<k, l, n>(M, t);
+    ab[0] += dot5(ob, t);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s[j] = a[0] * ob[j];
+    P_b<k, l, n>(M, s, B);
+    P<k + 1, l, n>(M, t);
+    ab[1] += dot5(ob, t);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s[j] = a[1] * ob[j];
+    P_b<k + 1, l, n>(M, s, B);
+    P<k, l + 1, n>(M, t);
+    ab[2] += dot5(ob, t);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s[j] = a[2] * ob[j];
+    P_b<k, l + 1, n>(M, s, B);
+    P<k, l, n + 1>(M, t);
+    ab[3] += dot5(ob, t);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s[j] = a[3] * ob[j];
+    P_b<k, l, n + 1>(M, s, B);
+    T q[5];
+    P<k + 2, l, n>(M, q);
+    P<k, l + 2, n>(M, t);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) q[j] += t[j];
+    P<k, l, n + 2>(M, t);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) q[j] += t[j];
+    Ps<k, l, n>(M, t);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) q[j] += t[j];
+    ab[4] += T(0.5) * dot5(ob, q);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s[j] = T(0.5) * a[4] * ob[j];
+    P_b<k + 2, l, n>(M, s, B);
+    P_b<k, l + 2, n>(M, s, B);
+    P_b<k, l, n + 2>(M, s, B);
+    Ps_b<k, l, n>(M, s, B);
+}
+
+template <int k, typename T>
+__host__ __device__ __forceinline__ void Padv_b(const Mom<T> &M, const T a[3][5], const T ob[5], MomB<T> &B, T ab[3][5])
+{
+    Pa_b<k + 1, 0, 0>(M, a[0], ob, B, ab[0]);
+    Pa_b<k, 1, 0>(M, a[1], ob, B, ab[1]);
+    Pa_b<k, 0, 1>(M, a[2], ob, B, ab[2]);
+}
+
+// reverse of slope_solve: a_b -> b_b and state cotangents (a: the forward result)
+template <typename T>
+__host__ __device__ __forceinline__ void slope_solve_b(const T b[5], T U, T V, T W, T lam, T K, const T a[5],
+                                                       const T ab_in[5], T bb[5], T &Ub, T &Vb, T &Wb, T &lamb)
+{
+    const T q = U * U + V * V + W * W + (K + T(3)) / (T(2) * lam);
+    const T R2 = b[1] - U * b[0], R3 = b[2] - V * b[0], R4 = b[3] - W * b[0];
+    const T R5 = T(2) * b[4] - q * b[0];
+    const T c = T(4) * lam * lam / (K + T(3));
+    const T X = R5 - T(2) * (U * R2 + V * R3 + W * R4);
+    T ab[5] = {ab_in[0], ab_in[1], ab_in[2], ab_in[3], ab_in[4]};
+    T qb = T(0), R2b = T(0), R3b = T(0), R4b = T(0), R5b = T(0), cb = T(0);
+    // a0 = b0 - U a1 - V a2 - W a3 - a4 q / 2
+    bb[0] += ab[0];
+    Ub += -a[1] * ab[0];
+    ab[1] += -U * ab[0];
+    Vb += -a[2] * ab[0];
+    ab[2] += -V * ab[0];
+    Wb += -a[3] * ab[0];
+    ab[3] += -W * ab[0];
+    ab[4] += T(-0.5) * q * ab[0];
+    qb += T(-0.5) * a[4] * ab[0];
+    // a3 = 2 lam R4 - W a4 (and a2, a1)
+    lamb += T(2) * R4 * ab[3];
+    R4b += T(2) * lam * ab[3];
+    Wb += -a[4] * ab[3];
+    ab[4] += -W * ab[3];
+    lamb += T(2) * R3 * ab[2];
+    R3b += T(2) * lam * ab[2];
+    Vb += -a[4] * ab[2];
+    ab[4] += -V * ab[2];
+    lamb += T(2) * R2 * ab[1];
+    R2b += T(2) * lam * ab[1];
+    Ub += -a[4] * ab[1];
+    ab[4] += -U * ab[1];
+    // a4 = c X
+    cb += X * ab[4];
+    const T Xb = c * ab[4];
+    R5b += Xb;
+    R2b += T(-2) * U * Xb;
+    Ub += T(-2) * R2 * Xb;
+    R3b += T(-2) * V * Xb;
+    Vb += T(-2) * R3 * Xb;
+    R4b += T(-2) * W * Xb;
+    Wb += T(-2) * R4 * Xb;
+    lamb += T(8) * lam / (K + T(3)) * cb;
+    // R5 = 2 b4 - q b0
+    bb[4] += T(2) * R5b;
+    qb += -b[0] * R5b;
+    bb[0] += -q * R5b;
+    // R4 = b3 - W b0 (and R3, R2)
+    bb[3] += R4b;
+    Wb += -b[0] * R4b;
+    bb[0] += -W * R4b;
+    bb[2] += R3b;
+    Vb += -b[0] * R3b;
+    bb[0] += -V * R3b;
+    bb[1] += R2b;
+    Ub += -b[0] * R2b;
+    bb[0] += -U * R2b;
+    // q
+    Ub += T(2) * U * qb;
+    Vb += T(2) * V * qb;
+    Wb += T(2) * W * qb;
+    lamb += -(K + T(3)) / (T(2) * lam * lam) * qb;
+}
+
+// reverse of to_prim
+template <typename T>
+__host__ __device__ __forceinline__ void to_prim_b(const T q[5], T gam, T rhob, T Ub, T Vb, T Wb, T lamb, T pb, T qb[5])
+{
+    T rho, U, V, W, lam, p;
+    to_prim(q, gam, rho, U, V, W, lam, p);
+    rhob += lamb / (T(2) * p);
+    pb += -lamb * lam / p;
+    qb[4] += (gam - T(1)) * pb;
+    rhob += -(gam - T(1)) * pb * T(0.5) * (U * U + V * V + W * W);
+    Ub += -(gam - T(1)) * pb * rho * U;
+    Vb += -(gam - T(1)) * pb * rho * V;
+    Wb += -(gam - T(1)) * pb * rho * W;
+    const T ir = T(1) / rho;
+    qb[1] += Ub * ir;
+    qb[2] += Vb * ir;
+    qb[3] += Wb * ir;
+    rhob += -(Ub * U + Vb * V + Wb * W) * ir;
+    qb[0] += rhob;
+}
+
+// cotangents of the half-space accumulators
+template <typename T, bool PR>
+struct FluxAccB {
+    T q0[5], bab[3][5], Mh[5], Mha[5], MhA[5];
+    T Wha[PR ? 5 : 1], WhA[PR ? 5 : 1];
+    T p[2];
+};
+
+template <typename T, bool PR>
+__host__ __device__ __forceinline__ void accb_zero(FluxAccB<T, PR> &A)
+{
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        A.q0[j] = A.Mh[j] = A.Mha[j] = A.MhA[j] = T(0);
+        A.bab[0][j] = A.bab[1][j] = A.bab[2][j] = T(0);
+        if constexpr (PR) A.Wha[j] = A.WhA[j] = T(0);
+    }
+    A.p[0] = A.p[1] = T(0);
+}
+
+// reverse of side_pass: accumulator cotangents -> q_b, dq_b
+template <typename T, bool PR>
+__host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, const FluxParams<T> &fp,
+                                     const FluxAccB<T, PR> &Ab, int side, T qb[5], T dqb[3][5])
+{
+    const T K = fp.K;
+    T rho, U, V, W, lam, p;
+    to_prim(q, fp.gamma, rho, U, V, W, lam, p);
+    Mom<T> Mf;
+    mom_common(Mf, V, W, lam, K);
+    mom_full_u(Mf, U, lam);
+    T a[3][5], Av[5], bA[5];
+    const T ir = T(1) / rho;
+    T bm[3][5];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) bm[m][j] = dq[m][j] * ir;
+        slope_solve(bm[m], U, V, W, lam, K, a[m]);
+    }
+    Padv<0>(Mf, a, bA);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
+    slope_solve(bA, U, V, W, lam, K, Av);
+    Mom<T> Mh = Mf;
+    mom_half_u(Mh, U, lam, sign);
+
+    T rhob = T(0), Ub = T(0), Vb = T(0), Wb = T(0), lamb = T(0), pb = Ab.p[side];
+    MomB<T> Bh, Bf;
+    momb_zero(Bh);
+    momb_zero(Bf);
+    T ab[3][5], Avb[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        Avb[j] = T(0);
+        ab[0][j] = ab[1][j] = ab[2][j] = T(0);
+    }
+    T t[5], s[5];
+    // q0 += rho P000
+    P<0, 0, 0>(Mh, t);
+    rhob += dot5(Ab.q0, t);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s[j] = rho * Ab.q0[j];
+    P_b<0, 0, 0>(Mh, s, Bh);
+    // bab[m] += rho Pa000(a[m])
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        Pa<0, 0, 0>(Mh, a[m], t);
+        rhob += dot5(Ab.bab[m], t);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) s[j] = rho * Ab.bab[m][j];
+        Pa_b<0, 0, 0>(Mh, a[m], s, Bh, ab[m]);
+    }
+    // Mh += rho P100
+    P<1, 0, 0>(Mh, t);
+    rhob += dot5(Ab.Mh, t);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s[j] = rho * Ab.Mh[j];
+    P_b<1, 0, 0>(Mh, s, Bh);
+    // Mha += rho Padv1(a)
+    Padv<1>(Mh, a, t);
+    rhob += dot5(Ab.Mha, t);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s[j] = rho * Ab.Mha[j];
+    Padv_b<1>(Mh, a, s, Bh, ab);
+    // MhA += rho Pa100(Av)
+    Pa<1, 0, 0>(Mh, Av, t);
+    rhob += dot5(Ab.MhA, t);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s[j] = rho * Ab.MhA[j];
+    Pa_b<1, 0, 0>(Mh, Av, s, Bh, Avb);
+    if constexpr (PR) {
+        Padv<0>(Mh, a, t);
+        rhob += dot5(Ab.Wha, t);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) s[j] = rho * Ab.Wha[j];
+        Padv_b<0>(Mh, a, s, Bh, ab);
+        Pa<0, 0, 0>(Mh, Av, t);
+        rhob += dot5(Ab.WhA, t);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) s[j] = rho * Ab.WhA[j];
+        Pa_b<0, 0, 0>(Mh, Av, s, Bh, Avb);
+    }
+    // half-space u moments; v, w, s moments are shared with the full set
+    mom_half_u_b(Mh, Bh, U, lam, sign, Ub, lamb);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        Bf.v[k] += Bh.v[k];
+        Bf.w[k] += Bh.w[k];
+    }
+    Bf.s1 += Bh.s1;
+    Bf.s2 += Bh.s2;
+    // Av = solve(-Padv0(Mf, a))
+    T bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
+    slope_solve_b(bA, U, V, W, lam, K, Av, Avb, bAb, Ub, Vb, Wb, lamb);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) bAb[j] = -bAb[j];
+    Padv_b<0>(Mf, a, bAb, Bf, ab);
+    // a[m] = solve(dq[m] / rho)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        T bmb[5] = {T(0), T(0), T(0), T(0), T(0)};
+        slope_solve_b(bm[m], U, V, W, lam, K, a[m], ab[m], bmb, Ub, Vb, Wb, lamb);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            dqb[m][j] += bmb[j] * ir;
+            rhob += -bmb[j] * bm[m][j] * ir;
+        }
+    }
+    mom_full_u_b(Mf, Bf, U, lam, Ub, lamb);
+    mom_common_b(Mf, Bf, V, W, lam, K, Vb, Wb, lamb);
+    to_prim_b(q, fp.gamma, rhob, Ub, Vb, Wb, lamb, pb, qb);
+}
+
+// T coefficients of the time integrals over [0, d] and their derivatives in tau
+template <typename T>
+__host__ __device__ __forceinline__ void tcoef(T d, T tau, T Tc[5], T dT[5])
+{
+    const T eta = exp_t(-d / tau);
+    const T om = -expm1_t(-d / tau);
+    const T deta = eta * d / (tau * tau);
+    const T dom = -deta;
+    Tc[0] = d - tau * om;
+    Tc[1] = T(2) * tau * tau * om - tau * d * (T(1) + eta);
+    Tc[2] = T(0.5) * d * d - tau * d + tau * tau * om;
+    Tc[3] = tau * om;
+    Tc[4] = T(2) * tau * tau * om - tau * d * eta;
+    dT[0] = -om - tau * dom;
+    dT[1] = T(4) * tau * om + T(2) * tau * tau * dom - d * (T(1) + eta) - tau * d * deta;
+    dT[2] = -d + T(2) * tau * om + tau * tau * dom;
+    dT[3] = om + tau * dom;
+    dT[4] = T(4) * tau * om + T(2) * tau * tau * dom - d * eta - tau * d * deta;
+}
+
+// reverse of finish_flux: out_b -> accumulator cotangents
+template <typename T, bool PR>
+__host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const FluxParams<T> &fp, const T outb[10],
+                                       FluxAccB<T, PR> &Ab)
+{
+    const T K = fp.K;
+    T r0, U0, V0, W0, lam0, p0;
+    to_prim(A.q0, fp.gamma, r0, U0, V0, W0, lam0, p0);
+    Mom<T> G;
+    mom_common(G, V0, W0, lam0, K);
+    mom_full_u(G, U0, lam0);
+    T ab[3][5], Av[5], bm[3][5], bA[5];
+    const T ir0 = T(1) / r0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) bm[m][j] = A.bab[m][j] * ir0;
+        slope_solve(bm[m], U0, V0, W0, lam0, K, ab[m]);
+    }
+    Padv<0>(G, ab, bA);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
+    slope_solve(bA, U0, V0, W0, lam0, K, Av);
+    const T dp = (A.p[0] - A.p[1]) / (A.p[0] + A.p[1]);
+    const T adp = dp < T(0) ? -dp : dp;
+    const T tau = fp.viscous ? fp.mu / p0 + fp.tau_C * adp * dt : fp.tau_eps * dt + fp.tau_C * adp * dt;
+    T M0[5], Ma[5], MA[5];
+    P<1, 0, 0>(G, M0);
+    Padv<1>(G, ab, Ma);
+    Pa<1, 0, 0>(G, Av, MA);
+    T W0m[PR ? 5 : 1], Wam[PR ? 5 : 1], WAm[PR ? 5 : 1];
+    if constexpr (PR) {
+        P<0, 0, 0>(G, W0m);
+        Padv<0>(G, ab, Wam);
+        Pa<0, 0, 0>(G, Av, WAm);
+    }
+    // out = combination of F(dt/2), F(dt)
+    const T idt = T(1) / dt;
+    T Fdb[2][5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        Fdb[0][j] = T(4) * idt * outb[j] - T(8) * idt * idt * outb[5 + j];
+        Fdb[1][j] = -idt * outb[j] + T(4) * idt * idt * outb[5 + j];
+    }
+    T r0b = T(0), taub = T(0), U0b = T(0), V0b = T(0), W0b = T(0), lam0b = T(0), p0b = T(0);
+    T M0b[5], Mab[5], MAb[5], W0mb[5], Wamb[5], WAmb[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) M0b[j] = Mab[j] = MAb[j] = W0mb[j] = Wamb[j] = WAmb[j] = T(0);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const T d = s == 0 ? T(0.5) * dt : dt;
+        T Tc[5], dT[5], Tb[5] = {T(0), T(0), T(0), T(0), T(0)};
+        tcoef(d, tau, Tc, dT);
+        T F[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            F[j] = r0 * (Tc[0] * M0[j] + Tc[1] * Ma[j] + Tc[2] * MA[j]) + Tc[3] * A.Mh[j] - Tc[4] * A.Mha[j] -
+                   tau * Tc[3] * A.MhA[j];
+        T Fb[5] = {Fdb[s][0], Fdb[s][1], Fdb[s][2], Fdb[s][3], Fdb[s][4]};
+        if constexpr (PR) {
+            T Wv[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j)
+                Wv[j] = r0 * (Tc[0] * W0m[j] + Tc[1] * Wam[j] + Tc[2] * WAm[j]) + Tc[3] * A.q0[j] - Tc[4] * A.Wha[j] -
+                        tau * Tc[3] * A.WhA[j];
+            const T U2 = U0 * U0 + V0 * V0 + W0 * W0;
+            const T Y = T(2) * Wv[4] - T(2) * (U0 * Wv[1] + V0 * Wv[2] + W0 * Wv[3]) + U2 * Wv[0];
+            const T q2b = (T(1) / fp.Pr - T(1)) * T(0.5) * Fdb[s][4];
+            Fb[4] += T(2) * q2b;
+            Fb[1] += T(-2) * U0 * q2b;
+            Fb[2] += T(-2) * V0 * q2b;
+            Fb[3] += T(-2) * W0 * q2b;
+            Fb[0] += U2 * q2b;
+            U0b += q2b * (T(-2) * F[1] + T(2) * U0 * F[0] - Y - U0 * (T(-2) * Wv[1] + T(2) * U0 * Wv[0]));
+            V0b += q2b * (T(-2) * F[2] + T(2) * V0 * F[0] - U0 * (T(-2) * Wv[2] + T(2) * V0 * Wv[0]));
+            W0b += q2b * (T(-2) * F[3] + T(2) * W0 * F[0] - U0 * (T(-2) * Wv[3] + T(2) * W0 * Wv[0]));
+            T Wvb[5];
+            Wvb[4] = T(-2) * U0 * q2b;
+            Wvb[1] = T(2) * U0 * U0 * q2b;
+            Wvb[2] = T(2) * U0 * V0 * q2b;
+            Wvb[3] = T(2) * U0 * W0 * q2b;
+            Wvb[0] = -U0 * U2 * q2b;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                r0b += Wvb[j] * (Tc[0] * W0m[j] + Tc[1] * Wam[j] + Tc[2] * WAm[j]);
+                Tb[0] += r0 * Wvb[j] * W0m[j];
+                Tb[1] += r0 * Wvb[j] * Wam[j];
+                Tb[2] += r0 * Wvb[j] * WAm[j];
+                Tb[3] += Wvb[j] * (A.q0[j] - tau * A.WhA[j]);
+                Tb[4] += -Wvb[j] * A.Wha[j];
+                taub += -Tc[3] * Wvb[j] * A.WhA[j];
+                W0mb[j] += r0 * Tc[0] * Wvb[j];
+                Wamb[j] += r0 * Tc[1] * Wvb[j];
+                WAmb[j] += r0 * Tc[2] * Wvb[j];
+                Ab.q0[j] += Tc[3] * Wvb[j];
+                Ab.Wha[j] += -Tc[4] * Wvb[j];
+                Ab.WhA[j] += -tau * Tc[3] * Wvb[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            r0b += Fb[j] * (Tc[0] * M0[j] + Tc[1] * Ma[j] + Tc[2] * MA[j]);
+            Tb[0] += r0 * Fb[j] * M0[j];
+            Tb[1] += r0 * Fb[j] * Ma[j];
+            Tb[2] += r0 * Fb[j] * MA[j];
+            Tb[3] += Fb[j] * (A.Mh[j] - tau * A.MhA[j]);
+            Tb[4] += -Fb[j] * A.Mha[j];
+            taub += -Tc[3] * Fb[j] * A.MhA[j];
+            M0b[j] += r0 * Tc[0] * Fb[j];
+            Mab[j] += r0 * Tc[1] * Fb[j];
+            MAb[j] += r0 * Tc[2] * Fb[j];
+            Ab.Mh[j] += Tc[3] * Fb[j];
+            Ab.Mha[j] += -Tc[4] * Fb[j];
+            Ab.MhA[j] += -tau * Tc[3] * Fb[j];
+        }
+#pragma unroll
+        for (int c = 0; c < 5; ++c) taub += Tb[c] * dT[c];
+    }
+    // collision time
+    {
+        const T sp = A.p[0] + A.p[1];
+        const T dpb = fp.tau_C * dt * sgn_t(dp) * taub;
+        Ab.p[0] += dpb * T(2) * A.p[1] / (sp * sp);
+        Ab.p[1] += -dpb * T(2) * A.p[0] / (sp * sp);
+        if (fp.viscous) p0b += -fp.mu / (p0 * p0) * taub;
+    }
+    // moment vectors of g0
+    MomB<T> Bg;
+    momb_zero(Bg);
+    T abb[3][5], Avb[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        Avb[j] = T(0);
+        abb[0][j] = abb[1][j] = abb[2][j] = T(0);
+    }
+    P_b<1, 0, 0>(G, M0b, Bg);
+    Padv_b<1>(G, ab, Mab, Bg, abb);
+    Pa_b<1, 0, 0>(G, Av, MAb, Bg, Avb);
+    if constexpr (PR) {
+        P_b<0, 0, 0>(G, W0mb, Bg);
+        Padv_b<0>(G, ab, Wamb, Bg, abb);
+        Pa_b<0, 0, 0>(G, Av, WAmb, Bg, Avb);
+    }
+    // Av = solve(-Padv0(G, ab))
+    T bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
+    slope_solve_b(bA, U0, V0, W0, lam0, K, Av, Avb, bAb, U0b, V0b, W0b, lam0b);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) bAb[j] = -bAb[j];
+    Padv_b<0>(G, ab, bAb, Bg, abb);
+    // ab[m] = solve(bab[m] / r0)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        T bmb[5] = {T(0), T(0), T(0), T(0), T(0)};
+        slope_solve_b(bm[m], U0, V0, W0, lam0, K, ab[m], abb[m], bmb, U0b, V0b, W0b, lam0b);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            Ab.bab[m][j] += bmb[j] * ir0;
+            r0b += -bmb[j] * bm[m][j] * ir0;
+        }
+    }
+    mom_full_u_b(G, Bg, U0, lam0, U0b, lam0b);
+    mom_common_b(G, Bg, V0, W0, lam0, K, V0b, W0b, lam0b);
+    to_prim_b(A.q0, fp.gamma, r0b, U0b, V0b, W0b, lam0b, p0b, Ab.q0);
+}
+
+// reverse of gp_flux: out_b -> cotangents of both local-frame states and their derivatives
+template <typename T, bool PR>
+__host__ __device__ void gp_flux_b(const T ql[5], const T dql[3][5], const T qr[5], const T dqr[3][5], T dt,
+                                   const FluxParams<T> &fp, const T outb[10], T qlb[5], T dqlb[3][5], T qrb[5],
+                                   T dqrb[3][5])
+{
+    FluxAcc<T, PR> A;
+    acc_zero(A);
+    side_pass<T, PR>(ql, dql, T(1), fp, A, 0);
+    side_pass<T, PR>(qr, dqr, T(-1), fp, A, 1);
+    FluxAccB<T, PR> Ab;
+    accb_zero(Ab);
+    finish_flux_b<T, PR>(A, dt, fp, outb, Ab);
+    side_pass_b<T, PR>(qr, dqr, T(-1), fp, Ab, 1, qrb, dqrb);
+    side_pass_b<T, PR>(ql, dql, T(1), fp, Ab, 0, qlb, dqlb);
+}
+
+// reverse of side_state: local-frame state cotangents -> coefficient cotangents cb[50] (accumulated)
+template <typename T>
+__host__ __device__ __forceinline__ void side_state_b(T X, T Y, T Z, const T n[3][3], const T qb[5], const T dqb[3][5],
+                                                      T cb[50])
+{
+    // q[1+k] = v . n_k; dq[m][1+k] = (g . n_m) . n_k
+    T vb[5], gb[5][3];
+    vb[0] = qb[0];
+    vb[4] = qb[4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) vb[1 + d] = qb[1] * n[0][d] + qb[2] * n[1][d] + qb[3] * n[2][d];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) gb[c][0] = gb[c][1] = gb[c][2] = T(0);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        T dnb[5];
+        dnb[0] = dqb[m][0];
+        dnb[4] = dqb[m][4];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dnb[1 + d] = dqb[m][1] * n[0][d] + dqb[m][2] * n[1][d] + dqb[m][3] * n[2][d];
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) gb[c][d] += dnb[c] * n[m][d];
+    }
+    const T XX = X * X, XY = X * Y, XZ = X * Z, YY = Y * Y, YZ = Y * Z, ZZ = Z * Z;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        T *cc = cb + 10 * c;
+        cc[0] += vb[c];
+        cc[1] += vb[c] * X + gb[c][0];
+        cc[2] += vb[c] * Y + gb[c][1];
+        cc[3] += vb[c] * Z + gb[c][2];
+        cc[4] += vb[c] * XX + T(2) * X * gb[c][0];
+        cc[5] += vb[c] * XY + Y * gb[c][0] + X * gb[c][1];
+        cc[6] += vb[c] * XZ + Z * gb[c][0] + X * gb[c][2];
+        cc[7] += vb[c] * YY + T(2) * Y * gb[c][1];
+        cc[8] += vb[c] * YZ + Z * gb[c][1] + Y * gb[c][2];
+        cc[9] += vb[c] * ZZ + T(2) * Z * gb[c][2];
+    }
+}
+
+/*
+ * Reverse of face_gp (FP64): out_b[10] -> cotangents of the owner's and the
+ * neighbour's 50 coefficients (accumulated into clb, crb).
+ */
+template <typename T, bool PR>
+__host__ __device__ void face_gp_b(const T *__restrict__ cl, const T *__restrict__ cr, const T geo[9], T dt,
+                                   const FluxParams<T> &fp, const T outb[10], T clb[50], T crb[50])
+{
+    T n3[3][3];
+    const T area = local_frame(geo[6], geo[7], geo[8], n3);
+    T ql[5], qr[5], dql[3][5], dqr[3][5];
+    side_state(cl, nullptr, geo[0], geo[1], geo[2], n3, ql, dql);
+    side_state(cr, nullptr, geo[3], geo[4], geo[5], n3, qr, dqr);
+    T Fb[10];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        Fb[5 * s] = area * outb[5 * s];
+        Fb[5 * s + 4] = area * outb[5 * s + 4];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            Fb[5 * s + 1 + k] =
+                area * (outb[5 * s + 1] * n3[k][0] + outb[5 * s + 2] * n3[k][1] + outb[5 * s + 3] * n3[k][2]);
+    }
+    T qlb[5] = {T(0), T(0), T(0), T(0), T(0)}, qrb[5] = {T(0), T(0), T(0), T(0), T(0)};
+    T dqlb[3][5], dqrb[3][5];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) dqlb[m][j] = dqrb[m][j] = T(0);
+    gp_flux_b<T, PR>(ql, dql, qr, dqr, dt, fp, Fb, qlb, dqlb, qrb, dqrb);
+    side_state_b(geo[0], geo[1], geo[2], n3, qlb, dqlb, clb);
+    side_state_b(geo[3], geo[4], geo[5], n3, qrb, dqrb, crb);
+}
+
+}  // namespace gks

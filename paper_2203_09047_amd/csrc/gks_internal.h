@@ -32,6 +32,8 @@ struct HostMesh {
     std::vector<double> fgeo;  // [9][4 nf]: d_owner(3), d_neighbour(3), weighted vector area(3) per Gauss point
     // cell -> faces in F_p order, encoded 2 * face + side (side 1: the cell is the neighbour)
     std::vector<int32_t> cf_ptr, cf_idx;
+    // transposed stencil CSR: entries e with st_idx[e] == i are tr_idx[tr_ptr[i] .. tr_ptr[i+1])
+    std::vector<int32_t> tr_ptr, tr_idx;
 };
 
 gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, const int8_t *types,

@@ -659,6 +659,15 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         H.cf_ptr[i + 1] = (int32_t)H.cf_idx.size();
         H.hcfl[i] = 6.0 * H.vol[i] / area_sum[i];
     }
+    // transposed stencil: for each cell, the stencil entries (of all cells) that name it, in entry order
+    H.tr_ptr.assign(n + 1, 0);
+    for (int32_t v : H.st_idx) H.tr_ptr[v + 1]++;
+    for (int64_t i = 0; i < n; ++i) H.tr_ptr[i + 1] += H.tr_ptr[i];
+    H.tr_idx.assign(H.st_idx.size(), 0);
+    {
+        std::vector<int32_t> fill(H.tr_ptr.begin(), H.tr_ptr.end() - 1);
+        for (size_t e = 0; e < H.st_idx.size(); ++e) H.tr_idx[fill[H.st_idx[e]]++] = (int32_t)e;
+    }
     return GKS_OK;
 }
 

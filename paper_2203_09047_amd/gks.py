@@ -24,9 +24,11 @@ SYMBOLS = [
     "gks_host_mesh_geometry", "gks_host_mesh_faces", "gks_mesh_sizes", "gks_init_mesh", "gks_destroy_mesh",
     "gks_reset_status", "gks_timestep", "gks_reconstruct", "gks_flux", "gks_residual", "gks_s2o4_step",
     "gks_poll_status", "gks_gp_flux_batch", "gks_profile", "gks_profile_read", "gks_gp_op_count",
-    "gks_last_error",
+    "gks_gp_flux_host", "gks_gp_flux_vjp_host", "gks_weno_combine_host", "gks_weno_combine_vjp_host",
+    "gks_adjoint_work_bytes", "gks_adjoint_step", "gks_kinetic_energy", "gks_last_error",
 ]
-KERNELS = ("timestep", "reconstruct", "flux", "stage1", "stage2", "residual")
+KERNELS = ("timestep", "reconstruct", "flux", "stage1", "stage2", "residual", "flux_adj", "reconstruct_adj",
+           "gather_adj")
 
 
 class GksError(RuntimeError):
@@ -101,6 +103,21 @@ def load():
         lib.gks_profile_read.restype = st
         lib.gks_gp_op_count.argtypes = [i32, ctypes.c_double, vp, vp, vp, vp]
         lib.gks_gp_op_count.restype = st
+        dbl = ctypes.c_double
+        lib.gks_gp_flux_host.argtypes = [vp, vp, vp, vp, dbl, pp, vp]
+        lib.gks_gp_flux_host.restype = st
+        lib.gks_gp_flux_vjp_host.argtypes = [vp, vp, vp, vp, dbl, pp, vp, vp, vp, vp, vp]
+        lib.gks_gp_flux_vjp_host.restype = st
+        lib.gks_weno_combine_host.argtypes = [vp, vp, vp, i32, dbl, vp, dbl, pp, vp]
+        lib.gks_weno_combine_host.restype = st
+        lib.gks_weno_combine_vjp_host.argtypes = [vp, vp, vp, i32, dbl, vp, pp, vp, vp, vp, vp]
+        lib.gks_weno_combine_vjp_host.restype = st
+        lib.gks_adjoint_work_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        lib.gks_adjoint_work_bytes.restype = st
+        lib.gks_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, pp, vp, vp]
+        lib.gks_adjoint_step.restype = st
+        lib.gks_kinetic_energy.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.gks_kinetic_energy.restype = st
         lib.gks_last_error.argtypes = []
         lib.gks_last_error.restype = ctypes.c_char_p
         _lib = lib
@@ -267,6 +284,41 @@ class Solver:
         _check(load().gks_s2o4_step(self.m, self._q(Q), _dp(self.dt), ctypes.byref(self.P), self._work_ptr, qs,
                                     self._s()))
         self.P.dt_given = 0
+        return Q
+
+    # adjoint -------------------------------------------------------------
+    def _adj_work(self):
+        if getattr(self, "adj_work", None) is None:
+            b = ctypes.c_size_t()
+            _check(load().gks_adjoint_work_bytes(self.host.h, ctypes.byref(b)))
+            self.adj_work = self.torch.empty(b.value + 256, dtype=self.torch.uint8, device=self.device)
+            self._adj_ptr = ctypes.c_void_p(self.adj_work.data_ptr() + ((-self.adj_work.data_ptr()) % 256))
+        return self._adj_ptr
+
+    def adjoint_step(self, Qn, Qstar, dt, lam_next, lam_out=None):
+        """lam_n from lam_{n+1} for the S2O4 step Qn -> (Qstar) -> Q_{n+1}; dt: 1-element device tensor."""
+        lam_out = self.torch.empty_like(lam_next) if lam_out is None else lam_out
+        _check(load().gks_adjoint_step(self.m, self._q(Qn), self._q(Qstar), _dp(dt), self._q(lam_next),
+                                       self._q(lam_out), ctypes.byref(self.P), self._adj_work(), self._s()))
+        return lam_out
+
+    def kinetic_energy(self, Q, grad=False):
+        """(J, dJ/dQ or None): J = sum |Omega| |rho U|^2 / (2 rho), on the device."""
+        J = self.torch.zeros(1, dtype=self.torch.float64, device=self.device)
+        g = self.torch.empty_like(Q) if grad else None
+        _check(load().gks_kinetic_energy(self.m, self._q(Q), _dp(J), _dp(g) if grad else None, self._work_ptr,
+                                         self._s()))
+        return J, g
+
+    def step_to(self, Q, dt_ptr_tensor, Q_star=None):
+        """One S2O4 step in place with dt read from a 1-element device tensor (no host round trip)."""
+        self.P.dt_given = 1
+        qs = _dp(Q_star) if Q_star is not None else None
+        try:
+            _check(load().gks_s2o4_step(self.m, self._q(Q), _dp(dt_ptr_tensor), ctypes.byref(self.P),
+                                        self._work_ptr, qs, self._s()))
+        finally:
+            self.P.dt_given = 0
         return Q
 
     def profile(self, enable=True):

@@ -1,0 +1,191 @@
+"""GPU discrete adjoint of the S2O4 step against finite differences (needs an MI355X).
+
+The adjoint step (gks_adjoint_step) is checked against central differences
+of the GPU forward step and, independently, of the FP64 oracle's step, both
+with the step size frozen; the checkpointed rollout's kinetic-energy gradient
+is checked against central differences along random directions.
+
+The collision time's term C |p_l - p_r| / (p_l + p_r) dt is not differentiable
+where the two reconstructed pressures at a Gauss point coincide, and for a
+smooth field they differ only by the O(h^3) reconstruction jump: central
+differences then straddle the kink at some Gauss points and disagree with
+themselves at the 1e-5 level as the step h changes.  The strict (1e-6) checks
+therefore use tau_C = 0; the paper's collision time is checked against the
+finite differences' own spread.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_09047_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gks():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_2203_09047_amd import gks as g
+
+    g.load()
+    return g
+
+
+def _setup(gks, kind, N, viscous=False, field=None, tau_C=0.0):
+    # a Taylor-Green field at Mach 0.5 on [0, 2 pi]^3: the pressure varies, so the collision
+    # time's |p_l - p_r| stays away from its kink under the finite-difference perturbations
+    mesh = inputs.lattice(N, kind, box=(2 * np.pi,) * 3)
+    fld = field or inputs.tgv(mach=0.5)
+    Q0 = inputs.cell_averages(mesh, fld)
+    host = gks.HostMesh(mesh)
+    prm = gks.params(viscous=viscous, mu=5e-3, Pr=0.72 if viscous else 1.0, tau_C=tau_C)
+    sol = gks.Solver(host, prm)
+    return mesh, Q0, host, sol
+
+
+def _step(sol, Qnp, dt):
+    import torch
+
+    Q = sol.upload(Qnp)
+    sol.step(Q, dt)
+    torch.cuda.synchronize()
+    return Q.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind,N,viscous", [("hex", 4, False), ("hybrid", 4, False), ("hybrid", 4, True)])
+def test_adjoint_step_matches_finite_differences_of_gpu_step(gks, kind, N, viscous):
+    import torch
+
+    print(f"case: adjoint step {kind} N={N} viscous={viscous}", flush=True)
+    mesh, Q0, host, sol = _setup(gks, kind, N, viscous)
+    Qn = host.to_internal(Q0)
+    rng = np.random.default_rng(5)
+    lam1 = rng.standard_normal(Qn.shape)
+    dt = 2e-2
+    # forward with stage state, then the adjoint
+    Q = sol.upload(Qn)
+    Qs = torch.empty_like(Q)
+    sol.step(Q, dt, Q_star=Qs)
+    dtt = torch.tensor([dt], dtype=torch.float64, device=Q.device)
+    lam = sol.adjoint_step(sol.upload(Qn), Qs, dtt, sol.upload(lam1))
+    sol.poll()
+    lam = lam.cpu().numpy()
+    for trial in range(3):
+        v = rng.standard_normal(Qn.shape) * np.abs(Qn).max(axis=1, keepdims=True)
+
+        def d(h):
+            return (lam1 * (_step(sol, Qn + h * v, dt) - _step(sol, Qn - h * v, dt))).sum() / (2 * h)
+
+        fd = (4 * d(5e-7) - d(1e-6)) / 3
+        ad = (lam * v).sum()
+        print(trial, fd, ad, abs(fd - ad) / abs(fd))
+        assert abs(fd - ad) <= 1e-6 * abs(fd)
+
+
+def test_adjoint_step_matches_finite_differences_of_oracle_step(gks):
+    """Independent of the GPU forward: central differences of the oracle's step."""
+    import torch
+
+    mesh, Q0, host, sol = _setup(gks, "hybrid", 4)
+    o = oracle.Oracle(mesh, oracle.params(tau_C=0.0))
+    rng = np.random.default_rng(9)
+    lam1 = rng.standard_normal(Q0.shape)
+    dt = 2e-2
+    Qn = host.to_internal(Q0)
+    Q = sol.upload(Qn)
+    Qs = torch.empty_like(Q)
+    sol.step(Q, dt, Q_star=Qs)
+    dtt = torch.tensor([dt], dtype=torch.float64, device=Q.device)
+    lam = host.to_external(sol.adjoint_step(sol.upload(Qn), Qs, dtt, sol.upload(host.to_internal(lam1))).cpu().numpy())
+    for trial in range(2):
+        v = rng.standard_normal(Q0.shape) * np.abs(Q0).max(axis=1, keepdims=True)
+
+        def d(h):
+            return (lam1 * (o.step(Q0 + h * v, dt) - o.step(Q0 - h * v, dt))).sum() / (2 * h)
+
+        fd = (4 * d(5e-7) - d(1e-6)) / 3
+        ad = (lam * v).sum()
+        print(trial, fd, ad, abs(fd - ad) / abs(fd))
+        assert abs(fd - ad) <= 1e-6 * abs(fd)
+
+
+def test_rollout_kinetic_energy_gradient_matches_finite_differences(gks):
+    import torch
+
+    from paper_2203_09047_amd.adjoint import Rollout, kinetic_energy_gradient
+
+    print("case: rollout KE gradient hybrid N=5, 7 steps, checkpoints every 3", flush=True)
+    mesh, Q0, host, sol = _setup(gks, "hybrid", 5)
+    Qn = host.to_internal(Q0)
+    nsteps = 7
+    J, g = kinetic_energy_gradient(sol, sol.upload(Qn), nsteps, ckpt_every=3)
+    # the frozen step sizes of that forward pass
+    Q = sol.upload(Qn)
+    dts = []
+    for _ in range(nsteps):
+        sol.step(Q)
+        dts.append(float(sol.dt.item()))
+    g = g.cpu().numpy()
+
+    def JT(Qnp):
+        Q = sol.upload(Qnp)
+        for dt in dts:
+            sol.step(Q, dt)
+        j, _ = sol.kinetic_energy(Q)
+        return float(j.item())
+
+    assert abs(JT(Qn) - float(J.item())) <= 1e-14 * abs(float(J.item()))
+    rng = np.random.default_rng(32)
+    for trial in range(4):
+        v = rng.standard_normal(Qn.shape)
+        v /= np.linalg.norm(v)
+        v *= np.abs(Qn).max(axis=1, keepdims=True)
+
+        def d(h):
+            return (JT(Qn + h * v) - JT(Qn - h * v)) / (2 * h)
+
+        fd = (4 * d(5e-7) - d(1e-6)) / 3
+        ad = (g * v).sum()
+        print(trial, fd, ad, abs(fd - ad) / abs(fd))
+        assert abs(fd - ad) <= 1e-6 * abs(fd)
+
+
+def test_adjoint_with_the_papers_collision_time(gks):
+    """tau_C = 1: agreement within the spread of the finite differences themselves."""
+    import torch
+
+    mesh, Q0, host, sol = _setup(gks, "hybrid", 4, tau_C=1.0)
+    Qn = host.to_internal(Q0)
+    rng = np.random.default_rng(5)
+    lam1 = rng.standard_normal(Qn.shape)
+    dt = 2e-2
+    Q = sol.upload(Qn)
+    Qs = torch.empty_like(Q)
+    sol.step(Q, dt, Q_star=Qs)
+    dtt = torch.tensor([dt], dtype=torch.float64, device=Q.device)
+    lam = sol.adjoint_step(sol.upload(Qn), Qs, dtt, sol.upload(lam1)).cpu().numpy()
+    v = rng.standard_normal(Qn.shape) * np.abs(Qn).max(axis=1, keepdims=True)
+    fds = [(lam1 * (_step(sol, Qn + h * v, dt) - _step(sol, Qn - h * v, dt))).sum() / (2 * h)
+           for h in (4e-6, 2e-6, 1e-6, 5e-7)]
+    ad = (lam * v).sum()
+    spread = max(fds) - min(fds)
+    print("fd", fds, "adjoint", ad, "spread", spread)
+    assert min(fds) - 2 * spread <= ad <= max(fds) + 2 * spread
+    assert abs(ad - np.mean(fds)) <= 1e-3 * abs(ad)
+
+
+def test_adjoint_is_bitwise_deterministic(gks):
+    import torch
+
+    mesh, Q0, host, sol = _setup(gks, "hybrid", 5)
+    Qn = host.to_internal(Q0)
+    Q = sol.upload(Qn)
+    Qs = torch.empty_like(Q)
+    sol.step(Q, 2e-2, Q_star=Qs)
+    dtt = torch.tensor([2e-2], dtype=torch.float64, device=Q.device)
+    lam1 = sol.upload(np.random.default_rng(1).standard_normal(Qn.shape))
+    a = sol.adjoint_step(sol.upload(Qn), Qs, dtt, lam1).cpu().numpy()
+    b = sol.adjoint_step(sol.upload(Qn), Qs, dtt, lam1).cpu().numpy()
+    assert np.array_equal(a, b)
