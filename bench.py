@@ -80,6 +80,42 @@ def run_gpu(args, mesh, Q0, precision):
     return host, sol, ms, prof
 
 
+def run_adjoint(args, host, mesh, Q0):
+    """Adjoint/forward time ratio of a checkpointed rollout (FP64): forward = nsteps S2O4 steps with
+    checkpoint stores, backward = segment recomputation + the discrete adjoint of every step."""
+    import torch
+
+    from paper_2203_09047_amd import gks
+    from paper_2203_09047_amd.adjoint import Rollout
+
+    prm = gks.params(precision=gks.FP64, viscous=True, mu=1.0 / 1600.0, Pr=0.72, cfl=0.5)
+    sol = gks.Solver(host, prm)
+    Q = sol.upload(host.to_internal(Q0)).requires_grad_(True)
+    # warm-up of every kernel involved
+    out = Rollout.apply(Q, sol, 2, 2)
+    J, g = sol.kinetic_energy(out.detach(), grad=True)
+    out.backward(g)
+    torch.cuda.synchronize()
+    Q.grad = None
+    sol.profile(True)
+    t0 = time.perf_counter()
+    out = Rollout.apply(Q, sol, args.adj_steps, 10)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof_f = sol.profile_read()
+    J, g = sol.kinetic_energy(out.detach(), grad=True)
+    out.backward(g)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    prof_b = sol.profile_read()
+    sol.profile(False)
+    sol.poll()
+    assert torch.isfinite(Q.grad).all()
+    kern = {k: dict(avg_ms=v[0] / max(v[1], 1), launches=v[1]) for k, v in prof_b.items() if v[1]}
+    return dict(steps=args.adj_steps, checkpoint_every=10, forward_s=t1 - t0, backward_s=t2 - t1,
+                ratio=(t2 - t1) / (t1 - t0), kernels_backward=kern)
+
+
 def cpu_baseline(N_sample=16):
     import oracle
     from paper_2203_09047_amd import inputs
@@ -105,6 +141,7 @@ def main():
     ap.add_argument("--N", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--adj-steps", type=int, default=20, help="steps of the adjoint/forward ratio (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -174,6 +211,14 @@ def main():
                                frac=achieved / HBM_PEAK_GBS, traffic=None)
     res["hbm_fraction_of_step_fp64"] = sum(bytes64[k] * kern[k]["launches"] for k in kern) / args.steps / (
         ms64 / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS
+    if args.adj_steps > 0:
+        del sol
+        torch.cuda.empty_cache()
+        adj = run_adjoint(args, host, mesh, Q0)
+        log(f"adjoint: {adj}")
+        res["adjoint"] = adj
+        res["adjoint_forward_ratio"] = adj["ratio"]
+        sol = None
     if not args.no_fp32:
         del sol
         torch.cuda.empty_cache()

@@ -208,7 +208,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return x * q + (x < r ? x : r) + j;
 }
 template <typename T>
-__global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff,
+__global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3))) k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff,
                                                           WenoParams wp)
 {
     const int t = xcd_block(blockIdx.x, gridDim.x) * kK1Block + threadIdx.x;
@@ -248,22 +248,20 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
     }
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = quad_sum(a[j]);
+    // linear sub-stencil fits: b^m = G_m^{-1} r_m / h (normal equations of the scaled offsets)
+    const T *gip = (const T *)m.ginv;
+    T b[8][3];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-        r[s][0] = quad_sum(r[s][0]);
-        r[s][1] = quad_sum(r[s][1]);
-        r[s][2] = quad_sum(r[s][2]);
+        T g[6], rs[3] = {quad_sum(r[s][0]), quad_sum(r[s][1]), quad_sum(r[s][2])};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) g[q] = gip[(size_t)(6 * s + q) * n + i];
+        sym3_apply(g, rs, b[s]);
     }
-    const T *gip = (const T *)m.ginv;
-    T gi[8][6];
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) gi[s][q] = gip[(size_t)(6 * s + q) * n + i];
     const T S[6] = {(T)m.m2[i], (T)m.m2[n + i], (T)m.m2[2 * n + i], (T)m.m2[3 * n + i], (T)m.m2[4 * n + i],
                     (T)m.m2[5 * n + i]};
     T c[10];
-    weno_combine<T>(a, r, gi, m.M[i], (T)m.vol23[i], S, q0, sizeof(T) == 8, wp, c);
+    weno_combine<T>(a, b, m.M[i], (T)m.vol23[i], S, q0, sizeof(T) == 8, wp, c);
     // lane l writes entries l, l + 4 and (lanes 0, 1) l + 8 of this component
     T v0 = c[0], v1 = c[4], v2 = c[8];
 #pragma unroll
@@ -422,7 +420,10 @@ __global__ void __launch_bounds__(kBlock) k_stage2(DevMesh m, const T *__restric
 // per (cell, component), and a gather over the transposed stencil.  All
 // gathers run in a fixed order: no atomics, bitwise reproducible.
 
+constexpr int kAccB = 47;  // accumulator cotangents per Gauss point (FluxAccB, Prandtl slots included)
+
 struct AdjWork {
+    double *abuf;   // [47][4F]   accumulator cotangents per Gauss point
     double *cbf;    // [F][2][50] coefficient cotangents per face side
     double *cbc;    // [N][50]    per cell
     double *dbar;   // [5][nnz]   cotangents of the stencil differences Q_k - Q_0
@@ -440,26 +441,88 @@ static size_t adj_layout(int64_t n, int64_t nf, int64_t nnz, AdjWork *w, char *b
         off = align256(off + bytes);
         return base ? (double *)(base + o) : nullptr;
     };
+    double *ab = take(8 * kAccB * 4 * nf);
     double *cbf = take(8 * 100 * nf), *cbc = take(8 * 50 * n), *dbar = take(8 * 5 * nnz), *own = take(8 * 5 * n),
            *ls = take(8 * 5 * n), *vj = take(8 * 5 * n), *co = take(8 * 50 * n);
-    if (w) *w = AdjWork{cbf, cbc, dbar, own, ls, vj, co};
+    if (w) *w = AdjWork{ab, cbf, cbc, dbar, own, ls, vj, co};
     return off;
 }
 
-// reverse of the flux: lane per (face, Gauss point)
+// pack / unpack the accumulator cotangents of one Gauss point ([47][4F], SoA)
 template <bool PR>
-__global__ void __launch_bounds__(kBlock) k_flux_adj(DevMesh m, const double *__restrict__ coeff,
-                                                     const double *__restrict__ dt_dev, const double *__restrict__ lp,
-                                                     const double *__restrict__ ls, double cL1, double cL2, double cD1,
-                                                     double cD2, FluxParams<double> fp, double *__restrict__ cbf)
+__device__ __forceinline__ void accb_store(const FluxAccB<double, PR> &A, double *__restrict__ buf, size_t stride, size_t t)
+{
+    int q = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) buf[(q + j) * stride + t] = A.q0[j];
+    q += 5;
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) buf[(q + 5 * m + j) * stride + t] = A.bab[m][j];
+    q += 15;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        buf[(q + j) * stride + t] = A.Mh[j];
+        buf[(q + 5 + j) * stride + t] = A.Mha[j];
+        buf[(q + 10 + j) * stride + t] = A.MhA[j];
+    }
+    q += 15;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        buf[(q + j) * stride + t] = PR ? A.Wha[PR ? j : 0] : 0.0;
+        buf[(q + 5 + j) * stride + t] = PR ? A.WhA[PR ? j : 0] : 0.0;
+    }
+    q += 10;
+    buf[(q + 0) * stride + t] = A.p[0];
+    buf[(q + 1) * stride + t] = A.p[1];
+}
+
+template <bool PR>
+__device__ __forceinline__ void accb_load(FluxAccB<double, PR> &A, const double *__restrict__ buf, size_t stride, size_t t)
+{
+    int q = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) A.q0[j] = buf[(q + j) * stride + t];
+    q += 5;
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) A.bab[m][j] = buf[(q + 5 * m + j) * stride + t];
+    q += 15;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        A.Mh[j] = buf[(q + j) * stride + t];
+        A.Mha[j] = buf[(q + 5 + j) * stride + t];
+        A.MhA[j] = buf[(q + 10 + j) * stride + t];
+    }
+    q += 15;
+    if constexpr (PR) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            A.Wha[j] = buf[(q + j) * stride + t];
+            A.WhA[j] = buf[(q + 5 + j) * stride + t];
+        }
+    }
+    q += 10;
+    A.p[0] = buf[(q + 0) * stride + t];
+    A.p[1] = buf[(q + 1) * stride + t];
+}
+
+// reverse of the flux, part 1 (lane per face Gauss point): both half-space passes forward,
+// then the reverse of the interface equilibrium, its slopes, the collision time, the time
+// integrals and the rotation/weighting, down to the half-space accumulators
+template <bool PR>
+__global__ void __launch_bounds__(kBlock) k_flux_adj_a(DevMesh m, const double *__restrict__ coeff,
+                                                       const double *__restrict__ dt_dev, const double *__restrict__ lp,
+                                                       const double *__restrict__ ls, double cL1, double cL2, double cD1,
+                                                       double cD2, FluxParams<double> fp, double *__restrict__ abuf)
 {
     const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int f = t >> 2;
-    const bool live = f < m.nf;
-    const int fs = live ? f : m.nf - 1;
+    if (f >= m.nf) return;
     const int nf4 = 4 * m.nf;
-    const int tt = 4 * fs + (t & 3);
-    const int o = m.owner[fs], nb = m.nbr[fs];
+    const int o = m.owner[f], nb = m.nbr[f];
     const int n = m.n;
     const double dt = dt_dev[0];
     // face cotangents from L = -(1/V) sum s F0, D = -(1/V) sum s F1 (owner s = +1, neighbour s = -1)
@@ -480,28 +543,86 @@ __global__ void __launch_bounds__(kBlock) k_flux_adj(DevMesh m, const double *__
     }
     double geo[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) geo[q] = m.fgeo[(size_t)q * nf4 + tt];
-    double cl[50], cr[50], clb[50], crb[50];
-    load_cell(coeff + (size_t)50 * o, cl);
-    load_cell(coeff + (size_t)50 * nb, cr);
-#pragma unroll
-    for (int j = 0; j < 50; ++j) clb[j] = crb[j] = 0.0;
-    face_gp_b<double, PR>(cl, cr, geo, dt, fp, outb, clb, crb);
-    // sum over the face's four Gauss points (a quad of lanes)
-#pragma unroll
-    for (int j = 0; j < 50; ++j) {
-        clb[j] = quad_sum(clb[j]);
-        crb[j] = quad_sum(crb[j]);
+    for (int q = 0; q < 9; ++q) geo[q] = m.fgeo[(size_t)q * nf4 + t];
+    double n3[3][3];
+    const double area = local_frame(geo[6], geo[7], geo[8], n3);
+    FluxAcc<double, PR> A;
+    acc_zero(A);
+    {
+        double q[5], dq[3][5], c[50];
+        load_cell(coeff + (size_t)50 * o, c);
+        side_state(c, nullptr, geo[0], geo[1], geo[2], n3, q, dq);
+        side_pass<double, PR>(q, dq, 1.0, fp, A, 0);
     }
+    {
+        double q[5], dq[3][5], c[50];
+        load_cell(coeff + (size_t)50 * nb, c);
+        side_state(c, nullptr, geo[3], geo[4], geo[5], n3, q, dq);
+        side_pass<double, PR>(q, dq, -1.0, fp, A, 1);
+    }
+    // rotation back and weighting: out = area R^T F
+    double Fb[10];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        Fb[5 * s] = area * outb[5 * s];
+        Fb[5 * s + 4] = area * outb[5 * s + 4];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            Fb[5 * s + 1 + k] =
+                area * (outb[5 * s + 1] * n3[k][0] + outb[5 * s + 2] * n3[k][1] + outb[5 * s + 3] * n3[k][2]);
+    }
+    FluxAccB<double, PR> Ab;
+    accb_zero(Ab);
+    finish_flux_b<double, PR>(A, dt, fp, Fb, Ab);
+    accb_store<PR>(Ab, abuf, (size_t)nf4, (size_t)t);
+}
+
+// reverse of the flux, part 2 (lane per face Gauss point and side): the reverse of that
+// side's half-space pass and of its state evaluation; the four Gauss points of a side
+// (a quad of lanes) are summed in a fixed order
+template <bool PR>
+__global__ void __launch_bounds__(kBlock) k_flux_adj_b(DevMesh m, const double *__restrict__ coeff,
+                                                       FluxParams<double> fp, const double *__restrict__ abuf,
+                                                       double *__restrict__ cbf)
+{
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int f = t >> 3;
+    const bool live = f < m.nf;
+    const int fs = live ? f : m.nf - 1;
+    const int side = (t >> 2) & 1;
+    const int g = t & 3;
+    const int nf4 = 4 * m.nf;
+    const size_t tg = (size_t)4 * fs + g;
+    const int cell = side ? m.nbr[fs] : m.owner[fs];
+    double geo[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) geo[q] = m.fgeo[(size_t)q * nf4 + tg];
+    double n3[3][3];
+    local_frame(geo[6], geo[7], geo[8], n3);
+    const double X = side ? geo[3] : geo[0], Y = side ? geo[4] : geo[1], Z = side ? geo[5] : geo[2];
+    double c[50];
+    load_cell(coeff + (size_t)50 * cell, c);
+    double q[5], dq[3][5];
+    side_state(c, nullptr, X, Y, Z, n3, q, dq);
+    FluxAccB<double, PR> Ab;
+    accb_load<PR>(Ab, abuf, (size_t)nf4, tg);
+    double qb[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, dqb[3][5];
+#pragma unroll
+    for (int mm = 0; mm < 3; ++mm)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) dqb[mm][j] = 0.0;
+    side_pass_b<double, PR>(q, dq, side ? -1.0 : 1.0, fp, Ab, side, qb, dqb);
+    double cb[50];
+#pragma unroll
+    for (int j = 0; j < 50; ++j) cb[j] = 0.0;
+    side_state_b(X, Y, Z, n3, qb, dqb, cb);
+#pragma unroll
+    for (int j = 0; j < 50; ++j) cb[j] = quad_sum(cb[j]);
     if (live) {
-        const int g4 = t & 3;
-        double *dst = cbf + (size_t)100 * f;
+        double *dst = cbf + (size_t)100 * f + 50 * side;
 #pragma unroll
         for (int j = 0; j < 50; ++j)
-            if ((j & 3) == g4) {
-                dst[j] = clb[j];
-                dst[50 + j] = crb[j];
-            }
+            if ((j & 3) == g) dst[j] = cb[j];
     }
 }
 
@@ -560,24 +681,23 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct_adj(DevMesh m, const d
     }
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = quad_sum(a[j]);
+    const double *gip = (const double *)m.ginv;
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         r[s][0] = quad_sum(r[s][0]);
         r[s][1] = quad_sum(r[s][1]);
         r[s][2] = quad_sum(r[s][2]);
     }
-    const double *gip = (const double *)m.ginv;
-    double gi[8][6];
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) gi[s][q] = gip[(size_t)(6 * s + q) * n + i];
     const double S[6] = {m.m2[i], m.m2[n + i], m.m2[2 * n + i], m.m2[3 * n + i], m.m2[4 * n + i], m.m2[5 * n + i]};
     double cb[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j) cb[j] = cbc[(size_t)50 * i + 10 * comp + j];
     double ab[9], rb[8][3], q0b = 0.0;
-    weno_combine_b<double>(a, r, gi, m.M[i], m.vol23[i], S, wp, cb, ab, rb, q0b);
+    auto getg = [&](int s, double g[6]) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) g[q] = gip[(size_t)(6 * s + q) * n + i];
+    };
+    weno_combine_b<double>(a, r, getg, m.M[i], m.vol23[i], S, wp, cb, ab, rb, q0b);
     // members: dbar_k = sum_j A+[j][k] ab_j + D_k . sum_{m in mask} rb_m
     double sumk = 0.0;
     for (int k = k0 + l; k < k1; k += kK1Lanes) {
@@ -1163,11 +1283,14 @@ static gks_status launch_vjp(gks_mesh *m, const double *Qe, const double *dt_dev
     const FluxParams<double> fp = flux_params<double>(p);
     {
         ProfScope ps(m, GKS_K_FLUX_ADJ, st);
-        const unsigned g = grid_for(4 * m->nf, kBlock);
-        if (pr)
-            k_flux_adj<true><<<g, kBlock, 0, st>>>(m->d, aw.coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.cbf);
-        else
-            k_flux_adj<false><<<g, kBlock, 0, st>>>(m->d, aw.coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.cbf);
+        const unsigned ga = grid_for(4 * m->nf, kBlock), gb = grid_for(8 * m->nf, kBlock);
+        if (pr) {
+            k_flux_adj_a<true><<<ga, kBlock, 0, st>>>(m->d, aw.coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.abuf);
+            k_flux_adj_b<true><<<gb, kBlock, 0, st>>>(m->d, aw.coeff, fp, aw.abuf, aw.cbf);
+        } else {
+            k_flux_adj_a<false><<<ga, kBlock, 0, st>>>(m->d, aw.coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.abuf);
+            k_flux_adj_b<false><<<gb, kBlock, 0, st>>>(m->d, aw.coeff, fp, aw.abuf, aw.cbf);
+        }
     }
     {
         ProfScope ps(m, GKS_K_GATHER_ADJ, st);
@@ -1301,12 +1424,9 @@ gks_status gks_weno_combine_host(const double *a, const double *r, const double 
                                  const double *S, double q0, const gks_params *p, double *c)
 {
     if (!a || !r || !gi || !S || !p || !c || M < 1 || M > 8) return fail(GKS_EINVAL, "bad argument");
-    double rr[8][3], gg[8][6];
-    for (int s = 0; s < 8; ++s) {
-        for (int q = 0; q < 3; ++q) rr[s][q] = r[3 * s + q];
-        for (int q = 0; q < 6; ++q) gg[s][q] = gi[6 * s + q];
-    }
-    weno_combine<double>(a, rr, gg, M, v23, S, q0, true, weno_params(p), c);
+    double b[8][3];
+    for (int s = 0; s < 8; ++s) sym3_apply(gi + 6 * s, r + 3 * s, b[s]);
+    weno_combine<double>(a, b, M, v23, S, q0, true, weno_params(p), c);
     return GKS_OK;
 }
 
@@ -1315,13 +1435,14 @@ gks_status gks_weno_combine_vjp_host(const double *a, const double *r, const dou
                                      double *q0b)
 {
     if (!a || !r || !gi || !S || !p || !cb || !ab || !rb || !q0b || M < 1 || M > 8) return fail(GKS_EINVAL, "bad argument");
-    double rr[8][3], gg[8][6], rrb[8][3];
-    for (int s = 0; s < 8; ++s) {
+    double rr[8][3], rrb[8][3];
+    for (int s = 0; s < 8; ++s)
         for (int q = 0; q < 3; ++q) rr[s][q] = r[3 * s + q];
-        for (int q = 0; q < 6; ++q) gg[s][q] = gi[6 * s + q];
-    }
+    auto getg = [&](int s, double g[6]) {
+        for (int q = 0; q < 6; ++q) g[q] = gi[6 * s + q];
+    };
     double qb = 0.0;
-    weno_combine_b<double>(a, rr, gg, M, v23, S, weno_params(p), cb, ab, rrb, qb);
+    weno_combine_b<double>(a, rr, getg, M, v23, S, weno_params(p), cb, ab, rrb, qb);
     for (int s = 0; s < 8; ++s)
         for (int q = 0; q < 3; ++q) rb[3 * s + q] = rrb[s][q];
     *q0b = qb;

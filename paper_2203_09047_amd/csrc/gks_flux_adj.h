@@ -336,7 +336,10 @@ __host__ __device__ __forceinline__ void accb_zero(FluxAccB<T, PR> &A)
     A.p[0] = A.p[1] = T(0);
 }
 
-// reverse of side_pass: accumulator cotangents -> q_b, dq_b
+// reverse of side_pass: accumulator cotangents -> q_b, dq_b.  One moment set M
+// holds the half-space u moments while the half-space accumulations are
+// reversed, then the full-space ones; v, w and internal moments (and their
+// cotangents) are shared by both.
 template <typename T, bool PR>
 __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, const FluxParams<T> &fp,
                                      const FluxAccB<T, PR> &Ab, int side, T qb[5], T dqb[3][5])
@@ -344,29 +347,30 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
     const T K = fp.K;
     T rho, U, V, W, lam, p;
     to_prim(q, fp.gamma, rho, U, V, W, lam, p);
-    Mom<T> Mf;
-    mom_common(Mf, V, W, lam, K);
-    mom_full_u(Mf, U, lam);
-    T a[3][5], Av[5], bA[5];
     const T ir = T(1) / rho;
-    T bm[3][5];
+    Mom<T> M;
+    mom_common(M, V, W, lam, K);
+    mom_full_u(M, U, lam);
+    T a[3][5], Av[5];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
+        T bm[5];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) bm[m][j] = dq[m][j] * ir;
-        slope_solve(bm[m], U, V, W, lam, K, a[m]);
+        for (int j = 0; j < 5; ++j) bm[j] = dq[m][j] * ir;
+        slope_solve(bm, U, V, W, lam, K, a[m]);
     }
-    Padv<0>(Mf, a, bA);
+    {
+        T bA[5];
+        Padv<0>(M, a, bA);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
-    slope_solve(bA, U, V, W, lam, K, Av);
-    Mom<T> Mh = Mf;
-    mom_half_u(Mh, U, lam, sign);
+        for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
+        slope_solve(bA, U, V, W, lam, K, Av);
+    }
+    mom_half_u(M, U, lam, sign);
 
-    T rhob = T(0), Ub = T(0), Vb = T(0), Wb = T(0), lamb = T(0), pb = Ab.p[side];
-    MomB<T> Bh, Bf;
-    momb_zero(Bh);
-    momb_zero(Bf);
+    T rhob = T(0), Ub = T(0), Vb = T(0), Wb = T(0), lamb = T(0);
+    MomB<T> B;
+    momb_zero(B);
     T ab[3][5], Avb[5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
@@ -374,80 +378,79 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
         ab[0][j] = ab[1][j] = ab[2][j] = T(0);
     }
     T t[5], s[5];
-    // q0 += rho P000
-    P<0, 0, 0>(Mh, t);
+    P<0, 0, 0>(M, t);
     rhob += dot5(Ab.q0, t);
 #pragma unroll
     for (int j = 0; j < 5; ++j) s[j] = rho * Ab.q0[j];
-    P_b<0, 0, 0>(Mh, s, Bh);
-    // bab[m] += rho Pa000(a[m])
+    P_b<0, 0, 0>(M, s, B);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        Pa<0, 0, 0>(Mh, a[m], t);
+        Pa<0, 0, 0>(M, a[m], t);
         rhob += dot5(Ab.bab[m], t);
 #pragma unroll
         for (int j = 0; j < 5; ++j) s[j] = rho * Ab.bab[m][j];
-        Pa_b<0, 0, 0>(Mh, a[m], s, Bh, ab[m]);
+        Pa_b<0, 0, 0>(M, a[m], s, B, ab[m]);
     }
-    // Mh += rho P100
-    P<1, 0, 0>(Mh, t);
+    P<1, 0, 0>(M, t);
     rhob += dot5(Ab.Mh, t);
 #pragma unroll
     for (int j = 0; j < 5; ++j) s[j] = rho * Ab.Mh[j];
-    P_b<1, 0, 0>(Mh, s, Bh);
-    // Mha += rho Padv1(a)
-    Padv<1>(Mh, a, t);
+    P_b<1, 0, 0>(M, s, B);
+    Padv<1>(M, a, t);
     rhob += dot5(Ab.Mha, t);
 #pragma unroll
     for (int j = 0; j < 5; ++j) s[j] = rho * Ab.Mha[j];
-    Padv_b<1>(Mh, a, s, Bh, ab);
-    // MhA += rho Pa100(Av)
-    Pa<1, 0, 0>(Mh, Av, t);
+    Padv_b<1>(M, a, s, B, ab);
+    Pa<1, 0, 0>(M, Av, t);
     rhob += dot5(Ab.MhA, t);
 #pragma unroll
     for (int j = 0; j < 5; ++j) s[j] = rho * Ab.MhA[j];
-    Pa_b<1, 0, 0>(Mh, Av, s, Bh, Avb);
+    Pa_b<1, 0, 0>(M, Av, s, B, Avb);
     if constexpr (PR) {
-        Padv<0>(Mh, a, t);
+        Padv<0>(M, a, t);
         rhob += dot5(Ab.Wha, t);
 #pragma unroll
         for (int j = 0; j < 5; ++j) s[j] = rho * Ab.Wha[j];
-        Padv_b<0>(Mh, a, s, Bh, ab);
-        Pa<0, 0, 0>(Mh, Av, t);
+        Padv_b<0>(M, a, s, B, ab);
+        Pa<0, 0, 0>(M, Av, t);
         rhob += dot5(Ab.WhA, t);
 #pragma unroll
         for (int j = 0; j < 5; ++j) s[j] = rho * Ab.WhA[j];
-        Pa_b<0, 0, 0>(Mh, Av, s, Bh, Avb);
+        Pa_b<0, 0, 0>(M, Av, s, B, Avb);
     }
-    // half-space u moments; v, w, s moments are shared with the full set
-    mom_half_u_b(Mh, Bh, U, lam, sign, Ub, lamb);
+    // half-space u moments done: their cotangents go to U and lambda, then the full set returns
+    mom_half_u_b(M, B, U, lam, sign, Ub, lamb);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        Bf.v[k] += Bh.v[k];
-        Bf.w[k] += Bh.w[k];
+    for (int k = 0; k < 7; ++k) B.u[k] = T(0);
+    mom_full_u(M, U, lam);
+    // Av = solve(-Padv0(M, a))
+    {
+        T bA[5];
+        Padv<0>(M, a, bA);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
+        T bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
+        slope_solve_b(bA, U, V, W, lam, K, Av, Avb, bAb, Ub, Vb, Wb, lamb);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) bAb[j] = -bAb[j];
+        Padv_b<0>(M, a, bAb, B, ab);
     }
-    Bf.s1 += Bh.s1;
-    Bf.s2 += Bh.s2;
-    // Av = solve(-Padv0(Mf, a))
-    T bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
-    slope_solve_b(bA, U, V, W, lam, K, Av, Avb, bAb, Ub, Vb, Wb, lamb);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) bAb[j] = -bAb[j];
-    Padv_b<0>(Mf, a, bAb, Bf, ab);
     // a[m] = solve(dq[m] / rho)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        T bmb[5] = {T(0), T(0), T(0), T(0), T(0)};
-        slope_solve_b(bm[m], U, V, W, lam, K, a[m], ab[m], bmb, Ub, Vb, Wb, lamb);
+        T bm[5], bmb[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int j = 0; j < 5; ++j) bm[j] = dq[m][j] * ir;
+        slope_solve_b(bm, U, V, W, lam, K, a[m], ab[m], bmb, Ub, Vb, Wb, lamb);
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
             dqb[m][j] += bmb[j] * ir;
-            rhob += -bmb[j] * bm[m][j] * ir;
+            rhob += -bmb[j] * bm[j] * ir;
         }
     }
-    mom_full_u_b(Mf, Bf, U, lam, Ub, lamb);
-    mom_common_b(Mf, Bf, V, W, lam, K, Vb, Wb, lamb);
-    to_prim_b(q, fp.gamma, rhob, Ub, Vb, Wb, lamb, pb, qb);
+    mom_full_u_b(M, B, U, lam, Ub, lamb);
+    mom_common_b(M, B, V, W, lam, K, Vb, Wb, lamb);
+    to_prim_b(q, fp.gamma, rhob, Ub, Vb, Wb, lamb, Ab.p[side], qb);
 }
 
 // T coefficients of the time integrals over [0, d] and their derivatives in tau

@@ -2,10 +2,11 @@
 // Eq. indicator), after the stencil sums, and its hand-written reverse.
 //
 // Inputs: a[9], the least-squares quadratic's coefficients of the monomials
-// x y z xx xy xz yy yz zz of (x - x_c); r[m][3] = sum_{k in S_m} D_k (Q_k - Q_0)
-// with D_k the member's centroid offset scaled by h; gi[m][6] the symmetric
-// inverse of sum_{k in S_m} D_k D_k^T divided by h, so that b^m = gi[m] r[m] is
-// the linear polynomial of sub-stencil m.  The smoothness indicators are
+// x y z xx xy xz yy yz zz of (x - x_c); b[m][3], the linear polynomial of
+// sub-stencil m, formed by the caller as b^m = gi[m] r[m] from the sums
+// r[m] = sum_{k in S_m} D_k (Q_k - Q_0) (D_k the member's centroid offset scaled
+// by h) and gi[m], the symmetric inverse of sum_{k in S_m} D_k D_k^T divided by
+// h (sym3_apply).  The smoothness indicators are
 // integrated over the cell with its centred second moments S (xx xy xz yy yz
 // zz) and v23 = |Omega|^(2/3); the nonlinear weights use tau_w = mean |beta_0 -
 // beta_m|; the nonlinear combination of Eq. weno is folded into one quadratic
@@ -41,19 +42,20 @@ __host__ __device__ __forceinline__ T wsgn(T x)
     return x > T(0) ? T(1) : (x < T(0) ? T(-1) : T(0));
 }
 
-// forward; q0 enters only c[0] (c[0] excludes it when with_q0 is false)
+// b^m = gi[m] r[m] for a symmetric gi stored as xx xy xz yy yz zz
 template <typename T>
-__host__ __device__ __forceinline__ void weno_combine(const T a[9], const T r[8][3], const T gi[8][6], int M, T v23,
-                                                      const T S[6], double q0, bool with_q0, const WenoParams &wp,
-                                                      T c[10])
+__host__ __device__ __forceinline__ void sym3_apply(const T g[6], const T r[3], T b[3])
 {
-    T b[8][3];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        b[s][0] = gi[s][0] * r[s][0] + gi[s][1] * r[s][1] + gi[s][2] * r[s][2];
-        b[s][1] = gi[s][1] * r[s][0] + gi[s][3] * r[s][1] + gi[s][4] * r[s][2];
-        b[s][2] = gi[s][2] * r[s][0] + gi[s][4] * r[s][1] + gi[s][5] * r[s][2];
-    }
+    b[0] = g[0] * r[0] + g[1] * r[1] + g[2] * r[2];
+    b[1] = g[1] * r[0] + g[3] * r[1] + g[4] * r[2];
+    b[2] = g[2] * r[0] + g[4] * r[1] + g[5] * r[2];
+}
+
+// forward from the linear polynomials b[m]; q0 enters only c[0] (c[0] excludes it when with_q0 is false)
+template <typename T>
+__host__ __device__ __forceinline__ void weno_combine(const T a[9], const T b[8][3], int M, T v23, const T S[6],
+                                                      double q0, bool with_q0, const WenoParams &wp, T c[10])
+{
     const T H[3][3] = {{T(2) * a[3], a[4], a[5]}, {a[4], T(2) * a[6], a[7]}, {a[5], a[7], T(2) * a[8]}};
     const T Sm[3][3] = {{S[0], S[1], S[2]}, {S[1], S[3], S[4]}, {S[2], S[4], S[5]}};
     T beta0 = T(0);
@@ -109,22 +111,17 @@ __host__ __device__ __forceinline__ void weno_combine(const T a[9], const T r[8]
 }
 
 /*
- * Reverse of weno_combine (FP64 adjoint): cb[10] -> ab[9], rb[8][3] (overwritten)
- * and q0b (the direct dependence of c[0] on the cell average).
+ * Reverse of weno_combine composed with b^m = gi[m] r[m] (FP64 adjoint):
+ * cb[10] -> ab[9], rb[8][3] (overwritten) and q0b (the direct dependence of
+ * c[0] on the cell average).  getg(m, g) loads gi[m].  The per-sub-stencil
+ * quantities are recomputed in four streaming passes over m instead of being
+ * held in arrays, which keeps the live state small.
  */
-template <typename T>
-__host__ __device__ __forceinline__ void weno_combine_b(const T a[9], const T r[8][3], const T gi[8][6], int M, T v23,
+template <typename T, typename GetG>
+__host__ __device__ __forceinline__ void weno_combine_b(const T a[9], const T r[8][3], GetG getg, int M, T v23,
                                                         const T S[6], const WenoParams &wp, const T cb_in[10], T ab[9],
                                                         T rb[8][3], T &q0b)
 {
-    // forward recomputation
-    T b[8][3];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        b[s][0] = gi[s][0] * r[s][0] + gi[s][1] * r[s][1] + gi[s][2] * r[s][2];
-        b[s][1] = gi[s][1] * r[s][0] + gi[s][3] * r[s][1] + gi[s][4] * r[s][2];
-        b[s][2] = gi[s][2] * r[s][0] + gi[s][4] * r[s][1] + gi[s][5] * r[s][2];
-    }
     const T H[3][3] = {{T(2) * a[3], a[4], a[5]}, {a[4], T(2) * a[6], a[7]}, {a[5], a[7], T(2) * a[8]}};
     const T Sm[3][3] = {{S[0], S[1], S[2]}, {S[1], S[3], S[4]}, {S[2], S[4], S[5]}};
     T beta0 = T(0);
@@ -140,83 +137,71 @@ __host__ __device__ __forceinline__ void weno_combine_b(const T a[9], const T r[
     const T sec = T(4) * (a[3] * a[3] + a[6] * a[6] + a[8] * a[8]) + a[4] * a[4] + a[5] * a[5] + a[7] * a[7];
     beta0 = v23 * beta0 + v23 * v23 * sec;
     const T gm = (T)wp.gm, g0 = T(1) - gm * T(M), eps = (T)wp.eps, pw = (T)wp.p;
-    T beta[8];
+    const bool lin = wp.force_linear != 0;
+    auto slot = [&](int s, T b[3], T &beta) {
+        T g[6];
+        getg(s, g);
+        sym3_apply(g, r[s], b);
+        beta = v23 * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    };
+    // pass A: tau_w and the weights' sum
     T tw = T(0);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        beta[s] = v23 * (b[s][0] * b[s][0] + b[s][1] * b[s][1] + b[s][2] * b[s][2]);
-        if (s < M) tw += wabs(beta0 - beta[s]);
-    }
+    for (int s = 0; s < 8; ++s)
+        if (s < M) {
+            T b[3], beta;
+            slot(s, b, beta);
+            tw += wabs(beta0 - beta);
+        }
     tw /= T(M);
-    T w0, ws[8], x0 = T(0), xs[8];
-    if (wp.force_linear) {
-        w0 = g0;
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            ws[s] = gm;
-            xs[s] = T(0);
-        }
-    } else {
-        x0 = tw / (beta0 + eps);
-        w0 = g0 * (T(1) + wpow(x0, pw));
-#pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            xs[s] = tw / (beta[s] + eps);
-            ws[s] = gm * (T(1) + wpow(xs[s], pw));
-        }
-    }
+    const T x0 = lin ? T(0) : tw / (beta0 + eps);
+    const T w0 = lin ? g0 : g0 * (T(1) + wpow(x0, pw));
     T sum = w0;
 #pragma unroll
     for (int s = 0; s < 8; ++s)
-        if (s < M) sum += ws[s];
+        if (s < M) {
+            T b[3], beta;
+            slot(s, b, beta);
+            sum += lin ? gm : gm * (T(1) + wpow(tw / (beta + eps), pw));
+        }
     const T isum = T(1) / sum;
     const T f0 = w0 * isum / g0;
     const T sub0 = f0 * gm;
-
-    // reverse
+    auto wslot = [&](T beta, T &xs) {
+        xs = lin ? T(0) : tw / (beta + eps);
+        return lin ? gm : gm * (T(1) + wpow(xs, pw));
+    };
+    // reverse of c[0] = q0 - sum c_n S_n and of c[1 + j] = f0 a_j
     T cb[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j) cb[j] = cb_in[j];
     q0b += cb[0];
-    cb[4] += -S[0] * cb[0];
-    cb[5] += -S[1] * cb[0];
-    cb[6] += -S[2] * cb[0];
-    cb[7] += -S[3] * cb[0];
-    cb[8] += -S[4] * cb[0];
-    cb[9] += -S[5] * cb[0];
-    T f0b = T(0), sumb = T(0), w0b = T(0), wsb[8], bb[8][3];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        wsb[s] = T(0);
-        bb[s][0] = bb[s][1] = bb[s][2] = T(0);
-    }
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-        if (s < M) {
-            const T fs = ws[s] * isum - sub0;
-            const T fsb = b[s][0] * cb[1] + b[s][1] * cb[2] + b[s][2] * cb[3];
-            bb[s][0] += fs * cb[1];
-            bb[s][1] += fs * cb[2];
-            bb[s][2] += fs * cb[3];
-            wsb[s] += fsb * isum;
-            sumb += -fsb * ws[s] * isum * isum;
-            f0b += -fsb * gm;
-        }
+    for (int q = 0; q < 6; ++q) cb[4 + q] += -S[q] * cb[0];
+    T f0b = T(0);
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
         ab[j] = f0 * cb[1 + j];
         f0b += a[j] * cb[1 + j];
     }
-    w0b += f0b * isum / g0;
-    sumb += -f0b * w0 * isum * isum / g0;
-    w0b += sumb;
+    // pass B: contributions of c[1..3] += f_m b^m to f0 and to the sum
+    T sumb = T(0);
 #pragma unroll
     for (int s = 0; s < 8; ++s)
-        if (s < M) wsb[s] += sumb;
-    T beta0b = T(0), betab[8], twb = T(0);
-#pragma unroll
-    for (int s = 0; s < 8; ++s) betab[s] = T(0);
-    if (!wp.force_linear) {
+        if (s < M) {
+            T b[3], beta, xs;
+            slot(s, b, beta);
+            const T ws = wslot(beta, xs);
+            const T fsb = b[0] * cb[1] + b[1] * cb[2] + b[2] * cb[3];
+            sumb += -fsb * ws * isum * isum;
+            f0b += -fsb * gm;
+            (void)xs;
+        }
+    sumb += -f0b * w0 * isum * isum / g0;
+    const T w0b = f0b * isum / g0 + sumb;
+    // pass C: tau_w cotangent
+    T twb = T(0), beta0b = T(0);
+    if (!lin) {
         const T dp0 = pw == T(1) ? T(1) : pw * wpow(x0, pw - T(1));
         const T x0b = w0b * g0 * dp0;
         twb += x0b / (beta0 + eps);
@@ -224,25 +209,43 @@ __host__ __device__ __forceinline__ void weno_combine_b(const T a[9], const T r[
 #pragma unroll
         for (int s = 0; s < 8; ++s)
             if (s < M) {
-                const T dps = pw == T(1) ? T(1) : pw * wpow(xs[s], pw - T(1));
-                const T xsb = wsb[s] * gm * dps;
-                twb += xsb / (beta[s] + eps);
-                betab[s] += -xsb * xs[s] / (beta[s] + eps);
+                T b[3], beta, xs;
+                slot(s, b, beta);
+                const T ws = wslot(beta, xs);
+                (void)ws;
+                const T fsb = b[0] * cb[1] + b[1] * cb[2] + b[2] * cb[3];
+                const T wsb = fsb * isum + sumb;
+                const T dps = pw == T(1) ? T(1) : pw * wpow(xs, pw - T(1));
+                twb += wsb * gm * dps / (beta + eps);
             }
     }
     twb /= T(M);
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-        if (s < M) {
-            const T sg = wsgn(beta0 - beta[s]);
-            beta0b += twb * sg;
-            betab[s] += -twb * sg;
-        }
+    // pass D: each sub-stencil's cotangents
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-        bb[s][0] += T(2) * v23 * betab[s] * b[s][0];
-        bb[s][1] += T(2) * v23 * betab[s] * b[s][1];
-        bb[s][2] += T(2) * v23 * betab[s] * b[s][2];
+        if (s < M) {
+            T b[3], beta, xs;
+            slot(s, b, beta);
+            const T ws = wslot(beta, xs);
+            const T fs = ws * isum - sub0;
+            const T fsb = b[0] * cb[1] + b[1] * cb[2] + b[2] * cb[3];
+            const T wsb = fsb * isum + sumb;
+            T betab = T(0);
+            if (!lin) {
+                const T dps = pw == T(1) ? T(1) : pw * wpow(xs, pw - T(1));
+                betab += -wsb * gm * dps * xs / (beta + eps);
+            }
+            const T sg = wsgn(beta0 - beta);
+            beta0b += twb * sg;
+            betab += -twb * sg;
+            T bb[3], g[6];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) bb[q] = fs * cb[1 + q] + T(2) * v23 * betab * b[q];
+            getg(s, g);
+            sym3_apply(g, bb, rb[s]);
+        } else {
+            rb[s][0] = rb[s][1] = rb[s][2] = T(0);
+        }
     }
     // beta0 = v23 sum_d (a_d^2 + H_d S H_d) + v23^2 sec
     const T g1 = v23 * beta0b, g2 = v23 * v23 * beta0b;
@@ -264,13 +267,6 @@ __host__ __device__ __forceinline__ void weno_combine_b(const T a[9], const T r[
     ab[6] += T(2) * Hb[1][1] + T(8) * g2 * a[6];
     ab[7] += Hb[1][2] + Hb[2][1] + T(2) * g2 * a[7];
     ab[8] += T(2) * Hb[2][2] + T(8) * g2 * a[8];
-    // b = gi r (gi symmetric)
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        rb[s][0] = gi[s][0] * bb[s][0] + gi[s][1] * bb[s][1] + gi[s][2] * bb[s][2];
-        rb[s][1] = gi[s][1] * bb[s][0] + gi[s][3] * bb[s][1] + gi[s][4] * bb[s][2];
-        rb[s][2] = gi[s][2] * bb[s][0] + gi[s][4] * bb[s][1] + gi[s][5] * bb[s][2];
-    }
 }
 
 }  // namespace gks
