@@ -420,10 +420,10 @@ __global__ void __launch_bounds__(kBlock) k_stage2(DevMesh m, const T *__restric
 // per (cell, component), and a gather over the transposed stencil.  All
 // gathers run in a fixed order: no atomics, bitwise reproducible.
 
-constexpr int kAccB = 47;  // accumulator cotangents per Gauss point (FluxAccB, Prandtl slots included)
+constexpr int kAccB = 47;  // accumulator cotangents per Gauss point (slots of AccSlot, Prandtl slots included)
 
 struct AdjWork {
-    double *abuf;   // [47][4F]   accumulator cotangents per Gauss point
+    double *abuf;   // [47][4F]   accumulator cotangents per Gauss point (slot-major)
     double *cbf;    // [F][2][50] coefficient cotangents per face side
     double *cbc;    // [N][50]    per cell
     double *dbar;   // [5][nnz]   cotangents of the stencil differences Q_k - Q_0
@@ -446,67 +446,6 @@ static size_t adj_layout(int64_t n, int64_t nf, int64_t nnz, AdjWork *w, char *b
            *ls = take(8 * 5 * n), *vj = take(8 * 5 * n), *co = take(8 * 50 * n);
     if (w) *w = AdjWork{ab, cbf, cbc, dbar, own, ls, vj, co};
     return off;
-}
-
-// pack / unpack the accumulator cotangents of one Gauss point ([47][4F], SoA)
-template <bool PR>
-__device__ __forceinline__ void accb_store(const FluxAccB<double, PR> &A, double *__restrict__ buf, size_t stride, size_t t)
-{
-    int q = 0;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) buf[(q + j) * stride + t] = A.q0[j];
-    q += 5;
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-#pragma unroll
-        for (int j = 0; j < 5; ++j) buf[(q + 5 * m + j) * stride + t] = A.bab[m][j];
-    q += 15;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        buf[(q + j) * stride + t] = A.Mh[j];
-        buf[(q + 5 + j) * stride + t] = A.Mha[j];
-        buf[(q + 10 + j) * stride + t] = A.MhA[j];
-    }
-    q += 15;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        buf[(q + j) * stride + t] = PR ? A.Wha[PR ? j : 0] : 0.0;
-        buf[(q + 5 + j) * stride + t] = PR ? A.WhA[PR ? j : 0] : 0.0;
-    }
-    q += 10;
-    buf[(q + 0) * stride + t] = A.p[0];
-    buf[(q + 1) * stride + t] = A.p[1];
-}
-
-template <bool PR>
-__device__ __forceinline__ void accb_load(FluxAccB<double, PR> &A, const double *__restrict__ buf, size_t stride, size_t t)
-{
-    int q = 0;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) A.q0[j] = buf[(q + j) * stride + t];
-    q += 5;
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-#pragma unroll
-        for (int j = 0; j < 5; ++j) A.bab[m][j] = buf[(q + 5 * m + j) * stride + t];
-    q += 15;
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        A.Mh[j] = buf[(q + j) * stride + t];
-        A.Mha[j] = buf[(q + 5 + j) * stride + t];
-        A.MhA[j] = buf[(q + 10 + j) * stride + t];
-    }
-    q += 15;
-    if constexpr (PR) {
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            A.Wha[j] = buf[(q + j) * stride + t];
-            A.WhA[j] = buf[(q + 5 + j) * stride + t];
-        }
-    }
-    q += 10;
-    A.p[0] = buf[(q + 0) * stride + t];
-    A.p[1] = buf[(q + 1) * stride + t];
 }
 
 // reverse of the flux, part 1 (lane per face Gauss point): both half-space passes forward,
@@ -571,10 +510,7 @@ __global__ void __launch_bounds__(kBlock) k_flux_adj_a(DevMesh m, const double *
             Fb[5 * s + 1 + k] =
                 area * (outb[5 * s + 1] * n3[k][0] + outb[5 * s + 2] * n3[k][1] + outb[5 * s + 3] * n3[k][2]);
     }
-    FluxAccB<double, PR> Ab;
-    accb_zero(Ab);
-    finish_flux_b<double, PR>(A, dt, fp, Fb, Ab);
-    accb_store<PR>(Ab, abuf, (size_t)nf4, (size_t)t);
+    finish_flux_b<double, PR>(A, dt, fp, Fb, [&](int slot, double v) { abuf[(size_t)slot * nf4 + t] = v; });
 }
 
 // reverse of the flux, part 2 (lane per face Gauss point and side): the reverse of that
@@ -604,14 +540,13 @@ __global__ void __launch_bounds__(kBlock) k_flux_adj_b(DevMesh m, const double *
     load_cell(coeff + (size_t)50 * cell, c);
     double q[5], dq[3][5];
     side_state(c, nullptr, X, Y, Z, n3, q, dq);
-    FluxAccB<double, PR> Ab;
-    accb_load<PR>(Ab, abuf, (size_t)nf4, tg);
     double qb[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, dqb[3][5];
 #pragma unroll
     for (int mm = 0; mm < 3; ++mm)
 #pragma unroll
         for (int j = 0; j < 5; ++j) dqb[mm][j] = 0.0;
-    side_pass_b<double, PR>(q, dq, side ? -1.0 : 1.0, fp, Ab, side, qb, dqb);
+    side_pass_b<double, PR>(q, dq, side ? -1.0 : 1.0, fp, [&](int slot) { return abuf[(size_t)slot * nf4 + tg]; }, side,
+                            qb, dqb);
     double cb[50];
 #pragma unroll
     for (int j = 0; j < 50; ++j) cb[j] = 0.0;

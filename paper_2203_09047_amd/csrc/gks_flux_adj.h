@@ -336,14 +336,38 @@ __host__ __device__ __forceinline__ void accb_zero(FluxAccB<T, PR> &A)
     A.p[0] = A.p[1] = T(0);
 }
 
-// reverse of side_pass: accumulator cotangents -> q_b, dq_b.  One moment set M
-// holds the half-space u moments while the half-space accumulations are
-// reversed, then the full-space ones; v, w and internal moments (and their
-// cotangents) are shared by both.
+// positions of the accumulator cotangents, in the member order of FluxAccB
+enum AccSlot { kSlotQ0 = 0, kSlotBab = 5, kSlotMh = 20, kSlotMha = 25, kSlotMhA = 30, kSlotWha = 35, kSlotWhA = 40,
+               kSlotP = 45 };
+
 template <typename T, bool PR>
-__host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, const FluxParams<T> &fp,
-                                     const FluxAccB<T, PR> &Ab, int side, T qb[5], T dqb[3][5])
+__host__ __device__ __forceinline__ T &accb_slot(FluxAccB<T, PR> &A, int s)
 {
+    if (s < kSlotBab) return A.q0[s];
+    if (s < kSlotMh) return A.bab[(s - kSlotBab) / 5][(s - kSlotBab) % 5];
+    if (s < kSlotMha) return A.Mh[s - kSlotMh];
+    if (s < kSlotMhA) return A.Mha[s - kSlotMha];
+    if (s < kSlotWha) return A.MhA[s - kSlotMhA];
+    if constexpr (PR) {
+        if (s < kSlotWhA) return A.Wha[s - kSlotWha];
+        if (s < kSlotP) return A.WhA[s - kSlotWhA];
+    }
+    return A.p[s - kSlotP];
+}
+
+// reverse of side_pass: accumulator cotangents (read through get(slot), each
+// once, where it is used) -> q_b, dq_b.  One moment set M holds the half-space
+// u moments while the half-space accumulations are reversed, then the
+// full-space ones; v, w and internal moments (and their cotangents) are shared
+// by both.
+template <typename T, bool PR, typename Get>
+__host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, const FluxParams<T> &fp, Get get, int side,
+                                     T qb[5], T dqb[3][5])
+{
+    auto ld = [&](int slot, T o[5]) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) o[j] = get(slot + j);
+    };
     const T K = fp.K;
     T rho, U, V, W, lam, p;
     to_prim(q, fp.gamma, rho, U, V, W, lam, p);
@@ -377,45 +401,52 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
         Avb[j] = T(0);
         ab[0][j] = ab[1][j] = ab[2][j] = T(0);
     }
-    T t[5], s[5];
+    T t[5], s[5], g[5];
     P<0, 0, 0>(M, t);
-    rhob += dot5(Ab.q0, t);
+    ld(kSlotQ0, g);
+    rhob += dot5(g, t);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = rho * Ab.q0[j];
+    for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
     P_b<0, 0, 0>(M, s, B);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         Pa<0, 0, 0>(M, a[m], t);
-        rhob += dot5(Ab.bab[m], t);
+        ld(kSlotBab + 5 * m, g);
+        rhob += dot5(g, t);
 #pragma unroll
-        for (int j = 0; j < 5; ++j) s[j] = rho * Ab.bab[m][j];
+        for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
         Pa_b<0, 0, 0>(M, a[m], s, B, ab[m]);
     }
     P<1, 0, 0>(M, t);
-    rhob += dot5(Ab.Mh, t);
+    ld(kSlotMh, g);
+    rhob += dot5(g, t);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = rho * Ab.Mh[j];
+    for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
     P_b<1, 0, 0>(M, s, B);
     Padv<1>(M, a, t);
-    rhob += dot5(Ab.Mha, t);
+    ld(kSlotMha, g);
+    rhob += dot5(g, t);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = rho * Ab.Mha[j];
+    for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
     Padv_b<1>(M, a, s, B, ab);
     Pa<1, 0, 0>(M, Av, t);
-    rhob += dot5(Ab.MhA, t);
+    ld(kSlotMhA, g);
+    rhob += dot5(g, t);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = rho * Ab.MhA[j];
+    for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
     Pa_b<1, 0, 0>(M, Av, s, B, Avb);
     if constexpr (PR) {
         Padv<0>(M, a, t);
-        rhob += dot5(Ab.Wha, t);
+        ld(kSlotWha, g);
+        rhob += dot5(g, t);
 #pragma unroll
-        for (int j = 0; j < 5; ++j) s[j] = rho * Ab.Wha[j];
+        for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
         Padv_b<0>(M, a, s, B, ab);
         Pa<0, 0, 0>(M, Av, t);
-        rhob += dot5(Ab.WhA, t);
+        ld(kSlotWhA, g);
+        rhob += dot5(g, t);
 #pragma unroll
-        for (int j = 0; j < 5; ++j) s[j] = rho * Ab.WhA[j];
+        for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
         Pa_b<0, 0, 0>(M, Av, s, B, Avb);
     }
     // half-space u moments done: their cotangents go to U and lambda, then the full set returns
@@ -450,7 +481,7 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
     }
     mom_full_u_b(M, B, U, lam, Ub, lamb);
     mom_common_b(M, B, V, W, lam, K, Vb, Wb, lamb);
-    to_prim_b(q, fp.gamma, rhob, Ub, Vb, Wb, lamb, Ab.p[side], qb);
+    to_prim_b(q, fp.gamma, rhob, Ub, Vb, Wb, lamb, get(kSlotP + side), qb);
 }
 
 // T coefficients of the time integrals over [0, d] and their derivatives in tau
@@ -473,10 +504,20 @@ __host__ __device__ __forceinline__ void tcoef(T d, T tau, T Tc[5], T dT[5])
     dT[4] = T(4) * tau * om + T(2) * tau * tau * dom - d * eta - tau * d * deta;
 }
 
-// reverse of finish_flux: out_b -> accumulator cotangents
-template <typename T, bool PR>
+/*
+ * Reverse of finish_flux: out_b -> accumulator cotangents, each handed to
+ * put(slot, value) once, as soon as it is final (slots of AccSlot; the
+ * Prandtl slots only when PR).
+ *
+ * The flux at each of the two integration lengths is a sum of coefficient x
+ * vector terms (g_0 moment vectors with r_0 T_1..T_3, accumulators with
+ * T_4, T_5, tau T_4; with PR the same for the heat-flux vector W), so the
+ * cotangents of the coefficients are dot products of the flux cotangents
+ * with one vector at a time: no vector stays live after its dot products.
+ */
+template <typename T, bool PR, typename Put>
 __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const FluxParams<T> &fp, const T outb[10],
-                                       FluxAccB<T, PR> &Ab)
+                                       Put put)
 {
     const T K = fp.K;
     T r0, U0, V0, W0, lam0, p0;
@@ -484,122 +525,156 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
     Mom<T> G;
     mom_common(G, V0, W0, lam0, K);
     mom_full_u(G, U0, lam0);
-    T ab[3][5], Av[5], bm[3][5], bA[5];
     const T ir0 = T(1) / r0;
+    T ab[3][5], Av[5];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
+        T bm[5];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) bm[m][j] = A.bab[m][j] * ir0;
-        slope_solve(bm[m], U0, V0, W0, lam0, K, ab[m]);
+        for (int j = 0; j < 5; ++j) bm[j] = A.bab[m][j] * ir0;
+        slope_solve(bm, U0, V0, W0, lam0, K, ab[m]);
     }
-    Padv<0>(G, ab, bA);
+    {
+        T bA[5];
+        Padv<0>(G, ab, bA);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
-    slope_solve(bA, U0, V0, W0, lam0, K, Av);
+        for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
+        slope_solve(bA, U0, V0, W0, lam0, K, Av);
+    }
     const T dp = (A.p[0] - A.p[1]) / (A.p[0] + A.p[1]);
     const T adp = dp < T(0) ? -dp : dp;
     const T tau = fp.viscous ? fp.mu / p0 + fp.tau_C * adp * dt : fp.tau_eps * dt + fp.tau_C * adp * dt;
-    T M0[5], Ma[5], MA[5];
-    P<1, 0, 0>(G, M0);
-    Padv<1>(G, ab, Ma);
-    Pa<1, 0, 0>(G, Av, MA);
-    T W0m[PR ? 5 : 1], Wam[PR ? 5 : 1], WAm[PR ? 5 : 1];
-    if constexpr (PR) {
-        P<0, 0, 0>(G, W0m);
-        Padv<0>(G, ab, Wam);
-        Pa<0, 0, 0>(G, Av, WAm);
-    }
-    // out = combination of F(dt/2), F(dt)
+    // time coefficients of F(dt/2) (s = 0) and F(dt) (s = 1), their tau derivatives, and the
+    // cotangents of F(dt/2), F(dt) from out = (4 F(dt/2) - F(dt)) / dt, 4 (F(dt) - 2 F(dt/2)) / dt^2
+    T Tc[2][5], dT[2][5], Fb[2][5];
+    tcoef(T(0.5) * dt, tau, Tc[0], dT[0]);
+    tcoef(dt, tau, Tc[1], dT[1]);
     const T idt = T(1) / dt;
-    T Fdb[2][5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
-        Fdb[0][j] = T(4) * idt * outb[j] - T(8) * idt * idt * outb[5 + j];
-        Fdb[1][j] = -idt * outb[j] + T(4) * idt * idt * outb[5 + j];
+        Fb[0][j] = T(4) * idt * outb[j] - T(8) * idt * idt * outb[5 + j];
+        Fb[1][j] = -idt * outb[j] + T(4) * idt * idt * outb[5 + j];
     }
-    T r0b = T(0), taub = T(0), U0b = T(0), V0b = T(0), W0b = T(0), lam0b = T(0), p0b = T(0);
-    T M0b[5], Mab[5], MAb[5], W0mb[5], Wamb[5], WAmb[5];
+    // Prandtl correction F_4 += kap q2, q2 = e . F - U0 e . W (uncorrected F): the cotangent of
+    // the uncorrected F gains q2b e, that of W is w e with w = -U0 q2b
+    const T U2 = U0 * U0 + V0 * V0 + W0 * W0;
+    const T e[5] = {U2, T(-2) * U0, T(-2) * V0, T(-2) * W0, T(2)};
+    T q2b[2] = {T(0), T(0)}, w[2] = {T(0), T(0)};
+    if constexpr (PR) {
+        const T kap = (T(1) / fp.Pr - T(1)) * T(0.5);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) M0b[j] = Mab[j] = MAb[j] = W0mb[j] = Wamb[j] = WAmb[j] = T(0);
+        for (int s = 0; s < 2; ++s) {
+            q2b[s] = kap * Fb[s][4];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        const T d = s == 0 ? T(0.5) * dt : dt;
-        T Tc[5], dT[5], Tb[5] = {T(0), T(0), T(0), T(0), T(0)};
-        tcoef(d, tau, Tc, dT);
-        T F[5];
-#pragma unroll
-        for (int j = 0; j < 5; ++j)
-            F[j] = r0 * (Tc[0] * M0[j] + Tc[1] * Ma[j] + Tc[2] * MA[j]) + Tc[3] * A.Mh[j] - Tc[4] * A.Mha[j] -
-                   tau * Tc[3] * A.MhA[j];
-        T Fb[5] = {Fdb[s][0], Fdb[s][1], Fdb[s][2], Fdb[s][3], Fdb[s][4]};
-        if constexpr (PR) {
-            T Wv[5];
-#pragma unroll
-            for (int j = 0; j < 5; ++j)
-                Wv[j] = r0 * (Tc[0] * W0m[j] + Tc[1] * Wam[j] + Tc[2] * WAm[j]) + Tc[3] * A.q0[j] - Tc[4] * A.Wha[j] -
-                        tau * Tc[3] * A.WhA[j];
-            const T U2 = U0 * U0 + V0 * V0 + W0 * W0;
-            const T Y = T(2) * Wv[4] - T(2) * (U0 * Wv[1] + V0 * Wv[2] + W0 * Wv[3]) + U2 * Wv[0];
-            const T q2b = (T(1) / fp.Pr - T(1)) * T(0.5) * Fdb[s][4];
-            Fb[4] += T(2) * q2b;
-            Fb[1] += T(-2) * U0 * q2b;
-            Fb[2] += T(-2) * V0 * q2b;
-            Fb[3] += T(-2) * W0 * q2b;
-            Fb[0] += U2 * q2b;
-            U0b += q2b * (T(-2) * F[1] + T(2) * U0 * F[0] - Y - U0 * (T(-2) * Wv[1] + T(2) * U0 * Wv[0]));
-            V0b += q2b * (T(-2) * F[2] + T(2) * V0 * F[0] - U0 * (T(-2) * Wv[2] + T(2) * V0 * Wv[0]));
-            W0b += q2b * (T(-2) * F[3] + T(2) * W0 * F[0] - U0 * (T(-2) * Wv[3] + T(2) * W0 * Wv[0]));
-            T Wvb[5];
-            Wvb[4] = T(-2) * U0 * q2b;
-            Wvb[1] = T(2) * U0 * U0 * q2b;
-            Wvb[2] = T(2) * U0 * V0 * q2b;
-            Wvb[3] = T(2) * U0 * W0 * q2b;
-            Wvb[0] = -U0 * U2 * q2b;
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                r0b += Wvb[j] * (Tc[0] * W0m[j] + Tc[1] * Wam[j] + Tc[2] * WAm[j]);
-                Tb[0] += r0 * Wvb[j] * W0m[j];
-                Tb[1] += r0 * Wvb[j] * Wam[j];
-                Tb[2] += r0 * Wvb[j] * WAm[j];
-                Tb[3] += Wvb[j] * (A.q0[j] - tau * A.WhA[j]);
-                Tb[4] += -Wvb[j] * A.Wha[j];
-                taub += -Tc[3] * Wvb[j] * A.WhA[j];
-                W0mb[j] += r0 * Tc[0] * Wvb[j];
-                Wamb[j] += r0 * Tc[1] * Wvb[j];
-                WAmb[j] += r0 * Tc[2] * Wvb[j];
-                Ab.q0[j] += Tc[3] * Wvb[j];
-                Ab.Wha[j] += -Tc[4] * Wvb[j];
-                Ab.WhA[j] += -tau * Tc[3] * Wvb[j];
-            }
+            for (int j = 0; j < 5; ++j) Fb[s][j] += q2b[s] * e[j];
+            w[s] = -U0 * q2b[s];
         }
+    }
+    // accumulator cotangents that are final already
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const T mh = Tc[0][3] * Fb[0][j] + Tc[1][3] * Fb[1][j];
+        put(kSlotMh + j, mh);
+        put(kSlotMha + j, -(Tc[0][4] * Fb[0][j] + Tc[1][4] * Fb[1][j]));
+        put(kSlotMhA + j, -tau * mh);
+    }
+    if constexpr (PR) {
+        const T c3 = Tc[0][3] * w[0] + Tc[1][3] * w[1], c4 = Tc[0][4] * w[0] + Tc[1][4] * w[1];
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            r0b += Fb[j] * (Tc[0] * M0[j] + Tc[1] * Ma[j] + Tc[2] * MA[j]);
-            Tb[0] += r0 * Fb[j] * M0[j];
-            Tb[1] += r0 * Fb[j] * Ma[j];
-            Tb[2] += r0 * Fb[j] * MA[j];
-            Tb[3] += Fb[j] * (A.Mh[j] - tau * A.MhA[j]);
-            Tb[4] += -Fb[j] * A.Mha[j];
-            taub += -Tc[3] * Fb[j] * A.MhA[j];
-            M0b[j] += r0 * Tc[0] * Fb[j];
-            Mab[j] += r0 * Tc[1] * Fb[j];
-            MAb[j] += r0 * Tc[2] * Fb[j];
-            Ab.Mh[j] += Tc[3] * Fb[j];
-            Ab.Mha[j] += -Tc[4] * Fb[j];
-            Ab.MhA[j] += -tau * Tc[3] * Fb[j];
+            put(kSlotWha + j, -c4 * e[j]);
+            put(kSlotWhA + j, -tau * c3 * e[j]);
         }
+    }
+    // coefficient cotangents Tb[s][k], tau, r0; with PR the parts of F and W that q2's
+    // explicit velocity dependence needs
+    T Tb[2][5], taub = T(0), r0b = T(0);
+    T Fs[2][4], Ws[2][4], eW[2] = {T(0), T(0)};
 #pragma unroll
-        for (int c = 0; c < 5; ++c) taub += Tb[c] * dT[c];
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            Tb[s][k] = T(0);
+            if (k < 4) Fs[s][k] = Ws[s][k] = T(0);
+        }
+    // F term coef_s X with coef_s = cs * Tc[s][k]: Tb[s][k] += cs Fb_s . X
+    auto fterm = [&](const T X[5], int k, T cs) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            Tb[s][k] += cs * dot5(Fb[s], X);
+            if constexpr (PR) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) Fs[s][i] += cs * Tc[s][k] * X[i];
+            }
+        }
+    };
+    // W term coef_s Y, coefficient cotangent w_s e . Y
+    auto wterm = [&](const T Y[5], int k, T cs) {
+        const T eY = dot5(e, Y);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            Tb[s][k] += cs * w[s] * eY;
+            eW[s] += cs * Tc[s][k] * eY;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Ws[s][i] += cs * Tc[s][k] * Y[i];
+        }
+    };
+    {
+        T X[5];
+        P<1, 0, 0>(G, X);
+        fterm(X, 0, r0);
+        r0b += Tc[0][0] * dot5(Fb[0], X) + Tc[1][0] * dot5(Fb[1], X);
+        Padv<1>(G, ab, X);
+        fterm(X, 1, r0);
+        r0b += Tc[0][1] * dot5(Fb[0], X) + Tc[1][1] * dot5(Fb[1], X);
+        Pa<1, 0, 0>(G, Av, X);
+        fterm(X, 2, r0);
+        r0b += Tc[0][2] * dot5(Fb[0], X) + Tc[1][2] * dot5(Fb[1], X);
+        if constexpr (PR) {
+            P<0, 0, 0>(G, X);
+            wterm(X, 0, r0);
+            r0b += (Tc[0][0] * w[0] + Tc[1][0] * w[1]) * dot5(e, X);
+            Padv<0>(G, ab, X);
+            wterm(X, 1, r0);
+            r0b += (Tc[0][1] * w[0] + Tc[1][1] * w[1]) * dot5(e, X);
+            Pa<0, 0, 0>(G, Av, X);
+            wterm(X, 2, r0);
+            r0b += (Tc[0][2] * w[0] + Tc[1][2] * w[1]) * dot5(e, X);
+        }
+    }
+    fterm(A.Mh, 3, T(1));
+    fterm(A.Mha, 4, T(-1));
+    fterm(A.MhA, 3, -tau);
+    taub += -(Tc[0][3] * dot5(Fb[0], A.MhA) + Tc[1][3] * dot5(Fb[1], A.MhA));
+    if constexpr (PR) {
+        wterm(A.q0, 3, T(1));
+        wterm(A.Wha, 4, T(-1));
+        wterm(A.WhA, 3, -tau);
+        taub += -(Tc[0][3] * w[0] + Tc[1][3] * w[1]) * dot5(e, A.WhA);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) taub += Tb[s][k] * dT[s][k];
+    T U0b = T(0), V0b = T(0), W0b = T(0), lam0b = T(0), p0b = T(0);
+    if constexpr (PR) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            U0b += q2b[s] * (T(-2) * Fs[s][1] + T(2) * U0 * Fs[s][0] - eW[s] -
+                             U0 * (T(-2) * Ws[s][1] + T(2) * U0 * Ws[s][0]));
+            V0b += q2b[s] * (T(-2) * Fs[s][2] + T(2) * V0 * Fs[s][0] - U0 * (T(-2) * Ws[s][2] + T(2) * V0 * Ws[s][0]));
+            W0b += q2b[s] * (T(-2) * Fs[s][3] + T(2) * W0 * Fs[s][0] - U0 * (T(-2) * Ws[s][3] + T(2) * W0 * Ws[s][0]));
+        }
     }
     // collision time
     {
         const T sp = A.p[0] + A.p[1];
         const T dpb = fp.tau_C * dt * sgn_t(dp) * taub;
-        Ab.p[0] += dpb * T(2) * A.p[1] / (sp * sp);
-        Ab.p[1] += -dpb * T(2) * A.p[0] / (sp * sp);
+        put(kSlotP + 0, dpb * T(2) * A.p[1] / (sp * sp));
+        put(kSlotP + 1, -dpb * T(2) * A.p[0] / (sp * sp));
         if (fp.viscous) p0b += -fp.mu / (p0 * p0) * taub;
     }
-    // moment vectors of g0
+    // moment vectors of g0: cotangents r0 (T_k(dt/2) Fb_0 + T_k(dt) Fb_1), and r0 c_k e for W
     MomB<T> Bg;
     momb_zero(Bg);
     T abb[3][5], Avb[5];
@@ -608,34 +683,68 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         Avb[j] = T(0);
         abb[0][j] = abb[1][j] = abb[2][j] = T(0);
     }
-    P_b<1, 0, 0>(G, M0b, Bg);
-    Padv_b<1>(G, ab, Mab, Bg, abb);
-    Pa_b<1, 0, 0>(G, Av, MAb, Bg, Avb);
-    if constexpr (PR) {
-        P_b<0, 0, 0>(G, W0mb, Bg);
-        Padv_b<0>(G, ab, Wamb, Bg, abb);
-        Pa_b<0, 0, 0>(G, Av, WAmb, Bg, Avb);
+    {
+        T ob[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) ob[j] = r0 * (Tc[0][0] * Fb[0][j] + Tc[1][0] * Fb[1][j]);
+        P_b<1, 0, 0>(G, ob, Bg);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) ob[j] = r0 * (Tc[0][1] * Fb[0][j] + Tc[1][1] * Fb[1][j]);
+        Padv_b<1>(G, ab, ob, Bg, abb);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) ob[j] = r0 * (Tc[0][2] * Fb[0][j] + Tc[1][2] * Fb[1][j]);
+        Pa_b<1, 0, 0>(G, Av, ob, Bg, Avb);
+        if constexpr (PR) {
+            T c = r0 * (Tc[0][0] * w[0] + Tc[1][0] * w[1]);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) ob[j] = c * e[j];
+            P_b<0, 0, 0>(G, ob, Bg);
+            c = r0 * (Tc[0][1] * w[0] + Tc[1][1] * w[1]);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) ob[j] = c * e[j];
+            Padv_b<0>(G, ab, ob, Bg, abb);
+            c = r0 * (Tc[0][2] * w[0] + Tc[1][2] * w[1]);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) ob[j] = c * e[j];
+            Pa_b<0, 0, 0>(G, Av, ob, Bg, Avb);
+        }
     }
     // Av = solve(-Padv0(G, ab))
-    T bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
-    slope_solve_b(bA, U0, V0, W0, lam0, K, Av, Avb, bAb, U0b, V0b, W0b, lam0b);
+    {
+        T bA[5], bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
+        Padv<0>(G, ab, bA);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) bAb[j] = -bAb[j];
-    Padv_b<0>(G, ab, bAb, Bg, abb);
+        for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
+        slope_solve_b(bA, U0, V0, W0, lam0, K, Av, Avb, bAb, U0b, V0b, W0b, lam0b);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) bAb[j] = -bAb[j];
+        Padv_b<0>(G, ab, bAb, Bg, abb);
+    }
     // ab[m] = solve(bab[m] / r0)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        T bmb[5] = {T(0), T(0), T(0), T(0), T(0)};
-        slope_solve_b(bm[m], U0, V0, W0, lam0, K, ab[m], abb[m], bmb, U0b, V0b, W0b, lam0b);
+        T bm[5], bmb[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int j = 0; j < 5; ++j) bm[j] = A.bab[m][j] * ir0;
+        slope_solve_b(bm, U0, V0, W0, lam0, K, ab[m], abb[m], bmb, U0b, V0b, W0b, lam0b);
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            Ab.bab[m][j] += bmb[j] * ir0;
-            r0b += -bmb[j] * bm[m][j] * ir0;
+            put(kSlotBab + 5 * m + j, bmb[j] * ir0);
+            r0b += -bmb[j] * bm[j] * ir0;
         }
     }
     mom_full_u_b(G, Bg, U0, lam0, U0b, lam0b);
     mom_common_b(G, Bg, V0, W0, lam0, K, V0b, W0b, lam0b);
-    to_prim_b(A.q0, fp.gamma, r0b, U0b, V0b, W0b, lam0b, p0b, Ab.q0);
+    // g_0's own conserved variables, plus (PR) their appearance in W with T_4
+    T q0b[5];
+    {
+        const T c3 = PR ? Tc[0][3] * w[0] + Tc[1][3] * w[1] : T(0);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) q0b[j] = c3 * e[j];
+    }
+    to_prim_b(A.q0, fp.gamma, r0b, U0b, V0b, W0b, lam0b, p0b, q0b);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) put(kSlotQ0 + j, q0b[j]);
 }
 
 // reverse of gp_flux: out_b -> cotangents of both local-frame states and their derivatives
@@ -650,9 +759,10 @@ __host__ __device__ void gp_flux_b(const T ql[5], const T dql[3][5], const T qr[
     side_pass<T, PR>(qr, dqr, T(-1), fp, A, 1);
     FluxAccB<T, PR> Ab;
     accb_zero(Ab);
-    finish_flux_b<T, PR>(A, dt, fp, outb, Ab);
-    side_pass_b<T, PR>(qr, dqr, T(-1), fp, Ab, 1, qrb, dqrb);
-    side_pass_b<T, PR>(ql, dql, T(1), fp, Ab, 0, qlb, dqlb);
+    finish_flux_b<T, PR>(A, dt, fp, outb, [&](int slot, T v) { accb_slot(Ab, slot) = v; });
+    auto get = [&](int slot) { return accb_slot(Ab, slot); };
+    side_pass_b<T, PR>(qr, dqr, T(-1), fp, get, 1, qrb, dqrb);
+    side_pass_b<T, PR>(ql, dql, T(1), fp, get, 0, qlb, dqlb);
 }
 
 // reverse of side_state: local-frame state cotangents -> coefficient cotangents cb[50] (accumulated)
