@@ -38,9 +38,13 @@ def log(*a):
 def algorithmic_bytes(host, es):
     """Compulsory HBM bytes per launch of each kernel (es = bytes of the reduced-precision type)."""
     n, nf, ns = host.n, host.n_faces, host.n_stencil
-    nsc = host.n_subcoef
+    nsc = host.n_subcoef  # sub-stencil entries
     ncf = host.n_cellfaces
-    recon = 40 * n + 4 * n + 8 * ns + 9 * es * ns + 3 * es * ns + 6 * es * nsc + n + 8 * n + 48 * n + 50 * es * n
+    # own cell averages (the gathered ones are the same array, read once), stencil pointers and member
+    # cells, pseudo-inverse rows, sub-stencil list pointers / positions / 3-vectors, M, |Omega|^(2/3),
+    # second moments, coefficients written
+    recon = (40 * n + 4 * n + 4 * ns + 9 * es * ns + 32 * n + nsc + 3 * es * nsc + n + 8 * n + 48 * n
+             + 50 * es * n)
     flux = 8 * nf + 9 * 4 * 8 * nf + 50 * es * n + 10 * es * nf + (40 * n if es == 4 else 0)
     stage1 = 4 * n + 4 * ncf + 10 * es * nf + 8 * n + 40 * n + 40 * n + 40 * n
     stage2 = 4 * n + 4 * ncf + 10 * es * nf + 8 * n + 40 * n + 40 * n

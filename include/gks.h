@@ -107,8 +107,8 @@ void gks_host_mesh_free(gks_host_mesh *h);
 
 /*
  * n_cells, n_faces, stencil entries (members of all cells), sub-stencil
- * normal-matrix slots (8 per cell), and the number of members appended by
- * rank growth.
+ * entries (members of all sub-stencils of all cells), and the number of
+ * members appended by rank growth.
  * Any pointer may be NULL.
  */
 gks_status gks_host_mesh_counts(const gks_host_mesh *h, int64_t *n_cells, int64_t *n_faces, int64_t *n_stencil,

@@ -137,11 +137,13 @@ class Oracle:
         if not h:
             raise OracleError(lib.orc_last_error().decode())
         self.h = h
+        self._lib = _load()  # kept for the destructor, which may run at interpreter shutdown
         self.n_faces = int(lib.orc_n_faces(h))
 
     def __del__(self):
-        if getattr(self, "h", None):
-            _load().orc_destroy(self.h)
+        lib = getattr(self, "_lib", None)
+        if lib is not None and getattr(self, "h", None):
+            lib.orc_destroy(self.h)
             self.h = None
 
     # geometry -----------------------------------------------------------

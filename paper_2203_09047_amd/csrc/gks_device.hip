@@ -62,9 +62,17 @@ struct DevMesh {
     const int32_t *st_ptr;  // [n+1]
     const int2 *st_rec;     // members: {cell, sub-stencil membership mask}
     int nnz;                // stencil members
-    const void *pinv;       // [9][nnz] (coefficient-major), FP64 or FP32
-    const void *dsc;        // [3][nnz] scaled member centroid offsets, FP64 or FP32
+    const void *pinv;       // [nnz][9] (member-major), FP64 or FP32
+    const void *dsc;        // [nnz][3] scaled member centroid offsets, FP64 or FP32
     const void *ginv;       // [48][n] inverses of the sub-stencil normal matrices / h, FP64 or FP32
+    const int32_t *st_cell; // [nnz] member cells (as in st_rec)
+    // sub-stencil lists: the members of sub-stencil s of cell i are entries
+    // ss_ptr[8 i + s] .. ss_ptr[8 i + s + 1], each the member's position in the cell's
+    // stencil and B = G_s^{-1} D_k / h, so that b^s = sum B (Q_k - Q_0)
+    const int32_t *ss_ptr;  // [8 n + 1]
+    const uint8_t *ss_loc;  // [nss]
+    const void *ss_B;       // [nss][3], FP64 or FP32
+    int nss;
     // faces
     const int32_t *owner, *nbr;
     const double *fgeo;     // [9][4 nf]
@@ -158,14 +166,22 @@ __global__ void __launch_bounds__(kBlock) k_dt_final(int nb, const double *__res
 // ---------------------------------------------------------------------------
 // K1: WENO reconstruction, one lane per (cell, component)
 // ---------------------------------------------------------------------------
-// Four lanes cooperate on one (cell, conserved component): lane l streams
-// members l, l+4, ... of the cell's stencil, so a cell's 20 lanes read
-// consecutive operator entries and each lane's chain of dependent loads is short;
-// the partial fits are summed over the quad with DPP lane permutations, so every
-// lane of the quad holds bitwise-identical totals (deterministic, no atomics).
+// K1: reconstruction.  Four lanes cooperate on one (cell, conserved component):
+// lane l streams members l, l+4, ... of the cell's stencil for the quadratic
+// fit, so a cell's 20 lanes read consecutive pseudo-inverse entries, and lane l
+// then fits sub-stencils l and l+4 from their member lists.  Partial sums are
+// combined over the quad with DPP lane permutations, so every lane of the quad
+// holds bitwise-identical totals (deterministic, no atomics).
+// ---------------------------------------------------------------------------
 constexpr int kK1Lanes = 4;
 constexpr int kK1CellLanes = 5 * kK1Lanes;
-constexpr int kK1Block = 16 * kK1CellLanes;  // 16 cells, 5 waves
+constexpr int kK1Cells = 16;
+constexpr int kK1Block = kK1Cells * kK1CellLanes;  // 16 cells, 5 waves
+// Staged in LDS per block (the 16 cells' stencil and sub-stencil ranges are
+// contiguous): the members' cell averages and the sub-stencil lists.  A block
+// whose ranges are longer reads them from global memory instead.
+constexpr int kK1Stage = 416;
+constexpr int kK1SubStage = 800;
 
 // DPP lane permutations (VALU, no LDS traffic) of a 32-bit value within a quad of lanes
 template <int CTRL>
@@ -207,11 +223,79 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     const int x = b & 7, j = b >> 3;
     return x * q + (x < r ? x : r) + j;
 }
+// The WENO combination (Eq. weno, Eq. indicator) of one (cell, component) held by a
+// quad of lanes: a[9] is the same on every lane, bs[h] is this lane's sub-stencil
+// l + 4 h.  The indicator differences, the nonlinear weights and the linear parts
+// of the sub-stencils are summed over the quad; every lane returns the same c[10].
 template <typename T>
-__global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3))) k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff,
+__device__ __forceinline__ void weno_combine_quad(const T a[9], const T bs[2][3], int l, int M, T v23, const T S[6],
+                                                  double q0, bool with_q0, const WenoParams &wp, T c[10])
+{
+    const T H[3][3] = {{T(2) * a[3], a[4], a[5]}, {a[4], T(2) * a[6], a[7]}, {a[5], a[7], T(2) * a[8]}};
+    const T Sm[3][3] = {{S[0], S[1], S[2]}, {S[1], S[3], S[4]}, {S[2], S[4], S[5]}};
+    T beta0 = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        T quad = T(0);
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) quad += H[d][p] * Sm[p][q] * H[d][q];
+        beta0 += a[d] * a[d] + quad;
+    }
+    const T sec = T(4) * (a[3] * a[3] + a[6] * a[6] + a[8] * a[8]) + a[4] * a[4] + a[5] * a[5] + a[7] * a[7];
+    beta0 = v23 * beta0 + v23 * v23 * sec;
+    const T gm = (T)wp.gm, g0 = T(1) - gm * T(M), eps = (T)wp.eps, pw = (T)wp.p;
+    T beta[2], tw = T(0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        beta[h] = v23 * (bs[h][0] * bs[h][0] + bs[h][1] * bs[h][1] + bs[h][2] * bs[h][2]);
+        if (l + 4 * h < M) tw += wabs(beta0 - beta[h]);
+    }
+    tw = quad_sum(tw) / T(M);
+    T w0, ws[2];
+    if (wp.force_linear) {
+        w0 = g0;
+        ws[0] = ws[1] = gm;
+    } else {
+        w0 = g0 * (T(1) + wpow(tw / (beta0 + eps), pw));
+#pragma unroll
+        for (int h = 0; h < 2; ++h) ws[h] = gm * (T(1) + wpow(tw / (beta[h] + eps), pw));
+    }
+    T wsum = T(0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (l + 4 * h < M) wsum += ws[h];
+    const T isum = T(1) / (w0 + quad_sum(wsum));
+    const T f0 = w0 * isum / g0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) c[1 + j] = f0 * a[j];
+    const T sub0 = f0 * gm;
+    T lin[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        if (l + 4 * h < M) {
+            const T fs = ws[h] * isum - sub0;
+            lin[0] += fs * bs[h][0];
+            lin[1] += fs * bs[h][1];
+            lin[2] += fs * bs[h][2];
+        }
+    c[1] += quad_sum(lin[0]);
+    c[2] += quad_sum(lin[1]);
+    c[3] += quad_sum(lin[2]);
+    const T corr = -(c[4] * S[0] + c[5] * S[1] + c[6] * S[2] + c[7] * S[3] + c[8] * S[4] + c[9] * S[5]);
+    c[0] = with_q0 ? (T)q0 + corr : corr;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff,
                                                           WenoParams wp)
 {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * kK1Block + threadIdx.x;
+    __shared__ double sq[5][kK1Stage];
+    __shared__ T sB[3][kK1SubStage];
+    __shared__ unsigned char sl[kK1SubStage];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int t = blk * kK1Block + threadIdx.x;
     const int n = m.n;
     const int ic = t / kK1CellLanes;
     const int lane = t - kK1CellLanes * ic;
@@ -219,49 +303,68 @@ __global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3
     const int l = lane & 3;
     const bool valid = ic < n;
     const int i = valid ? ic : n - 1;  // tail lanes shadow the last cell and write nothing
+    const T *B = (const T *)m.ss_B;
+    const int cb0 = blk * kK1Cells, cb1 = min(cb0 + kK1Cells, n);
+    const int e0 = m.st_ptr[cb0], e1 = m.st_ptr[cb1];
+    const int s0 = m.ss_ptr[8 * cb0], s1 = m.ss_ptr[8 * cb1];
+    const bool staged = e1 - e0 <= kK1Stage && s1 - s0 <= kK1SubStage;  // uniform over the block
+    if (staged) {
+        // one round of independent loads for the whole block
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += kK1Block) {
+            const int x = m.st_cell[e];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) sq[c][e - e0] = Q[(size_t)c * n + x];
+        }
+        for (int e = s0 + (int)threadIdx.x; e < s1; e += kK1Block) {
+            sl[e - s0] = m.ss_loc[e];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) sB[j][e - s0] = B[(size_t)3 * e + j];
+        }
+        __syncthreads();
+    }
     const T *pinv = (const T *)m.pinv;
-    const T *dsc = (const T *)m.dsc;
-    const int nnz = m.nnz;
     const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
     const double *Qc = Q + (size_t)comp * n;
     const double q0 = Qc[i];
-    T a[9], r[8][3];
+    // Q_k - Q_0 of stencil entry k, in FP64, then rounded to T
+    auto diff = [&](int k) -> T { return (T)((staged ? sq[comp][k - e0] : Qc[m.st_cell[k]]) - q0); };
+    T a[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = T(0);
-#pragma unroll
-    for (int s = 0; s < 8; ++s) r[s][0] = r[s][1] = r[s][2] = T(0);
 #pragma unroll 2
     for (int k = k0 + l; k < k1; k += kK1Lanes) {
-        const int2 rec = m.st_rec[k];
-        const T d = (T)(Qc[rec.x] - q0);
+        const T d = diff(k);
 #pragma unroll
-        for (int j = 0; j < 9; ++j) a[j] += pinv[(size_t)j * nnz + k] * d;
-        const T dx = dsc[k] * d, dy = dsc[(size_t)nnz + k] * d, dz = dsc[(size_t)2 * nnz + k] * d;
-        const unsigned mask = (unsigned)rec.y;
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-            if (mask & (1u << s)) {
-                r[s][0] += dx;
-                r[s][1] += dy;
-                r[s][2] += dz;
-            }
+        for (int j = 0; j < 9; ++j) a[j] += pinv[(size_t)9 * k + j] * d;
     }
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = quad_sum(a[j]);
-    // linear sub-stencil fits: b^m = G_m^{-1} r_m / h (normal equations of the scaled offsets)
-    const T *gip = (const T *)m.ginv;
-    T b[8][3];
+    // linear sub-stencil fits l and l + 4: b^s = sum B (Q_k - Q_0)
+    T bs[2][3];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        T g[6], rs[3] = {quad_sum(r[s][0]), quad_sum(r[s][1]), quad_sum(r[s][2])};
-#pragma unroll
-        for (int q = 0; q < 6; ++q) g[q] = gip[(size_t)(6 * s + q) * n + i];
-        sym3_apply(g, rs, b[s]);
+    for (int h = 0; h < 2; ++h) {
+        bs[h][0] = bs[h][1] = bs[h][2] = T(0);
+        const int p0 = m.ss_ptr[8 * i + l + 4 * h], p1 = m.ss_ptr[8 * i + l + 4 * h + 1];
+        if (staged) {
+            for (int e = p0 - s0; e < p1 - s0; ++e) {
+                const T d = diff(k0 + sl[e]);
+                bs[h][0] += sB[0][e] * d;
+                bs[h][1] += sB[1][e] * d;
+                bs[h][2] += sB[2][e] * d;
+            }
+        } else {
+            for (int e = p0; e < p1; ++e) {
+                const T d = diff(k0 + m.ss_loc[e]);
+                bs[h][0] += B[(size_t)3 * e] * d;
+                bs[h][1] += B[(size_t)3 * e + 1] * d;
+                bs[h][2] += B[(size_t)3 * e + 2] * d;
+            }
+        }
     }
     const T S[6] = {(T)m.m2[i], (T)m.m2[n + i], (T)m.m2[2 * n + i], (T)m.m2[3 * n + i], (T)m.m2[4 * n + i],
                     (T)m.m2[5 * n + i]};
     T c[10];
-    weno_combine<T>(a, b, m.M[i], (T)m.vol23[i], S, q0, sizeof(T) == 8, wp, c);
+    weno_combine_quad<T>(a, bs, l, m.M[i], (T)m.vol23[i], S, q0, sizeof(T) == 8, wp, c);
     // lane l writes entries l, l + 4 and (lanes 0, 1) l + 8 of this component
     T v0 = c[0], v1 = c[4], v2 = c[8];
 #pragma unroll
@@ -603,8 +706,8 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct_adj(DevMesh m, const d
         const int2 rec = m.st_rec[k];
         const double d = Qc[rec.x] - q0;
 #pragma unroll
-        for (int j = 0; j < 9; ++j) a[j] += pinv[(size_t)j * nnz + k] * d;
-        const double dx = dsc[k] * d, dy = dsc[(size_t)nnz + k] * d, dz = dsc[(size_t)2 * nnz + k] * d;
+        for (int j = 0; j < 9; ++j) a[j] += pinv[(size_t)9 * k + j] * d;
+        const double dx = dsc[(size_t)3 * k] * d, dy = dsc[(size_t)3 * k + 1] * d, dz = dsc[(size_t)3 * k + 2] * d;
         const unsigned mask = (unsigned)rec.y;
 #pragma unroll
         for (int s = 0; s < 8; ++s)
@@ -639,7 +742,7 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct_adj(DevMesh m, const d
         const int2 rec = m.st_rec[k];
         double v = 0.0;
 #pragma unroll
-        for (int j = 0; j < 9; ++j) v += pinv[(size_t)j * nnz + k] * ab[j];
+        for (int j = 0; j < 9; ++j) v += pinv[(size_t)9 * k + j] * ab[j];
         double sx = 0.0, sy = 0.0, sz = 0.0;
         const unsigned mask = (unsigned)rec.y;
 #pragma unroll
@@ -649,7 +752,7 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct_adj(DevMesh m, const d
                 sy += rb[s][1];
                 sz += rb[s][2];
             }
-        v += dsc[k] * sx + dsc[(size_t)nnz + k] * sy + dsc[(size_t)2 * nnz + k] * sz;
+        v += dsc[(size_t)3 * k] * sx + dsc[(size_t)3 * k + 1] * sy + dsc[(size_t)3 * k + 2] * sz;
         if (valid) dbar[(size_t)comp * nnz + k] = v;
         sumk += v;
     }
@@ -858,7 +961,11 @@ gks_status gks_host_mesh_counts(const gks_host_mesh *h, int64_t *n_cells, int64_
     if (n_cells) *n_cells = h->h.n;
     if (n_faces) *n_faces = h->h.nf;
     if (n_stencil) *n_stencil = (int64_t)h->h.st_idx.size();
-    if (n_subcoef) *n_subcoef = (int64_t)h->h.ginv.size() / 6;
+    if (n_subcoef) {
+        int64_t nss = 0;
+        for (uint8_t mk : h->h.st_mask) nss += __builtin_popcount((unsigned)mk);
+        *n_subcoef = nss;
+    }
     if (n_grown) *n_grown = h->h.n_grown;
     return GKS_OK;
 }
@@ -935,6 +1042,20 @@ static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *ba
         }
         return out;
     };
+    // host data as stored (row-major), FP64 or FP32
+    auto convert_n = [&](const std::vector<double> &v) {
+        std::vector<char> out(v.size() * es);
+        if (owned)
+            for (size_t o = 0; o < v.size(); ++o) {
+                if (es == 8)
+                    std::memcpy(&out[8 * o], &v[o], 8);
+                else {
+                    const float f = (float)v[o];
+                    std::memcpy(&out[4 * o], &f, 4);
+                }
+            }
+        return out;
+    };
     DevMesh dm{};
     dm.n = (int)n;
     dm.nf = (int)nf;
@@ -956,9 +1077,40 @@ static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *ba
         dm.st_rec = owned ? (const int2 *)put_vec(std::move(rec)) : (const int2 *)put(nullptr, 8 * H.st_idx.size());
     }
     dm.nnz = (int)H.st_idx.size();
-    dm.pinv = put_vec(convert_t(H.pinv, 9));
-    dm.dsc = put_vec(convert_t(H.dsc, 3));
+    dm.pinv = put_vec(convert_n(H.pinv));
+    dm.dsc = put_vec(convert_n(H.dsc));
     dm.ginv = put_vec(convert_t(H.ginv, 48));
+    dm.st_cell = (const int32_t *)put(H.st_idx.data(), 4 * H.st_idx.size());
+    {
+        // sub-stencil lists in slot order, members in stencil order
+        int64_t nss = 0;
+        for (size_t k = 0; k < H.st_mask.size(); ++k) nss += __builtin_popcount((unsigned)H.st_mask[k]);
+        std::vector<char> ptr(owned ? 4 * (8 * n + 1) : 0), loc(owned ? nss : 0);
+        std::vector<double> B(owned ? 3 * nss : 0);
+        if (owned) {
+            int32_t e = 0;
+            for (int64_t i = 0; i < n; ++i) {
+                const double *g = &H.ginv[48 * i];
+                for (int sl = 0; sl < 8; ++sl) {
+                    std::memcpy(&ptr[4 * (8 * i + sl)], &e, 4);
+                    for (int32_t k = H.st_ptr[i]; k < H.st_ptr[i + 1]; ++k) {
+                        if (!(H.st_mask[k] >> sl & 1)) continue;
+                        const double *gs = g + 6 * sl, *D = &H.dsc[3 * k];
+                        loc[e] = (char)(k - H.st_ptr[i]);
+                        B[3 * e + 0] = gs[0] * D[0] + gs[1] * D[1] + gs[2] * D[2];
+                        B[3 * e + 1] = gs[1] * D[0] + gs[3] * D[1] + gs[4] * D[2];
+                        B[3 * e + 2] = gs[2] * D[0] + gs[4] * D[1] + gs[5] * D[2];
+                        ++e;
+                    }
+                }
+            }
+            std::memcpy(&ptr[4 * 8 * n], &e, 4);
+        }
+        dm.ss_ptr = owned ? (const int32_t *)put_vec(std::move(ptr)) : (const int32_t *)put(nullptr, 4 * (8 * n + 1));
+        dm.ss_loc = owned ? (const uint8_t *)put_vec(std::move(loc)) : (const uint8_t *)put(nullptr, nss);
+        dm.ss_B = owned ? put_vec(convert_n(B)) : put(nullptr, es * 3 * nss);
+        dm.nss = (int)nss;
+    }
     dm.owner = (const int32_t *)put(H.owner.data(), 4 * nf);
     dm.nbr = (const int32_t *)put(H.nbr.data(), 4 * nf);
     dm.fgeo = (const double *)put(H.fgeo.data(), 8 * H.fgeo.size());

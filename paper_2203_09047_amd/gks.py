@@ -161,6 +161,7 @@ class HostMesh:
         _check(lib.gks_preprocess(self._nodes.shape[0], _np(self._nodes), self._types.shape[0], _np(self._types),
                                   _np(self._cells), _np(box), int(mesh.periodic), ctypes.byref(h)))
         self.h = h
+        self._lib = lib  # the library that owns h frees it, also at interpreter shutdown
         n, nf, ns, nsc, ng = (ctypes.c_int64() for _ in range(5))
         _check(lib.gks_host_mesh_counts(h, ctypes.byref(n), ctypes.byref(nf), ctypes.byref(ns), ctypes.byref(nsc),
                                         ctypes.byref(ng)))
@@ -194,8 +195,9 @@ class HostMesh:
         return out
 
     def __del__(self):
-        if getattr(self, "h", None):
-            load().gks_host_mesh_free(self.h)
+        lib = getattr(self, "_lib", None)
+        if lib is not None and getattr(self, "h", None):
+            lib.gks_host_mesh_free(self.h)
             self.h = None
 
 
@@ -226,6 +228,7 @@ class Solver:
         _check(lib.gks_init_mesh(host.h, self.P.precision, self._arena_ptr, self.mesh_bytes, self._s(),
                                  ctypes.byref(m)))
         self.m = m
+        self._lib = lib  # the library that owns m destroys it, also at interpreter shutdown
         self.n, self.n_faces = host.n, host.n_faces
         cdt = torch.float64 if self.P.precision == FP64 else torch.float32
         self.coeff_dtype = cdt
@@ -235,8 +238,9 @@ class Solver:
         return ctypes.c_void_p(self.stream.cuda_stream)
 
     def __del__(self):
-        if getattr(self, "m", None):
-            load().gks_destroy_mesh(self.m)
+        lib = getattr(self, "_lib", None)
+        if lib is not None and getattr(self, "m", None):
+            lib.gks_destroy_mesh(self.m)
             self.m = None
 
     # tensors ---------------------------------------------------------------
