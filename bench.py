@@ -14,6 +14,7 @@ the oracle's CPU rate on a bounded sample beside it.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -28,11 +29,72 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# FP64 operations the flux kernel executes per Gauss point (Navier-Stokes, Pr != 1): the hardware
+# counters SQ_INSTS_VALU_FMA_F64 (x 2), _MUL_F64 and _ADD_F64 over one launch at N = 64, divided by
+# the launch's 4 F Gauss points (2298 FMA + 912 MUL + 206 ADD per point).  The source-level count
+# (flux_ops_per_gauss_point) is larger: the compiler folds constant factors and shares products.
+FLUX_FP64_FLOPS_PER_GP = 2 * 2298 + 912 + 206
+# committed HBM counter summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated), valid only for the
+# kernel sources it was measured on
+COUNTERS_JSON = os.path.join(ROOT, "profiles", "hbm_counters_hybrid-N64-tgv.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2203_09047_amd", "csrc", f)
+                  for f in ("gks_device.hip", "gks_flux.h", "gks_flux_adj.h", "gks_weno.h", "gks_internal.h")]
+# rocprofv3 kernel names -> the library's kernel keys
+KERNEL_NAMES = {"k_reconstruct<double>(": "reconstruct", "k_flux<double, true>(": "flux", "k_stage1<double>(": "stage1",
+                "k_stage2<double>(": "stage2", "k_dt_partial(": "timestep", "k_flux_adj_a<true>(": "flux_adj_a",
+                "k_flux_adj_b<true>(": "flux_adj_b", "k_reconstruct_adj(": "reconstruct_adj",
+                "k_cbar_gather(": "cbar_gather", "k_transpose_gather(": "transpose_gather"}
 
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes (read + written) per launch from the committed counter summary; empty once the
+    kernel sources differ from the ones the counters were taken on."""
+    try:
+        with open(COUNTERS_JSON) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return {}
+    if d.get("kernel_source_sha256") != kernel_source_hash():
+        return {}
+    return {k: v["read_bytes"] + v["write_bytes"] for k, v in d["kernels"].items()}
+
+
+def counters_from(fetch_db, write_db):
+    """Counter summary from two rocprofv3 databases (one FETCH_SIZE run, one WRITE_SIZE run, both with
+    --copy-calibration): per-kernel mean KiB per dispatch scaled by what the counter reads for the
+    calibration copies of 1 GiB."""
+    import sqlite3
+
+    def per_kernel(db):
+        con = sqlite3.connect(db)
+        rows = con.execute("select dispatch_id, kernel_name, grid_size, value from counters_collection "
+                           "order by dispatch_id").fetchall()
+        copies = [r[3] for r in rows if r[1] == "__amd_rocclr_copyBuffer" and r[2] == 131072][:3]
+        factor = (1 << 30) / (sum(copies) / len(copies) * 1024.0)
+        acc = {}
+        for _, name, _, v in rows:
+            for frag, key in KERNEL_NAMES.items():
+                if frag in name:
+                    acc.setdefault(key, []).append(v)
+        return factor, {k: sum(v) / len(v) * 1024.0 * factor for k, v in acc.items()}
+
+    ff, rd = per_kernel(fetch_db)
+    wf, wr = per_kernel(write_db)
+    return dict(kernel_source_sha256=kernel_source_hash(), fetch_factor=ff, write_factor=wf,
+                kernels={k: dict(read_bytes=rd[k], write_bytes=wr.get(k, 0.0)) for k in rd})
 
 
 def algorithmic_bytes(host, es):
@@ -81,6 +143,7 @@ def run_gpu(args, mesh, Q0, precision):
     sol.poll()
     q = Q.cpu().numpy()
     assert np.isfinite(q).all()
+    run_gpu.last_q = q
     return host, sol, ms, prof
 
 
@@ -148,7 +211,12 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=20, help="steps of the adjoint/forward ratio (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--counters-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="print the HBM counter summary of two rocprofv3 databases as JSON and exit")
     args = ap.parse_args()
+    if args.counters_from:
+        print(json.dumps(counters_from(*args.counters_from), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built",
               file=sys.stderr)
@@ -197,22 +265,24 @@ def main():
     res["kernels_fp64"] = kern
     bytes64 = algorithmic_bytes(host, 8)
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
-    avg_s = kern[dom]["avg_ms"] * 1e-3
-    # FP64 operations of one Gauss point of the flux kernel (both sides' states, frame, BGK flux with
-    # both time integrals, rotation back), counted by the library from the kernel's own templated body
-    ops = gks.gp_op_count(viscous=True, Pr=0.72)
-    flops_gp = ops["add"] + ops["mul"] + ops["div"]
-    res["flux_ops_per_gauss_point"] = ops
-    if dom == "flux":
-        fl = flops_gp * 4 * host.n_faces
-        achieved = fl / avg_s / 1e12
-        res["roofline"] = dict(kernel=dom, bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS,
-                               unit="TFLOP/s", frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=None)
-    else:
-        b = bytes64[dom]
-        achieved = b / avg_s / 1e9
-        res["roofline"] = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                               frac=achieved / HBM_PEAK_GBS, traffic=None)
+    # source-level FP64 operation count of one Gauss point (informational)
+    res["flux_ops_per_gauss_point"] = gks.gp_op_count(viscous=True, Pr=0.72)
+    traffic = measured_traffic()
+
+    def roofline(k):
+        avg_s = kern[k]["avg_ms"] * 1e-3
+        tr = traffic.get(k)
+        if k == "flux":
+            achieved = FLUX_FP64_FLOPS_PER_GP * 4 * host.n_faces / avg_s / 1e12
+            return dict(kernel=k, bound="alu", achieved=achieved, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=achieved / FP64_VECTOR_PEAK_TFLOPS, traffic=tr)
+        achieved = bytes64[k] / avg_s / 1e9
+        return dict(kernel=k, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=tr)
+
+    res["roofline"] = roofline(dom)
+    res["roofline_kernels"] = {k: roofline(k) for k in ("reconstruct", "flux", "stage1", "stage2") if k in kern}
+    q64 = run_gpu.last_q
     res["hbm_fraction_of_step_fp64"] = sum(bytes64[k] * kern[k]["launches"] for k in kern) / args.steps / (
         ms64 / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS
     if args.adj_steps > 0:
@@ -228,8 +298,12 @@ def main():
         torch.cuda.empty_cache()
         _, sol32, ms32, prof32 = run_gpu(args, mesh, Q0, gks.FP32_MIXED)
         log(f"fp32-mixed: {ms32:.2f} ms {prof32}")
+        q32 = run_gpu.last_q
+        err = (np.abs(q32 - q64).max(axis=1) / np.abs(q64).max(axis=1)).tolist()
         res["fp32_mixed"] = dict(value=n * args.steps / (ms32 * 1e-3), ms_per_step=ms32 / args.steps,
                                  speedup_vs_fp64=ms64 / ms32,
+                                 rel_linf_error_vs_fp64_per_component=err,
+                                 error_after_steps=args.warmup + args.steps,
                                  kernels={k: dict(avg_ms=v[0] / max(v[1], 1), launches=v[1])
                                           for k, v in prof32.items() if v[1]})
     if not args.no_cpu:
