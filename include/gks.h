@@ -97,12 +97,20 @@ void gks_default_params(gks_params *p);
  *   types  [n_cells] int8: 0 tetrahedron, 1 pyramid, 2 prism, 3 hexahedron;
  *   cells  [n_cells][8] int64 node ids in the paper's vertex order, -1 padded;
  *   box    [3] periodic box lengths (the domain is [0,box_x] x [0,box_y] x [0,box_z]);
- *   periodic must be 1 (every face is then shared by exactly two cells).
+ *   periodic must be 1 (every face is then shared by exactly two cells);
+ *   min_big_stencil: 0 keeps the paper's big stencil (face neighbours and
+ *     their face neighbours); k > 0 also grows a big stencil with fewer than
+ *     k members, by the rule used for ill-posed fits (face neighbours of the
+ *     members, in order), to k members where the mesh has them.  The paper's
+ *     rule gives 12-member stencils on some tetrahedra of mixed meshes, on
+ *     which the linear scheme is unstable; 16 is the size it gives a
+ *     tetrahedron whose neighbours share no other cell.
  * All arrays are read only during the call.  Returns GKS_EMESH for a
  * non-conforming mesh and GKS_ESINGULAR when a fit cannot be made well posed.
  */
 gks_status gks_preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, const int8_t *types,
-                          const int64_t *cells, const double *box, int periodic, gks_host_mesh **out);
+                          const int64_t *cells, const double *box, int periodic, int min_big_stencil,
+                          gks_host_mesh **out);
 void gks_host_mesh_free(gks_host_mesh *h);
 
 /*

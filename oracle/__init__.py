@@ -76,7 +76,7 @@ def _load():
         lib = ctypes.CDLL(LIB_PATH)
         vp, i64, dbl, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
         pp = ctypes.POINTER(Params)
-        lib.orc_create.argtypes = [i64, vp, i64, vp, vp, vp, i32]
+        lib.orc_create.argtypes = [i64, vp, i64, vp, vp, vp, i32, i32]
         lib.orc_create.restype = vp
         lib.orc_destroy.argtypes = [vp]
         lib.orc_last_error.restype = ctypes.c_char_p
@@ -123,7 +123,8 @@ class OracleError(RuntimeError):
 class Oracle:
     """Reference solver on one mesh (mesh records as produced by the input generators)."""
 
-    def __init__(self, mesh, prm: Params | None = None):
+    def __init__(self, mesh, prm: Params | None = None, min_big: int = 0):
+        """min_big > 0 grows big stencils with fewer members like ill-posed fits (0: the paper's set)."""
         lib = _load()
         self.mesh = mesh
         self.n = mesh.n_cells
@@ -133,7 +134,7 @@ class Oracle:
         self._cells = np.ascontiguousarray(mesh.cells, np.int64)
         box = np.asarray(mesh.box, np.float64)
         h = lib.orc_create(self._nodes.shape[0], _p(self._nodes), self.n, _p(self._types), _p(self._cells), _p(box),
-                           int(mesh.periodic))
+                           int(mesh.periodic), int(min_big))
         if not h:
             raise OracleError(lib.orc_last_error().decode())
         self.h = h

@@ -159,6 +159,9 @@ typedef struct {
     double *a;  /* [n][5][9] */
     double *b;  /* [n][5][8][3] */
     double *w;  /* [n][5][9] normalised weights omega_0..omega_M */
+    /* option: a big stencil with fewer members than this is grown like an
+     * ill-posed fit (0: the paper's neighbours-of-neighbours set as it is) */
+    int min_big;
 } orc;
 
 static char g_err[256];
@@ -555,12 +558,15 @@ static int well_posed(const double *A, int n, int k)
 }
 
 /*
- * Grow a member list until its fit is well posed: candidates are the face
- * neighbours of the current members (members in order, faces in F_p order),
- * excluding the cell itself and existing members; they are appended one at
- * a time.  Returns the number appended, or -1 when the candidates run out.
+ * Grow a member list until its fit is well posed and has at least min_rows
+ * members: candidates are the face neighbours of the current members (members
+ * in order, faces in F_p order), excluding the cell itself and existing
+ * members; they are appended one at a time.  When the candidates run out a
+ * well-posed fit is kept below min_rows.  Returns the number appended, or -1
+ * when the candidates run out before the fit is well posed.
  */
-static int grow_until_posed(const orc *o, int64_t i, const ocell *C, sref *list, int *n, int cap, int k, double h)
+static int grow_until_posed(const orc *o, int64_t i, const ocell *C, sref *list, int *n, int cap, int k, double h,
+                            int min_rows)
 {
     sref self = {i, {0, 0, 0}};
     sref cand[MAXST * 6];
@@ -580,8 +586,9 @@ static int grow_until_posed(const orc *o, int64_t i, const ocell *C, sref *list,
     double A[MAXST * 9];
     for (;;) {
         lsq_rows(o, C, list, *n, k, h, A);
-        if (well_posed(A, *n, k)) return added;
-        if (added >= nc || *n >= cap) return -1;
+        const int posed = well_posed(A, *n, k);
+        if (posed && *n >= min_rows) return added;
+        if (added >= nc || *n >= cap) return posed ? added : -1;
         list[(*n)++] = cand[added++];
     }
 }
@@ -621,14 +628,14 @@ static int build_stencils(orc *o, int64_t i)
     /* least-squares fits in (x - x0)/h; ill-posed ones are grown by the next ring */
     double h = cbrt(C->vol);
     C->grown = 0;
-    int g = grow_until_posed(o, i, C, C->st, &C->K, MAXST, 9, h);
+    int g = grow_until_posed(o, i, C, C->st, &C->K, MAXST, 9, h, o->min_big);
     if (g < 0) return 2;
     C->grown += g;
     double A[MAXST * 9];
     lsq_rows(o, C, C->st, C->K, 9, h, A);
     if (lsq_build(&C->ls0, C->K, 9, A)) return 2;
     for (int m = 0; m < C->M; m++) {
-        g = grow_until_posed(o, i, C, C->sub[m], &C->subn[m], MAXSUB, 3, h);
+        g = grow_until_posed(o, i, C, C->sub[m], &C->subn[m], MAXSUB, 3, h, 0);
         if (g < 0) return 3;
         C->grown += g;
         lsq_rows(o, C, C->sub[m], C->subn[m], 3, h, A);
@@ -668,9 +675,10 @@ static void face_gauss(const double Xq[4][3], double gp[4][3], double va[4][3])
 void orc_destroy(orc *o);
 
 orc *orc_create(int64_t n_nodes, const double *nodes, int64_t n_cells, const int8_t *types, const int64_t *cells,
-                const double *box, int periodic)
+                const double *box, int periodic, int min_big)
 {
     orc *o = calloc(1, sizeof(orc));
+    o->min_big = min_big;
     o->n_nodes = n_nodes;
     o->n_cells = n_cells;
     o->periodic = periodic;

@@ -932,15 +932,17 @@ void gks_default_params(gks_params *p)
 const char *gks_last_error(void) { return g_err.c_str(); }
 
 gks_status gks_preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, const int8_t *types,
-                          const int64_t *cells, const double *box, int periodic, gks_host_mesh **out)
+                          const int64_t *cells, const double *box, int periodic, int min_big_stencil,
+                          gks_host_mesh **out)
 {
     if (!out) return fail(GKS_EINVAL, "null output");
+    if (min_big_stencil < 0 || min_big_stencil > 64) return fail(GKS_EINVAL, "min_big_stencil out of range 0..64");
     *out = nullptr;
     gks_host_mesh *h = new (std::nothrow) gks_host_mesh;
     if (!h) return fail(GKS_EINVAL, "out of host memory");
     gks_status s;
     try {
-        s = preprocess(n_nodes, nodes, n_cells, types, cells, box, periodic, h->h);
+        s = preprocess(n_nodes, nodes, n_cells, types, cells, box, periodic, min_big_stencil, h->h);
     } catch (const std::exception &e) {
         s = fail(GKS_EINVAL, std::string("preprocessing failed: ") + e.what());
     }

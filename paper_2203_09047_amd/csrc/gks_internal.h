@@ -37,7 +37,7 @@ struct HostMesh {
 };
 
 gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, const int8_t *types,
-                      const int64_t *cells, const double *box, int periodic, HostMesh &H);
+                      const int64_t *cells, const double *box, int periodic, int min_big, HostMesh &H);
 
 gks_status fail(gks_status s, const std::string &msg);
 

@@ -20,7 +20,9 @@
 //     polynomials (3 coefficients) in the zero-mean basis about the cell
 //     centroid; a fit whose scaled matrix has fewer rows than unknowns or
 //     sigma_min < 1e-6 sigma_max is grown by face neighbours of its members,
-//     one at a time, until it is well posed.
+//     one at a time, until it is well posed; optionally (min_big > 0) a big
+//     stencil with fewer than min_big members is grown the same way to
+//     min_big members (kept smaller if the candidates run out).
 // The pseudo-inverses come from a one-sided Jacobi SVD of the scaled matrix.
 // Cells are reordered along a Morton curve of their centroids; each face is
 // owned by its lower-numbered cell and oriented towards the other one.
@@ -35,6 +37,7 @@
 #include <vector>
 
 namespace gks {
+
 
 namespace {
 
@@ -259,7 +262,7 @@ uint64_t spread3(uint64_t v)
 
 // ---------------------------------------------------------------------------
 gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, const int8_t *types,
-                      const int64_t *cells, const double *box, int periodic, HostMesh &H)
+                      const int64_t *cells, const double *box, int periodic, int min_big, HostMesh &H)
 {
     if (!nodes || !types || !cells || !box || n_nodes <= 0 || n_cells <= 0) return fail(GKS_EINVAL, "null or empty mesh");
     if (!periodic) return fail(GKS_EINVAL, "only periodic meshes are supported");
@@ -418,7 +421,10 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
                                 gm.S[2][2] + D[2] * D[2] - g0.S[2][2]};
         for (int j = 0; j < k; ++j) row[j] = vals[j] / (j < 3 ? h : h * h);
     };
-    auto fit = [&](int64_t c, std::vector<Member> &list, int k, double h, std::vector<double> &P) -> int {
+    // min_rows: a well-posed fit is still grown while it has fewer members (best effort: kept when the
+    // candidates run out)
+    auto fit = [&](int64_t c, std::vector<Member> &list, int k, double h, std::vector<double> &P,
+                   int min_rows) -> int {
         const CellGeom &g0 = geo[c];
         const Member self{c, {0, 0, 0}};
         std::vector<Member> cand;
@@ -431,20 +437,22 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         size_t used = 0;
         for (;;) {
             const int rows = (int)list.size();
+            bool posed = false;
             if (rows >= k) {
                 std::vector<double> A((size_t)rows * k);
                 for (int r = 0; r < rows; ++r) member_row(g0, list[r], k, h, &A[(size_t)r * k]);
-                const double ratio = jacobi_pinv(A, rows, k, P);
-                if (ratio >= 1e-6) {
-                    // undo the column scaling: coefficient j = scaled unknown j / h^deg
-                    for (int j = 0; j < k; ++j) {
-                        const double s = j < 3 ? h : h * h;
-                        for (int r = 0; r < rows; ++r) P[(size_t)j * rows + r] /= s;
-                    }
-                    return (int)used;
-                }
+                posed = jacobi_pinv(A, rows, k, P) >= 1e-6;
             }
-            if (used >= cand.size()) return -1;
+            const bool out_of_candidates = used >= cand.size();
+            if (posed && (rows >= min_rows || out_of_candidates)) {
+                // undo the column scaling: coefficient j = scaled unknown j / h^deg
+                for (int j = 0; j < k; ++j) {
+                    const double s = j < 3 ? h : h * h;
+                    for (int r = 0; r < rows; ++r) P[(size_t)j * rows + r] /= s;
+                }
+                return (int)used;
+            }
+            if (out_of_candidates) return -1;
             list.push_back(cand[used++]);
         }
     };
@@ -503,7 +511,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         }
         const double h = std::cbrt(g.vol);
         std::vector<double> P0;
-        int gr = fit(c, big, 9, h, P0);
+        int gr = fit(c, big, 9, h, P0, min_big);
         if (gr < 0) {
             out.err = 1;
             return;
@@ -512,7 +520,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         const int nls = (int)big.size();
         std::vector<std::vector<double>> Pm(M);
         for (int m = 0; m < M; ++m) {
-            int gm = fit(c, subs[m], 3, h, Pm[m]);
+            int gm = fit(c, subs[m], 3, h, Pm[m], 0);
             if (gm < 0) {
                 out.err = 2;
                 return;

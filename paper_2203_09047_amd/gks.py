@@ -63,7 +63,7 @@ def load():
         st = ctypes.c_int
         lib.gks_default_params.argtypes = [pp]
         lib.gks_default_params.restype = None
-        lib.gks_preprocess.argtypes = [i64, vp, i64, vp, vp, vp, i32, ctypes.POINTER(vp)]
+        lib.gks_preprocess.argtypes = [i64, vp, i64, vp, vp, vp, i32, i32, ctypes.POINTER(vp)]
         lib.gks_preprocess.restype = st
         lib.gks_host_mesh_free.argtypes = [vp]
         lib.gks_host_mesh_free.restype = None
@@ -151,7 +151,8 @@ def params(precision=FP64, gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, viscous=False, we
 class HostMesh:
     """Host-side preprocessed mesh (connectivity, geometry, stencils, pseudo-inverses, Morton order)."""
 
-    def __init__(self, mesh):
+    def __init__(self, mesh, min_big: int = 0):
+        """min_big > 0 grows big stencils with fewer members like ill-posed fits (0: the paper's set)."""
         lib = load()
         self._nodes = np.ascontiguousarray(mesh.nodes, np.float64)
         self._types = np.ascontiguousarray(mesh.types, np.int8)
@@ -159,7 +160,7 @@ class HostMesh:
         box = np.asarray(mesh.box, np.float64)
         h = ctypes.c_void_p()
         _check(lib.gks_preprocess(self._nodes.shape[0], _np(self._nodes), self._types.shape[0], _np(self._types),
-                                  _np(self._cells), _np(box), int(mesh.periodic), ctypes.byref(h)))
+                                  _np(self._cells), _np(box), int(mesh.periodic), int(min_big), ctypes.byref(h)))
         self.h = h
         self._lib = lib  # the library that owns h frees it, also at interpreter shutdown
         n, nf, ns, nsc, ng = (ctypes.c_int64() for _ in range(5))

@@ -69,11 +69,11 @@ def test_preprocessor_rejects_bad_meshes():
     cells = np.ascontiguousarray(mesh.cells)
     box = np.asarray(mesh.box, float)
     code = lib.gks_preprocess(nodes.shape[0], gks._np(nodes), len(bad_types), gks._np(bad_types), gks._np(cells),
-                              gks._np(box), 1, ctypes.byref(h))
+                              gks._np(box), 1, 0, ctypes.byref(h))
     assert code == gks.GKS_EINVAL
     # drop one cell: the mesh is no longer closed
     code = lib.gks_preprocess(nodes.shape[0], gks._np(nodes), len(mesh.types) - 1, gks._np(mesh.types),
-                              gks._np(cells), gks._np(box), 1, ctypes.byref(h))
+                              gks._np(cells), gks._np(box), 1, 0, ctypes.byref(h))
     assert code == gks.GKS_EMESH
     assert b"face" in lib.gks_last_error()
 

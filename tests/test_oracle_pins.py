@@ -585,6 +585,39 @@ def _errors(m, o, Q, t):
     return float((np.abs(e) * vol).sum()), float(np.abs(e).max())
 
 
+def test_min_big_stencil_option():
+    """The paper's big stencils on the hybrid lattice include 12-member ones; min_big = 16 grows every
+    big stencil to 16 members (the lattice has enough neighbours everywhere), by face neighbours of
+    the members, and leaves larger stencils as they are."""
+    m = inputs.lattice(6, "hybrid")
+    o0, o16 = oracle.Oracle(m), oracle.Oracle(m, min_big=16)
+    K0 = np.array([o0.stencil_sizes(i)[0] for i in range(m.n_cells)])
+    K16 = np.array([o16.stencil_sizes(i)[0] for i in range(m.n_cells)])
+    assert K0.min() == 12
+    assert (K16 >= 16).all()
+    big = K0 >= 16
+    assert (K16[big] == K0[big]).all()
+    for i in np.flatnonzero(~big)[:20]:
+        # the paper's set comes first, the appended members after it
+        ids0, sh0 = o0.stencil(i)
+        ids16, sh16 = o16.stencil(i)
+        assert np.array_equal(ids16[:len(ids0)], ids0) and np.array_equal(sh16[:len(sh0)], sh0)
+
+
+@pytest.mark.slow
+def test_linear_scheme_stable_on_hybrid_lattice_only_with_16_member_stencils():
+    """Linear weights, density wave to t = 0.1 on the N = 8 hybrid lattice: with the paper's stencils
+    the scheme leaves the physical states; with min_big = 16 it stays within the WENO error."""
+    m = inputs.lattice(8, "hybrid")
+    Q0 = inputs.cell_averages(m, inputs.wave())
+    with pytest.raises(oracle.OracleError):
+        oracle.Oracle(m, oracle.params(force_linear=1)).run(Q0, t_end=0.1)
+    o = oracle.Oracle(m, oracle.params(force_linear=1), min_big=16)
+    Q, _ = o.run(Q0, t_end=0.1)
+    l1, linf = _errors(m, o, Q, 0.1)
+    assert l1 < 1e-2 and linf < 5e-2, (l1, linf)
+
+
 @pytest.mark.slow
 def test_third_order_convergence_on_hexahedra():
     errs = []
