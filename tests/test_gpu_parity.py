@@ -182,6 +182,35 @@ def test_hybrid_steps_fp64_parity(gks, kind, N, steps):
     assert (err <= TOL).all(), err
 
 
+def test_taylor_green_navier_stokes_fp64_parity(gks):
+    """The benchmark's workload at small size: Taylor-Green vortex at Mach 0.1, mu = 1/1600,
+    Pr = 0.72 on the hybrid lattice of [0, 2 pi]^3, 4 steps with the oracle's step sizes.  The
+    momentum components are scaled by the largest momentum (rho W starts at zero)."""
+    import torch
+
+    print("case: Taylor-Green NS hybrid N=6 x 4 steps", flush=True)
+    mesh = inputs.lattice(6, "hybrid", box=(2 * np.pi,) * 3)
+    Q0 = inputs.cell_averages(mesh, inputs.tgv())
+    kw = dict(viscous=True, mu=1.0 / 1600.0, Pr=0.72)
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host, gks.params(**kw))
+    o = oracle.Oracle(mesh, oracle.params(**kw))
+    Q = sol.upload(host.to_internal(Q0))
+    ref = Q0.copy()
+    for _ in range(4):
+        dt = o.timestep(ref)
+        ref = o.step(ref, dt)
+        sol.step(Q, dt)
+    sol.poll()
+    torch.cuda.synchronize()
+    got = host.to_external(Q.cpu().numpy())
+    scale = np.abs(ref).max(axis=1)
+    scale[1:4] = scale[1:4].max()
+    err = np.abs(got - ref).max(axis=1) / scale
+    print("relative Linf per component:", err)
+    assert (err <= TOL).all(), err
+
+
 def test_fp32_mixed_error_against_oracle(gks):
     print("case: fp32-mixed hybrid N=6 x 3 steps", flush=True)
     mesh = inputs.lattice(6, "hybrid")
