@@ -287,6 +287,144 @@ __device__ __forceinline__ void weno_combine_quad(const T a[9], const T bs[2][3]
     c[0] = with_q0 ? (T)q0 + corr : corr;
 }
 
+// DPP broadcast of lane o of each quad of lanes to the whole quad
+template <int O>
+__device__ __forceinline__ double quad_bcast(double v)
+{
+    return dpp_f64<O | (O << 2) | (O << 4) | (O << 6)>(v);
+}
+
+/*
+ * Reverse of weno_combine_quad (FP64): cb[10] (the same on every lane of the
+ * quad) -> ab[9] (the same on every lane), bsb[h] (this lane's sub-stencils
+ * l + 4 h) and q0b.  The forward quantities are recomputed; every sum over
+ * sub-stencils is a quad sum, so the lanes stay bitwise identical.
+ */
+__device__ __forceinline__ void weno_combine_quad_b(const double a[9], const double bs[2][3], int l, int M, double v23,
+                                                    const double S[6], const WenoParams &wp, const double cb_in[10],
+                                                    double ab[9], double bsb[2][3], double &q0b)
+{
+    const double H[3][3] = {{2.0 * a[3], a[4], a[5]}, {a[4], 2.0 * a[6], a[7]}, {a[5], a[7], 2.0 * a[8]}};
+    const double Sm[3][3] = {{S[0], S[1], S[2]}, {S[1], S[3], S[4]}, {S[2], S[4], S[5]}};
+    double beta0 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double quad = 0.0;
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) quad += H[d][p] * Sm[p][q] * H[d][q];
+        beta0 += a[d] * a[d] + quad;
+    }
+    const double sec = 4.0 * (a[3] * a[3] + a[6] * a[6] + a[8] * a[8]) + a[4] * a[4] + a[5] * a[5] + a[7] * a[7];
+    beta0 = v23 * beta0 + v23 * v23 * sec;
+    const double gm = wp.gm, g0 = 1.0 - gm * M, eps = wp.eps, pw = wp.p;
+    const bool lin = wp.force_linear != 0;
+    bool on[2];
+    double beta[2], xs[2], ws[2], tw = 0.0, wsum = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        on[h] = l + 4 * h < M;
+        beta[h] = v23 * (bs[h][0] * bs[h][0] + bs[h][1] * bs[h][1] + bs[h][2] * bs[h][2]);
+        if (on[h]) tw += wabs(beta0 - beta[h]);
+    }
+    tw = quad_sum(tw) / M;
+    const double x0 = lin ? 0.0 : tw / (beta0 + eps);
+    const double w0 = lin ? g0 : g0 * (1.0 + wpow(x0, pw));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        xs[h] = lin ? 0.0 : tw / (beta[h] + eps);
+        ws[h] = lin ? gm : gm * (1.0 + wpow(xs[h], pw));
+        if (on[h]) wsum += ws[h];
+    }
+    const double isum = 1.0 / (w0 + quad_sum(wsum));
+    const double f0 = w0 * isum / g0;
+    const double sub0 = f0 * gm;
+    // reverse of c[0] = q0 - sum c_n S_n and of c[1 + j] = f0 a_j
+    double cb[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) cb[j] = cb_in[j];
+    q0b = cb[0];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) cb[4 + q] += -S[q] * cb[0];
+    double f0b = 0.0;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        ab[j] = f0 * cb[1 + j];
+        f0b += a[j] * cb[1 + j];
+    }
+    // contributions of c[1..3] += f_m b^m (f_m = w_m / sum - f0 gm) to f0 and to the sum
+    double fsb[2], sumb = 0.0, f0bp = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        fsb[h] = bs[h][0] * cb[1] + bs[h][1] * cb[2] + bs[h][2] * cb[3];
+        if (on[h]) {
+            sumb += -fsb[h] * ws[h] * isum * isum;
+            f0bp += -fsb[h] * gm;
+        }
+    }
+    f0b += quad_sum(f0bp);
+    sumb = quad_sum(sumb) - f0b * w0 * isum * isum / g0;
+    const double w0b = f0b * isum / g0 + sumb;
+    // tau_w
+    double twb = 0.0, beta0b = 0.0;
+    if (!lin) {
+        const double dp0 = pw == 1.0 ? 1.0 : pw * wpow(x0, pw - 1.0);
+        const double x0b = w0b * g0 * dp0;
+        beta0b += -x0b * x0 / (beta0 + eps);
+        double twp = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (on[h]) {
+                const double dps = pw == 1.0 ? 1.0 : pw * wpow(xs[h], pw - 1.0);
+                twp += (fsb[h] * isum + sumb) * gm * dps / (beta[h] + eps);
+            }
+        twb = (x0b / (beta0 + eps) + quad_sum(twp)) / M;
+    }
+    // this lane's sub-stencils
+    double beta0bp = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (on[h]) {
+            const double fs = ws[h] * isum - sub0;
+            const double wsb = fsb[h] * isum + sumb;
+            double betab = 0.0;
+            if (!lin) {
+                const double dps = pw == 1.0 ? 1.0 : pw * wpow(xs[h], pw - 1.0);
+                betab += -wsb * gm * dps * xs[h] / (beta[h] + eps);
+            }
+            const double sg = wsgn(beta0 - beta[h]);
+            beta0bp += twb * sg;
+            betab += -twb * sg;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) bsb[h][q] = fs * cb[1 + q] + 2.0 * v23 * betab * bs[h][q];
+        } else {
+            bsb[h][0] = bsb[h][1] = bsb[h][2] = 0.0;
+        }
+    }
+    beta0b += quad_sum(beta0bp);
+    // beta0 = v23 sum_d (a_d^2 + H_d S H_d) + v23^2 sec
+    const double g1 = v23 * beta0b, g2 = v23 * v23 * beta0b;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ab[d] += 2.0 * g1 * a[d];
+    double Hb[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) t += Sm[p][q] * H[d][q];
+            Hb[d][p] = 2.0 * g1 * t;
+        }
+    ab[3] += 2.0 * Hb[0][0] + 8.0 * g2 * a[3];
+    ab[4] += Hb[0][1] + Hb[1][0] + 2.0 * g2 * a[4];
+    ab[5] += Hb[0][2] + Hb[2][0] + 2.0 * g2 * a[5];
+    ab[6] += 2.0 * Hb[1][1] + 8.0 * g2 * a[6];
+    ab[7] += Hb[1][2] + Hb[2][1] + 2.0 * g2 * a[7];
+    ab[8] += 2.0 * Hb[2][2] + 8.0 * g2 * a[8];
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff,
                                                           WenoParams wp)
@@ -683,7 +821,12 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct_adj(DevMesh m, const d
                                                               const double *__restrict__ cbc, WenoParams wp,
                                                               double *__restrict__ dbar, double *__restrict__ own)
 {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * kK1Block + threadIdx.x;
+    // forward recomputation exactly as in k_reconstruct (FP64): staged gathers and lists
+    __shared__ double sq[5][kK1Stage];
+    __shared__ double sB[3][kK1SubStage];
+    __shared__ unsigned char sl[kK1SubStage];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int t = blk * kK1Block + threadIdx.x;
     const int n = m.n;
     const int ic = t / kK1CellLanes;
     const int lane = t - kK1CellLanes * ic;
@@ -691,60 +834,101 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct_adj(DevMesh m, const d
     const int l = lane & 3;
     const bool valid = ic < n;
     const int i = valid ? ic : n - 1;
+    const double *B = (const double *)m.ss_B;
+    const int cb0 = blk * kK1Cells, cb1 = min(cb0 + kK1Cells, n);
+    const int e0 = m.st_ptr[cb0], e1 = m.st_ptr[cb1];
+    const int s0 = m.ss_ptr[8 * cb0], s1 = m.ss_ptr[8 * cb1];
+    const bool staged = e1 - e0 <= kK1Stage && s1 - s0 <= kK1SubStage;  // uniform over the block
+    if (staged) {
+        for (int e = e0 + (int)threadIdx.x; e < e1; e += kK1Block) {
+            const int x = m.st_cell[e];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) sq[c][e - e0] = Q[(size_t)c * n + x];
+        }
+        for (int e = s0 + (int)threadIdx.x; e < s1; e += kK1Block) {
+            sl[e - s0] = m.ss_loc[e];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) sB[j][e - s0] = B[(size_t)3 * e + j];
+        }
+        __syncthreads();
+    }
     const double *pinv = (const double *)m.pinv;
     const double *dsc = (const double *)m.dsc;
     const int nnz = m.nnz;
     const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
     const double *Qc = Q + (size_t)comp * n;
     const double q0 = Qc[i];
-    double a[9], r[8][3];
+    auto diff = [&](int k) -> double { return (staged ? sq[comp][k - e0] : Qc[m.st_cell[k]]) - q0; };
+    double a[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = 0.0;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) r[s][0] = r[s][1] = r[s][2] = 0.0;
+#pragma unroll 2
     for (int k = k0 + l; k < k1; k += kK1Lanes) {
-        const int2 rec = m.st_rec[k];
-        const double d = Qc[rec.x] - q0;
+        const double d = diff(k);
 #pragma unroll
         for (int j = 0; j < 9; ++j) a[j] += pinv[(size_t)9 * k + j] * d;
-        const double dx = dsc[(size_t)3 * k] * d, dy = dsc[(size_t)3 * k + 1] * d, dz = dsc[(size_t)3 * k + 2] * d;
-        const unsigned mask = (unsigned)rec.y;
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-            if (mask & (1u << s)) {
-                r[s][0] += dx;
-                r[s][1] += dy;
-                r[s][2] += dz;
-            }
     }
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = quad_sum(a[j]);
-    const double *gip = (const double *)m.ginv;
+    double bs[2][3];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        r[s][0] = quad_sum(r[s][0]);
-        r[s][1] = quad_sum(r[s][1]);
-        r[s][2] = quad_sum(r[s][2]);
+    for (int h = 0; h < 2; ++h) {
+        bs[h][0] = bs[h][1] = bs[h][2] = 0.0;
+        const int p0 = m.ss_ptr[8 * i + l + 4 * h], p1 = m.ss_ptr[8 * i + l + 4 * h + 1];
+        if (staged) {
+            for (int e = p0 - s0; e < p1 - s0; ++e) {
+                const double d = diff(k0 + sl[e]);
+                bs[h][0] += sB[0][e] * d;
+                bs[h][1] += sB[1][e] * d;
+                bs[h][2] += sB[2][e] * d;
+            }
+        } else {
+            for (int e = p0; e < p1; ++e) {
+                const double d = diff(k0 + m.ss_loc[e]);
+                bs[h][0] += B[(size_t)3 * e] * d;
+                bs[h][1] += B[(size_t)3 * e + 1] * d;
+                bs[h][2] += B[(size_t)3 * e + 2] * d;
+            }
+        }
     }
     const double S[6] = {m.m2[i], m.m2[n + i], m.m2[2 * n + i], m.m2[3 * n + i], m.m2[4 * n + i], m.m2[5 * n + i]};
     double cb[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j) cb[j] = cbc[(size_t)50 * i + 10 * comp + j];
-    double ab[9], rb[8][3], q0b = 0.0;
-    auto getg = [&](int s, double g[6]) {
+    double ab[9], bsb[2][3], q0b;
+    weno_combine_quad_b(a, bs, l, m.M[i], m.vol23[i], S, wp, cb, ab, bsb, q0b);
+    // b^s = sum_k (G_s^-1 D_k / h) d_k, so d_k receives D_k . r_s with r_s = (G_s^-1 / h) bsb_s for
+    // every sub-stencil s that holds member k; lane l forms r for its sub-stencils l, l + 4, and the
+    // quad shares all eight
+    const double *gip = (const double *)m.ginv;
+    double rown[2][3];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) g[q] = gip[(size_t)(6 * s + q) * n + i];
-    };
-    weno_combine_b<double>(a, r, getg, m.M[i], m.vol23[i], S, wp, cb, ab, rb, q0b);
-    // members: dbar_k = sum_j A+[j][k] ab_j + D_k . sum_{m in mask} rb_m
+    for (int h = 0; h < 2; ++h) {
+        double g[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) g[q] = gip[(size_t)(6 * (l + 4 * h) + q) * n + i];
+        sym3_apply(g, bsb[h], rown[h]);
+    }
+    double rb[8][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        rb[0][q] = quad_bcast<0>(rown[0][q]);
+        rb[1][q] = quad_bcast<1>(rown[0][q]);
+        rb[2][q] = quad_bcast<2>(rown[0][q]);
+        rb[3][q] = quad_bcast<3>(rown[0][q]);
+        rb[4][q] = quad_bcast<0>(rown[1][q]);
+        rb[5][q] = quad_bcast<1>(rown[1][q]);
+        rb[6][q] = quad_bcast<2>(rown[1][q]);
+        rb[7][q] = quad_bcast<3>(rown[1][q]);
+    }
+    // members: dbar_k = sum_j A+[k][j] ab_j + D_k . sum_{s in mask} r_s
     double sumk = 0.0;
     for (int k = k0 + l; k < k1; k += kK1Lanes) {
-        const int2 rec = m.st_rec[k];
+        const unsigned mask = (unsigned)m.st_rec[k].y;
         double v = 0.0;
 #pragma unroll
         for (int j = 0; j < 9; ++j) v += pinv[(size_t)9 * k + j] * ab[j];
         double sx = 0.0, sy = 0.0, sz = 0.0;
-        const unsigned mask = (unsigned)rec.y;
 #pragma unroll
         for (int s = 0; s < 8; ++s)
             if (mask & (1u << s)) {
