@@ -194,9 +194,13 @@ gks_status gks_residual(gks_mesh *m, const void *face_flux, double *L, double *d
  * with the same dt in both stages.  Q is updated in place.  If p->dt_given
  * is 0 the CFL step is computed first into *dt_dev; otherwise *dt_dev is
  * used as given.  Q_star (optional, may be NULL) receives Q* [5][n_cells].
+ * coeff_tape (optional, may be NULL): device buffer of 2 x n_cells x 50
+ * elements of the mesh precision that receives both stages' reconstructions
+ * (the per-cell quadratics of Q and of Q*, layout [2][n_cells][5][10]); the
+ * adjoint step can reuse it instead of reconstructing again.
  */
 gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_params *p, void *work, double *Q_star,
-                         gks_stream_t stream);
+                         void *coeff_tape, gks_stream_t stream);
 
 /*
  * Discrete adjoint of one S2O4 step (FP64 meshes only), the dt of the step
@@ -210,13 +214,16 @@ gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_param
  * time; |x| is differentiated as sign(x), sign(0) = 0).  Qn and Qstar are the
  * step's start state and stage state (as produced by gks_s2o4_step), dt_dev
  * the step's dt.  adj_work: caller-owned device buffer of
- * gks_adjoint_work_bytes(), 256-byte aligned.  Every gather runs in a fixed
- * order (no atomics): the result is bitwise reproducible.
+ * gks_adjoint_work_bytes(), 256-byte aligned.  coeff_tape (optional, may be
+ * NULL): the step's coefficient tape from gks_s2o4_step; when given, the two
+ * reconstructions of Qn and Qstar are read from it instead of recomputed.
+ * Every gather runs in a fixed order (no atomics): the result is bitwise
+ * reproducible, and the same with or without the tape.
  */
 gks_status gks_adjoint_work_bytes(const gks_host_mesh *h, size_t *bytes);
 gks_status gks_adjoint_step(gks_mesh *m, const double *Qn, const double *Qstar, const double *dt_dev,
                             const double *lam_np1, double *lam_n, const gks_params *p, void *adj_work,
-                            gks_stream_t stream);
+                            const double *coeff_tape, gks_stream_t stream);
 
 /*
  * Flow functional J = sum_i |Omega_i| |rho U_i|^2 / (2 rho_i) (kinetic energy)

@@ -4,7 +4,10 @@
 steps on the GPU and returns the final state; its backward propagates the
 cotangent of the final state to Q0 with the library's hand-written adjoint
 (``gks_adjoint_step``), recomputing each segment of ``ckpt_every`` steps from
-its checkpoint.  The step sizes chosen in the forward pass are frozen.
+its checkpoint.  The step sizes chosen in the forward pass are frozen.  The
+recomputation keeps each step's reconstructions (a coefficient tape of
+800 bytes per cell per step in FP64) so the adjoint does not redo them; with
+``keep_coefficients=False`` the adjoint recomputes them instead.
 """
 from __future__ import annotations
 
@@ -13,7 +16,7 @@ import torch
 
 class Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, Q0, solver, nsteps, ckpt_every=10):
+    def forward(ctx, Q0, solver, nsteps, ckpt_every=10, keep_coefficients=True):
         Q = Q0.detach().clone()
         dts = torch.zeros(max(nsteps, 1), dtype=torch.float64, device=Q.device)
         ckpts = {}
@@ -23,6 +26,7 @@ class Rollout(torch.autograd.Function):
             solver.step(Q)                       # CFL dt computed on the device into solver.dt
             dts[k:k + 1].copy_(solver.dt)        # frozen for the adjoint
         ctx.solver, ctx.nsteps, ctx.ckpt_every = solver, nsteps, ckpt_every
+        ctx.keep = keep_coefficients
         ctx.ckpts, ctx.dts = ckpts, dts
         return Q
 
@@ -39,13 +43,15 @@ class Rollout(torch.autograd.Function):
             for k in range(seg, last):
                 Qn = Q.clone()
                 Qs = torch.empty_like(Q)
-                solver.step_to(Q, ctx.dts[k:k + 1], Q_star=Qs)
-                states.append((Qn, Qs))
+                tape = solver.coeff_tape() if ctx.keep else None
+                solver.step_to(Q, ctx.dts[k:k + 1], Q_star=Qs, coeff_tape=tape)
+                states.append((Qn, Qs, tape))
             for k in reversed(range(seg, last)):
-                Qn, Qs = states[k - seg]
-                solver.adjoint_step(Qn, Qs, ctx.dts[k:k + 1], lam, lam_tmp)
+                Qn, Qs, tape = states[k - seg]
+                solver.adjoint_step(Qn, Qs, ctx.dts[k:k + 1], lam, lam_tmp, coeff_tape=tape)
                 lam, lam_tmp = lam_tmp, lam
-        return lam, None, None, None
+                states[k - seg] = None
+        return lam, None, None, None, None
 
 
 def kinetic_energy_gradient(solver, Q0, nsteps, ckpt_every=10):

@@ -817,7 +817,7 @@ __global__ void __launch_bounds__(kBlock) k_cbar_gather(DevMesh m, const double 
 }
 
 // reverse of the reconstruction: quad of lanes per (cell, component)
-__global__ void __launch_bounds__(kK1Block) k_reconstruct_adj(DevMesh m, const double *__restrict__ Q,
+__global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3))) k_reconstruct_adj(DevMesh m, const double *__restrict__ Q,
                                                               const double *__restrict__ cbc, WenoParams wp,
                                                               double *__restrict__ dbar, double *__restrict__ own)
 {
@@ -1502,7 +1502,7 @@ gks_status gks_residual(gks_mesh *m, const void *face_flux, double *L, double *d
 }
 
 gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_params *p, void *work, double *Q_star,
-                         gks_stream_t stream)
+                         void *coeff_tape, gks_stream_t stream)
 {
     gks_status s = check_params(m, p);
     if (s) return s;
@@ -1511,9 +1511,13 @@ gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_param
     Work w = work_of(m, work);
     if (!p->dt_given && (s = launch_timestep(m, Q, p, dt_dev, w, st))) return s;
     const unsigned gc = grid_for(m->n, kBlock);
+    // the stages' coefficients: the work buffer, or the caller's tape
+    const size_t es = m->precision == GKS_FP64 ? 8 : 4;
+    void *c1 = coeff_tape ? coeff_tape : w.coeff;
+    void *c2 = coeff_tape ? (void *)((char *)coeff_tape + es * 50 * (size_t)m->n) : w.coeff;
     // stage 1
-    if ((s = launch_reconstruct(m, Q, w.coeff, p, st))) return s;
-    if ((s = launch_flux(m, w.coeff, Q, dt_dev, w.ff, p, w, st))) return s;
+    if ((s = launch_reconstruct(m, Q, c1, p, st))) return s;
+    if ((s = launch_flux(m, c1, Q, dt_dev, w.ff, p, w, st))) return s;
     {
     ProfScope ps(m, GKS_K_STAGE1, st);
     if (m->precision == GKS_FP64)
@@ -1523,8 +1527,8 @@ gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_param
     }
     if ((s = hip_check(hipGetLastError(), "stage-1 launch"))) return s;
     // stage 2
-    if ((s = launch_reconstruct(m, w.Qs, w.coeff, p, st))) return s;
-    if ((s = launch_flux(m, w.coeff, w.Qs, dt_dev, w.ff, p, w, st))) return s;
+    if ((s = launch_reconstruct(m, w.Qs, c2, p, st))) return s;
+    if ((s = launch_flux(m, c2, w.Qs, dt_dev, w.ff, p, w, st))) return s;
     {
     ProfScope ps(m, GKS_K_STAGE2, st);
     if (m->precision == GKS_FP64)
@@ -1546,23 +1550,27 @@ gks_status gks_adjoint_work_bytes(const gks_host_mesh *h, size_t *bytes)
     return GKS_OK;
 }
 
-static gks_status launch_vjp(gks_mesh *m, const double *Qe, const double *dt_dev, const double *lp, const double *ls,
-                             double cL1, double cL2, double cD1, double cD2, const gks_params *p, AdjWork &aw,
-                             hipStream_t st, double *out)
+static gks_status launch_vjp(gks_mesh *m, const double *Qe, const double *coeff_in, const double *dt_dev,
+                             const double *lp, const double *ls, double cL1, double cL2, double cD1, double cD2,
+                             const gks_params *p, AdjWork &aw, hipStream_t st, double *out)
 {
     gks_status s;
-    if ((s = launch_reconstruct(m, Qe, aw.coeff, p, st))) return s;
+    const double *coeff = coeff_in;
+    if (!coeff) {
+        if ((s = launch_reconstruct(m, Qe, aw.coeff, p, st))) return s;
+        coeff = aw.coeff;
+    }
     const bool pr = p->viscous && p->Pr != 1.0;
     const FluxParams<double> fp = flux_params<double>(p);
     {
         ProfScope ps(m, GKS_K_FLUX_ADJ, st);
         const unsigned ga = grid_for(4 * m->nf, kBlock), gb = grid_for(8 * m->nf, kBlock);
         if (pr) {
-            k_flux_adj_a<true><<<ga, kBlock, 0, st>>>(m->d, aw.coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.abuf);
-            k_flux_adj_b<true><<<gb, kBlock, 0, st>>>(m->d, aw.coeff, fp, aw.abuf, aw.cbf);
+            k_flux_adj_a<true><<<ga, kBlock, 0, st>>>(m->d, coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.abuf);
+            k_flux_adj_b<true><<<gb, kBlock, 0, st>>>(m->d, coeff, fp, aw.abuf, aw.cbf);
         } else {
-            k_flux_adj_a<false><<<ga, kBlock, 0, st>>>(m->d, aw.coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.abuf);
-            k_flux_adj_b<false><<<gb, kBlock, 0, st>>>(m->d, aw.coeff, fp, aw.abuf, aw.cbf);
+            k_flux_adj_a<false><<<ga, kBlock, 0, st>>>(m->d, coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.abuf);
+            k_flux_adj_b<false><<<gb, kBlock, 0, st>>>(m->d, coeff, fp, aw.abuf, aw.cbf);
         }
     }
     {
@@ -1583,7 +1591,7 @@ static gks_status launch_vjp(gks_mesh *m, const double *Qe, const double *dt_dev
 
 gks_status gks_adjoint_step(gks_mesh *m, const double *Qn, const double *Qstar, const double *dt_dev,
                             const double *lam_np1, double *lam_n, const gks_params *p, void *adj_work,
-                            gks_stream_t stream)
+                            const double *coeff_tape, gks_stream_t stream)
 {
     gks_status s = check_params(m, p);
     if (s) return s;
@@ -1594,9 +1602,12 @@ gks_status gks_adjoint_step(gks_mesh *m, const double *Qn, const double *Qstar, 
     adj_layout(m->n, m->nf, m->d.nnz, &aw, (char *)adj_work);
     hipStream_t st = S(stream);
     // lam* = dt^2/3 J_D(Q*)^T lam'
-    if ((s = launch_vjp(m, Qstar, dt_dev, lam_np1, nullptr, 0.0, 0.0, 1.0 / 3.0, 0.0, p, aw, st, aw.lstar))) return s;
+    const double *cn = coeff_tape, *cs = coeff_tape ? coeff_tape + 50 * (size_t)m->n : nullptr;
+    if ((s = launch_vjp(m, Qstar, cs, dt_dev, lam_np1, nullptr, 0.0, 0.0, 1.0 / 3.0, 0.0, p, aw, st, aw.lstar)))
+        return s;
     // J_L(Q)^T (dt lam' + dt/2 lam*) + J_D(Q)^T (dt^2/6 lam' + dt^2/8 lam*)
-    if ((s = launch_vjp(m, Qn, dt_dev, lam_np1, aw.lstar, 1.0, 0.5, 1.0 / 6.0, 0.125, p, aw, st, aw.vjp))) return s;
+    if ((s = launch_vjp(m, Qn, cn, dt_dev, lam_np1, aw.lstar, 1.0, 0.5, 1.0 / 6.0, 0.125, p, aw, st, aw.vjp)))
+        return s;
     const int len = (int)(5 * m->n);
     k_adj_combine<<<grid_for(len, kBlock), kBlock, 0, st>>>(len, lam_np1, aw.lstar, aw.vjp, lam_n);
     return hip_check(hipGetLastError(), "adjoint combine launch");

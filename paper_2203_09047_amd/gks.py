@@ -91,7 +91,7 @@ def load():
         lib.gks_flux.restype = st
         lib.gks_residual.argtypes = [vp, vp, vp, vp, pp, vp]
         lib.gks_residual.restype = st
-        lib.gks_s2o4_step.argtypes = [vp, vp, vp, pp, vp, vp, vp]
+        lib.gks_s2o4_step.argtypes = [vp, vp, vp, pp, vp, vp, vp, vp]
         lib.gks_s2o4_step.restype = st
         lib.gks_poll_status.argtypes = [vp, vp, vp]
         lib.gks_poll_status.restype = st
@@ -114,7 +114,7 @@ def load():
         lib.gks_weno_combine_vjp_host.restype = st
         lib.gks_adjoint_work_bytes.argtypes = [vp, ctypes.POINTER(sz)]
         lib.gks_adjoint_work_bytes.restype = st
-        lib.gks_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, pp, vp, vp]
+        lib.gks_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, pp, vp, vp, vp]
         lib.gks_adjoint_step.restype = st
         lib.gks_kinetic_energy.argtypes = [vp, vp, vp, vp, vp, vp]
         lib.gks_kinetic_energy.restype = st
@@ -278,7 +278,11 @@ class Solver:
         _check(load().gks_residual(self.m, _dp(ff), _dp(L), _dp(D), ctypes.byref(self.P), self._s()))
         return L, D
 
-    def step(self, Q, dt=None, Q_star=None):
+    def coeff_tape(self):
+        """A device buffer for both stages' reconstructions of one step ([2][n][5][10])."""
+        return self.torch.empty(2 * self.n * 50, dtype=self.coeff_dtype, device=self.device)
+
+    def step(self, Q, dt=None, Q_star=None, coeff_tape=None):
         """One S2O4 step in place; dt=None computes the CFL step on the device."""
         if dt is None:
             self.P.dt_given = 0
@@ -286,8 +290,9 @@ class Solver:
             self.dt.fill_(float(dt))
             self.P.dt_given = 1
         qs = _dp(Q_star) if Q_star is not None else None
+        tape = _dp(coeff_tape) if coeff_tape is not None else None
         _check(load().gks_s2o4_step(self.m, self._q(Q), _dp(self.dt), ctypes.byref(self.P), self._work_ptr, qs,
-                                    self._s()))
+                                    tape, self._s()))
         self.P.dt_given = 0
         return Q
 
@@ -300,11 +305,13 @@ class Solver:
             self._adj_ptr = ctypes.c_void_p(self.adj_work.data_ptr() + ((-self.adj_work.data_ptr()) % 256))
         return self._adj_ptr
 
-    def adjoint_step(self, Qn, Qstar, dt, lam_next, lam_out=None):
-        """lam_n from lam_{n+1} for the S2O4 step Qn -> (Qstar) -> Q_{n+1}; dt: 1-element device tensor."""
+    def adjoint_step(self, Qn, Qstar, dt, lam_next, lam_out=None, coeff_tape=None):
+        """lam_n from lam_{n+1} for the S2O4 step Qn -> (Qstar) -> Q_{n+1}; dt: 1-element device tensor;
+        coeff_tape: that step's tape from step/step_to (optional: the reconstructions are recomputed)."""
         lam_out = self.torch.empty_like(lam_next) if lam_out is None else lam_out
+        tape = _dp(coeff_tape) if coeff_tape is not None else None
         _check(load().gks_adjoint_step(self.m, self._q(Qn), self._q(Qstar), _dp(dt), self._q(lam_next),
-                                       self._q(lam_out), ctypes.byref(self.P), self._adj_work(), self._s()))
+                                       self._q(lam_out), ctypes.byref(self.P), self._adj_work(), tape, self._s()))
         return lam_out
 
     def kinetic_energy(self, Q, grad=False):
@@ -315,13 +322,14 @@ class Solver:
                                          self._s()))
         return J, g
 
-    def step_to(self, Q, dt_ptr_tensor, Q_star=None):
+    def step_to(self, Q, dt_ptr_tensor, Q_star=None, coeff_tape=None):
         """One S2O4 step in place with dt read from a 1-element device tensor (no host round trip)."""
         self.P.dt_given = 1
         qs = _dp(Q_star) if Q_star is not None else None
+        tape = _dp(coeff_tape) if coeff_tape is not None else None
         try:
             _check(load().gks_s2o4_step(self.m, self._q(Q), _dp(dt_ptr_tensor), ctypes.byref(self.P),
-                                        self._work_ptr, qs, self._s()))
+                                        self._work_ptr, qs, tape, self._s()))
         finally:
             self.P.dt_given = 0
         return Q

@@ -189,3 +189,23 @@ def test_adjoint_is_bitwise_deterministic(gks):
     a = sol.adjoint_step(sol.upload(Qn), Qs, dtt, lam1).cpu().numpy()
     b = sol.adjoint_step(sol.upload(Qn), Qs, dtt, lam1).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def test_adjoint_with_coefficient_tape_is_identical(gks):
+    """The step's coefficient tape replaces the adjoint's own reconstructions bit for bit."""
+    import torch
+
+    mesh, Q0, host, sol = _setup(gks, "hybrid", 5, viscous=True)
+    Qn = host.to_internal(Q0)
+    Q = sol.upload(Qn)
+    Qs = torch.empty_like(Q)
+    tape = sol.coeff_tape()
+    sol.step(Q, 2e-2, Q_star=Qs, coeff_tape=tape)
+    Q2 = sol.upload(Qn)
+    sol.step(Q2, 2e-2)
+    assert torch.equal(Q, Q2)
+    dtt = torch.tensor([2e-2], dtype=torch.float64, device=Q.device)
+    lam1 = sol.upload(np.random.default_rng(4).standard_normal(Qn.shape))
+    a = sol.adjoint_step(sol.upload(Qn), Qs, dtt, lam1).cpu().numpy()
+    b = sol.adjoint_step(sol.upload(Qn), Qs, dtt, lam1, coeff_tape=tape).cpu().numpy()
+    assert np.array_equal(a, b)
