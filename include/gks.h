@@ -81,6 +81,9 @@ typedef struct {
     int precision;    /* gks_precision */
     int force_linear; /* 1: use the linear weights (testing of the quadratic reproduction) */
     int dt_given;     /* 1: gks_s2o4_step uses *dt_dev as given instead of computing the CFL step */
+    int first_order_fallback; /* 1: a reconstructed side state at a Gauss point with rho <= 0 or
+                                 p <= 0 is replaced by its cell's average with zero slopes (first
+                                 order there) and counted (gks_fallback_count); 0: the paper's scheme */
 } gks_params;
 
 typedef struct gks_host_mesh gks_host_mesh;
@@ -97,7 +100,13 @@ void gks_default_params(gks_params *p);
  *   types  [n_cells] int8: 0 tetrahedron, 1 pyramid, 2 prism, 3 hexahedron;
  *   cells  [n_cells][8] int64 node ids in the paper's vertex order, -1 padded;
  *   box    [3] periodic box lengths (the domain is [0,box_x] x [0,box_y] x [0,box_z]);
- *   periodic must be 1 (every face is then shared by exactly two cells);
+ *   periodic: 1, every face is shared by exactly two cells, opposite faces of
+ *     the box matched as periodic images; 0, a face of one cell must lie on a
+ *     face of the box and is a reflective wall: the cell's neighbour across it
+ *     is its own mirror image (the image's neighbours are the mirrors of the
+ *     cell's neighbours, its state the cell's with the normal momentum
+ *     negated), and the Gauss-point state beyond the wall is the mirror of the
+ *     inner one;
  *   min_big_stencil: 0 keeps the paper's big stencil (face neighbours and
  *     their face neighbours); k > 0 also grows a big stencil with fewer than
  *     k members, by the rule used for ill-posed fits (face neighbours of the
@@ -217,6 +226,7 @@ gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_param
  * gks_adjoint_work_bytes(), 256-byte aligned.  coeff_tape (optional, may be
  * NULL): the step's coefficient tape from gks_s2o4_step; when given, the two
  * reconstructions of Qn and Qstar are read from it instead of recomputed.
+ * Periodic meshes only (GKS_EINVAL on a mesh with walls).
  * Every gather runs in a fixed order (no atomics): the result is bitwise
  * reproducible, and the same with or without the tape.
  */
@@ -235,6 +245,10 @@ gks_status gks_kinetic_energy(gks_mesh *m, const double *Q, double *J_dev, doubl
 
 /* Synchronise the stream and report GKS_ENONPHYS if the sticky flag is set. */
 gks_status gks_poll_status(gks_mesh *m, void *work, gks_stream_t stream);
+
+/* Synchronise and read (then reset) the number of Gauss-point side states
+ * that fell back to first order since the last read (first_order_fallback). */
+gks_status gks_fallback_count(gks_mesh *m, void *work, int64_t *count, gks_stream_t stream);
 
 /*
  * Gauss-point flux in the local frame for a batch (kernel-level testing of the

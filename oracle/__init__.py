@@ -52,12 +52,14 @@ class Params(ctypes.Structure):
         ("tau_C", ctypes.c_double),
         ("viscous", ctypes.c_int),
         ("force_linear", ctypes.c_int),
+        ("fallback", ctypes.c_int),
     ]
 
 
 def params(gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, weno_eps=1e-6, weno_gamma_m=0.0125, weno_p=1.0, tau_eps=0.01,
-           tau_C=1.0, viscous=False, force_linear=False) -> Params:
-    return Params(gamma, cfl, mu, Pr, weno_eps, weno_gamma_m, weno_p, tau_eps, tau_C, int(viscous), int(force_linear))
+           tau_C=1.0, viscous=False, force_linear=False, fallback=False) -> Params:
+    return Params(gamma, cfl, mu, Pr, weno_eps, weno_gamma_m, weno_p, tau_eps, tau_C, int(viscous), int(force_linear),
+                  int(fallback))
 
 
 def _p(a):
@@ -107,6 +109,10 @@ def _load():
         lib.orc_stencil_members.argtypes = [vp, i64, vp, vp]
         lib.orc_stencil_members.restype = i32
         lib.orc_substencil_members.argtypes = [vp, i64, i32, vp, vp]
+        lib.orc_stencil_signs.argtypes = [vp, i64, vp]
+        lib.orc_fallback_count.argtypes = [vp]
+        lib.orc_fallback_count.restype = i64
+        lib.orc_stencil_signs.restype = i32
         lib.orc_substencil_members.restype = i32
         lib.orc_cell_faces.argtypes = [vp, i64, vp, vp]
         lib.orc_cell_faces.restype = i32
@@ -172,6 +178,16 @@ class Oracle:
         sh = np.zeros((96, 3), np.int32)
         k = _load().orc_stencil_members(self.h, c, _p(ids), _p(sh))
         return ids[:k].copy(), sh[:k].copy()
+
+    def fallback_count(self):
+        """Gauss-point sides that fell back to first order since the last call."""
+        return int(_load().orc_fallback_count(self.h))
+
+    def stencil_signs(self, c):
+        """Reflection signs [K][3] of the big stencil's members (walls mirror cells)."""
+        sg = np.zeros((96, 3), np.int32)
+        k = _load().orc_stencil_signs(self.h, c, _p(sg))
+        return sg[:k].copy()
 
     def substencil(self, c, m):
         ids = np.zeros(16, np.int64)

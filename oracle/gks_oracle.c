@@ -65,6 +65,8 @@ typedef struct {
     double tau_eps, tau_C;
     int viscous;
     int force_linear; /* use the linear weights gamma_m instead of the nonlinear ones */
+    int fallback;     /* 1: a side state at a Gauss point with rho <= 0 or p <= 0 is replaced by its
+                         cell's average with zero slopes (first order there), and counted */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -100,9 +102,14 @@ static const int MONO[9][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0}, {1, 1
 /* ------------------------------------------------------------------ */
 /* mesh state                                                           */
 /* ------------------------------------------------------------------ */
+/* A stencil member or face neighbour: the image x -> sg x + of L of a cell,
+ * sg = +-1 per axis (a reflection across a wall plane) and of an offset in
+ * units of the box (periodic images; 0 or 2 for the mirror across the wall at
+ * 0 or at L).  Momentum components of the image carry the signs sg. */
 typedef struct {
     int64_t cell;
-    int sh[3]; /* periodic image shift in units of the box */
+    int sg[3];
+    int of[3];
 } sref;
 
 #define MAXST 96
@@ -138,7 +145,8 @@ typedef struct {
 typedef struct {
     int64_t owner, nbr;
     int owner_lf;
-    int sh[3];               /* image shift of the neighbour seen from the owner */
+    sref nb;                 /* the neighbour seen from the owner: an image of nbr, or at a wall
+                                (nbr = -1) the owner's mirror image across it */
     int64_t key[4];          /* canonical node ids (sorted), -1 for triangles */
     double gp[4][3];         /* Gauss points in the owner's frame */
     double va[4][3];         /* vector area 1/4 X_eta x X_zeta, owner -> neighbour */
@@ -159,6 +167,7 @@ typedef struct {
     double *a;  /* [n][5][9] */
     double *b;  /* [n][5][8][3] */
     double *w;  /* [n][5][9] normalised weights omega_0..omega_M */
+    int64_t n_fallback; /* Gauss-point sides that fell back to first order since the last query */
     /* option: a big stencil with fewer members than this is grown like an
      * ill-posed fit (0: the paper's neighbours-of-neighbours set as it is) */
     int min_big;
@@ -374,7 +383,14 @@ static int face_nodes(const orc *o, int64_t c, int lf, int64_t v[4])
 
 static int same_sref(const sref *a, const sref *b)
 {
-    return a->cell == b->cell && a->sh[0] == b->sh[0] && a->sh[1] == b->sh[1] && a->sh[2] == b->sh[2];
+    return a->cell == b->cell && a->sg[0] == b->sg[0] && a->sg[1] == b->sg[1] && a->sg[2] == b->sg[2] &&
+           a->of[0] == b->of[0] && a->of[1] == b->of[1] && a->of[2] == b->of[2];
+}
+
+static sref sref_self(int64_t c)
+{
+    sref s = {c, {1, 1, 1}, {0, 0, 0}};
+    return s;
 }
 
 static int add_unique(sref *list, int *n, int cap, sref s)
@@ -386,18 +402,22 @@ static int add_unique(sref *list, int *n, int cap, sref s)
     return 1;
 }
 
+/* rel seen from base's cell, then base's image map: x -> sg_b (sg_r x + of_r L) + of_b L */
 static sref compose(sref base, sref rel)
 {
     sref r;
     r.cell = rel.cell;
-    for (int q = 0; q < 3; q++) r.sh[q] = base.sh[q] + rel.sh[q];
+    for (int q = 0; q < 3; q++) {
+        r.sg[q] = base.sg[q] * rel.sg[q];
+        r.of[q] = base.sg[q] * rel.of[q] + base.of[q];
+    }
     return r;
 }
 
 /* centroid of a stencil member in the frame of the cell owning the stencil */
 static void image_centroid(const orc *o, sref s, double x[3])
 {
-    for (int q = 0; q < 3; q++) x[q] = o->c[s.cell].xc[q] + s.sh[q] * o->L[q];
+    for (int q = 0; q < 3; q++) x[q] = s.sg[q] * o->c[s.cell].xc[q] + s.of[q] * o->L[q];
 }
 
 /* mean over the member's cell of (x - x0)^n for the nine monomials */
@@ -407,8 +427,10 @@ static void member_means(const orc *o, sref s, const double x0[3], double out[9]
     double xk[3];
     image_centroid(o, s, xk);
     double D[3] = {xk[0] - x0[0], xk[1] - x0[1], xk[2] - x0[2]};
-    /* second central moments of the member */
+    /* second central moments of the member (a reflection flips the mixed ones it touches) */
     double S[3][3] = {{K->m2[0], K->m2[1], K->m2[2]}, {K->m2[1], K->m2[3], K->m2[4]}, {K->m2[2], K->m2[4], K->m2[5]}};
+    for (int p = 0; p < 3; p++)
+        for (int q = 0; q < 3; q++) S[p][q] *= s.sg[p] * s.sg[q];
     for (int n = 0; n < 9; n++) {
         int e[3] = {MONO[n][0], MONO[n][1], MONO[n][2]};
         int deg = e[0] + e[1] + e[2];
@@ -461,7 +483,8 @@ static int ring_of(const orc *o, int64_t i, sref j, sref *out)
     const ocell *J = &o->c[j.cell];
     for (int p = 0; p < J->nf; p++) {
         sref s = compose(j, J->nb[p]);
-        if (s.cell == i && s.sh[0] == 0 && s.sh[1] == 0 && s.sh[2] == 0) continue;
+        sref self = sref_self(i);
+        if (same_sref(&s, &self)) continue;
         out[n++] = s;
     }
     return n;
@@ -568,7 +591,7 @@ static int well_posed(const double *A, int n, int k)
 static int grow_until_posed(const orc *o, int64_t i, const ocell *C, sref *list, int *n, int cap, int k, double h,
                             int min_rows)
 {
-    sref self = {i, {0, 0, 0}};
+    sref self = sref_self(i);
     sref cand[MAXST * 6];
     int nc = 0;
     for (int r = 0; r < *n; r++) {
@@ -596,7 +619,7 @@ static int grow_until_posed(const orc *o, int64_t i, const ocell *C, sref *list,
 static int build_stencils(orc *o, int64_t i)
 {
     ocell *C = &o->c[i];
-    sref self = {i, {0, 0, 0}};
+    sref self = sref_self(i);
     C->K = 0;
     for (int p = 0; p < C->nf; p++)
         if (add_unique(C->st, &C->K, MAXST, C->nb[p]) < 0) return 1;
@@ -738,10 +761,11 @@ orc *orc_create(int64_t n_nodes, const double *nodes, int64_t n_cells, const int
             r++;
         }
     qsort(fr, nrec_total, sizeof(frec), cmp_frec);
-    o->f = malloc(sizeof(oface) * (nrec_total / 2 + 1));
+    o->f = malloc(sizeof(oface) * (nrec_total + 1));
     int64_t nf = 0;
     for (int64_t a = 0; a < nrec_total;) {
-        if (a + 1 >= nrec_total || cmp_key4(fr[a].key, fr[a + 1].key) || (a + 2 < nrec_total && !cmp_key4(fr[a].key, fr[a + 2].key))) {
+        const int pair = a + 1 < nrec_total && !cmp_key4(fr[a].key, fr[a + 1].key);
+        if ((pair && a + 2 < nrec_total && !cmp_key4(fr[a].key, fr[a + 2].key)) || (!pair && periodic)) {
             seterr("face is not shared by exactly two cells (boundary faces need periodic matching)");
             free(fr);
             orc_destroy(o);
@@ -750,16 +774,44 @@ orc *orc_create(int64_t n_nodes, const double *nodes, int64_t n_cells, const int
         oface *F = &o->f[nf];
         F->owner = fr[a].cell;
         F->owner_lf = fr[a].lf;
-        F->nbr = fr[a + 1].cell;
+        F->nbr = pair ? fr[a + 1].cell : -1;
         memcpy(F->key, fr[a].key, sizeof F->key);
-        /* image shift: owner vertex minus the neighbour's vertex of the same canonical id */
-        int64_t vo[4], vn[4];
+        int64_t vo[4];
         int n = face_nodes(o, F->owner, fr[a].lf, vo);
-        face_nodes(o, F->nbr, fr[a + 1].lf, vn);
-        int64_t m = -1;
-        for (int q = 0; q < n && m < 0; q++)
-            if (o->canon[vn[q]] == o->canon[vo[0]]) m = vn[q];
-        for (int q = 0; q < 3; q++) F->sh[q] = (int)lround((o->nodes[3 * vo[0] + q] - o->nodes[3 * m + q]) / o->L[q]);
+        if (pair) {
+            /* image shift: owner vertex minus the neighbour's vertex of the same canonical id */
+            int64_t vn[4];
+            face_nodes(o, F->nbr, fr[a + 1].lf, vn);
+            int64_t m = -1;
+            for (int q = 0; q < n && m < 0; q++)
+                if (o->canon[vn[q]] == o->canon[vo[0]]) m = vn[q];
+            F->nb = sref_self(F->nbr);
+            for (int q = 0; q < 3; q++) F->nb.of[q] = (int)lround((o->nodes[3 * vo[0] + q] - o->nodes[3 * m + q]) / o->L[q]);
+        } else {
+            /* a wall: every vertex on the plane x_axis = 0 or L; the neighbour is the owner's mirror */
+            int axis = -1, side = 0;
+            for (int q = 0; q < 3 && axis < 0; q++) {
+                int lo = 1, hi = 1;
+                for (int v = 0; v < n; v++) {
+                    const double x = o->nodes[3 * vo[v] + q];
+                    if (fabs(x) > 1e-12 * o->L[q]) lo = 0;
+                    if (fabs(x - o->L[q]) > 1e-12 * o->L[q]) hi = 0;
+                }
+                if (lo || hi) {
+                    axis = q;
+                    side = hi;
+                }
+            }
+            if (axis < 0) {
+                seterr("boundary face not on a wall of the box");
+                free(fr);
+                orc_destroy(o);
+                return NULL;
+            }
+            F->nb = sref_self(F->owner);
+            F->nb.sg[axis] = -1;
+            F->nb.of[axis] = side ? 2 : 0;
+        }
         /* face geometry from the owner's vertices */
         double Xq[4][3];
         if (n == 4) {
@@ -790,23 +842,23 @@ orc *orc_create(int64_t n_nodes, const double *nodes, int64_t n_cells, const int
         if (s < 0)
             for (int k = 0; k < 4; k++)
                 for (int q = 0; q < 3; q++) F->va[k][q] = -F->va[k][q];
-        ocell *Co = &o->c[F->owner], *Cn = &o->c[F->nbr];
+        ocell *Co = &o->c[F->owner];
         Co->face[fr[a].lf] = nf;
         Co->fside[fr[a].lf] = 0;
-        Co->nb[fr[a].lf].cell = F->nbr;
-        Cn->face[fr[a + 1].lf] = nf;
-        Cn->fside[fr[a + 1].lf] = 1;
-        Cn->nb[fr[a + 1].lf].cell = F->owner;
-        for (int q = 0; q < 3; q++) {
-            Co->nb[fr[a].lf].sh[q] = F->sh[q];
-            Cn->nb[fr[a + 1].lf].sh[q] = -F->sh[q];
-        }
+        Co->nb[fr[a].lf] = F->nb;
         double ar = 0.0;
         for (int k = 0; k < 4; k++) ar += sqrt(F->va[k][0] * F->va[k][0] + F->va[k][1] * F->va[k][1] + F->va[k][2] * F->va[k][2]);
         Co->area_sum += ar;
-        Cn->area_sum += ar;
+        if (pair) {
+            ocell *Cn = &o->c[F->nbr];
+            Cn->face[fr[a + 1].lf] = nf;
+            Cn->fside[fr[a + 1].lf] = 1;
+            Cn->nb[fr[a + 1].lf] = sref_self(F->owner);
+            for (int q = 0; q < 3; q++) Cn->nb[fr[a + 1].lf].of[q] = -F->nb.of[q];
+            Cn->area_sum += ar;
+        }
         nf++;
-        a += 2;
+        a += pair ? 2 : 1;
     }
     free(fr);
     o->n_faces = nf;
@@ -849,6 +901,14 @@ void orc_destroy(orc *o)
 
 int64_t orc_n_faces(const orc *o) { return o->n_faces; }
 
+/* Gauss-point sides that fell back to first order since the last call (then reset) */
+int64_t orc_fallback_count(orc *o)
+{
+    const int64_t c = o->n_fallback;
+    o->n_fallback = 0;
+    return c;
+}
+
 void orc_cell_geometry(const orc *o, double *vol, double *xc, double *m2, double *area)
 {
     for (int64_t c = 0; c < o->n_cells; c++) {
@@ -875,7 +935,7 @@ void orc_face_info(const orc *o, int64_t *owner, int64_t *nbr, int64_t *key, dou
                 if (va) va[12 * f + 3 * k + q] = F->va[k][q];
             }
         for (int q = 0; q < 3; q++)
-            if (sh) sh[3 * f + q] = F->sh[q];
+            if (sh) sh[3 * f + q] = F->nb.of[q];
     }
 }
 
@@ -894,6 +954,13 @@ void orc_stencil_info(const orc *o, int64_t c, int *K, int *M, int *subn)
 /* ------------------------------------------------------------------ */
 static double Qat(const orc *o, const double *Q, int comp, int64_t cell) { return Q[comp * o->n_cells + cell]; }
 
+/* cell average of a member: its cell's, momentum components signed by the member's reflections */
+static double member_value(const orc *o, const double *Q, int comp, sref s)
+{
+    const double v = Qat(o, Q, comp, s.cell);
+    return comp >= 1 && comp <= 3 ? s.sg[comp - 1] * v : v;
+}
+
 static void weno_cell(orc *o, const orc_params *P, const double *Q, int64_t i)
 {
     ocell *C = &o->c[i];
@@ -905,12 +972,12 @@ static void weno_cell(orc *o, const orc_params *P, const double *Q, int64_t i)
         double q0 = Qat(o, Q, comp, i);
         double rhs[MAXST];
         /* P_0: least squares on the big stencil */
-        for (int k = 0; k < C->K; k++) rhs[k] = Qat(o, Q, comp, C->st[k].cell) - q0;
+        for (int k = 0; k < C->K; k++) rhs[k] = member_value(o, Q, comp, C->st[k]) - q0;
         double *ac = a + 9 * comp;
         lsq_apply(&C->ls0, rhs, ac);
         /* P_m on the sub-stencils */
         for (int m = 0; m < M; m++) {
-            for (int k = 0; k < C->subn[m]; k++) rhs[k] = Qat(o, Q, comp, C->sub[m][k].cell) - q0;
+            for (int k = 0; k < C->subn[m]; k++) rhs[k] = member_value(o, Q, comp, C->sub[m][k]) - q0;
             lsq_apply(&C->ls[m], rhs, b + 24 * comp + 3 * m);
         }
         /* smoothness indicators over Omega_0, each multi-index once */
@@ -1405,6 +1472,24 @@ static void to_local(const double n[3][3], const double val[5], const double gra
     }
 }
 
+static int physical_state(const orc_params *P, const double q[5])
+{
+    if (!(q[0] > 0.0)) return 0;
+    const double p = (P->gamma - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+    return p > 0.0;
+}
+
+/* first-order fallback of one side: the member's cell average in the local frame, zero slopes */
+static void fallback_state(const orc *o, const double *Q, sref s, const double n[3][3], double q[5], double dq[3][5])
+{
+    double v[5], g[5][3];
+    for (int c = 0; c < 5; c++) {
+        v[c] = member_value(o, Q, c, s);
+        g[c][0] = g[c][1] = g[c][2] = 0.0;
+    }
+    to_local(n, v, g, q, dq);
+}
+
 static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt, double *out)
 {
     weno_all(o, P, Q);
@@ -1414,14 +1499,32 @@ static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt
         for (int k = 0; k < 4; k++) {
             double vl[5], gl[5][3], vr[5], gr[5][3];
             weno_eval(o, P, Q, F->owner, -1, F->gp[k], vl, gl);
+            /* the neighbour's polynomial as its image: P(T^-1 x), momentum signed by the reflections */
+            const sref *T = &F->nb;
             double xr[3];
-            for (int q = 0; q < 3; q++) xr[q] = F->gp[k][q] - F->sh[q] * o->L[q];
-            weno_eval(o, P, Q, F->nbr, -1, xr, vr, gr);
+            for (int q = 0; q < 3; q++) xr[q] = T->sg[q] * (F->gp[k][q] - T->of[q] * o->L[q]);
+            weno_eval(o, P, Q, T->cell, -1, xr, vr, gr);
+            for (int c = 0; c < 5; c++)
+                for (int q = 0; q < 3; q++) gr[c][q] *= T->sg[q];
+            for (int c = 0; c < 3; c++) {
+                vr[1 + c] *= T->sg[c];
+                for (int q = 0; q < 3; q++) gr[1 + c][q] *= T->sg[c];
+            }
             double n[3][3];
             local_frame(F->va[k], n);
             double ql[5], qr[5], dql[3][5], dqr[3][5];
             to_local(n, vl, gl, ql, dql);
             to_local(n, vr, gr, qr, dqr);
+            if (P->fallback) {
+                if (!physical_state(P, ql)) {
+                    fallback_state(o, Q, sref_self(F->owner), n, ql, dql);
+                    o->n_fallback++;
+                }
+                if (!physical_state(P, qr)) {
+                    fallback_state(o, Q, F->nb, n, qr, dqr);
+                    o->n_fallback++;
+                }
+            }
             double Fb[10];
             int e = orc_gp_flux(P, ql, &dql[0][0], qr, &dqr[0][0], dt, Fb, NULL);
             if (e) return e;
@@ -1618,19 +1721,28 @@ int orc_stencil_members(const orc *o, int64_t c, int64_t *ids, int *sh)
     const ocell *C = &o->c[c];
     for (int k = 0; k < C->K; k++) {
         ids[k] = C->st[k].cell;
-        for (int q = 0; q < 3; q++) sh[3 * k + q] = C->st[k].sh[q];
+        for (int q = 0; q < 3; q++) sh[3 * k + q] = C->st[k].of[q];
     }
     return C->K;
 }
 
 /* sub-stencil m members of cell c; returns their count */
+/* reflection signs of the big stencil's members [K][3] (+1: no reflection on that axis) */
+int orc_stencil_signs(const orc *o, int64_t c, int *sg)
+{
+    const ocell *C = &o->c[c];
+    for (int k = 0; k < C->K; k++)
+        for (int q = 0; q < 3; q++) sg[3 * k + q] = C->st[k].sg[q];
+    return C->K;
+}
+
 int orc_substencil_members(const orc *o, int64_t c, int m, int64_t *ids, int *sh)
 {
     const ocell *C = &o->c[c];
     if (m < 0 || m >= C->M) return 0;
     for (int k = 0; k < C->subn[m]; k++) {
         ids[k] = C->sub[m][k].cell;
-        for (int q = 0; q < 3; q++) sh[3 * k + q] = C->sub[m][k].sh[q];
+        for (int q = 0; q < 3; q++) sh[3 * k + q] = C->sub[m][k].of[q];
     }
     return C->subn[m];
 }

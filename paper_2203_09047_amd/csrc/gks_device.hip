@@ -66,6 +66,8 @@ struct DevMesh {
     const void *dsc;        // [nnz][3] scaled member centroid offsets, FP64 or FP32
     const void *ginv;       // [48][n] inverses of the sub-stencil normal matrices / h, FP64 or FP32
     const int32_t *st_cell; // [nnz] member cells (as in st_rec)
+    const uint8_t *st_flip; // [nnz] bit d: the member is the mirror image across a wall on axis d
+    int walls;              // the mesh has reflective walls (faces with nbr = -1 - axis)
     // sub-stencil lists: the members of sub-stencil s of cell i are entries
     // ss_ptr[8 i + s] .. ss_ptr[8 i + s + 1], each the member's position in the cell's
     // stencil and B = G_s^{-1} D_k / h, so that b^s = sum B (Q_k - Q_0)
@@ -173,6 +175,12 @@ __global__ void __launch_bounds__(kBlock) k_dt_final(int nb, const double *__res
 // combined over the quad with DPP lane permutations, so every lane of the quad
 // holds bitwise-identical totals (deterministic, no atomics).
 // ---------------------------------------------------------------------------
+// sign of conserved component c of a stencil member mirrored across the walls in flip (bit d: axis d)
+__device__ __forceinline__ double mirror_sign(unsigned flip, int c)
+{
+    return c >= 1 && c <= 3 && (flip >> (c - 1) & 1u) ? -1.0 : 1.0;
+}
+
 constexpr int kK1Lanes = 4;
 constexpr int kK1CellLanes = 5 * kK1Lanes;
 constexpr int kK1Cells = 16;
@@ -450,8 +458,9 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
         // one round of independent loads for the whole block
         for (int e = e0 + (int)threadIdx.x; e < e1; e += kK1Block) {
             const int x = m.st_cell[e];
+            const unsigned fl = m.st_flip[e];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) sq[c][e - e0] = Q[(size_t)c * n + x];
+            for (int c = 0; c < 5; ++c) sq[c][e - e0] = mirror_sign(fl, c) * Q[(size_t)c * n + x];
         }
         for (int e = s0 + (int)threadIdx.x; e < s1; e += kK1Block) {
             sl[e - s0] = m.ss_loc[e];
@@ -465,7 +474,9 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
     const double *Qc = Q + (size_t)comp * n;
     const double q0 = Qc[i];
     // Q_k - Q_0 of stencil entry k, in FP64, then rounded to T
-    auto diff = [&](int k) -> T { return (T)((staged ? sq[comp][k - e0] : Qc[m.st_cell[k]]) - q0); };
+    auto diff = [&](int k) -> T {
+        return (T)((staged ? sq[comp][k - e0] : mirror_sign(m.st_flip[k], comp) * Qc[m.st_cell[k]]) - q0);
+    };
     T a[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = T(0);
@@ -545,17 +556,21 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict_
 #pragma unroll
     for (int q = 0; q < 9; ++q) geo[q] = (T)m.fgeo[(size_t)q * nf4 + tt];
     double ql0[5], qr0[5];
-    if constexpr (sizeof(T) == 4) {
+    if (sizeof(T) == 4 || fp.fallback) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             ql0[c] = Q[(size_t)c * m.n + o];
-            qr0[c] = Q[(size_t)c * m.n + nb];
+            qr0[c] = nb >= 0 ? Q[(size_t)c * m.n + nb] : 0.0;
         }
     }
     const T dt = (T)dt_dev[0];
     T out[10];
-    const bool ok = face_gp<T, PR>(coeff + (size_t)50 * o, coeff + (size_t)50 * nb, ql0, qr0, geo, dt, fp, out);
+    // nb < 0: a reflective wall, the right state is the mirror of the left one
+    int nfb = 0;
+    const bool ok = face_gp<T, PR>(coeff + (size_t)50 * o, nb >= 0 ? coeff + (size_t)50 * nb : nullptr, ql0, qr0,
+                                   geo, dt, fp, out, nfb);
     if (live && !ok) status[0] = 1;
+    if (live && nfb) atomicAdd(status + 1, nfb);  // integer count: the same total in any order
 #pragma unroll
     for (int j = 0; j < 10; ++j) {
         out[j] += shfl_xor_t(out[j], 1);
@@ -842,8 +857,9 @@ __global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3
     if (staged) {
         for (int e = e0 + (int)threadIdx.x; e < e1; e += kK1Block) {
             const int x = m.st_cell[e];
+            const unsigned fl = m.st_flip[e];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) sq[c][e - e0] = Q[(size_t)c * n + x];
+            for (int c = 0; c < 5; ++c) sq[c][e - e0] = mirror_sign(fl, c) * Q[(size_t)c * n + x];
         }
         for (int e = s0 + (int)threadIdx.x; e < s1; e += kK1Block) {
             sl[e - s0] = m.ss_loc[e];
@@ -858,7 +874,9 @@ __global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3
     const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
     const double *Qc = Q + (size_t)comp * n;
     const double q0 = Qc[i];
-    auto diff = [&](int k) -> double { return (staged ? sq[comp][k - e0] : Qc[m.st_cell[k]]) - q0; };
+    auto diff = [&](int k) -> double {
+        return (staged ? sq[comp][k - e0] : mirror_sign(m.st_flip[k], comp) * Qc[m.st_cell[k]]) - q0;
+    };
     double a[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = 0.0;
@@ -1045,6 +1063,7 @@ static FluxParams<T> flux_params(const gks_params *p)
     f.tau_eps = (T)p->tau_eps;
     f.tau_C = (T)p->tau_C;
     f.viscous = p->viscous;
+    f.fallback = p->first_order_fallback;
     return f;
 }
 
@@ -1267,6 +1286,10 @@ static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *ba
     dm.dsc = put_vec(convert_n(H.dsc));
     dm.ginv = put_vec(convert_t(H.ginv, 48));
     dm.st_cell = (const int32_t *)put(H.st_idx.data(), 4 * H.st_idx.size());
+    dm.st_flip = (const uint8_t *)put(H.st_flip.data(), H.st_flip.size());
+    dm.walls = 0;
+    for (int32_t b : H.nbr)
+        if (b < 0) dm.walls = 1;
     {
         // sub-stencil lists in slot order, members in stencil order
         int64_t nss = 0;
@@ -1405,7 +1428,7 @@ gks_status gks_reset_status(gks_mesh *m, void *work, gks_stream_t stream)
 {
     if (!m || !work) return fail(GKS_EINVAL, "null argument");
     Work w = work_of(m, work);
-    return hip_check(hipMemsetAsync(w.status, 0, sizeof(int), S(stream)), "status reset");
+    return hip_check(hipMemsetAsync(w.status, 0, 2 * sizeof(int), S(stream)), "status reset");
 }
 
 static gks_status launch_timestep(gks_mesh *m, const double *Q, const gks_params *p, double *dt_dev, Work &w,
@@ -1596,6 +1619,7 @@ gks_status gks_adjoint_step(gks_mesh *m, const double *Qn, const double *Qstar, 
     gks_status s = check_params(m, p);
     if (s) return s;
     if (m->precision != GKS_FP64) return fail(GKS_EINVAL, "the adjoint runs on an FP64 mesh");
+    if (m->d.walls) return fail(GKS_EINVAL, "the adjoint is built for periodic meshes (this one has walls)");
     if (!Qn || !Qstar || !dt_dev || !lam_np1 || !lam_n || !adj_work) return fail(GKS_EINVAL, "null argument");
     if (((uintptr_t)adj_work & 255) != 0) return fail(GKS_EINVAL, "adjoint work buffer must be 256-byte aligned");
     AdjWork aw;
@@ -1634,6 +1658,19 @@ gks_status gks_poll_status(gks_mesh *m, void *work, gks_stream_t stream)
     if ((s = hip_check(hipStreamSynchronize(S(stream)), "status sync"))) return s;
     if (flag) return fail(GKS_ENONPHYS, "non-physical state (rho <= 0 or p <= 0) met in a kernel");
     return GKS_OK;
+}
+
+gks_status gks_fallback_count(gks_mesh *m, void *work, int64_t *count, gks_stream_t stream)
+{
+    if (!m || !work || !count) return fail(GKS_EINVAL, "null argument");
+    Work w = work_of(m, work);
+    int c = 0;
+    gks_status s = hip_check(hipMemcpyAsync(&c, w.status + 1, sizeof(int), hipMemcpyDeviceToHost, S(stream)),
+                             "fallback count read");
+    if (s) return s;
+    if ((s = hip_check(hipStreamSynchronize(S(stream)), "fallback count sync"))) return s;
+    *count = c;
+    return hip_check(hipMemsetAsync(w.status + 1, 0, sizeof(int), S(stream)), "fallback count reset");
 }
 
 gks_status gks_gp_flux_batch(int64_t n, const double *ql, const double *dql, const double *qr, const double *dqr,
@@ -1759,10 +1796,12 @@ gks_status gks_gp_op_count(int viscous, double Pr, int64_t *adds, int64_t *muls,
     fp.tau_eps = Cnt(p.tau_eps);
     fp.tau_C = Cnt(p.tau_C);
     fp.viscous = p.viscous;
+    fp.fallback = 0;
     op_counts() = OpCounts();
     Cnt out[10];
-    const bool ok = (viscous && Pr != 1.0) ? face_gp<Cnt, true>(cl, cr, nullptr, nullptr, geo, Cnt(0.01), fp, out)
-                                           : face_gp<Cnt, false>(cl, cr, nullptr, nullptr, geo, Cnt(0.01), fp, out);
+    int nfb = 0;
+    const bool ok = (viscous && Pr != 1.0) ? face_gp<Cnt, true>(cl, cr, nullptr, nullptr, geo, Cnt(0.01), fp, out, nfb)
+                                           : face_gp<Cnt, false>(cl, cr, nullptr, nullptr, geo, Cnt(0.01), fp, out, nfb);
     const OpCounts c = op_counts();
     *adds = c.add;
     *muls = c.mul;

@@ -24,6 +24,7 @@ template <typename T>
 struct FluxParams {
     T gamma, K, mu, Pr, tau_eps, tau_C;
     int viscous;
+    int fallback;  // first-order fallback of non-physical side states
 };
 
 // Moments <u^k> (k <= 6), <v^k>, <w^k> (k <= 5), <s^2>, <s^4> of one normalised Maxwellian.
@@ -508,10 +509,50 @@ __host__ __device__ __forceinline__ void load_cell(const T *__restrict__ src, T 
 #endif
 }
 
+// The state beyond a reflective wall at a Gauss point: the mirror image of the inner one.  In the
+// local frame whose n1 is the wall normal the image negates the normal momentum, the normal
+// derivatives of the other variables and the tangential derivatives of the normal momentum.
+template <typename T>
+__host__ __device__ __forceinline__ void wall_mirror(const T q[5], const T dq[3][5], T qr[5], T dqr[3][5])
+{
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const T s = j == 1 ? T(-1) : T(1);
+        qr[j] = s * q[j];
+        dqr[0][j] = -s * dq[0][j];
+        dqr[1][j] = s * dq[1][j];
+        dqr[2][j] = s * dq[2][j];
+    }
+}
+
+// With fp.fallback: a side state with rho <= 0 or p <= 0 becomes its cell's average qav (FP64, global
+// frame) in the local frame with zero slopes.  Returns whether it did.
+template <typename T>
+__host__ __device__ __forceinline__ bool fallback_side(const FluxParams<T> &fp, const double *qav, const T n[3][3],
+                                                       T q[5], T dq[3][5])
+{
+    if (!fp.fallback) return false;
+    const T p = (fp.gamma - T(1)) * (q[4] - T(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+    if (q[0] > T(0) && p > T(0)) return false;
+    const T v1 = (T)qav[1], v2 = (T)qav[2], v3 = (T)qav[3];
+    q[0] = (T)qav[0];
+    q[4] = (T)qav[4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) q[1 + k] = v1 * n[k][0] + v2 * n[k][1] + v3 * n[k][2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) dq[m][j] = T(0);
+    return true;
+}
+
+// cr_g == nullptr: the face is a reflective wall and the right state is the mirror of the left one.
+// ql0, qr0: the two cells' FP64 averages (read for FP32 coefficients and for the fallback); nfb counts
+// the sides that fell back.
 template <typename T, bool PR>
 __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, const T *__restrict__ cr_g, const double *ql0,
                                                  const double *qr0, const T geo[9], T dt, const FluxParams<T> &fp,
-                                                 T out[10])
+                                                 T out[10], int &nfb)
 {
     T n3[3][3];
     const T area = local_frame(geo[6], geo[7], geo[8], n3);
@@ -522,12 +563,22 @@ __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, con
         T q[5], dq[3][5], cl[50];
         load_cell(cl_g, cl);
         side_state(cl, ql0, geo[0], geo[1], geo[2], n3, q, dq);
+        nfb += fallback_side(fp, ql0, n3, q, dq);
         ok = side_pass<T, PR>(q, dq, T(1), fp, A, 0);
     }
     {
         T q[5], dq[3][5], cr[50];
-        load_cell(cr_g, cr);
-        side_state(cr, qr0, geo[3], geo[4], geo[5], n3, q, dq);
+        if (cr_g) {
+            load_cell(cr_g, cr);
+            side_state(cr, qr0, geo[3], geo[4], geo[5], n3, q, dq);
+            nfb += fallback_side(fp, qr0, n3, q, dq);
+        } else {
+            T qi[5], dqi[3][5];
+            load_cell(cl_g, cr);
+            side_state(cr, ql0, geo[0], geo[1], geo[2], n3, qi, dqi);
+            nfb += fallback_side(fp, ql0, n3, qi, dqi);  // the mirror of a fallen-back side falls back too
+            wall_mirror(qi, dqi, q, dq);
+        }
         ok = side_pass<T, PR>(q, dq, T(-1), fp, A, 1) && ok;
     }
     T F[10];

@@ -26,9 +26,10 @@ struct HostMesh {
     // (6 unique entries xx xy xz yy yz zz for each of 8 slots)
     std::vector<int32_t> st_ptr, st_idx;
     std::vector<uint8_t> st_mask;
+    std::vector<uint8_t> st_flip;  // per member: bit d set if the member is mirrored across a wall on axis d
     std::vector<double> pinv, dsc, ginv;
     // faces
-    std::vector<int32_t> owner, nbr;
+    std::vector<int32_t> owner, nbr;  // nbr = -1 - axis for a reflective wall on that axis
     std::vector<double> fgeo;  // [9][4 nf]: d_owner(3), d_neighbour(3), weighted vector area(3) per Gauss point
     // cell -> faces in F_p order, encoded 2 * face + side (side 1: the cell is the neighbour)
     std::vector<int32_t> cf_ptr, cf_idx;

@@ -74,18 +74,32 @@ constexpr SubDef kSubTet[4] = {{{0, 1, 2}, 0}, {{0, 1, 3}, 1}, {{1, 2, 3}, 2}, {
 constexpr SubDef kSubPyr[8] = {{{0, 1, 2}, 0}, {{1, 2, 3}, 1}, {{2, 3, 0}, 2}, {{3, 0, 1}, 3},
                                {{0, 1, 4}, 0}, {{1, 2, 4}, 1}, {{2, 3, 4}, 2}, {{3, 0, 4}, 3}};
 
+// A stencil member or face neighbour: the image x -> sg x + of L of a cell, sg = +-1 per axis
+// (a reflection across a wall plane), of an offset in units of the box (periodic images; 0 or 2
+// for the mirror across the wall at 0 or at L).  The image's momentum components carry the signs sg.
 struct Member {
-    int64_t cell;  // external index
-    int sh[3];     // periodic image shift (units of the box)
+    int64_t cell = -1;  // external index
+    int sg[3] = {1, 1, 1};
+    int of[3] = {0, 0, 0};
     bool operator==(const Member &o) const
     {
-        return cell == o.cell && sh[0] == o.sh[0] && sh[1] == o.sh[1] && sh[2] == o.sh[2];
+        return cell == o.cell && sg[0] == o.sg[0] && sg[1] == o.sg[1] && sg[2] == o.sg[2] && of[0] == o.of[0] &&
+               of[1] == o.of[1] && of[2] == o.of[2];
     }
 };
 
+Member image(int64_t cell) { return Member{cell, {1, 1, 1}, {0, 0, 0}}; }
+
+// rel seen from base's cell, then base's image map
 Member shifted(const Member &base, const Member &rel)
 {
-    return Member{rel.cell, {base.sh[0] + rel.sh[0], base.sh[1] + rel.sh[1], base.sh[2] + rel.sh[2]}};
+    Member r;
+    r.cell = rel.cell;
+    for (int d = 0; d < 3; ++d) {
+        r.sg[d] = base.sg[d] * rel.sg[d];
+        r.of[d] = base.sg[d] * rel.of[d] + base.of[d];
+    }
+    return r;
 }
 
 bool contains(const std::vector<Member> &v, const Member &m) { return std::find(v.begin(), v.end(), m) != v.end(); }
@@ -265,7 +279,6 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
                       const int64_t *cells, const double *box, int periodic, int min_big, HostMesh &H)
 {
     if (!nodes || !types || !cells || !box || n_nodes <= 0 || n_cells <= 0) return fail(GKS_EINVAL, "null or empty mesh");
-    if (!periodic) return fail(GKS_EINVAL, "only periodic meshes are supported");
     if (n_cells >= (int64_t)1 << 30) return fail(GKS_EINVAL, "too many cells for 32-bit indices");
     for (int i = 0; i < 3; ++i)
         if (!(box[i] > 0)) return fail(GKS_EINVAL, "box lengths must be positive");
@@ -286,7 +299,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
             for (int i = 0; i < 3; ++i) {
                 const int64_t m = (int64_t)std::llround(q);
                 int64_t t = (int64_t)std::llround(nodes[3 * v + i] / box[i] * q);
-                k[i] = ((t % m) + m) % m;
+                k[i] = periodic ? ((t % m) + m) % m : t;
             }
             k[3] = 0;
             auto it = pos.find(k);
@@ -304,7 +317,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
             for (int i = 0; i < 3; ++i) {
                 const int64_t m = (int64_t)std::llround(q);
                 int64_t t = (int64_t)std::llround(nodes[3 * v + i] / box[i] * q);
-                k[i] = ((t % m) + m) % m;
+                k[i] = periodic ? ((t % m) + m) % m : t;
             }
             canon[v] = pos[k];
         }
@@ -327,7 +340,9 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
     std::vector<std::array<Member, 6>> nb(n);
     struct RawFace {
         Half a, b;
-        int sh[3];  // image of b's vertices as seen from a
+        int sh[3];      // image of b's vertices as seen from a
+        int wall = -1;  // b absent: the wall's axis (its side in wall_hi)
+        int wall_hi = 0;
     };
     std::vector<RawFace> raw;
     {
@@ -343,7 +358,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
                 auto it = open.find(k);
                 if (it == open.end()) {
                     open.emplace(k, (int64_t)raw.size());
-                    raw.push_back(RawFace{Half{c, lf}, Half{-1, -1}, {0, 0, 0}});
+                    raw.push_back(RawFace{Half{c, lf}, Half{-1, -1}, {0, 0, 0}, -1, 0});
                 } else {
                     RawFace &f = raw[it->second];
                     if (f.b.cell >= 0) return fail(GKS_EMESH, "face shared by more than two cells");
@@ -351,8 +366,31 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
                 }
             }
         for (auto &f : raw) {
-            if (f.b.cell < 0) return fail(GKS_EMESH, "face with one cell (mesh not closed periodically)");
             const int *sa = kFaceSlots[types[f.a.cell]][f.a.lf];
+            if (f.b.cell < 0) {
+                if (periodic) return fail(GKS_EMESH, "face with one cell (mesh not closed periodically)");
+                // a reflective wall: every vertex on the plane x_axis = 0 or L; the neighbour is the
+                // owner's mirror image across it
+                const int nv = sa[3] < 0 ? 3 : 4;
+                for (int d = 0; d < 3 && f.wall < 0; ++d) {
+                    bool lo = true, hi = true;
+                    for (int i = 0; i < nv; ++i) {
+                        const double x = nodes[3 * cells[8 * f.a.cell + sa[i]] + d];
+                        if (std::fabs(x) > 1e-12 * box[d]) lo = false;
+                        if (std::fabs(x - box[d]) > 1e-12 * box[d]) hi = false;
+                    }
+                    if (lo || hi) {
+                        f.wall = d;
+                        f.wall_hi = hi ? 1 : 0;
+                    }
+                }
+                if (f.wall < 0) return fail(GKS_EMESH, "boundary face not on a wall of the box");
+                Member g = image(f.a.cell);
+                g.sg[f.wall] = -1;
+                g.of[f.wall] = f.wall_hi ? 2 : 0;
+                nb[f.a.cell][f.a.lf] = g;
+                continue;
+            }
             const int *sb = kFaceSlots[types[f.b.cell]][f.b.lf];
             const int64_t va0 = cells[8 * f.a.cell + sa[0]];
             int64_t match = -1;
@@ -361,8 +399,8 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
                 if (canon[vb] == canon[va0]) match = vb;
             }
             for (int i = 0; i < 3; ++i) f.sh[i] = (int)std::lround((nodes[3 * va0 + i] - nodes[3 * match + i]) / box[i]);
-            nb[f.a.cell][f.a.lf] = Member{f.b.cell, {f.sh[0], f.sh[1], f.sh[2]}};
-            nb[f.b.cell][f.b.lf] = Member{f.a.cell, {-f.sh[0], -f.sh[1], -f.sh[2]}};
+            nb[f.a.cell][f.a.lf] = Member{f.b.cell, {1, 1, 1}, {f.sh[0], f.sh[1], f.sh[2]}};
+            nb[f.b.cell][f.b.lf] = Member{f.a.cell, {1, 1, 1}, {-f.sh[0], -f.sh[1], -f.sh[2]}};
         }
     }
     // Morton order of the centroids
@@ -400,15 +438,20 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
     H.st_ptr.assign(n + 1, 0);
     H.st_idx.clear();
     H.st_mask.clear();
+    H.st_flip.clear();
     H.pinv.clear();
     H.dsc.clear();
     H.ginv.clear();
     H.n_grown = 0;
 
     auto member_row = [&](const CellGeom &g0, const Member &m, int k, double h, double *row) {
-        const CellGeom &gm = geo[m.cell];
+        const CellGeom &gm0 = geo[m.cell];
+        // the image's moments: reflections flip the mixed second moments they touch
+        CellGeom gm = gm0;
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) gm.S[p][q] = m.sg[p] * m.sg[q] * gm0.S[p][q];
         double D[3];
-        for (int i = 0; i < 3; ++i) D[i] = gm.xc[i] + m.sh[i] * box[i] - g0.xc[i];
+        for (int i = 0; i < 3; ++i) D[i] = m.sg[i] * gm0.xc[i] + m.of[i] * box[i] - g0.xc[i];
         // means over the member of (x - x0)^n minus the means over the cell itself
         const double vals[9] = {D[0],
                                 D[1],
@@ -426,7 +469,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
     auto fit = [&](int64_t c, std::vector<Member> &list, int k, double h, std::vector<double> &P,
                    int min_rows) -> int {
         const CellGeom &g0 = geo[c];
-        const Member self{c, {0, 0, 0}};
+        const Member self = image(c);
         std::vector<Member> cand;
         for (const Member &m : list)
             for (int p = 0; p < kFaces[types[m.cell]]; ++p) {
@@ -459,7 +502,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
 
     struct CellOut {
         std::vector<int32_t> idx;
-        std::vector<uint8_t> mask;
+        std::vector<uint8_t> mask, flip;
         std::vector<double> pinv, dsc, ginv;
         int grown = 0;
         int err = 0;  // 0 ok, 1 big fit singular, 2 sub fit singular, 3 too large
@@ -469,7 +512,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         const int64_t c = perm[i];
         const int t = types[c];
         const CellGeom &g = geo[c];
-        const Member self{c, {0, 0, 0}};
+        const Member self = image(c);
         H.type[i] = (int8_t)t;
         H.vol[i] = g.vol;
         for (int d = 0; d < 3; ++d) H.xc[3 * i + d] = g.xc[d];
@@ -546,7 +589,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         std::vector<std::array<double, 3>> Ds(members.size());
         for (size_t k = 0; k < members.size(); ++k)
             for (int d = 0; d < 3; ++d)
-                Ds[k][d] = (geo[members[k].cell].xc[d] + members[k].sh[d] * box[d] - g.xc[d]) / h;
+                Ds[k][d] = (members[k].sg[d] * geo[members[k].cell].xc[d] + members[k].of[d] * box[d] - g.xc[d]) / h;
         out.ginv.assign(48, 0.0);
         for (int m = 0; m < M; ++m) {
             double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -572,6 +615,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
                     if (slot[m][e] == (int)k) mask |= (uint8_t)(1u << m);
             out.idx.push_back((int32_t)members[k].cell);  // external for now
             out.mask.push_back(mask);
+            out.flip.push_back((uint8_t)((members[k].sg[0] < 0) | (members[k].sg[1] < 0) << 1 | (members[k].sg[2] < 0) << 2));
             for (int j = 0; j < 9; ++j)
                 out.pinv.push_back((int)k < nls ? P0[(size_t)j * nls + k] : 0.0);
             for (int d = 0; d < 3; ++d) out.dsc.push_back(Ds[k][d]);
@@ -588,6 +632,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         H.st_ptr[i + 1] = H.st_ptr[i] + (int32_t)o.idx.size();
         H.st_idx.insert(H.st_idx.end(), o.idx.begin(), o.idx.end());
         H.st_mask.insert(H.st_mask.end(), o.mask.begin(), o.mask.end());
+        H.st_flip.insert(H.st_flip.end(), o.flip.begin(), o.flip.end());
         H.pinv.insert(H.pinv.end(), o.pinv.begin(), o.pinv.end());
         H.dsc.insert(H.dsc.end(), o.dsc.begin(), o.dsc.end());
         H.ginv.insert(H.ginv.end(), o.ginv.begin(), o.ginv.end());
@@ -596,6 +641,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         std::vector<double>().swap(o.dsc);
         std::vector<double>().swap(o.ginv);
         std::vector<uint8_t>().swap(o.mask);
+        std::vector<uint8_t>().swap(o.flip);
     }
     for (auto &v : H.st_idx) v = (int32_t)inv[v];
 
@@ -604,7 +650,8 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
     std::vector<int64_t> forder(nf);
     std::vector<std::pair<int64_t, int64_t>> fkey(nf);
     for (int64_t f = 0; f < nf; ++f) {
-        int64_t a = inv[raw[f].a.cell], b = inv[raw[f].b.cell];
+        const int64_t a = inv[raw[f].a.cell];
+        const int64_t b = raw[f].b.cell >= 0 ? inv[raw[f].b.cell] : INT64_MAX;  // walls after the owner's faces
         fkey[f] = {std::min(a, b), std::max(a, b)};
         forder[f] = f;
     }
@@ -618,13 +665,16 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
     for (int64_t i = 0; i < n; ++i) cf[i].resize(kFaces[H.type[i]], {-1, -1});
     for (int64_t fo = 0; fo < nf; ++fo) {
         const RawFace &r = raw[forder[fo]];
-        const bool a_owns = inv[r.a.cell] < inv[r.b.cell];
+        const bool wall = r.b.cell < 0;
+        const bool a_owns = wall || inv[r.a.cell] < inv[r.b.cell];
         const Half own = a_owns ? r.a : r.b;
         const Half oth = a_owns ? r.b : r.a;
-        int sh[3];  // image of the neighbour as seen from the owner
-        for (int d = 0; d < 3; ++d) sh[d] = a_owns ? r.sh[d] : -r.sh[d];
+        // the neighbour's image as seen from the owner: a periodic image, or the owner's mirror
+        Member img = wall ? nb[own.cell][own.lf] : image(oth.cell);
+        if (!wall)
+            for (int d = 0; d < 3; ++d) img.of[d] = a_owns ? r.sh[d] : -r.sh[d];
         H.owner[fo] = (int32_t)inv[own.cell];
-        H.nbr[fo] = (int32_t)inv[oth.cell];
+        H.nbr[fo] = wall ? -1 - r.wall : (int32_t)inv[oth.cell];
         const int *sl = kFaceSlots[types[own.cell]][own.lf];
         double V[4][3];
         if (sl[3] >= 0) {
@@ -639,7 +689,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         }
         double gp[4][3], va[4][3];
         face_points(V, gp, va);
-        const CellGeom &go = geo[own.cell], &gn = geo[oth.cell];
+        const CellGeom &go = geo[own.cell], &gn = geo[img.cell];
         double orient = 0;
         for (int k = 0; k < 4; ++k)
             for (int d = 0; d < 3; ++d) orient += va[k][d] * (gp[k][d] - go.xc[d]);
@@ -648,7 +698,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         for (int k = 0; k < 4; ++k) {
             for (int d = 0; d < 3; ++d) {
                 const double dl = gp[k][d] - go.xc[d];
-                const double dr = gp[k][d] - (gn.xc[d] + sh[d] * box[d]);
+                const double dr = gp[k][d] - (img.sg[d] * gn.xc[d] + img.of[d] * box[d]);
                 H.fgeo[(size_t)(0 + d) * 4 * nf + 4 * fo + k] = dl;
                 H.fgeo[(size_t)(3 + d) * 4 * nf + 4 * fo + k] = dr;
                 H.fgeo[(size_t)(6 + d) * 4 * nf + 4 * fo + k] = s * va[k][d];
@@ -656,9 +706,11 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
             ar += std::sqrt(va[k][0] * va[k][0] + va[k][1] * va[k][1] + va[k][2] * va[k][2]);
         }
         area_sum[inv[own.cell]] += ar;
-        area_sum[inv[oth.cell]] += ar;
         cf[inv[own.cell]][own.lf] = {(int)fo, 0};
-        cf[inv[oth.cell]][oth.lf] = {(int)fo, 1};
+        if (!wall) {
+            area_sum[inv[oth.cell]] += ar;
+            cf[inv[oth.cell]][oth.lf] = {(int)fo, 1};
+        }
     }
     H.cf_ptr.assign(n + 1, 0);
     H.cf_idx.clear();

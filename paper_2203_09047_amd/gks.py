@@ -7,6 +7,7 @@ missing or no GPU is present: there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 
@@ -23,7 +24,7 @@ SYMBOLS = [
     "gks_default_params", "gks_preprocess", "gks_host_mesh_free", "gks_host_mesh_counts", "gks_host_mesh_perm",
     "gks_host_mesh_geometry", "gks_host_mesh_faces", "gks_mesh_sizes", "gks_init_mesh", "gks_destroy_mesh",
     "gks_reset_status", "gks_timestep", "gks_reconstruct", "gks_flux", "gks_residual", "gks_s2o4_step",
-    "gks_poll_status", "gks_gp_flux_batch", "gks_profile", "gks_profile_read", "gks_gp_op_count",
+    "gks_poll_status", "gks_fallback_count", "gks_gp_flux_batch", "gks_profile", "gks_profile_read", "gks_gp_op_count",
     "gks_gp_flux_host", "gks_gp_flux_vjp_host", "gks_weno_combine_host", "gks_weno_combine_vjp_host",
     "gks_adjoint_work_bytes", "gks_adjoint_step", "gks_kinetic_energy", "gks_last_error",
 ]
@@ -43,6 +44,7 @@ class Params(ctypes.Structure):
         ("weno_eps", ctypes.c_double), ("weno_gamma_m", ctypes.c_double), ("weno_p", ctypes.c_double),
         ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double), ("viscous", ctypes.c_int),
         ("precision", ctypes.c_int), ("force_linear", ctypes.c_int), ("dt_given", ctypes.c_int),
+        ("first_order_fallback", ctypes.c_int),
     ]
 
 
@@ -94,6 +96,8 @@ def load():
         lib.gks_s2o4_step.argtypes = [vp, vp, vp, pp, vp, vp, vp, vp]
         lib.gks_s2o4_step.restype = st
         lib.gks_poll_status.argtypes = [vp, vp, vp]
+        lib.gks_fallback_count.argtypes = [vp, vp, ctypes.POINTER(i64), vp]
+        lib.gks_fallback_count.restype = st
         lib.gks_poll_status.restype = st
         lib.gks_gp_flux_batch.argtypes = [i64, vp, vp, vp, vp, vp, vp, pp, vp]
         lib.gks_gp_flux_batch.restype = st
@@ -138,13 +142,14 @@ def _dp(t):
 
 
 def params(precision=FP64, gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, viscous=False, weno_eps=1e-6, weno_gamma_m=0.0125,
-           weno_p=1.0, tau_eps=0.01, tau_C=1.0, force_linear=False, dt_given=False) -> Params:
+           weno_p=1.0, tau_eps=0.01, tau_C=1.0, force_linear=False, dt_given=False, fallback=False) -> Params:
     p = Params()
     load().gks_default_params(ctypes.byref(p))
     p.gamma, p.cfl, p.mu, p.Pr = gamma, cfl, mu, Pr
     p.weno_eps, p.weno_gamma_m, p.weno_p = weno_eps, weno_gamma_m, weno_p
     p.tau_eps, p.tau_C = tau_eps, tau_C
     p.viscous, p.precision, p.force_linear, p.dt_given = int(viscous), int(precision), int(force_linear), int(dt_given)
+    p.first_order_fallback = int(fallback)
     return p
 
 
@@ -348,6 +353,12 @@ class Solver:
     def poll(self):
         _check(load().gks_poll_status(self.m, self._work_ptr, self._s()))
 
+    def fallback_count(self):
+        """Gauss-point side states that fell back to first order since the last call (synchronises)."""
+        c = ctypes.c_int64()
+        _check(load().gks_fallback_count(self.m, self._work_ptr, ctypes.byref(c), self._s()))
+        return c.value
+
     def run(self, Q, nsteps=0, t_end=0.0):
         """Advance nsteps steps, or to t_end with the last step shortened; returns the step sizes."""
         dts = []
@@ -360,6 +371,11 @@ class Solver:
                 break
             if t_end > 0:
                 dt = float(self.timestep(Q).item())
+                # the step size is read back anyway: stop at the first non-physical state instead of
+                # marching a broken field with ever smaller steps
+                self.poll()
+                if not (math.isfinite(dt) and dt > 0.0):
+                    raise GksError(GKS_ENONPHYS, f"time step {dt} at t = {t}")
                 dt = min(dt, t_end - t)
                 self.step(Q, dt)
             else:
@@ -368,6 +384,8 @@ class Solver:
             dts.append(dt)
             if dt is not None:
                 t += dt
+        if t_end > 0:
+            self.poll()
         return dts
 
 

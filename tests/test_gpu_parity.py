@@ -211,6 +211,94 @@ def test_taylor_green_navier_stokes_fp64_parity(gks):
     assert (err <= TOL).all(), err
 
 
+@pytest.mark.parametrize("kind", ["hex", "hybrid"])
+def test_reflective_walls_fp64_parity(gks, kind):
+    """Walls on the six faces of [0, pi]^3, Taylor-Green field (Mach 0.3), 3 steps: GPU = oracle."""
+    print(f"case: walls {kind} N=5 x 3 steps", flush=True)
+    mesh = inputs.lattice(5, kind, box=(np.pi,) * 3, periodic=False)
+    Q0 = inputs.cell_averages(mesh, inputs.tgv(mach=0.3))
+    got, ref, *_ = _run_both(gks, mesh, Q0, nsteps=3)
+    scale = np.abs(ref).max(axis=1)
+    scale[1:4] = scale[1:4].max()
+    err = np.abs(got - ref).max(axis=1) / scale
+    print("relative Linf per component:", err)
+    assert (err <= TOL).all(), err
+
+
+@pytest.mark.parametrize("kind", ["hex", "tet", "pyr", "prism", "hybrid"])
+def test_closed_box_at_rest_on_gpu(gks, kind):
+    import torch
+
+    mesh = inputs.lattice(4, kind, periodic=False)
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host)
+    Q0 = host.to_internal(inputs.cell_averages(mesh, inputs.uniform(1.3, 0.0, 0.0, 0.0, 0.9)))
+    Q = sol.upload(Q0)
+    sol.step(Q)
+    sol.poll()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(Q.cpu().numpy(), Q0, rtol=0, atol=5e-15 * np.abs(Q0).max())
+
+
+def test_walls_conserve_mass_and_energy_on_gpu(gks):
+    import torch
+
+    mesh = inputs.lattice(8, "hybrid", box=(np.pi,) * 3, periodic=False)
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host)
+    Q0 = host.to_internal(inputs.cell_averages(mesh, inputs.tgv(mach=0.3)))
+    Q = sol.upload(Q0)
+    sol.run(Q, nsteps=5)
+    sol.poll()
+    torch.cuda.synchronize()
+    vol, _ = host.geometry()
+    t0, t1 = (Q0 * vol).sum(axis=1), (Q.cpu().numpy() * vol).sum(axis=1)
+    np.testing.assert_allclose(t1[[0, 4]], t0[[0, 4]], rtol=1e-14)
+
+
+def test_first_order_fallback_matches_oracle(gks):
+    """The walled 3-D Riemann problem on the hybrid lattice (N = 6), first-order fallback on, 3 steps
+    with the oracle's step sizes: the same states to 1e-12 and the same number of fallbacks."""
+    import torch
+
+    print("case: walls + fallback, hybrid N=6 Riemann x 3 steps", flush=True)
+    mesh = inputs.lattice(6, "hybrid", periodic=False)
+    Q0 = inputs.cell_averages(mesh, inputs.riemann())
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host, gks.params(fallback=True))
+    o = oracle.Oracle(mesh, oracle.params(fallback=True))
+    Q = sol.upload(host.to_internal(Q0))
+    ref = Q0.copy()
+    for _ in range(3):
+        dt = o.timestep(ref)
+        ref = o.step(ref, dt)
+        sol.step(Q, dt)
+    sol.poll()
+    torch.cuda.synchronize()
+    nf_gpu, nf_orc = sol.fallback_count(), o.fallback_count()
+    print("fallbacks gpu", nf_gpu, "oracle", nf_orc)
+    assert nf_gpu == nf_orc > 0
+    got = host.to_external(Q.cpu().numpy())
+    scale = np.abs(ref).max(axis=1)
+    scale[1:4] = scale[1:4].max()
+    err = np.abs(got - ref).max(axis=1) / scale
+    print("relative Linf per component:", err)
+    assert (err <= TOL).all(), err
+
+
+def test_adjoint_refuses_walls(gks):
+    import torch
+
+    mesh = inputs.lattice(3, "hex", periodic=False)
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host)
+    Q = sol.upload(host.to_internal(inputs.cell_averages(mesh, inputs.uniform())))
+    dtt = torch.tensor([1e-3], dtype=torch.float64, device=Q.device)
+    with pytest.raises(gks.GksError) as e:
+        sol.adjoint_step(Q, Q.clone(), dtt, torch.zeros_like(Q))
+    assert e.value.code == gks.GKS_EINVAL
+
+
 def test_fp32_mixed_error_against_oracle(gks):
     print("case: fp32-mixed hybrid N=6 x 3 steps", flush=True)
     mesh = inputs.lattice(6, "hybrid")

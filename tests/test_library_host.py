@@ -59,6 +59,30 @@ def test_preprocessor_matches_oracle_construction(kind, N):
     assert pairs == opairs
 
 
+@pytest.mark.parametrize("kind", ["hex", "hybrid"])
+def test_preprocessor_walls_match_oracle(kind):
+    """Reflective walls: the same interior face pairs as the oracle, one wall face per boundary face,
+    the same volumes and centroids."""
+    mesh = inputs.lattice(4, kind, periodic=False)
+    host = gks.HostMesh(mesh)
+    o = oracle.Oracle(mesh)
+    assert host.n_faces == o.n_faces
+    owner, nbr = host.faces()
+    fi = o.face_info()
+    walls = nbr < 0
+    assert walls.sum() == (fi["nbr"] < 0).sum() > 0
+    assert set((-1 - nbr[walls]).tolist()) == {0, 1, 2}
+    pairs = sorted(tuple(sorted((host.perm[a], host.perm[b]))) for a, b in zip(owner[~walls], nbr[~walls]))
+    ow = fi["nbr"] >= 0
+    opairs = sorted(tuple(sorted((a, b))) for a, b in zip(fi["owner"][ow], fi["nbr"][ow]))
+    assert pairs == opairs
+    assert sorted(host.perm[owner[walls]].tolist()) == sorted(fi["owner"][~ow].tolist())
+    vol, xc = host.geometry()
+    ovol, oxc, _, _ = o.cell_geometry()
+    np.testing.assert_allclose(vol, ovol[host.perm], rtol=1e-14, atol=0)
+    assert host.n_grown == sum(o.grown(c) for c in range(mesh.n_cells))
+
+
 def test_preprocessor_rejects_bad_meshes():
     mesh = inputs.lattice(3, "hex")
     bad_types = mesh.types.copy()

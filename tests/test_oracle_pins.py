@@ -618,6 +618,93 @@ def test_linear_scheme_stable_on_hybrid_lattice_only_with_16_member_stencils():
     assert l1 < 1e-2 and linf < 5e-2, (l1, linf)
 
 
+# ---------------------------------------------------------------------------
+# reflective walls (mirror-image ghosts)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["hex", "tet", "pyr", "prism", "hybrid"])
+def test_closed_box_at_rest_stays_at_rest(kind):
+    m = inputs.lattice(4, kind, periodic=False)
+    o = oracle.Oracle(m)
+    Q = inputs.cell_averages(m, inputs.uniform(1.3, 0.0, 0.0, 0.0, 0.9))
+    Q1 = o.step(Q, o.timestep(Q))
+    np.testing.assert_allclose(Q1, Q, rtol=0, atol=5e-15 * np.abs(Q).max())
+
+
+def test_walls_conserve_mass_and_energy():
+    m = inputs.lattice(5, "hybrid", box=(np.pi,) * 3, periodic=False)
+    o = oracle.Oracle(m)
+    Q = inputs.cell_averages(m, inputs.tgv(mach=0.3))
+    vol, _, _, _ = o.cell_geometry()
+    Q1, _ = o.run(Q, nsteps=3)
+    tot0, tot1 = (Q * vol).sum(axis=1), (Q1 * vol).sum(axis=1)
+    np.testing.assert_allclose(tot1[[0, 4]], tot0[[0, 4]], rtol=1e-14)
+    assert np.abs(tot1[1:4] - tot0[1:4]).max() > 1e-6  # the walls push back
+
+
+def test_walls_equal_the_mirrored_periodic_box():
+    """The Taylor-Green field is even or odd about every plane x_d = 0 and x_d = pi (its normal
+    momentum odd, everything else even), so on hexahedra the box [0, pi]^3 with walls must evolve
+    exactly like [0, 2 pi]^3 periodic restricted to [0, pi]^3: the wall's ghosts are the cells of
+    the mirrored half."""
+    L = np.pi
+    mw = inputs.lattice(4, "hex", box=(L, L, L), periodic=False)
+    mp = inputs.lattice(8, "hex", box=(2 * L, 2 * L, 2 * L))
+    ow, op = oracle.Oracle(mw), oracle.Oracle(mp)
+    Qw = inputs.cell_averages(mw, inputs.tgv(mach=0.3))
+    _, xw, _, _ = ow.cell_geometry()
+    _, xp, _, _ = op.cell_geometry()
+    key = lambda x: tuple(np.round(x * 1e6).astype(np.int64))
+    idx = {key(x): i for i, x in enumerate(xw)}
+    # the doubled box's data: mirror images of the walled box's averages (normal momenta negated)
+    Qp = np.empty((5, mp.n_cells))
+    for i, x in enumerate(xp):
+        s = np.where(x > L, -1.0, 1.0)
+        w = idx[key(np.where(x > L, 2 * L - x, x))]
+        Qp[:, i] = Qw[:, w]
+        Qp[1:4, i] *= s
+    idx_p = {key(x): i for i, x in enumerate(xp)}
+    sel = np.array([idx_p[key(x)] for x in xw])
+    dt = 0.5 * ow.timestep(Qw)
+    for _ in range(3):
+        Qw, Qp = ow.step(Qw, dt), op.step(Qp, dt)
+    np.testing.assert_allclose(Qw, Qp[:, sel], rtol=0, atol=1e-13 * np.abs(Qp).max())
+
+
+# ---------------------------------------------------------------------------
+# first-order fallback at non-physical Gauss-point states (optional)
+# ---------------------------------------------------------------------------
+def test_fallback_inactive_on_smooth_data():
+    """Where every reconstructed state is physical the option changes nothing, bit for bit."""
+    m = inputs.lattice(4, "hybrid")
+    Q0 = inputs.cell_averages(m, inputs.wave())
+    Qa, _ = oracle.Oracle(m).run(Q0, nsteps=2)
+    ob = oracle.Oracle(m, oracle.params(fallback=True))
+    Qb, _ = ob.run(Q0, nsteps=2)
+    assert ob.fallback_count() == 0
+    assert np.array_equal(Qa, Qb)
+
+
+def test_fallback_keeps_walled_riemann_problem_physical_and_conservative():
+    """The planar Riemann problem in the closed unit box (hybrid lattice, N = 5) to t = 0.15: the
+    scheme as printed reaches a non-physical state; with the fallback the densities and pressures
+    stay positive, close to the smaller initial state's from below, and mass and energy are
+    conserved to round-off because the fallback changes states, not the flux balance."""
+    m = inputs.lattice(5, "hybrid", periodic=False)
+    Q0 = inputs.cell_averages(m, inputs.riemann())
+    with pytest.raises(oracle.OracleError):
+        oracle.Oracle(m).run(Q0, t_end=0.15)
+    o = oracle.Oracle(m, oracle.params(fallback=True))
+    Q, dts = o.run(Q0, t_end=0.15)
+    assert abs(sum(dts) - 0.15) < 1e-14
+    assert o.fallback_count() > 0
+    rho = Q[0]
+    p = 0.4 * (Q[4] - 0.5 * (Q[1:4] ** 2).sum(axis=0) / rho)
+    assert rho.min() > 0.08 and p.min() > 0.06, (rho.min(), p.min())
+    vol = o.cell_geometry()[0]
+    tot0, tot1 = (Q0 * vol).sum(axis=1), (Q * vol).sum(axis=1)
+    np.testing.assert_allclose(tot1[[0, 4]], tot0[[0, 4]], rtol=1e-14)
+
+
 @pytest.mark.slow
 def test_third_order_convergence_on_hexahedra():
     errs = []
