@@ -84,6 +84,9 @@ typedef struct {
     int first_order_fallback; /* 1: a reconstructed side state at a Gauss point with rho <= 0 or
                                  p <= 0 is replaced by its cell's average with zero slopes (first
                                  order there) and counted (gks_fallback_count); 0: the paper's scheme */
+    double fallback_floor;    /* with first_order_fallback: a side state also falls back when its
+                                 rho or p is at most fallback_floor times its cell average's
+                                 (0: positivity only; must lie in [0, 1)) */
 } gks_params;
 
 typedef struct gks_host_mesh gks_host_mesh;
@@ -134,8 +137,14 @@ gks_status gks_host_mesh_counts(const gks_host_mesh *h, int64_t *n_cells, int64_
 gks_status gks_host_mesh_perm(const gks_host_mesh *h, int64_t *perm);
 /* per cell (internal order): volume, centroid [n][3]; either pointer may be NULL */
 gks_status gks_host_mesh_geometry(const gks_host_mesh *h, double *vol, double *xc);
-/* per face: owner and neighbour (internal indices) */
+/* per face: owner and neighbour (internal indices; a wall face has neighbour -1 - axis) */
 gks_status gks_host_mesh_faces(const gks_host_mesh *h, int32_t *owner, int32_t *nbr);
+/*
+ * Face Gauss-point geometry [9][4 n_faces] (Gauss point 4 f + g): offset from
+ * the owner's centroid (3), offset from the neighbour's (image) centroid (3),
+ * weighted vector area (3), as the flux kernel reads it.
+ */
+gks_status gks_host_mesh_face_geometry(const gks_host_mesh *h, double *fgeo);
 
 /*
  * Bytes of the device mesh arena and of the work buffer for a precision.
@@ -226,8 +235,9 @@ gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_param
  * gks_adjoint_work_bytes(), 256-byte aligned.  coeff_tape (optional, may be
  * NULL): the step's coefficient tape from gks_s2o4_step; when given, the two
  * reconstructions of Qn and Qstar are read from it instead of recomputed.
- * Periodic meshes only (GKS_EINVAL on a mesh with walls).
- * Every gather runs in a fixed order (no atomics): the result is bitwise
+ * Periodic meshes only (GKS_EINVAL on a mesh with walls), and the
+ * first-order fallback off (GKS_EINVAL otherwise: its switch is not
+ * differentiated).  Every gather runs in a fixed order (no atomics): the result is bitwise
  * reproducible, and the same with or without the tape.
  */
 gks_status gks_adjoint_work_bytes(const gks_host_mesh *h, size_t *bytes);
@@ -284,8 +294,10 @@ gks_status gks_profile_read(gks_mesh *m, double *total_ms, int64_t *launches);
 
 /*
  * Host (CPU) execution of the same templated Gauss-point flux and of its
- * hand-written reverse (vector-Jacobian product), FP64, for testing the
- * adjoint against finite differences.  Arguments as gks_gp_flux_batch for
+ * hand-written reverse (vector-Jacobian product), for testing the adjoint
+ * against finite differences.  gks_gp_flux_host runs in FP32 arithmetic when
+ * p->precision is GKS_FP32_MIXED (inputs and outputs stay FP64), else FP64;
+ * the reverse is FP64.  Arguments as gks_gp_flux_batch for
  * one point (host pointers); outb [10] is the cotangent of (Fbar0, Fbar1),
  * qlb, qrb [5] and dqlb, dqrb [3][5] receive the input cotangents.
  */

@@ -67,6 +67,8 @@ typedef struct {
     int force_linear; /* use the linear weights gamma_m instead of the nonlinear ones */
     int fallback;     /* 1: a side state at a Gauss point with rho <= 0 or p <= 0 is replaced by its
                          cell's average with zero slopes (first order there), and counted */
+    double fallback_floor; /* with fallback: also when rho or p is at most this fraction of the
+                              cell average's */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -1479,6 +1481,21 @@ static int physical_state(const orc_params *P, const double q[5])
     return p > 0.0;
 }
 
+/* a side state that keeps its reconstruction: rho and p positive and, with a floor, above that
+   fraction of the side cell's average density and pressure */
+static int admissible_state(const orc *o, const orc_params *P, const double *Q, sref s, const double q[5])
+{
+    if (!physical_state(P, q)) return 0;
+    if (P->fallback_floor > 0.0) {
+        double v[5];
+        for (int c = 0; c < 5; c++) v[c] = member_value(o, Q, c, s);
+        const double pav = (P->gamma - 1.0) * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
+        const double p = (P->gamma - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+        if (!(q[0] > P->fallback_floor * v[0]) || !(p > P->fallback_floor * pav)) return 0;
+    }
+    return 1;
+}
+
 /* first-order fallback of one side: the member's cell average in the local frame, zero slopes */
 static void fallback_state(const orc *o, const double *Q, sref s, const double n[3][3], double q[5], double dq[3][5])
 {
@@ -1516,11 +1533,11 @@ static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt
             to_local(n, vl, gl, ql, dql);
             to_local(n, vr, gr, qr, dqr);
             if (P->fallback) {
-                if (!physical_state(P, ql)) {
+                if (!admissible_state(o, P, Q, sref_self(F->owner), ql)) {
                     fallback_state(o, Q, sref_self(F->owner), n, ql, dql);
                     o->n_fallback++;
                 }
-                if (!physical_state(P, qr)) {
+                if (!admissible_state(o, P, Q, F->nb, qr)) {
                     fallback_state(o, Q, F->nb, n, qr, dqr);
                     o->n_fallback++;
                 }

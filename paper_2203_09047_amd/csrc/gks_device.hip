@@ -540,7 +540,9 @@ __device__ __forceinline__ T shfl_xor_t(T v, int mask)
     return __shfl_xor(v, mask, 64);
 }
 
-template <typename T, bool PR>
+// EXT: walls or the first-order fallback can occur (a separate instantiation keeps the periodic
+// kernel free of both branches)
+template <typename T, bool PR, bool EXT>
 __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict__ coeff, const double *__restrict__ Q,
                                                  const double *__restrict__ dt_dev, T *__restrict__ ff, FluxParams<T> fp,
                                                  int *status)
@@ -556,7 +558,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict_
 #pragma unroll
     for (int q = 0; q < 9; ++q) geo[q] = (T)m.fgeo[(size_t)q * nf4 + tt];
     double ql0[5], qr0[5];
-    if (sizeof(T) == 4 || fp.fallback) {
+    if (sizeof(T) == 4 || EXT) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             ql0[c] = Q[(size_t)c * m.n + o];
@@ -567,10 +569,10 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict_
     T out[10];
     // nb < 0: a reflective wall, the right state is the mirror of the left one
     int nfb = 0;
-    const bool ok = face_gp<T, PR>(coeff + (size_t)50 * o, nb >= 0 ? coeff + (size_t)50 * nb : nullptr, ql0, qr0,
-                                   geo, dt, fp, out, nfb);
+    const bool ok = face_gp<T, PR, EXT>(coeff + (size_t)50 * o, nb >= 0 ? coeff + (size_t)50 * nb : nullptr, ql0,
+                                        qr0, geo, dt, fp, out, nfb);
     if (live && !ok) status[0] = 1;
-    if (live && nfb) atomicAdd(status + 1, nfb);  // integer count: the same total in any order
+    if (EXT && live && nfb) atomicAdd(status + 1, nfb);  // integer count: the same total in any order
 #pragma unroll
     for (int j = 0; j < 10; ++j) {
         out[j] += shfl_xor_t(out[j], 1);
@@ -1064,6 +1066,7 @@ static FluxParams<T> flux_params(const gks_params *p)
     f.tau_C = (T)p->tau_C;
     f.viscous = p->viscous;
     f.fallback = p->first_order_fallback;
+    f.floor = p->fallback_floor;
     return f;
 }
 
@@ -1187,6 +1190,13 @@ gks_status gks_host_mesh_geometry(const gks_host_mesh *h, double *vol, double *x
     if (!h) return fail(GKS_EINVAL, "null mesh");
     if (vol) std::memcpy(vol, h->h.vol.data(), sizeof(double) * h->h.n);
     if (xc) std::memcpy(xc, h->h.xc.data(), sizeof(double) * 3 * h->h.n);
+    return GKS_OK;
+}
+
+gks_status gks_host_mesh_face_geometry(const gks_host_mesh *h, double *fgeo)
+{
+    if (!h || !fgeo) return fail(GKS_EINVAL, "null argument");
+    std::memcpy(fgeo, h->h.fgeo.data(), sizeof(double) * h->h.fgeo.size());
     return GKS_OK;
 }
 
@@ -1414,6 +1424,7 @@ static gks_status check_params(const gks_mesh *m, const gks_params *p)
     if (!(p->gamma > 1.0) || !(p->cfl > 0.0)) return fail(GKS_EINVAL, "bad gamma or cfl");
     if (p->viscous && !(p->mu >= 0.0)) return fail(GKS_EINVAL, "bad viscosity");
     if (!(p->Pr > 0.0)) return fail(GKS_EINVAL, "bad Prandtl number");
+    if (!(p->fallback_floor >= 0.0 && p->fallback_floor < 1.0)) return fail(GKS_EINVAL, "fallback_floor outside [0, 1)");
     return GKS_OK;
 }
 
@@ -1467,24 +1478,38 @@ static gks_status launch_reconstruct(gks_mesh *m, const double *Q, void *coeff, 
     return hip_check(hipGetLastError(), "reconstruct launch");
 }
 
+extern "C++" template <typename T, bool PR>
+static void launch_flux_t(gks_mesh *m, bool ext, unsigned grid, const T *coeff, const double *Q, const double *dt_dev,
+                          T *ff, const FluxParams<T> &fp, int *status, hipStream_t st)
+{
+    if (ext)
+        k_flux<T, PR, true><<<grid, kBlock, 0, st>>>(m->d, coeff, Q, dt_dev, ff, fp, status);
+    else
+        k_flux<T, PR, false><<<grid, kBlock, 0, st>>>(m->d, coeff, Q, dt_dev, ff, fp, status);
+}
+
 static gks_status launch_flux(gks_mesh *m, const void *coeff, const double *Q, const double *dt_dev, void *ff,
                               const gks_params *p, Work &w, hipStream_t st)
 {
     const unsigned grid = grid_for(4 * m->nf, kBlock);
     ProfScope ps(m, GKS_K_FLUX, st);
     const bool pr = p->viscous && p->Pr != 1.0;
+    // wall faces (neighbour < 0) and the fallback exist only in the EXT instantiation
+    const bool ext = m->d.walls || p->first_order_fallback;
     if (m->precision == GKS_FP64) {
         auto fp = flux_params<double>(p);
+        const double *c = (const double *)coeff;
         if (pr)
-            k_flux<double, true><<<grid, kBlock, 0, st>>>(m->d, (const double *)coeff, Q, dt_dev, (double *)ff, fp, w.status);
+            launch_flux_t<double, true>(m, ext, grid, c, Q, dt_dev, (double *)ff, fp, w.status, st);
         else
-            k_flux<double, false><<<grid, kBlock, 0, st>>>(m->d, (const double *)coeff, Q, dt_dev, (double *)ff, fp, w.status);
+            launch_flux_t<double, false>(m, ext, grid, c, Q, dt_dev, (double *)ff, fp, w.status, st);
     } else {
         auto fp = flux_params<float>(p);
+        const float *c = (const float *)coeff;
         if (pr)
-            k_flux<float, true><<<grid, kBlock, 0, st>>>(m->d, (const float *)coeff, Q, dt_dev, (float *)ff, fp, w.status);
+            launch_flux_t<float, true>(m, ext, grid, c, Q, dt_dev, (float *)ff, fp, w.status, st);
         else
-            k_flux<float, false><<<grid, kBlock, 0, st>>>(m->d, (const float *)coeff, Q, dt_dev, (float *)ff, fp, w.status);
+            launch_flux_t<float, false>(m, ext, grid, c, Q, dt_dev, (float *)ff, fp, w.status, st);
     }
     return hip_check(hipGetLastError(), "flux launch");
 }
@@ -1620,6 +1645,7 @@ gks_status gks_adjoint_step(gks_mesh *m, const double *Qn, const double *Qstar, 
     if (s) return s;
     if (m->precision != GKS_FP64) return fail(GKS_EINVAL, "the adjoint runs on an FP64 mesh");
     if (m->d.walls) return fail(GKS_EINVAL, "the adjoint is built for periodic meshes (this one has walls)");
+    if (p->first_order_fallback) return fail(GKS_EINVAL, "the adjoint does not differentiate the first-order fallback");
     if (!Qn || !Qstar || !dt_dev || !lam_np1 || !lam_n || !adj_work) return fail(GKS_EINVAL, "null argument");
     if (((uintptr_t)adj_work & 255) != 0) return fail(GKS_EINVAL, "adjoint work buffer must be 256-byte aligned");
     AdjWork aw;
@@ -1699,15 +1725,32 @@ gks_status gks_gp_flux_host(const double *ql, const double *dql, const double *q
                             const gks_params *p, double *out)
 {
     if (!ql || !dql || !qr || !dqr || !p || !out) return fail(GKS_EINVAL, "null argument");
-    const FluxParams<double> fp = flux_params<double>(p);
-    double dl[3][5], dr[3][5];
-    for (int m = 0; m < 3; ++m)
+    const bool pr = p->viscous && p->Pr != 1.0;
+    bool ok;
+    if (p->precision == GKS_FP32_MIXED) {
+        const FluxParams<float> fp = flux_params<float>(p);
+        float l[5], r[5], dl[3][5], dr[3][5], o[10];
         for (int j = 0; j < 5; ++j) {
-            dl[m][j] = dql[5 * m + j];
-            dr[m][j] = dqr[5 * m + j];
+            l[j] = (float)ql[j];
+            r[j] = (float)qr[j];
         }
-    const bool ok = (p->viscous && p->Pr != 1.0) ? gp_flux<double, true>(ql, dl, qr, dr, dt, fp, out)
-                                                 : gp_flux<double, false>(ql, dl, qr, dr, dt, fp, out);
+        for (int m = 0; m < 3; ++m)
+            for (int j = 0; j < 5; ++j) {
+                dl[m][j] = (float)dql[5 * m + j];
+                dr[m][j] = (float)dqr[5 * m + j];
+            }
+        ok = pr ? gp_flux<float, true>(l, dl, r, dr, (float)dt, fp, o) : gp_flux<float, false>(l, dl, r, dr, (float)dt, fp, o);
+        for (int j = 0; j < 10; ++j) out[j] = o[j];
+    } else {
+        const FluxParams<double> fp = flux_params<double>(p);
+        double dl[3][5], dr[3][5];
+        for (int m = 0; m < 3; ++m)
+            for (int j = 0; j < 5; ++j) {
+                dl[m][j] = dql[5 * m + j];
+                dr[m][j] = dqr[5 * m + j];
+            }
+        ok = pr ? gp_flux<double, true>(ql, dl, qr, dr, dt, fp, out) : gp_flux<double, false>(ql, dl, qr, dr, dt, fp, out);
+    }
     return ok ? GKS_OK : fail(GKS_ENONPHYS, "non-physical state");
 }
 
@@ -1797,11 +1840,12 @@ gks_status gks_gp_op_count(int viscous, double Pr, int64_t *adds, int64_t *muls,
     fp.tau_C = Cnt(p.tau_C);
     fp.viscous = p.viscous;
     fp.fallback = 0;
+    fp.floor = 0.0;
     op_counts() = OpCounts();
     Cnt out[10];
     int nfb = 0;
-    const bool ok = (viscous && Pr != 1.0) ? face_gp<Cnt, true>(cl, cr, nullptr, nullptr, geo, Cnt(0.01), fp, out, nfb)
-                                           : face_gp<Cnt, false>(cl, cr, nullptr, nullptr, geo, Cnt(0.01), fp, out, nfb);
+    const bool ok = (viscous && Pr != 1.0) ? face_gp<Cnt, true, false>(cl, cr, nullptr, nullptr, geo, Cnt(0.01), fp, out, nfb)
+                                           : face_gp<Cnt, false, false>(cl, cr, nullptr, nullptr, geo, Cnt(0.01), fp, out, nfb);
     const OpCounts c = op_counts();
     *adds = c.add;
     *muls = c.mul;

@@ -25,6 +25,7 @@ struct FluxParams {
     T gamma, K, mu, Pr, tau_eps, tau_C;
     int viscous;
     int fallback;  // first-order fallback of non-physical side states
+    double floor;  // ... and of states whose rho or p is at most floor times the cell average's
 };
 
 // Moments <u^k> (k <= 6), <v^k>, <w^k> (k <= 5), <s^2>, <s^4> of one normalised Maxwellian.
@@ -525,15 +526,22 @@ __host__ __device__ __forceinline__ void wall_mirror(const T q[5], const T dq[3]
     }
 }
 
-// With fp.fallback: a side state with rho <= 0 or p <= 0 becomes its cell's average qav (FP64, global
-// frame) in the local frame with zero slopes.  Returns whether it did.
+// With fp.fallback: a side state with rho <= 0 or p <= 0, or with rho or p at most fp.floor times
+// that of its cell's average qav (FP64, global frame), becomes qav in the local frame with zero
+// slopes.  Returns whether it did.
 template <typename T>
 __host__ __device__ __forceinline__ bool fallback_side(const FluxParams<T> &fp, const double *qav, const T n[3][3],
                                                        T q[5], T dq[3][5])
 {
     if (!fp.fallback) return false;
     const T p = (fp.gamma - T(1)) * (q[4] - T(0.5) * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
-    if (q[0] > T(0) && p > T(0)) return false;
+    double rmin = 0.0, pmin = 0.0;
+    if (fp.floor > 0.0) {
+        const double pav = ((double)fp.gamma - 1.0) * (qav[4] - 0.5 * (qav[1] * qav[1] + qav[2] * qav[2] + qav[3] * qav[3]) / qav[0]);
+        rmin = fp.floor * qav[0];
+        pmin = fp.floor * pav;
+    }
+    if ((double)q[0] > rmin && (double)p > pmin && q[0] > T(0) && p > T(0)) return false;
     const T v1 = (T)qav[1], v2 = (T)qav[2], v3 = (T)qav[3];
     q[0] = (T)qav[0];
     q[4] = (T)qav[4];
@@ -546,10 +554,11 @@ __host__ __device__ __forceinline__ bool fallback_side(const FluxParams<T> &fp, 
     return true;
 }
 
-// cr_g == nullptr: the face is a reflective wall and the right state is the mirror of the left one.
-// ql0, qr0: the two cells' FP64 averages (read for FP32 coefficients and for the fallback); nfb counts
-// the sides that fell back.
-template <typename T, bool PR>
+// EXT: walls and the first-order fallback can occur; without it cr_g is never null and fp.fallback is
+// ignored.  With it, cr_g == nullptr means the face is a reflective wall and the right state is the
+// mirror of the left one.  ql0, qr0: the two cells' FP64 averages (read for FP32 coefficients and for
+// the fallback); nfb counts the sides that fell back.
+template <typename T, bool PR, bool EXT>
 __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, const T *__restrict__ cr_g, const double *ql0,
                                                  const double *qr0, const T geo[9], T dt, const FluxParams<T> &fp,
                                                  T out[10], int &nfb)
@@ -563,15 +572,15 @@ __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, con
         T q[5], dq[3][5], cl[50];
         load_cell(cl_g, cl);
         side_state(cl, ql0, geo[0], geo[1], geo[2], n3, q, dq);
-        nfb += fallback_side(fp, ql0, n3, q, dq);
+        if (EXT) nfb += fallback_side(fp, ql0, n3, q, dq);
         ok = side_pass<T, PR>(q, dq, T(1), fp, A, 0);
     }
     {
         T q[5], dq[3][5], cr[50];
-        if (cr_g) {
+        if (!EXT || cr_g) {
             load_cell(cr_g, cr);
             side_state(cr, qr0, geo[3], geo[4], geo[5], n3, q, dq);
-            nfb += fallback_side(fp, qr0, n3, q, dq);
+            if (EXT) nfb += fallback_side(fp, qr0, n3, q, dq);
         } else {
             T qi[5], dqi[3][5];
             load_cell(cl_g, cr);

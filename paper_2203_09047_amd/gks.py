@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EDEVICE", 3: "ESINGULAR", 4: "ENONPHYS
 
 SYMBOLS = [
     "gks_default_params", "gks_preprocess", "gks_host_mesh_free", "gks_host_mesh_counts", "gks_host_mesh_perm",
-    "gks_host_mesh_geometry", "gks_host_mesh_faces", "gks_mesh_sizes", "gks_init_mesh", "gks_destroy_mesh",
+    "gks_host_mesh_geometry", "gks_host_mesh_faces", "gks_host_mesh_face_geometry", "gks_mesh_sizes", "gks_init_mesh", "gks_destroy_mesh",
     "gks_reset_status", "gks_timestep", "gks_reconstruct", "gks_flux", "gks_residual", "gks_s2o4_step",
     "gks_poll_status", "gks_fallback_count", "gks_gp_flux_batch", "gks_profile", "gks_profile_read", "gks_gp_op_count",
     "gks_gp_flux_host", "gks_gp_flux_vjp_host", "gks_weno_combine_host", "gks_weno_combine_vjp_host",
@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
         ("weno_eps", ctypes.c_double), ("weno_gamma_m", ctypes.c_double), ("weno_p", ctypes.c_double),
         ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double), ("viscous", ctypes.c_int),
         ("precision", ctypes.c_int), ("force_linear", ctypes.c_int), ("dt_given", ctypes.c_int),
-        ("first_order_fallback", ctypes.c_int),
+        ("first_order_fallback", ctypes.c_int), ("fallback_floor", ctypes.c_double),
     ]
 
 
@@ -77,6 +77,8 @@ def load():
         lib.gks_host_mesh_geometry.restype = st
         lib.gks_host_mesh_faces.argtypes = [vp, vp, vp]
         lib.gks_host_mesh_faces.restype = st
+        lib.gks_host_mesh_face_geometry.argtypes = [vp, vp]
+        lib.gks_host_mesh_face_geometry.restype = st
         lib.gks_mesh_sizes.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         lib.gks_mesh_sizes.restype = st
         lib.gks_init_mesh.argtypes = [vp, i32, vp, sz, vp, ctypes.POINTER(vp)]
@@ -142,7 +144,8 @@ def _dp(t):
 
 
 def params(precision=FP64, gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, viscous=False, weno_eps=1e-6, weno_gamma_m=0.0125,
-           weno_p=1.0, tau_eps=0.01, tau_C=1.0, force_linear=False, dt_given=False, fallback=False) -> Params:
+           weno_p=1.0, tau_eps=0.01, tau_C=1.0, force_linear=False, dt_given=False, fallback=False,
+           fallback_floor=0.0) -> Params:
     p = Params()
     load().gks_default_params(ctypes.byref(p))
     p.gamma, p.cfl, p.mu, p.Pr = gamma, cfl, mu, Pr
@@ -150,6 +153,7 @@ def params(precision=FP64, gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, viscous=False, we
     p.tau_eps, p.tau_C = tau_eps, tau_C
     p.viscous, p.precision, p.force_linear, p.dt_given = int(viscous), int(precision), int(force_linear), int(dt_given)
     p.first_order_fallback = int(fallback)
+    p.fallback_floor = float(fallback_floor)
     return p
 
 
@@ -190,6 +194,13 @@ class HostMesh:
         nb = np.zeros(self.n_faces, np.int32)
         _check(load().gks_host_mesh_faces(self.h, _np(o), _np(nb)))
         return o, nb
+
+    def face_geometry(self):
+        """[9, 4 n_faces]: offsets of each Gauss point from the owner's and the neighbour's centroid,
+        weighted vector area."""
+        g = np.zeros((9, 4 * self.n_faces))
+        _check(load().gks_host_mesh_face_geometry(self.h, _np(g)))
+        return g
 
     def to_internal(self, Q):
         """[5, n] in the caller's cell order -> internal order."""

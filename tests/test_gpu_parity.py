@@ -256,17 +256,19 @@ def test_walls_conserve_mass_and_energy_on_gpu(gks):
     np.testing.assert_allclose(t1[[0, 4]], t0[[0, 4]], rtol=1e-14)
 
 
-def test_first_order_fallback_matches_oracle(gks):
-    """The walled 3-D Riemann problem on the hybrid lattice (N = 6), first-order fallback on, 3 steps
-    with the oracle's step sizes: the same states to 1e-12 and the same number of fallbacks."""
+@pytest.mark.parametrize("floor", [0.0, 0.1])
+def test_first_order_fallback_matches_oracle(gks, floor):
+    """The walled 3-D Riemann problem on the hybrid lattice (N = 6), first-order fallback on (with
+    and without a floor), 3 steps with the oracle's step sizes: the same states to 1e-12 and the same
+    number of fallbacks."""
     import torch
 
-    print("case: walls + fallback, hybrid N=6 Riemann x 3 steps", flush=True)
+    print(f"case: walls + fallback (floor {floor}), hybrid N=6 Riemann x 3 steps", flush=True)
     mesh = inputs.lattice(6, "hybrid", periodic=False)
     Q0 = inputs.cell_averages(mesh, inputs.riemann())
     host = gks.HostMesh(mesh)
-    sol = gks.Solver(host, gks.params(fallback=True))
-    o = oracle.Oracle(mesh, oracle.params(fallback=True))
+    sol = gks.Solver(host, gks.params(fallback=True, fallback_floor=floor))
+    o = oracle.Oracle(mesh, oracle.params(fallback=True, fallback_floor=floor))
     Q = sol.upload(host.to_internal(Q0))
     ref = Q0.copy()
     for _ in range(3):
@@ -286,12 +288,75 @@ def test_first_order_fallback_matches_oracle(gks):
     assert (err <= TOL).all(), err
 
 
+def _box_averages(Q, vol, x, nbox):
+    """Volume averages of Q [5][n] over the nbox^3 boxes of the unit cube (cells lie inside one box)."""
+    b = np.clip(np.floor(x * nbox).astype(np.int64), 0, nbox - 1)
+    k = (b[:, 0] * nbox + b[:, 1]) * nbox + b[:, 2]
+    w = np.bincount(k, weights=vol, minlength=nbox ** 3)
+    return np.stack([np.bincount(k, weights=vol * Q[c], minlength=nbox ** 3) / w for c in range(5)])
+
+
+@pytest.mark.slow
+def test_walled_riemann_problem_fp32_fp64_and_coarse_oracle(gks):
+    """The discontinuous workload (3-D Riemann problem in the closed unit box, Euler) on the hybrid
+    lattice at N = 48 to t = 0.15, first-order fallback with a floor of 0.1 of the cell average, CFL
+    0.3, in FP64 and FP32-mixed: both reach t = 0.15 with positive states and nearly the same fallback
+    count; they differ by little in L1; and, averaged over the boxes of the N = 12 lattice, both lie
+    close to the oracle's solution of the same problem on that lattice (the coarsened copy the oracle
+    can run)."""
+    import torch
+
+    print("case: walled Riemann problem, hybrid N=48 to t=0.15, oracle at N=12", flush=True)
+    prm = dict(fallback=True, fallback_floor=0.1, cfl=0.3)
+    mc = inputs.lattice(12, "hybrid", periodic=False)
+    oc = oracle.Oracle(mc, oracle.params(**prm))
+    Qc, _ = oc.run(inputs.cell_averages(mc, inputs.riemann()), t_end=0.15)
+    volc, xc, _, _ = oc.cell_geometry()
+    Bc = _box_averages(Qc, volc, xc, 12)
+    mesh = inputs.lattice(48, "hybrid", periodic=False)
+    Q0 = inputs.cell_averages(mesh, inputs.riemann())
+    host = gks.HostMesh(mesh)
+    vol, x = host.geometry()
+    res, nfb = {}, {}
+    for prec in (gks.FP64, gks.FP32_MIXED):
+        sol = gks.Solver(host, gks.params(precision=prec, **prm))
+        Q = sol.upload(host.to_internal(Q0))
+        dts = sol.run(Q, t_end=0.15)
+        nfb[prec] = sol.fallback_count()
+        q = Q.cpu().numpy()
+        rho = q[0]
+        p = 0.4 * (q[4] - 0.5 * (q[1:4] ** 2).sum(axis=0) / rho)
+        print(f"precision {prec}: {len(dts)} steps, min rho {rho.min():.4f}, min p {p.min():.4f}, fallbacks {nfb[prec]}")
+        assert abs(sum(dts) - 0.15) < 1e-12 and rho.min() > 0.05 and p.min() > 0.03
+        res[prec] = q
+        l1c = np.abs(_box_averages(q, vol, x, 12) - Bc).sum(axis=1) / 12 ** 3
+        print(f"  L1 against the oracle at N=12 (box averages): {l1c}")
+        assert (l1c < np.array([0.05, 0.05, 0.05, 0.05, 0.1])).all(), l1c
+    d = (np.abs(res[gks.FP32_MIXED] - res[gks.FP64]) * vol).sum(axis=1)
+    print("FP32-mixed vs FP64, L1:", d)
+    assert (d < 1e-4).all(), d
+    assert abs(nfb[gks.FP32_MIXED] - nfb[gks.FP64]) < 1e-3 * nfb[gks.FP64]
+
+
 def test_adjoint_refuses_walls(gks):
     import torch
 
     mesh = inputs.lattice(3, "hex", periodic=False)
     host = gks.HostMesh(mesh)
     sol = gks.Solver(host)
+    Q = sol.upload(host.to_internal(inputs.cell_averages(mesh, inputs.uniform())))
+    dtt = torch.tensor([1e-3], dtype=torch.float64, device=Q.device)
+    with pytest.raises(gks.GksError) as e:
+        sol.adjoint_step(Q, Q.clone(), dtt, torch.zeros_like(Q))
+    assert e.value.code == gks.GKS_EINVAL
+
+
+def test_adjoint_refuses_the_fallback(gks):
+    import torch
+
+    mesh = inputs.lattice(3, "hex")
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host, gks.params(fallback=True))
     Q = sol.upload(host.to_internal(inputs.cell_averages(mesh, inputs.uniform())))
     dtt = torch.tensor([1e-3], dtype=torch.float64, device=Q.device)
     with pytest.raises(gks.GksError) as e:

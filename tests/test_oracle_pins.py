@@ -684,16 +684,18 @@ def test_fallback_inactive_on_smooth_data():
     assert np.array_equal(Qa, Qb)
 
 
-def test_fallback_keeps_walled_riemann_problem_physical_and_conservative():
+@pytest.mark.parametrize("floor", [0.0, 0.1])
+def test_fallback_keeps_walled_riemann_problem_physical_and_conservative(floor):
     """The planar Riemann problem in the closed unit box (hybrid lattice, N = 5) to t = 0.15: the
-    scheme as printed reaches a non-physical state; with the fallback the densities and pressures
-    stay positive, close to the smaller initial state's from below, and mass and energy are
-    conserved to round-off because the fallback changes states, not the flux balance."""
+    scheme as printed reaches a non-physical state; with the fallback (positivity only, or with a
+    floor of 0.1 of the cell average) the densities and pressures stay positive, close to the smaller
+    initial state's from below, and mass and energy are conserved to round-off because the fallback
+    changes states, not the flux balance."""
     m = inputs.lattice(5, "hybrid", periodic=False)
     Q0 = inputs.cell_averages(m, inputs.riemann())
     with pytest.raises(oracle.OracleError):
         oracle.Oracle(m).run(Q0, t_end=0.15)
-    o = oracle.Oracle(m, oracle.params(fallback=True))
+    o = oracle.Oracle(m, oracle.params(fallback=True, fallback_floor=floor))
     Q, dts = o.run(Q0, t_end=0.15)
     assert abs(sum(dts) - 0.15) < 1e-14
     assert o.fallback_count() > 0
@@ -703,6 +705,26 @@ def test_fallback_keeps_walled_riemann_problem_physical_and_conservative():
     vol = o.cell_geometry()[0]
     tot0, tot1 = (Q0 * vol).sum(axis=1), (Q * vol).sum(axis=1)
     np.testing.assert_allclose(tot1[[0, 4]], tot0[[0, 4]], rtol=1e-14)
+
+
+def test_fallback_floor_only_adds_fallbacks():
+    """On the same state a floor keeps every positivity fallback and adds the states below that
+    fraction of their cell's average, so the count grows with the floor; on uniform data no state
+    falls back even at a floor just below 1."""
+    m = inputs.lattice(5, "hybrid", periodic=False)
+    Q0 = inputs.cell_averages(m, inputs.riemann())
+    dt = oracle.Oracle(m).timestep(Q0)
+    counts, fluxes = [], []
+    for floor in (0.0, 0.01, 0.1, 0.5):
+        o = oracle.Oracle(m, oracle.params(fallback=True, fallback_floor=floor))
+        fluxes.append(o.face_flux(Q0, dt))
+        counts.append(o.fallback_count())
+    assert counts[0] > 0 and all(a <= b for a, b in zip(counts, counts[1:])) and counts[-1] > counts[0], counts
+    # uniform data: no state is below any floor < 1 of itself
+    Qu = inputs.cell_averages(m, inputs.uniform(1.0, 0.2, -0.1, 0.3, 0.8))
+    o = oracle.Oracle(m, oracle.params(fallback=True, fallback_floor=0.999))
+    o.face_flux(Qu, dt)
+    assert o.fallback_count() == 0
 
 
 @pytest.mark.slow
