@@ -183,13 +183,17 @@ __device__ __forceinline__ double mirror_sign(unsigned flip, int c)
 
 constexpr int kK1Lanes = 4;
 constexpr int kK1CellLanes = 5 * kK1Lanes;
-constexpr int kK1Cells = 16;
-constexpr int kK1Block = kK1Cells * kK1CellLanes;  // 16 cells, 5 waves
-// Staged in LDS per block (the 16 cells' stencil and sub-stencil ranges are
-// contiguous): the members' cell averages and the sub-stencil lists.  A block
-// whose ranges are longer reads them from global memory instead.
-constexpr int kK1Stage = 416;
-constexpr int kK1SubStage = 800;
+// 12 cells = 240 lanes = 4 waves (the last one 48 lanes) and 27.5 KB of LDS per block, so five
+// blocks fill a CU at 5 waves/SIMD; blocks of 16 cells (5 waves, 4 per CU) leave more of the CU
+// waiting at the staging barrier and measure 19% slower (8 cells: 8% slower).
+constexpr int kK1Cells = 12;
+constexpr int kK1Block = kK1Cells * kK1CellLanes;
+// Staged in LDS per block (the cells' stencil and sub-stencil ranges are
+// contiguous): the members' cell averages and the sub-stencil lists, 26 members and
+// 50 sub-stencil entries per cell on average.  A block whose ranges are longer reads
+// them from global memory instead.
+constexpr int kK1Stage = 26 * kK1Cells;
+constexpr int kK1SubStage = 50 * kK1Cells;
 
 // DPP lane permutations (VALU, no LDS traffic) of a 32-bit value within a quad of lanes
 template <int CTRL>
