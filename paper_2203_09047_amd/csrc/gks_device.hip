@@ -591,6 +591,53 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict_
     }
 }
 
+// FP64, periodic, no fallback (the benchmark path).  At 1 wave/SIMD nothing hides the latency of a
+// wave's first coefficient loads, so a grid of one block per CU walks contiguous chunks of Gauss
+// points 256 at a time and loads the next chunk's neighbour coefficients while it computes the
+// current chunk (the owners' are mostly the previous chunk's cells, still in cache).
+template <bool PR_ANY>
+__global__ void __launch_bounds__(kBlock) k_flux_chunked(DevMesh m, const double *__restrict__ coeff,
+                                                         const double *__restrict__ dt_dev, double *__restrict__ ff,
+                                                         FluxParams<double> fp, int *status, int chunk)
+{
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int nf4 = 4 * m.nf;
+    const int b0 = (int)min((int64_t)blk * chunk, (int64_t)nf4), b1 = min(b0 + chunk, nf4);
+    const double dt = dt_dev[0];
+    auto face_of = [&](int t) { return min(t >> 2, m.nf - 1); };  // tail lanes shadow the last face
+    double cr[50];
+    if (b0 < b1) load_cell(coeff + (size_t)50 * m.nbr[face_of(b0 + (int)threadIdx.x)], cr);
+    for (int base = b0; base < b1; base += kBlock) {  // uniform over the block
+        const int t = base + (int)threadIdx.x;
+        const bool live = t < b1;
+        const int fs = face_of(t);
+        const int tt = 4 * fs + (t & 3);
+        double geo[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) geo[q] = m.fgeo[(size_t)q * nf4 + tt];
+        double cl[50], crn[50];
+        load_cell(coeff + (size_t)50 * m.owner[fs], cl);
+        if (base + kBlock < b1) load_cell(coeff + (size_t)50 * m.nbr[face_of(t + kBlock)], crn);
+        double out[10];
+        const bool ok = face_gp_pre<double, PR_ANY>(cl, cr, nullptr, nullptr, geo, dt, fp, out);
+        if (live && !ok) status[0] = 1;
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+            out[j] += shfl_xor_t(out[j], 1);
+            out[j] += shfl_xor_t(out[j], 2);
+        }
+        if (live) {
+            const int g4 = t & 3;
+            double *dst = ff + (size_t)10 * (t >> 2);
+#pragma unroll
+            for (int j = 0; j < 10; ++j)
+                if ((j & 3) == g4) dst[j] = out[j];
+        }
+#pragma unroll
+        for (int q = 0; q < 50; ++q) cr[q] = crn[q];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K3: per-cell gather of face fluxes and stage updates
 // ---------------------------------------------------------------------------
@@ -1085,6 +1132,7 @@ struct gks_mesh {
     DevMesh d;
     int64_t n, nf;
     int precision;
+    int n_cu = 256;  // compute units of the device the mesh lives on (grid of the chunked flux kernel)
     // optional per-kernel HIP-event timing (gks_profile)
     bool prof = false;
     std::vector<hipEvent_t> pool;
@@ -1380,6 +1428,10 @@ gks_status gks_init_mesh(const gks_host_mesh *h, int precision, void *mesh_arena
     m->n = h->h.n;
     m->nf = h->h.nf;
     m->precision = precision;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        m->n_cu = ncu;
     *out = m;
     return GKS_OK;
 }
@@ -1486,10 +1538,17 @@ extern "C++" template <typename T, bool PR>
 static void launch_flux_t(gks_mesh *m, bool ext, unsigned grid, const T *coeff, const double *Q, const double *dt_dev,
                           T *ff, const FluxParams<T> &fp, int *status, hipStream_t st)
 {
-    if (ext)
+    if (ext) {
         k_flux<T, PR, true><<<grid, kBlock, 0, st>>>(m->d, coeff, Q, dt_dev, ff, fp, status);
-    else
+    } else if constexpr (sizeof(T) == 8) {
+        const int64_t ncu = m->n_cu;
+        const int64_t nf4 = 4 * (int64_t)m->nf;
+        const int64_t per = ((nf4 + ncu * kBlock - 1) / (ncu * kBlock)) * kBlock;
+        const int nblk = (int)((nf4 + per - 1) / per);
+        k_flux_chunked<PR><<<nblk, kBlock, 0, st>>>(m->d, coeff, dt_dev, ff, fp, status, (int)per);
+    } else {
         k_flux<T, PR, false><<<grid, kBlock, 0, st>>>(m->d, coeff, Q, dt_dev, ff, fp, status);
+    }
 }
 
 static gks_status launch_flux(gks_mesh *m, const void *coeff, const double *Q, const double *dt_dev, void *ff,

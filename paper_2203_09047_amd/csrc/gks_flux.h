@@ -554,6 +554,47 @@ __host__ __device__ __forceinline__ bool fallback_side(const FluxParams<T> &fp, 
     return true;
 }
 
+// The flux of one Gauss point of an interior face from both cells' coefficients already in registers
+// (ql0, qr0: the FP64 cell averages that FP32 coefficients exclude; unused in FP64); the same
+// arithmetic as face_gp without walls or the fallback.
+template <typename T, bool PR>
+__host__ __device__ __forceinline__ bool face_gp_pre(const T cl[50], const T cr[50], const double *ql0,
+                                                     const double *qr0, const T geo[9], T dt,
+                                                     const FluxParams<T> &fp, T out[10])
+{
+    T n3[3][3];
+    const T area = local_frame(geo[6], geo[7], geo[8], n3);
+    FluxAcc<T, PR> A;
+    acc_zero(A);
+    bool ok;
+    {
+        T q[5], dq[3][5];
+        side_state(cl, ql0, geo[0], geo[1], geo[2], n3, q, dq);
+        ok = side_pass<T, PR>(q, dq, T(1), fp, A, 0);
+    }
+    {
+        T q[5], dq[3][5];
+        side_state(cr, qr0, geo[3], geo[4], geo[5], n3, q, dq);
+        ok = side_pass<T, PR>(q, dq, T(-1), fp, A, 1) && ok;
+    }
+    T F[10];
+    if (ok) {
+        ok = finish_flux<T, PR>(A, dt, fp, F);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 10; ++j) F[j] = T(0);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const T *Fl = F + 5 * s;
+        out[5 * s] = area * Fl[0];
+        out[5 * s + 4] = area * Fl[4];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) out[5 * s + 1 + q] = area * (Fl[1] * n3[0][q] + Fl[2] * n3[1][q] + Fl[3] * n3[2][q]);
+    }
+    return ok;
+}
+
 // EXT: walls and the first-order fallback can occur; without it cr_g is never null and fp.fallback is
 // ignored.  With it, cr_g == nullptr means the face is a reflective wall and the right state is the
 // mirror of the left one.  ql0, qr0: the two cells' FP64 averages (read for FP32 coefficients and for
