@@ -31,12 +31,13 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 # FP64 operations the flux kernel executes per Gauss point (Navier-Stokes, Pr != 1): the hardware
 # counters SQ_INSTS_VALU_FMA_F64 (x 2), _MUL_F64 and _ADD_F64 over one launch at N = 64, divided by
-# the launch's 4 F Gauss points (2298 FMA + 912 MUL + 206 ADD per point).  The source-level count
+# the launch's 4 F Gauss points (2289 FMA + 903 MUL + 197 ADD per point).  The source-level count
 # (flux_ops_per_gauss_point) is larger: the compiler folds constant factors and shares products.
-FLUX_FP64_FLOPS_PER_GP = 2 * 2298 + 912 + 206
+FLUX_FP64_FLOPS_PER_GP = 2 * 2289 + 903 + 197
 # committed HBM counter summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated), valid only for the
-# kernel sources it was measured on
+# kernel sources it was measured on and for the workload it was measured on (N = 64)
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "hbm_counters_hybrid-N64-tgv.json")
+COUNTERS_N = 64
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2203_09047_amd", "csrc", f)
                   for f in ("gks_device.hip", "gks_flux.h", "gks_flux_adj.h", "gks_weno.h", "gks_internal.h")]
 # rocprofv3 kernel names -> the library's kernel keys
@@ -267,7 +268,7 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
     # source-level FP64 operation count of one Gauss point (informational)
     res["flux_ops_per_gauss_point"] = gks.gp_op_count(viscous=True, Pr=0.72)
-    traffic = measured_traffic()
+    traffic = measured_traffic() if args.N == COUNTERS_N else {}
 
     def roofline(k):
         avg_s = kern[k]["avg_ms"] * 1e-3
