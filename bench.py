@@ -188,6 +188,7 @@ def cpu_baseline(N_sample=16):
     import oracle
     from paper_2203_09047_amd import inputs
 
+    oracle.set_threads(1)  # the oracle's loops run single-threaded for this baseline
     mesh = inputs.lattice(N_sample, "hybrid", box=(2 * math.pi,) * 3)
     Q0 = inputs.cell_averages(mesh, inputs.tgv())
     prm = oracle.params(viscous=True, mu=1.0 / 1600.0, Pr=0.72, cfl=0.5)
@@ -286,6 +287,16 @@ def main():
     q64 = run_gpu.last_q
     res["hbm_fraction_of_step_fp64"] = sum(bytes64[k] * kern[k]["launches"] for k in kern) / args.steps / (
         ms64 / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+    # attainable-roofline fraction of the step: each kernel's lower bound max(bytes / HBM peak,
+    # flops / FP64 peak) summed over the step's launches, over the measured step time
+    def bound_s(k):
+        t_mem = bytes64[k] / (HBM_PEAK_GBS * 1e9)
+        t_alu = FLUX_FP64_FLOPS_PER_GP * 4 * host.n_faces / (FP64_VECTOR_PEAK_TFLOPS * 1e12) if k == "flux" else 0.0
+        return max(t_mem, t_alu)
+
+    res["roofline_fraction_of_step_fp64"] = sum(bound_s(k) * kern[k]["launches"] for k in kern if k in bytes64) / (
+        ms64 * 1e-3)
     if args.adj_steps > 0:
         del sol
         torch.cuda.empty_cache()

@@ -29,8 +29,8 @@ _lib = None
 
 def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (no fast-math, FP64)."""
-    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", "-o", LIB_PATH,
-           SOURCE, "-lm"]
+    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o",
+           LIB_PATH, SOURCE, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
@@ -111,6 +111,10 @@ def _load():
         lib.orc_stencil_members.restype = i32
         lib.orc_substencil_members.argtypes = [vp, i64, i32, vp, vp]
         lib.orc_stencil_signs.argtypes = [vp, i64, vp]
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = None
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = ctypes.c_int
         lib.orc_fallback_count.argtypes = [vp]
         lib.orc_fallback_count.restype = i64
         lib.orc_stencil_signs.restype = i32
@@ -121,6 +125,16 @@ def _load():
         lib.orc_stencil_grown.restype = i32
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's reconstruction and face-flux loops (each output is written by one
+    iteration, so results do not depend on the count)."""
+    _load().orc_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(_load().orc_threads())
 
 
 class OracleError(RuntimeError):

@@ -56,6 +56,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 enum { TET = 0, PYR = 1, PRISM = 2, HEX = 3 };
 
@@ -904,6 +907,25 @@ void orc_destroy(orc *o)
 int64_t orc_n_faces(const orc *o) { return o->n_faces; }
 
 /* Gauss-point sides that fell back to first order since the last call (then reset) */
+/* threads of the two parallel loops (reconstruction, face fluxes); results do not depend on it */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 int64_t orc_fallback_count(orc *o)
 {
     const int64_t c = o->n_fallback;
@@ -1097,8 +1119,11 @@ static void weno_eval(const orc *o, const orc_params *P, const double *Q, int64_
     }
 }
 
+/* every cell's reconstruction; each iteration writes only its own cell's coefficients, so the
+   OpenMP loop gives the same result as the serial one */
 static void weno_all(orc *o, const orc_params *P, const double *Q)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < o->n_cells; i++) weno_cell(o, P, Q, i);
 }
 
@@ -1510,6 +1535,10 @@ static void fallback_state(const orc *o, const double *Q, sref s, const double n
 static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt, double *out)
 {
     weno_all(o, P, Q);
+    /* each iteration writes only its own face's fluxes; the fallback count is an integer sum */
+    int err = 0;
+    int64_t nfb = 0;
+#pragma omp parallel for schedule(static) reduction(+ : nfb) reduction(max : err)
     for (int64_t f = 0; f < o->n_faces; f++) {
         const oface *F = &o->f[f];
         double acc[10] = {0};
@@ -1535,16 +1564,19 @@ static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt
             if (P->fallback) {
                 if (!admissible_state(o, P, Q, sref_self(F->owner), ql)) {
                     fallback_state(o, Q, sref_self(F->owner), n, ql, dql);
-                    o->n_fallback++;
+                    nfb++;
                 }
                 if (!admissible_state(o, P, Q, F->nb, qr)) {
                     fallback_state(o, Q, F->nb, n, qr, dqr);
-                    o->n_fallback++;
+                    nfb++;
                 }
             }
             double Fb[10];
-            int e = orc_gp_flux(P, ql, &dql[0][0], qr, &dqr[0][0], dt, Fb, NULL);
-            if (e) return e;
+            const int e = orc_gp_flux(P, ql, &dql[0][0], qr, &dqr[0][0], dt, Fb, NULL);
+            if (e) {
+                if (e > err) err = e;
+                break;
+            }
             double area = sqrt(F->va[k][0] * F->va[k][0] + F->va[k][1] * F->va[k][1] + F->va[k][2] * F->va[k][2]);
             for (int s = 0; s < 2; s++) {
                 const double *Fl = Fb + 5 * s;
@@ -1557,7 +1589,8 @@ static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt
         }
         for (int c = 0; c < 10; c++) out[10 * f + c] = acc[c];
     }
-    return 0;
+    o->n_fallback += nfb;
+    return err;
 }
 
 /* face fluxes [F][10]: (Fbar0, Fbar1), area-integrated, owner -> neighbour */
