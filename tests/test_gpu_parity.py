@@ -338,6 +338,108 @@ def test_walled_riemann_problem_fp32_fp64_and_coarse_oracle(gks):
     assert abs(nfb[gks.FP32_MIXED] - nfb[gks.FP64]) < 1e-3 * nfb[gks.FP64]
 
 
+_MONOMIALS = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (1, 1, 0), (1, 0, 1), (0, 2, 0), (0, 1, 1), (0, 0, 2)]
+
+
+def _local_frame(va):
+    """Normal and tangents of a Gauss point: e = the axis least aligned with the normal (lowest index
+    on ties), n2 = e projected off n1 and normalised, n3 = n1 x n2."""
+    n1 = va / np.linalg.norm(va)
+    e = np.zeros(3)
+    e[np.argmin(np.abs(n1))] = 1.0
+    n2 = e - (e @ n1) * n1
+    n2 /= np.linalg.norm(n2)
+    return np.stack([n1, n2, np.cross(n1, n2)])
+
+
+def _local_state(c, X, n):
+    """Value and gradient of one cell's quadratics c [5][10] at offset X, in the local frame n: q [5]
+    and dq [3][5] (derivative along n_m; momentum components rotated)."""
+    v = np.zeros(5)
+    g = np.zeros((5, 3))
+    for k, (a, b, d) in enumerate(_MONOMIALS):
+        v += c[:, k] * X[0] ** a * X[1] ** b * X[2] ** d
+        if a:
+            g[:, 0] += c[:, k] * a * X[0] ** (a - 1) * X[1] ** b * X[2] ** d
+        if b:
+            g[:, 1] += c[:, k] * b * X[0] ** a * X[1] ** (b - 1) * X[2] ** d
+        if d:
+            g[:, 2] += c[:, k] * d * X[0] ** a * X[1] ** b * X[2] ** (d - 1)
+    q = np.array([v[0], v[1:4] @ n[0], v[1:4] @ n[1], v[1:4] @ n[2], v[4]])
+    dq = np.zeros((3, 5))
+    for m in range(3):
+        dn = g @ n[m]
+        dq[m] = [dn[0], dn[1:4] @ n[0], dn[1:4] @ n[1], dn[1:4] @ n[2], dn[4]]
+    return q, dq
+
+
+@pytest.mark.slow
+def test_benchmark_workload_sampled_fluxes_and_invariants(gks):
+    """The benchmark workload at full size (hybrid lattice N = 64, Taylor-Green Navier-Stokes, FP64,
+    the launch configuration the benchmark times): for 2000 sampled faces the oracle's Gauss-point
+    flux, fed the states of the GPU's own reconstruction and summed over the face's Gauss points,
+    reproduces the kernel's face fluxes to 1e-12; over 3 steps sum |Omega| Q is conserved to
+    round-off and two runs are bitwise identical."""
+    import torch
+
+    print("case: hybrid N=64 Taylor-Green NS, 2000 sampled faces + conservation + determinism", flush=True)
+    mesh = inputs.lattice(64, "hybrid", box=(2 * math.pi,) * 3)
+    Q0 = inputs.cell_averages(mesh, inputs.tgv())
+    host = gks.HostMesh(mesh)
+    prm = dict(viscous=True, mu=1.0 / 1600.0, Pr=0.72)
+    sol = gks.Solver(host, gks.params(**prm))
+    Q = sol.upload(host.to_internal(Q0))
+    dtt = sol.timestep(Q)
+    coeff = sol.reconstruct(Q)
+    ff = sol.flux(coeff, Q, dtt)
+    sol.poll()
+    C, F, dt = coeff.cpu().numpy(), ff.cpu().numpy(), float(dtt.item())
+    own, nbr = host.faces()
+    geo = host.face_geometry()
+    faces = np.random.default_rng(2203).choice(host.n_faces, 2000, replace=False)
+    op = oracle.params(**prm)
+    ref = np.zeros((len(faces), 10))
+    for r, f in enumerate(faces):
+        for g in range(4):
+            t = 4 * f + g
+            n = _local_frame(geo[6:9, t])
+            ql, dql = _local_state(C[own[f]], geo[0:3, t], n)
+            qr, dqr = _local_state(C[nbr[f]], geo[3:6, t], n)
+            Fb, _ = oracle.gp_flux(op, ql, dql, qr, dqr, dt)
+            area = np.linalg.norm(geo[6:9, t])
+            for s in range(2):
+                Fl = Fb[5 * s:5 * s + 5]
+                ref[r, 5 * s] += area * Fl[0]
+                ref[r, 5 * s + 4] += area * Fl[4]
+                ref[r, 5 * s + 1:5 * s + 4] += area * (Fl[1] * n[0] + Fl[2] * n[1] + Fl[3] * n[2])
+    # Fbar1 = 4 (F(dt) - 2 F(dt/2)) / dt^2 cancels two O(F dt) integrals down to O(Fbar1 dt^2), so
+    # rounding differences between two implementations grow by |Fbar0| / (|Fbar1| dt); the step uses
+    # it only as dt Fbar1 next to Fbar0 (L + dt dL/dt), so both outputs are measured on the scale of
+    # Fbar0: |dFbar0| and dt |dFbar1| against max |Fbar0| per component (momentum shares one scale)
+    scale = np.abs(ref[:, :5]).max(axis=0)
+    scale[1:4] = scale[1:4].max()
+    d = np.abs(F[faces] - ref)
+    err0 = (d[:, :5] / scale).max(axis=0)
+    err1 = (dt * d[:, 5:] / scale).max(axis=0)
+    own_scale1 = np.abs(ref[:, 5:]).max(axis=0)
+    print("sampled face fluxes, Fbar0 relative Linf:", err0, "dt Fbar1 on the Fbar0 scale:", err1,
+          "(Fbar1 on its own scale:", (d[:, 5:] / own_scale1).max(axis=0), ")")
+    assert (err0 <= TOL).all() and (err1 <= TOL).all(), (err0, err1)
+    vol, _ = host.geometry()
+    tot0 = (Q.cpu().numpy() * vol).sum(axis=1)
+    Q2 = Q.clone()
+    for _ in range(3):
+        sol.step(Q)
+        sol.step(Q2)
+    sol.poll()
+    torch.cuda.synchronize()
+    q = Q.cpu().numpy()
+    assert np.array_equal(q, Q2.cpu().numpy())
+    tot1 = (q * vol).sum(axis=1)
+    mag = (np.abs(q) * vol).sum(axis=1)
+    assert (np.abs(tot1 - tot0) <= 1e-13 * mag).all(), (tot1 - tot0) / mag
+
+
 def test_adjoint_refuses_walls(gks):
     import torch
 
@@ -433,6 +535,11 @@ def test_bad_arguments_rejected(gks):
     code = gks.load().gks_timestep(sol.m, ctypes.c_void_p(sol.dt.data_ptr()), ctypes.byref(p),
                                    ctypes.c_void_p(sol.dt.data_ptr()), sol._work_ptr, sol._s())
     assert code == gks.GKS_EINVAL
+    for floor in (-0.1, 1.0, float("nan")):
+        p = gks.params(fallback=True, fallback_floor=floor)
+        code = gks.load().gks_timestep(sol.m, ctypes.c_void_p(sol.dt.data_ptr()), ctypes.byref(p),
+                                       ctypes.c_void_p(sol.dt.data_ptr()), sol._work_ptr, sol._s())
+        assert code == gks.GKS_EINVAL, floor
 
 
 def _wave_errors(gks, kind, N, min_big=0):
