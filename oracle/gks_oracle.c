@@ -72,6 +72,7 @@ typedef struct {
                          cell's average with zero slopes (first order there), and counted */
     double fallback_floor; /* with fallback: also when rho or p is at most this fraction of the
                               cell average's */
+    int smooth;       /* 1: the smooth-flow distribution (Eq. flux-2) instead of the full one (Eq. flux-1) */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -1420,10 +1421,19 @@ int orc_gp_flux(const orc_params *P, const double *ql, const double *dql, const 
         double T4 = tau * om;
         double T5 = 2.0 * tau * tau * om - tau * d * eta;
         double W[2][5];
-        for (int up = 0; up < 2; up++)
-            for (int j = 0; j < 5; j++)
-                W[up][j] = r0 * (T1 * Mg0[up][j] + T2 * Mg0a[up][j] + T3 * Mg0A[up][j]) + T4 * Mh[up][j] -
-                           T5 * Mha[up][j] - tau * T4 * MhA[up][j];
+        if (P->smooth) {
+            /* Eq. flux-2 with the -tau Abar term that the smooth limit of Eq. flux-1 carries (the
+               printed line drops it): f = g0 (1 - tau (abar.u + Abar) + Abar t), integrated over
+               [0, d]: d <.>g0 - tau d <.(abar.u + Abar)>g0 + d^2/2 <.Abar>g0 */
+            for (int up = 0; up < 2; up++)
+                for (int j = 0; j < 5; j++)
+                    W[up][j] = r0 * (d * Mg0[up][j] - tau * d * (Mg0a[up][j] + Mg0A[up][j]) + 0.5 * d * d * Mg0A[up][j]);
+        } else {
+            for (int up = 0; up < 2; up++)
+                for (int j = 0; j < 5; j++)
+                    W[up][j] = r0 * (T1 * Mg0[up][j] + T2 * Mg0a[up][j] + T3 * Mg0A[up][j]) + T4 * Mh[up][j] -
+                               T5 * Mha[up][j] - tau * T4 * MhA[up][j];
+        }
         for (int j = 0; j < 5; j++) Fd[s][j] = W[1][j];
         if (P->viscous && P->Pr != 1.0) {
             /* heat flux about U0 of the time-integrated distribution */

@@ -484,6 +484,47 @@ def test_flux_pieces_and_time_integrals_by_brute_force():
         np.testing.assert_allclose(F[5:], 4 * (Ff - 2 * Fh) / dt ** 2, rtol=1e-12)
 
 
+def test_smooth_flux_by_brute_force_and_as_the_smooth_limit_of_the_full_flux():
+    """Eq. flux-2 with the -tau Abar term (reading R15): its time integrals by quadrature in u and t
+    of g0 (1 - tau (abar.u + Abar) + Abar t) with the oracle's own g0, abar, Abar and tau; and, when
+    both sides carry the same state and slopes, equal to Eq. flux-1 (whose smooth limit it is),
+    inviscid and viscous with Pr != 1."""
+    rng = np.random.default_rng(11)
+    for trial in range(2):
+        ql = prim_to_cons(1.0 + 0.3 * rng.random(), 0.4 * rng.standard_normal(3), 1.0 + 0.3 * rng.random())
+        qr = prim_to_cons(0.6 + 0.3 * rng.random(), 0.4 * rng.standard_normal(3), 0.7 + 0.3 * rng.random())
+        dql = 0.2 * rng.standard_normal((3, 5))
+        dqr = 0.2 * rng.standard_normal((3, 5))
+        dt = 0.03
+        F, dbg = oracle.gp_flux(oracle.params(smooth=True), ql, dql, qr, dqr, dt)
+        rho0, U0, lam0 = dbg[0], dbg[1:4], dbg[4]
+        ab, Ab, tau = dbg[35:50].reshape(3, 5), dbg[60:65], dbg[65]
+        Fh, Ff = dbg[66:71], dbg[71:76]
+        G0 = Quad5(rho0, U0, lam0)
+        adv = G0.slope(ab[0]) * G0.u + G0.slope(ab[1]) * G0.v + G0.slope(ab[2]) * G0.w
+        M0, Ma, MA = G0.moment(G0.u), G0.moment(G0.u * adv), G0.moment(G0.u * G0.slope(Ab))
+
+        def F_of(delta):
+            xt, wt = np.polynomial.legendre.leggauss(8)
+            return sum(w * (M0 - tau * (Ma + MA) + t * MA) for t, w in zip(0.5 * delta * (xt + 1), 0.5 * delta * wt))
+
+        np.testing.assert_allclose(Fh, F_of(0.5 * dt), rtol=1e-9, atol=1e-13)
+        np.testing.assert_allclose(Ff, F_of(dt), rtol=1e-9, atol=1e-13)
+        # the smooth branch keeps the full flux's g0, slopes and collision time
+        _, dbg1 = oracle.gp_flux(oracle.params(), ql, dql, qr, dqr, dt)
+        np.testing.assert_array_equal(dbg[:50], dbg1[:50])
+        np.testing.assert_array_equal(dbg[60:66], dbg1[60:66])
+        # the smooth limit: one state and one set of slopes on both sides
+        for kw in (dict(), dict(viscous=True, mu=2e-3, Pr=0.72)):
+            F1, _ = oracle.gp_flux(oracle.params(**kw), ql, dql, ql, dql, dt)
+            F2, _ = oracle.gp_flux(oracle.params(smooth=True, **kw), ql, dql, ql, dql, dt)
+            np.testing.assert_allclose(F2[:5], F1[:5], rtol=1e-12, atol=1e-13 * np.abs(F1[:5]).max())
+            np.testing.assert_allclose(dt * F2[5:], dt * F1[5:], rtol=0, atol=1e-11 * np.abs(F1[:5]).max())
+        # with different sides the two distributions differ
+        F1, _ = oracle.gp_flux(oracle.params(), ql, dql, qr, dqr, dt)
+        assert np.abs(F1[:5] - F[:5]).max() > 1e-3 * np.abs(F1[:5]).max()
+
+
 def _mirror(q):
     q = np.array(q, float)
     q[..., 1] = -q[..., 1]
