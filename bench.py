@@ -115,14 +115,14 @@ def algorithmic_bytes(host, es):
     return dict(reconstruct=recon, flux=flux, stage1=stage1, stage2=stage2, timestep=timestep)
 
 
-def run_gpu(args, mesh, Q0, precision):
+def run_gpu(args, mesh, Q0, precision, smooth=False):
     import torch
 
     from paper_2203_09047_amd import gks
 
     host = gks.HostMesh(mesh) if not hasattr(run_gpu, "host") else run_gpu.host
     run_gpu.host = host
-    prm = gks.params(precision=precision, viscous=True, mu=1.0 / 1600.0, Pr=0.72, cfl=0.5)
+    prm = gks.params(precision=precision, viscous=True, mu=1.0 / 1600.0, Pr=0.72, cfl=0.5, smooth=smooth)
     sol = gks.Solver(host, prm)
     Q = sol.upload(host.to_internal(Q0))
     for _ in range(args.warmup):
@@ -210,6 +210,7 @@ def main():
     ap.add_argument("--N", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-smooth", action="store_true", help="skip the smooth-flow flux (Eq. flux-2) comparison")
     ap.add_argument("--adj-steps", type=int, default=20, help="steps of the adjoint/forward ratio (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -318,6 +319,19 @@ def main():
                                  error_after_steps=args.warmup + args.steps,
                                  kernels={k: dict(avg_ms=v[0] / max(v[1], 1), launches=v[1])
                                           for k, v in prof32.items() if v[1]})
+    if not args.no_smooth:
+        # the same workload with the smooth-flow flux (Eq. flux-2) at the Gauss points
+        _, solsm, mssm, profsm = run_gpu(args, mesh, Q0, gks.FP64, smooth=True)
+        log(f"fp64 smooth flux: {mssm:.2f} ms {profsm}")
+        qsm = run_gpu.last_q
+        del solsm
+        ksm = {k: dict(avg_ms=v[0] / max(v[1], 1), launches=v[1]) for k, v in profsm.items() if v[1]}
+        res["smooth_flux_fp64"] = dict(
+            value=n * args.steps / (mssm * 1e-3), ms_per_step=mssm / args.steps, speedup_vs_full_flux=ms64 / mssm,
+            flux_kernel_speedup=kern["flux"]["avg_ms"] / ksm["flux"]["avg_ms"],
+            rel_linf_difference_vs_full_flux_per_component=(np.abs(qsm - q64).max(axis=1)
+                                                            / np.abs(q64).max(axis=1)).tolist(),
+            after_steps=args.warmup + args.steps, kernels=ksm)
     if not args.no_cpu:
         t = time.perf_counter()
         res["cpu_baseline"] = cpu_baseline()

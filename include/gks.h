@@ -87,6 +87,10 @@ typedef struct {
     double fallback_floor;    /* with first_order_fallback: a side state also falls back when its
                                  rho or p is at most fallback_floor times its cell average's
                                  (0: positivity only; must lie in [0, 1)) */
+    int smooth_flux;          /* 1: the smooth-flow distribution of Eq. flux-2 at the Gauss points,
+                                 f = g0 (1 - tau (abar . u + Abar) + Abar t) (with the -tau Abar term
+                                 that the smooth limit of Eq. flux-1 carries; the printed equation
+                                 drops it), for smooth flows; 0: Eq. flux-1 (the default) */
 } gks_params;
 
 typedef struct gks_host_mesh gks_host_mesh;
@@ -235,9 +239,9 @@ gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_param
  * gks_adjoint_work_bytes(), 256-byte aligned.  coeff_tape (optional, may be
  * NULL): the step's coefficient tape from gks_s2o4_step; when given, the two
  * reconstructions of Qn and Qstar are read from it instead of recomputed.
- * Periodic meshes only (GKS_EINVAL on a mesh with walls), and the
- * first-order fallback off (GKS_EINVAL otherwise: its switch is not
- * differentiated).  Every gather runs in a fixed order (no atomics): the result is bitwise
+ * Periodic meshes only (GKS_EINVAL on a mesh with walls), with the
+ * first-order fallback and the smooth flux off (GKS_EINVAL otherwise: the
+ * adjoint differentiates Eq. flux-1 without the fallback's switch).  Every gather runs in a fixed order (no atomics): the result is bitwise
  * reproducible, and the same with or without the tape.
  */
 gks_status gks_adjoint_work_bytes(const gks_host_mesh *h, size_t *bytes);

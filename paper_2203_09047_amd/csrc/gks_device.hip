@@ -546,7 +546,7 @@ __device__ __forceinline__ T shfl_xor_t(T v, int mask)
 
 // EXT: walls or the first-order fallback can occur (a separate instantiation keeps the periodic
 // kernel free of both branches)
-template <typename T, bool PR, bool EXT>
+template <typename T, bool PR, bool EXT, bool SM>
 __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict__ coeff, const double *__restrict__ Q,
                                                  const double *__restrict__ dt_dev, T *__restrict__ ff, FluxParams<T> fp,
                                                  int *status)
@@ -573,8 +573,8 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict_
     T out[10];
     // nb < 0: a reflective wall, the right state is the mirror of the left one
     int nfb = 0;
-    const bool ok = face_gp<T, PR, EXT>(coeff + (size_t)50 * o, nb >= 0 ? coeff + (size_t)50 * nb : nullptr, ql0,
-                                        qr0, geo, dt, fp, out, nfb);
+    const bool ok = face_gp<T, PR, EXT, SM>(coeff + (size_t)50 * o, nb >= 0 ? coeff + (size_t)50 * nb : nullptr, ql0,
+                                            qr0, geo, dt, fp, out, nfb);
     if (live && !ok) status[0] = 1;
     if (EXT && live && nfb) atomicAdd(status + 1, nfb);  // integer count: the same total in any order
 #pragma unroll
@@ -595,7 +595,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict_
 // wave's first coefficient loads, so a grid of one block per CU walks contiguous chunks of Gauss
 // points 256 at a time and loads the next chunk's neighbour coefficients while it computes the
 // current chunk (the owners' are mostly the previous chunk's cells, still in cache).
-template <bool PR_ANY>
+template <bool PR_ANY, bool SM>
 __global__ void __launch_bounds__(kBlock) k_flux_chunked(DevMesh m, const double *__restrict__ coeff,
                                                          const double *__restrict__ dt_dev, double *__restrict__ ff,
                                                          FluxParams<double> fp, int *status, int chunk)
@@ -619,7 +619,7 @@ __global__ void __launch_bounds__(kBlock) k_flux_chunked(DevMesh m, const double
         load_cell(coeff + (size_t)50 * m.owner[fs], cl);
         if (base + kBlock < b1) load_cell(coeff + (size_t)50 * m.nbr[face_of(t + kBlock)], crn);
         double out[10];
-        const bool ok = face_gp_pre<double, PR_ANY>(cl, cr, nullptr, nullptr, geo, dt, fp, out);
+        const bool ok = face_gp_pre<double, PR_ANY, SM>(cl, cr, nullptr, nullptr, geo, dt, fp, out);
         if (live && !ok) status[0] = 1;
 #pragma unroll
         for (int j = 0; j < 10; ++j) {
@@ -1100,7 +1100,10 @@ __global__ void __launch_bounds__(kBlock) k_gp_batch(int64_t n, const double *__
             da[mm][j] = (T)dql[15 * i + 5 * mm + j];
             db[mm][j] = (T)dqr[15 * i + 5 * mm + j];
         }
-    gp_flux<T, PR>(a, da, b, db, (T)dt[i], fp, F);
+    if (fp.smooth)
+        gp_flux<T, PR, true>(a, da, b, db, (T)dt[i], fp, F);
+    else
+        gp_flux<T, PR>(a, da, b, db, (T)dt[i], fp, F);
 #pragma unroll
     for (int j = 0; j < 10; ++j) out[10 * i + j] = (double)F[j];
 }
@@ -1118,6 +1121,7 @@ static FluxParams<T> flux_params(const gks_params *p)
     f.viscous = p->viscous;
     f.fallback = p->first_order_fallback;
     f.floor = p->fallback_floor;
+    f.smooth = p->smooth_flux;
     return f;
 }
 
@@ -1534,21 +1538,33 @@ static gks_status launch_reconstruct(gks_mesh *m, const double *Q, void *coeff, 
     return hip_check(hipGetLastError(), "reconstruct launch");
 }
 
-extern "C++" template <typename T, bool PR>
+extern "C++" template <typename T, bool PR, bool SM>
 static void launch_flux_t(gks_mesh *m, bool ext, unsigned grid, const T *coeff, const double *Q, const double *dt_dev,
                           T *ff, const FluxParams<T> &fp, int *status, hipStream_t st)
 {
     if (ext) {
-        k_flux<T, PR, true><<<grid, kBlock, 0, st>>>(m->d, coeff, Q, dt_dev, ff, fp, status);
-    } else if constexpr (sizeof(T) == 8) {
+        k_flux<T, PR, true, SM><<<grid, kBlock, 0, st>>>(m->d, coeff, Q, dt_dev, ff, fp, status);
+    } else if constexpr (sizeof(T) == 8 && !SM) {
+        // the full FP64 flux runs 1 wave/SIMD: chunked with prefetch; the smooth one fits 2 waves/SIMD
+        // one Gauss point per lane and measures faster that way (1.35 vs 1.53 ms at N = 64)
         const int64_t ncu = m->n_cu;
         const int64_t nf4 = 4 * (int64_t)m->nf;
         const int64_t per = ((nf4 + ncu * kBlock - 1) / (ncu * kBlock)) * kBlock;
         const int nblk = (int)((nf4 + per - 1) / per);
-        k_flux_chunked<PR><<<nblk, kBlock, 0, st>>>(m->d, coeff, dt_dev, ff, fp, status, (int)per);
+        k_flux_chunked<PR, SM><<<nblk, kBlock, 0, st>>>(m->d, coeff, dt_dev, ff, fp, status, (int)per);
     } else {
-        k_flux<T, PR, false><<<grid, kBlock, 0, st>>>(m->d, coeff, Q, dt_dev, ff, fp, status);
+        k_flux<T, PR, false, SM><<<grid, kBlock, 0, st>>>(m->d, coeff, Q, dt_dev, ff, fp, status);
     }
+}
+
+extern "C++" template <typename T, bool PR>
+static void launch_flux_s(gks_mesh *m, bool ext, bool smooth, unsigned grid, const T *coeff, const double *Q,
+                          const double *dt_dev, T *ff, const FluxParams<T> &fp, int *status, hipStream_t st)
+{
+    if (smooth)
+        launch_flux_t<T, PR, true>(m, ext, grid, coeff, Q, dt_dev, ff, fp, status, st);
+    else
+        launch_flux_t<T, PR, false>(m, ext, grid, coeff, Q, dt_dev, ff, fp, status, st);
 }
 
 static gks_status launch_flux(gks_mesh *m, const void *coeff, const double *Q, const double *dt_dev, void *ff,
@@ -1559,20 +1575,21 @@ static gks_status launch_flux(gks_mesh *m, const void *coeff, const double *Q, c
     const bool pr = p->viscous && p->Pr != 1.0;
     // wall faces (neighbour < 0) and the fallback exist only in the EXT instantiation
     const bool ext = m->d.walls || p->first_order_fallback;
+    const bool sm = p->smooth_flux != 0;
     if (m->precision == GKS_FP64) {
         auto fp = flux_params<double>(p);
         const double *c = (const double *)coeff;
         if (pr)
-            launch_flux_t<double, true>(m, ext, grid, c, Q, dt_dev, (double *)ff, fp, w.status, st);
+            launch_flux_s<double, true>(m, ext, sm, grid, c, Q, dt_dev, (double *)ff, fp, w.status, st);
         else
-            launch_flux_t<double, false>(m, ext, grid, c, Q, dt_dev, (double *)ff, fp, w.status, st);
+            launch_flux_s<double, false>(m, ext, sm, grid, c, Q, dt_dev, (double *)ff, fp, w.status, st);
     } else {
         auto fp = flux_params<float>(p);
         const float *c = (const float *)coeff;
         if (pr)
-            launch_flux_t<float, true>(m, ext, grid, c, Q, dt_dev, (float *)ff, fp, w.status, st);
+            launch_flux_s<float, true>(m, ext, sm, grid, c, Q, dt_dev, (float *)ff, fp, w.status, st);
         else
-            launch_flux_t<float, false>(m, ext, grid, c, Q, dt_dev, (float *)ff, fp, w.status, st);
+            launch_flux_s<float, false>(m, ext, sm, grid, c, Q, dt_dev, (float *)ff, fp, w.status, st);
     }
     return hip_check(hipGetLastError(), "flux launch");
 }
@@ -1709,6 +1726,7 @@ gks_status gks_adjoint_step(gks_mesh *m, const double *Qn, const double *Qstar, 
     if (m->precision != GKS_FP64) return fail(GKS_EINVAL, "the adjoint runs on an FP64 mesh");
     if (m->d.walls) return fail(GKS_EINVAL, "the adjoint is built for periodic meshes (this one has walls)");
     if (p->first_order_fallback) return fail(GKS_EINVAL, "the adjoint does not differentiate the first-order fallback");
+    if (p->smooth_flux) return fail(GKS_EINVAL, "the adjoint differentiates the full flux (Eq. flux-1) only");
     if (!Qn || !Qstar || !dt_dev || !lam_np1 || !lam_n || !adj_work) return fail(GKS_EINVAL, "null argument");
     if (((uintptr_t)adj_work & 255) != 0) return fail(GKS_EINVAL, "adjoint work buffer must be 256-byte aligned");
     AdjWork aw;
@@ -1802,7 +1820,11 @@ gks_status gks_gp_flux_host(const double *ql, const double *dql, const double *q
                 dl[m][j] = (float)dql[5 * m + j];
                 dr[m][j] = (float)dqr[5 * m + j];
             }
-        ok = pr ? gp_flux<float, true>(l, dl, r, dr, (float)dt, fp, o) : gp_flux<float, false>(l, dl, r, dr, (float)dt, fp, o);
+        if (fp.smooth)
+            ok = pr ? gp_flux<float, true, true>(l, dl, r, dr, (float)dt, fp, o)
+                    : gp_flux<float, false, true>(l, dl, r, dr, (float)dt, fp, o);
+        else
+            ok = pr ? gp_flux<float, true>(l, dl, r, dr, (float)dt, fp, o) : gp_flux<float, false>(l, dl, r, dr, (float)dt, fp, o);
         for (int j = 0; j < 10; ++j) out[j] = o[j];
     } else {
         const FluxParams<double> fp = flux_params<double>(p);
@@ -1812,7 +1834,11 @@ gks_status gks_gp_flux_host(const double *ql, const double *dql, const double *q
                 dl[m][j] = dql[5 * m + j];
                 dr[m][j] = dqr[5 * m + j];
             }
-        ok = pr ? gp_flux<double, true>(ql, dl, qr, dr, dt, fp, out) : gp_flux<double, false>(ql, dl, qr, dr, dt, fp, out);
+        if (fp.smooth)
+            ok = pr ? gp_flux<double, true, true>(ql, dl, qr, dr, dt, fp, out)
+                    : gp_flux<double, false, true>(ql, dl, qr, dr, dt, fp, out);
+        else
+            ok = pr ? gp_flux<double, true>(ql, dl, qr, dr, dt, fp, out) : gp_flux<double, false>(ql, dl, qr, dr, dt, fp, out);
     }
     return ok ? GKS_OK : fail(GKS_ENONPHYS, "non-physical state");
 }
@@ -1823,6 +1849,7 @@ gks_status gks_gp_flux_vjp_host(const double *ql, const double *dql, const doubl
 {
     if (!ql || !dql || !qr || !dqr || !p || !outb || !qlb || !dqlb || !qrb || !dqrb)
         return fail(GKS_EINVAL, "null argument");
+    if (p->smooth_flux) return fail(GKS_EINVAL, "the reverse covers the full flux (Eq. flux-1) only");
     const FluxParams<double> fp = flux_params<double>(p);
     double dl[3][5], dr[3][5], dlb[3][5] = {}, drb[3][5] = {};
     double a[5] = {}, b[5] = {};
@@ -1904,6 +1931,7 @@ gks_status gks_gp_op_count(int viscous, double Pr, int64_t *adds, int64_t *muls,
     fp.viscous = p.viscous;
     fp.fallback = 0;
     fp.floor = 0.0;
+    fp.smooth = 0;
     op_counts() = OpCounts();
     Cnt out[10];
     int nfb = 0;

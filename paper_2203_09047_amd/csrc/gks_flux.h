@@ -25,6 +25,7 @@ struct FluxParams {
     T gamma, K, mu, Pr, tau_eps, tau_C;
     int viscous;
     int fallback;  // first-order fallback of non-physical side states
+    int smooth;    // the smooth-flow distribution (Eq. flux-2) instead of Eq. flux-1
     double floor;  // ... and of states whose rho or p is at most floor times the cell average's
 };
 
@@ -246,7 +247,9 @@ __host__ __device__ __forceinline__ void axpy5(T *y, T a, const T *x)
 }
 
 // One side of the interface: sign = +1 for the left state (u > 0), -1 for the right (u < 0).
-template <typename T, bool PR>
+// SM: the smooth-flow flux needs only the half-space moments of the side state and of its spatial
+// slopes (g_0 and its slopes); the side's time slope and non-equilibrium terms are skipped.
+template <typename T, bool PR, bool SM = false>
 __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5], T sign, const FluxParams<T> &fp,
                                                    FluxAcc<T, PR> &A, int side)
 {
@@ -257,7 +260,7 @@ __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5
     if (!ok) return false;
     Mom<T> M;
     mom_common(M, V, W, lam, K);
-    mom_full_u(M, U, lam);
+    if constexpr (!SM) mom_full_u(M, U, lam);
     // spatial slopes <a_m> = dQ/dn_m / rho, time slope from <a_1 u + a_2 v + a_3 w + A> = 0
     T a[3][5], Ab[5];
     const T ir = T(1) / rho;
@@ -268,7 +271,7 @@ __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5
         for (int j = 0; j < 5; ++j) b[j] = dq[m][j] * ir;
         slope_solve(b, U, V, W, lam, K, a[m]);
     }
-    {
+    if constexpr (!SM) {
         T b[5];
         Padv<0>(M, a, b);
 #pragma unroll
@@ -285,6 +288,7 @@ __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5
         Pa<0, 0, 0>(M, a[m], t);
         axpy5(A.bab[m], rho, t);
     }
+    if constexpr (SM) return true;
     P<1, 0, 0>(M, t);
     axpy5(A.Mh, rho, t);
     Padv<1>(M, a, t);
@@ -304,7 +308,9 @@ __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5
  * out[0..4]: flux per unit area at the start of the step, out[5..9]: its time
  * derivative.  Returns false if the interface state is non-physical.
  */
-template <typename T, bool PR>
+// SM: the time integrals of Eq. flux-2, f = g0 (1 - tau (abar . u + Abar) + Abar t) (with the -tau Abar
+// term that the smooth limit of Eq. flux-1 carries), instead of those of Eq. flux-1.
+template <typename T, bool PR, bool SM = false>
 __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T dt, const FluxParams<T> &fp, T out[10])
 {
     const T K = fp.K;
@@ -347,22 +353,32 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const T d = s == 0 ? T(0.5) * dt : dt;
-        const T eta = exp_t(-d / tau);
-        const T om = -expm1_t(-d / tau);
-        const T T1 = d - tau * om;
-        const T T2 = T(2) * tau * tau * om - tau * d * (T(1) + eta);
-        const T T3 = T(0.5) * d * d - tau * d + tau * tau * om;
-        const T T4 = tau * om;
-        const T T5 = T(2) * tau * tau * om - tau * d * eta;
+        T T1, T2, T3, T4 = T(0), T5 = T(0);
+        if constexpr (SM) {
+            T1 = d;
+            T2 = -tau * d;
+            T3 = T(0.5) * d * d - tau * d;
+        } else {
+            const T eta = exp_t(-d / tau);
+            const T om = -expm1_t(-d / tau);
+            T1 = d - tau * om;
+            T2 = T(2) * tau * tau * om - tau * d * (T(1) + eta);
+            T3 = T(0.5) * d * d - tau * d + tau * tau * om;
+            T4 = tau * om;
+            T5 = T(2) * tau * tau * om - tau * d * eta;
+        }
 #pragma unroll
-        for (int j = 0; j < 5; ++j)
-            Fd[s][j] = r0 * (T1 * M0[j] + T2 * Ma[j] + T3 * MA[j]) + T4 * A.Mh[j] - T5 * A.Mha[j] - tau * T4 * A.MhA[j];
+        for (int j = 0; j < 5; ++j) {
+            Fd[s][j] = r0 * (T1 * M0[j] + T2 * Ma[j] + T3 * MA[j]);
+            if constexpr (!SM) Fd[s][j] += T4 * A.Mh[j] - T5 * A.Mha[j] - tau * T4 * A.MhA[j];
+        }
         if constexpr (PR) {
             T Wv[5];
 #pragma unroll
-            for (int j = 0; j < 5; ++j)
-                Wv[j] = r0 * (T1 * W0m[j] + T2 * Wam[j] + T3 * WAm[j]) + T4 * A.q0[j] - T5 * A.Wha[j] -
-                        tau * T4 * A.WhA[j];
+            for (int j = 0; j < 5; ++j) {
+                Wv[j] = r0 * (T1 * W0m[j] + T2 * Wam[j] + T3 * WAm[j]);
+                if constexpr (!SM) Wv[j] += T4 * A.q0[j] - T5 * A.Wha[j] - tau * T4 * A.WhA[j];
+            }
             const T *F = Fd[s];
             const T U2 = U0 * U0 + V0 * V0 + W0 * W0;
             // heat flux about the interface velocity of the time-integrated distribution (times 2)
@@ -385,20 +401,20 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
  * derivatives.  Returns false if a state (left, right or interface) is
  * non-physical; the output is then zero.
  */
-template <typename T, bool PR>
+template <typename T, bool PR, bool SM = false>
 __host__ __device__ bool gp_flux(const T ql[5], const T dql[3][5], const T qr[5], const T dqr[3][5], T dt,
                                  const FluxParams<T> &fp, T out[10])
 {
     FluxAcc<T, PR> A;
     acc_zero(A);
-    bool ok = side_pass<T, PR>(ql, dql, T(1), fp, A, 0);
-    ok = side_pass<T, PR>(qr, dqr, T(-1), fp, A, 1) && ok;
+    bool ok = side_pass<T, PR, SM>(ql, dql, T(1), fp, A, 0);
+    ok = side_pass<T, PR, SM>(qr, dqr, T(-1), fp, A, 1) && ok;
     if (!ok) {
 #pragma unroll
         for (int j = 0; j < 10; ++j) out[j] = T(0);
         return false;
     }
-    return finish_flux<T, PR>(A, dt, fp, out);
+    return finish_flux<T, PR, SM>(A, dt, fp, out);
 }
 
 // Local frame at a Gauss point: n1 = unit weighted vector area; e = the coordinate
@@ -557,7 +573,7 @@ __host__ __device__ __forceinline__ bool fallback_side(const FluxParams<T> &fp, 
 // The flux of one Gauss point of an interior face from both cells' coefficients already in registers
 // (ql0, qr0: the FP64 cell averages that FP32 coefficients exclude; unused in FP64); the same
 // arithmetic as face_gp without walls or the fallback.
-template <typename T, bool PR>
+template <typename T, bool PR, bool SM = false>
 __host__ __device__ __forceinline__ bool face_gp_pre(const T cl[50], const T cr[50], const double *ql0,
                                                      const double *qr0, const T geo[9], T dt,
                                                      const FluxParams<T> &fp, T out[10])
@@ -570,16 +586,16 @@ __host__ __device__ __forceinline__ bool face_gp_pre(const T cl[50], const T cr[
     {
         T q[5], dq[3][5];
         side_state(cl, ql0, geo[0], geo[1], geo[2], n3, q, dq);
-        ok = side_pass<T, PR>(q, dq, T(1), fp, A, 0);
+        ok = side_pass<T, PR, SM>(q, dq, T(1), fp, A, 0);
     }
     {
         T q[5], dq[3][5];
         side_state(cr, qr0, geo[3], geo[4], geo[5], n3, q, dq);
-        ok = side_pass<T, PR>(q, dq, T(-1), fp, A, 1) && ok;
+        ok = side_pass<T, PR, SM>(q, dq, T(-1), fp, A, 1) && ok;
     }
     T F[10];
     if (ok) {
-        ok = finish_flux<T, PR>(A, dt, fp, F);
+        ok = finish_flux<T, PR, SM>(A, dt, fp, F);
     } else {
 #pragma unroll
         for (int j = 0; j < 10; ++j) F[j] = T(0);
@@ -599,7 +615,7 @@ __host__ __device__ __forceinline__ bool face_gp_pre(const T cl[50], const T cr[
 // ignored.  With it, cr_g == nullptr means the face is a reflective wall and the right state is the
 // mirror of the left one.  ql0, qr0: the two cells' FP64 averages (read for FP32 coefficients and for
 // the fallback); nfb counts the sides that fell back.
-template <typename T, bool PR, bool EXT>
+template <typename T, bool PR, bool EXT, bool SM = false>
 __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, const T *__restrict__ cr_g, const double *ql0,
                                                  const double *qr0, const T geo[9], T dt, const FluxParams<T> &fp,
                                                  T out[10], int &nfb)
@@ -614,7 +630,7 @@ __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, con
         load_cell(cl_g, cl);
         side_state(cl, ql0, geo[0], geo[1], geo[2], n3, q, dq);
         if (EXT) nfb += fallback_side(fp, ql0, n3, q, dq);
-        ok = side_pass<T, PR>(q, dq, T(1), fp, A, 0);
+        ok = side_pass<T, PR, SM>(q, dq, T(1), fp, A, 0);
     }
     {
         T q[5], dq[3][5], cr[50];
@@ -629,11 +645,11 @@ __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, con
             nfb += fallback_side(fp, ql0, n3, qi, dqi);  // the mirror of a fallen-back side falls back too
             wall_mirror(qi, dqi, q, dq);
         }
-        ok = side_pass<T, PR>(q, dq, T(-1), fp, A, 1) && ok;
+        ok = side_pass<T, PR, SM>(q, dq, T(-1), fp, A, 1) && ok;
     }
     T F[10];
     if (ok) {
-        ok = finish_flux<T, PR>(A, dt, fp, F);
+        ok = finish_flux<T, PR, SM>(A, dt, fp, F);
     } else {
 #pragma unroll
         for (int j = 0; j < 10; ++j) F[j] = T(0);

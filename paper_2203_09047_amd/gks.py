@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "EDEVICE", 3: "ESINGULAR", 4: "ENONPHYS
 
 SYMBOLS = [
     "gks_default_params", "gks_preprocess", "gks_host_mesh_free", "gks_host_mesh_counts", "gks_host_mesh_perm",
-    "gks_host_mesh_geometry", "gks_host_mesh_faces", "gks_host_mesh_face_geometry", "gks_mesh_sizes", "gks_init_mesh", "gks_destroy_mesh",
+    "gks_host_mesh_geometry", "gks_host_mesh_faces", "gks_host_mesh_face_geometry", "gks_mesh_sizes", "gks_init_mesh",
+    "gks_destroy_mesh",
     "gks_reset_status", "gks_timestep", "gks_reconstruct", "gks_flux", "gks_residual", "gks_s2o4_step",
     "gks_poll_status", "gks_fallback_count", "gks_gp_flux_batch", "gks_profile", "gks_profile_read", "gks_gp_op_count",
     "gks_gp_flux_host", "gks_gp_flux_vjp_host", "gks_weno_combine_host", "gks_weno_combine_vjp_host",
@@ -44,7 +45,7 @@ class Params(ctypes.Structure):
         ("weno_eps", ctypes.c_double), ("weno_gamma_m", ctypes.c_double), ("weno_p", ctypes.c_double),
         ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double), ("viscous", ctypes.c_int),
         ("precision", ctypes.c_int), ("force_linear", ctypes.c_int), ("dt_given", ctypes.c_int),
-        ("first_order_fallback", ctypes.c_int), ("fallback_floor", ctypes.c_double),
+        ("first_order_fallback", ctypes.c_int), ("fallback_floor", ctypes.c_double), ("smooth_flux", ctypes.c_int),
     ]
 
 
@@ -145,7 +146,7 @@ def _dp(t):
 
 def params(precision=FP64, gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, viscous=False, weno_eps=1e-6, weno_gamma_m=0.0125,
            weno_p=1.0, tau_eps=0.01, tau_C=1.0, force_linear=False, dt_given=False, fallback=False,
-           fallback_floor=0.0) -> Params:
+           fallback_floor=0.0, smooth=False) -> Params:
     p = Params()
     load().gks_default_params(ctypes.byref(p))
     p.gamma, p.cfl, p.mu, p.Pr = gamma, cfl, mu, Pr
@@ -154,6 +155,7 @@ def params(precision=FP64, gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, viscous=False, we
     p.viscous, p.precision, p.force_linear, p.dt_given = int(viscous), int(precision), int(force_linear), int(dt_given)
     p.first_order_fallback = int(fallback)
     p.fallback_floor = float(fallback_floor)
+    p.smooth_flux = int(smooth)
     return p
 
 

@@ -182,6 +182,65 @@ def test_hybrid_steps_fp64_parity(gks, kind, N, steps):
     assert (err <= TOL).all(), err
 
 
+@pytest.mark.parametrize("case", ["tgv-ns-hybrid", "wave-euler-tet", "riemann-walls-hybrid"])
+def test_smooth_flux_matches_oracle(gks, case):
+    """The smooth-flow flux (Eq. flux-2) through the whole step: Taylor-Green Navier-Stokes on the
+    hybrid lattice (the FP64 periodic kernel), the density wave on Kuhn tetrahedra (Euler), and the
+    walled Riemann problem with the fallback (the walls/fallback kernel), 3 steps with the oracle's
+    step sizes, FP64 to 1e-12; FP32-mixed on the first case to 1e-5."""
+    import torch
+
+    print(f"case: smooth flux, {case} x 3 steps", flush=True)
+    if case == "tgv-ns-hybrid":
+        mesh = inputs.lattice(6, "hybrid", box=(2 * np.pi,) * 3)
+        Q0 = inputs.cell_averages(mesh, inputs.tgv())
+        kw = dict(viscous=True, mu=1.0 / 1600.0, Pr=0.72)
+    elif case == "wave-euler-tet":
+        mesh = inputs.lattice(5, "tet")
+        Q0 = inputs.cell_averages(mesh, inputs.wave())
+        kw = dict()
+    else:
+        mesh = inputs.lattice(6, "hybrid", periodic=False)
+        Q0 = inputs.cell_averages(mesh, inputs.riemann())
+        kw = dict(fallback=True, fallback_floor=0.1, cfl=0.3)
+    host = gks.HostMesh(mesh)
+    o = oracle.Oracle(mesh, oracle.params(smooth=True, **kw))
+    dts, ref = [], Q0.copy()
+    for _ in range(3):
+        dts.append(o.timestep(ref))
+        ref = o.step(ref, dts[-1])
+    scale = np.abs(ref).max(axis=1)
+    scale[1:4] = scale[1:4].max()
+    for prec, tol in ((gks.FP64, TOL), (gks.FP32_MIXED, 1e-5)):
+        if prec == gks.FP32_MIXED and case != "tgv-ns-hybrid":
+            continue
+        sol = gks.Solver(host, gks.params(precision=prec, smooth=True, **kw))
+        Q = sol.upload(host.to_internal(Q0))
+        for dt in dts:
+            sol.step(Q, dt)
+        sol.poll()
+        torch.cuda.synchronize()
+        err = np.abs(host.to_external(Q.cpu().numpy()) - ref).max(axis=1) / scale
+        print(f"precision {prec}: relative Linf per component:", err)
+        assert (err <= tol).all(), err
+    # the full flux differs from the smooth one on these data
+    full = oracle.Oracle(mesh, oracle.params(**kw)).step(Q0, dts[0])
+    assert np.abs(full - o.step(Q0, dts[0])).max() > 1e-10 * np.abs(Q0).max()
+
+
+def test_adjoint_refuses_the_smooth_flux(gks):
+    import torch
+
+    mesh = inputs.lattice(3, "hex")
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host, gks.params(smooth=True))
+    Q = sol.upload(host.to_internal(inputs.cell_averages(mesh, inputs.uniform())))
+    dtt = torch.tensor([1e-3], dtype=torch.float64, device=Q.device)
+    with pytest.raises(gks.GksError) as e:
+        sol.adjoint_step(Q, Q.clone(), dtt, torch.zeros_like(Q))
+    assert e.value.code == gks.GKS_EINVAL
+
+
 def test_taylor_green_navier_stokes_fp64_parity(gks):
     """The benchmark's workload at small size: Taylor-Green vortex at Mach 0.1, mu = 1/1600,
     Pr = 0.72 on the hybrid lattice of [0, 2 pi]^3, 4 steps with the oracle's step sizes.  The

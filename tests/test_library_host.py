@@ -83,6 +83,37 @@ def test_preprocessor_walls_match_oracle(kind):
     assert host.n_grown == sum(o.grown(c) for c in range(mesh.n_cells))
 
 
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@pytest.mark.parametrize("smooth", [False, True])
+@pytest.mark.parametrize("viscous", [False, True])
+def test_host_gauss_point_flux_matches_oracle(smooth, viscous):
+    """The library's templated Gauss-point flux, executed on the host in FP64, against the oracle's
+    independent one, for Eq. flux-1 and for the smooth-flow Eq. flux-2."""
+    lib = gks.load()
+    kw = dict(viscous=viscous, mu=2e-3, Pr=0.72 if viscous else 1.0, smooth=smooth)
+    prm, oprm = gks.params(**kw), oracle.params(**kw)
+    rng = np.random.default_rng(5 + 2 * smooth + viscous)
+
+    def cons(rho, U, p):
+        U = np.asarray(U, float)
+        return np.r_[rho, rho * U, p / 0.4 + 0.5 * rho * U @ U]
+
+    for _ in range(4):
+        ql = cons(1 + 0.3 * rng.random(), 0.5 * rng.standard_normal(3), 1 + 0.3 * rng.random())
+        qr = cons(0.6 + 0.3 * rng.random(), 0.5 * rng.standard_normal(3), 0.7 + 0.3 * rng.random())
+        dql, dqr = 0.3 * rng.standard_normal((3, 5)), 0.3 * rng.standard_normal((3, 5))
+        dt = 0.02
+        out = np.zeros(10)
+        assert lib.gks_gp_flux_host(_p(ql), _p(dql), _p(qr), _p(dqr), dt, ctypes.byref(prm), _p(out)) == 0
+        ref, _ = oracle.gp_flux(oprm, ql, dql, qr, dqr, dt)
+        scale = np.abs(ref[:5]).max()
+        np.testing.assert_allclose(out[:5], ref[:5], rtol=0, atol=1e-13 * scale)
+        np.testing.assert_allclose(dt * out[5:], dt * ref[5:], rtol=0, atol=1e-13 * scale)
+
+
 def test_preprocessor_rejects_bad_meshes():
     mesh = inputs.lattice(3, "hex")
     bad_types = mesh.types.copy()
