@@ -184,11 +184,29 @@ def run_adjoint(args, host, mesh, Q0):
                 ratio=(t2 - t1) / (t1 - t0), kernels_backward=kern)
 
 
-def cpu_baseline(N_sample=16):
+def copy_bandwidth():
+    """Device-to-device copy of 1 GiB (FP64), 10 times between HIP events: bytes read + written / time."""
+    import torch
+
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 10 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def cpu_baseline(N_sample=16, threads=1):
     import oracle
     from paper_2203_09047_amd import inputs
 
-    oracle.set_threads(1)  # the oracle's loops run single-threaded for this baseline
+    oracle.set_threads(threads)  # the oracle's two parallel loops (results do not depend on the count)
     mesh = inputs.lattice(N_sample, "hybrid", box=(2 * math.pi,) * 3)
     Q0 = inputs.cell_averages(mesh, inputs.tgv())
     prm = oracle.params(viscous=True, mu=1.0 / 1600.0, Pr=0.72, cfl=0.5)
@@ -197,9 +215,10 @@ def cpu_baseline(N_sample=16):
     t = time.perf_counter()
     o.step(Q0, dt)
     el = time.perf_counter() - t
-    return dict(value=mesh.n_cells / el, unit="cell-updates/s", cores=1, kind="oracle",
+    used = oracle.threads()
+    return dict(value=mesh.n_cells / el, unit="cell-updates/s", cores=used, kind="oracle",
                 sample=f"hybrid lattice N={N_sample} ({mesh.n_cells} cells), Taylor-Green Mach 0.1 NS, "
-                       f"1 S2O4 step, single-threaded FP64 C oracle, {el:.1f} s")
+                       f"1 S2O4 step, FP64 C oracle on {used} thread(s), {el:.1f} s")
 
 
 def main():
@@ -332,9 +351,12 @@ def main():
             rel_linf_difference_vs_full_flux_per_component=(np.abs(qsm - q64).max(axis=1)
                                                             / np.abs(q64).max(axis=1)).tolist(),
             after_steps=args.warmup + args.steps, kernels=ksm)
+    res["hbm_copy_gbs_measured"] = copy_bandwidth()
     if not args.no_cpu:
         t = time.perf_counter()
         res["cpu_baseline"] = cpu_baseline()
+        res["cpu_all_cores"] = cpu_baseline(threads=os.cpu_count() if os.environ.get("OMP_NUM_THREADS") is None
+                                            else int(os.environ["OMP_NUM_THREADS"]))
         log(f"cpu baseline {time.perf_counter() - t:.1f} s")
     print(json.dumps(res), flush=True)
 
