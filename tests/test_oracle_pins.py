@@ -768,6 +768,51 @@ def test_fallback_floor_only_adds_fallbacks():
     assert o.fallback_count() == 0
 
 
+# ---------------------------------------------------------------------------
+# implicit Jacobi step of the steady solver
+# ---------------------------------------------------------------------------
+def _decay_problem():
+    """A gas at rest with the seeded low-pass velocity perturbation, viscous: it decays to rest."""
+    from oracle import implicit
+
+    m = inputs.lattice(4, "hybrid")
+    Q0 = inputs.cell_averages(m, inputs.perturbed_wave(amp=0.0, U=(0.0, 0.0, 0.0)))
+    return implicit, m, Q0, oracle.Oracle(m, oracle.params(viscous=True, mu=0.02, Pr=0.72))
+
+
+def test_implicit_step_keeps_uniform_flow_and_tends_to_the_explicit_residual():
+    """A uniform flow is a steady state of the implicit step; as dt -> 0 the implicit increment
+    tends to dt times the GKS residual (forward Euler), the implicit operator's share being O(dt)."""
+    implicit, m, Q0, o = _decay_problem()
+    Qu = inputs.cell_averages(m, inputs.uniform(1.2, 0.3, -0.2, 0.1, 0.9))
+    dtf = o.timestep(Qu)
+    d = implicit.jacobi_step(o, Qu, 10 * dtf, dt_flux=dtf) - Qu
+    assert np.abs(d).max() <= 1e-13 * np.abs(Qu).max()
+    dt = 1e-6 * o.timestep(Q0)
+    L, D = o.residual(Q0, dt)
+    res = L + 0.5 * dt * D
+    dQ = implicit.jacobi_step(o, Q0, dt) - Q0
+    assert np.abs(dQ / dt - res).max() <= 1e-5 * np.abs(res).max()
+
+
+def test_implicit_jacobi_sweeps_converge_and_the_steady_state_is_reached():
+    """The spectral radius r >= |U.n| + c makes the system diagonally dominant: the Jacobi sweeps
+    converge geometrically to its solution; and implicit steps 10 times the explicit step drive the
+    decaying perturbation to rest, the residual falling by more than three orders of magnitude."""
+    implicit, m, Q0, o = _decay_problem()
+    dtf = o.timestep(Q0)
+    its = [implicit.jacobi_step(o, Q0, 4 * dtf, kmax=k, dt_flux=dtf) for k in (10, 20, 40, 80, 81)]
+    ch = [np.abs(b - a).max() for a, b in zip(its, its[1:])]
+    assert all(b < 0.1 * a for a, b in zip(ch, ch[1:-1])) and ch[-1] <= 1e-10 * np.abs(its[-1] - Q0).max(), ch
+    Q = Q0.copy()
+    r0 = implicit.residual_norm(o, Q, dtf)
+    for _ in range(30):
+        dtf = o.timestep(Q)
+        Q = implicit.jacobi_step(o, Q, 10 * dtf, dt_flux=dtf)
+    assert implicit.residual_norm(o, Q, o.timestep(Q)) < 1e-3 * r0
+    assert np.abs(Q[1:4]).max() < 0.1 * np.abs(Q0[1:4]).max()
+
+
 @pytest.mark.slow
 def test_third_order_convergence_on_hexahedra():
     errs = []
