@@ -230,6 +230,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-smooth", action="store_true", help="skip the smooth-flow flux (Eq. flux-2) comparison")
+    ap.add_argument("--no-implicit", action="store_true", help="skip the implicit Jacobi step timing")
     ap.add_argument("--adj-steps", type=int, default=20, help="steps of the adjoint/forward ratio (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -351,6 +352,31 @@ def main():
             rel_linf_difference_vs_full_flux_per_component=(np.abs(qsm - q64).max(axis=1)
                                                             / np.abs(q64).max(axis=1)).tolist(),
             after_steps=args.warmup + args.steps, kernels=ksm)
+    if not args.no_implicit:
+        # the paper's steady-solver path: one implicit step = reconstruction + flux over the CFL step,
+        # the flux-split implicit operator with a pseudo-time step 10 times that, 3 Jacobi sweeps
+        from paper_2203_09047_amd import gks as _g
+        soli = _g.Solver(run_gpu.host, _g.params(viscous=True, mu=1.0 / 1600.0, Pr=0.72, cfl=0.5))
+        Qi = soli.upload(run_gpu.host.to_internal(Q0))
+        for _ in range(args.warmup):
+            soli.implicit_step(Qi, dt_factor=10.0, kmax=3)
+        soli.poll()
+        soli.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            soli.implicit_step(Qi, dt_factor=10.0, kmax=3)
+        e1.record()
+        torch.cuda.synchronize()
+        msi = e0.elapsed_time(e1)
+        profi = soli.profile_read()
+        soli.profile(False)
+        soli.poll()
+        del soli
+        res["implicit_jacobi_fp64"] = dict(
+            value=n * args.steps / (msi * 1e-3), unit="cell-steps/s", ms_per_step=msi / args.steps, kmax=3,
+            dt_factor=10.0, kernels={k: dict(avg_ms=v[0] / max(v[1], 1), launches=v[1]) for k, v in profi.items() if v[1]})
     res["hbm_copy_gbs_measured"] = copy_bandwidth()
     if not args.no_cpu:
         t = time.perf_counter()

@@ -244,6 +244,24 @@ gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_param
  * adjoint differentiates Eq. flux-1 without the fallback's switch).  Every gather runs in a fixed order (no atomics): the result is bitwise
  * reproducible, and the same with or without the tape.
  */
+/*
+ * One implicit step of the steady solver (Section 3.3: Eq. impEuler with the
+ * flux-split operator of Eq. euler-scheme, solved by the Jacobi iteration of
+ * Eq. jacobi with kmax sweeps).  Res = L + dt_f/2 dL/dt is the GKS residual
+ * (reconstruction + Eq. flux-1, or Eq. flux-2 with smooth_flux) integrated
+ * over the flux step dt_f = *dt_dev (the CFL step unless p->dt_given); the
+ * implicit pseudo-time step is dt = dt_factor * dt_f.  Per cell i, with T
+ * the Euler flux along the outward face normal, S the face area and
+ * r = |U_nb . n| + c_nb at t_n:
+ *   D_i dQ_i^(k) = |Omega_i| Res_i - 1/2 sum_f [T(Q_nb + dQ_nb^(k-1)) - T(Q_nb) - r dQ_nb^(k-1)] S,
+ *   D_i = |Omega_i| / dt + 1/2 sum_f r S,  dQ^(0) = |Omega| Res / D,
+ * and Q += dQ^(kmax) in place.  The work buffer's coefficient area holds the
+ * iteration.  Periodic meshes only (GKS_EINVAL with walls); dt_factor > 0,
+ * 0 <= kmax <= 1000.  The paper times this path with kmax = 3.
+ */
+gks_status gks_implicit_step(gks_mesh *m, double *Q, double *dt_dev, double dt_factor, int kmax, const gks_params *p,
+                             void *work, gks_stream_t stream);
+
 gks_status gks_adjoint_work_bytes(const gks_host_mesh *h, size_t *bytes);
 gks_status gks_adjoint_step(gks_mesh *m, const double *Qn, const double *Qstar, const double *dt_dev,
                             const double *lam_np1, double *lam_n, const gks_params *p, void *adj_work,
@@ -291,7 +309,8 @@ enum {
     GKS_K_FLUX_ADJ = 6,
     GKS_K_RECONSTRUCT_ADJ = 7,
     GKS_K_GATHER_ADJ = 8,
-    GKS_K_COUNT = 9
+    GKS_K_IMPLICIT = 9,
+    GKS_K_COUNT = 10
 };
 gks_status gks_profile(gks_mesh *m, int enable);
 gks_status gks_profile_read(gks_mesh *m, double *total_ms, int64_t *launches);

@@ -78,6 +78,7 @@ struct DevMesh {
     // faces
     const int32_t *owner, *nbr;
     const double *fgeo;     // [9][4 nf]
+    const double *fnS;      // [4][nf]: unit normal (owner -> neighbour) and area of each face
     const int32_t *cf_ptr, *cf_idx;
     const int32_t *tr_ptr, *tr_idx;  // transposed stencil (adjoint gathers)
 };
@@ -712,6 +713,103 @@ __global__ void __launch_bounds__(kBlock) k_stage2(DevMesh m, const T *__restric
     for (int c = 0; c < 5; ++c) Q[(size_t)c * m.n + i] += dt * dt / 3.0 * D[c];
 }
 
+
+// ---------------------------------------------------------------------------
+// Implicit Jacobi step of the steady solver (Section 3.3, Eq. euler-scheme and Eq. jacobi):
+// D_i dQ_i + 1/2 sum_f [T(Q_nb + dQ_nb) - T(Q_nb) - r dQ_nb] S = |Omega_i| Res_i with
+// D_i = |Omega_i| / dt + 1/2 sum_f r S, T the Euler flux along the cell's outward face normal,
+// r = |U_nb . n| + c_nb at t_n and Res = L + dt_f/2 dL/dt the GKS residual over the explicit step
+// dt_f (dt = factor x dt_f); every gather runs over the cell's faces in F_p order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double euler_flux_n(const double q[5], double nx, double ny, double nz, double gam,
+                                               double T[5])
+{
+    const double ir = 1.0 / q[0];
+    const double u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
+    const double un = u * nx + v * ny + w * nz;
+    const double p = (gam - 1.0) * (q[4] - 0.5 * (q[1] * u + q[2] * v + q[3] * w));
+    T[0] = q[0] * un;
+    T[1] = q[1] * un + p * nx;
+    T[2] = q[2] * un + p * ny;
+    T[3] = q[3] * un + p * nz;
+    T[4] = (q[4] + p) * un;
+    return fabs(un) + sqrt(gam * p * ir);  // spectral radius of the normal flux Jacobian
+}
+
+// the neighbour across a cell's face (code = 2 face + side) and the cell's outward unit normal
+__device__ __forceinline__ int face_side(const DevMesh &m, int code, double &nx, double &ny, double &nz, double &S)
+{
+    const int f = code >> 1;
+    const double sg = (code & 1) ? -1.0 : 1.0;  // side 0: the owner, normal owner -> neighbour
+    nx = sg * m.fnS[f];
+    ny = sg * m.fnS[m.nf + f];
+    nz = sg * m.fnS[2 * m.nf + f];
+    S = m.fnS[3 * m.nf + f];
+    return (code & 1) ? m.owner[f] : m.nbr[f];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_implicit_init(DevMesh m, const T *__restrict__ ff, const double *__restrict__ Q,
+                                                          const double *__restrict__ dt_dev, double factor, double gam,
+                                                          double *__restrict__ b, double *__restrict__ diag,
+                                                          double *__restrict__ dq)
+{
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= m.n) return;
+    const int n = m.n;
+    double L[5], D[5];
+    gather(m, ff, i, L, D);
+    const double dtf = dt_dev[0], vol = m.vol[i];
+    double sumr = 0.0;
+    for (int p = m.cf_ptr[i]; p < m.cf_ptr[i + 1]; ++p) {
+        double nx, ny, nz, S, q[5], Tn[5];
+        const int nb = face_side(m, m.cf_idx[p], nx, ny, nz, S);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) q[c] = Q[(size_t)c * n + nb];
+        sumr += euler_flux_n(q, nx, ny, nz, gam, Tn) * S;
+    }
+    const double d = vol / (factor * dtf) + 0.5 * sumr;
+    diag[i] = d;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        const double bc = vol * (L[c] + 0.5 * dtf * D[c]);
+        b[(size_t)c * n + i] = bc;
+        dq[(size_t)c * n + i] = bc / d;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_implicit_sweep(DevMesh m, const double *__restrict__ Q, double gam,
+                                                           const double *__restrict__ b, const double *__restrict__ diag,
+                                                           const double *__restrict__ dq_in, double *__restrict__ dq_out)
+{
+    const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= m.n) return;
+    const int n = m.n;
+    double off[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int p = m.cf_ptr[i]; p < m.cf_ptr[i + 1]; ++p) {
+        double nx, ny, nz, S, q[5], d[5], q1[5], T0[5], T1[5];
+        const int nb = face_side(m, m.cf_idx[p], nx, ny, nz, S);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            q[c] = Q[(size_t)c * n + nb];
+            d[c] = dq_in[(size_t)c * n + nb];
+            q1[c] = q[c] + d[c];
+        }
+        const double r = euler_flux_n(q, nx, ny, nz, gam, T0);
+        euler_flux_n(q1, nx, ny, nz, gam, T1);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) off[c] += (T1[c] - T0[c] - r * d[c]) * S;
+    }
+    const double di = diag[i];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) dq_out[(size_t)c * n + i] = (b[(size_t)c * n + i] - 0.5 * off[c]) / di;
+}
+
+__global__ void __launch_bounds__(kBlock) k_implicit_update(int len, double *__restrict__ Q, const double *__restrict__ dq)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < len) Q[t] += dq[t];
+}
 
 // ===========================================================================
 // Discrete adjoint of one S2O4 step (FP64)
@@ -1389,6 +1487,26 @@ static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *ba
     dm.owner = (const int32_t *)put(H.owner.data(), 4 * nf);
     dm.nbr = (const int32_t *)put(H.nbr.data(), 4 * nf);
     dm.fgeo = (const double *)put(H.fgeo.data(), 8 * H.fgeo.size());
+    {
+        // face normal from the summed weighted vector areas of the Gauss points, area as their sum of norms
+        std::vector<char> fn(owned ? 8 * 4 * nf : 0);
+        if (owned)
+            for (int64_t f = 0; f < nf; ++f) {
+                double A[3] = {0.0, 0.0, 0.0}, S = 0.0;
+                for (int g = 0; g < 4; ++g) {
+                    double v[3];
+                    for (int q = 0; q < 3; ++q) {
+                        v[q] = H.fgeo[(size_t)(6 + q) * 4 * nf + 4 * f + g];
+                        A[q] += v[q];
+                    }
+                    S += std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                }
+                const double a = std::sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+                const double row[4] = {A[0] / a, A[1] / a, A[2] / a, S};
+                for (int q = 0; q < 4; ++q) std::memcpy(&fn[8 * ((size_t)q * nf + f)], &row[q], 8);
+            }
+        dm.fnS = owned ? (const double *)put_vec(std::move(fn)) : (const double *)put(nullptr, 8 * 4 * nf);
+    }
     dm.cf_ptr = (const int32_t *)put(H.cf_ptr.data(), 4 * (n + 1));
     dm.cf_idx = (const int32_t *)put(H.cf_idx.data(), 4 * H.cf_idx.size());
     dm.tr_ptr = (const int32_t *)put(H.tr_ptr.data(), 4 * (n + 1));
@@ -1669,6 +1787,40 @@ gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_param
         return hip_check(hipMemcpyAsync(Q_star, w.Qs, sizeof(double) * 5 * m->n, hipMemcpyDeviceToDevice, st),
                          "Q* copy");
     return GKS_OK;
+}
+
+gks_status gks_implicit_step(gks_mesh *m, double *Q, double *dt_dev, double dt_factor, int kmax, const gks_params *p,
+                             void *work, gks_stream_t stream)
+{
+    gks_status s = check_params(m, p);
+    if (s) return s;
+    if (!Q || !dt_dev || !work) return fail(GKS_EINVAL, "null argument");
+    if (m->d.walls) return fail(GKS_EINVAL, "the implicit step is built for periodic meshes (this one has walls)");
+    if (!(dt_factor > 0.0) || kmax < 0 || kmax > 1000) return fail(GKS_EINVAL, "dt_factor must be > 0 and kmax in 0..1000");
+    hipStream_t st = S(stream);
+    Work w = work_of(m, work);
+    if (!p->dt_given && (s = launch_timestep(m, Q, p, dt_dev, w, st))) return s;
+    if ((s = launch_reconstruct(m, Q, w.coeff, p, st))) return s;
+    if ((s = launch_flux(m, w.coeff, Q, dt_dev, w.ff, p, w, st))) return s;
+    // the coefficients are consumed: their area holds b [5][n], the diagonal [n] and dQ [2][5][n]
+    // (16 doubles per cell, within the 50 coefficients of either precision)
+    const int64_t n = m->n;
+    double *b = (double *)w.coeff, *diag = b + 5 * n, *dq[2] = {diag + n, diag + 6 * n};
+    const unsigned gc = grid_for(n, kBlock);
+    {
+        ProfScope ps(m, GKS_K_IMPLICIT, st);
+        if (m->precision == GKS_FP64)
+            k_implicit_init<double><<<gc, kBlock, 0, st>>>(m->d, (const double *)w.ff, Q, dt_dev, dt_factor, p->gamma, b,
+                                                          diag, dq[0]);
+        else
+            k_implicit_init<float><<<gc, kBlock, 0, st>>>(m->d, (const float *)w.ff, Q, dt_dev, dt_factor, p->gamma, b,
+                                                         diag, dq[0]);
+        for (int k = 0; k < kmax; ++k)
+            k_implicit_sweep<<<gc, kBlock, 0, st>>>(m->d, Q, p->gamma, b, diag, dq[k & 1], dq[(k + 1) & 1]);
+        const int len = (int)(5 * n);
+        k_implicit_update<<<grid_for(len, kBlock), kBlock, 0, st>>>(len, Q, dq[kmax & 1]);
+    }
+    return hip_check(hipGetLastError(), "implicit step launch");
 }
 
 gks_status gks_adjoint_work_bytes(const gks_host_mesh *h, size_t *bytes)

@@ -27,10 +27,10 @@ SYMBOLS = [
     "gks_reset_status", "gks_timestep", "gks_reconstruct", "gks_flux", "gks_residual", "gks_s2o4_step",
     "gks_poll_status", "gks_fallback_count", "gks_gp_flux_batch", "gks_profile", "gks_profile_read", "gks_gp_op_count",
     "gks_gp_flux_host", "gks_gp_flux_vjp_host", "gks_weno_combine_host", "gks_weno_combine_vjp_host",
-    "gks_adjoint_work_bytes", "gks_adjoint_step", "gks_kinetic_energy", "gks_last_error",
+    "gks_adjoint_work_bytes", "gks_adjoint_step", "gks_kinetic_energy", "gks_last_error", "gks_implicit_step",
 ]
 KERNELS = ("timestep", "reconstruct", "flux", "stage1", "stage2", "residual", "flux_adj", "reconstruct_adj",
-           "gather_adj")
+           "gather_adj", "implicit")
 
 
 class GksError(RuntimeError):
@@ -123,6 +123,8 @@ def load():
         lib.gks_adjoint_work_bytes.restype = st
         lib.gks_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, pp, vp, vp, vp]
         lib.gks_adjoint_step.restype = st
+        lib.gks_implicit_step.argtypes = [vp, vp, vp, dbl, i32, pp, vp, vp]
+        lib.gks_implicit_step.restype = st
         lib.gks_kinetic_energy.argtypes = [vp, vp, vp, vp, vp, vp]
         lib.gks_kinetic_energy.restype = st
         lib.gks_last_error.argtypes = []
@@ -311,6 +313,19 @@ class Solver:
         tape = _dp(coeff_tape) if coeff_tape is not None else None
         _check(load().gks_s2o4_step(self.m, self._q(Q), _dp(self.dt), ctypes.byref(self.P), self._work_ptr, qs,
                                     tape, self._s()))
+        self.P.dt_given = 0
+        return Q
+
+    def implicit_step(self, Q, dt_factor=10.0, kmax=3, dt=None):
+        """One implicit Jacobi step in place: the GKS residual over the flux step (the CFL step, or dt),
+        the implicit operator with the pseudo-time step dt_factor times it, kmax sweeps."""
+        if dt is None:
+            self.P.dt_given = 0
+        else:
+            self.dt.fill_(float(dt))
+            self.P.dt_given = 1
+        _check(load().gks_implicit_step(self.m, self._q(Q), _dp(self.dt), float(dt_factor), int(kmax),
+                                        ctypes.byref(self.P), self._work_ptr, self._s()))
         self.P.dt_given = 0
         return Q
 

@@ -228,6 +228,53 @@ def test_smooth_flux_matches_oracle(gks, case):
     assert np.abs(full - o.step(Q0, dts[0])).max() > 1e-10 * np.abs(Q0).max()
 
 
+@pytest.mark.parametrize("case", ["decay-ns-hybrid", "decay-ns-hybrid-smooth", "wave-euler-tet"])
+def test_implicit_jacobi_step_matches_oracle(gks, case):
+    """The implicit steady-solver step (flux-split implicit operator, 3 Jacobi sweeps, pseudo-time step
+    10 times the flux step) against the oracle's statement of it, 3 steps with the oracle's flux
+    steps: FP64 to 1e-12; FP32-mixed GKS residual (FP64 implicit operator) to 1e-5."""
+    import torch
+    from oracle import implicit
+
+    print(f"case: implicit Jacobi, {case} x 3 steps", flush=True)
+    if case.startswith("decay"):
+        mesh = inputs.lattice(5, "hybrid")
+        Q0 = inputs.cell_averages(mesh, inputs.perturbed_wave(amp=0.0, U=(0.0, 0.0, 0.0)))
+        kw = dict(viscous=True, mu=0.02, Pr=0.72, smooth=case.endswith("smooth"))
+    else:
+        mesh = inputs.lattice(5, "tet")
+        Q0 = inputs.cell_averages(mesh, inputs.wave())
+        kw = dict()
+    o = oracle.Oracle(mesh, oracle.params(**kw))
+    dts, ref = [], Q0.copy()
+    for _ in range(3):
+        dts.append(o.timestep(ref))
+        ref = implicit.jacobi_step(o, ref, 10.0 * dts[-1], kmax=3, dt_flux=dts[-1])
+    scale = np.abs(ref).max(axis=1)
+    scale[1:4] = scale[1:4].max()
+    host = gks.HostMesh(mesh)
+    for prec, tol in ((gks.FP64, TOL), (gks.FP32_MIXED, 1e-5)):
+        sol = gks.Solver(host, gks.params(precision=prec, **kw))
+        Q = sol.upload(host.to_internal(Q0))
+        for dt in dts:
+            sol.implicit_step(Q, dt_factor=10.0, kmax=3, dt=dt)
+        sol.poll()
+        torch.cuda.synchronize()
+        err = np.abs(host.to_external(Q.cpu().numpy()) - ref).max(axis=1) / scale
+        print(f"precision {prec}: relative Linf per component:", err)
+        assert (err <= tol).all(), err
+
+
+def test_implicit_step_refuses_walls(gks):
+    mesh = inputs.lattice(3, "hex", periodic=False)
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host)
+    Q = sol.upload(host.to_internal(inputs.cell_averages(mesh, inputs.uniform())))
+    with pytest.raises(gks.GksError) as e:
+        sol.implicit_step(Q)
+    assert e.value.code == gks.GKS_EINVAL
+
+
 def test_adjoint_refuses_the_smooth_flux(gks):
     import torch
 
