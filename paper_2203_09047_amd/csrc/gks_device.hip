@@ -592,51 +592,160 @@ __global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict_
     }
 }
 
-// FP64, periodic, no fallback (the benchmark path).  At 1 wave/SIMD nothing hides the latency of a
-// wave's first coefficient loads, so a grid of one block per CU walks contiguous chunks of Gauss
-// points 256 at a time and loads the next chunk's neighbour coefficients while it computes the
-// current chunk (the owners' are mostly the previous chunk's cells, still in cache).
+// FP64, periodic, no fallback (the benchmark path).  At 1 wave/SIMD nothing hides a wave's memory
+// latency, so a grid of one block per CU walks contiguous chunks of Gauss points 256 at a time and
+// keeps every load of a chunk off its critical path:
+// - the next chunk's neighbour coefficients and face geometry (per wave) and the coefficient rows
+//   of the cells that own its faces (per block: faces are sorted by owner, so these are a window
+//   of consecutive cells starting at the owner of the chunk's first face) travel from memory
+//   straight into shared memory (global_load_lds, 16 B per lane and instruction, lane L of a wave
+//   writing bytes [16 L, 16 L + 16) of the instruction's 1 KiB row) while the current chunk
+//   computes; an owner beyond the window (win_cells <= kWinCells cells) is read from memory directly;
+// - the next chunk's owner and neighbour indices are loaded one chunk ahead into registers;
+// - the neighbour's side is computed first, so the owner's coefficients need no register before
+//   the owner's side;
+// - a chunk's results are stored at the start of the next chunk, after its wait for memory.
+constexpr int kPfRows = 25;  // 16-byte rows of one cell's 50 coefficients
+constexpr int kGeoRows = 5;  // rows of the 9 geometry values: q = 2k in bytes [0, 512), 2k + 1 in [512, 1024)
+constexpr int kPfWaveBytes = (kPfRows + kGeoRows) * 1024;  // one wave's buffers
+constexpr int kWinRows = 36;                                // owner window, 4 waves x 9 rows
+constexpr int kWinCells = kWinRows * 1024 / 400;            // 92 whole cells
+constexpr int kFluxLds = (kBlock / 64) * kPfWaveBytes + kWinRows * 1024;
+static_assert(kFluxLds <= 160 * 1024, "one block of the chunked flux fits a CU's shared memory");
+static_assert(kWinCells == 92, "the window size is part of gks_set_flux_window's contract");
+
 template <bool PR_ANY, bool SM>
 __global__ void __launch_bounds__(kBlock) k_flux_chunked(DevMesh m, const double *__restrict__ coeff,
                                                          const double *__restrict__ dt_dev, double *__restrict__ ff,
-                                                         FluxParams<double> fp, int *status, int chunk)
+                                                         FluxParams<double> fp, int *status, int chunk, int win_cells)
 {
+    __shared__ __attribute__((aligned(16))) char pf[kFluxLds];
+    typedef __attribute__((address_space(3))) void *lds_ptr;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int nf4 = 4 * m.nf;
     const int b0 = (int)min((int64_t)blk * chunk, (int64_t)nf4), b1 = min(b0 + chunk, nf4);
     const double dt = dt_dev[0];
+    const int lane = (int)threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // wave-uniform
+    char *cbuf = pf + wv * kPfWaveBytes;
+    char *gbuf = cbuf + kPfRows * 1024;
+    char *win = pf + (kBlock / 64) * kPfWaveBytes;
+    const size_t coeff_last = (size_t)400 * m.n - 16;  // last 16-byte piece of the coefficients
     auto face_of = [&](int t) { return min(t >> 2, m.nf - 1); };  // tail lanes shadow the last face
-    double cr[50];
-    if (b0 < b1) load_cell(coeff + (size_t)50 * m.nbr[face_of(b0 + (int)threadIdx.x)], cr);
+    auto tt_of = [&](int t) { return 4 * face_of(t) + (t & 3); };
+    // the wave's rows of the chunk starting at cbase: the lane's neighbour cell nb, and the geometry
+    // (instruction lane l fetches the values of wave lanes 2 (l & 31) and 2 (l & 31) + 1: t is even,
+    // so both lie in one face, also where the tail shadows the last face)
+    auto prefetch = [&](int cbase, int nb) {
+        const double *src = coeff + (size_t)50 * nb;
+#pragma unroll
+        for (int k = 0; k < kPfRows; ++k) __builtin_amdgcn_global_load_lds(src + 2 * k, (lds_ptr)(cbuf + k * 1024), 16, 0, 0);
+        const int tg = tt_of(cbase + 64 * wv + 2 * (lane & 31));
+#pragma unroll
+        for (int k = 0; k < kGeoRows; ++k) {
+            const int q = min(2 * k + (lane >> 5), 8);
+            __builtin_amdgcn_global_load_lds(m.fgeo + (size_t)q * nf4 + tg, (lds_ptr)(gbuf + k * 1024), 16, 0, 0);
+        }
+    };
+    // the wave's rows (wv, wv + 4, ...) of the owner window starting at cell w0
+    auto prefetch_win = [&](int w0) {
+#pragma unroll
+        for (int k = 0; k < kWinRows / 4; ++k) {
+            const int r = 4 * k + wv;
+            const size_t off = min((size_t)400 * w0 + (size_t)(1024 * r + 16 * lane), coeff_last);
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(coeff) + off, (lds_ptr)(win + r * 1024), 16, 0, 0);
+        }
+    };
+    int own = 0, nb1 = 0, w0 = 0;  // this chunk's owner and window; the next chunk's neighbour
+    if (b0 < b1) {
+        const int t0 = b0 + (int)threadIdx.x;
+        own = m.owner[face_of(t0)];
+        w0 = m.owner[face_of(b0)];
+        prefetch(b0, m.nbr[face_of(t0)]);
+        prefetch_win(w0);
+        nb1 = m.nbr[face_of(t0 + kBlock)];
+    }
+    const int g4 = (int)threadIdx.x & 3;
+    bool pend = false;  // results of the previous chunk not yet stored
+    double sv0 = 0.0, sv1 = 0.0, sv2 = 0.0, *sdst = ff;
+    auto store_pending = [&]() {
+        if (pend) {
+            sdst[g4] = sv0;
+            sdst[g4 + 4] = sv1;
+            if (g4 < 2) sdst[g4 + 8] = sv2;
+        }
+    };
     for (int base = b0; base < b1; base += kBlock) {  // uniform over the block
         const int t = base + (int)threadIdx.x;
         const bool live = t < b1;
-        const int fs = face_of(t);
-        const int tt = 4 * fs + (t & 3);
-        double geo[9];
+        // this wave's rows and indices have landed (vmcnt covers the shared-memory loads) ...
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        // ... and so have every wave's rows of the owner window
+        __syncthreads();
+        double geo[9], cr[50];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) geo[q] = m.fgeo[(size_t)q * nf4 + tt];
-        double cl[50], crn[50];
-        load_cell(coeff + (size_t)50 * m.owner[fs], cl);
-        if (base + kBlock < b1) load_cell(coeff + (size_t)50 * m.nbr[face_of(t + kBlock)], crn);
+        for (int q = 0; q < 9; ++q) geo[q] = *reinterpret_cast<const double *>(gbuf + (q >> 1) * 1024 + (q & 1) * 512 + 8 * lane);
+#pragma unroll
+        for (int k = 0; k < kPfRows; ++k) {
+            const double2 v = *reinterpret_cast<const double2 *>(cbuf + k * 1024 + 16 * lane);
+            cr[2 * k] = v.x;
+            cr[2 * k + 1] = v.y;
+        }
+        // read before the next chunk's rows overwrite them
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        store_pending();
+        // the loads for the next chunk are issued unconditionally (after the last chunk they fetch
+        // the last face's rows again, unused): a conditional load would make the compiler's waits
+        // for this chunk's loads cover them too
+        const int own_n = m.owner[face_of(t + kBlock)];
+        const int w0_n = m.owner[face_of(base + kBlock)];
+        const int nb2 = m.nbr[face_of(t + 2 * kBlock)];
+        prefetch(base + kBlock, nb1);
+        auto load_r = [&](double c[50]) {
+#pragma unroll
+            for (int q = 0; q < 50; ++q) c[q] = cr[q];
+        };
+        auto load_l = [&](double c[50]) {
+            const int idx = own - w0;  // >= 0: owners do not decrease along the faces
+            // (one unconditional shared-memory read and a rare overwrite from memory through a
+            // volatile pointer: plain loads on both paths fold into loads through a generic pointer,
+            // whose waits also cover the next window's rows)
+            const char *src = win + 400 * min(idx, kWinCells - 1);
+#pragma unroll
+            for (int k = 0; k < kPfRows; ++k) {
+                const double2 v = *reinterpret_cast<const double2 *>(src + 16 * k);
+                c[2 * k] = v.x;
+                c[2 * k + 1] = v.y;
+            }
+            if (idx >= win_cells) {
+                const volatile double *g = coeff + (size_t)50 * own;
+#pragma unroll
+                for (int q = 0; q < 50; ++q) c[q] = g[q];
+            }
+            // every wave has read the window before the next chunk's rows overwrite it
+            __syncthreads();
+            prefetch_win(w0_n);
+        };
         double out[10];
-        const bool ok = face_gp_pre<double, PR_ANY, SM>(cl, cr, nullptr, nullptr, geo, dt, fp, out);
+        const bool ok = face_gp_pre<double, PR_ANY, SM>(load_l, load_r, nullptr, nullptr, geo, dt, fp, out);
         if (live && !ok) status[0] = 1;
 #pragma unroll
         for (int j = 0; j < 10; ++j) {
             out[j] += shfl_xor_t(out[j], 1);
             out[j] += shfl_xor_t(out[j], 2);
         }
-        if (live) {
-            const int g4 = t & 3;
-            double *dst = ff + (size_t)10 * (t >> 2);
-#pragma unroll
-            for (int j = 0; j < 10; ++j)
-                if ((j & 3) == g4) dst[j] = out[j];
-        }
-#pragma unroll
-        for (int q = 0; q < 50; ++q) cr[q] = crn[q];
+        sv0 = g4 == 0 ? out[0] : g4 == 1 ? out[1] : g4 == 2 ? out[2] : out[3];
+        sv1 = g4 == 0 ? out[4] : g4 == 1 ? out[5] : g4 == 2 ? out[6] : out[7];
+        sv2 = g4 == 0 ? out[8] : out[9];
+        sdst = ff + (size_t)10 * (t >> 2);
+        pend = live;
+        own = own_n;
+        w0 = w0_n;
+        nb1 = nb2;
     }
+    store_pending();
+    // no shared-memory load may still be in flight when the block's shared memory is released
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
 // ---------------------------------------------------------------------------
@@ -1235,6 +1344,7 @@ struct gks_mesh {
     int64_t n, nf;
     int precision;
     int n_cu = 256;  // compute units of the device the mesh lives on (grid of the chunked flux kernel)
+    int flux_win = kWinCells;  // owner window of the chunked flux kernel (narrowed by tests only)
     // optional per-kernel HIP-event timing (gks_profile)
     bool prof = false;
     std::vector<hipEvent_t> pool;
@@ -1565,6 +1675,14 @@ void gks_destroy_mesh(gks_mesh *m)
     delete m;
 }
 
+gks_status gks_set_flux_window(gks_mesh *m, int cells)
+{
+    if (!m) return fail(GKS_EINVAL, "null mesh");
+    if (cells < 0 || cells > kWinCells) return fail(GKS_EINVAL, "flux window outside [0, 92] cells");
+    m->flux_win = cells;
+    return GKS_OK;
+}
+
 gks_status gks_profile(gks_mesh *m, int enable)
 {
     if (!m) return fail(GKS_EINVAL, "null mesh");
@@ -1669,7 +1787,7 @@ static void launch_flux_t(gks_mesh *m, bool ext, unsigned grid, const T *coeff, 
         const int64_t nf4 = 4 * (int64_t)m->nf;
         const int64_t per = ((nf4 + ncu * kBlock - 1) / (ncu * kBlock)) * kBlock;
         const int nblk = (int)((nf4 + per - 1) / per);
-        k_flux_chunked<PR, SM><<<nblk, kBlock, 0, st>>>(m->d, coeff, dt_dev, ff, fp, status, (int)per);
+        k_flux_chunked<PR, SM><<<nblk, kBlock, 0, st>>>(m->d, coeff, dt_dev, ff, fp, status, (int)per, m->flux_win);
     } else {
         k_flux<T, PR, false, SM><<<grid, kBlock, 0, st>>>(m->d, coeff, Q, dt_dev, ff, fp, status);
     }

@@ -570,11 +570,14 @@ __host__ __device__ __forceinline__ bool fallback_side(const FluxParams<T> &fp, 
     return true;
 }
 
-// The flux of one Gauss point of an interior face from both cells' coefficients already in registers
-// (ql0, qr0: the FP64 cell averages that FP32 coefficients exclude; unused in FP64); the same
-// arithmetic as face_gp without walls or the fallback.
-template <typename T, bool PR, bool SM = false>
-__host__ __device__ __forceinline__ bool face_gp_pre(const T cl[50], const T cr[50], const double *ql0,
+// The flux of one Gauss point of an interior face, each cell's coefficients fetched by a loader
+// (load_l(T[50]), load_r(T[50])) just before that side's state is formed; the neighbour's side
+// is taken first, so a caller can have the owner's coefficients in flight meanwhile (ql0, qr0:
+// the FP64 cell averages that FP32 coefficients exclude; unused in FP64).  The arithmetic of
+// face_gp without walls or the fallback, up to the order in which the two sides' moments are
+// added to the accumulators.
+template <typename T, bool PR, bool SM, typename LoadL, typename LoadR>
+__host__ __device__ __forceinline__ bool face_gp_pre(LoadL load_l, LoadR load_r, const double *ql0,
                                                      const double *qr0, const T geo[9], T dt,
                                                      const FluxParams<T> &fp, T out[10])
 {
@@ -584,14 +587,16 @@ __host__ __device__ __forceinline__ bool face_gp_pre(const T cl[50], const T cr[
     acc_zero(A);
     bool ok;
     {
-        T q[5], dq[3][5];
-        side_state(cl, ql0, geo[0], geo[1], geo[2], n3, q, dq);
-        ok = side_pass<T, PR, SM>(q, dq, T(1), fp, A, 0);
+        T q[5], dq[3][5], cr[50];
+        load_r(cr);
+        side_state(cr, qr0, geo[3], geo[4], geo[5], n3, q, dq);
+        ok = side_pass<T, PR, SM>(q, dq, T(-1), fp, A, 1);
     }
     {
-        T q[5], dq[3][5];
-        side_state(cr, qr0, geo[3], geo[4], geo[5], n3, q, dq);
-        ok = side_pass<T, PR, SM>(q, dq, T(-1), fp, A, 1) && ok;
+        T q[5], dq[3][5], cl[50];
+        load_l(cl);
+        side_state(cl, ql0, geo[0], geo[1], geo[2], n3, q, dq);
+        ok = side_pass<T, PR, SM>(q, dq, T(1), fp, A, 0) && ok;
     }
     T F[10];
     if (ok) {

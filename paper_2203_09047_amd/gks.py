@@ -28,6 +28,7 @@ SYMBOLS = [
     "gks_poll_status", "gks_fallback_count", "gks_gp_flux_batch", "gks_profile", "gks_profile_read", "gks_gp_op_count",
     "gks_gp_flux_host", "gks_gp_flux_vjp_host", "gks_weno_combine_host", "gks_weno_combine_vjp_host",
     "gks_adjoint_work_bytes", "gks_adjoint_step", "gks_kinetic_energy", "gks_last_error", "gks_implicit_step",
+    "gks_set_flux_window",
 ]
 KERNELS = ("timestep", "reconstruct", "flux", "stage1", "stage2", "residual", "flux_adj", "reconstruct_adj",
            "gather_adj", "implicit")
@@ -104,6 +105,8 @@ def load():
         lib.gks_poll_status.restype = st
         lib.gks_gp_flux_batch.argtypes = [i64, vp, vp, vp, vp, vp, vp, pp, vp]
         lib.gks_gp_flux_batch.restype = st
+        lib.gks_set_flux_window.argtypes = [vp, i32]
+        lib.gks_set_flux_window.restype = st
         lib.gks_profile.argtypes = [vp, i32]
         lib.gks_profile.restype = st
         lib.gks_profile_read.argtypes = [vp, vp, vp]
@@ -366,6 +369,11 @@ class Solver:
         finally:
             self.P.dt_given = 0
         return Q
+
+    def set_flux_window(self, cells: int):
+        """Testing aid: narrow the owner window of the FP64 periodic flux kernel to `cells` in [0, 92]
+        (owners beyond it are read from memory directly; results are bitwise the same)."""
+        _check(load().gks_set_flux_window(self.m, int(cells)))
 
     def profile(self, enable=True):
         """Record HIP events around every kernel launch of this solver (host-side events)."""

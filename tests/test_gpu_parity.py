@@ -647,6 +647,45 @@ def test_bitwise_deterministic(gks):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("kind,N", [("hybrid", 14), ("tet", 12)])
+def test_flux_owner_window_paths_agree_bitwise(gks, kind, N):
+    """The FP64 periodic flux kernel reads the owners' coefficients from a window of consecutive cells
+    staged in shared memory, and an owner beyond it from memory; narrowing the window (92 cells by
+    default, never exceeded on these lattices) sends every lane, or all but the first owner's, down
+    the direct path.  The arithmetic is the same, so 3 Taylor-Green Navier-Stokes steps agree
+    bitwise, and with the oracle to 1e-12 (momentum on the largest momentum's scale).  The lattice sizes give each block of the kernel 3 and 2
+    chunks of 256 Gauss points (the last block a ragged one), so the next-chunk loads run too."""
+    import torch
+
+    print(f"case: flux owner window, {kind} N={N}", flush=True)
+    mesh = inputs.lattice(N, kind, box=(2 * np.pi,) * 3)
+    Q0 = inputs.cell_averages(mesh, inputs.tgv())
+    kw = dict(viscous=True, mu=1.0 / 1600.0, Pr=0.72)
+    host = gks.HostMesh(mesh)
+    W = host.to_internal(Q0)
+    outs = {}
+    for cells in (92, 7, 1, 0):
+        sol = gks.Solver(host, gks.params(**kw))
+        sol.set_flux_window(cells)
+        Q = sol.upload(W)
+        sol.run(Q, nsteps=3)
+        sol.poll()
+        torch.cuda.synchronize()
+        outs[cells] = Q.cpu().numpy()
+    for cells in (7, 1, 0):
+        assert np.array_equal(outs[cells], outs[92]), cells
+    ref, _ = oracle.Oracle(mesh, oracle.params(**kw)).run(Q0, nsteps=3)
+    scale = np.abs(ref).max(axis=1)
+    scale[1:4] = scale[1:4].max()  # rho W starts at zero: momentum on the largest momentum's scale
+    err = np.abs(host.to_external(outs[92]) - ref).max(axis=1) / scale
+    print("relative Linf per component:", err)
+    assert (err <= TOL).all(), err
+    for bad in (-1, 93):
+        with pytest.raises(gks.GksError) as e:
+            sol.set_flux_window(bad)
+        assert e.value.code == gks.GKS_EINVAL
+
+
 def test_non_physical_state_is_reported(gks):
     mesh = inputs.lattice(4, "hex")
     host = gks.HostMesh(mesh)
