@@ -183,10 +183,12 @@ __host__ __device__ __forceinline__ void Padv(const Mom<T> &M, const T a[3][5], 
 template <typename T>
 __host__ __device__ __forceinline__ void slope_solve(const T b[5], T U, T V, T W, T lam, T K, T a[5])
 {
-    const T q = U * U + V * V + W * W + (K + T(3)) / (T(2) * lam);
+    // 1 / (2 lambda) is the moments' recursion factor and 1 / (K + 3) a constant of the launch:
+    // both are shared, no division of its own
+    const T q = U * U + V * V + W * W + (K + T(3)) * (T(0.5) / lam);
     const T R2 = b[1] - U * b[0], R3 = b[2] - V * b[0], R4 = b[3] - W * b[0];
     const T R5 = T(2) * b[4] - q * b[0];
-    a[4] = T(4) * lam * lam / (K + T(3)) * (R5 - T(2) * (U * R2 + V * R3 + W * R4));
+    a[4] = T(4) * lam * lam * (T(1) / (K + T(3))) * (R5 - T(2) * (U * R2 + V * R3 + W * R4));
     a[1] = T(2) * lam * R2 - U * a[4];
     a[2] = T(2) * lam * R3 - V * a[4];
     a[3] = T(2) * lam * R4 - W * a[4];
@@ -350,6 +352,7 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
         Pa<0, 0, 0>(G, Ab, WAm);
     }
     T Fd[2][5];
+    const T itau = T(1) / tau;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const T d = s == 0 ? T(0.5) * dt : dt;
@@ -359,8 +362,8 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
             T2 = -tau * d;
             T3 = T(0.5) * d * d - tau * d;
         } else {
-            const T eta = exp_t(-d / tau);
-            const T om = -expm1_t(-d / tau);
+            const T eta = exp_t(-d * itau);
+            const T om = -expm1_t(-d * itau);
             T1 = d - tau * om;
             T2 = T(2) * tau * tau * om - tau * d * (T(1) + eta);
             T3 = T(0.5) * d * d - tau * d + tau * tau * om;
