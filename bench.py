@@ -31,9 +31,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 # FP64 operations the flux kernel executes per Gauss point (Navier-Stokes, Pr != 1): the hardware
 # counters SQ_INSTS_VALU_FMA_F64 (x 2), _MUL_F64 and _ADD_F64 over one launch at N = 64, divided by
-# the launch's 4 F Gauss points (2289 FMA + 903 MUL + 197 ADD per point).  The source-level count
+# the launch's 4 F Gauss points (2250 FMA + 901 MUL + 194 ADD per point).  The source-level count
 # (flux_ops_per_gauss_point) is larger: the compiler folds constant factors and shares products.
-FLUX_FP64_FLOPS_PER_GP = 2 * 2289 + 903 + 197
+FLUX_FP64_FLOPS_PER_GP = 2 * 2250 + 901 + 194
 # committed HBM counter summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated), valid only for the
 # kernel sources it was measured on and for the workload it was measured on (N = 64)
 COUNTERS_JSON = os.path.join(ROOT, "profiles", "hbm_counters_hybrid-N64-tgv.json")
