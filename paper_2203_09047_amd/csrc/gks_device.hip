@@ -1031,13 +1031,24 @@ __global__ void __launch_bounds__(kBlock) k_flux_adj_a(DevMesh m, const double *
 
 // reverse of the flux, part 2 (lane per face Gauss point and side): the reverse of that
 // side's half-space pass and of its state evaluation; the four Gauss points of a side
-// (a quad of lanes) are summed in a fixed order
+// (a quad of lanes) are summed in a fixed order.  The reverse pass reads the accumulator
+// cotangents one at a time deep inside its arithmetic, where a wave alone on its SIMD would
+// wait for each; so the wave's 8 faces x 4 Gauss points of every slot (32 consecutive values
+// per slot) travel from memory into shared memory at the start (global_load_lds, 16 B per lane
+// and instruction: instruction lane l fetches 2 values of slot 4 r + (l >> 4) in row r) and
+// arrive while the side's state and forward pass are computed.
+constexpr int kAdjRows = (kAccB + 3) / 4;  // 1 KiB rows of 4 slots x 32 values
+
 template <bool PR>
 __global__ void __launch_bounds__(kBlock) k_flux_adj_b(DevMesh m, const double *__restrict__ coeff,
                                                        FluxParams<double> fp, const double *__restrict__ abuf,
                                                        double *__restrict__ cbf)
 {
+    __shared__ __attribute__((aligned(16))) double sab[(kBlock / 64) * kAdjRows * 128];
+    typedef __attribute__((address_space(3))) void *lds_ptr;
     const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int f0 = __builtin_amdgcn_readfirstlane(t >> 3) & ~7;  // the wave's first face (wave-uniform)
+    if (f0 >= m.nf) return;                                       // the whole wave is past the last face
     const int f = t >> 3;
     const bool live = f < m.nf;
     const int fs = live ? f : m.nf - 1;
@@ -1045,7 +1056,19 @@ __global__ void __launch_bounds__(kBlock) k_flux_adj_b(DevMesh m, const double *
     const int g = t & 3;
     const int nf4 = 4 * m.nf;
     const size_t tg = (size_t)4 * fs + g;
+    const int lane = (int)threadIdx.x & 63;
+    double *wab = sab + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) * (kAdjRows * 128);
+    // the cell index first: its wait then need not cover the slots
     const int cell = side ? m.nbr[fs] : m.owner[fs];
+    {
+        const int e = min(4 * f0 + 2 * (lane & 15), nf4 - 2);  // past the last face: shadows, unused
+#pragma unroll
+        for (int r = 0; r < kAdjRows; ++r) {
+            const int slot = min(4 * r + (lane >> 4), kAccB - 1);
+            __builtin_amdgcn_global_load_lds(abuf + (size_t)slot * nf4 + e, (lds_ptr)(wab + 128 * r), 16, 0, 0);
+        }
+    }
+    const int col = (int)tg - 4 * f0;  // in [0, 32): the lane's value within a slot's 32
     double geo[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) geo[q] = m.fgeo[(size_t)q * nf4 + tg];
@@ -1061,8 +1084,10 @@ __global__ void __launch_bounds__(kBlock) k_flux_adj_b(DevMesh m, const double *
     for (int mm = 0; mm < 3; ++mm)
 #pragma unroll
         for (int j = 0; j < 5; ++j) dqb[mm][j] = 0.0;
-    side_pass_b<double, PR>(q, dq, side ? -1.0 : 1.0, fp, [&](int slot) { return abuf[(size_t)slot * nf4 + tg]; }, side,
-                            qb, dqb);
+    // the slots have landed (vmcnt covers the shared-memory loads)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    side_pass_b<double, PR>(q, dq, side ? -1.0 : 1.0, fp, [&](int slot) { return wab[32 * slot + col]; }, side, qb,
+                            dqb);
     double cb[50];
 #pragma unroll
     for (int j = 0; j < 50; ++j) cb[j] = 0.0;
