@@ -966,52 +966,83 @@ static size_t adj_layout(int64_t n, int64_t nf, int64_t nnz, AdjWork *w, char *b
 
 // reverse of the flux, part 1 (lane per face Gauss point): both half-space passes forward,
 // then the reverse of the interface equilibrium, its slopes, the collision time, the time
-// integrals and the rotation/weighting, down to the half-space accumulators
+// integrals and the rotation/weighting, down to the half-space accumulators.  Alone on its SIMD a
+// wave would wait for each load, so all cell cotangents are loaded in one group, and the
+// neighbour's coefficients travel from memory into shared memory (global_load_lds, 16 B per lane
+// and instruction, lane L writing bytes [16 L, 16 L + 16) of each 1 KiB row) while the owner's
+// side is computed.
 template <bool PR>
 __global__ void __launch_bounds__(kBlock) k_flux_adj_a(DevMesh m, const double *__restrict__ coeff,
                                                        const double *__restrict__ dt_dev, const double *__restrict__ lp,
                                                        const double *__restrict__ ls, double cL1, double cL2, double cD1,
                                                        double cD2, FluxParams<double> fp, double *__restrict__ abuf)
 {
+    __shared__ __attribute__((aligned(16))) char sco[(kBlock / 64) * kPfRows * 1024];
+    typedef __attribute__((address_space(3))) void *lds_ptr;
     const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int f = t >> 2;
     if (f >= m.nf) return;
+    const double dt = dt_dev[0];
     const int nf4 = 4 * m.nf;
     const int o = m.owner[f], nb = m.nbr[f];
     const int n = m.n;
-    const double dt = dt_dev[0];
-    // face cotangents from L = -(1/V) sum s F0, D = -(1/V) sum s F1 (owner s = +1, neighbour s = -1)
-    const double io = 1.0 / m.vol[o], inb = 1.0 / m.vol[nb];
+    const int lane = (int)threadIdx.x & 63;
+    char *wco = sco + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) * (kPfRows * 1024);
+#pragma unroll
+    for (int k = 0; k < kPfRows; ++k)
+        __builtin_amdgcn_global_load_lds(coeff + (size_t)50 * nb + 2 * k, (lds_ptr)(wco + 1024 * k), 16, 0, 0);
+    // every load that needs only the two cell indices, in one group: cell cotangents (the second
+    // set read from lp again when there is none, unused then), volumes, geometry, the owner's
+    // coefficients
+    const double *ls_or_lp = ls ? ls : lp;
+    double po[5], pn[5], so[5], sn[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        po[c] = lp[(size_t)c * n + o];
+        pn[c] = lp[(size_t)c * n + nb];
+        so[c] = ls_or_lp[(size_t)c * n + o];
+        sn[c] = ls_or_lp[(size_t)c * n + nb];
+    }
+    const double vo = m.vol[o], vnb = m.vol[nb];
+    double geo[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) geo[q] = m.fgeo[(size_t)q * nf4 + t];
+    double cl[50];
+    load_cell(coeff + (size_t)50 * o, cl);
+    const double io = 1.0 / vo, inb = 1.0 / vnb;
     double outb[10];
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-        double Lo = cL1 * lp[(size_t)c * n + o], Ln = cL1 * lp[(size_t)c * n + nb];
-        double Do = cD1 * lp[(size_t)c * n + o], Dn = cD1 * lp[(size_t)c * n + nb];
+        double Lo = cL1 * po[c], Ln = cL1 * pn[c];
+        double Do = cD1 * po[c], Dn = cD1 * pn[c];
         if (ls) {
-            Lo += cL2 * ls[(size_t)c * n + o];
-            Ln += cL2 * ls[(size_t)c * n + nb];
-            Do += cD2 * ls[(size_t)c * n + o];
-            Dn += cD2 * ls[(size_t)c * n + nb];
+            Lo += cL2 * so[c];
+            Ln += cL2 * sn[c];
+            Do += cD2 * so[c];
+            Dn += cD2 * sn[c];
         }
         outb[c] = dt * (-Lo * io + Ln * inb);
         outb[5 + c] = dt * dt * (-Do * io + Dn * inb);
     }
-    double geo[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) geo[q] = m.fgeo[(size_t)q * nf4 + t];
     double n3[3][3];
     const double area = local_frame(geo[6], geo[7], geo[8], n3);
     FluxAcc<double, PR> A;
     acc_zero(A);
     {
-        double q[5], dq[3][5], c[50];
-        load_cell(coeff + (size_t)50 * o, c);
-        side_state(c, nullptr, geo[0], geo[1], geo[2], n3, q, dq);
+        double q[5], dq[3][5];
+        side_state(cl, nullptr, geo[0], geo[1], geo[2], n3, q, dq);
         side_pass<double, PR>(q, dq, 1.0, fp, A, 0);
     }
     {
         double q[5], dq[3][5], c[50];
-        load_cell(coeff + (size_t)50 * nb, c);
+        // the neighbour's rows have landed (vmcnt covers the shared-memory loads)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#pragma unroll
+        for (int k = 0; k < kPfRows; ++k) {
+            const double2 v = *reinterpret_cast<const double2 *>(wco + 1024 * k + 16 * lane);
+            c[2 * k] = v.x;
+            c[2 * k + 1] = v.y;
+        }
         side_state(c, nullptr, geo[3], geo[4], geo[5], n3, q, dq);
         side_pass<double, PR>(q, dq, -1.0, fp, A, 1);
     }
