@@ -1177,6 +1177,14 @@ __global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3
     const int e0 = m.st_ptr[cb0], e1 = m.st_ptr[cb1];
     const int s0 = m.ss_ptr[8 * cb0], s1 = m.ss_ptr[8 * cb1];
     const bool staged = e1 - e0 <= kK1Stage && s1 - s0 <= kK1SubStage;  // uniform over the block
+    // the lane's own ranges, loaded before the staging so that no load after it waits on them
+    const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
+    int pr[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        pr[h][0] = m.ss_ptr[8 * i + l + 4 * h];
+        pr[h][1] = m.ss_ptr[8 * i + l + 4 * h + 1];
+    }
     if (staged) {
         for (int e = e0 + (int)threadIdx.x; e < e1; e += kK1Block) {
             const int x = m.st_cell[e];
@@ -1194,7 +1202,6 @@ __global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3
     const double *pinv = (const double *)m.pinv;
     const double *dsc = (const double *)m.dsc;
     const int nnz = m.nnz;
-    const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
     const double *Qc = Q + (size_t)comp * n;
     const double q0 = Qc[i];
     auto diff = [&](int k) -> double {
@@ -1215,7 +1222,7 @@ __global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         bs[h][0] = bs[h][1] = bs[h][2] = 0.0;
-        const int p0 = m.ss_ptr[8 * i + l + 4 * h], p1 = m.ss_ptr[8 * i + l + 4 * h + 1];
+        const int p0 = pr[h][0], p1 = pr[h][1];
         if (staged) {
             for (int e = p0 - s0; e < p1 - s0; ++e) {
                 const double d = diff(k0 + sl[e]);
