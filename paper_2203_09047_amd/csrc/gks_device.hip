@@ -553,11 +553,12 @@ __device__ __forceinline__ T shfl_xor_t(T v, int mask)
 }
 
 // EXT: walls or the first-order fallback can occur (a separate instantiation keeps the periodic
-// kernel free of both branches)
+// kernel free of both branches).  The FP32 periodic kernels are held to 168 registers, 3 waves/SIMD
+// (without spill; at their natural 173 they run 2 waves/SIMD and measure 6% slower)
 template <typename T, bool PR, bool EXT, bool SM>
-__global__ void __launch_bounds__(kBlock) k_flux(DevMesh m, const T *__restrict__ coeff, const double *__restrict__ Q,
-                                                 const double *__restrict__ dt_dev, T *__restrict__ ff, FluxParams<T> fp,
-                                                 int *status)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !EXT ? 3 : 1)))
+k_flux(DevMesh m, const T *__restrict__ coeff, const double *__restrict__ Q, const double *__restrict__ dt_dev,
+       T *__restrict__ ff, FluxParams<T> fp, int *status)
 {
     const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int f = t >> 2;
