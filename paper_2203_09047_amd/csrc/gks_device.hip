@@ -950,7 +950,8 @@ struct AdjWork {
     double *abuf;   // [47][4F]   accumulator cotangents per Gauss point (slot-major)
     double *cbf;    // [F][2][50] coefficient cotangents per face side
     double *cbc;    // [N][50]    per cell
-    double *dbar;   // [5][nnz]   cotangents of the stencil differences Q_k - Q_0
+    double *dbar;   // [nnz][5]   cotangents of the stencil differences Q_k - Q_0 (entry-major: a
+                    //            cell's 5 gathering lanes read one 40-byte record per entry)
     double *own;    // [5][N]     direct cotangent of each cell's own average
     double *lstar;  // [5][N]     lam*
     double *vjp;    // [5][N]     result of the latest vector-Jacobian product
@@ -1202,7 +1203,6 @@ __global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3
     }
     const double *pinv = (const double *)m.pinv;
     const double *dsc = (const double *)m.dsc;
-    const int nnz = m.nnz;
     const double *Qc = Q + (size_t)comp * n;
     const double q0 = Qc[i];
     auto diff = [&](int k) -> double {
@@ -1286,7 +1286,7 @@ __global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3
                 sz += rb[s][2];
             }
         v += dsc[(size_t)3 * k] * sx + dsc[(size_t)3 * k + 1] * sy + dsc[(size_t)3 * k + 2] * sz;
-        if (valid) dbar[(size_t)comp * nnz + k] = v;
+        if (valid) dbar[(size_t)5 * k + comp] = v;
         sumk += v;
     }
     sumk = quad_sum(sumk);
@@ -1301,8 +1301,7 @@ __global__ void __launch_bounds__(kBlock) k_transpose_gather(DevMesh m, const do
     const int i = t / 5, c = t - 5 * (t / 5);
     if (i >= m.n) return;
     double s = own[(size_t)c * m.n + i];
-    const double *dc = dbar + (size_t)c * m.nnz;
-    for (int p = m.tr_ptr[i]; p < m.tr_ptr[i + 1]; ++p) s += dc[m.tr_idx[p]];
+    for (int p = m.tr_ptr[i]; p < m.tr_ptr[i + 1]; ++p) s += dbar[(size_t)5 * m.tr_idx[p] + c];
     out[(size_t)c * m.n + i] = s;
 }
 
