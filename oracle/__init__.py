@@ -55,13 +55,17 @@ class Params(ctypes.Structure):
         ("fallback", ctypes.c_int),
         ("fallback_floor", ctypes.c_double),
         ("smooth", ctypes.c_int),
+        ("mu_power", ctypes.c_double),
+        ("T_ref", ctypes.c_double),
     ]
 
 
 def params(gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, weno_eps=1e-6, weno_gamma_m=0.0125, weno_p=1.0, tau_eps=0.01,
-           tau_C=1.0, viscous=False, force_linear=False, fallback=False, fallback_floor=0.0, smooth=False) -> Params:
+           tau_C=1.0, viscous=False, force_linear=False, fallback=False, fallback_floor=0.0, smooth=False,
+           mu_power=0.0, T_ref=1.0) -> Params:
+    """mu_power != 0 (viscous): mu (T / T_ref)^mu_power at the interface temperature T = p / rho."""
     return Params(gamma, cfl, mu, Pr, weno_eps, weno_gamma_m, weno_p, tau_eps, tau_C, int(viscous), int(force_linear),
-                  int(fallback), float(fallback_floor), int(smooth))
+                  int(fallback), float(fallback_floor), int(smooth), float(mu_power), float(T_ref))
 
 
 def _p(a):

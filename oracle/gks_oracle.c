@@ -73,6 +73,9 @@ typedef struct {
     double fallback_floor; /* with fallback: also when rho or p is at most this fraction of the
                               cell average's */
     int smooth;       /* 1: the smooth-flow distribution (Eq. flux-2) instead of the full one (Eq. flux-1) */
+    double mu_power;  /* viscous: mu (T / T_ref)^mu_power at the interface temperature T = p0 / rho0 (gas
+                         constant 1), the power law of the paper's hypersonic sphere case; 0: constant mu */
+    double T_ref;
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -1384,7 +1387,9 @@ int orc_gp_flux(const orc_params *P, const double *ql, const double *dql, const 
     }
     /* collision time (Section 4) */
     double jump = fabs((pl - pr) / (pl + pr)) * dt;
-    double tau = P->viscous ? P->mu / p0 + P->tau_C * jump : P->tau_eps * dt + P->tau_C * jump;
+    double mu = P->mu;
+    if (P->viscous && P->mu_power != 0.0) mu *= pow((p0 / r0) / P->T_ref, P->mu_power);
+    double tau = P->viscous ? mu / p0 + P->tau_C * jump : P->tau_eps * dt + P->tau_C * jump;
     /* moment vectors shared by both time integrals; upow = 1 gives flux moments, 0 conserved moments */
     double Mg0[2][5], Mg0a[2][5], Mg0A[2][5], Mh[2][5], Mha[2][5], MhA[2][5];
     {

@@ -840,3 +840,38 @@ def test_paper_hex_accuracy_table_first_row():
     l1, _ = _errors(m, o, Q, 1.0)
     paper = ref["L1"][0] / 8.0
     assert paper / 2.5 < l1 < paper * 2.5, (l1, paper)
+
+
+def test_power_law_viscosity_is_constant_viscosity_at_the_interface_temperature():
+    """mu (T / T_ref)^omega (the viscosity law of the paper's hypersonic sphere case) enters only through
+    the collision time, at the interface temperature T = p0 / rho0: with one state on both sides that is
+    the state's own p / rho, so the flux equals the constant-viscosity flux with mu (T / T_ref)^omega
+    (computed from the input state); with different sides it equals it at the interface temperature of
+    the oracle's g0; omega = 0 and inviscid flow ignore the law bitwise."""
+    rng = np.random.default_rng(23)
+    mu, om, dt = 2e-3, 0.7, 0.02
+    for trial in range(2):
+        ql = prim_to_cons(1.0 + 0.3 * rng.random(), 0.4 * rng.standard_normal(3), 1.0 + 0.3 * rng.random())
+        qr = prim_to_cons(0.6 + 0.3 * rng.random(), 0.4 * rng.standard_normal(3), 0.7 + 0.3 * rng.random())
+        dql = 0.2 * rng.standard_normal((3, 5))
+        dqr = 0.2 * rng.standard_normal((3, 5))
+        kw = dict(viscous=True, Pr=0.72)
+        # one state on both sides: T = p / rho of the input
+        rho, m, E = ql[0], ql[1:4], ql[4]
+        T = 0.4 * (E - 0.5 * (m @ m) / rho) / rho
+        Fp, _ = oracle.gp_flux(oracle.params(mu=mu, mu_power=om, T_ref=0.5 * T, **kw), ql, dql, ql, dql, dt)
+        Fc, _ = oracle.gp_flux(oracle.params(mu=mu * 2.0 ** om, **kw), ql, dql, ql, dql, dt)
+        np.testing.assert_allclose(Fp, Fc, rtol=1e-12, atol=1e-14 * np.abs(Fc).max())
+        # different sides: the interface temperature of g0
+        Fp, dbg = oracle.gp_flux(oracle.params(mu=mu, mu_power=om, T_ref=0.8, **kw), ql, dql, qr, dqr, dt)
+        T0 = 1.0 / (2.0 * dbg[4])
+        Fc, _ = oracle.gp_flux(oracle.params(mu=mu * (T0 / 0.8) ** om, **kw), ql, dql, qr, dqr, dt)
+        np.testing.assert_allclose(Fp, Fc, rtol=1e-13, atol=1e-15 * np.abs(Fc).max())
+        F0, _ = oracle.gp_flux(oracle.params(mu=mu, **kw), ql, dql, qr, dqr, dt)
+        assert np.abs(Fp - F0).max() > 1e-6 * np.abs(F0).max()  # the law does change the flux here
+        # omega = 0, and inviscid flow, ignore the law
+        Fz, _ = oracle.gp_flux(oracle.params(mu=mu, mu_power=0.0, T_ref=0.3, **kw), ql, dql, qr, dqr, dt)
+        np.testing.assert_array_equal(Fz, F0)
+        Fi, _ = oracle.gp_flux(oracle.params(mu=mu, mu_power=om, T_ref=0.3), ql, dql, qr, dqr, dt)
+        Fi0, _ = oracle.gp_flux(oracle.params(mu=mu), ql, dql, qr, dqr, dt)
+        np.testing.assert_array_equal(Fi, Fi0)
