@@ -91,6 +91,11 @@ typedef struct {
                                  f = g0 (1 - tau (abar . u + Abar) + Abar t) (with the -tau Abar term
                                  that the smooth limit of Eq. flux-1 carries; the printed equation
                                  drops it), for smooth flows; 0: Eq. flux-1 (the default) */
+    double mu_power;          /* viscous only: mu (T0 / T_ref)^mu_power in the collision time, T0 = p0 / rho0
+                                 the interface temperature (gas constant 1): the power law of the
+                                 paper's hypersonic case (Section 5, exponent 0.7 there); 0 (the
+                                 default): constant mu.  The adjoint refuses it (GKS_EINVAL) */
+    double T_ref;             /* the temperature at which the viscosity is mu (> 0 when used; default 1) */
 } gks_params;
 
 typedef struct gks_host_mesh gks_host_mesh;

@@ -1399,6 +1399,8 @@ static FluxParams<T> flux_params(const gks_params *p)
     f.fallback = p->first_order_fallback;
     f.floor = p->fallback_floor;
     f.smooth = p->smooth_flux;
+    f.mu_power = (T)p->mu_power;
+    f.iT_ref = p->mu_power != 0.0 ? (T)(1.0 / p->T_ref) : T(1);
     return f;
 }
 
@@ -1467,6 +1469,8 @@ void gks_default_params(gks_params *p)
     p->weno_p = 1.0;
     p->tau_eps = 0.01;
     p->tau_C = 1.0;
+    p->mu_power = 0.0;
+    p->T_ref = 1.0;
 }
 
 const char *gks_last_error(void) { return g_err.c_str(); }
@@ -1791,6 +1795,8 @@ static gks_status check_params(const gks_mesh *m, const gks_params *p)
     if (p->viscous && !(p->mu >= 0.0)) return fail(GKS_EINVAL, "bad viscosity");
     if (!(p->Pr > 0.0)) return fail(GKS_EINVAL, "bad Prandtl number");
     if (!(p->fallback_floor >= 0.0 && p->fallback_floor < 1.0)) return fail(GKS_EINVAL, "fallback_floor outside [0, 1)");
+    if (!std::isfinite(p->mu_power) || (p->mu_power != 0.0 && !(p->T_ref > 0.0 && std::isfinite(p->T_ref))))
+        return fail(GKS_EINVAL, "bad viscosity power law (mu_power, T_ref)");
     return GKS_OK;
 }
 
@@ -2067,6 +2073,7 @@ gks_status gks_adjoint_step(gks_mesh *m, const double *Qn, const double *Qstar, 
     if (m->d.walls) return fail(GKS_EINVAL, "the adjoint is built for periodic meshes (this one has walls)");
     if (p->first_order_fallback) return fail(GKS_EINVAL, "the adjoint does not differentiate the first-order fallback");
     if (p->smooth_flux) return fail(GKS_EINVAL, "the adjoint differentiates the full flux (Eq. flux-1) only");
+    if (p->viscous && p->mu_power != 0.0) return fail(GKS_EINVAL, "the adjoint covers a constant viscosity only");
     if (!Qn || !Qstar || !dt_dev || !lam_np1 || !lam_n || !adj_work) return fail(GKS_EINVAL, "null argument");
     if (((uintptr_t)adj_work & 255) != 0) return fail(GKS_EINVAL, "adjoint work buffer must be 256-byte aligned");
     AdjWork aw;
@@ -2190,6 +2197,7 @@ gks_status gks_gp_flux_vjp_host(const double *ql, const double *dql, const doubl
     if (!ql || !dql || !qr || !dqr || !p || !outb || !qlb || !dqlb || !qrb || !dqrb)
         return fail(GKS_EINVAL, "null argument");
     if (p->smooth_flux) return fail(GKS_EINVAL, "the reverse covers the full flux (Eq. flux-1) only");
+    if (p->viscous && p->mu_power != 0.0) return fail(GKS_EINVAL, "the reverse covers a constant viscosity only");
     const FluxParams<double> fp = flux_params<double>(p);
     double dl[3][5], dr[3][5], dlb[3][5] = {}, drb[3][5] = {};
     double a[5] = {}, b[5] = {};
@@ -2268,6 +2276,8 @@ gks_status gks_gp_op_count(int viscous, double Pr, int64_t *adds, int64_t *muls,
     fp.Pr = Cnt(p.Pr);
     fp.tau_eps = Cnt(p.tau_eps);
     fp.tau_C = Cnt(p.tau_C);
+    fp.mu_power = Cnt(0.0);  // constant viscosity (the benchmark's)
+    fp.iT_ref = Cnt(1.0);
     fp.viscous = p.viscous;
     fp.fallback = 0;
     fp.floor = 0.0;

@@ -23,6 +23,7 @@ namespace gks {
 template <typename T>
 struct FluxParams {
     T gamma, K, mu, Pr, tau_eps, tau_C;
+    T mu_power, iT_ref;  // viscosity mu (T0 / T_ref)^mu_power at the interface temperature (0: constant)
     int viscous;
     int fallback;  // first-order fallback of non-physical side states
     int smooth;    // the smooth-flow distribution (Eq. flux-2) instead of Eq. flux-1
@@ -61,6 +62,12 @@ template <>
 __host__ __device__ __forceinline__ double exp_t<double>(double x) { return exp(x); }
 template <>
 __host__ __device__ __forceinline__ float exp_t<float>(float x) { return expf(x); }
+template <typename T>
+__host__ __device__ __forceinline__ T pow_t(T x, T y);
+template <>
+__host__ __device__ __forceinline__ double pow_t<double>(double x, double y) { return pow(x, y); }
+template <>
+__host__ __device__ __forceinline__ float pow_t<float>(float x, float y) { return powf(x, y); }
 template <typename T>
 __host__ __device__ __forceinline__ T expm1_t(T x);
 template <>
@@ -340,7 +347,9 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
     // collision time
     const T dp = (A.p[0] - A.p[1]) / (A.p[0] + A.p[1]);
     const T jump = (dp < T(0) ? -dp : dp) * dt;
-    const T tau = fp.viscous ? fp.mu / p0 + fp.tau_C * jump : fp.tau_eps * dt + fp.tau_C * jump;
+    // viscosity at the interface temperature T0 = p0 / rho0 = 1 / (2 lambda0) (power law when asked)
+    const T mu = fp.viscous && fp.mu_power != T(0) ? fp.mu * pow_t(T(0.5) / lam0 * fp.iT_ref, fp.mu_power) : fp.mu;
+    const T tau = fp.viscous ? mu / p0 + fp.tau_C * jump : fp.tau_eps * dt + fp.tau_C * jump;
     T M0[5], Ma[5], MA[5];
     P<1, 0, 0>(G, M0);
     Padv<1>(G, ab, Ma);

@@ -44,6 +44,8 @@ __host__ __device__ inline Cnt exp_t<Cnt>(Cnt x) { ++op_counts().transc; return 
 template <>
 __host__ __device__ inline Cnt expm1_t<Cnt>(Cnt x) { ++op_counts().transc; return Cnt(std::expm1(x.v)); }
 template <>
+__host__ __device__ inline Cnt pow_t<Cnt>(Cnt x, Cnt y) { ++op_counts().transc; return Cnt(std::pow(x.v, y.v)); }
+template <>
 __host__ __device__ inline Cnt sqrt_t<Cnt>(Cnt x) { ++op_counts().transc; return Cnt(std::sqrt(x.v)); }
 
 }  // namespace gks

@@ -47,6 +47,7 @@ class Params(ctypes.Structure):
         ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double), ("viscous", ctypes.c_int),
         ("precision", ctypes.c_int), ("force_linear", ctypes.c_int), ("dt_given", ctypes.c_int),
         ("first_order_fallback", ctypes.c_int), ("fallback_floor", ctypes.c_double), ("smooth_flux", ctypes.c_int),
+        ("mu_power", ctypes.c_double), ("T_ref", ctypes.c_double),
     ]
 
 
@@ -151,7 +152,8 @@ def _dp(t):
 
 def params(precision=FP64, gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, viscous=False, weno_eps=1e-6, weno_gamma_m=0.0125,
            weno_p=1.0, tau_eps=0.01, tau_C=1.0, force_linear=False, dt_given=False, fallback=False,
-           fallback_floor=0.0, smooth=False) -> Params:
+           fallback_floor=0.0, smooth=False, mu_power=0.0, T_ref=1.0) -> Params:
+    """mu_power != 0 (viscous): viscosity mu (T / T_ref)^mu_power at the interface temperature T = p / rho."""
     p = Params()
     load().gks_default_params(ctypes.byref(p))
     p.gamma, p.cfl, p.mu, p.Pr = gamma, cfl, mu, Pr
@@ -161,6 +163,7 @@ def params(precision=FP64, gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, viscous=False, we
     p.first_order_fallback = int(fallback)
     p.fallback_floor = float(fallback_floor)
     p.smooth_flux = int(smooth)
+    p.mu_power, p.T_ref = float(mu_power), float(T_ref)
     return p
 
 

@@ -228,6 +228,65 @@ def test_smooth_flux_matches_oracle(gks, case):
     assert np.abs(full - o.step(Q0, dts[0])).max() > 1e-10 * np.abs(Q0).max()
 
 
+@pytest.mark.parametrize("case", ["tgv-hybrid-12", "tgv-hybrid-6-smooth", "tgv-walls-hybrid-6"])
+def test_power_law_viscosity_matches_oracle(gks, case):
+    """The viscosity law mu (T / T_ref)^0.7 at the interface temperature through the whole step:
+    Taylor-Green Navier-Stokes on the hybrid lattice at N = 12 (the FP64 periodic kernel over several
+    chunks per block), with the smooth-flow flux at N = 6, and in a walled box (the walls kernel);
+    T_ref 0.8 times the initial mean temperature, 3 steps with the oracle's step sizes, FP64 to
+    1e-12 (momentum on the largest momentum's scale), FP32-mixed on the first case to 1e-5."""
+    import torch
+
+    print(f"case: power-law viscosity, {case} x 3 steps", flush=True)
+    N = 12 if case == "tgv-hybrid-12" else 6
+    mesh = inputs.lattice(N, "hybrid", box=(2 * np.pi,) * 3, periodic=case != "tgv-walls-hybrid-6")
+    Q0 = inputs.cell_averages(mesh, inputs.tgv())
+    T = (0.4 * (Q0[4] - 0.5 * (Q0[1:4] ** 2).sum(axis=0) / Q0[0]) / Q0[0]).mean()
+    kw = dict(viscous=True, mu=1.0 / 1600.0, Pr=0.72, mu_power=0.7, T_ref=0.8 * T,
+              smooth=case == "tgv-hybrid-6-smooth")
+    host = gks.HostMesh(mesh)
+    o = oracle.Oracle(mesh, oracle.params(**kw))
+    dts, ref = [], Q0.copy()
+    for _ in range(3):
+        dts.append(o.timestep(ref))
+        ref = o.step(ref, dts[-1])
+    scale = np.abs(ref).max(axis=1)
+    scale[1:4] = scale[1:4].max()
+    for prec, tol in ((gks.FP64, TOL), (gks.FP32_MIXED, 1e-5)):
+        if prec == gks.FP32_MIXED and case != "tgv-hybrid-12":
+            continue
+        sol = gks.Solver(host, gks.params(precision=prec, **kw))
+        Q = sol.upload(host.to_internal(Q0))
+        for dt in dts:
+            sol.step(Q, dt)
+        sol.poll()
+        torch.cuda.synchronize()
+        err = np.abs(host.to_external(Q.cpu().numpy()) - ref).max(axis=1) / scale
+        print(f"precision {prec}: relative Linf per component:", err)
+        assert (err <= tol).all(), err
+    # the law changes the result on these data
+    const = oracle.Oracle(mesh, oracle.params(**dict(kw, mu_power=0.0))).step(Q0, dts[0])
+    assert np.abs(const - o.step(Q0, dts[0])).max() > 1e-12 * np.abs(Q0).max()
+
+
+def test_power_law_viscosity_refused_by_the_adjoint_and_checked(gks):
+    import torch
+
+    mesh = inputs.lattice(3, "hex")
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host, gks.params(viscous=True, mu=1e-3, mu_power=0.7, T_ref=1.0))
+    Q = sol.upload(host.to_internal(inputs.cell_averages(mesh, inputs.uniform())))
+    dtt = torch.tensor([1e-3], dtype=torch.float64, device=Q.device)
+    with pytest.raises(gks.GksError) as e:
+        sol.adjoint_step(Q, Q.clone(), dtt, torch.zeros_like(Q))
+    assert e.value.code == gks.GKS_EINVAL
+    for bad in (dict(T_ref=0.0), dict(T_ref=-1.0), dict(mu_power=float("nan"))):
+        with pytest.raises(gks.GksError) as e:
+            sol.P = gks.params(viscous=True, mu=1e-3, **dict(dict(mu_power=0.7, T_ref=1.0), **bad))
+            sol.step(Q, 1e-3)
+        assert e.value.code == gks.GKS_EINVAL, bad
+
+
 @pytest.mark.parametrize("case", ["decay-ns-hybrid", "decay-ns-hybrid-smooth", "wave-euler-tet"])
 def test_implicit_jacobi_step_matches_oracle(gks, case):
     """The implicit steady-solver step (flux-split implicit operator, 3 Jacobi sweeps, pseudo-time step

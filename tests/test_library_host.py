@@ -88,14 +88,17 @@ def _p(a):
 
 
 @pytest.mark.parametrize("smooth", [False, True])
-@pytest.mark.parametrize("viscous", [False, True])
+@pytest.mark.parametrize("viscous", [False, True, "power-law"])
 def test_host_gauss_point_flux_matches_oracle(smooth, viscous):
     """The library's templated Gauss-point flux, executed on the host in FP64, against the oracle's
-    independent one, for Eq. flux-1 and for the smooth-flow Eq. flux-2."""
+    independent one, for Eq. flux-1 and for the smooth-flow Eq. flux-2; viscous with a constant
+    viscosity and with the power law mu (T / T_ref)^0.7."""
     lib = gks.load()
-    kw = dict(viscous=viscous, mu=2e-3, Pr=0.72 if viscous else 1.0, smooth=smooth)
+    law = dict(mu_power=0.7, T_ref=0.6) if viscous == "power-law" else {}
+    viscous = bool(viscous)
+    kw = dict(viscous=viscous, mu=2e-3, Pr=0.72 if viscous else 1.0, smooth=smooth, **law)
     prm, oprm = gks.params(**kw), oracle.params(**kw)
-    rng = np.random.default_rng(5 + 2 * smooth + viscous)
+    rng = np.random.default_rng(5 + 2 * smooth + viscous + 7 * bool(law))
 
     def cons(rho, U, p):
         U = np.asarray(U, float)
