@@ -115,14 +115,15 @@ def algorithmic_bytes(host, es):
     return dict(reconstruct=recon, flux=flux, stage1=stage1, stage2=stage2, timestep=timestep)
 
 
-def run_gpu(args, mesh, Q0, precision, smooth=False):
+def run_gpu(args, mesh, Q0, precision, smooth=False, law=None):
     import torch
 
     from paper_2203_09047_amd import gks
 
     host = gks.HostMesh(mesh) if not hasattr(run_gpu, "host") else run_gpu.host
     run_gpu.host = host
-    prm = gks.params(precision=precision, viscous=True, mu=1.0 / 1600.0, Pr=0.72, cfl=0.5, smooth=smooth)
+    prm = gks.params(precision=precision, viscous=True, mu=1.0 / 1600.0, Pr=0.72, cfl=0.5, smooth=smooth,
+                     **(law or {}))
     sol = gks.Solver(host, prm)
     Q = sol.upload(host.to_internal(Q0))
     for _ in range(args.warmup):
@@ -231,6 +232,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-smooth", action="store_true", help="skip the smooth-flow flux (Eq. flux-2) comparison")
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit Jacobi step timing")
+    ap.add_argument("--no-power-law", action="store_true", help="skip the power-law viscosity timing")
     ap.add_argument("--adj-steps", type=int, default=20, help="steps of the adjoint/forward ratio (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -352,6 +354,20 @@ def main():
             rel_linf_difference_vs_full_flux_per_component=(np.abs(qsm - q64).max(axis=1)
                                                             / np.abs(q64).max(axis=1)).tolist(),
             after_steps=args.warmup + args.steps, kernels=ksm)
+    if not args.no_power_law:
+        # the same workload with the viscosity law mu (T / T_ref)^0.7 (T_ref the initial mean temperature)
+        T = float((0.4 * (Q0[4] - 0.5 * (Q0[1:4] ** 2).sum(axis=0) / Q0[0]) / Q0[0]).mean())
+        _, solpl, mspl, profpl = run_gpu(args, mesh, Q0, gks.FP64, law=dict(mu_power=0.7, T_ref=T))
+        log(f"fp64 power-law viscosity: {mspl:.2f} ms {profpl}")
+        qpl = run_gpu.last_q
+        del solpl
+        kpl = {k: dict(avg_ms=v[0] / max(v[1], 1), launches=v[1]) for k, v in profpl.items() if v[1]}
+        res["power_law_viscosity_fp64"] = dict(
+            value=n * args.steps / (mspl * 1e-3), ms_per_step=mspl / args.steps, mu_power=0.7, T_ref=T,
+            flux_kernel_slowdown=kpl["flux"]["avg_ms"] / kern["flux"]["avg_ms"],
+            rel_linf_difference_vs_constant_mu_per_component=(np.abs(qpl - q64).max(axis=1)
+                                                              / np.abs(q64).max(axis=1)).tolist(),
+            after_steps=args.warmup + args.steps, kernels=kpl)
     if not args.no_implicit:
         # the paper's steady-solver path: one implicit step = reconstruction + flux over the CFL step,
         # the flux-split implicit operator with a pseudo-time step 10 times that, 3 Jacobi sweeps
