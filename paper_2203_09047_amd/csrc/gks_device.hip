@@ -1885,8 +1885,9 @@ static gks_status launch_flux(gks_mesh *m, const void *coeff, const double *Q, c
     const unsigned grid = grid_for(4 * m->nf, kBlock);
     ProfScope ps(m, GKS_K_FLUX, st);
     const bool pr = p->viscous && p->Pr != 1.0;
-    // wall faces (neighbour < 0) and the fallback exist only in the EXT instantiation
-    const bool ext = m->d.walls || p->first_order_fallback;
+    // wall faces (neighbour < 0), the fallback and the viscosity power law exist only in the EXT
+    // instantiation
+    const bool ext = m->d.walls || p->first_order_fallback || (p->viscous && p->mu_power != 0.0);
     const bool sm = p->smooth_flux != 0;
     if (m->precision == GKS_FP64) {
         auto fp = flux_params<double>(p);

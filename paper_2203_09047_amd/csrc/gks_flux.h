@@ -319,7 +319,9 @@ __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5
  */
 // SM: the time integrals of Eq. flux-2, f = g0 (1 - tau (abar . u + Abar) + Abar t) (with the -tau Abar
 // term that the smooth limit of Eq. flux-1 carries), instead of those of Eq. flux-1.
-template <typename T, bool PR, bool SM = false>
+// PL: the viscosity law fp.mu_power can be active (a separate instantiation keeps the fast periodic
+// kernels free of its branch and of pow's registers).
+template <typename T, bool PR, bool SM = false, bool PL = true>
 __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T dt, const FluxParams<T> &fp, T out[10])
 {
     const T K = fp.K;
@@ -348,7 +350,9 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
     const T dp = (A.p[0] - A.p[1]) / (A.p[0] + A.p[1]);
     const T jump = (dp < T(0) ? -dp : dp) * dt;
     // viscosity at the interface temperature T0 = p0 / rho0 = 1 / (2 lambda0) (power law when asked)
-    const T mu = fp.viscous && fp.mu_power != T(0) ? fp.mu * pow_t(T(0.5) / lam0 * fp.iT_ref, fp.mu_power) : fp.mu;
+    T mu = fp.mu;
+    if constexpr (PL)
+        if (fp.viscous && fp.mu_power != T(0)) mu *= pow_t(T(0.5) / lam0 * fp.iT_ref, fp.mu_power);
     const T tau = fp.viscous ? mu / p0 + fp.tau_C * jump : fp.tau_eps * dt + fp.tau_C * jump;
     T M0[5], Ma[5], MA[5];
     P<1, 0, 0>(G, M0);
@@ -612,7 +616,7 @@ __host__ __device__ __forceinline__ bool face_gp_pre(LoadL load_l, LoadR load_r,
     }
     T F[10];
     if (ok) {
-        ok = finish_flux<T, PR, SM>(A, dt, fp, F);
+        ok = finish_flux<T, PR, SM, false>(A, dt, fp, F);
     } else {
 #pragma unroll
         for (int j = 0; j < 10; ++j) F[j] = T(0);
@@ -628,9 +632,9 @@ __host__ __device__ __forceinline__ bool face_gp_pre(LoadL load_l, LoadR load_r,
     return ok;
 }
 
-// EXT: walls and the first-order fallback can occur; without it cr_g is never null and fp.fallback is
-// ignored.  With it, cr_g == nullptr means the face is a reflective wall and the right state is the
-// mirror of the left one.  ql0, qr0: the two cells' FP64 averages (read for FP32 coefficients and for
+// EXT: walls, the first-order fallback and the viscosity power law can occur; without it cr_g is never
+// null and fp.fallback and fp.mu_power are ignored.  With it, cr_g == nullptr means the face is a
+// reflective wall and the right state is the mirror of the left one.  ql0, qr0: the two cells' FP64 averages (read for FP32 coefficients and for
 // the fallback); nfb counts the sides that fell back.
 template <typename T, bool PR, bool EXT, bool SM = false>
 __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, const T *__restrict__ cr_g, const double *ql0,
@@ -666,7 +670,7 @@ __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, con
     }
     T F[10];
     if (ok) {
-        ok = finish_flux<T, PR, SM>(A, dt, fp, F);
+        ok = finish_flux<T, PR, SM, EXT>(A, dt, fp, F);
     } else {
 #pragma unroll
         for (int j = 0; j < 10; ++j) F[j] = T(0);
