@@ -230,6 +230,26 @@ gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_param
                          void *coeff_tape, gks_stream_t stream);
 
 /*
+ * Allocation-free variant of gks_s2o4_step, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels and results, with the work buffer
+ * replaced by a static device array of the library (64 MiB, held by every
+ * device the library runs on until the process ends).  Meshes whose work
+ * buffer (gks_mesh_sizes) exceeds 64 MiB are refused with GKS_EINVAL (about
+ * 100 k hybrid cells in FP64, 200 k in FP32_MIXED).  The call allocates
+ * nothing and only enqueues kernels and copies on the stream.
+ *   status_dev: caller-owned device int32[2] that takes the role of the work
+ *     buffer's status word: word 0 becomes nonzero when a non-physical state
+ *     is met, word 1 counts first-order fallbacks.  Sticky: the call never
+ *     clears it (the caller zeroes it before the first call).
+ * Other arguments as gks_s2o4_step.  Every call on one device shares that
+ * device's array, so calls that overlap in time on one device (different
+ * streams, threads or meshes) race and must be serialised by the caller.
+ */
+gks_status gks_s2o4_step_noalloc(gks_mesh *m, double *Q, double *dt_dev, const gks_params *p, int32_t *status_dev,
+                                 double *Q_star, void *coeff_tape, gks_stream_t stream);
+
+/*
  * Discrete adjoint of one S2O4 step (FP64 meshes only), the dt of the step
  * being a constant.  With the step written as
  *   Q* = Q + dt/2 L(Q) + dt^2/8 D(Q),  Q' = Q + dt L(Q) + dt^2/6 (D(Q) + 2 D(Q*)),

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -119,6 +120,37 @@ static size_t work_layout(int64_t n, int64_t nf, int precision, Work *w, char *b
         w->ff = ff;
     }
     return off;
+}
+
+// Static scratch of the allocation-free step (gks_s2o4_step_noalloc): the same layout as a
+// caller's work buffer, held by every device the library runs on until the process ends.  Host
+// code never uses the array's name as an address: gks_init_mesh resolves each device's copy with
+// hipGetSymbolAddress, with that device current, and the entry point passes that pointer.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// resolve (once) the scratch address of the current device
+static gks_status scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(GKS_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return GKS_OK;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(GKS_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+    return GKS_OK;
+}
+
+static void *scratch_of(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
 }
 
 // ---------------------------------------------------------------------------
@@ -1416,6 +1448,7 @@ struct gks_mesh {
     int64_t n, nf;
     int precision;
     int n_cu = 256;  // compute units of the device the mesh lives on (grid of the chunked flux kernel)
+    int dev = 0;     // the device the mesh lives on
     int flux_win = kWinCells;  // owner window of the chunked flux kernel (narrowed by tests only)
     // optional per-kernel HIP-event timing (gks_profile)
     bool prof = false;
@@ -1735,8 +1768,12 @@ gks_status gks_init_mesh(const gks_host_mesh *h, int precision, void *mesh_arena
     m->nf = h->h.nf;
     m->precision = precision;
     int dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+    if ((s = hip_check(hipGetDevice(&dev), "current device")) || (s = scratch_setup(dev))) {
+        delete m;
+        return s;
+    }
+    m->dev = dev;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
         m->n_cu = ncu;
     *out = m;
     return GKS_OK;
@@ -1942,14 +1979,11 @@ gks_status gks_residual(gks_mesh *m, const void *face_flux, double *L, double *d
     return hip_check(hipGetLastError(), "residual launch");
 }
 
-gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_params *p, void *work, double *Q_star,
-                         void *coeff_tape, gks_stream_t stream)
+// one S2O4 step on the buffers of w (a caller's work buffer or the static scratch)
+static gks_status run_s2o4(gks_mesh *m, double *Q, double *dt_dev, const gks_params *p, Work &w, double *Q_star,
+                           void *coeff_tape, hipStream_t st)
 {
-    gks_status s = check_params(m, p);
-    if (s) return s;
-    if (!Q || !dt_dev || !work) return fail(GKS_EINVAL, "null argument");
-    hipStream_t st = S(stream);
-    Work w = work_of(m, work);
+    gks_status s;
     if (!p->dt_given && (s = launch_timestep(m, Q, p, dt_dev, w, st))) return s;
     const unsigned gc = grid_for(m->n, kBlock);
     // the stages' coefficients: the work buffer, or the caller's tape
@@ -1982,6 +2016,36 @@ gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_param
         return hip_check(hipMemcpyAsync(Q_star, w.Qs, sizeof(double) * 5 * m->n, hipMemcpyDeviceToDevice, st),
                          "Q* copy");
     return GKS_OK;
+}
+
+gks_status gks_s2o4_step(gks_mesh *m, double *Q, double *dt_dev, const gks_params *p, void *work, double *Q_star,
+                         void *coeff_tape, gks_stream_t stream)
+{
+    gks_status s = check_params(m, p);
+    if (s) return s;
+    if (!Q || !dt_dev || !work) return fail(GKS_EINVAL, "null argument");
+    Work w = work_of(m, work);
+    return run_s2o4(m, Q, dt_dev, p, w, Q_star, coeff_tape, S(stream));
+}
+
+gks_status gks_s2o4_step_noalloc(gks_mesh *m, double *Q, double *dt_dev, const gks_params *p, int32_t *status_dev,
+                                 double *Q_star, void *coeff_tape, gks_stream_t stream)
+{
+    gks_status s = check_params(m, p);
+    if (s) return s;
+    if (!Q || !dt_dev || !status_dev) return fail(GKS_EINVAL, "null argument");
+    const size_t need = work_layout(m->n, m->nf, m->precision, nullptr, nullptr);
+    if (need > kScratchBytes)
+        return fail(GKS_EINVAL, "mesh too large for the allocation-free step: it needs " + std::to_string(need) +
+                                    " bytes of scratch, the library holds " + std::to_string(kScratchBytes));
+    void *base = scratch_of(m->dev);
+    if (!base) return fail(GKS_EDEVICE, "no scratch address for the mesh's device");
+    Work w;
+    work_layout(m->n, m->nf, m->precision, &w, (char *)base);
+    // the sticky status word and the fallback count are the caller's; nothing in the scratch has to
+    // start at zero (every other part is written before it is read)
+    w.status = status_dev;
+    return run_s2o4(m, Q, dt_dev, p, w, Q_star, coeff_tape, S(stream));
 }
 
 gks_status gks_implicit_step(gks_mesh *m, double *Q, double *dt_dev, double dt_factor, int kmax, const gks_params *p,

@@ -28,7 +28,7 @@ SYMBOLS = [
     "gks_poll_status", "gks_fallback_count", "gks_gp_flux_batch", "gks_profile", "gks_profile_read", "gks_gp_op_count",
     "gks_gp_flux_host", "gks_gp_flux_vjp_host", "gks_weno_combine_host", "gks_weno_combine_vjp_host",
     "gks_adjoint_work_bytes", "gks_adjoint_step", "gks_kinetic_energy", "gks_last_error", "gks_implicit_step",
-    "gks_set_flux_window",
+    "gks_set_flux_window", "gks_s2o4_step_noalloc",
 ]
 KERNELS = ("timestep", "reconstruct", "flux", "stage1", "stage2", "residual", "flux_adj", "reconstruct_adj",
            "gather_adj", "implicit")
@@ -100,6 +100,8 @@ def load():
         lib.gks_residual.restype = st
         lib.gks_s2o4_step.argtypes = [vp, vp, vp, pp, vp, vp, vp, vp]
         lib.gks_s2o4_step.restype = st
+        lib.gks_s2o4_step_noalloc.argtypes = [vp, vp, vp, pp, vp, vp, vp, vp]
+        lib.gks_s2o4_step_noalloc.restype = st
         lib.gks_poll_status.argtypes = [vp, vp, vp]
         lib.gks_fallback_count.argtypes = [vp, vp, ctypes.POINTER(i64), vp]
         lib.gks_fallback_count.restype = st
@@ -320,6 +322,25 @@ class Solver:
         _check(load().gks_s2o4_step(self.m, self._q(Q), _dp(self.dt), ctypes.byref(self.P), self._work_ptr, qs,
                                     tape, self._s()))
         self.P.dt_given = 0
+        return Q
+
+    def step_noalloc(self, Q, status, dt=None, Q_star=None, coeff_tape=None):
+        """One S2O4 step in place through the allocation-free entry point: the library's static scratch
+        replaces the work buffer; status is a caller-owned int32[2] device tensor (sticky non-physical
+        flag, fallback count) that the call never clears."""
+        assert status.dtype == self.torch.int32 and status.numel() >= 2 and status.device == self.device
+        if dt is None:
+            self.P.dt_given = 0
+        else:
+            self.dt.fill_(float(dt))
+            self.P.dt_given = 1
+        qs = _dp(Q_star) if Q_star is not None else None
+        tape = _dp(coeff_tape) if coeff_tape is not None else None
+        try:
+            _check(load().gks_s2o4_step_noalloc(self.m, self._q(Q), _dp(self.dt), ctypes.byref(self.P), _dp(status),
+                                                qs, tape, self._s()))
+        finally:
+            self.P.dt_given = 0
         return Q
 
     def implicit_step(self, Q, dt_factor=10.0, kmax=3, dt=None):
