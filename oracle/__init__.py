@@ -10,7 +10,12 @@ does, and the two share no code.  Inputs come from the seeded generators in
 Parity unpinned (readings only, checked by oracle == GPU under a shared
 reading): the ring rule of enlarged sub-stencils when a neighbour is not a
 tetrahedron, the rank fallback of the least-squares fits, the nonlinear-weight
-exponent and epsilon, the time-step formula, the Prandtl-number fix.
+exponent and epsilon, the time-step formula.
+
+``Tangent`` runs the same C source built on complex numbers (complex-step
+differentiation): the directional derivatives of the oracle's own step, exact
+to rounding, with the step sizes frozen and |x| differentiated as sign(x),
+sign(0) = 0.  It is the FP64 CPU reference of the GPU's discrete adjoint.
 """
 from __future__ import annotations
 
@@ -23,17 +28,23 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCE = os.path.join(_HERE, "gks_oracle.c")
 LIB_PATH = os.path.join(_HERE, "libgks_oracle.so")
+LIB_CS_PATH = os.path.join(_HERE, "libgks_oracle_cs.so")
 
 _lib = None
+_lib_cs = None
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (no fast-math, FP64)."""
-    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o",
-           LIB_PATH, SOURCE, "-lm"]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.check_call(cmd)
+    """Compile the oracle with gcc (no fast-math, FP64), and its complex-step build."""
+    for path, extra in ((LIB_PATH, []), (LIB_CS_PATH, ["-DORC_COMPLEX_STEP"])):
+        # built beside and renamed into place: a process that has the old library loaded keeps it
+        tmp = f"{path}.{os.getpid()}.tmp"
+        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+               *extra, "-o", tmp, SOURCE, "-lm"]
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.check_call(cmd)
+        os.replace(tmp, path)
     return LIB_PATH
 
 
@@ -76,10 +87,14 @@ OP_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_
                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 
 
+def _stale(path):
+    return not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SOURCE)
+
+
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SOURCE):
+        if _stale(LIB_PATH):
             build()
         lib = ctypes.CDLL(LIB_PATH)
         vp, i64, dbl, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
@@ -130,6 +145,44 @@ def _load():
         lib.orc_stencil_grown.restype = i32
         _lib = lib
     return _lib
+
+
+def _load_cs():
+    """The complex-step build: the same entry points on complex128 state arrays."""
+    global _lib_cs
+    if _lib_cs is None:
+        if _stale(LIB_CS_PATH):
+            build()
+        lib = ctypes.CDLL(LIB_CS_PATH)
+        vp, i64, dbl, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+        pp = ctypes.POINTER(Params)
+        lib.orc_create.argtypes = [i64, vp, i64, vp, vp, vp, i32, i32]
+        lib.orc_create.restype = vp
+        lib.orc_destroy.argtypes = [vp]
+        lib.orc_last_error.restype = ctypes.c_char_p
+        lib.orc_cell_geometry.argtypes = [vp, vp, vp, vp, vp]
+        lib.orc_gp_flux.argtypes = [pp, vp, vp, vp, vp, dbl, vp, vp]
+        lib.orc_gp_flux.restype = i32
+        lib.orc_residual.argtypes = [vp, pp, vp, dbl, vp, vp]
+        lib.orc_residual.restype = i32
+        lib.orc_s2o4.argtypes = [i64, vp, dbl, OP_CB, vp]
+        lib.orc_s2o4.restype = i32
+        lib.orc_step.argtypes = [vp, pp, vp, dbl]
+        lib.orc_step.restype = i32
+        _lib_cs = lib
+    return _lib_cs
+
+
+#: size of the imaginary seed: every product of two imaginary parts underflows to zero
+CS_H = 1e-200
+
+
+def _seed(x, v):
+    return np.ascontiguousarray(np.asarray(x, np.float64) + 1j * CS_H * np.asarray(v, np.float64), np.complex128)
+
+
+def _split(z):
+    return z.real.copy(), z.imag / CS_H
 
 
 def set_threads(n: int) -> None:
@@ -290,6 +343,115 @@ class Oracle:
         if e:
             raise OracleError(f"run failed (code {e})")
         return Q, dts[:k.value].copy()
+
+
+class Tangent:
+    """Forward-mode derivatives of the oracle's operators (complex-step build of the same source).
+
+    Every method takes a state and a direction and returns the primal result (equal bitwise to the
+    FP64 oracle's) and its directional derivative.  Step sizes are inputs, so they are frozen."""
+
+    def __init__(self, mesh, prm: Params | None = None, min_big: int = 0):
+        lib = _load_cs()
+        self.mesh = mesh
+        self.n = mesh.n_cells
+        self.P = prm if prm is not None else params()
+        self._nodes = np.ascontiguousarray(mesh.nodes, np.float64)
+        self._types = np.ascontiguousarray(mesh.types, np.int8)
+        self._cells = np.ascontiguousarray(mesh.cells, np.int64)
+        box = np.asarray(mesh.box, np.float64)
+        h = lib.orc_create(self._nodes.shape[0], _p(self._nodes), self.n, _p(self._types), _p(self._cells), _p(box),
+                           int(mesh.periodic), int(min_big))
+        if not h:
+            raise OracleError(lib.orc_last_error().decode())
+        self.h = h
+        self._lib = lib
+
+    def __del__(self):
+        lib = getattr(self, "_lib", None)
+        if lib is not None and getattr(self, "h", None):
+            lib.orc_destroy(self.h)
+            self.h = None
+
+    def volumes(self):
+        vol = np.zeros(self.n)
+        xc = np.zeros((self.n, 3))
+        m2 = np.zeros((self.n, 6))
+        area = np.zeros(self.n)
+        self._lib.orc_cell_geometry(self.h, _p(vol), _p(xc), _p(m2), _p(area))
+        return vol
+
+    def residual(self, Q, V, dt):
+        """(L, dL/dt) of Eq. finite at Q and their derivatives along V: (L, D, L', D')."""
+        Z = _seed(Q, V)
+        L = np.zeros((5, self.n), np.complex128)
+        D = np.zeros((5, self.n), np.complex128)
+        e = self._lib.orc_residual(self.h, ctypes.byref(self.P), _p(Z), dt, _p(L), _p(D))
+        if e:
+            raise OracleError(f"non-physical state in flux (code {e})")
+        (Lr, Lt), (Dr, Dt) = _split(L), _split(D)
+        return Lr, Dr, Lt, Dt
+
+    def step(self, Q, V, dt):
+        """One S2O4 step of size dt: (Q^{n+1}, dQ^{n+1}/dQ^n . V)."""
+        Z = _seed(Q, V)
+        e = self._lib.orc_step(self.h, ctypes.byref(self.P), _p(Z), dt)
+        if e:
+            raise OracleError(f"step failed (code {e})")
+        return _split(Z)
+
+    def run(self, Q, V, dts):
+        """The steps of the given sizes: final state and its derivative along V."""
+        Z = _seed(Q, V)
+        for dt in dts:
+            e = self._lib.orc_step(self.h, ctypes.byref(self.P), _p(Z), float(dt))
+            if e:
+                raise OracleError(f"step failed (code {e})")
+        return _split(Z)
+
+
+def kinetic_energy(vol, Q, V=None):
+    """J = sum_i |Omega_i| |rho U_i|^2 / (2 rho_i) and, with a direction V, its derivative along V."""
+    rho, m = Q[0], Q[1:4]
+    J = float((vol * 0.5 * (m * m).sum(axis=0) / rho).sum())
+    if V is None:
+        return J
+    dJ = float((vol * ((m * V[1:4]).sum(axis=0) / rho - 0.5 * (m * m).sum(axis=0) * V[0] / rho ** 2)).sum())
+    return J, dJ
+
+
+def gp_flux_tangent(prm: Params, ql, dql, qr, dqr, dt, vql, vdql, vqr, vdqr):
+    """Single Gauss-point flux (as gp_flux) and its derivative along the input direction."""
+    zs = [_seed(a, b) for a, b in ((ql, vql), (dql, vdql), (qr, vqr), (dqr, vdqr))]
+    out = np.zeros(10, np.complex128)
+    dbg = np.zeros(80, np.complex128)
+    e = _load_cs().orc_gp_flux(ctypes.byref(prm), *(_p(z) for z in zs), dt, _p(out), _p(dbg))
+    if e:
+        raise OracleError(f"gp flux failed (code {e})")
+    return _split(out)
+
+
+def s2o4_tangent(Q, V, dt, op):
+    """The generic two-stage step on complex states with a Python operator op(Z) -> (L, dL) on complex
+    arrays: (Q^{n+1}, its derivative along V)."""
+    Z = _seed(Q, V)
+    n = Z.size
+
+    def cb(ctx, q, L, D):
+        def view(ptr):
+            return np.frombuffer((ctypes.c_double * (2 * n)).from_address(ctypes.addressof(ptr.contents)),
+                                 np.complex128)
+
+        l, d = op(view(q).copy())
+        view(L)[:] = l
+        view(D)[:] = d
+        return 0
+
+    f = OP_CB(cb)
+    e = _load_cs().orc_s2o4(n, _p(Z), dt, f, None)
+    if e:
+        raise OracleError("s2o4 failed")
+    return _split(Z)
 
 
 # ---------------------------------------------------------------------------

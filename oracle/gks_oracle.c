@@ -60,6 +60,60 @@
 #include <omp.h>
 #endif
 
+/*
+ * Scalar type of every quantity that depends on the conserved state.  The default build is plain
+ * FP64.  Built with -DORC_COMPLEX_STEP, the same code runs on complex numbers x + i h v with a tiny
+ * h: the imaginary parts then carry h times the directional derivative along v of every quantity,
+ * exact to rounding since no difference of nearby values is formed (the complex-step derivative of
+ * Squire & Trapp 1998 and Martins, Sturdza & Alonso 2003; with h = 1e-200 every product of two
+ * imaginary parts underflows to zero, so the arithmetic is that of dual numbers).  Each elementary
+ * function below extends its FP64 value by its first-order Taylor term in the imaginary part, |x|
+ * by sign(Re x) x with sign(0) = 0, and every branch and comparison looks at the real part, so the
+ * real parts are those of the FP64 build.  Geometry, stencils, least-squares operators and the
+ * time step stay FP64 in both builds.
+ */
+#ifdef ORC_COMPLEX_STEP
+#include <complex.h>
+typedef double _Complex real;
+static inline double RE(real x) { return creal(x); }
+static inline real r_sqrt(real x)
+{
+    const double s = sqrt(creal(x));
+    return CMPLX(s, cimag(x) / (2.0 * s));
+}
+static inline real r_exp(real x)
+{
+    const double e = exp(creal(x));
+    return CMPLX(e, cimag(x) * e);
+}
+static inline real r_expm1(real x) { return CMPLX(expm1(creal(x)), cimag(x) * exp(creal(x))); }
+/* d erfc(a) / da = -2/sqrt(pi) exp(-a^2) */
+static inline real r_erfc(real x)
+{
+    const double a = creal(x);
+    return CMPLX(erfc(a), -cimag(x) * M_2_SQRTPI * exp(-a * a));
+}
+static inline real r_abs(real x)
+{
+    const double a = creal(x);
+    return a > 0.0 ? x : (a < 0.0 ? -x : CMPLX(0.0, 0.0));
+}
+static inline real r_pow(real x, double e)
+{
+    const double a = creal(x);
+    return CMPLX(pow(a, e), cimag(x) * e * pow(a, e - 1.0));
+}
+#else
+typedef double real;
+static inline double RE(real x) { return x; }
+static inline real r_sqrt(real x) { return sqrt(x); }
+static inline real r_exp(real x) { return exp(x); }
+static inline real r_expm1(real x) { return expm1(x); }
+static inline real r_erfc(real x) { return erfc(x); }
+static inline real r_abs(real x) { return fabs(x); }
+static inline real r_pow(real x, double e) { return pow(x, e); }
+#endif
+
 enum { TET = 0, PYR = 1, PRISM = 2, HEX = 3 };
 
 typedef struct {
@@ -173,9 +227,9 @@ typedef struct {
     ocell *c;
     oface *f;
     /* per-stage WENO data */
-    double *a;  /* [n][5][9] */
-    double *b;  /* [n][5][8][3] */
-    double *w;  /* [n][5][9] normalised weights omega_0..omega_M */
+    real *a;  /* [n][5][9] */
+    real *b;  /* [n][5][8][3] */
+    real *w;  /* [n][5][9] normalised weights omega_0..omega_M */
     int64_t n_fallback; /* Gauss-point sides that fell back to first order since the last query */
     /* option: a big stencil with fewer members than this is grown like an
      * ill-posed fit (0: the paper's neighbours-of-neighbours set as it is) */
@@ -217,48 +271,48 @@ static void house_qr(double *A, int n, int k, double *tau)
 }
 
 /* least-squares solve with the factors of house_qr; b (length n) is overwritten */
-static void house_solve(const double *A, int n, int k, const double *tau, double *b, double *x)
+static void house_solve(const double *A, int n, int k, const double *tau, real *b, real *x)
 {
     for (int j = 0; j < k; j++) {
-        double s = b[j];
+        real s = b[j];
         for (int i = j + 1; i < n; i++) s += A[i + n * j] * b[i];
         s *= tau[j];
         b[j] -= s;
         for (int i = j + 1; i < n; i++) b[i] -= s * A[i + n * j];
     }
     for (int j = k - 1; j >= 0; j--) {
-        double s = b[j];
+        real s = b[j];
         for (int c = j + 1; c < k; c++) s -= A[j + n * c] * x[c];
         x[j] = s / A[j + n * j];
     }
 }
 
 /* Gaussian elimination with partial pivoting, n <= 8, row-major A */
-static int gauss_solve(int n, double *A, double *b, double *x)
+static int gauss_solve(int n, real *A, real *b, real *x)
 {
     for (int c = 0; c < n; c++) {
         int p = c;
         for (int r = c + 1; r < n; r++)
-            if (fabs(A[r * n + c]) > fabs(A[p * n + c])) p = r;
-        if (A[p * n + c] == 0.0) return 1;
+            if (fabs(RE(A[r * n + c])) > fabs(RE(A[p * n + c]))) p = r;
+        if (RE(A[p * n + c]) == 0.0) return 1;
         if (p != c) {
             for (int q = 0; q < n; q++) {
-                double t = A[c * n + q];
+                real t = A[c * n + q];
                 A[c * n + q] = A[p * n + q];
                 A[p * n + q] = t;
             }
-            double t = b[c];
+            real t = b[c];
             b[c] = b[p];
             b[p] = t;
         }
         for (int r = c + 1; r < n; r++) {
-            double f = A[r * n + c] / A[c * n + c];
+            real f = A[r * n + c] / A[c * n + c];
             for (int q = c; q < n; q++) A[r * n + q] -= f * A[c * n + q];
             b[r] -= f * b[c];
         }
     }
     for (int r = n - 1; r >= 0; r--) {
-        double s = b[r];
+        real s = b[r];
         for (int q = r + 1; q < n; q++) s -= A[r * n + q] * x[q];
         x[r] = s / A[r * n + r];
     }
@@ -470,11 +524,11 @@ static int lsq_build(lsq *L, int n, int k, const double *A_rowmajor)
     return 0;
 }
 
-static void lsq_apply(const lsq *L, const double *rhs, double *x)
+static void lsq_apply(const lsq *L, const real *rhs, real *x)
 {
-    double b[MAXST];
+    real b[MAXST];
     for (int i = 0; i < L->n; i++) b[i] = rhs[i];
-    double y[9];
+    real y[9];
     house_solve(L->qr, L->n, L->k, L->tau, b, y);
     for (int j = 0; j < L->k; j++) x[j] = y[j] / L->scale[j];
 }
@@ -871,19 +925,31 @@ orc *orc_create(int64_t n_nodes, const double *nodes, int64_t n_cells, const int
     }
     free(fr);
     o->n_faces = nf;
+    /* each iteration writes only its own cell's stencils and fits: the same result at any thread
+       count; the failure reported is the lowest failing cell's */
+    int64_t bad = -1;
+    int bad_code = 0;
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t c = 0; c < n_cells; c++) {
         int e = build_stencils(o, c);
         if (e) {
-            char m[160];
-            snprintf(m, sizeof m, "stencil construction failed at cell %lld (code %d)", (long long)c, e);
-            seterr(m);
-            orc_destroy(o);
-            return NULL;
+#pragma omp critical
+            if (bad < 0 || c < bad) {
+                bad = c;
+                bad_code = e;
+            }
         }
     }
-    o->a = malloc(sizeof(double) * n_cells * 45);
-    o->b = malloc(sizeof(double) * n_cells * 120);
-    o->w = malloc(sizeof(double) * n_cells * 45);
+    if (bad >= 0) {
+        char m[160];
+        snprintf(m, sizeof m, "stencil construction failed at cell %lld (code %d)", (long long)bad, bad_code);
+        seterr(m);
+        orc_destroy(o);
+        return NULL;
+    }
+    o->a = malloc(sizeof(real) * n_cells * 45);
+    o->b = malloc(sizeof(real) * n_cells * 120);
+    o->w = malloc(sizeof(real) * n_cells * 45);
     return o;
 }
 
@@ -980,28 +1046,28 @@ void orc_stencil_info(const orc *o, int64_t c, int *K, int *M, int *subn)
 /* ------------------------------------------------------------------ */
 /* WENO reconstruction (Section 2, Eq. weno, Eq. indicator)            */
 /* ------------------------------------------------------------------ */
-static double Qat(const orc *o, const double *Q, int comp, int64_t cell) { return Q[comp * o->n_cells + cell]; }
+static real Qat(const orc *o, const real *Q, int comp, int64_t cell) { return Q[comp * o->n_cells + cell]; }
 
 /* cell average of a member: its cell's, momentum components signed by the member's reflections */
-static double member_value(const orc *o, const double *Q, int comp, sref s)
+static real member_value(const orc *o, const real *Q, int comp, sref s)
 {
-    const double v = Qat(o, Q, comp, s.cell);
+    const real v = Qat(o, Q, comp, s.cell);
     return comp >= 1 && comp <= 3 ? s.sg[comp - 1] * v : v;
 }
 
-static void weno_cell(orc *o, const orc_params *P, const double *Q, int64_t i)
+static void weno_cell(orc *o, const orc_params *P, const real *Q, int64_t i)
 {
     ocell *C = &o->c[i];
-    double *a = o->a + 45 * i, *b = o->b + 120 * i, *w = o->w + 45 * i;
+    real *a = o->a + 45 * i, *b = o->b + 120 * i, *w = o->w + 45 * i;
     double S[3][3] = {{C->m2[0], C->m2[1], C->m2[2]}, {C->m2[1], C->m2[3], C->m2[4]}, {C->m2[2], C->m2[4], C->m2[5]}};
     int M = C->M;
     double gm = P->weno_gamma_m, g0 = 1.0 - gm * M;
     for (int comp = 0; comp < 5; comp++) {
-        double q0 = Qat(o, Q, comp, i);
-        double rhs[MAXST];
+        real q0 = Qat(o, Q, comp, i);
+        real rhs[MAXST];
         /* P_0: least squares on the big stencil */
         for (int k = 0; k < C->K; k++) rhs[k] = member_value(o, Q, comp, C->st[k]) - q0;
-        double *ac = a + 9 * comp;
+        real *ac = a + 9 * comp;
         lsq_apply(&C->ls0, rhs, ac);
         /* P_m on the sub-stencils */
         for (int m = 0; m < M; m++) {
@@ -1012,35 +1078,35 @@ static void weno_cell(orc *o, const orc_params *P, const double *Q, int64_t i)
         double vol = C->vol;
         double v13 = cbrt(vol);
         /* first derivatives of P_0 are linear: d/dx = a_x + 2a_xx X + a_xy Y + a_xz Z, ... */
-        double G[3][4] = {
+        real G[3][4] = {
             {ac[0], 2 * ac[3], ac[4], ac[5]},
             {ac[1], ac[4], 2 * ac[6], ac[7]},
             {ac[2], ac[5], ac[7], 2 * ac[8]},
         };
-        double beta0 = 0.0;
+        real beta0 = 0.0;
         for (int d = 0; d < 3; d++) {
-            double lin = 0.0;
+            real lin = 0.0;
             for (int p = 0; p < 3; p++)
                 for (int q = 0; q < 3; q++) lin += G[d][1 + p] * S[p][q] * G[d][1 + q];
-            double integral = vol * (G[d][0] * G[d][0] + lin);
+            real integral = vol * (G[d][0] * G[d][0] + lin);
             beta0 += integral / v13;
         }
-        double sec[6] = {2 * ac[3], 2 * ac[6], 2 * ac[8], ac[4], ac[5], ac[7]};
+        real sec[6] = {2 * ac[3], 2 * ac[6], 2 * ac[8], ac[4], ac[5], ac[7]};
         for (int d = 0; d < 6; d++) beta0 += v13 * vol * sec[d] * sec[d];
-        double beta[8];
-        double tw = 0.0;
+        real beta[8];
+        real tw = 0.0;
         for (int m = 0; m < M; m++) {
-            const double *bm = b + 24 * comp + 3 * m;
+            const real *bm = b + 24 * comp + 3 * m;
             beta[m] = vol * (bm[0] * bm[0] + bm[1] * bm[1] + bm[2] * bm[2]) / v13;
-            tw += fabs(beta0 - beta[m]) / M;
+            tw += r_abs(beta0 - beta[m]) / M;
         }
-        double om[9], sum = 0.0;
+        real om[9], sum = 0.0;
         if (P->force_linear) {
             om[0] = g0;
             for (int m = 0; m < M; m++) om[1 + m] = gm;
         } else {
-            om[0] = g0 * (1.0 + pow(tw / (beta0 + P->weno_eps), P->weno_p));
-            for (int m = 0; m < M; m++) om[1 + m] = gm * (1.0 + pow(tw / (beta[m] + P->weno_eps), P->weno_p));
+            om[0] = g0 * (1.0 + r_pow(tw / (beta0 + P->weno_eps), P->weno_p));
+            for (int m = 0; m < M; m++) om[1 + m] = gm * (1.0 + r_pow(tw / (beta[m] + P->weno_eps), P->weno_p));
         }
         for (int m = 0; m <= M; m++) sum += om[m];
         for (int m = 0; m <= M; m++) w[9 * comp + m] = om[m] / sum;
@@ -1048,11 +1114,11 @@ static void weno_cell(orc *o, const orc_params *P, const double *Q, int64_t i)
 }
 
 /* value and gradient at x (cell's own frame) of P_m (m = 0..M) or of Eq. weno (m < 0) */
-static void weno_eval(const orc *o, const orc_params *P, const double *Q, int64_t i, int which, const double x[3],
-                      double val[5], double grad[5][3])
+static void weno_eval(const orc *o, const orc_params *P, const real *Q, int64_t i, int which, const double x[3],
+                      real val[5], real grad[5][3])
 {
     const ocell *C = &o->c[i];
-    const double *a = o->a + 45 * i, *b = o->b + 120 * i, *w = o->w + 45 * i;
+    const real *a = o->a + 45 * i, *b = o->b + 120 * i, *w = o->w + 45 * i;
     double X[3] = {x[0] - C->xc[0], x[1] - C->xc[1], x[2] - C->xc[2]};
     double S[3][3] = {{C->m2[0], C->m2[1], C->m2[2]}, {C->m2[1], C->m2[3], C->m2[4]}, {C->m2[2], C->m2[4], C->m2[5]}};
     /* basis p_n(x) = (x-x0)^n - mean over Omega_0, and its gradient */
@@ -1081,10 +1147,10 @@ static void weno_eval(const orc *o, const orc_params *P, const double *Q, int64_
     int M = C->M;
     double gm = P->weno_gamma_m, g0 = 1.0 - gm * M;
     for (int comp = 0; comp < 5; comp++) {
-        double q0 = Qat(o, Q, comp, i);
-        const double *ac = a + 9 * comp;
+        real q0 = Qat(o, Q, comp, i);
+        const real *ac = a + 9 * comp;
         /* every candidate polynomial at x */
-        double pv[9], pg[9][3];
+        real pv[9], pg[9][3];
         pv[0] = q0;
         pg[0][0] = pg[0][1] = pg[0][2] = 0.0;
         for (int n = 0; n < 9; n++) {
@@ -1092,7 +1158,7 @@ static void weno_eval(const orc *o, const orc_params *P, const double *Q, int64_
             for (int d = 0; d < 3; d++) pg[0][d] += ac[n] * dp[n][d];
         }
         for (int m = 0; m < M; m++) {
-            const double *bm = b + 24 * comp + 3 * m;
+            const real *bm = b + 24 * comp + 3 * m;
             pv[1 + m] = q0;
             for (int d = 0; d < 3; d++) pg[1 + m][d] = 0.0;
             for (int n = 0; n < 3; n++) {
@@ -1106,8 +1172,8 @@ static void weno_eval(const orc *o, const orc_params *P, const double *Q, int64_
             continue;
         }
         /* Eq. weno */
-        const double *wc = w + 9 * comp;
-        double v = pv[0] / g0, g[3] = {pg[0][0] / g0, pg[0][1] / g0, pg[0][2] / g0};
+        const real *wc = w + 9 * comp;
+        real v = pv[0] / g0, g[3] = {pg[0][0] / g0, pg[0][1] / g0, pg[0][2] / g0};
         for (int m = 0; m < M; m++) {
             v -= gm / g0 * pv[1 + m];
             for (int d = 0; d < 3; d++) g[d] -= gm / g0 * pg[1 + m][d];
@@ -1125,17 +1191,17 @@ static void weno_eval(const orc *o, const orc_params *P, const double *Q, int64_
 
 /* every cell's reconstruction; each iteration writes only its own cell's coefficients, so the
    OpenMP loop gives the same result as the serial one */
-static void weno_all(orc *o, const orc_params *P, const double *Q)
+static void weno_all(orc *o, const orc_params *P, const real *Q)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < o->n_cells; i++) weno_cell(o, P, Q, i);
 }
 
 /* exported: evaluate at point x of cell i (m=-1: Eq. weno; m>=0: P_m) */
-int orc_weno_eval(orc *o, const orc_params *P, const double *Q, int64_t i, int m, const double *x, double *val, double *grad)
+int orc_weno_eval(orc *o, const orc_params *P, const real *Q, int64_t i, int m, const double *x, real *val, real *grad)
 {
     weno_cell(o, P, Q, i);
-    double g[5][3];
+    real g[5][3];
     weno_eval(o, P, Q, i, m, x, val, g);
     for (int c = 0; c < 5; c++)
         for (int d = 0; d < 3; d++) grad[3 * c + d] = g[c][d];
@@ -1143,10 +1209,12 @@ int orc_weno_eval(orc *o, const orc_params *P, const double *Q, int64_t i, int m
 }
 
 /* normalised nonlinear weights of cell i (for inspection) */
-void orc_weno_weights(orc *o, const orc_params *P, const double *Q, int64_t i, double *w)
+void orc_weno_weights(orc *o, const orc_params *P, const real *Q, int64_t i, real *w)
 {
     weno_cell(o, P, Q, i);
-    memcpy(w, o->w + 45 * i, sizeof(double) * 45);
+    /* omega_0..omega_M per component; the slots beyond M are zero */
+    for (int c = 0; c < 5; c++)
+        for (int m = 0; m < 9; m++) w[9 * c + m] = m <= o->c[i].M ? o->w[45 * i + 9 * c + m] : 0.0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -1156,12 +1224,12 @@ void orc_weno_weights(orc *o, const orc_params *P, const double *Q, int64_t i, d
 #define MAXT 48
 typedef struct {
     int n;
-    double c[MAXT];
+    real c[MAXT];
     int e[MAXT][4];
 } vpoly;
 
 static void vp_zero(vpoly *p) { p->n = 0; }
-static void vp_add(vpoly *p, double c, int a, int b, int w, int d)
+static void vp_add(vpoly *p, real c, int a, int b, int w, int d)
 {
     if (c == 0.0) return;
     p->c[p->n] = c;
@@ -1191,7 +1259,7 @@ static void vp_psi(vpoly *p, int j)
 }
 
 /* a . psi for a slope vector a[5] */
-static void vp_slope(vpoly *p, const double a[5])
+static void vp_slope(vpoly *p, const real a[5])
 {
     vp_zero(p);
     vp_add(p, a[0], 0, 0, 0, 0);
@@ -1205,7 +1273,7 @@ static void vp_slope(vpoly *p, const double a[5])
 }
 
 /* (a_1 . psi) u + (a_2 . psi) v + (a_3 . psi) w for three slope vectors */
-static void vp_advect(vpoly *p, const double a[3][5])
+static void vp_advect(vpoly *p, const real a[3][5])
 {
     vp_zero(p);
     for (int m = 0; m < 3; m++) {
@@ -1222,18 +1290,18 @@ static void vp_advect(vpoly *p, const double a[3][5])
 #define MAXO 14
 /* normalised moments of a Maxwellian: <u^n> (full, u>0, u<0), <v^n>, <w^n>, <varsigma^(2d)> */
 typedef struct {
-    double rho, U, V, W, lam;
-    double uf[MAXO], up[MAXO], un[MAXO], v[MAXO], w[MAXO], s[6];
+    real rho, U, V, W, lam;
+    real uf[MAXO], up[MAXO], un[MAXO], v[MAXO], w[MAXO], s[6];
 } maxw;
 
-static void moments_1d_full(double U, double lam, double *m)
+static void moments_1d_full(real U, real lam, real *m)
 {
     m[0] = 1.0;
     m[1] = U;
     for (int n = 0; n + 2 < MAXO; n++) m[n + 2] = U * m[n + 1] + (n + 1) / (2.0 * lam) * m[n];
 }
 
-static void maxw_init(maxw *g, double rho, double U, double V, double W, double lam, double K)
+static void maxw_init(maxw *g, real rho, real U, real V, real W, real lam, double K)
 {
     g->rho = rho;
     g->U = U;
@@ -1244,9 +1312,9 @@ static void maxw_init(maxw *g, double rho, double U, double V, double W, double 
     moments_1d_full(V, lam, g->v);
     moments_1d_full(W, lam, g->w);
     /* half spaces: <u^0> = erfc(-+ sqrt(lam) U)/2, <u^1> = U<u^0> +- exp(-lam U^2)/(2 sqrt(pi lam)) */
-    double e = exp(-lam * U * U) / (2.0 * sqrt(M_PI * lam));
-    g->up[0] = 0.5 * erfc(-sqrt(lam) * U);
-    g->un[0] = 0.5 * erfc(sqrt(lam) * U);
+    real e = r_exp(-lam * U * U) / (2.0 * r_sqrt(M_PI * lam));
+    g->up[0] = 0.5 * r_erfc(-r_sqrt(lam) * U);
+    g->un[0] = 0.5 * r_erfc(r_sqrt(lam) * U);
     g->up[1] = U * g->up[0] + e;
     g->un[1] = U * g->un[0] - e;
     for (int n = 0; n + 2 < MAXO; n++) {
@@ -1259,10 +1327,10 @@ static void maxw_init(maxw *g, double rho, double U, double V, double W, double 
 }
 
 /* half = 0 full space, +1 u > 0, -1 u < 0; moment of u^upow * P * R */
-static double mom2(const maxw *g, int half, int upow, const vpoly *P, const vpoly *R)
+static real mom2(const maxw *g, int half, int upow, const vpoly *P, const vpoly *R)
 {
-    const double *mu = half > 0 ? g->up : (half < 0 ? g->un : g->uf);
-    double s = 0.0;
+    const real *mu = half > 0 ? g->up : (half < 0 ? g->un : g->uf);
+    real s = 0.0;
     for (int i = 0; i < P->n; i++)
         for (int j = 0; j < R->n; j++) {
             int a = P->e[i][0] + R->e[j][0] + upow;
@@ -1275,7 +1343,7 @@ static double mom2(const maxw *g, int half, int upow, const vpoly *P, const vpol
 }
 
 /* <u^upow P psi> (normalised, 5-vector) */
-static void mom_psi(const maxw *g, int half, int upow, const vpoly *P, double out[5])
+static void mom_psi(const maxw *g, int half, int upow, const vpoly *P, real out[5])
 {
     for (int j = 0; j < 5; j++) {
         vpoly pj;
@@ -1285,9 +1353,9 @@ static void mom_psi(const maxw *g, int half, int upow, const vpoly *P, double ou
 }
 
 /* solve <a psi> = b for the slope a: M_jk = <psi_j psi_k> (normalised) */
-static int slope_solve(const maxw *g, const double b[5], double a[5])
+static int slope_solve(const maxw *g, const real b[5], real a[5])
 {
-    double A[25], r[5];
+    real A[25], r[5];
     for (int j = 0; j < 5; j++) {
         vpoly pj;
         vp_psi(&pj, j);
@@ -1301,7 +1369,7 @@ static int slope_solve(const maxw *g, const double b[5], double a[5])
     return gauss_solve(5, A, r, a);
 }
 
-static void cons_to_prim(double gam, const double q[5], double *rho, double U[3], double *lam, double *p)
+static void cons_to_prim(double gam, const real q[5], real *rho, real U[3], real *lam, real *p)
 {
     *rho = q[0];
     for (int d = 0; d < 3; d++) U[d] = q[1 + d] / q[0];
@@ -1318,14 +1386,14 @@ static void cons_to_prim(double gam, const double q[5], double *rho, double U[3]
  * lam0, al[3][5], ar[3][5], abar[3][5], Al[5], Ar[5], Abar[5], tau, F(dt/2)[5],
  * F(dt)[5].
  */
-int orc_gp_flux(const orc_params *P, const double *ql, const double *dql, const double *qr, const double *dqr, double dt,
-                double *Fbar, double *dbg)
+int orc_gp_flux(const orc_params *P, const real *ql, const real *dql, const real *qr, const real *dqr, double dt,
+                real *Fbar, real *dbg)
 {
     double gam = P->gamma, K = (5.0 - 3.0 * gam) / (gam - 1.0);
-    double rl, rr, Ul[3], Ur[3], laml, lamr, pl, pr;
+    real rl, rr, Ul[3], Ur[3], laml, lamr, pl, pr;
     cons_to_prim(gam, ql, &rl, Ul, &laml, &pl);
     cons_to_prim(gam, qr, &rr, Ur, &lamr, &pr);
-    if (!(rl > 0 && rr > 0 && pl > 0 && pr > 0)) return 4;
+    if (!(RE(rl) > 0 && RE(rr) > 0 && RE(pl) > 0 && RE(pr) > 0)) return 4;
     maxw gl, gr, g0;
     maxw_init(&gl, rl, Ul[0], Ul[1], Ul[2], laml, K);
     maxw_init(&gr, rr, Ur[0], Ur[1], Ur[2], lamr, K);
@@ -1333,18 +1401,18 @@ int orc_gp_flux(const orc_params *P, const double *ql, const double *dql, const 
     vp_zero(&one);
     vp_add(&one, 1.0, 0, 0, 0, 0);
     /* interface equilibrium: Q0 = rho_l <psi>_{u>0,l} + rho_r <psi>_{u<0,r} */
-    double hl[5], hr[5], q0[5];
+    real hl[5], hr[5], q0[5];
     mom_psi(&gl, 1, 0, &one, hl);
     mom_psi(&gr, -1, 0, &one, hr);
     for (int j = 0; j < 5; j++) q0[j] = rl * hl[j] + rr * hr[j];
-    double r0, U0[3], lam0, p0;
+    real r0, U0[3], lam0, p0;
     cons_to_prim(gam, q0, &r0, U0, &lam0, &p0);
-    if (!(r0 > 0 && p0 > 0)) return 4;
+    if (!(RE(r0) > 0 && RE(p0) > 0)) return 4;
     maxw_init(&g0, r0, U0[0], U0[1], U0[2], lam0, K);
     /* slopes from the directional derivatives: <a_m> = dQ/dn_m */
-    double al[3][5], ar[3][5];
+    real al[3][5], ar[3][5];
     for (int m = 0; m < 3; m++) {
-        double bl[5], br[5];
+        real bl[5], br[5];
         for (int j = 0; j < 5; j++) {
             bl[j] = dql[5 * m + j] / rl;
             br[j] = dqr[5 * m + j] / rr;
@@ -1352,10 +1420,10 @@ int orc_gp_flux(const orc_params *P, const double *ql, const double *dql, const 
         if (slope_solve(&gl, bl, al[m]) || slope_solve(&gr, br, ar[m])) return 5;
     }
     /* time slopes from compatibility: <a_1 u + a_2 v + a_3 w + A> = 0 */
-    double Al[5], Ar[5];
+    real Al[5], Ar[5];
     {
         vpoly adv;
-        double b[5];
+        real b[5];
         vp_advect(&adv, al);
         mom_psi(&gl, 0, 0, &adv, b);
         for (int j = 0; j < 5; j++) b[j] = -b[j];
@@ -1366,12 +1434,12 @@ int orc_gp_flux(const orc_params *P, const double *ql, const double *dql, const 
         if (slope_solve(&gr, b, Ar)) return 5;
     }
     /* equilibrium slopes: rho0 <abar_m psi> = rho_l <a^l_m psi>_{u>0} + rho_r <a^r_m psi>_{u<0} */
-    double ab[3][5], Ab[5];
+    real ab[3][5], Ab[5];
     for (int m = 0; m < 3; m++) {
         vpoly sl, sr;
         vp_slope(&sl, al[m]);
         vp_slope(&sr, ar[m]);
-        double ml[5], mr[5], b[5];
+        real ml[5], mr[5], b[5];
         mom_psi(&gl, 1, 0, &sl, ml);
         mom_psi(&gr, -1, 0, &sr, mr);
         for (int j = 0; j < 5; j++) b[j] = (rl * ml[j] + rr * mr[j]) / r0;
@@ -1379,19 +1447,19 @@ int orc_gp_flux(const orc_params *P, const double *ql, const double *dql, const 
     }
     {
         vpoly adv;
-        double b[5];
+        real b[5];
         vp_advect(&adv, ab);
         mom_psi(&g0, 0, 0, &adv, b);
         for (int j = 0; j < 5; j++) b[j] = -b[j];
         if (slope_solve(&g0, b, Ab)) return 5;
     }
     /* collision time (Section 4) */
-    double jump = fabs((pl - pr) / (pl + pr)) * dt;
-    double mu = P->mu;
-    if (P->viscous && P->mu_power != 0.0) mu *= pow((p0 / r0) / P->T_ref, P->mu_power);
-    double tau = P->viscous ? mu / p0 + P->tau_C * jump : P->tau_eps * dt + P->tau_C * jump;
+    real jump = r_abs((pl - pr) / (pl + pr)) * dt;
+    real mu = P->mu;
+    if (P->viscous && P->mu_power != 0.0) mu *= r_pow((p0 / r0) / P->T_ref, P->mu_power);
+    real tau = P->viscous ? mu / p0 + P->tau_C * jump : P->tau_eps * dt + P->tau_C * jump;
     /* moment vectors shared by both time integrals; upow = 1 gives flux moments, 0 conserved moments */
-    double Mg0[2][5], Mg0a[2][5], Mg0A[2][5], Mh[2][5], Mha[2][5], MhA[2][5];
+    real Mg0[2][5], Mg0a[2][5], Mg0A[2][5], Mh[2][5], Mha[2][5], MhA[2][5];
     {
         vpoly adv0, A0, advl, advr, Alp, Arp;
         vp_advect(&adv0, ab);
@@ -1401,7 +1469,7 @@ int orc_gp_flux(const orc_params *P, const double *ql, const double *dql, const 
         vp_slope(&Alp, Al);
         vp_slope(&Arp, Ar);
         for (int up = 0; up < 2; up++) {
-            double x[5], y[5];
+            real x[5], y[5];
             mom_psi(&g0, 0, up, &one, Mg0[up]);
             mom_psi(&g0, 0, up, &adv0, Mg0a[up]);
             mom_psi(&g0, 0, up, &A0, Mg0A[up]);
@@ -1416,16 +1484,16 @@ int orc_gp_flux(const orc_params *P, const double *ql, const double *dql, const 
             for (int j = 0; j < 5; j++) MhA[up][j] = rl * x[j] + rr * y[j];
         }
     }
-    double Fd[2][5];
+    real Fd[2][5];
     for (int s = 0; s < 2; s++) {
         double d = s == 0 ? 0.5 * dt : dt;
-        double eta = exp(-d / tau), om = -expm1(-d / tau);
-        double T1 = d - tau * om;
-        double T2 = 2.0 * tau * tau * om - tau * d * (1.0 + eta);
-        double T3 = 0.5 * d * d - tau * d + tau * tau * om;
-        double T4 = tau * om;
-        double T5 = 2.0 * tau * tau * om - tau * d * eta;
-        double W[2][5];
+        real eta = r_exp(-d / tau), om = -r_expm1(-d / tau);
+        real T1 = d - tau * om;
+        real T2 = 2.0 * tau * tau * om - tau * d * (1.0 + eta);
+        real T3 = 0.5 * d * d - tau * d + tau * tau * om;
+        real T4 = tau * om;
+        real T5 = 2.0 * tau * tau * om - tau * d * eta;
+        real W[2][5];
         if (P->smooth) {
             /* Eq. flux-2 with the -tau Abar term that the smooth limit of Eq. flux-1 carries (the
                printed line drops it): f = g0 (1 - tau (abar.u + Abar) + Abar t), integrated over
@@ -1442,9 +1510,9 @@ int orc_gp_flux(const orc_params *P, const double *ql, const double *dql, const 
         for (int j = 0; j < 5; j++) Fd[s][j] = W[1][j];
         if (P->viscous && P->Pr != 1.0) {
             /* heat flux about U0 of the time-integrated distribution */
-            const double *Fm = W[1], *Wm = W[0];
-            double U2 = U0[0] * U0[0] + U0[1] * U0[1] + U0[2] * U0[2];
-            double q2 = 2.0 * Fm[4] - 2.0 * (U0[0] * Fm[1] + U0[1] * Fm[2] + U0[2] * Fm[3]) + U2 * Fm[0] -
+            const real *Fm = W[1], *Wm = W[0];
+            real U2 = U0[0] * U0[0] + U0[1] * U0[1] + U0[2] * U0[2];
+            real q2 = 2.0 * Fm[4] - 2.0 * (U0[0] * Fm[1] + U0[1] * Fm[2] + U0[2] * Fm[3]) + U2 * Fm[0] -
                         U0[0] * 2.0 * Wm[4] + 2.0 * U0[0] * (U0[0] * Wm[1] + U0[1] * Wm[2] + U0[2] * Wm[3]) -
                         U0[0] * U2 * Wm[0];
             Fd[s][4] += (1.0 / P->Pr - 1.0) * 0.5 * q2;
@@ -1455,7 +1523,7 @@ int orc_gp_flux(const orc_params *P, const double *ql, const double *dql, const 
         Fbar[5 + j] = 4.0 * (Fd[1][j] - 2.0 * Fd[0][j]) / (dt * dt);
     }
     if (dbg) {
-        double *z = dbg;
+        real *z = dbg;
         z[0] = r0;
         z[1] = U0[0];
         z[2] = U0[1];
@@ -1500,13 +1568,13 @@ static void local_frame(const double va[3], double n[3][3])
     n[2][2] = n[0][0] * n[1][1] - n[0][1] * n[1][0];
 }
 
-static void to_local(const double n[3][3], const double val[5], const double grad[5][3], double q[5], double dq[3][5])
+static void to_local(const double n[3][3], const real val[5], const real grad[5][3], real q[5], real dq[3][5])
 {
     q[0] = val[0];
     q[4] = val[4];
     for (int m = 0; m < 3; m++) q[1 + m] = val[1] * n[m][0] + val[2] * n[m][1] + val[3] * n[m][2];
     for (int m = 0; m < 3; m++) {
-        double dn[5];
+        real dn[5];
         for (int c = 0; c < 5; c++) dn[c] = grad[c][0] * n[m][0] + grad[c][1] * n[m][1] + grad[c][2] * n[m][2];
         dq[m][0] = dn[0];
         dq[m][4] = dn[4];
@@ -1514,32 +1582,32 @@ static void to_local(const double n[3][3], const double val[5], const double gra
     }
 }
 
-static int physical_state(const orc_params *P, const double q[5])
+static int physical_state(const orc_params *P, const real q[5])
 {
-    if (!(q[0] > 0.0)) return 0;
-    const double p = (P->gamma - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
-    return p > 0.0;
+    if (!(RE(q[0]) > 0.0)) return 0;
+    const real p = (P->gamma - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+    return RE(p) > 0.0;
 }
 
 /* a side state that keeps its reconstruction: rho and p positive and, with a floor, above that
    fraction of the side cell's average density and pressure */
-static int admissible_state(const orc *o, const orc_params *P, const double *Q, sref s, const double q[5])
+static int admissible_state(const orc *o, const orc_params *P, const real *Q, sref s, const real q[5])
 {
     if (!physical_state(P, q)) return 0;
     if (P->fallback_floor > 0.0) {
-        double v[5];
+        real v[5];
         for (int c = 0; c < 5; c++) v[c] = member_value(o, Q, c, s);
-        const double pav = (P->gamma - 1.0) * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
-        const double p = (P->gamma - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
-        if (!(q[0] > P->fallback_floor * v[0]) || !(p > P->fallback_floor * pav)) return 0;
+        const real pav = (P->gamma - 1.0) * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
+        const real p = (P->gamma - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
+        if (!(RE(q[0]) > P->fallback_floor * RE(v[0])) || !(RE(p) > P->fallback_floor * RE(pav))) return 0;
     }
     return 1;
 }
 
 /* first-order fallback of one side: the member's cell average in the local frame, zero slopes */
-static void fallback_state(const orc *o, const double *Q, sref s, const double n[3][3], double q[5], double dq[3][5])
+static void fallback_state(const orc *o, const real *Q, sref s, const double n[3][3], real q[5], real dq[3][5])
 {
-    double v[5], g[5][3];
+    real v[5], g[5][3];
     for (int c = 0; c < 5; c++) {
         v[c] = member_value(o, Q, c, s);
         g[c][0] = g[c][1] = g[c][2] = 0.0;
@@ -1547,7 +1615,7 @@ static void fallback_state(const orc *o, const double *Q, sref s, const double n
     to_local(n, v, g, q, dq);
 }
 
-static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt, double *out)
+static int face_flux_all(orc *o, const orc_params *P, const real *Q, double dt, real *out)
 {
     weno_all(o, P, Q);
     /* each iteration writes only its own face's fluxes; the fallback count is an integer sum */
@@ -1556,9 +1624,9 @@ static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt
 #pragma omp parallel for schedule(static) reduction(+ : nfb) reduction(max : err)
     for (int64_t f = 0; f < o->n_faces; f++) {
         const oface *F = &o->f[f];
-        double acc[10] = {0};
+        real acc[10] = {0};
         for (int k = 0; k < 4; k++) {
-            double vl[5], gl[5][3], vr[5], gr[5][3];
+            real vl[5], gl[5][3], vr[5], gr[5][3];
             weno_eval(o, P, Q, F->owner, -1, F->gp[k], vl, gl);
             /* the neighbour's polynomial as its image: P(T^-1 x), momentum signed by the reflections */
             const sref *T = &F->nb;
@@ -1573,7 +1641,7 @@ static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt
             }
             double n[3][3];
             local_frame(F->va[k], n);
-            double ql[5], qr[5], dql[3][5], dqr[3][5];
+            real ql[5], qr[5], dql[3][5], dqr[3][5];
             to_local(n, vl, gl, ql, dql);
             to_local(n, vr, gr, qr, dqr);
             if (P->fallback) {
@@ -1586,7 +1654,7 @@ static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt
                     nfb++;
                 }
             }
-            double Fb[10];
+            real Fb[10];
             const int e = orc_gp_flux(P, ql, &dql[0][0], qr, &dqr[0][0], dt, Fb, NULL);
             if (e) {
                 if (e > err) err = e;
@@ -1594,8 +1662,8 @@ static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt
             }
             double area = sqrt(F->va[k][0] * F->va[k][0] + F->va[k][1] * F->va[k][1] + F->va[k][2] * F->va[k][2]);
             for (int s = 0; s < 2; s++) {
-                const double *Fl = Fb + 5 * s;
-                double g[5];
+                const real *Fl = Fb + 5 * s;
+                real g[5];
                 g[0] = Fl[0];
                 g[4] = Fl[4];
                 for (int q = 0; q < 3; q++) g[1 + q] = Fl[1] * n[0][q] + Fl[2] * n[1][q] + Fl[3] * n[2][q];
@@ -1609,16 +1677,16 @@ static int face_flux_all(orc *o, const orc_params *P, const double *Q, double dt
 }
 
 /* face fluxes [F][10]: (Fbar0, Fbar1), area-integrated, owner -> neighbour */
-int orc_face_flux(orc *o, const orc_params *P, const double *Q, double dt, double *out)
+int orc_face_flux(orc *o, const orc_params *P, const real *Q, double dt, real *out)
 {
     return face_flux_all(o, P, Q, dt, out);
 }
 
 /* L and dL/dt per cell, layout [5][n] each */
-int orc_residual(orc *o, const orc_params *P, const double *Q, double dt, double *L, double *dL)
+int orc_residual(orc *o, const orc_params *P, const real *Q, double dt, real *L, real *dL)
 {
     int64_t n = o->n_cells;
-    double *ff = malloc(sizeof(double) * 10 * o->n_faces);
+    real *ff = malloc(sizeof(real) * 10 * o->n_faces);
     int e = face_flux_all(o, P, Q, dt, ff);
     if (e) {
         free(ff);
@@ -1626,10 +1694,10 @@ int orc_residual(orc *o, const orc_params *P, const double *Q, double dt, double
     }
     for (int64_t i = 0; i < n; i++) {
         const ocell *C = &o->c[i];
-        double s0[5] = {0}, s1[5] = {0};
+        real s0[5] = {0}, s1[5] = {0};
         for (int p = 0; p < C->nf; p++) {
             double sg = C->fside[p] == 0 ? 1.0 : -1.0;
-            const double *fx = ff + 10 * C->face[p];
+            const real *fx = ff + 10 * C->face[p];
             for (int c = 0; c < 5; c++) {
                 s0[c] += sg * fx[c];
                 s1[c] += sg * fx[5 + c];
@@ -1645,14 +1713,16 @@ int orc_residual(orc *o, const orc_params *P, const double *Q, double dt, double
 }
 
 /* time step: CFL min_i h_i / (|U_i| + c_i), h_i = 6 |Omega_i| / sum of face areas */
-double orc_timestep(const orc *o, const orc_params *P, const double *Q)
+double orc_timestep(const orc *o, const orc_params *P, const real *Q)
 {
     int64_t n = o->n_cells;
     double dt = INFINITY;
     for (int64_t i = 0; i < n; i++) {
-        double q[5], rho, U[3], lam, p;
-        for (int c = 0; c < 5; c++) q[c] = Q[c * n + i];
-        cons_to_prim(P->gamma, q, &rho, U, &lam, &p);
+        double q[5], U[3];
+        for (int c = 0; c < 5; c++) q[c] = RE(Q[c * n + i]);
+        const double rho = q[0];
+        for (int d = 0; d < 3; d++) U[d] = q[1 + d] / q[0];
+        const double p = (P->gamma - 1.0) * (q[4] - 0.5 * q[0] * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
         if (!(rho > 0 && p > 0)) return -1.0;
         double h = 6.0 * o->c[i].vol / o->c[i].area_sum;
         double s = sqrt(U[0] * U[0] + U[1] * U[1] + U[2] * U[2]) + sqrt(P->gamma * p / rho);
@@ -1663,12 +1733,12 @@ double orc_timestep(const orc *o, const orc_params *P, const double *Q)
 }
 
 /* two-stage fourth-order step for a generic operator Q -> (L, dL/dt) */
-typedef int (*orc_op)(void *ctx, const double *Q, double *L, double *dL);
+typedef int (*orc_op)(void *ctx, const real *Q, real *L, real *dL);
 
-int orc_s2o4(int64_t len, double *Q, double dt, orc_op op, void *ctx)
+int orc_s2o4(int64_t len, real *Q, double dt, orc_op op, void *ctx)
 {
-    double *L0 = malloc(sizeof(double) * len), *D0 = malloc(sizeof(double) * len);
-    double *Qs = malloc(sizeof(double) * len), *L1 = malloc(sizeof(double) * len), *D1 = malloc(sizeof(double) * len);
+    real *L0 = malloc(sizeof(real) * len), *D0 = malloc(sizeof(real) * len);
+    real *Qs = malloc(sizeof(real) * len), *L1 = malloc(sizeof(real) * len), *D1 = malloc(sizeof(real) * len);
     int e = op(ctx, Q, L0, D0);
     if (!e) {
         for (int64_t k = 0; k < len; k++) Qs[k] = Q[k] + 0.5 * dt * L0[k] + 0.125 * dt * dt * D0[k];
@@ -1690,13 +1760,13 @@ typedef struct {
     double dt;
 } step_ctx;
 
-static int scheme_op(void *vctx, const double *Q, double *L, double *dL)
+static int scheme_op(void *vctx, const real *Q, real *L, real *dL)
 {
     step_ctx *s = vctx;
     return orc_residual(s->o, s->P, Q, s->dt, L, dL);
 }
 
-int orc_step(orc *o, const orc_params *P, double *Q, double dt)
+int orc_step(orc *o, const orc_params *P, real *Q, double dt)
 {
     step_ctx s = {o, P, dt};
     return orc_s2o4(5 * o->n_cells, Q, dt, scheme_op, &s);
@@ -1707,7 +1777,7 @@ int orc_step(orc *o, const orc_params *P, double *Q, double dt)
  * dt_fixed > 0 uses that step size instead of the CFL one.  dts (optional)
  * receives the step sizes.  Returns 0 or a status code.
  */
-int orc_run(orc *o, const orc_params *P, double *Q, int nsteps, double t_end, double dt_fixed, double *dts, int *steps_done,
+int orc_run(orc *o, const orc_params *P, real *Q, int nsteps, double t_end, double dt_fixed, double *dts, int *steps_done,
             double *t_out)
 {
     double t = 0.0;
@@ -1773,11 +1843,11 @@ void orc_maxwell_moments(double U, double lam, double K, double *full, double *p
     maxw g;
     maxw_init(&g, 1.0, U, 0.0, 0.0, lam, K);
     for (int n = 0; n < MAXO; n++) {
-        full[n] = g.uf[n];
-        pos[n] = g.up[n];
-        neg[n] = g.un[n];
+        full[n] = RE(g.uf[n]);
+        pos[n] = RE(g.up[n]);
+        neg[n] = RE(g.un[n]);
     }
-    for (int d = 0; d < 6; d++) s[d] = g.s[d];
+    for (int d = 0; d < 6; d++) s[d] = RE(g.s[d]);
 }
 
 /* big-stencil members of cell c (cell ids and image shifts); returns K */

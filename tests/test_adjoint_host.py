@@ -104,3 +104,34 @@ def test_weno_combination_vjp_matches_finite_differences(force_linear, M):
             want = richardson(d, 1e-4) if s < M else 0.0
             assert abs(want - rb[s, q]) < 1e-8, (s, q)
     assert abs(richardson(lambda h: cb @ (f(a, r, q0 + h) - f(a, r, q0 - h)) / (2 * h), 1e-4) - qb[0]) < 1e-8
+
+
+@pytest.mark.parametrize("case", ["euler", "ns_pr072"])
+def test_gauss_point_flux_vjp_against_the_oracle_tangent(case):
+    """The library's hand-written reverse of the Gauss-point flux against the oracle's forward-mode
+    derivative (its complex-step build), with the paper's collision time (tau_C = 1): for random input
+    directions v and output cotangents w, w . (J v) from the oracle equals (J^T w) . v from the
+    library, to rounding."""
+    import oracle
+
+    lib = gks.load()
+    kw = dict(euler={}, ns_pr072=dict(viscous=True, mu=2e-3, Pr=0.72))[case]
+    prm = gks.params(tau_C=1.0, **kw)
+    oprm = oracle.params(tau_C=1.0, **kw)
+    rng = np.random.default_rng(21)
+    for _ in range(5):
+        x = [prim_to_cons(1 + 0.3 * rng.random(), 0.5 * rng.standard_normal(3), 1 + 0.3 * rng.random()),
+             0.3 * rng.standard_normal((3, 5)),
+             prim_to_cons(0.6 + 0.3 * rng.random(), 0.5 * rng.standard_normal(3), 0.7 + 0.3 * rng.random()),
+             0.3 * rng.standard_normal((3, 5))]
+        v = [rng.standard_normal(a.shape) for a in x]
+        dt = 0.02
+        ob = rng.standard_normal(10)
+        g = [np.zeros(5), np.zeros((3, 5)), np.zeros(5), np.zeros((3, 5))]
+        assert lib.gks_gp_flux_vjp_host(*(_p(np.ascontiguousarray(a)) for a in x), dt, ctypes.byref(prm), _p(ob),
+                                        *(_p(a) for a in g)) == 0
+        _, jv = oracle.gp_flux_tangent(oprm, *x, dt, *v)
+        lhs = float(ob @ jv)
+        rhs = float(sum((a * b).sum() for a, b in zip(g, v)))
+        scale = np.abs(ob).sum() * np.abs(jv).max()
+        assert abs(lhs - rhs) <= 1e-13 * scale, (lhs, rhs)

@@ -1,18 +1,25 @@
-"""GPU discrete adjoint of the S2O4 step against finite differences (needs an MI355X).
+"""GPU discrete adjoint of the S2O4 step (needs an MI355X).
 
-The adjoint step (gks_adjoint_step) is checked against central differences
-of the GPU forward step and, independently, of the FP64 oracle's step, both
-with the step size frozen; the checkpointed rollout's kinetic-energy gradient
-is checked against central differences along random directions.
+The FP64 CPU reference is the oracle's tangent (its complex-step build): exact
+directional derivatives of the oracle's own step with the step sizes frozen and
+|x| differentiated as sign(x), sign(0) = 0, the adjoint's conventions.  The
+adjoint step (gks_adjoint_step) and the checkpointed rollout's kinetic-energy
+gradient are checked against it with the paper's collision time (tau_C = 1):
+lam . (T v) from the oracle against (A lam) . v from the GPU.  The gradient
+workload (hybrid lattice, 100 steps, 32 directions) compares with the oracle's
+values stored by tests/golden/make_config4_tangent.py.
 
-The collision time's term C |p_l - p_r| / (p_l + p_r) dt is not differentiable
-where the two reconstructed pressures at a Gauss point coincide, and for a
-smooth field they differ only by the O(h^3) reconstruction jump: central
-differences then straddle the kink at some Gauss points and disagree with
-themselves at the 1e-5 level as the step h changes.  The strict (1e-6) checks
-therefore use tau_C = 0; the paper's collision time is checked against the
-finite differences' own spread.
+Central differences (of the GPU step and, independently, of the oracle's step)
+are a second witness.  The collision time's term C |p_l - p_r| / (p_l + p_r) dt
+is not differentiable where the two reconstructed pressures at a Gauss point
+coincide, and for a smooth field they differ only by the O(h^3) reconstruction
+jump: central differences then straddle the kink at some Gauss points and
+disagree with themselves at the 1e-5 level as the step h changes.  The checks
+against differences therefore use tau_C = 0 (or the differences' own spread).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -263,3 +270,99 @@ def test_config4_kinetic_energy_gradient_at_step_100(gks):
     errs = np.array(errs)
     print("relative error median", np.median(errs), "max", errs.max())
     assert np.median(errs) < 1e-4 and errs.max() < 5e-3
+
+
+@pytest.mark.parametrize("kind,viscous", [("hybrid", False), ("hybrid", True), ("hex", True)])
+def test_adjoint_step_matches_the_oracle_tangent(gks, kind, viscous):
+    """One step (the oracle's CFL step size), tau_C = 1: lam' . (T v) = (A lam') . v to 1e-10 along random
+    directions, T the oracle's tangent and A the GPU adjoint step."""
+    import torch
+
+    print(f"case: adjoint step vs oracle tangent {kind} N=4 viscous={viscous}", flush=True)
+    mesh, Q0, host, sol = _setup(gks, kind, 4, viscous, tau_C=1.0)
+    kw = dict(viscous=viscous, mu=5e-3, Pr=0.72 if viscous else 1.0, tau_C=1.0)
+    o, T = oracle.Oracle(mesh, oracle.params(**kw)), oracle.Tangent(mesh, oracle.params(**kw))
+    dt = o.timestep(Q0)
+    Qn = host.to_internal(Q0)
+    rng = np.random.default_rng(15)
+    lam1 = rng.standard_normal(Qn.shape)
+    Q = sol.upload(Qn)
+    Qs = torch.empty_like(Q)
+    sol.step(Q, dt, Q_star=Qs)
+    dtt = torch.tensor([dt], dtype=torch.float64, device=Q.device)
+    lam = host.to_external(sol.adjoint_step(sol.upload(Qn), Qs, dtt, sol.upload(lam1)).cpu().numpy())
+    sol.poll()
+    lam1e = host.to_external(lam1)
+    for trial in range(3):
+        v = rng.standard_normal(Q0.shape) * np.abs(Q0).max(axis=1, keepdims=True)
+        _, Tv = T.step(Q0, v, dt)
+        want, got = float((lam1e * Tv).sum()), float((lam * v).sum())
+        err = abs(got - want) / abs(want)
+        print(trial, want, got, err, flush=True)
+        assert err <= 1e-10
+
+
+def test_rollout_gradient_matches_the_oracle_tangent(gks):
+    """Checkpointed rollout (hybrid N = 5, Taylor-Green Mach 0.5, Euler, 12 steps, checkpoints every
+    5, tau_C = 1): the kinetic-energy gradient along random directions against the oracle's tangent
+    of the same 12 steps (step sizes of the GPU's forward pass)."""
+    from paper_2203_09047_amd.adjoint import kinetic_energy_gradient
+
+    print("case: rollout gradient vs oracle tangent hybrid N=5, 12 steps", flush=True)
+    mesh, Q0, host, sol = _setup(gks, "hybrid", 5, tau_C=1.0)
+    Qn = host.to_internal(Q0)
+    nsteps = 12
+    J, g = kinetic_energy_gradient(sol, sol.upload(Qn), nsteps, ckpt_every=5)
+    Q = sol.upload(Qn)
+    dts = []
+    for _ in range(nsteps):
+        sol.step(Q)
+        dts.append(float(sol.dt.item()))
+    g = host.to_external(g.cpu().numpy())
+    T = oracle.Tangent(mesh, oracle.params(tau_C=1.0))
+    vol = T.volumes()
+    rng = np.random.default_rng(33)
+    for trial in range(3):
+        v = rng.standard_normal(Q0.shape) * np.abs(Q0).max(axis=1, keepdims=True)
+        QT, VT = T.run(Q0, v, dts)
+        Jo, dJ = oracle.kinetic_energy(vol, QT, VT)
+        got = float((g * v).sum())
+        err = abs(got - dJ) / abs(dJ)
+        print(trial, "J", float(J.item()), Jo, "dJ", dJ, got, err, flush=True)
+        assert abs(float(J.item()) - Jo) <= 1e-12 * abs(Jo)
+        assert err <= 1e-9
+
+
+@pytest.mark.slow
+def test_gradient_workload_matches_the_oracle_tangent(gks):
+    """The gradient workload: hybrid lattice N = 16 (23,031 cells), Euler, density wave plus the seeded
+    low-pass velocity perturbation, the paper's collision time (tau_C = 1), kinetic energy at step 100,
+    checkpoints every 10.  dJ/dQ0 from the GPU adjoint along 32 seeded directions against the oracle's
+    tangent (stored by tests/golden/make_config4_tangent.py), to 1e-6 relative."""
+    import torch
+
+    from paper_2203_09047_amd.adjoint import kinetic_energy_gradient
+
+    rec = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config4_tangent_N16.json")))
+    assert len(rec["directions"]) == 32 and rec["steps"] == 100
+    print("case: gradient workload, hybrid N=16, 100 steps, 32 directions vs the oracle tangent", flush=True)
+    mesh = inputs.lattice(16, "hybrid")
+    Q0 = inputs.cell_averages(mesh, inputs.perturbed_wave())
+    assert mesh.n_cells == rec["n_cells"]
+    host = gks.HostMesh(mesh)
+    sol = gks.Solver(host, gks.params(tau_C=1.0))
+    J, g = kinetic_energy_gradient(sol, sol.upload(host.to_internal(Q0)), 100, ckpt_every=10)
+    torch.cuda.synchronize()
+    g = host.to_external(g.cpu().numpy())
+    J = float(J.item())
+    print("J gpu", J, "oracle", rec["J"], "relative", abs(J - rec["J"]) / rec["J"], flush=True)
+    assert abs(J - rec["J"]) <= 1e-10 * abs(rec["J"])
+    errs = []
+    for d in rec["directions"]:
+        v = inputs.gaussian(d["seed"], Q0.size).reshape(Q0.shape)
+        v = v / np.linalg.norm(v) * np.abs(Q0).max(axis=1, keepdims=True)
+        got = float((g * v).sum())
+        errs.append(abs(got - d["dJ"]) / abs(d["dJ"]))
+    errs = np.array(errs)
+    print("relative difference median", np.median(errs), "max", errs.max(), flush=True)
+    assert errs.max() <= 1e-6

@@ -415,9 +415,17 @@ class Quad5:
         return self.psi().T @ a
 
 
-def test_flux_pieces_and_time_integrals_by_brute_force():
-    """Slopes, interface equilibrium and the time-integrated flux of Eq. flux-1, by quadrature in u and t."""
-    prm = oracle.params()
+@pytest.mark.parametrize("case", ["euler", "ns_pr072", "ns_pr1"])
+def test_flux_pieces_and_time_integrals_by_brute_force(case):
+    """Slopes, interface equilibrium and the time-integrated flux of Eq. flux-1, by quadrature in u and t.
+
+    Navier-Stokes cases: the collision time mu / p0 + C |p_l - p_r| / (p_l + p_r) dt (opening of
+    Section 5) with p0 the pressure of the interface equilibrium taken from the quadrature, and, for
+    Pr != 1, the energy flux corrected by (1/Pr - 1) q, q = 1/2 int (u - U0)(|c - U0|^2 + s^2) f dXi of
+    the time-integrated distribution f of Eq. flux-1 (the heat flux about the g0 velocity), computed
+    node by node on the quadrature grids."""
+    kw = dict(euler={}, ns_pr072=dict(viscous=True, mu=2e-3, Pr=0.72), ns_pr1=dict(viscous=True, mu=2e-3, Pr=1.0))[case]
+    prm = oracle.params(**kw)
     rng = np.random.default_rng(7)
     for trial in range(2):
         ql = prim_to_cons(1.0 + 0.3 * rng.random(), 0.4 * rng.standard_normal(3), 1.0 + 0.3 * rng.random())
@@ -439,12 +447,17 @@ def test_flux_pieces_and_time_integrals_by_brute_force():
 
         rl, Ul, laml, pl = prim(ql)
         rr, Ur, lamr, pr = prim(qr)
-        assert tau == pytest.approx(0.01 * dt + abs(pl - pr) / (pl + pr) * dt, rel=1e-14)
         Gl, Gr = Quad5(rl, Ul, laml), Quad5(rr, Ur, lamr)
         Hl, Hr = Quad5(rl, Ul, laml, +1), Quad5(rr, Ur, lamr, -1)
         # interface equilibrium from the two half spaces
         q0 = Hl.moment(1.0) + Hr.moment(1.0)
-        r0, U0b, lam0b, _ = prim(q0)
+        r0, U0b, lam0b, p0b = prim(q0)
+        jump = abs(pl - pr) / (pl + pr) * dt
+        if prm.viscous:
+            assert tau == pytest.approx(prm.mu / p0b + jump, rel=1e-10)
+            assert prm.mu / p0b > 0.3 * jump  # a sizeable part of tau: a wrong p0 would show
+        else:
+            assert tau == pytest.approx(0.01 * dt + jump, rel=1e-14)
         assert rho0 == pytest.approx(r0, rel=1e-11)
         np.testing.assert_allclose(U0, U0b, rtol=1e-10, atol=1e-12)
         assert lam0 == pytest.approx(lam0b, rel=1e-10)
@@ -478,8 +491,34 @@ def test_flux_pieces_and_time_integrals_by_brute_force():
                             + e * (Mh - (tau + t) * Mha - tau * MhA))
             return out
 
-        np.testing.assert_allclose(Fh, F_of(0.5 * dt), rtol=1e-9, atol=1e-13)
-        np.testing.assert_allclose(Ff, F_of(dt), rtol=1e-9, atol=1e-13)
+        # heat flux about U0 of the time-integrated distribution: the same time coefficients applied
+        # to the node-wise moments of (u - U0)(|c - U0|^2 + s^2) / 2
+        def hq(Gq, f):
+            c2 = (Gq.u - U0[0]) ** 2 + (Gq.v - U0[1]) ** 2 + (Gq.w - U0[2]) ** 2 + Gq.s1 ** 2 + Gq.s2 ** 2
+            return np.array([0.5 * (Gq.W * f * (Gq.u - U0[0]) * c2).sum()] + [0.0] * 4)
+
+        Q0q, Qaq, QAq = hq(G0, 1.0), hq(G0, adv(G0, ab)), hq(G0, G0.slope(Ab))
+        Qh = hq(Hl, 1.0) + hq(Hr, 1.0)
+        Qha = hq(Hl, adv(Hl, al)) + hq(Hr, adv(Hr, ar))
+        QhA = hq(Hl, Hl.slope(Al)) + hq(Hr, Hr.slope(Ar))
+
+        def q_of(delta):
+            xt, wt = np.polynomial.legendre.leggauss(40)
+            out = np.zeros(5)
+            for t, w in zip(0.5 * delta * (xt + 1), 0.5 * delta * wt):
+                e = math.exp(-t / tau)
+                out += w * ((1 - e) * Q0q + ((t + tau) * e - tau) * Qaq + (t - tau + tau * e) * QAq
+                            + e * (Qh - (tau + t) * Qha - tau * QhA))
+            return out[0]
+
+        Fq_h, Fq_f = F_of(0.5 * dt), F_of(dt)
+        if prm.viscous and prm.Pr != 1.0:
+            corr_h, corr_f = (1 / prm.Pr - 1) * q_of(0.5 * dt), (1 / prm.Pr - 1) * q_of(dt)
+            assert abs(corr_f) > 1e-4 * abs(Ff[4])  # large enough for a wrong factor to show
+            Fq_h[4] += corr_h
+            Fq_f[4] += corr_f
+        np.testing.assert_allclose(Fh, Fq_h, rtol=1e-9, atol=1e-13)
+        np.testing.assert_allclose(Ff, Fq_f, rtol=1e-9, atol=1e-13)
         np.testing.assert_allclose(F[:5], (4 * Fh - Ff) / dt, rtol=1e-12)
         np.testing.assert_allclose(F[5:], 4 * (Ff - 2 * Fh) / dt ** 2, rtol=1e-12)
 

@@ -1,0 +1,178 @@
+"""Pins of the oracle's tangent (its complex-step build) against what fixes a derivative.
+
+The tangent is the reference the GPU's discrete adjoint is checked against, so it is pinned on the
+CPU by properties that a wrong derivative breaks: agreement with Richardson-extrapolated central
+differences of the FP64 oracle where the step is differentiable, exact linearity in the direction,
+the exact derivative of a linear step, the derivative of free-stream preservation, conservation,
+and the second-order Taylor remainder.  It also checks that its real parts reproduce the FP64
+oracle bitwise (same branches, same arithmetic).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_09047_amd import inputs
+
+NS = dict(viscous=True, mu=5e-3, Pr=0.72)
+
+
+def _case(kind="hybrid", N=3, field=None, **kw):
+    mesh = inputs.lattice(N, kind, box=(2 * np.pi,) * 3)
+    Q0 = inputs.cell_averages(mesh, field or inputs.tgv(mach=0.5))
+    prm = oracle.params(**kw)
+    return mesh, Q0, oracle.Oracle(mesh, prm), oracle.Tangent(mesh, prm)
+
+
+def _dir(rng, Q0):
+    return rng.standard_normal(Q0.shape) * np.abs(Q0).max(axis=1, keepdims=True)
+
+
+@pytest.mark.parametrize("kw", [dict(), NS], ids=["euler", "ns"])
+def test_real_parts_are_the_fp64_oracle_bitwise(kw):
+    mesh, Q0, o, T = _case(tau_C=1.0, **kw)
+    dt = o.timestep(Q0)
+    v = _dir(np.random.default_rng(1), Q0)
+    Q1, _ = T.step(Q0, v, dt)
+    assert np.array_equal(Q1, o.step(Q0, dt))
+    L, D, _, _ = T.residual(Q0, v, dt)
+    Lr, Dr = o.residual(Q0, dt)
+    assert np.array_equal(L, Lr) and np.array_equal(D, Dr)
+
+
+@pytest.mark.parametrize("kw", [dict(), NS, dict(weno_p=2.0)], ids=["euler", "ns", "weno_p2"])
+def test_tangent_matches_central_differences(kw):
+    """tau_C = 0: the step is smooth in Q (the |p_l - p_r| kink of the collision time is the only
+    non-smooth part met here); the nonlinear WENO weights stay on."""
+    mesh, Q0, o, T = _case(tau_C=0.0, **kw)
+    dt = 2e-2
+    rng = np.random.default_rng(2)
+    for _ in range(2):
+        v = _dir(rng, Q0)
+        _, V = T.step(Q0, v, dt)
+
+        def d(h):
+            return (o.step(Q0 + h * v, dt) - o.step(Q0 - h * v, dt)) / (2 * h)
+
+        fd = (4 * d(5e-7) - d(1e-6)) / 3
+        err = np.abs(fd - V).max() / np.abs(V).max()
+        print("relative difference", err)
+        assert err < 1e-7
+
+
+def test_tangent_is_linear_in_the_direction():
+    mesh, Q0, o, T = _case(tau_C=1.0, **NS)
+    dt = o.timestep(Q0)
+    rng = np.random.default_rng(3)
+    v, w = _dir(rng, Q0), _dir(rng, Q0)
+    _, Vv = T.step(Q0, v, dt)
+    _, Vw = T.step(Q0, w, dt)
+    _, Vs = T.step(Q0, 2 * v - 3 * w, dt)
+    assert np.abs(Vs - (2 * Vv - 3 * Vw)).max() <= 1e-12 * np.abs(Vs).max()
+
+
+def test_tangent_of_the_linear_two_stage_step_is_its_taylor_polynomial():
+    """For u' = -u (L = -u, dL/dt = u) one step multiplies by 1 - dt + dt^2/2 - dt^3/6 + dt^4/24, and
+    so does its derivative."""
+    rng = np.random.default_rng(4)
+    Q, V = rng.random(20), rng.standard_normal(20)
+    dt = 0.3
+    Q1, V1 = oracle.s2o4_tangent(Q, V, dt, lambda z: (-z, z))
+    poly = 1 - dt + dt ** 2 / 2 - dt ** 3 / 6 + dt ** 4 / 24
+    np.testing.assert_allclose(Q1, poly * Q, rtol=1e-15)
+    np.testing.assert_allclose(V1, poly * V, rtol=1e-15)
+
+
+@pytest.mark.parametrize("kind", ["hybrid", "tet", "pyr"])
+def test_tangent_of_free_stream_preservation(kind):
+    """Uniform states are fixed points of the step, so along a uniform direction the tangent is the
+    direction itself (the collision time's |p_l - p_r| stays zero along it: no kink)."""
+    mesh = inputs.lattice(3, kind)
+    Q0 = inputs.cell_averages(mesh, inputs.uniform(1.2, 0.3, -0.4, 0.5, 0.9))
+    T = oracle.Tangent(mesh, oracle.params(**NS))
+    v = np.array([0.1, -0.2, 0.3, 0.05, 0.7])[:, None] * np.ones((1, mesh.n_cells))
+    Q1, V1 = T.step(Q0, v, 1e-2)
+    np.testing.assert_allclose(Q1, Q0, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(V1, v, rtol=1e-11, atol=1e-11)
+
+
+def test_tangent_conserves():
+    """Sum |Omega| Q is conserved exactly by every step, so sum |Omega| dQ is too."""
+    mesh, Q0, o, T = _case(tau_C=1.0, **NS)
+    vol = T.volumes()
+    v = _dir(np.random.default_rng(5), Q0)
+    _, V = T.run(Q0, v, [2e-2, 1.5e-2, 2e-2])
+    before, after = (v * vol).sum(axis=1), (V * vol).sum(axis=1)
+    np.testing.assert_allclose(after, before, rtol=1e-12, atol=1e-12 * np.abs(v * vol).sum())
+
+
+def test_taylor_remainder_is_second_order():
+    """|f(x + e v) - f(x) - e f'(x) v| falls as e^2 (a wrong derivative leaves an O(e) remainder)."""
+    mesh, Q0, o, T = _case(tau_C=0.0, **NS)
+    dt = 2e-2
+    v = _dir(np.random.default_rng(6), Q0)
+    f0 = o.step(Q0, dt)
+    _, V = T.step(Q0, v, dt)
+    r = [np.abs(o.step(Q0 + e * v, dt) - f0 - e * V).max() for e in (1e-4, 5e-5, 2.5e-5)]
+    print("remainders", r)
+    assert 3.7 < r[0] / r[1] < 4.3 and 3.7 < r[1] / r[2] < 4.3
+
+
+def test_kinetic_energy_derivative():
+    mesh, Q0, o, T = _case()
+    vol = T.volumes()
+    v = _dir(np.random.default_rng(7), Q0)
+    J, dJ = oracle.kinetic_energy(vol, Q0, v)
+    h = 1e-6
+    fd = (oracle.kinetic_energy(vol, Q0 + h * v) - oracle.kinetic_energy(vol, Q0 - h * v)) / (2 * h)
+    assert dJ == pytest.approx(fd, rel=1e-8)
+
+
+def _growth(mesh, min_big, cfl=0.1, iters=300):
+    """Dominant amplification per step of the step linearised about a uniform flow (where the
+    nonlinear weights reduce to the linear ones), by power iteration with the tangent, and the
+    amplitude of the dominant mode per cell."""
+    Q0 = inputs.cell_averages(mesh, inputs.uniform(1.0, 1.0, 1.0, 1.0, 1.0))
+    T = oracle.Tangent(mesh, oracle.params(tau_C=0.0), min_big=min_big)
+    o = oracle.Oracle(mesh, oracle.params(cfl=cfl), min_big=min_big)
+    dt = o.timestep(Q0)
+    vol = T.volumes()
+
+    def zero_mean(x):
+        # the step conserves sum |Omega| v, so directions with zero volume-weighted mean form an
+        # invariant subspace; it excludes the uniform directions, which the step keeps (eigenvalue 1)
+        return x - (x * vol).sum(axis=1, keepdims=True) / vol.sum()
+
+    v = zero_mean(np.random.default_rng(0).standard_normal(Q0.shape))
+    v /= np.linalg.norm(v)
+    lam = []
+    for _ in range(iters):
+        _, w = T.step(Q0, v, dt)
+        w = zero_mean(w)
+        lam.append(np.linalg.norm(w))
+        v = w / lam[-1]
+    return float(np.exp(np.mean(np.log(lam[-50:])))), dt, np.abs(v).max(axis=0), o
+
+
+@pytest.mark.slow
+def test_linearised_scheme_grows_on_the_hybrid_lattice_only_with_the_papers_stencils():
+    """The hybrid lattice with the paper's stencils: the linearised step has a mode that grows at a rate
+    per unit time independent of dt (a growing mode of the semi-discrete operator, not a time-step
+    limit), supported on tetrahedra whose big stencils have 12-14 members (the lattice's mean is
+    about 16).  With big stencils grown to 16 members, and on the pure tetrahedral lattice, no mode grows
+    at even a hundredth of that rate."""
+    mesh = inputs.lattice(4, "hybrid")
+    rates = []
+    for cfl in (0.1, 0.05):
+        lam, dt, amp, o = _growth(mesh, 0, cfl)
+        rates.append(np.log(lam) / dt)
+        top = np.argsort(-amp)[:10]
+        K = np.array([o.stencil_sizes(c)[0] for c in range(mesh.n_cells)])
+        print(f"CFL {cfl}: amplification {lam}, rate per unit time {rates[-1]}, top cells types",
+              mesh.types[top].tolist(), "K", K[top].tolist(), "mean K", K.mean())
+        assert lam > 1.01
+        assert (mesh.types[top] == 0).mean() >= 0.8 and K[top].max() <= 14 and K.mean() > 15
+    assert rates[0] > 10 and 0.5 < rates[1] / rates[0] < 2
+    for m, mb in ((mesh, 16), (inputs.lattice(3, "tet"), 0)):
+        lam, dt, *_ = _growth(m, mb, 0.1)
+        print("min_big", mb, "amplification", lam, "rate per unit time", np.log(lam) / dt)
+        assert np.log(lam) / dt < 0.01 * rates[0]
