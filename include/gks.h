@@ -62,7 +62,7 @@ typedef enum { GKS_FP64 = 0, GKS_FP32_MIXED = 1 } gks_precision;
  * and weno_eps = 1e-6 (the paper leaves epsilon unspecified); collision time
  * tau = tau_eps dt + tau_C |p_l - p_r| / (p_l + p_r) dt for inviscid flow and
  * mu / p_0 + tau_C |p_l - p_r| / (p_l + p_r) dt for viscous flow with
- * tau_eps = 0.01, tau_C = 1 (Section 4); CFL time step
+ * tau_eps = 0.01, tau_C = 1 (opening of Section 5); CFL time step
  * dt = cfl min_i h_i / (|U_i| + c_i) with h_i = 6 |Omega_i| / (sum of face areas).
  * Pr != 1 adds (1/Pr - 1) q to the energy flux, q being the heat flux of the
  * time-integrated distribution about the interface velocity.
@@ -96,6 +96,8 @@ typedef struct {
                                  paper's hypersonic case (Section 5, exponent 0.7 there); 0 (the
                                  default): constant mu.  The adjoint refuses it (GKS_EINVAL) */
     double T_ref;             /* the temperature at which the viscosity is mu (> 0 when used; default 1) */
+    double dt_max;            /* > 0: the CFL step is capped at dt_max on the device (the time left to an
+                                 end time, so that the last step lands on it); 0 (the default): no cap */
 } gks_params;
 
 typedef struct gks_host_mesh gks_host_mesh;
@@ -156,11 +158,15 @@ gks_status gks_host_mesh_faces(const gks_host_mesh *h, int32_t *owner, int32_t *
 gks_status gks_host_mesh_face_geometry(const gks_host_mesh *h, double *fgeo);
 
 /*
- * Bytes of the device mesh arena and of the work buffer for a precision.
- * The work buffer holds the stage state, reconstruction coefficients, face
- * fluxes, time-step partials and the status word.
+ * Bytes of the device mesh arena and of the work buffer for a precision, and
+ * of one step's coefficient tape (the optional coeff_tape of gks_s2o4_step,
+ * read back by gks_adjoint_step: both stages' per-cell quadratics,
+ * 2 x n_cells x 50 elements of the precision).  The work buffer holds the
+ * stage state, reconstruction coefficients, face fluxes, time-step partials
+ * and the status word.  Any output pointer may be NULL.
  */
-gks_status gks_mesh_sizes(const gks_host_mesh *h, int precision, size_t *mesh_bytes, size_t *work_bytes);
+gks_status gks_mesh_sizes(const gks_host_mesh *h, int precision, size_t *mesh_bytes, size_t *work_bytes,
+                          size_t *tape_bytes_per_step);
 
 /*
  * Upload the mesh into the caller's device arena (mesh_bytes from
@@ -177,7 +183,8 @@ gks_status gks_reset_status(gks_mesh *m, void *work, gks_stream_t stream);
 /*
  * CFL time step (reading of the paper's time-step step of its solution
  * algorithm, which gives no formula): *dt_dev = cfl min_i h_i / (|U_i| + c_i),
- * computed in FP64 with a deterministic two-pass minimum.
+ * computed in FP64 with a deterministic two-pass minimum, and capped at
+ * p->dt_max when that is positive.
  */
 gks_status gks_timestep(gks_mesh *m, const double *Q, const gks_params *p, double *dt_dev, void *work,
                         gks_stream_t stream);
@@ -250,26 +257,6 @@ gks_status gks_s2o4_step_noalloc(gks_mesh *m, double *Q, double *dt_dev, const g
                                  double *Q_star, void *coeff_tape, gks_stream_t stream);
 
 /*
- * Discrete adjoint of one S2O4 step (FP64 meshes only), the dt of the step
- * being a constant.  With the step written as
- *   Q* = Q + dt/2 L(Q) + dt^2/8 D(Q),  Q' = Q + dt L(Q) + dt^2/6 (D(Q) + 2 D(Q*)),
- * and lam' = dJ/dQ' [5][n_cells] (device), it computes
- *   lam* = dt^2/3 J_D(Q*)^T lam',
- *   lam  = lam' + lam* + J_L(Q)^T (dt lam' + dt/2 lam*) + J_D(Q)^T (dt^2/6 lam' + dt^2/8 lam*)
- * into lam_n, where J_L, J_D are the Jacobians of the reconstruction -> flux ->
- * Eq. finite operator (including the nonlinear WENO weights and the collision
- * time; |x| is differentiated as sign(x), sign(0) = 0).  Qn and Qstar are the
- * step's start state and stage state (as produced by gks_s2o4_step), dt_dev
- * the step's dt.  adj_work: caller-owned device buffer of
- * gks_adjoint_work_bytes(), 256-byte aligned.  coeff_tape (optional, may be
- * NULL): the step's coefficient tape from gks_s2o4_step; when given, the two
- * reconstructions of Qn and Qstar are read from it instead of recomputed.
- * Periodic meshes only (GKS_EINVAL on a mesh with walls), with the
- * first-order fallback and the smooth flux off (GKS_EINVAL otherwise: the
- * adjoint differentiates Eq. flux-1 without the fallback's switch).  Every gather runs in a fixed order (no atomics): the result is bitwise
- * reproducible, and the same with or without the tape.
- */
-/*
  * One implicit step of the steady solver (Section 3.3: Eq. impEuler with the
  * flux-split operator of Eq. euler-scheme, solved by the Jacobi iteration of
  * Eq. jacobi with kmax sweeps).  Res = L + dt_f/2 dL/dt is the GKS residual
@@ -287,6 +274,30 @@ gks_status gks_s2o4_step_noalloc(gks_mesh *m, double *Q, double *dt_dev, const g
 gks_status gks_implicit_step(gks_mesh *m, double *Q, double *dt_dev, double dt_factor, int kmax, const gks_params *p,
                              void *work, gks_stream_t stream);
 
+/*
+ * Discrete adjoint of one S2O4 step (FP64 meshes only), the dt of the step
+ * being a constant.  With the step written as
+ *   Q* = Q + dt/2 L(Q) + dt^2/8 D(Q),  Q' = Q + dt L(Q) + dt^2/6 (D(Q) + 2 D(Q*)),
+ * and lam' = dJ/dQ' [5][n_cells] (device), it computes
+ *   lam* = dt^2/3 J_D(Q*)^T lam',
+ *   lam  = lam' + lam* + J_L(Q)^T (dt lam' + dt/2 lam*) + J_D(Q)^T (dt^2/6 lam' + dt^2/8 lam*)
+ * into lam_n, where J_L, J_D are the Jacobians of the reconstruction -> flux ->
+ * Eq. finite operator (including the nonlinear WENO weights and the collision
+ * time; |x| is differentiated as sign(x), sign(0) = 0).  Qn and Qstar are the
+ * step's start state and stage state (as produced by gks_s2o4_step), dt_dev
+ * the step's dt.  adj_work: caller-owned device buffer of the size that
+ * gks_adjoint_work_bytes() reports, 256-byte aligned.  coeff_tape (optional,
+ * may be NULL): the step's coefficient tape from gks_s2o4_step
+ * (tape_bytes_per_step of gks_mesh_sizes); when given, the two
+ * reconstructions of Qn and Qstar are read from it instead of recomputed.
+ * Periodic meshes only (GKS_EINVAL on a mesh with walls), with the
+ * first-order fallback, the smooth flux and the viscosity power law off
+ * (GKS_EINVAL otherwise: the adjoint differentiates Eq. flux-1 without the
+ * fallback's switch).  Every gather runs in a fixed order (no atomics): the
+ * result is bitwise reproducible, and the same with or without the tape.
+ * The same conventions define the tangent of the FP64 reference it is
+ * tested against.
+ */
 gks_status gks_adjoint_work_bytes(const gks_host_mesh *h, size_t *bytes);
 gks_status gks_adjoint_step(gks_mesh *m, const double *Qn, const double *Qstar, const double *dt_dev,
                             const double *lam_np1, double *lam_n, const gks_params *p, void *adj_work,

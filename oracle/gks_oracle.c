@@ -21,7 +21,7 @@
  *     time-dependent distribution at a face Gauss point (Eq. flux-1), the
  *     slopes from reconstructed directional derivatives and compatibility,
  *     the interface equilibrium and its slopes (Section 3.2);
- *   - the collision time of Section 4;
+ *   - the collision time of the opening of Section 5;
  *   - the semi-discrete operator (Eq. semi, Eq. finite) and the two-stage
  *     fourth-order time stepping the paper cites for unsteady flow
  *     (Section 3.3: Li & Du 2016; Pan, Xu, Li & Li 2016).
@@ -1453,7 +1453,7 @@ int orc_gp_flux(const orc_params *P, const real *ql, const real *dql, const real
         for (int j = 0; j < 5; j++) b[j] = -b[j];
         if (slope_solve(&g0, b, Ab)) return 5;
     }
-    /* collision time (Section 4) */
+    /* collision time (opening of Section 5) */
     real jump = r_abs((pl - pr) / (pl + pr)) * dt;
     real mu = P->mu;
     if (P->viscous && P->mu_power != 0.0) mu *= r_pow((p0 / r0) / P->T_ref, P->mu_power);

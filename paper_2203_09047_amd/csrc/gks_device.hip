@@ -184,7 +184,8 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(int n, const double *__re
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void __launch_bounds__(kBlock) k_dt_final(int nb, const double *__restrict__ part, double *dt)
+// the minimum of the per-block partials, capped at dt_max when dt_max > 0 (the time left to an end time)
+__global__ void __launch_bounds__(kBlock) k_dt_final(int nb, const double *__restrict__ part, double *dt, double dt_max)
 {
     __shared__ double red[kBlock];
     double best = INFINITY;
@@ -195,7 +196,7 @@ __global__ void __launch_bounds__(kBlock) k_dt_final(int nb, const double *__res
         if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) dt[0] = red[0];
+    if (threadIdx.x == 0) dt[0] = dt_max > 0.0 ? fmin(red[0], dt_max) : red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1732,11 +1733,13 @@ static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *ba
     return off;
 }
 
-gks_status gks_mesh_sizes(const gks_host_mesh *h, int precision, size_t *mesh_bytes, size_t *work_bytes)
+gks_status gks_mesh_sizes(const gks_host_mesh *h, int precision, size_t *mesh_bytes, size_t *work_bytes,
+                          size_t *tape_bytes_per_step)
 {
     if (!h || (precision != GKS_FP64 && precision != GKS_FP32_MIXED)) return fail(GKS_EINVAL, "bad argument");
     if (mesh_bytes) *mesh_bytes = mesh_layout(h->h, precision, nullptr, nullptr, nullptr, nullptr);
     if (work_bytes) *work_bytes = work_layout(h->h.n, h->h.nf, precision, nullptr, nullptr);
+    if (tape_bytes_per_step) *tape_bytes_per_step = (precision == GKS_FP64 ? 8 : 4) * size_t(2) * 50 * (size_t)h->h.n;
     return GKS_OK;
 }
 
@@ -1831,6 +1834,7 @@ static gks_status check_params(const gks_mesh *m, const gks_params *p)
     if (!(p->gamma > 1.0) || !(p->cfl > 0.0)) return fail(GKS_EINVAL, "bad gamma or cfl");
     if (p->viscous && !(p->mu >= 0.0)) return fail(GKS_EINVAL, "bad viscosity");
     if (!(p->Pr > 0.0)) return fail(GKS_EINVAL, "bad Prandtl number");
+    if (!(p->dt_max >= 0.0) || !std::isfinite(p->dt_max)) return fail(GKS_EINVAL, "dt_max must be finite and >= 0");
     if (!(p->fallback_floor >= 0.0 && p->fallback_floor < 1.0)) return fail(GKS_EINVAL, "fallback_floor outside [0, 1)");
     if (!std::isfinite(p->mu_power) || (p->mu_power != 0.0 && !(p->T_ref > 0.0 && std::isfinite(p->T_ref))))
         return fail(GKS_EINVAL, "bad viscosity power law (mu_power, T_ref)");
@@ -1857,7 +1861,7 @@ static gks_status launch_timestep(gks_mesh *m, const double *Q, const gks_params
     ProfScope ps(m, GKS_K_TIMESTEP, st);
     int nb = (int)std::min<int64_t>(kDtBlocks, grid_for(m->n, kBlock));
     k_dt_partial<<<nb, kBlock, 0, st>>>((int)m->n, Q, m->d.hcfl, p->gamma, p->cfl, w.dtpart, w.status);
-    k_dt_final<<<1, kBlock, 0, st>>>(nb, w.dtpart, dt_dev);
+    k_dt_final<<<1, kBlock, 0, st>>>(nb, w.dtpart, dt_dev, p->dt_max);
     return hip_check(hipGetLastError(), "timestep launch");
 }
 

@@ -47,7 +47,7 @@ class Params(ctypes.Structure):
         ("tau_eps", ctypes.c_double), ("tau_C", ctypes.c_double), ("viscous", ctypes.c_int),
         ("precision", ctypes.c_int), ("force_linear", ctypes.c_int), ("dt_given", ctypes.c_int),
         ("first_order_fallback", ctypes.c_int), ("fallback_floor", ctypes.c_double), ("smooth_flux", ctypes.c_int),
-        ("mu_power", ctypes.c_double), ("T_ref", ctypes.c_double),
+        ("mu_power", ctypes.c_double), ("T_ref", ctypes.c_double), ("dt_max", ctypes.c_double),
     ]
 
 
@@ -82,7 +82,7 @@ def load():
         lib.gks_host_mesh_faces.restype = st
         lib.gks_host_mesh_face_geometry.argtypes = [vp, vp]
         lib.gks_host_mesh_face_geometry.restype = st
-        lib.gks_mesh_sizes.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        lib.gks_mesh_sizes.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]
         lib.gks_mesh_sizes.restype = st
         lib.gks_init_mesh.argtypes = [vp, i32, vp, sz, vp, ctypes.POINTER(vp)]
         lib.gks_init_mesh.restype = st
@@ -244,9 +244,9 @@ class Solver:
         self.P = prm if prm is not None else params()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        mb, wb = ctypes.c_size_t(), ctypes.c_size_t()
-        _check(lib.gks_mesh_sizes(host.h, self.P.precision, ctypes.byref(mb), ctypes.byref(wb)))
-        self.mesh_bytes, self.work_bytes = mb.value, wb.value
+        mb, wb, tb = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib.gks_mesh_sizes(host.h, self.P.precision, ctypes.byref(mb), ctypes.byref(wb), ctypes.byref(tb)))
+        self.mesh_bytes, self.work_bytes, self.tape_bytes = mb.value, wb.value, tb.value
         self.arena = torch.empty(self.mesh_bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self.arena.data_ptr()) % 256
         self._arena_ptr = ctypes.c_void_p(self.arena.data_ptr() + off)
@@ -307,8 +307,9 @@ class Solver:
         return L, D
 
     def coeff_tape(self):
-        """A device buffer for both stages' reconstructions of one step ([2][n][5][10])."""
-        return self.torch.empty(2 * self.n * 50, dtype=self.coeff_dtype, device=self.device)
+        """A device buffer for both stages' reconstructions of one step (tape_bytes_per_step)."""
+        return self.torch.empty(self.tape_bytes // self.coeff_dtype.itemsize, dtype=self.coeff_dtype,
+                                device=self.device)
 
     def step(self, Q, dt=None, Q_star=None, coeff_tape=None):
         """One S2O4 step in place; dt=None computes the CFL step on the device."""
@@ -430,14 +431,18 @@ class Solver:
             elif len(dts) >= nsteps:
                 break
             if t_end > 0:
-                dt = float(self.timestep(Q).item())
-                # the step size is read back anyway: stop at the first non-physical state instead of
-                # marching a broken field with ever smaller steps
+                # the time step kernel caps the CFL step at the time left, so the last step lands on t_end
+                self.P.dt_max = t_end - t
+                try:
+                    self.step(Q)
+                finally:
+                    self.P.dt_max = 0.0
+                # the step size is read back for the clock: stop at the first non-physical state instead
+                # of marching a broken field with ever smaller steps
+                dt = float(self.dt.item())
                 self.poll()
                 if not (math.isfinite(dt) and dt > 0.0):
                     raise GksError(GKS_ENONPHYS, f"time step {dt} at t = {t}")
-                dt = min(dt, t_end - t)
-                self.step(Q, dt)
             else:
                 self.step(Q)
                 dt = None
