@@ -85,3 +85,34 @@ def test_algorithmic_bytes_scale_with_the_mesh_and_the_precision():
     b2 = bench.algorithmic_bytes(h2, 8)
     for k, v in b64.items():
         assert b2[k] == 2 * v, k
+
+
+def test_flops_count_lanes_and_fma_twice():
+    c = {"SQ_INSTS_VALU_FMA_F64": 10.0, "SQ_INSTS_VALU_MUL_F64": 3.0, "SQ_INSTS_VALU_ADD_F64": 2.0,
+         "SQ_INSTS_VALU_FMA_F32": 1.0}
+    assert bench.flops(c, 64) == 64 * (2 * 10 + 3 + 2)
+    assert bench.flops(c, 32) == 64 * 2
+
+
+def test_valu_summary_from_a_counter_database(tmp_path):
+    db = str(tmp_path / "valu.db")
+    con = sqlite3.connect(db)
+    con.execute("create table counters_collection (dispatch_id integer, kernel_name text, counter_name text, "
+                "value real)")
+    flux = "void gks::k_flux_chunked<true, false>(gks::DevMesh, ...)"
+    con.executemany("insert into counters_collection values (?, ?, ?, ?)",
+                    [(1, flux, "SQ_INSTS_VALU", 100.0), (1, flux, "SQ_INSTS_VALU_FMA_F64", 40.0),
+                     (2, flux, "SQ_INSTS_VALU", 300.0), (2, flux, "SQ_INSTS_VALU_FMA_F64", 60.0),
+                     (3, "other(", "SQ_INSTS_VALU", 7.0)])
+    con.commit()
+    con.close()
+    d = bench.valu_from([db])
+    assert d["kernel_source_sha256"] == bench.kernel_source_hash()
+    assert d["kernels"] == {"flux": {"SQ_INSTS_VALU": 200.0, "SQ_INSTS_VALU_FMA_F64": 50.0}}
+
+
+def test_committed_valu_summary_has_the_flux_counts():
+    with open(bench.VALU_JSON) as fh:
+        d = json.load(fh)
+    f = d["kernels"]["flux"]
+    assert f["SQ_INSTS_VALU_FMA_F64"] > 0 and f["SQ_INSTS_VALU"] > f["SQ_INSTS_VALU_FMA_F64"]

@@ -914,3 +914,19 @@ def test_power_law_viscosity_is_constant_viscosity_at_the_interface_temperature(
         Fi, _ = oracle.gp_flux(oracle.params(mu=mu, mu_power=om, T_ref=0.3), ql, dql, qr, dqr, dt)
         Fi0, _ = oracle.gp_flux(oracle.params(mu=mu), ql, dql, qr, dqr, dt)
         np.testing.assert_array_equal(Fi, Fi0)
+
+
+@pytest.mark.slow
+def test_paper_tet_accuracy_table_first_row():
+    """Table tab-3d-2 (6 N^3 tetrahedra, N = 5), scaled to the unit cube as the hexahedral pin: the Kuhn
+    split of the N^3 lattice has the table's 6 N^3 tetrahedra.  Same factor 2.5 either way (the paper's
+    flux there is the smooth-flow one with tau = 0, and its tetrahedral split may differ)."""
+    ref = json.load(open(os.path.join(GOLDEN, "paper_accuracy_tables.json")))["tet"]
+    m = inputs.lattice(5, "tet")
+    assert m.n_cells == 6 * 5 ** 3
+    o = oracle.Oracle(m)
+    Q, _ = o.run(inputs.cell_averages(m, inputs.wave()), t_end=1.0)
+    l1, _ = _errors(m, o, Q, 1.0)
+    paper = ref["L1"][0] / 8.0
+    print("unit-cube L1", l1, "paper / 8", paper)
+    assert paper / 2.5 < l1 < paper * 2.5, (l1, paper)
