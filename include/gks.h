@@ -55,6 +55,45 @@ typedef enum {
 typedef enum { GKS_FP64 = 0, GKS_FP32_MIXED = 1 } gks_precision;
 
 /*
+ * Boundary condition of one box plane of a mesh with walls (gks_preprocess
+ * with periodic = 0).  Section 2 builds stencils across a boundary from ghost
+ * cells: the mirror images of interior cells, whose flow variables the
+ * condition sets from the mirrored cell's.  At a face Gauss point on the
+ * plane the state beyond it is the condition applied to the inner
+ * reconstructed state (its gradient by the chain rule, the derivative across
+ * the plane negated); the far field's ghost is uniform.
+ *   GKS_BC_SLIP        reflective wall: normal momentum negated (the default);
+ *   GKS_BC_NOSLIP      adiabatic no-slip wall moving with velocity uw:
+ *                      U -> 2 uw - U, density and pressure kept;
+ *   GKS_BC_ISOTHERMAL  no-slip wall at temperature Tw = p / rho (gas constant 1):
+ *                      U -> 2 uw - U, T -> 2 Tw - T, pressure kept (the
+ *                      paper's cavity: "isothermal and nonslip");
+ *   GKS_BC_FARFIELD    Riemann invariants U_n +- 2c/(gamma-1) along the outward
+ *                      normal against the free stream far = (rho, U, V, W, p):
+ *                      the outgoing one from the interior, the incoming one
+ *                      from the free stream, entropy and tangential velocity
+ *                      from the upwind side; supersonic inflow takes the free
+ *                      stream, supersonic outflow the interior (the sphere's
+ *                      inlet and outlet);
+ *   GKS_BC_EXTRAPOLATE the ghost repeats the mirrored cell (zero-gradient
+ *                      outflow; the Riemann problems' non-reflecting ends).
+ */
+typedef enum {
+    GKS_BC_SLIP = 0,
+    GKS_BC_NOSLIP = 1,
+    GKS_BC_ISOTHERMAL = 2,
+    GKS_BC_FARFIELD = 3,
+    GKS_BC_EXTRAPOLATE = 4
+} gks_bc_type;
+
+typedef struct {
+    int type;      /* gks_bc_type */
+    double uw[3];  /* wall velocity (no-slip types; tangential to the plane) */
+    double Tw;     /* wall temperature p / rho (isothermal; > 0) */
+    double far[5]; /* free stream rho, U, V, W, p (far field; rho, p > 0) */
+} gks_boundary;
+
+/*
  * Scheme parameters.  Defaults (gks_default_params) follow the paper:
  * gamma = 1.4; linear weights gamma_m = 0.0125 for every sub-stencil and
  * gamma_0 = 1 - 0.0125 M (Section 2); nonlinear weights
@@ -98,6 +137,11 @@ typedef struct {
     double T_ref;             /* the temperature at which the viscosity is mu (> 0 when used; default 1) */
     double dt_max;            /* > 0: the CFL step is capped at dt_max on the device (the time left to an
                                  end time, so that the last step lands on it); 0 (the default): no cap */
+    gks_boundary bc[6];       /* conditions of the box planes x = 0, x = L, y = 0, y = L, z = 0, z = L
+                                 (index 2 axis + hi) on a mesh with walls; ignored on periodic meshes.
+                                 Default: all GKS_BC_SLIP.  Conditions other than the reflective one
+                                 are refused (GKS_EINVAL) on a mesh so thin that a stencil reaches across
+                                 both walls of an axis */
 } gks_params;
 
 typedef struct gks_host_mesh gks_host_mesh;
@@ -116,11 +160,10 @@ void gks_default_params(gks_params *p);
  *   box    [3] periodic box lengths (the domain is [0,box_x] x [0,box_y] x [0,box_z]);
  *   periodic: 1, every face is shared by exactly two cells, opposite faces of
  *     the box matched as periodic images; 0, a face of one cell must lie on a
- *     face of the box and is a reflective wall: the cell's neighbour across it
- *     is its own mirror image (the image's neighbours are the mirrors of the
- *     cell's neighbours, its state the cell's with the normal momentum
- *     negated), and the Gauss-point state beyond the wall is the mirror of the
- *     inner one;
+ *     face of the box (a wall): the cell's neighbour across it is its own
+ *     mirror image (the image's neighbours are the mirrors of the cell's
+ *     neighbours), its state given by the plane's condition (gks_params.bc,
+ *     reflective by default: the cell's with the normal momentum negated);
  *   min_big_stencil: 0 keeps the paper's big stencil (face neighbours and
  *     their face neighbours); k > 0 also grows a big stencil with fewer than
  *     k members, by the rule used for ill-posed fits (face neighbours of the
@@ -148,7 +191,8 @@ gks_status gks_host_mesh_counts(const gks_host_mesh *h, int64_t *n_cells, int64_
 gks_status gks_host_mesh_perm(const gks_host_mesh *h, int64_t *perm);
 /* per cell (internal order): volume, centroid [n][3]; either pointer may be NULL */
 gks_status gks_host_mesh_geometry(const gks_host_mesh *h, double *vol, double *xc);
-/* per face: owner and neighbour (internal indices; a wall face has neighbour -1 - axis) */
+/* per face: owner and neighbour (internal indices; a wall face on box plane 2 axis + hi has neighbour
+   -1 - (2 axis + hi)) */
 gks_status gks_host_mesh_faces(const gks_host_mesh *h, int32_t *owner, int32_t *nbr);
 /*
  * Face Gauss-point geometry [9][4 n_faces] (Gauss point 4 f + g): offset from

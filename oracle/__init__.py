@@ -48,8 +48,24 @@ def build(verbose: bool = False) -> str:
     return LIB_PATH
 
 
+BC_SLIP, BC_NOSLIP, BC_ISOTHERMAL, BC_FARFIELD, BC_EXTRAPOLATE = range(5)
+
+
+class Boundary(ctypes.Structure):
+    """Condition of one box plane of a mesh with walls: type, wall velocity, wall temperature p / rho,
+    free stream (rho, U, V, W, p)."""
+
+    _fields_ = [("type", ctypes.c_int), ("uw", ctypes.c_double * 3), ("Tw", ctypes.c_double),
+                ("far", ctypes.c_double * 5)]
+
+
+def boundary(type=BC_SLIP, uw=(0.0, 0.0, 0.0), Tw=1.0, far=(1.0, 0.0, 0.0, 0.0, 1.0)) -> Boundary:
+    return Boundary(int(type), (ctypes.c_double * 3)(*uw), float(Tw), (ctypes.c_double * 5)(*far))
+
+
 class Params(ctypes.Structure):
-    """Scheme parameters (gamma, CFL, viscosity, Prandtl number, WENO and collision-time constants)."""
+    """Scheme parameters (gamma, CFL, viscosity, Prandtl number, WENO and collision-time constants, the
+    box planes' boundary conditions)."""
 
     _fields_ = [
         ("gamma", ctypes.c_double),
@@ -68,15 +84,19 @@ class Params(ctypes.Structure):
         ("smooth", ctypes.c_int),
         ("mu_power", ctypes.c_double),
         ("T_ref", ctypes.c_double),
+        ("bc", Boundary * 6),
     ]
 
 
 def params(gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, weno_eps=1e-6, weno_gamma_m=0.0125, weno_p=1.0, tau_eps=0.01,
            tau_C=1.0, viscous=False, force_linear=False, fallback=False, fallback_floor=0.0, smooth=False,
-           mu_power=0.0, T_ref=1.0) -> Params:
-    """mu_power != 0 (viscous): mu (T / T_ref)^mu_power at the interface temperature T = p / rho."""
+           mu_power=0.0, T_ref=1.0, bc=None) -> Params:
+    """mu_power != 0 (viscous): mu (T / T_ref)^mu_power at the interface temperature T = p / rho.
+    bc: six Boundary records for the planes x=0, x=L, y=0, y=L, z=0, z=L of a mesh with walls
+    (default: all reflective)."""
+    bcs = (Boundary * 6)(*(bc if bc is not None else [boundary() for _ in range(6)]))
     return Params(gamma, cfl, mu, Pr, weno_eps, weno_gamma_m, weno_p, tau_eps, tau_C, int(viscous), int(force_linear),
-                  int(fallback), float(fallback_floor), int(smooth), float(mu_power), float(T_ref))
+                  int(fallback), float(fallback_floor), int(smooth), float(mu_power), float(T_ref), bcs)
 
 
 def _p(a):
@@ -143,6 +163,8 @@ def _load():
         lib.orc_cell_faces.restype = i32
         lib.orc_stencil_grown.argtypes = [vp, i64]
         lib.orc_stencil_grown.restype = i32
+        lib.orc_bc_ghost.argtypes = [pp, i32, vp, vp, vp, vp, vp]
+        lib.orc_bc_ghost.restype = None
         _lib = lib
     return _lib
 
@@ -494,6 +516,16 @@ def gp_flux(prm: Params, ql, dql, qr, dqr, dt):
     if e:
         raise OracleError(f"gp flux failed (code {e})")
     return out, dbg
+
+
+def bc_ghost(prm: Params, plane: int, v, gv):
+    """The condition of box plane `plane` (2 axis + hi) on a cell average v [5] (ghost average) and at a
+    Gauss point with inner value v and gradient gv [5, 3] (value [5] and gradient [5, 3] beyond)."""
+    v = np.ascontiguousarray(v, np.float64)
+    gv = np.ascontiguousarray(gv, np.float64)
+    g, gp, ggp = np.zeros(5), np.zeros(5), np.zeros((5, 3))
+    _load().orc_bc_ghost(ctypes.byref(prm), int(plane), _p(v), _p(gv), _p(g), _p(gp), _p(ggp))
+    return g, gp, ggp
 
 
 def s2o4(Q: np.ndarray, dt: float, op) -> np.ndarray:

@@ -116,6 +116,24 @@ static inline real r_pow(real x, double e) { return pow(x, e); }
 
 enum { TET = 0, PYR = 1, PRISM = 2, HEX = 3 };
 
+/* Boundary conditions of the six box planes of a mesh with walls (plane 2 d + hi: axis d, at 0 or at
+ * L).  Every one keeps the paper's ghost-cell construction (Section 2): the ghost across a plane is
+ * the mirror image of an interior cell, its flow variables set by the condition from the mirrored
+ * cell's.  At a face Gauss point on the plane the state beyond it is the condition applied to the
+ * inner reconstructed state, with the mirror's sign on the derivatives across the plane. */
+enum { BC_SLIP = 0,       /* reflective: normal momentum negated (the Riemann problems' walls) */
+       BC_NOSLIP = 1,     /* no-slip adiabatic wall moving with velocity uw: U -> 2 uw - U, rho and p kept */
+       BC_ISOTHERMAL = 2, /* no-slip wall at temperature Tw: U -> 2 uw - U, T -> 2 Tw - T, p kept (the cavity) */
+       BC_FARFIELD = 3,   /* far field by Riemann invariants against the free stream far (the sphere's inlet/outlet) */
+       BC_EXTRAPOLATE = 4 /* zero-gradient outflow: the ghost repeats the mirrored cell (non-reflecting ends) */ };
+
+typedef struct {
+    int type;
+    double uw[3]; /* wall velocity (no-slip types) */
+    double Tw;    /* wall temperature p / rho (isothermal) */
+    double far[5]; /* free stream rho, U, V, W, p (far field) */
+} orc_bc;
+
 typedef struct {
     double gamma, cfl, mu, Pr;
     double weno_eps, weno_gamma_m, weno_p;
@@ -130,6 +148,7 @@ typedef struct {
     double mu_power;  /* viscous: mu (T / T_ref)^mu_power at the interface temperature T = p0 / rho0 (gas
                          constant 1), the power law of the paper's hypersonic sphere case; 0: constant mu */
     double T_ref;
+    orc_bc bc[6];     /* the box planes' conditions on meshes with walls (plane 2 axis + hi) */
 } orc_params;
 
 /* ------------------------------------------------------------------ */
@@ -1048,11 +1067,189 @@ void orc_stencil_info(const orc *o, int64_t c, int *K, int *M, int *subn)
 /* ------------------------------------------------------------------ */
 static real Qat(const orc *o, const real *Q, int comp, int64_t cell) { return Q[comp * o->n_cells + cell]; }
 
-/* cell average of a member: its cell's, momentum components signed by the member's reflections */
-static real member_value(const orc *o, const real *Q, int comp, sref s)
+static void prim_of(double gam, const real v[5], real *rho, real U[3], real *p)
 {
-    const real v = Qat(o, Q, comp, s.cell);
-    return comp >= 1 && comp <= 3 ? s.sg[comp - 1] * v : v;
+    *rho = v[0];
+    for (int d = 0; d < 3; d++) U[d] = v[1 + d] / v[0];
+    *p = (gam - 1.0) * (v[4] - 0.5 * v[0] * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
+}
+
+static void cons_of(double gam, real rho, const real U[3], real p, real v[5])
+{
+    v[0] = rho;
+    for (int d = 0; d < 3; d++) v[1 + d] = rho * U[d];
+    v[4] = p / (gam - 1.0) + 0.5 * rho * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+}
+
+/*
+ * Far field by Riemann invariants along the outward normal (axis d, sign sn) against the free stream:
+ * U_n +- 2c/(gamma-1) carried out of the domain by the interior and into it by the free stream
+ * (subsonic), the entropy p / rho^gamma and the tangential velocity from the upwind side; supersonic
+ * inflow takes the free stream, supersonic outflow the interior state.
+ */
+static void farfield_state(const orc_params *P, int d, double sn, const real v[5], real g[5])
+{
+    const double gam = P->gamma;
+    const double *f = P->bc[2 * d + (sn > 0)].far;
+    real rho, U[3], p;
+    prim_of(gam, v, &rho, U, &p);
+    const real c = r_sqrt(gam * p / rho);
+    const real un = sn * U[d];
+    const double fU[3] = {f[1], f[2], f[3]};
+    const double cf = sqrt(gam * f[4] / f[0]), unf = sn * fU[d];
+    if (RE(un) >= RE(c)) { /* supersonic outflow */
+        for (int j = 0; j < 5; j++) g[j] = v[j];
+        return;
+    }
+    real gU[3], grho, gp;
+    if (unf <= -cf) { /* supersonic inflow */
+        const real fr = f[0], fp = f[4];
+        const real fu[3] = {fU[0], fU[1], fU[2]};
+        cons_of(gam, fr, fu, fp, g);
+        return;
+    }
+    const real Rp = un + 2.0 * c / (gam - 1.0), Rm = unf - 2.0 * cf / (gam - 1.0);
+    const real unb = 0.5 * (Rp + Rm), cb = 0.25 * (gam - 1.0) * (Rp - Rm);
+    real s;
+    if (RE(unb) > 0.0) { /* outflow: entropy and tangential velocity of the interior */
+        s = p / r_pow(rho, gam);
+        for (int q = 0; q < 3; q++) gU[q] = U[q];
+    } else {
+        s = f[4] / pow(f[0], gam);
+        for (int q = 0; q < 3; q++) gU[q] = fU[q];
+    }
+    gU[d] = sn * unb;
+    grho = r_pow(cb * cb / (gam * s), 1.0 / (gam - 1.0));
+    gp = grho * cb * cb / gam;
+    cons_of(gam, grho, gU, gp, g);
+}
+
+/* the ghost state across box plane `plane` of the state v (cell average, global frame) */
+static void bc_state(const orc_params *P, int plane, const real v[5], real g[5])
+{
+    const orc_bc *B = &P->bc[plane];
+    const int d = plane / 2;
+    const double gam = P->gamma;
+    switch (B->type) {
+    case BC_SLIP:
+        for (int j = 0; j < 5; j++) g[j] = v[j];
+        g[1 + d] = -v[1 + d];
+        return;
+    case BC_FARFIELD: farfield_state(P, d, plane % 2 ? 1.0 : -1.0, v, g); return;
+    case BC_EXTRAPOLATE:
+        for (int j = 0; j < 5; j++) g[j] = v[j];
+        return;
+    default: {
+        real rho, U[3], p, gU[3];
+        prim_of(gam, v, &rho, U, &p);
+        for (int q = 0; q < 3; q++) gU[q] = 2.0 * B->uw[q] - U[q];
+        const real grho = B->type == BC_ISOTHERMAL ? p / (2.0 * B->Tw - p / rho) : rho;
+        cons_of(gam, grho, gU, p, g);
+    }
+    }
+}
+
+/*
+ * Cell average of a member: its cell's, through the boundary condition of every wall plane the member
+ * is mirrored across (axis order; an axis mirrored twice, at 0 and at L, is a translation by 2L and
+ * crosses both planes: first the one at 0 for +2L, first the one at L for -2L).
+ */
+static void member_state(const orc *o, const orc_params *P, const real *Q, sref s, real v[5])
+{
+    for (int c = 0; c < 5; c++) v[c] = Qat(o, Q, c, s.cell);
+    for (int d = 0; d < 3; d++) {
+        int planes[2], np = 0;
+        if (s.sg[d] < 0)
+            planes[np++] = 2 * d + (s.of[d] == 2);
+        else if (s.of[d] == 2 && !o->periodic) {
+            planes[np++] = 2 * d;
+            planes[np++] = 2 * d + 1;
+        } else if (s.of[d] == -2 && !o->periodic) {
+            planes[np++] = 2 * d + 1;
+            planes[np++] = 2 * d;
+        }
+        for (int k = 0; k < np; k++) {
+            real g[5];
+            bc_state(P, planes[k], v, g);
+            for (int c = 0; c < 5; c++) v[c] = g[c];
+        }
+    }
+}
+
+static real member_value(const orc *o, const orc_params *P, const real *Q, int comp, sref s)
+{
+    if (s.sg[0] > 0 && s.sg[1] > 0 && s.sg[2] > 0 &&
+        (o->periodic || (abs(s.of[0]) < 2 && abs(s.of[1]) < 2 && abs(s.of[2]) < 2)))
+        return Qat(o, Q, comp, s.cell); /* not mirrored */
+    real v[5];
+    member_state(o, P, Q, s, v);
+    return v[comp];
+}
+
+/*
+ * Value and gradient (global frame) beyond box plane `plane` at a Gauss point on it, from the inner
+ * reconstructed ones: the ghost field is the condition applied to the mirrored inner field, so its
+ * value is the condition of the inner value and its gradient the condition's derivative applied to
+ * the inner gradient, with the derivative across the plane negated (the mirror).  The far field's
+ * ghost is uniform (zero gradient).  The flux's reflective walls evaluate the image's reconstruction
+ * instead (the same state).
+ */
+static void bc_ghost_point(const orc_params *P, int plane, const real v[5], const real gv[5][3], real g[5], real gg[5][3])
+{
+    const orc_bc *B = &P->bc[plane];
+    const int d = plane / 2;
+    const double gam = P->gamma;
+    if (B->type == BC_FARFIELD) {
+        farfield_state(P, d, plane % 2 ? 1.0 : -1.0, v, g);
+        for (int c = 0; c < 5; c++)
+            for (int q = 0; q < 3; q++) gg[c][q] = 0.0;
+        return;
+    }
+    if (B->type == BC_EXTRAPOLATE || B->type == BC_SLIP) {
+        /* linear conditions: the sign of the normal momentum (reflective), the mirror on the gradient */
+        for (int c = 0; c < 5; c++) {
+            const double s = B->type == BC_SLIP && c == 1 + d ? -1.0 : 1.0;
+            g[c] = s * v[c];
+            for (int q = 0; q < 3; q++) gg[c][q] = (q == d ? -s : s) * gv[c][q];
+        }
+        return;
+    }
+    /* no-slip: primitive variables and their derivatives along x, y, z */
+    real rho, U[3], p, drho[3], dU[3][3], dp[3];
+    prim_of(gam, v, &rho, U, &p);
+    for (int q = 0; q < 3; q++) {
+        drho[q] = gv[0][q];
+        real udu = 0.0;
+        for (int a = 0; a < 3; a++) {
+            dU[a][q] = (gv[1 + a][q] - U[a] * gv[0][q]) / rho;
+            udu += U[a] * dU[a][q];
+        }
+        dp[q] = (gam - 1.0) * (gv[4][q] - 0.5 * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]) * gv[0][q] - rho * udu);
+    }
+    real gU[3], gdU[3][3], grho = rho, gdrho[3];
+    for (int a = 0; a < 3; a++) {
+        gU[a] = 2.0 * B->uw[a] - U[a];
+        for (int q = 0; q < 3; q++) gdU[a][q] = -dU[a][q];
+    }
+    for (int q = 0; q < 3; q++) gdrho[q] = drho[q];
+    if (B->type == BC_ISOTHERMAL) {
+        const real T = p / rho, Tg = 2.0 * B->Tw - T;
+        grho = p / Tg;
+        for (int q = 0; q < 3; q++) {
+            const real dT = (dp[q] - T * drho[q]) / rho;
+            gdrho[q] = (dp[q] + grho * dT) / Tg; /* d(p / Tg) with dTg = -dT */
+        }
+    }
+    cons_of(gam, grho, gU, p, g);
+    const real u2 = gU[0] * gU[0] + gU[1] * gU[1] + gU[2] * gU[2];
+    for (int q = 0; q < 3; q++) {
+        real udu = 0.0;
+        for (int a = 0; a < 3; a++) udu += gU[a] * gdU[a][q];
+        gg[0][q] = gdrho[q];
+        for (int a = 0; a < 3; a++) gg[1 + a][q] = gU[a] * gdrho[q] + grho * gdU[a][q];
+        gg[4][q] = dp[q] / (gam - 1.0) + 0.5 * u2 * gdrho[q] + grho * udu;
+    }
+    for (int c = 0; c < 5; c++) gg[c][d] = -gg[c][d];
 }
 
 static void weno_cell(orc *o, const orc_params *P, const real *Q, int64_t i)
@@ -1066,12 +1263,12 @@ static void weno_cell(orc *o, const orc_params *P, const real *Q, int64_t i)
         real q0 = Qat(o, Q, comp, i);
         real rhs[MAXST];
         /* P_0: least squares on the big stencil */
-        for (int k = 0; k < C->K; k++) rhs[k] = member_value(o, Q, comp, C->st[k]) - q0;
+        for (int k = 0; k < C->K; k++) rhs[k] = member_value(o, P, Q, comp, C->st[k]) - q0;
         real *ac = a + 9 * comp;
         lsq_apply(&C->ls0, rhs, ac);
         /* P_m on the sub-stencils */
         for (int m = 0; m < M; m++) {
-            for (int k = 0; k < C->subn[m]; k++) rhs[k] = member_value(o, Q, comp, C->sub[m][k]) - q0;
+            for (int k = 0; k < C->subn[m]; k++) rhs[k] = member_value(o, P, Q, comp, C->sub[m][k]) - q0;
             lsq_apply(&C->ls[m], rhs, b + 24 * comp + 3 * m);
         }
         /* smoothness indicators over Omega_0, each multi-index once */
@@ -1596,7 +1793,7 @@ static int admissible_state(const orc *o, const orc_params *P, const real *Q, sr
     if (!physical_state(P, q)) return 0;
     if (P->fallback_floor > 0.0) {
         real v[5];
-        for (int c = 0; c < 5; c++) v[c] = member_value(o, Q, c, s);
+        member_state(o, P, Q, s, v);
         const real pav = (P->gamma - 1.0) * (v[4] - 0.5 * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0]);
         const real p = (P->gamma - 1.0) * (q[4] - 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0]);
         if (!(RE(q[0]) > P->fallback_floor * RE(v[0])) || !(RE(p) > P->fallback_floor * RE(pav))) return 0;
@@ -1605,13 +1802,12 @@ static int admissible_state(const orc *o, const orc_params *P, const real *Q, sr
 }
 
 /* first-order fallback of one side: the member's cell average in the local frame, zero slopes */
-static void fallback_state(const orc *o, const real *Q, sref s, const double n[3][3], real q[5], real dq[3][5])
+static void fallback_state(const orc *o, const orc_params *P, const real *Q, sref s, const double n[3][3], real q[5],
+                           real dq[3][5])
 {
     real v[5], g[5][3];
-    for (int c = 0; c < 5; c++) {
-        v[c] = member_value(o, Q, c, s);
-        g[c][0] = g[c][1] = g[c][2] = 0.0;
-    }
+    member_state(o, P, Q, s, v);
+    for (int c = 0; c < 5; c++) g[c][0] = g[c][1] = g[c][2] = 0.0;
     to_local(n, v, g, q, dq);
 }
 
@@ -1625,34 +1821,53 @@ static int face_flux_all(orc *o, const orc_params *P, const real *Q, double dt, 
     for (int64_t f = 0; f < o->n_faces; f++) {
         const oface *F = &o->f[f];
         real acc[10] = {0};
+        /* a wall face: its box plane, and whether its condition is other than the reflective one */
+        const sref *T = &F->nb;
+        int plane = -1;
+        if (F->nbr < 0)
+            for (int d = 0; d < 3; d++)
+                if (T->sg[d] < 0) plane = 2 * d + (T->of[d] == 2);
+        const int general = plane >= 0 && P->bc[plane].type != BC_SLIP;
         for (int k = 0; k < 4; k++) {
             real vl[5], gl[5][3], vr[5], gr[5][3];
             weno_eval(o, P, Q, F->owner, -1, F->gp[k], vl, gl);
-            /* the neighbour's polynomial as its image: P(T^-1 x), momentum signed by the reflections */
-            const sref *T = &F->nb;
-            double xr[3];
-            for (int q = 0; q < 3; q++) xr[q] = T->sg[q] * (F->gp[k][q] - T->of[q] * o->L[q]);
-            weno_eval(o, P, Q, T->cell, -1, xr, vr, gr);
-            for (int c = 0; c < 5; c++)
-                for (int q = 0; q < 3; q++) gr[c][q] *= T->sg[q];
-            for (int c = 0; c < 3; c++) {
-                vr[1 + c] *= T->sg[c];
-                for (int q = 0; q < 3; q++) gr[1 + c][q] *= T->sg[c];
-            }
             double n[3][3];
             local_frame(F->va[k], n);
             real ql[5], qr[5], dql[3][5], dqr[3][5];
             to_local(n, vl, gl, ql, dql);
-            to_local(n, vr, gr, qr, dqr);
-            if (P->fallback) {
-                if (!admissible_state(o, P, Q, sref_self(F->owner), ql)) {
-                    fallback_state(o, Q, sref_self(F->owner), n, ql, dql);
-                    nfb++;
+            if (!general) {
+                /* the neighbour's polynomial as its image: P(T^-1 x), momentum signed by the reflections */
+                double xr[3];
+                for (int q = 0; q < 3; q++) xr[q] = T->sg[q] * (F->gp[k][q] - T->of[q] * o->L[q]);
+                weno_eval(o, P, Q, T->cell, -1, xr, vr, gr);
+                for (int c = 0; c < 5; c++)
+                    for (int q = 0; q < 3; q++) gr[c][q] *= T->sg[q];
+                for (int c = 0; c < 3; c++) {
+                    vr[1 + c] *= T->sg[c];
+                    for (int q = 0; q < 3; q++) gr[1 + c][q] *= T->sg[c];
                 }
-                if (!admissible_state(o, P, Q, F->nb, qr)) {
-                    fallback_state(o, Q, F->nb, n, qr, dqr);
-                    nfb++;
+                to_local(n, vr, gr, qr, dqr);
+                if (P->fallback) {
+                    if (!admissible_state(o, P, Q, sref_self(F->owner), ql)) {
+                        fallback_state(o, P, Q, sref_self(F->owner), n, ql, dql);
+                        nfb++;
+                    }
+                    if (!admissible_state(o, P, Q, F->nb, qr)) {
+                        fallback_state(o, P, Q, F->nb, n, qr, dqr);
+                        nfb++;
+                    }
                 }
+            } else {
+                /* the state beyond the plane: its condition applied to the inner state (after the inner
+                   side's fallback, whose ghost then falls back too) */
+                if (P->fallback && !admissible_state(o, P, Q, sref_self(F->owner), ql)) {
+                    member_state(o, P, Q, sref_self(F->owner), vl);
+                    for (int c = 0; c < 5; c++) gl[c][0] = gl[c][1] = gl[c][2] = 0.0;
+                    to_local(n, vl, gl, ql, dql);
+                    nfb += 2;
+                }
+                bc_ghost_point(P, plane, vl, gl, vr, gr);
+                to_local(n, vr, gr, qr, dqr);
             }
             real Fb[10];
             const int e = orc_gp_flux(P, ql, &dql[0][0], qr, &dqr[0][0], dt, Fb, NULL);
@@ -1835,6 +2050,19 @@ void orc_face_gauss_raw(const double *quad, double *gp, double *va)
             gp[3 * k + q] = g[k][q];
             va[3 * k + q] = v[k][q];
         }
+}
+
+/* boundary condition of box plane `plane` applied to a cell average (g) and at a Gauss point on the
+   plane (gp, ggp [5][3]: the value and gradient beyond it from the inner v, gv [5][3]) */
+void orc_bc_ghost(const orc_params *P, int plane, const real *v, const real *gv, real *g, real *gp, real *ggp)
+{
+    real gvv[5][3], gg[5][3];
+    for (int c = 0; c < 5; c++)
+        for (int q = 0; q < 3; q++) gvv[c][q] = gv[3 * c + q];
+    bc_state(P, plane, v, g);
+    bc_ghost_point(P, plane, v, gvv, gp, gg);
+    for (int c = 0; c < 5; c++)
+        for (int q = 0; q < 3; q++) ggp[3 * c + q] = gg[c][q];
 }
 
 /* normalised Maxwellian moments <u^n> full / u>0 / u<0 (n < 14) and <varsigma^(2d)> (d < 6) */

@@ -67,8 +67,10 @@ struct DevMesh {
     const void *dsc;        // [nnz][3] scaled member centroid offsets, FP64 or FP32
     const void *ginv;       // [48][n] inverses of the sub-stencil normal matrices / h, FP64 or FP32
     const int32_t *st_cell; // [nnz] member cells (as in st_rec)
-    const uint8_t *st_flip; // [nnz] bit d: the member is the mirror image across a wall on axis d
-    int walls;              // the mesh has reflective walls (faces with nbr = -1 - axis)
+    const uint8_t *st_flip; // [nnz] bit d: the member is the mirror image across a wall on axis d (bit 3 + d:
+                            // the wall at L; bit 6: mirrored at both walls of an axis)
+    int walls;              // the mesh has walls (faces with nbr = -1 - plane, plane = 2 axis + hi)
+    int double_mirror;      // some member is mirrored at both walls of an axis
     // sub-stencil lists: the members of sub-stencil s of cell i are entries
     // ss_ptr[8 i + s] .. ss_ptr[8 i + s + 1], each the member's position in the cell's
     // stencil and B = G_s^{-1} D_k / h, so that b^s = sum B (Q_k - Q_0)
@@ -473,7 +475,7 @@ __device__ __forceinline__ void weno_combine_quad_b(const double a[9], const dou
 
 template <typename T>
 __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff,
-                                                          WenoParams wp)
+                                                          WenoParams wp, BoundarySet bcs)
 {
     __shared__ double sq[5][kK1Stage];
     __shared__ T sB[3][kK1SubStage];
@@ -505,8 +507,12 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
         for (int e = e0 + (int)threadIdx.x; e < e1; e += kK1Block) {
             const int x = m.st_cell[e];
             const unsigned fl = m.st_flip[e];
+            double v[5];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) sq[c][e - e0] = mirror_sign(fl, c) * Q[(size_t)c * n + x];
+            for (int c = 0; c < 5; ++c) v[c] = Q[(size_t)c * n + x];
+            if (fl & 7u) ghost_average(bcs, fl, v);  // a ghost: its planes' conditions
+#pragma unroll
+            for (int c = 0; c < 5; ++c) sq[c][e - e0] = v[c];
         }
         for (int e = s0 + (int)threadIdx.x; e < s1; e += kK1Block) {
             sl[e - s0] = m.ss_loc[e];
@@ -518,10 +524,19 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
     const T *pinv = (const T *)m.pinv;
     const double *Qc = Q + (size_t)comp * n;
     const double q0 = Qc[i];
-    // Q_k - Q_0 of stencil entry k, in FP64, then rounded to T
-    auto diff = [&](int k) -> T {
-        return (T)((staged ? sq[comp][k - e0] : mirror_sign(m.st_flip[k], comp) * Qc[m.st_cell[k]]) - q0);
+    // a member's average from memory (blocks too large to stage)
+    auto member = [&](int k) -> double {
+        const unsigned fl = m.st_flip[k];
+        const int x = m.st_cell[k];
+        if (!(fl & 7u)) return Qc[x];
+        double v[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) v[c] = Q[(size_t)c * n + x];
+        ghost_average(bcs, fl, v);
+        return v[comp];
     };
+    // Q_k - Q_0 of stencil entry k, in FP64, then rounded to T
+    auto diff = [&](int k) -> T { return (T)((staged ? sq[comp][k - e0] : member(k)) - q0); };
     T a[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = T(0);
@@ -613,10 +628,10 @@ k_flux(DevMesh m, const T *__restrict__ coeff, const double *__restrict__ Q, con
     }
     const T dt = (T)dt_dev[0];
     T out[10];
-    // nb < 0: a reflective wall, the right state is the mirror of the left one
+    // nb < 0: a wall on box plane -1 - nb, the right state is its condition's ghost of the left one
     int nfb = 0;
     const bool ok = face_gp<T, PR, EXT, SM>(coeff + (size_t)50 * o, nb >= 0 ? coeff + (size_t)50 * nb : nullptr, ql0,
-                                            qr0, geo, dt, fp, out, nfb);
+                                            qr0, geo, dt, fp, out, nfb, nb < 0 ? -1 - nb : 0);
     if (live && !ok) status[0] = 1;
     if (EXT && live && nfb) atomicAdd(status + 1, nfb);  // integer count: the same total in any order
 #pragma unroll
@@ -1434,7 +1449,28 @@ static FluxParams<T> flux_params(const gks_params *p)
     f.smooth = p->smooth_flux;
     f.mu_power = (T)p->mu_power;
     f.iT_ref = p->mu_power != 0.0 ? (T)(1.0 / p->T_ref) : T(1);
+    for (int b = 0; b < 6; ++b) {
+        f.bc_type[b] = p->bc[b].type;
+        f.bc_Tw[b] = (T)p->bc[b].Tw;
+        for (int q = 0; q < 3; ++q) f.bc_uw[b][q] = (T)p->bc[b].uw[q];
+        for (int q = 0; q < 5; ++q) f.bc_far[b][q] = (T)p->bc[b].far[q];
+    }
     return f;
+}
+
+static BoundarySet boundary_set(const gks_params *p)
+{
+    BoundarySet b;
+    b.gamma = p->gamma;
+    b.any_general = 0;
+    for (int k = 0; k < 6; ++k) {
+        b.type[k] = p->bc[k].type;
+        b.Tw[k] = p->bc[k].Tw;
+        for (int q = 0; q < 3; ++q) b.uw[k][q] = p->bc[k].uw[q];
+        for (int q = 0; q < 5; ++q) b.far[k][q] = p->bc[k].far[q];
+        if (b.type[k] != kBcSlip) b.any_general = 1;
+    }
+    return b;
 }
 
 }  // namespace gks
@@ -1672,6 +1708,9 @@ static size_t mesh_layout(const HostMesh &H, int precision, DevMesh *d, char *ba
     dm.walls = 0;
     for (int32_t b : H.nbr)
         if (b < 0) dm.walls = 1;
+    dm.double_mirror = 0;
+    for (uint8_t fl : H.st_flip)
+        if (fl & 64u) dm.double_mirror = 1;
     {
         // sub-stencil lists in slot order, members in stencil order
         int64_t nss = 0;
@@ -1835,6 +1874,23 @@ static gks_status check_params(const gks_mesh *m, const gks_params *p)
     if (p->viscous && !(p->mu >= 0.0)) return fail(GKS_EINVAL, "bad viscosity");
     if (!(p->Pr > 0.0)) return fail(GKS_EINVAL, "bad Prandtl number");
     if (!(p->dt_max >= 0.0) || !std::isfinite(p->dt_max)) return fail(GKS_EINVAL, "dt_max must be finite and >= 0");
+    bool general = false;
+    for (int k = 0; k < 6; ++k) {
+        const gks_boundary &b = p->bc[k];
+        if (b.type < GKS_BC_SLIP || b.type > GKS_BC_EXTRAPOLATE) return fail(GKS_EINVAL, "unknown boundary condition");
+        if (b.type != GKS_BC_SLIP) general = true;
+        if (b.type == GKS_BC_ISOTHERMAL && !(b.Tw > 0.0 && std::isfinite(b.Tw)))
+            return fail(GKS_EINVAL, "isothermal wall temperature must be finite and > 0");
+        if (b.type == GKS_BC_FARFIELD && !(b.far[0] > 0.0 && b.far[4] > 0.0 && std::isfinite(b.far[1]) &&
+                                           std::isfinite(b.far[2]) && std::isfinite(b.far[3])))
+            return fail(GKS_EINVAL, "far-field state needs rho > 0, p > 0 and a finite velocity");
+        if ((b.type == GKS_BC_NOSLIP || b.type == GKS_BC_ISOTHERMAL) &&
+            !(std::isfinite(b.uw[0]) && std::isfinite(b.uw[1]) && std::isfinite(b.uw[2])))
+            return fail(GKS_EINVAL, "wall velocity must be finite");
+    }
+    if (general && m->d.walls && m->d.double_mirror)
+        return fail(GKS_EINVAL, "a stencil of this mesh reaches across both walls of an axis: only the reflective "
+                                "condition is defined there");
     if (!(p->fallback_floor >= 0.0 && p->fallback_floor < 1.0)) return fail(GKS_EINVAL, "fallback_floor outside [0, 1)");
     if (!std::isfinite(p->mu_power) || (p->mu_power != 0.0 && !(p->T_ref > 0.0 && std::isfinite(p->T_ref))))
         return fail(GKS_EINVAL, "bad viscosity power law (mu_power, T_ref)");
@@ -1885,9 +1941,9 @@ static gks_status launch_reconstruct(gks_mesh *m, const double *Q, void *coeff, 
     const unsigned grid = grid_for((int64_t)kK1CellLanes * m->n, kK1Block);
     ProfScope ps(m, GKS_K_RECONSTRUCT, st);
     if (m->precision == GKS_FP64)
-        k_reconstruct<double><<<grid, kK1Block, 0, st>>>(m->d, Q, (double *)coeff, weno_params(p));
+        k_reconstruct<double><<<grid, kK1Block, 0, st>>>(m->d, Q, (double *)coeff, weno_params(p), boundary_set(p));
     else
-        k_reconstruct<float><<<grid, kK1Block, 0, st>>>(m->d, Q, (float *)coeff, weno_params(p));
+        k_reconstruct<float><<<grid, kK1Block, 0, st>>>(m->d, Q, (float *)coeff, weno_params(p), boundary_set(p));
     return hip_check(hipGetLastError(), "reconstruct launch");
 }
 

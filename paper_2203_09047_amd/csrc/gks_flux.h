@@ -18,6 +18,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "gks_bc.h"
+
 namespace gks {
 
 template <typename T>
@@ -28,6 +30,9 @@ struct FluxParams {
     int fallback;  // first-order fallback of non-physical side states
     int smooth;    // the smooth-flow distribution (Eq. flux-2) instead of Eq. flux-1
     double floor;  // ... and of states whose rho or p is at most floor times the cell average's
+    // the box planes' boundary conditions (meshes with walls; plane 2 axis + hi)
+    int bc_type[6];
+    T bc_uw[6][3], bc_Tw[6], bc_far[6][5];
 };
 
 // Moments <u^k> (k <= 6), <v^k>, <w^k> (k <= 5), <s^2>, <s^4> of one normalised Maxwellian.
@@ -558,6 +563,86 @@ __host__ __device__ __forceinline__ void wall_mirror(const T q[5], const T dq[3]
     }
 }
 
+// The state beyond box plane `plane` at a Gauss point on it, in the local frame whose n1 is the plane's
+// outward normal: its condition applied to the inner state (q, dq: value and derivatives along n1, n2,
+// n3), the derivatives along n1 negated (the mirror), the far field's ghost uniform.
+template <typename T>
+__host__ __device__ __forceinline__ void bc_gauss_point(const FluxParams<T> &fp, int plane, const T n[3][3], const T q[5],
+                                                        const T dq[3][5], T qr[5], T dqr[3][5])
+{
+    const int type = fp.bc_type[plane];
+    if (type == kBcSlip) {
+        wall_mirror(q, dq, qr, dqr);
+        return;
+    }
+    if (type == kBcExtrapolate) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            qr[j] = q[j];
+            dqr[0][j] = -dq[0][j];
+            dqr[1][j] = dq[1][j];
+            dqr[2][j] = dq[2][j];
+        }
+        return;
+    }
+    const T g1 = fp.gamma - T(1);
+    const T rho = q[0], ir = T(1) / rho;
+    const T U[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
+    const T u2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+    const T p = g1 * (q[4] - T(0.5) * rho * u2);
+    T rb, Ub[3];
+    if (type == kBcFarField) {
+        T Uf[3], pb;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            Uf[k] = fp.bc_far[plane][1] * n[k][0] + fp.bc_far[plane][2] * n[k][1] + fp.bc_far[plane][3] * n[k][2];
+        farfield_frame<T>(fp.gamma, rho, U, p, fp.bc_far[plane][0], Uf, fp.bc_far[plane][4], rb, Ub, pb);
+        qr[0] = rb;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) qr[1 + k] = rb * Ub[k];
+        qr[4] = pb / g1 + T(0.5) * rb * (Ub[0] * Ub[0] + Ub[1] * Ub[1] + Ub[2] * Ub[2]);
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int j = 0; j < 5; ++j) dqr[m][j] = T(0);
+        return;
+    }
+    // no-slip: the wall velocity in the local frame, U -> 2 u_w - U, p kept; rho kept (adiabatic) or
+    // rho -> p / (2 T_w - p / rho) (isothermal)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        Ub[k] = T(2) * (fp.bc_uw[plane][0] * n[k][0] + fp.bc_uw[plane][1] * n[k][1] + fp.bc_uw[plane][2] * n[k][2]) - U[k];
+    const bool iso = type == kBcIsothermal;
+    const T Tg = iso ? T(2) * fp.bc_Tw[plane] - p * ir : T(1);
+    rb = iso ? p / Tg : rho;
+    const T ub2 = Ub[0] * Ub[0] + Ub[1] * Ub[1] + Ub[2] * Ub[2];
+    qr[0] = rb;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) qr[1 + k] = rb * Ub[k];
+    qr[4] = p / g1 + T(0.5) * rb * ub2;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        // derivatives along n_m of the inner primitives, then of the ghost's
+        const T dr = dq[m][0];
+        T dU[3], udu = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            dU[k] = (dq[m][1 + k] - U[k] * dr) * ir;
+            udu += U[k] * dU[k];
+        }
+        const T dp = g1 * (dq[m][4] - T(0.5) * u2 * dr - rho * udu);
+        const T drb = iso ? (dp + rb * (dp - p * ir * dr) * ir) / Tg : dr;
+        T ubdu = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ubdu -= Ub[k] * dU[k];
+        const T s = m == 0 ? T(-1) : T(1);  // the mirror across the plane
+        dqr[m][0] = s * drb;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dqr[m][1 + k] = s * (Ub[k] * drb - rb * dU[k]);
+        dqr[m][4] = s * (dp / g1 + T(0.5) * ub2 * drb + rb * ubdu);
+    }
+}
+
 // With fp.fallback: a side state with rho <= 0 or p <= 0, or with rho or p at most fp.floor times
 // that of its cell's average qav (FP64, global frame), becomes qav in the local frame with zero
 // slopes.  Returns whether it did.
@@ -639,7 +724,7 @@ __host__ __device__ __forceinline__ bool face_gp_pre(LoadL load_l, LoadR load_r,
 template <typename T, bool PR, bool EXT, bool SM = false>
 __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, const T *__restrict__ cr_g, const double *ql0,
                                                  const double *qr0, const T geo[9], T dt, const FluxParams<T> &fp,
-                                                 T out[10], int &nfb)
+                                                 T out[10], int &nfb, int wall_plane = 0)
 {
     T n3[3][3];
     const T area = local_frame(geo[6], geo[7], geo[8], n3);
@@ -655,16 +740,19 @@ __host__ __device__ __forceinline__ bool face_gp(const T *__restrict__ cl_g, con
     }
     {
         T q[5], dq[3][5], cr[50];
-        if (!EXT || cr_g) {
+        if constexpr (!EXT) {
             load_cell(cr_g, cr);
             side_state(cr, qr0, geo[3], geo[4], geo[5], n3, q, dq);
-            if (EXT) nfb += fallback_side(fp, qr0, n3, q, dq);
+        } else if (cr_g) {
+            load_cell(cr_g, cr);
+            side_state(cr, qr0, geo[3], geo[4], geo[5], n3, q, dq);
+            nfb += fallback_side(fp, qr0, n3, q, dq);
         } else {
             T qi[5], dqi[3][5];
             load_cell(cl_g, cr);
             side_state(cr, ql0, geo[0], geo[1], geo[2], n3, qi, dqi);
-            nfb += fallback_side(fp, ql0, n3, qi, dqi);  // the mirror of a fallen-back side falls back too
-            wall_mirror(qi, dqi, q, dq);
+            nfb += fallback_side(fp, ql0, n3, qi, dqi);  // the ghost of a fallen-back side falls back too
+            bc_gauss_point(fp, wall_plane, n3, qi, dqi, q, dq);
         }
         ok = side_pass<T, PR, SM>(q, dq, T(-1), fp, A, 1) && ok;
     }

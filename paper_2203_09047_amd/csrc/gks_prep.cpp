@@ -615,7 +615,14 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
                     if (slot[m][e] == (int)k) mask |= (uint8_t)(1u << m);
             out.idx.push_back((int32_t)members[k].cell);  // external for now
             out.mask.push_back(mask);
-            out.flip.push_back((uint8_t)((members[k].sg[0] < 0) | (members[k].sg[1] < 0) << 1 | (members[k].sg[2] < 0) << 2));
+            // bit d: mirrored on axis d; bit 3 + d: at the plane x_d = L; bit 6: mirrored twice on an axis
+            // (at 0 and at L: a translation by 2L, which only the reflective condition leaves invariant)
+            unsigned fl = 0;
+            for (int d = 0; d < 3; ++d) {
+                if (members[k].sg[d] < 0) fl |= 1u << d | (members[k].of[d] == 2 ? 1u << (3 + d) : 0u);
+                else if (!periodic && (members[k].of[d] == 2 || members[k].of[d] == -2)) fl |= 1u << 6;
+            }
+            out.flip.push_back((uint8_t)fl);
             for (int j = 0; j < 9; ++j)
                 out.pinv.push_back((int)k < nls ? P0[(size_t)j * nls + k] : 0.0);
             for (int d = 0; d < 3; ++d) out.dsc.push_back(Ds[k][d]);
@@ -674,7 +681,7 @@ gks_status preprocess(int64_t n_nodes, const double *nodes, int64_t n_cells, con
         if (!wall)
             for (int d = 0; d < 3; ++d) img.of[d] = a_owns ? r.sh[d] : -r.sh[d];
         H.owner[fo] = (int32_t)inv[own.cell];
-        H.nbr[fo] = wall ? -1 - r.wall : (int32_t)inv[oth.cell];
+        H.nbr[fo] = wall ? -1 - (2 * r.wall + r.wall_hi) : (int32_t)inv[oth.cell];
         const int *sl = kFaceSlots[types[own.cell]][own.lf];
         double V[4][3];
         if (sl[3] >= 0) {

@@ -40,6 +40,20 @@ class GksError(RuntimeError):
         self.code = code
 
 
+BC_SLIP, BC_NOSLIP, BC_ISOTHERMAL, BC_FARFIELD, BC_EXTRAPOLATE = range(5)
+
+
+class Boundary(ctypes.Structure):
+    """gks_boundary: condition of one box plane (type, wall velocity, wall temperature, free stream)."""
+
+    _fields_ = [("type", ctypes.c_int), ("uw", ctypes.c_double * 3), ("Tw", ctypes.c_double),
+                ("far", ctypes.c_double * 5)]
+
+
+def boundary(type=BC_SLIP, uw=(0.0, 0.0, 0.0), Tw=1.0, far=(1.0, 0.0, 0.0, 0.0, 1.0)) -> Boundary:
+    return Boundary(int(type), (ctypes.c_double * 3)(*uw), float(Tw), (ctypes.c_double * 5)(*far))
+
+
 class Params(ctypes.Structure):
     _fields_ = [
         ("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("mu", ctypes.c_double), ("Pr", ctypes.c_double),
@@ -48,6 +62,7 @@ class Params(ctypes.Structure):
         ("precision", ctypes.c_int), ("force_linear", ctypes.c_int), ("dt_given", ctypes.c_int),
         ("first_order_fallback", ctypes.c_int), ("fallback_floor", ctypes.c_double), ("smooth_flux", ctypes.c_int),
         ("mu_power", ctypes.c_double), ("T_ref", ctypes.c_double), ("dt_max", ctypes.c_double),
+        ("bc", Boundary * 6),
     ]
 
 
@@ -154,8 +169,9 @@ def _dp(t):
 
 def params(precision=FP64, gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, viscous=False, weno_eps=1e-6, weno_gamma_m=0.0125,
            weno_p=1.0, tau_eps=0.01, tau_C=1.0, force_linear=False, dt_given=False, fallback=False,
-           fallback_floor=0.0, smooth=False, mu_power=0.0, T_ref=1.0) -> Params:
-    """mu_power != 0 (viscous): viscosity mu (T / T_ref)^mu_power at the interface temperature T = p / rho."""
+           fallback_floor=0.0, smooth=False, mu_power=0.0, T_ref=1.0, bc=None) -> Params:
+    """mu_power != 0 (viscous): viscosity mu (T / T_ref)^mu_power at the interface temperature T = p / rho.
+    bc: six Boundary records for the box planes x=0, x=L, y=0, y=L, z=0, z=L of a mesh with walls."""
     p = Params()
     load().gks_default_params(ctypes.byref(p))
     p.gamma, p.cfl, p.mu, p.Pr = gamma, cfl, mu, Pr
@@ -166,6 +182,9 @@ def params(precision=FP64, gamma=1.4, cfl=0.5, mu=0.0, Pr=1.0, viscous=False, we
     p.fallback_floor = float(fallback_floor)
     p.smooth_flux = int(smooth)
     p.mu_power, p.T_ref = float(mu_power), float(T_ref)
+    if bc is not None:
+        for k in range(6):
+            p.bc[k] = bc[k]
     return p
 
 

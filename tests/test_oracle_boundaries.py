@@ -1,0 +1,175 @@
+"""Pins of the oracle's boundary conditions on the box planes of meshes with walls.
+
+Every condition keeps Section 2's ghost-cell construction (the ghost is the mirror image of an
+interior cell, its flow variables set by the condition); the pins check what each condition fixes:
+wall values as the averages of inner and ghost states, the ghost gradient as the derivative of the
+mirrored condition field, a gas at rest staying at rest between no-slip walls at its own temperature,
+the Riemann invariants of the far field and its preservation of a uniform free stream, and the drag
+of a moving lid.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_09047_amd import inputs
+
+GAMMA = 1.4
+
+
+def cons(rho, U, p):
+    U = np.asarray(U, float)
+    return np.r_[rho, rho * U, p / (GAMMA - 1) + 0.5 * rho * U @ U]
+
+
+def prim(q):
+    rho = q[0]
+    U = q[1:4] / rho
+    return rho, U, (GAMMA - 1) * (q[4] - 0.5 * rho * U @ U)
+
+
+def _bcs(kind, **kw):
+    return [oracle.boundary(kind, **kw) for _ in range(6)]
+
+
+def test_wall_values_are_the_averages_of_inner_and_ghost_states():
+    rng = np.random.default_rng(1)
+    uw = np.array([0.3, -0.1, 0.2])
+    for _ in range(5):
+        rho, U, p = 0.8 + 0.4 * rng.random(), rng.standard_normal(3), 0.7 + 0.5 * rng.random()
+        v = cons(rho, U, p)
+        for plane in range(6):
+            d = plane // 2
+            uwp = uw.copy()
+            uwp[d] = 0.0  # a wall moves in its own plane
+            for kind, extra in ((oracle.BC_SLIP, {}), (oracle.BC_NOSLIP, dict(uw=tuple(uwp))),
+                                (oracle.BC_ISOTHERMAL, dict(uw=tuple(uwp), Tw=1.1)), (oracle.BC_EXTRAPOLATE, {})):
+                bc = [oracle.boundary() for _ in range(6)]
+                bc[plane] = oracle.boundary(kind, **extra)
+                g, gp, _ = oracle.bc_ghost(oracle.params(bc=bc), plane, v, np.zeros((5, 3)))
+                rg, Ug, pg = prim(g)
+                np.testing.assert_allclose(gp, g, rtol=1e-15)  # the same condition at a Gauss point
+                if kind == oracle.BC_SLIP:
+                    Um = U.copy()
+                    Um[d] = -U[d]
+                    np.testing.assert_allclose(Ug, Um, rtol=1e-14, atol=1e-15)
+                    assert rg == pytest.approx(rho, rel=1e-15) and pg == pytest.approx(p, rel=1e-13)
+                elif kind == oracle.BC_EXTRAPOLATE:
+                    np.testing.assert_array_equal(g, v)
+                else:
+                    np.testing.assert_allclose(0.5 * (U + Ug), uwp, atol=1e-14)
+                    assert pg == pytest.approx(p, rel=1e-13)
+                    if kind == oracle.BC_NOSLIP:
+                        assert rg == pytest.approx(rho, rel=1e-15)
+                    else:
+                        assert 0.5 * (p / rho + pg / rg) == pytest.approx(1.1, rel=1e-13)
+
+
+@pytest.mark.parametrize("kind", [oracle.BC_SLIP, oracle.BC_NOSLIP, oracle.BC_ISOTHERMAL, oracle.BC_EXTRAPOLATE])
+def test_ghost_gradient_is_the_derivative_of_the_mirrored_condition_field(kind):
+    """With a linear inner field Q(x) = v + G (x - x0) about a point x0 on the plane, the ghost field is
+    B(Q(M x)), M the mirror: its central differences at x0 along each axis equal the ghost gradient."""
+    rng = np.random.default_rng(2)
+    for plane in range(6):
+        d = plane // 2
+        uw = np.array([0.2, -0.3, 0.1])
+        uw[d] = 0.0
+        bc = [oracle.boundary() for _ in range(6)]
+        bc[plane] = oracle.boundary(kind, uw=tuple(uw), Tw=0.9)
+        prm = oracle.params(bc=bc)
+        v = cons(1.0 + 0.2 * rng.random(), 0.5 * rng.standard_normal(3), 0.8 + 0.2 * rng.random())
+        G = 0.3 * rng.standard_normal((5, 3))
+        _, gp, gg = oracle.bc_ghost(prm, plane, v, G)
+        h = 1e-5
+        for q in range(3):
+            def ghost_at(s):
+                x = np.zeros(3)
+                x[q] = s
+                mx = x.copy()
+                mx[d] = -mx[d]  # the mirror across the plane through x0 = 0
+                return oracle.bc_ghost(prm, plane, v + G @ mx, np.zeros((5, 3)))[0]
+
+            fd = (ghost_at(h) - ghost_at(-h)) / (2 * h)
+            np.testing.assert_allclose(gg[:, q], fd, rtol=1e-7, atol=1e-8 * np.abs(G).max())
+
+
+def test_far_field_riemann_invariants_and_limits():
+    rng = np.random.default_rng(3)
+    far = (1.0, 0.4, -0.2, 0.1, 1.0 / GAMMA)
+    bc = [oracle.boundary(oracle.BC_FARFIELD, far=far) for _ in range(6)]
+    prm = oracle.params(bc=bc)
+    cf = math.sqrt(GAMMA * far[4] / far[0])
+    for _ in range(4):
+        for plane in range(6):
+            d, sn = plane // 2, (1.0 if plane % 2 else -1.0)
+            rho, U, p = 0.9 + 0.2 * rng.random(), 0.3 * rng.standard_normal(3), 0.6 + 0.2 * rng.random()
+            g = oracle.bc_ghost(prm, plane, cons(rho, U, p), np.zeros((5, 3)))[0]
+            rb, Ub, pb = prim(g)
+            c, cb = math.sqrt(GAMMA * p / rho), math.sqrt(GAMMA * pb / rb)
+            un, unb, unf = sn * U[d], sn * Ub[d], sn * far[1 + d]
+            # subsonic: the outgoing invariant from the interior, the incoming one from the free stream
+            assert unb + 2 * cb / (GAMMA - 1) == pytest.approx(un + 2 * c / (GAMMA - 1), rel=1e-13)
+            assert unb - 2 * cb / (GAMMA - 1) == pytest.approx(unf - 2 * cf / (GAMMA - 1), rel=1e-13)
+            up = (p, rho, U) if unb > 0 else (far[4], far[0], np.array(far[1:4]))
+            assert pb / rb ** GAMMA == pytest.approx(up[0] / up[1] ** GAMMA, rel=1e-12)
+            t = [q for q in range(3) if q != d]
+            np.testing.assert_allclose(Ub[t], up[2][t], rtol=1e-14)
+    # supersonic outflow keeps the interior, supersonic inflow takes the free stream
+    fast = (1.0, 3.0, 0.0, 0.0, 1.0 / GAMMA)
+    prm2 = oracle.params(bc=[oracle.boundary(oracle.BC_FARFIELD, far=fast) for _ in range(6)])
+    v = cons(1.1, (3.2, 0.1, 0.0), 0.8)
+    np.testing.assert_array_equal(oracle.bc_ghost(prm2, 1, v, np.zeros((5, 3)))[0], v)
+    np.testing.assert_allclose(oracle.bc_ghost(prm2, 0, v, np.zeros((5, 3)))[0], cons(1.0, (3.0, 0, 0), 1 / GAMMA),
+                               rtol=1e-15)
+
+
+@pytest.mark.parametrize("kind", ["hex", "hybrid"])
+def test_uniform_free_stream_preserved_by_the_far_field(kind):
+    mesh = inputs.lattice(4, kind, periodic=False)
+    for rho, U, p in ((1.0, (0.3, -0.2, 0.1), 1 / GAMMA), (1.0, (2.0, 0.5, 0.0), 1 / GAMMA)):
+        far = (rho, *U, p)
+        o = oracle.Oracle(mesh, oracle.params(bc=_bcs(oracle.BC_FARFIELD, far=far)))
+        Q0 = inputs.cell_averages(mesh, inputs.uniform(rho, *U, p))
+        Q, _ = o.run(Q0, nsteps=3)
+        assert np.abs(Q - Q0).max() <= 1e-13 * np.abs(Q0).max()
+
+
+@pytest.mark.parametrize("kind", ["hex", "hybrid"])
+def test_gas_at_rest_stays_at_rest_between_no_slip_walls(kind):
+    """Adiabatic no-slip walls, and isothermal ones at the gas's own temperature, Navier-Stokes."""
+    mesh = inputs.lattice(4, kind, periodic=False)
+    rho, p = 1.2, 1.0
+    Q0 = inputs.cell_averages(mesh, inputs.uniform(rho, 0, 0, 0, p))
+    for bc in (_bcs(oracle.BC_NOSLIP), _bcs(oracle.BC_ISOTHERMAL, Tw=p / rho)):
+        o = oracle.Oracle(mesh, oracle.params(viscous=True, mu=1e-2, Pr=0.72, bc=bc))
+        Q, _ = o.run(Q0, nsteps=5)
+        assert np.abs(Q - Q0).max() <= 1e-13 * np.abs(Q0).max()
+
+
+def test_a_moving_lid_drags_the_gas():
+    """Lid-driven box (the paper's cavity): isothermal no-slip walls at the gas's temperature, the plane
+    y = L moving along x.  The gas gains x-momentum in the lid's direction, the cells next to the lid
+    most, and energy.  Mass is conserved exactly only by reflective walls: the no-slip ghosts' reversed
+    tangential velocity, and the isothermal ghosts' density where the gas's temperature departs from
+    the wall's, let a little mass through the walls (here 0.1 % over the first 8 steps of the
+    impulsively started lid; 2e-5 with adiabatic walls)."""
+    mesh = inputs.lattice(4, "hybrid", periodic=False)
+    rho, p, ul = 1.0, 1.0 / GAMMA, 0.3
+    bc = _bcs(oracle.BC_ISOTHERMAL, Tw=p / rho)
+    bc[3] = oracle.boundary(oracle.BC_ISOTHERMAL, uw=(ul, 0, 0), Tw=p / rho)
+    o = oracle.Oracle(mesh, oracle.params(viscous=True, mu=1e-2, Pr=0.72, bc=bc))
+    vol, xc, _, _ = o.cell_geometry()
+    Q0 = inputs.cell_averages(mesh, inputs.uniform(rho, 0, 0, 0, p))
+    Q, _ = o.run(Q0, nsteps=8)
+    mom = Q[1] * vol
+    assert mom.sum() > 0
+    top, bottom = xc[:, 1] > 0.75, xc[:, 1] < 0.25
+    assert (Q[1][top] / Q[0][top]).mean() > 10 * abs((Q[1][bottom] / Q[0][bottom]).mean())
+    assert abs(((Q - Q0)[0] * vol).sum()) < 3e-3 * (Q0[0] * vol).sum()
+    assert ((Q - Q0)[4] * vol).sum() > 0
+    bc = _bcs(oracle.BC_NOSLIP)
+    bc[3] = oracle.boundary(oracle.BC_NOSLIP, uw=(ul, 0, 0))
+    Qa, _ = oracle.Oracle(mesh, oracle.params(viscous=True, mu=1e-2, Pr=0.72, bc=bc)).run(Q0, nsteps=8)
+    assert (Qa[1] * vol).sum() > 0
+    assert abs(((Qa - Q0)[0] * vol).sum()) < 1e-4 * (Q0[0] * vol).sum()
