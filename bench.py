@@ -306,7 +306,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-n96", action="store_true", help="skip the N = 96 lattice (4.96 M cells)")
-    ap.add_argument("--n96-steps", type=int, default=20)
+    ap.add_argument("--n96-steps", type=int, default=20, help="timed steps of the N = 96 and cavity legs")
+    ap.add_argument("--no-cavity", action="store_true", help="skip the lid-driven cavity (walls) timing")
     ap.add_argument("--no-smooth", action="store_true", help="skip the smooth-flow flux (Eq. flux-2) comparison")
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit Jacobi step timing")
     ap.add_argument("--no-power-law", action="store_true", help="skip the power-law viscosity timing")
@@ -512,6 +513,44 @@ def main():
         res["implicit_jacobi_fp64"] = dict(
             value=n * nimp / (msi * 1e-3), unit="cell-steps/s", steps=nimp, ms_per_step=msi / nimp, kmax=3,
             dt_factor=10.0, kernels=kernel_table(profi))
+    if not args.no_cavity:
+        # the paper's lid-driven cavity (Mach 0.15, Re = 1000, isothermal no-slip walls, the lid y = 1) on the
+        # walled hybrid lattice of the unit box at the same N, FP64, events off
+        t = time.perf_counter()
+        meshc = inputs.lattice(args.N, "hybrid", periodic=False)
+        p0 = 1.0 / 1.4
+        Qc = inputs.cell_averages(meshc, inputs.uniform(1.0, 0.0, 0.0, 0.0, p0))
+        hostc = gks.HostMesh(meshc)
+        bc = [gks.boundary(gks.BC_ISOTHERMAL, Tw=p0) for _ in range(6)]
+        bc[3] = gks.boundary(gks.BC_ISOTHERMAL, uw=(0.15, 0.0, 0.0), Tw=p0)
+        prm = gks.params(viscous=True, mu=0.15 / 1000.0, Pr=0.72, cfl=args.cfl, bc=bc)
+        solc = gks.Solver(hostc, prm)
+        Qd = solc.upload(hostc.to_internal(Qc))
+        for _ in range(args.warmup):
+            solc.step(Qd)
+        solc.poll()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(solc.stream)
+        for _ in range(args.n96_steps):
+            solc.step(Qd)
+        e1.record(solc.stream)
+        torch.cuda.synchronize()
+        msc = e0.elapsed_time(e1)
+        solc.profile(True)
+        for _ in range(args.prof_steps):
+            solc.step(Qd)
+        profc = solc.profile_read()
+        solc.profile(False)
+        solc.poll()
+        qc = Qd.cpu().numpy()
+        res["lid_driven_cavity_fp64"] = dict(
+            value=hostc.n * args.n96_steps / (msc * 1e-3), ms_per_step=msc / args.n96_steps, cells=hostc.n,
+            steps=args.n96_steps, state_after_timed_steps=state_summary(qc),
+            max_speed=float(np.sqrt((qc[1:4] ** 2).sum(axis=0)).max() / qc[0].min()), kernels=kernel_table(profc))
+        log(f"cavity: {msc:.2f} ms ({time.perf_counter() - t:.1f} s)")
+        del solc, hostc, Qd
+        torch.cuda.empty_cache()
     if not args.no_n96:
         # the workload's larger lattice: FP64 and FP32-mixed, events off
         t = time.perf_counter()
