@@ -10,6 +10,7 @@ LIB = os.path.join(HERE, "libgks.so")
 SOURCES = [os.path.join(HERE, "csrc", "gks_device.hip"), os.path.join(HERE, "csrc", "gks_prep.cpp")]
 DEPS = SOURCES + [os.path.join(HERE, "csrc", "gks_flux.h"), os.path.join(HERE, "csrc", "gks_internal.h"),
                   os.path.join(HERE, "csrc", "gks_flux_adj.h"), os.path.join(HERE, "csrc", "gks_opcount.h"),
+                  os.path.join(HERE, "csrc", "gks_bc.h"), os.path.join(HERE, "csrc", "gks_weno.h"),
                   os.path.join(ROOT, "include", "gks.h")]
 
 HIPCC_FLAGS = [

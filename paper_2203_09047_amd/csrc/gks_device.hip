@@ -473,7 +473,9 @@ __device__ __forceinline__ void weno_combine_quad_b(const double a[9], const dou
     ab[8] += 2.0 * Hb[2][2] + 8.0 * g2 * a[8];
 }
 
-template <typename T>
+// GEN: some plane of a mesh with walls has a condition other than the reflective one (a separate
+// instantiation keeps the periodic and reflective-wall kernel free of the conditions' code)
+template <typename T, bool GEN>
 __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff,
                                                           WenoParams wp, BoundarySet bcs)
 {
@@ -507,12 +509,17 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
         for (int e = e0 + (int)threadIdx.x; e < e1; e += kK1Block) {
             const int x = m.st_cell[e];
             const unsigned fl = m.st_flip[e];
-            double v[5];
+            if constexpr (GEN) {
+                double v[5];
 #pragma unroll
-            for (int c = 0; c < 5; ++c) v[c] = Q[(size_t)c * n + x];
-            if (fl & 7u) ghost_average(bcs, fl, v);  // a ghost: its planes' conditions
+                for (int c = 0; c < 5; ++c) v[c] = Q[(size_t)c * n + x];
+                if (fl & 7u) ghost_average(bcs, fl, v);  // a ghost: its planes' conditions
 #pragma unroll
-            for (int c = 0; c < 5; ++c) sq[c][e - e0] = v[c];
+                for (int c = 0; c < 5; ++c) sq[c][e - e0] = v[c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) sq[c][e - e0] = mirror_sign(fl, c) * Q[(size_t)c * n + x];
+            }
         }
         for (int e = s0 + (int)threadIdx.x; e < s1; e += kK1Block) {
             sl[e - s0] = m.ss_loc[e];
@@ -528,12 +535,16 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
     auto member = [&](int k) -> double {
         const unsigned fl = m.st_flip[k];
         const int x = m.st_cell[k];
-        if (!(fl & 7u)) return Qc[x];
-        double v[5];
+        if constexpr (GEN) {
+            if (!(fl & 7u)) return Qc[x];
+            double v[5];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) v[c] = Q[(size_t)c * n + x];
-        ghost_average(bcs, fl, v);
-        return v[comp];
+            for (int c = 0; c < 5; ++c) v[c] = Q[(size_t)c * n + x];
+            ghost_average(bcs, fl, v);
+            return v[comp];
+        } else {
+            return mirror_sign(fl, comp) * Qc[x];
+        }
     };
     // Q_k - Q_0 of stencil entry k, in FP64, then rounded to T
     auto diff = [&](int k) -> T { return (T)((staged ? sq[comp][k - e0] : member(k)) - q0); };
@@ -1940,10 +1951,19 @@ static gks_status launch_reconstruct(gks_mesh *m, const double *Q, void *coeff, 
 {
     const unsigned grid = grid_for((int64_t)kK1CellLanes * m->n, kK1Block);
     ProfScope ps(m, GKS_K_RECONSTRUCT, st);
-    if (m->precision == GKS_FP64)
-        k_reconstruct<double><<<grid, kK1Block, 0, st>>>(m->d, Q, (double *)coeff, weno_params(p), boundary_set(p));
-    else
-        k_reconstruct<float><<<grid, kK1Block, 0, st>>>(m->d, Q, (float *)coeff, weno_params(p), boundary_set(p));
+    const BoundarySet bcs = boundary_set(p);
+    const bool gen = m->d.walls && bcs.any_general;
+    if (m->precision == GKS_FP64) {
+        if (gen)
+            k_reconstruct<double, true><<<grid, kK1Block, 0, st>>>(m->d, Q, (double *)coeff, weno_params(p), bcs);
+        else
+            k_reconstruct<double, false><<<grid, kK1Block, 0, st>>>(m->d, Q, (double *)coeff, weno_params(p), bcs);
+    } else {
+        if (gen)
+            k_reconstruct<float, true><<<grid, kK1Block, 0, st>>>(m->d, Q, (float *)coeff, weno_params(p), bcs);
+        else
+            k_reconstruct<float, false><<<grid, kK1Block, 0, st>>>(m->d, Q, (float *)coeff, weno_params(p), bcs);
+    }
     return hip_check(hipGetLastError(), "reconstruct launch");
 }
 
