@@ -219,15 +219,16 @@ __device__ __forceinline__ double mirror_sign(unsigned flip, int c)
 
 constexpr int kK1Lanes = 4;
 constexpr int kK1CellLanes = 5 * kK1Lanes;
-// 12 cells = 240 lanes = 4 waves (the last one 48 lanes) and 27.5 KB of LDS per block, so five
-// blocks fill a CU at 5 waves/SIMD; blocks of 16 cells (5 waves, 4 per CU) leave more of the CU
-// waiting at the staging barrier and measure 19% slower (8 cells: 8% slower).
+// 12 cells = 240 lanes = 4 waves (the last one 48 lanes).  The forward reconstruction stages
+// 51.9 KB per block (FP64; three blocks per CU), its reverse 27.5 KB (five blocks per CU);
+// blocks of 16 cells leave more of the CU waiting at the staging barrier and measured 19%
+// slower (8 cells: 8% slower).
 constexpr int kK1Cells = 12;
 constexpr int kK1Block = kK1Cells * kK1CellLanes;
-// Staged in LDS per block (the cells' stencil and sub-stencil ranges are
-// contiguous): the members' cell averages and the sub-stencil lists, 26 members and
-// 50 sub-stencil entries per cell on average.  A block whose ranges are longer reads
-// them from global memory instead.
+// Staged in LDS per block (the cells' stencil and sub-stencil ranges are contiguous): the
+// members' cell averages, pseudo-inverse rows (forward kernel) and sub-stencil lists, up to 26
+// members and 50 sub-stencil entries per cell on average (the hybrid lattices' largest blocks
+// hold 312 and 576).  A block whose ranges are longer reads them from global memory instead.
 constexpr int kK1Stage = 26 * kK1Cells;
 constexpr int kK1SubStage = 50 * kK1Cells;
 
@@ -473,15 +474,34 @@ __device__ __forceinline__ void weno_combine_quad_b(const double a[9], const dou
     ab[8] += 2.0 * Hb[2][2] + 8.0 * g2 * a[8];
 }
 
+// 16-byte windows of the per-member and per-entry arrays that one block stages: a window of
+// bytes [b0, b1) is copied from its 16-byte aligned start; the at most 15 bytes read beyond b1
+// lie in the array's padding or the next array of the mesh arena.  Every lane copies a whole
+// number of rows (the buffers hold kIter * kK1Block rows, those past a window's end repeat its
+// last row), so the copies need no branch into which the compiler could sink their loads.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+template <typename T>
+struct K1Windows {
+    static constexpr int kP = (kK1Stage * 9 * (int)sizeof(T) + 30) / 16;     // pseudo-inverse rows
+    static constexpr int kB = (kK1SubStage * 3 * (int)sizeof(T) + 30) / 16;  // sub-stencil B rows
+    static constexpr int kL = (kK1SubStage + 6) / 4;                          // sub-stencil member bytes, 4 B words
+    static constexpr int kPIter = (kP + kK1Block - 1) / kK1Block;
+    static constexpr int kBIter = (kB + kK1Block - 1) / kK1Block;
+    static constexpr int kLIter = (kL + kK1Block - 1) / kK1Block;
+    static constexpr int kEIter = (kK1Stage + kK1Block - 1) / kK1Block;
+};
+
 // GEN: some plane of a mesh with walls has a condition other than the reflective one (a separate
 // instantiation keeps the periodic and reflective-wall kernel free of the conditions' code)
 template <typename T, bool GEN>
-__global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff,
-                                                          WenoParams wp, BoundarySet bcs)
+__global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3)))
+k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff, WenoParams wp, BoundarySet bcs)
 {
-    __shared__ double sq[5][kK1Stage];
-    __shared__ T sB[3][kK1SubStage];
-    __shared__ unsigned char sl[kK1SubStage];
+    using W = K1Windows<T>;
+    __shared__ double sq[5][kK1Stage + 1];  // the last column takes the stores of lanes past the range
+    __shared__ u32x4 sP[W::kPIter * kK1Block];
+    __shared__ u32x4 sBw[W::kBIter * kK1Block];
+    __shared__ unsigned sLw[W::kLIter * kK1Block];
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int t = blk * kK1Block + threadIdx.x;
     const int n = m.n;
@@ -495,8 +515,10 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
     const int cb0 = blk * kK1Cells, cb1 = min(cb0 + kK1Cells, n);
     const int e0 = m.st_ptr[cb0], e1 = m.st_ptr[cb1];
     const int s0 = m.ss_ptr[8 * cb0], s1 = m.ss_ptr[8 * cb1];
-    const bool staged = e1 - e0 <= kK1Stage && s1 - s0 <= kK1SubStage;  // uniform over the block
-    // the lane's own ranges, loaded before the staging so that no load after it waits on them
+    // uniform over the block; non-empty windows keep the clamped row indices below in range
+    const bool staged = e1 > e0 && s1 > s0 && e1 - e0 <= kK1Stage && s1 - s0 <= kK1SubStage;
+    // the lane's own ranges and cell data, loaded before the staging so that no load after it
+    // waits on them
     const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
     int pr[2][2];
 #pragma unroll
@@ -504,33 +526,83 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
         pr[h][0] = m.ss_ptr[8 * i + l + 4 * h];
         pr[h][1] = m.ss_ptr[8 * i + l + 4 * h + 1];
     }
+    const double *Qc = Q + (size_t)comp * n;
+    const double q0 = Qc[i];
+    const T S[6] = {(T)m.m2[i], (T)m.m2[n + i], (T)m.m2[2 * n + i], (T)m.m2[3 * n + i], (T)m.m2[4 * n + i],
+                    (T)m.m2[5 * n + i]};
+    const int Mi = m.M[i];
+    const T v23i = (T)m.vol23[i];
+    const T *pinv = (const T *)m.pinv;
+    // byte offsets of the block's rows inside the staged windows
+    const size_t pA = (sizeof(T) * 9 * (size_t)e0) & ~(size_t)15;
+    const size_t bA = (sizeof(T) * 3 * (size_t)s0) & ~(size_t)15;
+    const int lA = s0 & ~3;
     if (staged) {
-        // one round of independent loads for the whole block
-        for (int e = e0 + (int)threadIdx.x; e < e1; e += kK1Block) {
-            const int x = m.st_cell[e];
-            const unsigned fl = m.st_flip[e];
+        // one round of independent loads for the whole block: the member indices and flips, and
+        // the pseudo-inverse, B and member-byte windows as 16-byte (4-byte) rows; then the
+        // members' averages, which need the indices
+        const int pC = (int)((sizeof(T) * 9 * (size_t)e1 - pA + 15) >> 4);
+        const int bC = (int)((sizeof(T) * 3 * (size_t)s1 - bA + 15) >> 4);
+        const int lC = (s1 - lA + 3) >> 2;
+        const char *pinv_b = (const char *)m.pinv + pA;
+        const char *B_b = (const char *)m.ss_B + bA;
+        const unsigned *L_w = (const unsigned *)(m.ss_loc + lA);
+        int cx[W::kEIter];
+        unsigned cf[W::kEIter];
+        u32x4 rp[W::kPIter], rb[W::kBIter];
+        unsigned rl[W::kLIter];
+#pragma unroll
+        for (int r = 0; r < W::kEIter; ++r) {
+            const int e = min(e0 + (int)threadIdx.x + r * kK1Block, e1 - 1);
+            cx[r] = m.st_cell[e];
+            cf[r] = m.st_flip[e];
+        }
+#pragma unroll
+        for (int r = 0; r < W::kPIter; ++r) {
+            const int c = min((int)threadIdx.x + r * kK1Block, pC - 1);
+            rp[r] = *(const u32x4 *)(pinv_b + 16 * (size_t)c);
+        }
+#pragma unroll
+        for (int r = 0; r < W::kBIter; ++r) {
+            const int c = min((int)threadIdx.x + r * kK1Block, bC - 1);
+            rb[r] = *(const u32x4 *)(B_b + 16 * (size_t)c);
+        }
+#pragma unroll
+        for (int r = 0; r < W::kLIter; ++r) {
+            const int c = min((int)threadIdx.x + r * kK1Block, lC - 1);
+            rl[r] = L_w[c];
+        }
+        double v[W::kEIter][5];
+#pragma unroll
+        for (int r = 0; r < W::kEIter; ++r)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) v[r][c] = Q[(size_t)c * n + cx[r]];
+#pragma unroll
+        for (int r = 0; r < W::kPIter; ++r) sP[(int)threadIdx.x + r * kK1Block] = rp[r];
+#pragma unroll
+        for (int r = 0; r < W::kBIter; ++r) sBw[(int)threadIdx.x + r * kK1Block] = rb[r];
+#pragma unroll
+        for (int r = 0; r < W::kLIter; ++r) sLw[(int)threadIdx.x + r * kK1Block] = rl[r];
+#pragma unroll
+        for (int r = 0; r < W::kEIter; ++r) {
+            const int e = (int)threadIdx.x + r * kK1Block;
+            const int ew = e0 + e < e1 ? e : kK1Stage;
+            const unsigned fl = cf[r];
             if constexpr (GEN) {
-                double v[5];
+                if (fl & 7u) ghost_average(bcs, fl, v[r]);  // a ghost: its planes' conditions
 #pragma unroll
-                for (int c = 0; c < 5; ++c) v[c] = Q[(size_t)c * n + x];
-                if (fl & 7u) ghost_average(bcs, fl, v);  // a ghost: its planes' conditions
-#pragma unroll
-                for (int c = 0; c < 5; ++c) sq[c][e - e0] = v[c];
+                for (int c = 0; c < 5; ++c) sq[c][ew] = v[r][c];
             } else {
 #pragma unroll
-                for (int c = 0; c < 5; ++c) sq[c][e - e0] = mirror_sign(fl, c) * Q[(size_t)c * n + x];
+                for (int c = 0; c < 5; ++c) sq[c][ew] = mirror_sign(fl, c) * v[r][c];
             }
-        }
-        for (int e = s0 + (int)threadIdx.x; e < s1; e += kK1Block) {
-            sl[e - s0] = m.ss_loc[e];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) sB[j][e - s0] = B[(size_t)3 * e + j];
         }
         __syncthreads();
     }
-    const T *pinv = (const T *)m.pinv;
-    const double *Qc = Q + (size_t)comp * n;
-    const double q0 = Qc[i];
+    // the staged rows, indexed by member and sub-stencil entry
+    const T *sPinv = (const T *)((const char *)sP + (sizeof(T) * 9 * (size_t)e0 - pA));
+    const T *sB = (const T *)((const char *)sBw + (sizeof(T) * 3 * (size_t)s0 - bA));
+    const unsigned char *sl = (const unsigned char *)sLw + (s0 - lA);
     // a member's average from memory (blocks too large to stage)
     auto member = [&](int k) -> double {
         const unsigned fl = m.st_flip[k];
@@ -551,11 +623,21 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
     T a[9];
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = T(0);
+    if (staged) {
 #pragma unroll 2
-    for (int k = k0 + l; k < k1; k += kK1Lanes) {
-        const T d = diff(k);
+        for (int k = k0 + l; k < k1; k += kK1Lanes) {
+            const T d = diff(k);
+            const T *row = sPinv + 9 * (k - e0);
 #pragma unroll
-        for (int j = 0; j < 9; ++j) a[j] += pinv[(size_t)9 * k + j] * d;
+            for (int j = 0; j < 9; ++j) a[j] += row[j] * d;
+        }
+    } else {
+#pragma unroll 2
+        for (int k = k0 + l; k < k1; k += kK1Lanes) {
+            const T d = diff(k);
+#pragma unroll
+            for (int j = 0; j < 9; ++j) a[j] += pinv[(size_t)9 * k + j] * d;
+        }
     }
 #pragma unroll
     for (int j = 0; j < 9; ++j) a[j] = quad_sum(a[j]);
@@ -568,9 +650,9 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
         if (staged) {
             for (int e = p0 - s0; e < p1 - s0; ++e) {
                 const T d = diff(k0 + sl[e]);
-                bs[h][0] += sB[0][e] * d;
-                bs[h][1] += sB[1][e] * d;
-                bs[h][2] += sB[2][e] * d;
+                bs[h][0] += sB[3 * e] * d;
+                bs[h][1] += sB[3 * e + 1] * d;
+                bs[h][2] += sB[3 * e + 2] * d;
             }
         } else {
             for (int e = p0; e < p1; ++e) {
@@ -581,10 +663,8 @@ __global__ void __launch_bounds__(kK1Block) k_reconstruct(DevMesh m, const doubl
             }
         }
     }
-    const T S[6] = {(T)m.m2[i], (T)m.m2[n + i], (T)m.m2[2 * n + i], (T)m.m2[3 * n + i], (T)m.m2[4 * n + i],
-                    (T)m.m2[5 * n + i]};
     T c[10];
-    weno_combine_quad<T>(a, bs, l, m.M[i], (T)m.vol23[i], S, q0, sizeof(T) == 8, wp, c);
+    weno_combine_quad<T>(a, bs, l, Mi, v23i, S, q0, sizeof(T) == 8, wp, c);
     // lane l writes entries l, l + 4 and (lanes 0, 1) l + 8 of this component
     T v0 = c[0], v1 = c[4], v2 = c[8];
 #pragma unroll

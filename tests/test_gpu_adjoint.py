@@ -218,6 +218,22 @@ def test_adjoint_with_coefficient_tape_is_identical(gks):
     assert np.array_equal(a, b)
 
 
+def test_store_all_rollout_gradient_is_identical_to_the_checkpointed_one(gks):
+    """Keeping every step in the forward pass replaces the segment recomputation bit for bit (the
+    recomputation takes the forward pass's frozen step sizes, so it rebuilds the same states)."""
+    import torch
+
+    from paper_2203_09047_amd.adjoint import kinetic_energy_gradient
+
+    mesh, Q0, host, sol = _setup(gks, "hybrid", 5, viscous=True)
+    Qn = host.to_internal(Q0)
+    J1, g1 = kinetic_energy_gradient(sol, sol.upload(Qn), 7, ckpt_every=3)
+    J2, g2 = kinetic_energy_gradient(sol, sol.upload(Qn), 7, ckpt_every=3, store_all=True)
+    torch.cuda.synchronize()
+    assert float(J1) == float(J2)
+    assert torch.equal(g1, g2)
+
+
 @pytest.mark.slow
 def test_config4_kinetic_energy_gradient_at_step_100(gks):
     """N = 32 hybrid lattice, Euler, density wave plus the seeded low-pass velocity perturbation; the
