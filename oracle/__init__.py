@@ -103,6 +103,13 @@ def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
+def _failure(what, code):
+    """The error of a failed operator call; code 7 is a call on an oracle built for some cells only."""
+    if code == 7:
+        return OracleError(_load().orc_last_error().decode())
+    return OracleError(f"{what} (code {code})")
+
+
 OP_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 
@@ -121,6 +128,8 @@ def _load():
         pp = ctypes.POINTER(Params)
         lib.orc_create.argtypes = [i64, vp, i64, vp, vp, vp, i32, i32]
         lib.orc_create.restype = vp
+        lib.orc_create_cells.argtypes = [i64, vp, i64, vp, vp, vp, i32, i32, vp]
+        lib.orc_create_cells.restype = vp
         lib.orc_destroy.argtypes = [vp]
         lib.orc_last_error.restype = ctypes.c_char_p
         lib.orc_n_faces.argtypes = [vp]
@@ -129,7 +138,9 @@ def _load():
         lib.orc_face_info.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         lib.orc_stencil_info.argtypes = [vp, i64, vp, vp, vp]
         lib.orc_weno_eval.argtypes = [vp, pp, vp, i64, i32, vp, vp, vp]
+        lib.orc_weno_eval.restype = i32
         lib.orc_weno_weights.argtypes = [vp, pp, vp, i64, vp]
+        lib.orc_weno_weights.restype = i32
         lib.orc_gp_flux.argtypes = [pp, vp, vp, vp, vp, dbl, vp, vp]
         lib.orc_gp_flux.restype = i32
         lib.orc_face_flux.argtypes = [vp, pp, vp, dbl, vp]
@@ -224,8 +235,10 @@ class OracleError(RuntimeError):
 class Oracle:
     """Reference solver on one mesh (mesh records as produced by the input generators)."""
 
-    def __init__(self, mesh, prm: Params | None = None, min_big: int = 0):
-        """min_big > 0 grows big stencils with fewer members like ill-posed fits (0: the paper's set)."""
+    def __init__(self, mesh, prm: Params | None = None, min_big: int = 0, cells=None):
+        """min_big > 0 grows big stencils with fewer members like ill-posed fits (0: the paper's set).
+        cells (optional): build the stencils of these cells only (their reconstructions can then be
+        evaluated; residuals and steps are refused)."""
         lib = _load()
         self.mesh = mesh
         self.n = mesh.n_cells
@@ -234,8 +247,12 @@ class Oracle:
         self._types = np.ascontiguousarray(mesh.types, np.int8)
         self._cells = np.ascontiguousarray(mesh.cells, np.int64)
         box = np.asarray(mesh.box, np.float64)
-        h = lib.orc_create(self._nodes.shape[0], _p(self._nodes), self.n, _p(self._types), _p(self._cells), _p(box),
-                           int(mesh.periodic), int(min_big))
+        want = None
+        if cells is not None:
+            want = np.zeros(self.n, np.uint8)
+            want[np.asarray(cells, np.int64)] = 1
+        h = lib.orc_create_cells(self._nodes.shape[0], _p(self._nodes), self.n, _p(self._types), _p(self._cells),
+                                 _p(box), int(mesh.periodic), int(min_big), None if want is None else _p(want))
         if not h:
             raise OracleError(lib.orc_last_error().decode())
         self.h = h
@@ -314,13 +331,17 @@ class Oracle:
         x = np.ascontiguousarray(x, np.float64)
         val = np.zeros(5)
         grad = np.zeros((5, 3))
-        _load().orc_weno_eval(self.h, ctypes.byref(self.P), _p(Q), c, m, _p(x), _p(val), _p(grad))
+        lib = _load()
+        if lib.orc_weno_eval(self.h, ctypes.byref(self.P), _p(Q), c, m, _p(x), _p(val), _p(grad)):
+            raise OracleError(lib.orc_last_error().decode())
         return val, grad
 
     def weno_weights(self, Q, c):
         Q = np.ascontiguousarray(Q, np.float64)
         w = np.zeros((5, 9))
-        _load().orc_weno_weights(self.h, ctypes.byref(self.P), _p(Q), c, _p(w))
+        lib = _load()
+        if lib.orc_weno_weights(self.h, ctypes.byref(self.P), _p(Q), c, _p(w)):
+            raise OracleError(lib.orc_last_error().decode())
         return w
 
     # operators ----------------------------------------------------------
@@ -330,7 +351,7 @@ class Oracle:
         out = np.zeros((self.n_faces, 10))
         e = _load().orc_face_flux(self.h, ctypes.byref(self.P), _p(Q), dt, _p(out))
         if e:
-            raise OracleError(f"non-physical state in flux (code {e})")
+            raise _failure("non-physical state in flux", e)
         return out
 
     def residual(self, Q, dt):
@@ -339,7 +360,7 @@ class Oracle:
         D = np.zeros((5, self.n))
         e = _load().orc_residual(self.h, ctypes.byref(self.P), _p(Q), dt, _p(L), _p(D))
         if e:
-            raise OracleError(f"non-physical state in flux (code {e})")
+            raise _failure("non-physical state in flux", e)
         return L, D
 
     def timestep(self, Q):
@@ -350,7 +371,7 @@ class Oracle:
         Q = np.array(Q, np.float64, copy=True, order="C")
         e = _load().orc_step(self.h, ctypes.byref(self.P), _p(Q), dt)
         if e:
-            raise OracleError(f"step failed (code {e})")
+            raise _failure("step failed", e)
         return Q
 
     def run(self, Q, nsteps=0, t_end=0.0, dt_fixed=0.0):
@@ -363,7 +384,7 @@ class Oracle:
         e = _load().orc_run(self.h, ctypes.byref(self.P), _p(Q), nsteps, t_end, dt_fixed, _p(dts), ctypes.byref(k),
                             ctypes.byref(t))
         if e:
-            raise OracleError(f"run failed (code {e})")
+            raise _failure("run failed", e)
         return Q, dts[:k.value].copy()
 
 

@@ -253,6 +253,9 @@ typedef struct {
     /* option: a big stencil with fewer members than this is grown like an
      * ill-posed fit (0: the paper's neighbours-of-neighbours set as it is) */
     int min_big;
+    /* stencils built for a subset of the cells only: per-cell reconstructions of those cells,
+       no residual or step */
+    int partial;
 } orc;
 
 static char g_err[256];
@@ -779,11 +782,13 @@ static void face_gauss(const double Xq[4][3], double gp[4][3], double va[4][3])
 
 void orc_destroy(orc *o);
 
-orc *orc_create(int64_t n_nodes, const double *nodes, int64_t n_cells, const int8_t *types, const int64_t *cells,
-                const double *box, int periodic, int min_big)
+/* want (optional): build the stencils and fits of the cells with want[c] != 0 only */
+orc *orc_create_cells(int64_t n_nodes, const double *nodes, int64_t n_cells, const int8_t *types, const int64_t *cells,
+                      const double *box, int periodic, int min_big, const unsigned char *want)
 {
     orc *o = calloc(1, sizeof(orc));
     o->min_big = min_big;
+    o->partial = want != NULL;
     o->n_nodes = n_nodes;
     o->n_cells = n_cells;
     o->periodic = periodic;
@@ -950,6 +955,7 @@ orc *orc_create(int64_t n_nodes, const double *nodes, int64_t n_cells, const int
     int bad_code = 0;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t c = 0; c < n_cells; c++) {
+        if (want && !want[c]) continue;
         int e = build_stencils(o, c);
         if (e) {
 #pragma omp critical
@@ -970,6 +976,22 @@ orc *orc_create(int64_t n_nodes, const double *nodes, int64_t n_cells, const int
     o->b = malloc(sizeof(real) * n_cells * 120);
     o->w = malloc(sizeof(real) * n_cells * 45);
     return o;
+}
+
+orc *orc_create(int64_t n_nodes, const double *nodes, int64_t n_cells, const int8_t *types, const int64_t *cells,
+                const double *box, int periodic, int min_big)
+{
+    return orc_create_cells(n_nodes, nodes, n_cells, types, cells, box, periodic, min_big, NULL);
+}
+
+/* a cell whose stencils were not built (an oracle made for a subset of the cells) */
+static int unbuilt(const orc *o, int64_t i)
+{
+    if (o->partial && o->c[i].K == 0) {
+        seterr("stencils of this cell were not built");
+        return 1;
+    }
+    return 0;
 }
 
 void orc_destroy(orc *o)
@@ -1397,6 +1419,7 @@ static void weno_all(orc *o, const orc_params *P, const real *Q)
 /* exported: evaluate at point x of cell i (m=-1: Eq. weno; m>=0: P_m) */
 int orc_weno_eval(orc *o, const orc_params *P, const real *Q, int64_t i, int m, const double *x, real *val, real *grad)
 {
+    if (unbuilt(o, i)) return 7;
     weno_cell(o, P, Q, i);
     real g[5][3];
     weno_eval(o, P, Q, i, m, x, val, g);
@@ -1406,12 +1429,14 @@ int orc_weno_eval(orc *o, const orc_params *P, const real *Q, int64_t i, int m, 
 }
 
 /* normalised nonlinear weights of cell i (for inspection) */
-void orc_weno_weights(orc *o, const orc_params *P, const real *Q, int64_t i, real *w)
+int orc_weno_weights(orc *o, const orc_params *P, const real *Q, int64_t i, real *w)
 {
+    if (unbuilt(o, i)) return 7;
     weno_cell(o, P, Q, i);
     /* omega_0..omega_M per component; the slots beyond M are zero */
     for (int c = 0; c < 5; c++)
         for (int m = 0; m < 9; m++) w[9 * c + m] = m <= o->c[i].M ? o->w[45 * i + 9 * c + m] : 0.0;
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -1813,6 +1838,10 @@ static void fallback_state(const orc *o, const orc_params *P, const real *Q, sre
 
 static int face_flux_all(orc *o, const orc_params *P, const real *Q, double dt, real *out)
 {
+    if (o->partial) {
+        seterr("stencils built for a subset of the cells: no residual");
+        return 7;
+    }
     weno_all(o, P, Q);
     /* each iteration writes only its own face's fluxes; the fallback count is an integer sum */
     int err = 0;

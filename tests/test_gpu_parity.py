@@ -570,13 +570,16 @@ def _local_state(c, X, n):
 @pytest.mark.slow
 def test_benchmark_workload_sampled_fluxes_and_invariants(gks):
     """The benchmark workload at full size (hybrid lattice N = 64, Taylor-Green Navier-Stokes, FP64,
-    the launch configuration the benchmark times): for 2000 sampled faces the oracle's Gauss-point
-    flux, fed the states of the GPU's own reconstruction and summed over the face's Gauss points,
-    reproduces the kernel's face fluxes to 1e-12; over 3 steps sum |Omega| Q is conserved to
-    round-off and two runs are bitwise identical."""
+    the launch configuration the benchmark times): for 2000 sampled cells the GPU's quadratic matches
+    the oracle's Eq. weno at a random point of each (value 1e-12 of the component's scale, gradient
+    1e-10; an oracle that builds those cells' stencils only); for 2000 sampled faces the oracle's
+    Gauss-point flux, fed the states of the GPU's own reconstruction and summed over the face's
+    Gauss points, reproduces the kernel's face fluxes to 1e-12; over 3 steps sum |Omega| Q is
+    conserved to round-off and two runs are bitwise identical."""
     import torch
 
-    print("case: hybrid N=64 Taylor-Green NS, 2000 sampled faces + conservation + determinism", flush=True)
+    print("case: hybrid N=64 Taylor-Green NS, 2000 sampled cells and faces + conservation + determinism",
+          flush=True)
     mesh = inputs.lattice(64, "hybrid", box=(2 * math.pi,) * 3)
     Q0 = inputs.cell_averages(mesh, inputs.tgv())
     host = gks.HostMesh(mesh)
@@ -588,6 +591,26 @@ def test_benchmark_workload_sampled_fluxes_and_invariants(gks):
     ff = sol.flux(coeff, Q, dtt)
     sol.poll()
     C, F, dt = coeff.cpu().numpy(), ff.cpu().numpy(), float(dtt.item())
+    cells = np.random.default_rng(64).choice(host.n, 2000, replace=False)
+    o = oracle.Oracle(mesh, oracle.params(**prm), cells=host.perm[cells])
+    ovol, oxc, _, _ = o.cell_geometry()
+    rng = np.random.default_rng(65)
+    V, RV, G, RG = [], [], [], []
+    for i in cells:
+        ext = int(host.perm[i])
+        X = 0.4 * ovol[ext] ** (1 / 3) * rng.standard_normal(3)
+        v, g = _poly_eval(C[i], X)
+        rv, rg = o.weno_eval(Q0, ext, oxc[ext] + X)
+        V.append(v), RV.append(rv), G.append(g), RG.append(rg)
+    del o
+    V, RV, G, RG = map(np.array, (V, RV, G, RG))
+    vs = np.abs(RV).max(axis=0)
+    gs = np.abs(RG).max(axis=(0, 2))
+    vs[1:4], gs[1:4] = vs[1:4].max(), gs[1:4].max()  # rho W starts at zero: momentum shares one scale
+    ev = (np.abs(V - RV) / vs).max(axis=0)
+    eg = (np.abs(G - RG).max(axis=2) / gs).max(axis=0)
+    print("sampled cells' reconstruction, relative value error per component", ev, "gradient", eg, flush=True)
+    assert (ev <= TOL).all() and (eg <= 1e-10).all(), (ev, eg)
     own, nbr = host.faces()
     geo = host.face_geometry()
     faces = np.random.default_rng(2203).choice(host.n_faces, 2000, replace=False)

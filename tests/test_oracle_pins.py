@@ -930,3 +930,30 @@ def test_paper_tet_accuracy_table_first_row():
     paper = ref["L1"][0] / 8.0
     print("unit-cube L1", l1, "paper / 8", paper)
     assert paper / 2.5 < l1 < paper * 2.5, (l1, paper)
+
+
+def test_oracle_built_for_some_cells_reconstructs_them_as_the_full_one():
+    """Each cell's stencils and fits depend on the mesh alone, so an oracle that builds them for a
+    subset of the cells reconstructs those cells bitwise as the full oracle does; it refuses the
+    other cells and every operator that needs all of them."""
+    import math
+
+    mesh = inputs.lattice(4, "hybrid", box=(2 * math.pi,) * 3)
+    Q0 = inputs.cell_averages(mesh, inputs.tgv())
+    full = oracle.Oracle(mesh)
+    rng = np.random.default_rng(7)
+    cells = rng.choice(mesh.n_cells, 40, replace=False)
+    part = oracle.Oracle(mesh, cells=cells)
+    _, xc, _, _ = full.cell_geometry()
+    for c in cells:
+        x = xc[c] + 0.1 * rng.standard_normal(3)
+        for m in (-1, 0):
+            a, b = full.weno_eval(Q0, int(c), x, m), part.weno_eval(Q0, int(c), x, m)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    other = int(np.setdiff1d(np.arange(mesh.n_cells), cells)[0])
+    with pytest.raises(oracle.OracleError, match="not built"):
+        part.weno_eval(Q0, other, xc[other])
+    with pytest.raises(oracle.OracleError, match="subset"):
+        part.residual(Q0, 1e-3)
+    with pytest.raises(oracle.OracleError, match="subset"):
+        part.step(Q0, 1e-3)
