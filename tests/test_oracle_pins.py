@@ -6,6 +6,7 @@ kinetic moments, symmetries of the flux, the exact Taylor polynomial of the
 two-stage fourth-order step, free-stream preservation, conservation, the
 convergence order and the paper's own accuracy table.
 """
+import functools
 import json
 import math
 import os
@@ -327,13 +328,18 @@ def test_smoothness_indicators_and_weights_by_brute_force():
 # ---------------------------------------------------------------------------
 # Maxwellian moments (Eq. bgk-3d, Eq. compatibility)
 # ---------------------------------------------------------------------------
+@functools.lru_cache(maxsize=None)
+def _legendre(npts):
+    return np.polynomial.legendre.leggauss(npts)
+
+
 def _half_line(U, lam, n, sign):
     """Brute-force normalised moments of u^n over a half line (Gauss-Legendre on a truncated interval)."""
     sd = 1 / math.sqrt(2 * lam)
     lo, hi = (0.0, U + 14 * sd) if sign > 0 else (U - 14 * sd, 0.0)
     if sign > 0 and hi <= 0 or sign < 0 and lo >= 0:
         return 0.0
-    x, w = np.polynomial.legendre.leggauss(400)
+    x, w = _legendre(400)
     u = 0.5 * (hi - lo) * x + 0.5 * (hi + lo)
     wt = 0.5 * (hi - lo) * w
     g = math.sqrt(lam / math.pi) * np.exp(-lam * (u - U) ** 2)
