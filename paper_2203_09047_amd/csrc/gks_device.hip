@@ -220,7 +220,8 @@ __device__ __forceinline__ double mirror_sign(unsigned flip, int c)
 constexpr int kK1Lanes = 4;
 constexpr int kK1CellLanes = 5 * kK1Lanes;
 // 12 cells = 240 lanes = 4 waves (the last one 48 lanes).  The forward reconstruction stages
-// 51.9 KB per block (FP64; three blocks per CU), its reverse 27.5 KB (five blocks per CU);
+// 50.1 KB per block in FP64 (three blocks per CU) and 31.6 KB in FP32 (five), its reverse
+// 27.5 KB (five blocks per CU);
 // blocks of 16 cells leave more of the CU waiting at the staging barrier and measured 19%
 // slower (8 cells: 8% slower).
 constexpr int kK1Cells = 12;
@@ -477,8 +478,9 @@ __device__ __forceinline__ void weno_combine_quad_b(const double a[9], const dou
 // 16-byte windows of the per-member and per-entry arrays that one block stages: a window of
 // bytes [b0, b1) is copied from its 16-byte aligned start; the at most 15 bytes read beyond b1
 // lie in the array's padding or the next array of the mesh arena.  Every lane copies a whole
-// number of rows (the buffers hold kIter * kK1Block rows, those past a window's end repeat its
-// last row), so the copies need no branch into which the compiler could sink their loads.
+// number of rows (those past a window's end repeat its last row; those past the buffer go to
+// its last row, which nothing reads), so the copies need no branch into which the compiler could
+// sink their loads.
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 struct K1Windows {
@@ -499,9 +501,9 @@ k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff, We
 {
     using W = K1Windows<T>;
     __shared__ double sq[5][kK1Stage + 1];  // the last column takes the stores of lanes past the range
-    __shared__ u32x4 sP[W::kPIter * kK1Block];
-    __shared__ u32x4 sBw[W::kBIter * kK1Block];
-    __shared__ unsigned sLw[W::kLIter * kK1Block];
+    __shared__ u32x4 sP[W::kP + 1];
+    __shared__ u32x4 sBw[W::kB + 1];
+    __shared__ unsigned sLw[W::kL + 1];
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int t = blk * kK1Block + threadIdx.x;
     const int n = m.n;
@@ -578,11 +580,11 @@ k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff, We
 #pragma unroll
             for (int c = 0; c < 5; ++c) v[r][c] = Q[(size_t)c * n + cx[r]];
 #pragma unroll
-        for (int r = 0; r < W::kPIter; ++r) sP[(int)threadIdx.x + r * kK1Block] = rp[r];
+        for (int r = 0; r < W::kPIter; ++r) sP[min((int)threadIdx.x + r * kK1Block, W::kP)] = rp[r];
 #pragma unroll
-        for (int r = 0; r < W::kBIter; ++r) sBw[(int)threadIdx.x + r * kK1Block] = rb[r];
+        for (int r = 0; r < W::kBIter; ++r) sBw[min((int)threadIdx.x + r * kK1Block, W::kB)] = rb[r];
 #pragma unroll
-        for (int r = 0; r < W::kLIter; ++r) sLw[(int)threadIdx.x + r * kK1Block] = rl[r];
+        for (int r = 0; r < W::kLIter; ++r) sLw[min((int)threadIdx.x + r * kK1Block, W::kL)] = rl[r];
 #pragma unroll
         for (int r = 0; r < W::kEIter; ++r) {
             const int e = (int)threadIdx.x + r * kK1Block;
