@@ -220,7 +220,7 @@ __device__ __forceinline__ double mirror_sign(unsigned flip, int c)
 constexpr int kK1Lanes = 4;
 constexpr int kK1CellLanes = 5 * kK1Lanes;
 // 12 cells = 240 lanes = 4 waves (the last one 48 lanes).  The forward reconstruction stages
-// 50.1 KB per block in FP64 (three blocks per CU) and 31.6 KB in FP32 (five), its reverse
+// 40.8 KB per block in FP64 (four blocks per CU) and 31.6 KB in FP32 (five), its reverse
 // 27.5 KB (five blocks per CU);
 // blocks of 16 cells leave more of the CU waiting at the staging barrier and measured 19%
 // slower (8 cells: 8% slower).
@@ -481,16 +481,22 @@ __device__ __forceinline__ void weno_combine_quad_b(const double a[9], const dou
 // number of rows (those past a window's end repeat its last row; those past the buffer go to
 // its last row, which nothing reads), so the copies need no branch into which the compiler could
 // sink their loads.
+// The forward kernel's staging limits: in FP64, 240 members and 552 sub-stencil entries per block
+// (40.8 KB of LDS, four blocks per CU; 2.4% of the hybrid lattice's blocks exceed them and read
+// global memory, and the kernel measures 11% faster than with the limits below at three blocks
+// per CU); in FP32 the limits below (31.6 KB, five blocks per CU).
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 struct K1Windows {
-    static constexpr int kP = (kK1Stage * 9 * (int)sizeof(T) + 30) / 16;     // pseudo-inverse rows
-    static constexpr int kB = (kK1SubStage * 3 * (int)sizeof(T) + 30) / 16;  // sub-stencil B rows
-    static constexpr int kL = (kK1SubStage + 6) / 4;                          // sub-stencil member bytes, 4 B words
+    static constexpr int kStage = sizeof(T) == 8 ? 20 * kK1Cells : kK1Stage;
+    static constexpr int kSubStage = sizeof(T) == 8 ? 46 * kK1Cells : kK1SubStage;
+    static constexpr int kP = (kStage * 9 * (int)sizeof(T) + 30) / 16;     // pseudo-inverse rows
+    static constexpr int kB = (kSubStage * 3 * (int)sizeof(T) + 30) / 16;  // sub-stencil B rows
+    static constexpr int kL = (kSubStage + 6) / 4;                          // sub-stencil member bytes, 4 B words
     static constexpr int kPIter = (kP + kK1Block - 1) / kK1Block;
     static constexpr int kBIter = (kB + kK1Block - 1) / kK1Block;
     static constexpr int kLIter = (kL + kK1Block - 1) / kK1Block;
-    static constexpr int kEIter = (kK1Stage + kK1Block - 1) / kK1Block;
+    static constexpr int kEIter = (kStage + kK1Block - 1) / kK1Block;
 };
 
 // GEN: some plane of a mesh with walls has a condition other than the reflective one (a separate
@@ -500,7 +506,7 @@ __global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3
 k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff, WenoParams wp, BoundarySet bcs)
 {
     using W = K1Windows<T>;
-    __shared__ double sq[5][kK1Stage + 1];  // the last column takes the stores of lanes past the range
+    __shared__ double sq[5][W::kStage + 1];  // the last column takes the stores of lanes past the range
     __shared__ u32x4 sP[W::kP + 1];
     __shared__ u32x4 sBw[W::kB + 1];
     __shared__ unsigned sLw[W::kL + 1];
@@ -518,7 +524,7 @@ k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff, We
     const int e0 = m.st_ptr[cb0], e1 = m.st_ptr[cb1];
     const int s0 = m.ss_ptr[8 * cb0], s1 = m.ss_ptr[8 * cb1];
     // uniform over the block; non-empty windows keep the clamped row indices below in range
-    const bool staged = e1 > e0 && s1 > s0 && e1 - e0 <= kK1Stage && s1 - s0 <= kK1SubStage;
+    const bool staged = e1 > e0 && s1 > s0 && e1 - e0 <= W::kStage && s1 - s0 <= W::kSubStage;
     // the lane's own ranges and cell data, loaded before the staging so that no load after it
     // waits on them
     const int k0 = m.st_ptr[i], k1 = m.st_ptr[i + 1];
@@ -588,7 +594,7 @@ k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff, We
 #pragma unroll
         for (int r = 0; r < W::kEIter; ++r) {
             const int e = (int)threadIdx.x + r * kK1Block;
-            const int ew = e0 + e < e1 ? e : kK1Stage;
+            const int ew = e0 + e < e1 ? e : W::kStage;
             const unsigned fl = cf[r];
             if constexpr (GEN) {
                 if (fl & 7u) ghost_average(bcs, fl, v[r]);  // a ghost: its planes' conditions
