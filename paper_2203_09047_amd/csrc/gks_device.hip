@@ -221,15 +221,15 @@ constexpr int kK1Lanes = 4;
 constexpr int kK1CellLanes = 5 * kK1Lanes;
 // 12 cells = 240 lanes = 4 waves (the last one 48 lanes).  The forward reconstruction stages
 // 40.8 KB per block in FP64 (four blocks per CU) and 31.6 KB in FP32 (five), its reverse
-// 27.5 KB (five blocks per CU);
-// blocks of 16 cells leave more of the CU waiting at the staging barrier and measured 19%
-// slower (8 cells: 8% slower).
+// 27.5 KB (five).  Blocks of 16 cells leave more of the CU waiting at the staging barrier and
+// measured 19% slower (8 cells: 8% slower).
 constexpr int kK1Cells = 12;
 constexpr int kK1Block = kK1Cells * kK1CellLanes;
 // Staged in LDS per block (the cells' stencil and sub-stencil ranges are contiguous): the
-// members' cell averages, pseudo-inverse rows (forward kernel) and sub-stencil lists, up to 26
-// members and 50 sub-stencil entries per cell on average (the hybrid lattices' largest blocks
-// hold 312 and 576).  A block whose ranges are longer reads them from global memory instead.
+// members' cell averages, pseudo-inverse rows (forward kernel) and sub-stencil lists.  The
+// reverse and the FP32 forward kernel stage up to 26 members and 50 sub-stencil entries per
+// cell on average (the hybrid lattices' largest blocks hold 312 and 576; the FP64 forward
+// kernel's limits are below).  A block whose ranges are longer reads them from global memory.
 constexpr int kK1Stage = 26 * kK1Cells;
 constexpr int kK1SubStage = 50 * kK1Cells;
 

@@ -657,6 +657,83 @@ def test_benchmark_workload_sampled_fluxes_and_invariants(gks):
     assert (np.abs(tot1 - tot0) <= 1e-13 * mag).all(), (tot1 - tot0) / mag
 
 
+@pytest.mark.slow
+def test_benchmark_workload_fp32_mixed_sampled_cells_and_faces(gks):
+    """The FP32-mixed path at the benchmark's full size and launch configuration (hybrid lattice
+    N = 64, Taylor-Green Navier-Stokes): for 2000 sampled cells the GPU's FP32 quadratic (its
+    constant term holds the correction to the FP64 cell average) matches the oracle's Eq. weno to
+    1e-6 of the component's scale in value and 1e-5 in gradient; for 2000 sampled faces the
+    oracle's Gauss-point flux, fed the states of the GPU's own FP32 reconstruction, reproduces the
+    FP32 face fluxes to 1e-5 of max |Fbar0| (Fbar0, and dt Fbar1 on the same scale).  The bars are
+    FP32's unit round-off (6e-8) grown by the length of the computation (about a hundred
+    dependent operations); measured: 2e-8, 8e-7 and 7e-7."""
+    import torch
+
+    print("case: hybrid N=64 Taylor-Green NS FP32-mixed, 2000 sampled cells and faces", flush=True)
+    mesh = inputs.lattice(64, "hybrid", box=(2 * math.pi,) * 3)
+    Q0 = inputs.cell_averages(mesh, inputs.tgv())
+    host = gks.HostMesh(mesh)
+    prm = dict(viscous=True, mu=1.0 / 1600.0, Pr=0.72)
+    sol = gks.Solver(host, gks.params(precision=gks.FP32_MIXED, **prm))
+    Qi = host.to_internal(Q0)
+    Q = sol.upload(Qi)
+    dtt = sol.timestep(Q)
+    coeff = sol.reconstruct(Q)
+    ff = sol.flux(coeff, Q, dtt)
+    sol.poll()
+    torch.cuda.synchronize()
+    assert coeff.dtype == torch.float32 and ff.dtype == torch.float32
+    C = coeff.cpu().numpy().astype(np.float64)
+    C[:, :, 0] += Qi.T  # the FP64 cell averages the FP32 constant terms correct
+    F, dt = ff.cpu().numpy().astype(np.float64), float(dtt.item())
+    cells = np.random.default_rng(64).choice(host.n, 2000, replace=False)
+    o = oracle.Oracle(mesh, oracle.params(**prm), cells=host.perm[cells])
+    ovol, oxc, _, _ = o.cell_geometry()
+    rng = np.random.default_rng(65)
+    V, RV, G, RG = [], [], [], []
+    for i in cells:
+        ext = int(host.perm[i])
+        X = 0.4 * ovol[ext] ** (1 / 3) * rng.standard_normal(3)
+        v, g = _poly_eval(C[i], X)
+        rv, rg = o.weno_eval(Q0, ext, oxc[ext] + X)
+        V.append(v), RV.append(rv), G.append(g), RG.append(rg)
+    del o
+    V, RV, G, RG = map(np.array, (V, RV, G, RG))
+    vs = np.abs(RV).max(axis=0)
+    gs = np.abs(RG).max(axis=(0, 2))
+    vs[1:4], gs[1:4] = vs[1:4].max(), gs[1:4].max()
+    ev = (np.abs(V - RV) / vs).max(axis=0)
+    eg = (np.abs(G - RG).max(axis=2) / gs).max(axis=0)
+    print("FP32 sampled cells' reconstruction, relative value error per component", ev, "gradient", eg,
+          flush=True)
+    assert (ev <= 1e-6).all() and (eg <= 1e-5).all(), (ev, eg)
+    own, nbr = host.faces()
+    geo = host.face_geometry()
+    faces = np.random.default_rng(2203).choice(host.n_faces, 2000, replace=False)
+    op = oracle.params(**prm)
+    ref = np.zeros((len(faces), 10))
+    for r, f in enumerate(faces):
+        for g in range(4):
+            t = 4 * f + g
+            n = _local_frame(geo[6:9, t])
+            ql, dql = _local_state(C[own[f]], geo[0:3, t], n)
+            qr, dqr = _local_state(C[nbr[f]], geo[3:6, t], n)
+            Fb, _ = oracle.gp_flux(op, ql, dql, qr, dqr, dt)
+            area = np.linalg.norm(geo[6:9, t])
+            for s_ in range(2):
+                Fl = Fb[5 * s_:5 * s_ + 5]
+                ref[r, 5 * s_] += area * Fl[0]
+                ref[r, 5 * s_ + 4] += area * Fl[4]
+                ref[r, 5 * s_ + 1:5 * s_ + 4] += area * (Fl[1] * n[0] + Fl[2] * n[1] + Fl[3] * n[2])
+    scale = np.abs(ref[:, :5]).max(axis=0)
+    scale[1:4] = scale[1:4].max()
+    d = np.abs(F[faces] - ref)
+    err0 = (d[:, :5] / scale).max(axis=0)
+    err1 = (dt * d[:, 5:] / scale).max(axis=0)
+    print("FP32 sampled face fluxes, Fbar0 relative Linf:", err0, "dt Fbar1 on the Fbar0 scale:", err1, flush=True)
+    assert (err0 <= 1e-5).all() and (err1 <= 1e-5).all(), (err0, err1)
+
+
 def test_adjoint_refuses_walls(gks):
     import torch
 
