@@ -20,12 +20,18 @@ One step from Q^n with pseudo-time step dt:
       D_i = |Omega_i| / dt + 1/2 sum_f r S
   (the cell's own T(Q_i) terms cancel: T is linear in n and a closed cell's areas sum to 0);
 - Jacobi: dQ^(0) = |Omega| Res / D, then k_max sweeps with the neighbours' previous iterate;
-  Q^{n+1} = Q^n + dQ^(k_max).
-Periodic meshes only.
+  Q^{n+1} = Q^n + dQ^(k_max);
+- a face on a box plane of a mesh with walls has as neighbour the ghost of Section 2's
+  construction: the plane's condition applied to the cell's own state, Q_nb = B(Q_i); its
+  increment is that of the condition applied to the cell's updated state,
+  dQ_nb = B(Q_i + dQ_i) - B(Q_i), with the cell's previous iterate in each sweep (the paper's
+  implicit cases have walls but print no ghost treatment for the implicit operator).
 """
 from __future__ import annotations
 
 import numpy as np
+
+import oracle
 
 
 def euler_flux(Q: np.ndarray, n: np.ndarray, gamma: float) -> np.ndarray:
@@ -50,23 +56,45 @@ def face_normals(o):
     return fi["owner"], fi["nbr"], A / np.linalg.norm(A, axis=1)[:, None], S
 
 
+def wall_planes(nf: np.ndarray) -> np.ndarray:
+    """Box plane (2 axis + hi) of wall faces with outward unit normals nf [m, 3]: the axis the normal
+    lies along, hi where it points up that axis (the plane x_axis = L)."""
+    d = np.abs(nf).argmax(axis=1)
+    return 2 * d + (nf[np.arange(len(d)), d] > 0)
+
+
+def ghosts(prm, planes: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """The condition of each face's plane on the matching column of the cell averages V [5, m]."""
+    out = np.empty_like(V)
+    for j, pl in enumerate(planes):
+        out[:, j] = oracle.bc_ghost(prm, int(pl), V[:, j], np.zeros((5, 3)))[0]
+    return out
+
+
 def jacobi_step(o, Q: np.ndarray, dt: float, kmax: int = 3, gamma: float = 1.4, dt_flux: float | None = None) -> np.ndarray:
     """Q^{n+1} of one implicit step of pseudo-time step dt on the oracle `o` (whose parameters set the
-    GKS flux); the flux is integrated over dt_flux (default dt)."""
+    GKS flux and the box planes' conditions); the flux is integrated over dt_flux (default dt)."""
     dt_flux = dt if dt_flux is None else dt_flux
     n = Q.shape[1]
     owner, nbr, nf, S = face_normals(o)
-    if (nbr < 0).any():
-        raise ValueError("the implicit step is stated for periodic meshes")
+    wall = nbr < 0
     L, D = o.residual(Q, dt_flux)
     res = L + 0.5 * dt_flux * D
     vol = o.cell_geometry()[0]
-    # every face seen from each of its two cells: (cell, neighbour, outward normal, area)
-    cell = np.r_[owner, nbr]
-    other = np.r_[nbr, owner]
-    nout = np.r_[nf, -nf]
-    S2 = np.r_[S, S]
+    # every interior face seen from each of its two cells and every wall face from its cell:
+    # (cell, neighbour, outward normal, area); a wall face's neighbour is the ghost of its cell
+    inner = ~wall
+    cell = np.r_[owner[inner], nbr[inner], owner[wall]]
+    other = np.r_[nbr[inner], owner[inner], owner[wall]]
+    nout = np.r_[nf[inner], -nf[inner], nf[wall]]
+    S2 = np.r_[S[inner], S[inner], S[wall]]
+    ng = int(wall.sum())
+    planes = wall_planes(nf[wall])
+    gslot = slice(len(cell) - ng, len(cell))
+
     Qo = Q[:, other]
+    if ng:
+        Qo[:, gslot] = ghosts(o.P, planes, Qo[:, gslot])
     rho = Qo[0]
     U = Qo[1:4] / rho
     p = (gamma - 1.0) * (Qo[4] - 0.5 * rho * (U * U).sum(axis=0))
@@ -77,7 +105,11 @@ def jacobi_step(o, Q: np.ndarray, dt: float, kmax: int = 3, gamma: float = 1.4, 
     dQ = b / diag
     for _ in range(kmax):
         dQo = dQ[:, other]
-        term = (euler_flux(Qo + dQo, nout, gamma) - T0 - r * dQo) * S2
+        Q1 = Qo + dQo
+        if ng:  # a ghost's increment: the condition on the cell's updated state
+            Q1[:, gslot] = ghosts(o.P, planes, Q[:, other[gslot]] + dQo[:, gslot])
+            dQo[:, gslot] = Q1[:, gslot] - Qo[:, gslot]
+        term = (euler_flux(Q1, nout, gamma) - T0 - r * dQo) * S2
         off = np.stack([np.bincount(cell, weights=term[c], minlength=n) for c in range(5)])
         dQ = (b - 0.5 * off) / diag
     return Q + dQ
