@@ -323,6 +323,8 @@ def main():
     ap.add_argument("--no-n96", action="store_true", help="skip the N = 96 lattice (4.96 M cells)")
     ap.add_argument("--n96-steps", type=int, default=20, help="timed steps of the N = 96 and cavity legs")
     ap.add_argument("--no-cavity", action="store_true", help="skip the lid-driven cavity (walls) timing")
+    ap.add_argument("--no-paper-cavity", action="store_true",
+                    help="skip the paper's implicit cavity timing (102,400 cells, 1000 steps)")
     ap.add_argument("--no-smooth", action="store_true", help="skip the smooth-flow flux (Eq. flux-2) comparison")
     ap.add_argument("--no-implicit", action="store_true", help="skip the implicit Jacobi step timing")
     ap.add_argument("--no-power-law", action="store_true", help="skip the power-law viscosity timing")
@@ -591,6 +593,49 @@ def main():
                              state_after_timed_steps=state_summary(q96))
         res["n96"] = dict(cells=host96.n, faces=host96.n_faces, steps=args.n96_steps, warmup=args.warmup, **n96)
         del host96
+    if not args.no_paper_cavity:
+        # the paper's own GPU timing case: its lid-driven cavity (Mach 0.15, Re = 1000, isothermal no-slip
+        # walls) with the smooth-flow flux and the implicit Jacobi steady solver at k_max = 3, on a mesh
+        # of the paper's size and cell mix (102,400 cells: 25,600 hexahedra and 76,800 prisms, here the
+        # unrefined 40^3 lattice of the unit box in columns of either); 1000 steps timed, FP64, events off
+        t = time.perf_counter()
+        meshp = inputs.lattice(40, "hexprism", periodic=False)
+        p0 = 1.0 / 1.4
+        hostp = gks.HostMesh(meshp)
+        bc = [gks.boundary(gks.BC_ISOTHERMAL, Tw=p0) for _ in range(6)]
+        bc[3] = gks.boundary(gks.BC_ISOTHERMAL, uw=(0.15, 0.0, 0.0), Tw=p0)
+        solp = gks.Solver(hostp, gks.params(viscous=True, mu=0.15 / 1000.0, Pr=0.72, cfl=args.cfl, smooth=True,
+                                            bc=bc))
+        Qp = solp.upload(hostp.to_internal(inputs.cell_averages(meshp, inputs.uniform(1.0, 0.0, 0.0, 0.0, p0))))
+        for _ in range(10):
+            solp.implicit_step(Qp, dt_factor=10.0, kmax=3)
+        solp.poll()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(solp.stream)
+        for _ in range(1000):
+            solp.implicit_step(Qp, dt_factor=10.0, kmax=3)
+        e1.record(solp.stream)
+        torch.cuda.synchronize()
+        msp = e0.elapsed_time(e1)
+        solp.profile(True)
+        for _ in range(args.prof_steps):
+            solp.implicit_step(Qp, dt_factor=10.0, kmax=3)
+        profp = solp.profile_read()
+        solp.profile(False)
+        solp.poll()
+        qp = Qp.cpu().numpy()
+        res["paper_cavity_implicit_fp64"] = dict(
+            s_per_1000_steps=msp * 1e-3, value=hostp.n * 1000 / (msp * 1e-3), unit="cell-steps/s", cells=hostp.n,
+            faces=hostp.n_faces, hist=meshp.hist, steps=1000, kmax=3, dt_factor=10.0, flux="smooth (Eq. flux-2)",
+            state_after_timed_steps=state_summary(qp),
+            max_speed=float(np.sqrt((qp[1:4] ** 2).sum(axis=0)).max() / qp[0].min()), kernels=kernel_table(profp),
+            paper=dict(s_per_1000_steps=97.0, cells=102400, faces=274560,
+                       hardware="Nvidia TITAN RTX, CUDA Fortran, FP64 (Jacobi k_max = 3, smooth-flow flux)"),
+            speedup_vs_paper=97.0 / (msp * 1e-3))
+        log(f"paper cavity (implicit): {msp:.1f} ms per 1000 steps ({time.perf_counter() - t:.1f} s)")
+        del solp, hostp, Qp
+        torch.cuda.empty_cache()
     res["hbm_copy_gbs_measured"] = copy_bandwidth()
     if not args.no_cpu:
         t = time.perf_counter()

@@ -311,9 +311,13 @@ gks_status gks_s2o4_step_noalloc(gks_mesh *m, double *Q, double *dt_dev, const g
  * r = |U_nb . n| + c_nb at t_n:
  *   D_i dQ_i^(k) = |Omega_i| Res_i - 1/2 sum_f [T(Q_nb + dQ_nb^(k-1)) - T(Q_nb) - r dQ_nb^(k-1)] S,
  *   D_i = |Omega_i| / dt + 1/2 sum_f r S,  dQ^(0) = |Omega| Res / D,
- * and Q += dQ^(kmax) in place.  The work buffer's coefficient area holds the
- * iteration.  Periodic meshes only (GKS_EINVAL with walls); dt_factor > 0,
- * 0 <= kmax <= 1000.  The paper times this path with kmax = 3.
+ * and Q += dQ^(kmax) in place.  On a mesh with walls the neighbour across a
+ * face on a box plane is the ghost of Section 2's construction, the plane's
+ * condition (p->bc) on the cell's own state, Q_nb = B(Q_i), and its increment
+ * dQ_nb = B(Q_i + dQ_i) - B(Q_i) with the cell's previous iterate.  The work
+ * buffer's coefficient area holds the iteration.  dt_factor > 0,
+ * 0 <= kmax <= 1000 (GKS_EINVAL otherwise).  The paper times this path with
+ * kmax = 3 (the lid-driven cavity with the smooth-flow flux, and the sphere).
  */
 gks_status gks_implicit_step(gks_mesh *m, double *Q, double *dt_dev, double dt_factor, int kmax, const gks_params *p,
                              void *work, gks_stream_t stream);

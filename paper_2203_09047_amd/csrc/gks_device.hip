@@ -983,7 +983,10 @@ __global__ void __launch_bounds__(kBlock) k_stage2(DevMesh m, const T *__restric
 // D_i dQ_i + 1/2 sum_f [T(Q_nb + dQ_nb) - T(Q_nb) - r dQ_nb] S = |Omega_i| Res_i with
 // D_i = |Omega_i| / dt + 1/2 sum_f r S, T the Euler flux along the cell's outward face normal,
 // r = |U_nb . n| + c_nb at t_n and Res = L + dt_f/2 dL/dt the GKS residual over the explicit step
-// dt_f (dt = factor x dt_f); every gather runs over the cell's faces in F_p order.
+// dt_f (dt = factor x dt_f); every gather runs over the cell's faces in F_p order.  Across a face
+// on a box plane the neighbour is the ghost of Section 2's construction, the plane's condition on
+// the cell's own state, B(Q_i), and its increment B(Q_i + dQ_i) - B(Q_i) with the cell's previous
+// iterate.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double euler_flux_n(const double q[5], double nx, double ny, double nz, double gam,
                                                double T[5])
@@ -1000,7 +1003,8 @@ __device__ __forceinline__ double euler_flux_n(const double q[5], double nx, dou
     return fabs(un) + sqrt(gam * p * ir);  // spectral radius of the normal flux Jacobian
 }
 
-// the neighbour across a cell's face (code = 2 face + side) and the cell's outward unit normal
+// the neighbour across a cell's face (code = 2 face + side) and the cell's outward unit normal; a
+// wall face gives -1 - its box plane
 __device__ __forceinline__ int face_side(const DevMesh &m, int code, double &nx, double &ny, double &nz, double &S)
 {
     const int f = code >> 1;
@@ -1016,7 +1020,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_implicit_init(DevMesh m, const T *__restrict__ ff, const double *__restrict__ Q,
                                                           const double *__restrict__ dt_dev, double factor, double gam,
                                                           double *__restrict__ b, double *__restrict__ diag,
-                                                          double *__restrict__ dq)
+                                                          double *__restrict__ dq, BoundarySet bcs)
 {
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= m.n) return;
@@ -1029,7 +1033,8 @@ __global__ void __launch_bounds__(kBlock) k_implicit_init(DevMesh m, const T *__
         double nx, ny, nz, S, q[5], Tn[5];
         const int nb = face_side(m, m.cf_idx[p], nx, ny, nz, S);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) q[c] = Q[(size_t)c * n + nb];
+        for (int c = 0; c < 5; ++c) q[c] = Q[(size_t)c * n + (nb >= 0 ? nb : i)];
+        if (nb < 0) bc_average(bcs, -1 - nb, q);  // the ghost
         sumr += euler_flux_n(q, nx, ny, nz, gam, Tn) * S;
     }
     const double d = vol / (factor * dtf) + 0.5 * sumr;
@@ -1044,7 +1049,8 @@ __global__ void __launch_bounds__(kBlock) k_implicit_init(DevMesh m, const T *__
 
 __global__ void __launch_bounds__(kBlock) k_implicit_sweep(DevMesh m, const double *__restrict__ Q, double gam,
                                                            const double *__restrict__ b, const double *__restrict__ diag,
-                                                           const double *__restrict__ dq_in, double *__restrict__ dq_out)
+                                                           const double *__restrict__ dq_in, double *__restrict__ dq_out,
+                                                           BoundarySet bcs)
 {
     const int i = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= m.n) return;
@@ -1053,11 +1059,18 @@ __global__ void __launch_bounds__(kBlock) k_implicit_sweep(DevMesh m, const doub
     for (int p = m.cf_ptr[i]; p < m.cf_ptr[i + 1]; ++p) {
         double nx, ny, nz, S, q[5], d[5], q1[5], T0[5], T1[5];
         const int nb = face_side(m, m.cf_idx[p], nx, ny, nz, S);
+        const int x = nb >= 0 ? nb : i;
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-            q[c] = Q[(size_t)c * n + nb];
-            d[c] = dq_in[(size_t)c * n + nb];
+            q[c] = Q[(size_t)c * n + x];
+            d[c] = dq_in[(size_t)c * n + x];
             q1[c] = q[c] + d[c];
+        }
+        if (nb < 0) {  // the ghost and its increment: the condition on the cell's state and updated state
+            bc_average(bcs, -1 - nb, q);
+            bc_average(bcs, -1 - nb, q1);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) d[c] = q1[c] - q[c];
         }
         const double r = euler_flux_n(q, nx, ny, nz, gam, T0);
         euler_flux_n(q1, nx, ny, nz, gam, T1);
@@ -2222,7 +2235,6 @@ gks_status gks_implicit_step(gks_mesh *m, double *Q, double *dt_dev, double dt_f
     gks_status s = check_params(m, p);
     if (s) return s;
     if (!Q || !dt_dev || !work) return fail(GKS_EINVAL, "null argument");
-    if (m->d.walls) return fail(GKS_EINVAL, "the implicit step is built for periodic meshes (this one has walls)");
     if (!(dt_factor > 0.0) || kmax < 0 || kmax > 1000) return fail(GKS_EINVAL, "dt_factor must be > 0 and kmax in 0..1000");
     hipStream_t st = S(stream);
     Work w = work_of(m, work);
@@ -2234,16 +2246,17 @@ gks_status gks_implicit_step(gks_mesh *m, double *Q, double *dt_dev, double dt_f
     const int64_t n = m->n;
     double *b = (double *)w.coeff, *diag = b + 5 * n, *dq[2] = {diag + n, diag + 6 * n};
     const unsigned gc = grid_for(n, kBlock);
+    const BoundarySet bcs = boundary_set(p);
     {
         ProfScope ps(m, GKS_K_IMPLICIT, st);
         if (m->precision == GKS_FP64)
             k_implicit_init<double><<<gc, kBlock, 0, st>>>(m->d, (const double *)w.ff, Q, dt_dev, dt_factor, p->gamma, b,
-                                                          diag, dq[0]);
+                                                          diag, dq[0], bcs);
         else
             k_implicit_init<float><<<gc, kBlock, 0, st>>>(m->d, (const float *)w.ff, Q, dt_dev, dt_factor, p->gamma, b,
-                                                         diag, dq[0]);
+                                                         diag, dq[0], bcs);
         for (int k = 0; k < kmax; ++k)
-            k_implicit_sweep<<<gc, kBlock, 0, st>>>(m->d, Q, p->gamma, b, diag, dq[k & 1], dq[(k + 1) & 1]);
+            k_implicit_sweep<<<gc, kBlock, 0, st>>>(m->d, Q, p->gamma, b, diag, dq[k & 1], dq[(k + 1) & 1], bcs);
         const int len = (int)(5 * n);
         k_implicit_update<<<grid_for(len, kBlock), kBlock, 0, st>>>(len, Q, dq[kmax & 1]);
     }

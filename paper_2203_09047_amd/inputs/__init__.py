@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgks_inputs.so")
 SOURCE = os.path.join(_HERE, "gks_inputs.c")
 
-KINDS = {"hybrid": 0, "hex": 1, "tet": 2, "pyr": 3, "prism": 4}
+KINDS = {"hybrid": 0, "hex": 1, "tet": 2, "pyr": 3, "prism": 4, "hexprism": 5}
 TYPE_NAMES = ("tet", "pyr", "prism", "hex")
 MESH_SEED = 2203
 PERTURB_SEED = 9047

@@ -39,8 +39,9 @@
 enum { T_TET = 0, T_PYR = 1, T_PRISM = 2, T_HEX = 3 };
 /* draw codes */
 enum { D_HEX = 0, D_PRISM = 1, D_TET = 2, D_PYR = 3 };
-/* mesh kinds */
-enum { K_HYBRID = 0, K_HEX = 1, K_TET = 2, K_PYR = 3, K_PRISM = 4 };
+/* mesh kinds (K_HEXPRISM: whole columns along z of hexahedra, 40 % of them, or of prisms; the
+   cavity meshes' cell mix) */
+enum { K_HYBRID = 0, K_HEX = 1, K_TET = 2, K_PYR = 3, K_PRISM = 4, K_HEXPRISM = 5 };
 
 uint64_t gin_splitmix64(uint64_t x)
 {
@@ -115,6 +116,12 @@ static int face_type(const lat_t *L, int i, int j, int k, int axis, int s)
     return dm == 0 ? 1 : dm;
 }
 
+static int cmp_u64(const void *a, const void *b)
+{
+    const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : x > y;
+}
+
 static void lat_init(lat_t *L, int N, int kind, uint64_t seed, int periodic)
 {
     L->N = N;
@@ -124,9 +131,25 @@ static void lat_init(lat_t *L, int N, int kind, uint64_t seed, int periodic)
     int64_t nh = (int64_t)N * N * N;
     L->draw = (int8_t *)malloc((size_t)nh);
     L->native = (int8_t *)malloc((size_t)nh);
-    for (int k = 0; k < N; k++)
-        for (int j = 0; j < N; j++)
-            for (int i = 0; i < N; i++) L->draw[hidx(L, i, j, k)] = (int8_t)draw_of(L, i, j, k);
+    if (kind == K_HEXPRISM) {
+        /* the columns (i, j) with the round(0.4 N^2) smallest seeded hashes hold hexahedra, the others
+           prisms (split alike in every layer, so every face matches) */
+        const int64_t nc = (int64_t)N * N, nhex = (4 * nc + 5) / 10;
+        uint64_t *h = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)nc), *srt = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)nc);
+        for (int64_t c = 0; c < nc; c++) h[c] = srt[c] = gin_splitmix64(seed ^ (0xC0C0C0C0ull + (uint64_t)c));
+        qsort(srt, (size_t)nc, sizeof(uint64_t), cmp_u64);
+        const uint64_t cut = nhex < nc ? srt[nhex] : ~0ull;
+        for (int k = 0; k < N; k++)
+            for (int j = 0; j < N; j++)
+                for (int i = 0; i < N; i++)
+                    L->draw[hidx(L, i, j, k)] = (int8_t)(h[i + (int64_t)N * j] < cut ? D_HEX : D_PRISM);
+        free(h);
+        free(srt);
+    } else {
+        for (int k = 0; k < N; k++)
+            for (int j = 0; j < N; j++)
+                for (int i = 0; i < N; i++) L->draw[hidx(L, i, j, k)] = (int8_t)draw_of(L, i, j, k);
+    }
     for (int k = 0; k < N; k++)
         for (int j = 0; j < N; j++)
             for (int i = 0; i < N; i++) {
@@ -248,7 +271,7 @@ static void realise(const lat_t *L, int i, int j, int k, int64_t center_id, sink
 int gin_lattice(int N, int kind, uint64_t seed, int periodic, const double *box, int64_t *n_nodes, int64_t *n_cells,
                 int64_t *hist, double *nodes, int8_t *types, int64_t *cells)
 {
-    if (N < 1 || kind < 0 || kind > 4) return 1;
+    if (N < 1 || kind < 0 || kind > 5) return 1;
     lat_t L;
     lat_init(&L, N, kind, seed, periodic);
     int64_t nlat = (int64_t)(N + 1) * (N + 1) * (N + 1);
