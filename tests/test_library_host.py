@@ -59,7 +59,7 @@ def test_preprocessor_matches_oracle_construction(kind, N):
     assert pairs == opairs
 
 
-@pytest.mark.parametrize("kind", ["hex", "hybrid"])
+@pytest.mark.parametrize("kind", ["hex", "hybrid", "hexprism"])
 def test_preprocessor_walls_match_oracle(kind):
     """Reflective walls: the same interior face pairs as the oracle, one wall face per boundary face,
     the same volumes and centroids."""
@@ -81,6 +81,14 @@ def test_preprocessor_walls_match_oracle(kind):
     ovol, oxc, _, _ = o.cell_geometry()
     np.testing.assert_allclose(vol, ovol[host.perm], rtol=1e-14, atol=0)
     assert host.n_grown == sum(o.grown(c) for c in range(mesh.n_cells))
+
+
+def test_hexahedron_prism_lattice_has_the_papers_cavity_counts():
+    """The column lattice at N = 40 in the walled unit box: the paper's cavity mesh sizes, 102,400 cells
+    (25,600 hexahedra, 76,800 prisms) and 274,560 faces."""
+    mesh = inputs.lattice(40, "hexprism", periodic=False)
+    assert mesh.n_cells == 102400 and mesh.hist == {"tet": 0, "pyr": 0, "prism": 76800, "hex": 25600}
+    assert gks.HostMesh(mesh).n_faces == 274560
 
 
 def _p(a):
