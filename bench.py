@@ -45,11 +45,11 @@ COUNTERS_N = 64
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2203_09047_amd", "csrc", f)
                   for f in ("gks_device.hip", "gks_flux.h", "gks_flux_adj.h", "gks_weno.h", "gks_internal.h", "gks_bc.h")]
 # rocprofv3 kernel names -> the library's kernel keys
-KERNEL_NAMES = {"k_reconstruct<double, false>(": "reconstruct", "k_flux_chunked<true, false>(": "flux", "k_stage1<double>(": "stage1",
+KERNEL_NAMES = {"k_reconstruct<double, false, 0>(": "reconstruct", "k_flux_chunked<true, false>(": "flux", "k_stage1<double>(": "stage1",
                 "k_stage2<double>(": "stage2", "k_dt_partial(": "timestep", "k_flux_adj_a<true>(": "flux_adj_a",
                 "k_flux_adj_b<true>(": "flux_adj_b", "k_reconstruct_adj(": "reconstruct_adj",
                 "k_cbar_gather(": "cbar_gather", "k_transpose_gather(": "transpose_gather",
-                "k_reconstruct<float, false>(": "reconstruct_fp32", "k_flux<float, true, false, false>(": "flux_fp32",
+                "k_reconstruct<float, false, 0>(": "reconstruct_fp32", "k_flux<float, true, false, false>(": "flux_fp32",
                 "k_stage1<float>(": "stage1_fp32", "k_stage2<float>(": "stage2_fp32"}
 VALU_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_ADD_F64",
                  "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_ADD_F32")

@@ -481,15 +481,20 @@ __device__ __forceinline__ void weno_combine_quad_b(const double a[9], const dou
 // number of rows (those past a window's end repeat its last row; those past the buffer go to
 // its last row, which nothing reads), so the copies need no branch into which the compiler could
 // sink their loads.
-// The forward kernel's staging limits: in FP64, 240 members and 552 sub-stencil entries per block
-// (40.8 KB of LDS, four blocks per CU; 2.4% of the hybrid lattice's blocks exceed them and read
-// global memory, and the kernel measures 11% faster than with the limits below at three blocks
-// per CU); in FP32 the limits below (31.6 KB, five blocks per CU).
+// The forward kernel's staging limits per block.  FP64 blocks fit four per CU in 40.96 KB of LDS,
+// which holds members and sub-stencil entries in one of three splits, chosen per mesh as the one
+// that stages the most of its blocks (k1_staging_class): 240 members and 552 entries (the hybrid
+// lattice: 2.4% of its blocks exceed them and read global memory; the kernel measures 11% faster
+// than with the FP32 limits at three blocks per CU), 288 and 300 (hexahedra and prisms) or 228 and
+// 576 (pyramids).  FP32 blocks stage up to 312 members and 600 entries (31.6 KB, five per CU).
+constexpr int kK1Classes = 3;
+constexpr int kK1StageOf[kK1Classes] = {20 * kK1Cells, 24 * kK1Cells, 19 * kK1Cells};
+constexpr int kK1SubStageOf[kK1Classes] = {46 * kK1Cells, 25 * kK1Cells, 48 * kK1Cells};
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-template <typename T>
+template <typename T, int CAP = 0>
 struct K1Windows {
-    static constexpr int kStage = sizeof(T) == 8 ? 20 * kK1Cells : kK1Stage;
-    static constexpr int kSubStage = sizeof(T) == 8 ? 46 * kK1Cells : kK1SubStage;
+    static constexpr int kStage = sizeof(T) == 8 ? kK1StageOf[CAP] : kK1Stage;
+    static constexpr int kSubStage = sizeof(T) == 8 ? kK1SubStageOf[CAP] : kK1SubStage;
     static constexpr int kP = (kStage * 9 * (int)sizeof(T) + 30) / 16;     // pseudo-inverse rows
     static constexpr int kB = (kSubStage * 3 * (int)sizeof(T) + 30) / 16;  // sub-stencil B rows
     static constexpr int kL = (kSubStage + 6) / 4;                          // sub-stencil member bytes, 4 B words
@@ -501,11 +506,11 @@ struct K1Windows {
 
 // GEN: some plane of a mesh with walls has a condition other than the reflective one (a separate
 // instantiation keeps the periodic and reflective-wall kernel free of the conditions' code)
-template <typename T, bool GEN>
+template <typename T, bool GEN, int CAP>
 __global__ void __launch_bounds__(kK1Block) __attribute__((amdgpu_waves_per_eu(3)))
 k_reconstruct(DevMesh m, const double *__restrict__ Q, T *__restrict__ coeff, WenoParams wp, BoundarySet bcs)
 {
-    using W = K1Windows<T>;
+    using W = K1Windows<T, CAP>;
     __shared__ double sq[5][W::kStage + 1];  // the last column takes the stores of lanes past the range
     __shared__ u32x4 sP[W::kP + 1];
     __shared__ u32x4 sBw[W::kB + 1];
@@ -1599,6 +1604,7 @@ struct gks_mesh {
     int n_cu = 256;  // compute units of the device the mesh lives on (grid of the chunked flux kernel)
     int dev = 0;     // the device the mesh lives on
     int flux_win = kWinCells;  // owner window of the chunked flux kernel (narrowed by tests only)
+    int k1_class = 0;          // staging split of the FP64 reconstruction (k1_staging_class)
     // optional per-kernel HIP-event timing (gks_profile)
     bool prof = false;
     std::vector<hipEvent_t> pool;
@@ -1726,6 +1732,26 @@ gks_status gks_host_mesh_faces(const gks_host_mesh *h, int32_t *owner, int32_t *
     if (owner) std::memcpy(owner, h->h.owner.data(), sizeof(int32_t) * h->h.nf);
     if (nbr) std::memcpy(nbr, h->h.nbr.data(), sizeof(int32_t) * h->h.nf);
     return GKS_OK;
+}
+
+// The FP64 reconstruction's staging split for a mesh: the class whose limits hold the most of its
+// 12-cell blocks (members and sub-stencil entries counted in the library's cell order).
+static int k1_staging_class(const HostMesh &H)
+{
+    const int64_t n = H.n;
+    int64_t staged[kK1Classes] = {0};
+    for (int64_t c0 = 0; c0 < n; c0 += kK1Cells) {
+        const int64_t c1 = std::min<int64_t>(c0 + kK1Cells, n);
+        const int64_t e0 = H.st_ptr[c0], e1 = H.st_ptr[c1];
+        int64_t subs = 0;
+        for (int64_t k = e0; k < e1; ++k) subs += __builtin_popcount((unsigned)H.st_mask[k]);
+        for (int c = 0; c < kK1Classes; ++c)
+            if (e1 - e0 <= kK1StageOf[c] && subs <= kK1SubStageOf[c]) ++staged[c];
+    }
+    int best = 0;
+    for (int c = 1; c < kK1Classes; ++c)
+        if (staged[c] > staged[best]) best = c;
+    return best;
 }
 
 // mesh arena layout (offsets only when base == nullptr)
@@ -1921,6 +1947,7 @@ gks_status gks_init_mesh(const gks_host_mesh *h, int precision, void *mesh_arena
     m->n = h->h.n;
     m->nf = h->h.nf;
     m->precision = precision;
+    m->k1_class = k1_staging_class(h->h);
     int dev = 0, ncu = 0;
     if ((s = hip_check(hipGetDevice(&dev), "current device")) || (s = scratch_setup(dev))) {
         delete m;
@@ -2054,16 +2081,22 @@ static gks_status launch_reconstruct(gks_mesh *m, const double *Q, void *coeff, 
     ProfScope ps(m, GKS_K_RECONSTRUCT, st);
     const BoundarySet bcs = boundary_set(p);
     const bool gen = m->d.walls && bcs.any_general;
+    const WenoParams wp = weno_params(p);
     if (m->precision == GKS_FP64) {
-        if (gen)
-            k_reconstruct<double, true><<<grid, kK1Block, 0, st>>>(m->d, Q, (double *)coeff, weno_params(p), bcs);
-        else
-            k_reconstruct<double, false><<<grid, kK1Block, 0, st>>>(m->d, Q, (double *)coeff, weno_params(p), bcs);
+        double *c = (double *)coeff;
+        switch (m->k1_class * 2 + (int)gen) {
+        case 0: k_reconstruct<double, false, 0><<<grid, kK1Block, 0, st>>>(m->d, Q, c, wp, bcs); break;
+        case 1: k_reconstruct<double, true, 0><<<grid, kK1Block, 0, st>>>(m->d, Q, c, wp, bcs); break;
+        case 2: k_reconstruct<double, false, 1><<<grid, kK1Block, 0, st>>>(m->d, Q, c, wp, bcs); break;
+        case 3: k_reconstruct<double, true, 1><<<grid, kK1Block, 0, st>>>(m->d, Q, c, wp, bcs); break;
+        case 4: k_reconstruct<double, false, 2><<<grid, kK1Block, 0, st>>>(m->d, Q, c, wp, bcs); break;
+        default: k_reconstruct<double, true, 2><<<grid, kK1Block, 0, st>>>(m->d, Q, c, wp, bcs); break;
+        }
     } else {
         if (gen)
-            k_reconstruct<float, true><<<grid, kK1Block, 0, st>>>(m->d, Q, (float *)coeff, weno_params(p), bcs);
+            k_reconstruct<float, true, 0><<<grid, kK1Block, 0, st>>>(m->d, Q, (float *)coeff, wp, bcs);
         else
-            k_reconstruct<float, false><<<grid, kK1Block, 0, st>>>(m->d, Q, (float *)coeff, weno_params(p), bcs);
+            k_reconstruct<float, false, 0><<<grid, kK1Block, 0, st>>>(m->d, Q, (float *)coeff, wp, bcs);
     }
     return hip_check(hipGetLastError(), "reconstruct launch");
 }

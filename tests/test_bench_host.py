@@ -35,7 +35,7 @@ def test_counter_summary_is_scaled_by_the_copy_calibration(tmp_path):
     # FETCH_SIZE reading half of each 1 GiB copy (factor 2), WRITE_SIZE all of it (factor 1)
     fetch, write = str(tmp_path / "fetch.db"), str(tmp_path / "write.db")
     flux = "void gks::k_flux_chunked<true, false>(gks::DevMesh, ...)"
-    recon = "void gks::k_reconstruct<double, false>(gks::DevMesh, ...)"
+    recon = "void gks::k_reconstruct<double, false, 0>(gks::DevMesh, ...)"
     _db(fetch, [524288.0] * 3, [(flux, 1000.0), (flux, 3000.0), (recon, 10.0), ("other_kernel(", 5.0)])
     _db(write, [1048576.0] * 3, [(flux, 100.0), (flux, 300.0), (recon, 1.0)])
     d = bench.counters_from(fetch, write)
