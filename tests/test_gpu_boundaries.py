@@ -52,6 +52,11 @@ def _case(name):
         far = (1.0, *U, p0)
         return (inputs.lattice(6, "hybrid", periodic=False), inputs.wave(amp=0.1, U=U, p0=p0), {},
                 [(3, (0, 0, 0), 1.0, far)] * 6, 5)
+    if name == "farfield-subsonic-pyr":
+        U = (0.2, -0.1, 0.3)
+        far = (1.0, *U, p0)
+        return (inputs.lattice(4, "pyr", periodic=False), inputs.wave(amp=0.1, U=U, p0=p0), {},
+                [(3, (0, 0, 0), 1.0, far)] * 6, 5)
     if name == "farfield-supersonic-hex":
         U = (2.0, 0.2, 0.0)
         far = (1.0, *U, p0)
@@ -64,8 +69,10 @@ def _case(name):
     raise KeyError(name)
 
 
+# the reconstruction's staging splits, each with the conditions' ghost members: the hybrid lattice,
+# hexahedra and the pyramid lattice
 CASES = ["cavity-isothermal-hex", "cavity-isothermal-hybrid", "noslip-adiabatic-hex", "farfield-subsonic-hybrid",
-         "farfield-supersonic-hex", "extrapolate-riemann-hybrid"]
+         "farfield-subsonic-pyr", "farfield-supersonic-hex", "extrapolate-riemann-hybrid"]
 
 
 @pytest.mark.parametrize("name", CASES)

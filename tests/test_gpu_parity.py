@@ -353,7 +353,8 @@ def test_implicit_steady_solver_converges_on_gpu(gks):
     assert r < 1e-2 * r0
 
 
-@pytest.mark.parametrize("case", ["cavity-hybrid", "cavity-hybrid-smooth", "slip-tgv-hex", "farfield-hybrid"])
+@pytest.mark.parametrize("case", ["cavity-hybrid", "cavity-hybrid-smooth", "cavity-hexprism-smooth", "slip-tgv-hex",
+                                  "farfield-hybrid"])
 def test_implicit_step_with_walls_matches_oracle(gks, case):
     """The implicit step on meshes with walls (the ghost of Section 2's construction as the neighbour
     of a wall face, its increment the condition on the cell's updated state): the paper's cavity
@@ -370,7 +371,7 @@ def test_implicit_step_with_walls_matches_oracle(gks, case):
     p0 = 1.0 / 1.4
     far0 = (1.0, 0.0, 0.0, 0.0, 1.0)
     if case.startswith("cavity"):
-        mesh = inputs.lattice(6, "hybrid", periodic=False)
+        mesh = inputs.lattice(6, case.split("-")[1], periodic=False)
         Q0 = inputs.cell_averages(mesh, inputs.uniform(1.0, 0, 0, 0, p0))
         bcs = [(2, (0.0, 0.0, 0.0), p0, far0)] * 6
         bcs[3] = (2, (0.15, 0.0, 0.0), p0, far0)
