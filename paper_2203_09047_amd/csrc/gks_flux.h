@@ -120,75 +120,88 @@ __host__ __device__ __forceinline__ void mom_half_u(Mom<T> &m, T U, T lam, T sig
     recur7(m.u, U, T(0.5) / lam);
 }
 
-// <u^k v^l w^m psi>
+// The symmetric moment matrix Q = <u^k v^l w^n psi psi^T> of one moment set, upper triangle by
+// rows (00 01 02 03 04 11 12 13 14 22 23 24 33 34 44), psi = (1, u, v, w, (u^2 + v^2 + w^2 + xi^2)/2).
+// The flux needs <u^k v^l w^n psi> (Q's first column, psi_0 = 1) and, for slopes a,
+// <u^k v^l w^n (a . psi) psi> = Q a: each matrix is formed once and applied to every slope.
+template <typename T>
+struct Q5 {
+    T e[15];
+};
+
 template <int k, int l, int n, typename T>
-__host__ __device__ __forceinline__ void P(const Mom<T> &M, T o[5])
+__host__ __device__ __forceinline__ void qmat(const Mom<T> &M, Q5<T> &Q)
 {
-    const T vw = M.v[l] * M.w[n];
-    const T base = M.u[k] * vw;
-    o[0] = base;
-    o[1] = M.u[k + 1] * vw;
-    o[2] = M.u[k] * M.v[l + 1] * M.w[n];
-    o[3] = M.u[k] * M.v[l] * M.w[n + 1];
-    o[4] = T(0.5) * (M.u[k + 2] * vw + M.u[k] * M.v[l + 2] * M.w[n] + M.u[k] * M.v[l] * M.w[n + 2] + base * M.s1);
+    const T *u = M.u + k, *v = M.v + l, *w = M.w + n;
+    // products of the v and w moments that the entries share
+    const T a00 = v[0] * w[0], a10 = v[1] * w[0], a01 = v[0] * w[1], a20 = v[2] * w[0], a11 = v[1] * w[1];
+    const T a02 = v[0] * w[2], a30 = v[3] * w[0], a21 = v[2] * w[1], a12 = v[1] * w[2], a03 = v[0] * w[3];
+    const T a40 = v[4] * w[0], a22 = v[2] * w[2], a04 = v[0] * w[4];
+    Q.e[0] = u[0] * a00;
+    Q.e[1] = u[1] * a00;
+    Q.e[2] = u[0] * a10;
+    Q.e[3] = u[0] * a01;
+    Q.e[5] = u[2] * a00;
+    Q.e[6] = u[1] * a10;
+    Q.e[7] = u[1] * a01;
+    Q.e[9] = u[0] * a20;
+    Q.e[10] = u[0] * a11;
+    Q.e[12] = u[0] * a02;
+    const T tr = Q.e[5] + Q.e[9] + Q.e[12];  // <u^k v^l w^n (u^2 + v^2 + w^2)>
+    Q.e[4] = T(0.5) * (tr + M.s1 * Q.e[0]);
+    Q.e[8] = T(0.5) * (u[3] * a00 + u[1] * (a20 + a02) + M.s1 * Q.e[1]);
+    Q.e[11] = T(0.5) * (u[2] * a10 + u[0] * (a30 + a12) + M.s1 * Q.e[2]);
+    Q.e[13] = T(0.5) * (u[2] * a01 + u[0] * (a21 + a03) + M.s1 * Q.e[3]);
+    Q.e[14] = T(0.25) * (u[4] * a00 + u[0] * (a40 + a04 + T(2) * a22) + T(2) * u[2] * (a20 + a02) +
+                         M.s2 * Q.e[0] + T(2) * M.s1 * tr);
 }
 
-// <u^k v^l w^m s^2 psi>
-template <int k, int l, int n, typename T>
-__host__ __device__ __forceinline__ void Ps(const Mom<T> &M, T o[5])
+// o = Q a
+template <typename T>
+__host__ __device__ __forceinline__ void qmul(const Q5<T> &Q, const T a[5], T o[5])
 {
-    const T vw = M.v[l] * M.w[n];
-    const T base = M.u[k] * vw;
-    o[0] = base * M.s1;
-    o[1] = M.u[k + 1] * vw * M.s1;
-    o[2] = M.u[k] * M.v[l + 1] * M.w[n] * M.s1;
-    o[3] = M.u[k] * M.v[l] * M.w[n + 1] * M.s1;
-    o[4] = T(0.5) * ((M.u[k + 2] * vw + M.u[k] * M.v[l + 2] * M.w[n] + M.u[k] * M.v[l] * M.w[n + 2]) * M.s1 +
-                     base * M.s2);
+    const T *e = Q.e;
+    o[0] = e[0] * a[0] + e[1] * a[1] + e[2] * a[2] + e[3] * a[3] + e[4] * a[4];
+    o[1] = e[1] * a[0] + e[5] * a[1] + e[6] * a[2] + e[7] * a[3] + e[8] * a[4];
+    o[2] = e[2] * a[0] + e[6] * a[1] + e[9] * a[2] + e[10] * a[3] + e[11] * a[4];
+    o[3] = e[3] * a[0] + e[7] * a[1] + e[10] * a[2] + e[12] * a[3] + e[13] * a[4];
+    o[4] = e[4] * a[0] + e[8] * a[1] + e[11] * a[2] + e[13] * a[3] + e[14] * a[4];
 }
 
-// <u^k v^l w^m (a . psi) psi> for a slope a = (a1, a2, a3, a4, a5)
-template <int k, int l, int n, typename T>
-__host__ __device__ __forceinline__ void Pa(const Mom<T> &M, const T a[5], T o[5])
+// o += Q a
+template <typename T>
+__host__ __device__ __forceinline__ void qmul_add(const Q5<T> &Q, const T a[5], T o[5])
 {
     T t[5];
-    P<k, l, n>(M, t);
+    qmul(Q, a, t);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) o[j] = a[0] * t[j];
-    P<k + 1, l, n>(M, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) o[j] += a[1] * t[j];
-    P<k, l + 1, n>(M, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) o[j] += a[2] * t[j];
-    P<k, l, n + 1>(M, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) o[j] += a[3] * t[j];
-    T q[5];
-    P<k + 2, l, n>(M, q);
-    P<k, l + 2, n>(M, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) q[j] += t[j];
-    P<k, l, n + 2>(M, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) q[j] += t[j];
-    Ps<k, l, n>(M, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) o[j] += T(0.5) * a[4] * (q[j] + t[j]);
+    for (int j = 0; j < 5; ++j) o[j] += t[j];
 }
 
-// <u^k (a1.psi u + a2.psi v + a3.psi w) psi> for k = 0 (compatibility) or 1 (flux)
+// y += s * (first column of Q) = s * P<k,l,n>
+template <typename T>
+__host__ __device__ __forceinline__ void qcol0_axpy(const Q5<T> &Q, T s, T y[5])
+{
+    y[0] += s * Q.e[0];
+    y[1] += s * Q.e[1];
+    y[2] += s * Q.e[2];
+    y[3] += s * Q.e[3];
+    y[4] += s * Q.e[4];
+}
+
+// <u^k (a_1 . psi u + a_2 . psi v + a_3 . psi w) psi> for the three spatial slopes a (k = 0: the
+// compatibility condition's right-hand side; k = 1: the flux) =
+// <u^(k+1) psi psi^T> a_1 + <u^k v psi psi^T> a_2 + <u^k w psi psi^T> a_3
 template <int k, typename T>
-__host__ __device__ __forceinline__ void Padv(const Mom<T> &M, const T a[3][5], T o[5])
+__host__ __device__ __forceinline__ void qadv(const Mom<T> &M, const T a[3][5], T o[5])
 {
-    T t[5];
-    Pa<k + 1, 0, 0>(M, a[0], o);
-    Pa<k, 1, 0>(M, a[1], t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) o[j] += t[j];
-    Pa<k, 0, 1>(M, a[2], t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) o[j] += t[j];
+    Q5<T> Q;
+    qmat<k + 1, 0, 0>(M, Q);
+    qmul(Q, a[0], o);
+    qmat<k, 1, 0>(M, Q);
+    qmul_add(Q, a[1], o);
+    qmat<k, 0, 1>(M, Q);
+    qmul_add(Q, a[2], o);
 }
 
 // Closed-form solution of <psi psi^T> a = b for a Maxwellian (U, V, W, lambda).
@@ -287,33 +300,47 @@ __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5
     }
     if constexpr (!SM) {
         T b[5];
-        Padv<0>(M, a, b);
+        qadv<0>(M, a, b);
 #pragma unroll
         for (int j = 0; j < 5; ++j) b[j] = -b[j];
         slope_solve(b, U, V, W, lam, K, Ab);
     }
-    // half-space moments of u replace the full ones
+    // half-space moments of u replace the full ones; each moment matrix serves every slope
     mom_half_u(M, U, lam, sign);
     T t[5];
-    P<0, 0, 0>(M, t);
-    axpy5(A.q0, rho, t);
+    Q5<T> Q;
+    qmat<0, 0, 0>(M, Q);
+    qcol0_axpy(Q, rho, A.q0);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        Pa<0, 0, 0>(M, a[m], t);
+        qmul(Q, a[m], t);
         axpy5(A.bab[m], rho, t);
     }
     if constexpr (SM) return true;
-    P<1, 0, 0>(M, t);
-    axpy5(A.Mh, rho, t);
-    Padv<1>(M, a, t);
-    axpy5(A.Mha, rho, t);
-    Pa<1, 0, 0>(M, Ab, t);
-    axpy5(A.MhA, rho, t);
     if constexpr (PR) {
-        Padv<0>(M, a, t);
-        axpy5(A.Wha, rho, t);
-        Pa<0, 0, 0>(M, Ab, t);
+        qmul(Q, Ab, t);
         axpy5(A.WhA, rho, t);
+    }
+    T wa[5];  // qadv<0> of the half-space set (PR)
+    qmat<1, 0, 0>(M, Q);
+    qcol0_axpy(Q, rho, A.Mh);
+    qmul(Q, Ab, t);
+    axpy5(A.MhA, rho, t);
+    if constexpr (PR) qmul(Q, a[0], wa);
+    T ma[5];  // qadv<1> of the half-space set
+    qmat<2, 0, 0>(M, Q);
+    qmul(Q, a[0], ma);
+    qmat<1, 1, 0>(M, Q);
+    qmul_add(Q, a[1], ma);
+    qmat<1, 0, 1>(M, Q);
+    qmul_add(Q, a[2], ma);
+    axpy5(A.Mha, rho, ma);
+    if constexpr (PR) {
+        qmat<0, 1, 0>(M, Q);
+        qmul_add(Q, a[1], wa);
+        qmat<0, 0, 1>(M, Q);
+        qmul_add(Q, a[2], wa);
+        axpy5(A.Wha, rho, wa);
     }
     return true;
 }
@@ -344,11 +371,20 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
         for (int j = 0; j < 5; ++j) b[j] = A.bab[m][j] * ir0;
         slope_solve(b, U0, V0, W0, lam0, K, ab[m]);
     }
+    // qadv<0>(G, ab): the time slope's right-hand side (negated) and, with PR, a heat-flux moment
+    T pv[5];
+    Q5<T> Q1;  // <u psi psi^T> of g_0
+    qmat<1, 0, 0>(G, Q1);
     {
+        Q5<T> Q;
+        qmul(Q1, ab[0], pv);
+        qmat<0, 1, 0>(G, Q);
+        qmul_add(Q, ab[1], pv);
+        qmat<0, 0, 1>(G, Q);
+        qmul_add(Q, ab[2], pv);
         T b[5];
-        Padv<0>(G, ab, b);
 #pragma unroll
-        for (int j = 0; j < 5; ++j) b[j] = -b[j];
+        for (int j = 0; j < 5; ++j) b[j] = -pv[j];
         slope_solve(b, U0, V0, W0, lam0, K, Ab);
     }
     // collision time
@@ -360,14 +396,28 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
         if (fp.viscous && fp.mu_power != T(0)) mu *= pow_t(T(0.5) / lam0 * fp.iT_ref, fp.mu_power);
     const T tau = fp.viscous ? mu / p0 + fp.tau_C * jump : fp.tau_eps * dt + fp.tau_C * jump;
     T M0[5], Ma[5], MA[5];
-    P<1, 0, 0>(G, M0);
-    Padv<1>(G, ab, Ma);
-    Pa<1, 0, 0>(G, Ab, MA);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) M0[j] = Q1.e[j];
+    qmul(Q1, Ab, MA);
+    {
+        Q5<T> Q;
+        qmat<2, 0, 0>(G, Q);
+        qmul(Q, ab[0], Ma);
+        qmat<1, 1, 0>(G, Q);
+        qmul_add(Q, ab[1], Ma);
+        qmat<1, 0, 1>(G, Q);
+        qmul_add(Q, ab[2], Ma);
+    }
     T W0m[PR ? 5 : 1], Wam[PR ? 5 : 1], WAm[PR ? 5 : 1];
     if constexpr (PR) {
-        P<0, 0, 0>(G, W0m);
-        Padv<0>(G, ab, Wam);
-        Pa<0, 0, 0>(G, Ab, WAm);
+        Q5<T> Q;
+        qmat<0, 0, 0>(G, Q);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            W0m[j] = Q.e[j];
+            Wam[j] = pv[j];
+        }
+        qmul(Q, Ab, WAm);
     }
     T Fd[2][5];
     const T itau = T(1) / tau;

@@ -93,139 +93,10 @@ __host__ __device__ __forceinline__ void mom_half_u_b(const Mom<T> &M, MomB<T> &
     lamb += u0b * sign * U * g * ip / (T(2) * sl);
 }
 
-// reverse of P<k,l,n>: o_b -> moment cotangents
-template <int k, int l, int n, typename T>
-__host__ __device__ __forceinline__ void P_b(const Mom<T> &M, const T ob[5], MomB<T> &B)
-{
-    const T uk = M.u[k], vl = M.v[l], wn = M.w[n];
-    // o0 = uk vl wn
-    B.u[k] += ob[0] * vl * wn;
-    B.v[l] += ob[0] * uk * wn;
-    B.w[n] += ob[0] * uk * vl;
-    // o1 = u[k+1] vl wn
-    B.u[k + 1] += ob[1] * vl * wn;
-    B.v[l] += ob[1] * M.u[k + 1] * wn;
-    B.w[n] += ob[1] * M.u[k + 1] * vl;
-    // o2 = uk v[l+1] wn
-    B.u[k] += ob[2] * M.v[l + 1] * wn;
-    B.v[l + 1] += ob[2] * uk * wn;
-    B.w[n] += ob[2] * uk * M.v[l + 1];
-    // o3 = uk vl w[n+1]
-    B.u[k] += ob[3] * vl * M.w[n + 1];
-    B.v[l] += ob[3] * uk * M.w[n + 1];
-    B.w[n + 1] += ob[3] * uk * vl;
-    // o4 = (u[k+2] vl wn + uk v[l+2] wn + uk vl w[n+2] + uk vl wn s1) / 2
-    const T h4 = T(0.5) * ob[4];
-    B.u[k + 2] += h4 * vl * wn;
-    B.v[l] += h4 * M.u[k + 2] * wn;
-    B.w[n] += h4 * M.u[k + 2] * vl;
-    B.u[k] += h4 * M.v[l + 2] * wn;
-    B.v[l + 2] += h4 * uk * wn;
-    B.w[n] += h4 * uk * M.v[l + 2];
-    B.u[k] += h4 * vl * M.w[n + 2];
-    B.v[l] += h4 * uk * M.w[n + 2];
-    B.w[n + 2] += h4 * uk * vl;
-    B.u[k] += h4 * vl * wn * M.s1;
-    B.v[l] += h4 * uk * wn * M.s1;
-    B.w[n] += h4 * uk * vl * M.s1;
-    B.s1 += h4 * uk * vl * wn;
-}
-
-// reverse of Ps<k,l,n>
-template <int k, int l, int n, typename T>
-__host__ __device__ __forceinline__ void Ps_b(const Mom<T> &M, const T ob[5], MomB<T> &B)
-{
-    // o_j (j < 4) = P_j * s1; o4 = (sum of three) s1 / 2 + base s2 / 2
-    T pb[5];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) pb[j] = ob[j] * M.s1;
-    T t[5];
-    P<k, l, n>(M, t);
-    // P<>'s o4 includes base*s1/2, which Ps does not have in that form: handle the three
-    // squared-velocity terms through P_b with o0..o3 zeroed, then the base terms directly
-    const T uk = M.u[k], vl = M.v[l], wn = M.w[n];
-    const T base = uk * vl * wn;
-    const T three = T(2) * t[4] - base * M.s1;  // u[k+2] vl wn + uk v[l+2] wn + uk vl w[n+2]
-    B.s1 += ob[0] * t[0] + ob[1] * t[1] + ob[2] * t[2] + ob[3] * t[3] + T(0.5) * ob[4] * three;
-    B.s2 += T(0.5) * ob[4] * base;
-    // base s2 / 2
-    const T bb = T(0.5) * ob[4] * M.s2;
-    B.u[k] += bb * vl * wn;
-    B.v[l] += bb * uk * wn;
-    B.w[n] += bb * uk * vl;
-    // three * s1 / 2: same as P's o4 without its s1 term, scaled by s1
-    const T h4 = T(0.5) * ob[4] * M.s1;
-    B.u[k + 2] += h4 * vl * wn;
-    B.v[l] += h4 * M.u[k + 2] * wn;
-    B.w[n] += h4 * M.u[k + 2] * vl;
-    B.u[k] += h4 * M.v[l + 2] * wn;
-    B.v[l + 2] += h4 * uk * wn;
-    B.w[n] += h4 * uk * M.v[l + 2];
-    B.u[k] += h4 * vl * M.w[n + 2];
-    B.v[l] += h4 * uk * M.w[n + 2];
-    B.w[n + 2] += h4 * uk * vl;
-    // o0..o3 = P0..P3 * s1
-    T ob4[5] = {pb[0], pb[1], pb[2], pb[3], T(0)};
-    P_b<k, l, n>(M, ob4, B);
-}
-
 template <typename T>
 __host__ __device__ __forceinline__ T dot5(const T *a, const T *b)
 {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4];
-}
-
-// reverse of Pa<k,l,n>(M, a): o_b -> moment cotangents and a_b
-template <int k, int l, int n, typename T>
-__host__ __device__ __forceinline__ void Pa_b(const Mom<T> &M, const T a[5], const T ob[5], MomB<T> &B, T ab[5])
-{
-    T t[5], s[5];
-    P<k, l, n>(M, t);
-    ab[0] += dot5(ob, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = a[0] * ob[j];
-    P_b<k, l, n>(M, s, B);
-    P<k + 1, l, n>(M, t);
-    ab[1] += dot5(ob, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = a[1] * ob[j];
-    P_b<k + 1, l, n>(M, s, B);
-    P<k, l + 1, n>(M, t);
-    ab[2] += dot5(ob, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = a[2] * ob[j];
-    P_b<k, l + 1, n>(M, s, B);
-    P<k, l, n + 1>(M, t);
-    ab[3] += dot5(ob, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = a[3] * ob[j];
-    P_b<k, l, n + 1>(M, s, B);
-    T q[5];
-    P<k + 2, l, n>(M, q);
-    P<k, l + 2, n>(M, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) q[j] += t[j];
-    P<k, l, n + 2>(M, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) q[j] += t[j];
-    Ps<k, l, n>(M, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) q[j] += t[j];
-    ab[4] += T(0.5) * dot5(ob, q);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = T(0.5) * a[4] * ob[j];
-    P_b<k + 2, l, n>(M, s, B);
-    P_b<k, l + 2, n>(M, s, B);
-    P_b<k, l, n + 2>(M, s, B);
-    Ps_b<k, l, n>(M, s, B);
-}
-
-template <int k, typename T>
-__host__ __device__ __forceinline__ void Padv_b(const Mom<T> &M, const T a[3][5], const T ob[5], MomB<T> &B, T ab[3][5])
-{
-    Pa_b<k + 1, 0, 0>(M, a[0], ob, B, ab[0]);
-    Pa_b<k, 1, 0>(M, a[1], ob, B, ab[1]);
-    Pa_b<k, 0, 1>(M, a[2], ob, B, ab[2]);
 }
 
 // reverse of slope_solve: a_b -> b_b and state cotangents (a: the forward result)
@@ -293,6 +164,105 @@ __host__ __device__ __forceinline__ void slope_solve_b(const T b[5], T U, T V, T
     Vb += T(2) * V * qb;
     Wb += T(2) * W * qb;
     lamb += -(K + T(3)) / (T(2) * lam * lam) * qb;
+}
+
+// Reverses of the moment-matrix products.  A matrix's cotangent Qb (same symmetric layout) gathers
+// the cotangents of every product that used the matrix; qmat_b then takes it to the moments once.
+template <typename T>
+__host__ __device__ __forceinline__ void q5_zero(Q5<T> &Q)
+{
+#pragma unroll
+    for (int e = 0; e < 15; ++e) Q.e[e] = T(0);
+}
+
+// reverse of o = Q a (or o += Q a): Qb += cotangent of Q, ab += Q ob
+template <typename T>
+__host__ __device__ __forceinline__ void qmul_b(const Q5<T> &Q, const T a[5], const T ob[5], Q5<T> &Qb, T ab[5])
+{
+    T *g = Qb.e;
+    g[0] += ob[0] * a[0];
+    g[1] += ob[0] * a[1] + ob[1] * a[0];
+    g[2] += ob[0] * a[2] + ob[2] * a[0];
+    g[3] += ob[0] * a[3] + ob[3] * a[0];
+    g[4] += ob[0] * a[4] + ob[4] * a[0];
+    g[5] += ob[1] * a[1];
+    g[6] += ob[1] * a[2] + ob[2] * a[1];
+    g[7] += ob[1] * a[3] + ob[3] * a[1];
+    g[8] += ob[1] * a[4] + ob[4] * a[1];
+    g[9] += ob[2] * a[2];
+    g[10] += ob[2] * a[3] + ob[3] * a[2];
+    g[11] += ob[2] * a[4] + ob[4] * a[2];
+    g[12] += ob[3] * a[3];
+    g[13] += ob[3] * a[4] + ob[4] * a[3];
+    g[14] += ob[4] * a[4];
+    qmul_add(Q, ob, ab);
+}
+
+// reverse of y += s * (first column of Q) for the cotangent yb (the cotangent of s is left out)
+template <typename T>
+__host__ __device__ __forceinline__ void qcol0_b(T s, const T yb[5], Q5<T> &Qb)
+{
+#pragma unroll
+    for (int j = 0; j < 5; ++j) Qb.e[j] += s * yb[j];
+}
+
+// sum over the entries of Q times Qb
+template <typename T>
+__host__ __device__ __forceinline__ T q5_dot(const Q5<T> &Q, const Q5<T> &Qb)
+{
+    T s = Q.e[0] * Qb.e[0];
+#pragma unroll
+    for (int e = 1; e < 15; ++e) s += Q.e[e] * Qb.e[e];
+    return s;
+}
+
+// reverse of qmat<k,l,n>: matrix cotangent -> moment cotangents
+template <int k, int l, int n, typename T>
+__host__ __device__ __forceinline__ void qmat_b(const Mom<T> &M, const Q5<T> &Qb, MomB<T> &B)
+{
+    const T *u = M.u + k, *v = M.v + l, *w = M.w + n;
+    const T a00 = v[0] * w[0], a10 = v[1] * w[0], a01 = v[0] * w[1], a20 = v[2] * w[0], a11 = v[1] * w[1];
+    const T a02 = v[0] * w[2], a30 = v[3] * w[0], a21 = v[2] * w[1], a12 = v[1] * w[2], a03 = v[0] * w[3];
+    const T a40 = v[4] * w[0], a22 = v[2] * w[2], a04 = v[0] * w[4];
+    const T e0 = u[0] * a00, e1 = u[1] * a00, e2 = u[0] * a10, e3 = u[0] * a01;
+    const T tr = u[2] * a00 + u[0] * a20 + u[0] * a02;
+    const T *g = Qb.e;
+    // the entries with psi_4 first: their parts in the other entries, s1, s2 and the raw factors
+    const T h4 = T(0.5) * g[4], h8 = T(0.5) * g[8], h11 = T(0.5) * g[11], h13 = T(0.5) * g[13], q = T(0.25) * g[14];
+    const T trb = h4 + T(2) * q * M.s1;
+    B.s1 += h4 * e0 + h8 * e1 + h11 * e2 + h13 * e3 + T(2) * q * tr;
+    B.s2 += q * e0;
+    const T g0 = g[0] + h4 * M.s1 + q * M.s2, g1 = g[1] + h8 * M.s1, g2 = g[2] + h11 * M.s1, g3 = g[3] + h13 * M.s1;
+    const T g5 = g[5] + trb, g9 = g[9] + trb, g12 = g[12] + trb;
+    // cotangents of the u moments
+    T ub[5];
+    ub[0] = g0 * a00 + g2 * a10 + g3 * a01 + g9 * a20 + g[10] * a11 + g12 * a02 + h11 * (a30 + a12) +
+            h13 * (a21 + a03) + q * (a40 + a04 + T(2) * a22);
+    ub[1] = g1 * a00 + g[6] * a10 + g[7] * a01 + h8 * (a20 + a02);
+    ub[2] = g5 * a00 + h11 * a10 + h13 * a01 + T(2) * q * (a20 + a02);
+    ub[3] = h8 * a00;
+    ub[4] = q * a00;
+    // cotangents of the v w products
+    const T b00 = g0 * u[0] + g1 * u[1] + g5 * u[2] + h8 * u[3] + q * u[4];
+    const T b10 = g2 * u[0] + g[6] * u[1] + h11 * u[2];
+    const T b01 = g3 * u[0] + g[7] * u[1] + h13 * u[2];
+    const T b20 = g9 * u[0] + h8 * u[1] + T(2) * q * u[2];
+    const T b02 = g12 * u[0] + h8 * u[1] + T(2) * q * u[2];
+    const T b11 = g[10] * u[0];
+    const T b30 = h11 * u[0], b12 = h11 * u[0], b21 = h13 * u[0], b03 = h13 * u[0];
+    const T b40 = q * u[0], b04 = q * u[0], b22 = T(2) * q * u[0];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) B.u[k + i] += ub[i];
+    B.v[l] += b00 * w[0] + b01 * w[1] + b02 * w[2] + b03 * w[3] + b04 * w[4];
+    B.v[l + 1] += b10 * w[0] + b11 * w[1] + b12 * w[2];
+    B.v[l + 2] += b20 * w[0] + b21 * w[1] + b22 * w[2];
+    B.v[l + 3] += b30 * w[0];
+    B.v[l + 4] += b40 * w[0];
+    B.w[n] += b00 * v[0] + b10 * v[1] + b20 * v[2] + b30 * v[3] + b40 * v[4];
+    B.w[n + 1] += b01 * v[0] + b11 * v[1] + b21 * v[2];
+    B.w[n + 2] += b02 * v[0] + b12 * v[1] + b22 * v[2];
+    B.w[n + 3] += b03 * v[0];
+    B.w[n + 4] += b04 * v[0];
 }
 
 // reverse of to_prim
@@ -385,7 +355,7 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
     }
     {
         T bA[5];
-        Padv<0>(M, a, bA);
+        qadv<0>(M, a, bA);
 #pragma unroll
         for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
         slope_solve(bA, U, V, W, lam, K, Av);
@@ -401,70 +371,102 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
         Avb[j] = T(0);
         ab[0][j] = ab[1][j] = ab[2][j] = T(0);
     }
-    T t[5], s[5], g[5];
-    P<0, 0, 0>(M, t);
-    ld(kSlotQ0, g);
-    rhob += dot5(g, t);
+    // Every half-space accumulation is rho times a moment-matrix product; the matrix's cotangent
+    // gathers the rho-scaled slot cotangents of all its products, and rho's cotangent is
+    // sum(Q Qb) / rho.
+    T g[5], s[5], sw[5];
+    auto scaled = [&](int slot, T o[5]) {
+        ld(slot, g);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
-    P_b<0, 0, 0>(M, s, B);
+        for (int j = 0; j < 5; ++j) o[j] = rho * g[j];
+    };
+    Q5<T> Q, Qb;
+    // <psi psi^T>: q0 (first column), bab[m] (a[m]), WhA (Av, PR)
+    qmat<0, 0, 0>(M, Q);
+    q5_zero(Qb);
+    scaled(kSlotQ0, s);
+    qcol0_b(T(1), s, Qb);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        Pa<0, 0, 0>(M, a[m], t);
-        ld(kSlotBab + 5 * m, g);
-        rhob += dot5(g, t);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
-        Pa_b<0, 0, 0>(M, a[m], s, B, ab[m]);
+        scaled(kSlotBab + 5 * m, s);
+        qmul_b(Q, a[m], s, Qb, ab[m]);
     }
-    P<1, 0, 0>(M, t);
-    ld(kSlotMh, g);
-    rhob += dot5(g, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
-    P_b<1, 0, 0>(M, s, B);
-    Padv<1>(M, a, t);
-    ld(kSlotMha, g);
-    rhob += dot5(g, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
-    Padv_b<1>(M, a, s, B, ab);
-    Pa<1, 0, 0>(M, Av, t);
-    ld(kSlotMhA, g);
-    rhob += dot5(g, t);
-#pragma unroll
-    for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
-    Pa_b<1, 0, 0>(M, Av, s, B, Avb);
     if constexpr (PR) {
-        Padv<0>(M, a, t);
-        ld(kSlotWha, g);
-        rhob += dot5(g, t);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
-        Padv_b<0>(M, a, s, B, ab);
-        Pa<0, 0, 0>(M, Av, t);
-        ld(kSlotWhA, g);
-        rhob += dot5(g, t);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) s[j] = rho * g[j];
-        Pa_b<0, 0, 0>(M, Av, s, B, Avb);
+        scaled(kSlotWhA, s);
+        qmul_b(Q, Av, s, Qb, Avb);
+    }
+    rhob += ir * q5_dot(Q, Qb);
+    qmat_b<0, 0, 0>(M, Qb, B);
+    // <u psi psi^T>: Mh (first column), MhA (Av), with PR the a[0] term of Wha
+    qmat<1, 0, 0>(M, Q);
+    q5_zero(Qb);
+    scaled(kSlotMh, s);
+    qcol0_b(T(1), s, Qb);
+    scaled(kSlotMhA, s);
+    qmul_b(Q, Av, s, Qb, Avb);
+    if constexpr (PR) {
+        scaled(kSlotWha, sw);
+        qmul_b(Q, a[0], sw, Qb, ab[0]);
+    }
+    rhob += ir * q5_dot(Q, Qb);
+    qmat_b<1, 0, 0>(M, Qb, B);
+    // Mha = <u^2 psi psi^T> a[0] + <u v psi psi^T> a[1] + <u w psi psi^T> a[2]
+    scaled(kSlotMha, s);
+    qmat<2, 0, 0>(M, Q);
+    q5_zero(Qb);
+    qmul_b(Q, a[0], s, Qb, ab[0]);
+    rhob += ir * q5_dot(Q, Qb);
+    qmat_b<2, 0, 0>(M, Qb, B);
+    qmat<1, 1, 0>(M, Q);
+    q5_zero(Qb);
+    qmul_b(Q, a[1], s, Qb, ab[1]);
+    rhob += ir * q5_dot(Q, Qb);
+    qmat_b<1, 1, 0>(M, Qb, B);
+    qmat<1, 0, 1>(M, Q);
+    q5_zero(Qb);
+    qmul_b(Q, a[2], s, Qb, ab[2]);
+    rhob += ir * q5_dot(Q, Qb);
+    qmat_b<1, 0, 1>(M, Qb, B);
+    if constexpr (PR) {
+        // the v and w terms of Wha
+        qmat<0, 1, 0>(M, Q);
+        q5_zero(Qb);
+        qmul_b(Q, a[1], sw, Qb, ab[1]);
+        rhob += ir * q5_dot(Q, Qb);
+        qmat_b<0, 1, 0>(M, Qb, B);
+        qmat<0, 0, 1>(M, Q);
+        q5_zero(Qb);
+        qmul_b(Q, a[2], sw, Qb, ab[2]);
+        rhob += ir * q5_dot(Q, Qb);
+        qmat_b<0, 0, 1>(M, Qb, B);
     }
     // half-space u moments done: their cotangents go to U and lambda, then the full set returns
     mom_half_u_b(M, B, U, lam, sign, Ub, lamb);
 #pragma unroll
     for (int k = 0; k < 7; ++k) B.u[k] = T(0);
     mom_full_u(M, U, lam);
-    // Av = solve(-Padv0(M, a))
+    // Av = solve(-qadv<0>(M, a))
     {
         T bA[5];
-        Padv<0>(M, a, bA);
+        qadv<0>(M, a, bA);
 #pragma unroll
         for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
         T bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
         slope_solve_b(bA, U, V, W, lam, K, Av, Avb, bAb, Ub, Vb, Wb, lamb);
 #pragma unroll
         for (int j = 0; j < 5; ++j) bAb[j] = -bAb[j];
-        Padv_b<0>(M, a, bAb, B, ab);
+        qmat<1, 0, 0>(M, Q);
+        q5_zero(Qb);
+        qmul_b(Q, a[0], bAb, Qb, ab[0]);
+        qmat_b<1, 0, 0>(M, Qb, B);
+        qmat<0, 1, 0>(M, Q);
+        q5_zero(Qb);
+        qmul_b(Q, a[1], bAb, Qb, ab[1]);
+        qmat_b<0, 1, 0>(M, Qb, B);
+        qmat<0, 0, 1>(M, Q);
+        q5_zero(Qb);
+        qmul_b(Q, a[2], bAb, Qb, ab[2]);
+        qmat_b<0, 0, 1>(M, Qb, B);
     }
     // a[m] = solve(dq[m] / rho)
 #pragma unroll
@@ -534,11 +536,12 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         for (int j = 0; j < 5; ++j) bm[j] = A.bab[m][j] * ir0;
         slope_solve(bm, U0, V0, W0, lam0, K, ab[m]);
     }
+    T pv[5];  // qadv<0>(G, ab): the time slope's right-hand side (negated), with PR a heat-flux moment
+    qadv<0>(G, ab, pv);
     {
         T bA[5];
-        Padv<0>(G, ab, bA);
 #pragma unroll
-        for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
+        for (int j = 0; j < 5; ++j) bA[j] = -pv[j];
         slope_solve(bA, U0, V0, W0, lam0, K, Av);
     }
     const T dp = (A.p[0] - A.p[1]) / (A.p[0] + A.p[1]);
@@ -621,25 +624,29 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
     };
     {
         T X[5];
-        P<1, 0, 0>(G, X);
+        Q5<T> Q;
+        qmat<1, 0, 0>(G, Q);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) X[j] = Q.e[j];
         fterm(X, 0, r0);
         r0b += Tc[0][0] * dot5(Fb[0], X) + Tc[1][0] * dot5(Fb[1], X);
-        Padv<1>(G, ab, X);
-        fterm(X, 1, r0);
-        r0b += Tc[0][1] * dot5(Fb[0], X) + Tc[1][1] * dot5(Fb[1], X);
-        Pa<1, 0, 0>(G, Av, X);
+        qmul(Q, Av, X);
         fterm(X, 2, r0);
         r0b += Tc[0][2] * dot5(Fb[0], X) + Tc[1][2] * dot5(Fb[1], X);
+        qadv<1>(G, ab, X);
+        fterm(X, 1, r0);
+        r0b += Tc[0][1] * dot5(Fb[0], X) + Tc[1][1] * dot5(Fb[1], X);
         if constexpr (PR) {
-            P<0, 0, 0>(G, X);
+            qmat<0, 0, 0>(G, Q);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) X[j] = Q.e[j];
             wterm(X, 0, r0);
             r0b += (Tc[0][0] * w[0] + Tc[1][0] * w[1]) * dot5(e, X);
-            Padv<0>(G, ab, X);
-            wterm(X, 1, r0);
-            r0b += (Tc[0][1] * w[0] + Tc[1][1] * w[1]) * dot5(e, X);
-            Pa<0, 0, 0>(G, Av, X);
+            qmul(Q, Av, X);
             wterm(X, 2, r0);
             r0b += (Tc[0][2] * w[0] + Tc[1][2] * w[1]) * dot5(e, X);
+            wterm(pv, 1, r0);
+            r0b += (Tc[0][1] * w[0] + Tc[1][1] * w[1]) * dot5(e, pv);
         }
     }
     fterm(A.Mh, 3, T(1));
@@ -683,43 +690,70 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         Avb[j] = T(0);
         abb[0][j] = abb[1][j] = abb[2][j] = T(0);
     }
-    {
-        T ob[5];
+    // g_0's moment matrices, each reversed once: <u psi psi^T> serves <u psi> (ob0), <u (Av . psi) psi>
+    // (ob2) and the a[0] term of qadv<0>(G, ab) (pvb: the time slope's and, with PR, W's cotangent)
+    T ob0[5], ob1[5], ob2[5], pvb[5];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) ob[j] = r0 * (Tc[0][0] * Fb[0][j] + Tc[1][0] * Fb[1][j]);
-        P_b<1, 0, 0>(G, ob, Bg);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) ob[j] = r0 * (Tc[0][1] * Fb[0][j] + Tc[1][1] * Fb[1][j]);
-        Padv_b<1>(G, ab, ob, Bg, abb);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) ob[j] = r0 * (Tc[0][2] * Fb[0][j] + Tc[1][2] * Fb[1][j]);
-        Pa_b<1, 0, 0>(G, Av, ob, Bg, Avb);
-        if constexpr (PR) {
-            T c = r0 * (Tc[0][0] * w[0] + Tc[1][0] * w[1]);
-#pragma unroll
-            for (int j = 0; j < 5; ++j) ob[j] = c * e[j];
-            P_b<0, 0, 0>(G, ob, Bg);
-            c = r0 * (Tc[0][1] * w[0] + Tc[1][1] * w[1]);
-#pragma unroll
-            for (int j = 0; j < 5; ++j) ob[j] = c * e[j];
-            Padv_b<0>(G, ab, ob, Bg, abb);
-            c = r0 * (Tc[0][2] * w[0] + Tc[1][2] * w[1]);
-#pragma unroll
-            for (int j = 0; j < 5; ++j) ob[j] = c * e[j];
-            Pa_b<0, 0, 0>(G, Av, ob, Bg, Avb);
-        }
+    for (int j = 0; j < 5; ++j) {
+        ob0[j] = r0 * (Tc[0][0] * Fb[0][j] + Tc[1][0] * Fb[1][j]);
+        ob1[j] = r0 * (Tc[0][1] * Fb[0][j] + Tc[1][1] * Fb[1][j]);
+        ob2[j] = r0 * (Tc[0][2] * Fb[0][j] + Tc[1][2] * Fb[1][j]);
+        pvb[j] = T(0);
     }
-    // Av = solve(-Padv0(G, ab))
+    Q5<T> Q, Qb, Q1, Qb1;
+    if constexpr (PR) {
+        const T c0 = r0 * (Tc[0][0] * w[0] + Tc[1][0] * w[1]);
+        const T c1 = r0 * (Tc[0][1] * w[0] + Tc[1][1] * w[1]);
+        const T c2 = r0 * (Tc[0][2] * w[0] + Tc[1][2] * w[1]);
+        T o2[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            o2[j] = c2 * e[j];
+            pvb[j] = c1 * e[j];
+        }
+        qmat<0, 0, 0>(G, Q);
+        q5_zero(Qb);
+        qcol0_b(c0, e, Qb);
+        qmul_b(Q, Av, o2, Qb, Avb);
+        qmat_b<0, 0, 0>(G, Qb, Bg);
+    }
+    qmat<1, 0, 0>(G, Q1);
+    q5_zero(Qb1);
+    qcol0_b(T(1), ob0, Qb1);
+    qmul_b(Q1, Av, ob2, Qb1, Avb);
+    // qadv<1>(G, ab)
+    qmat<2, 0, 0>(G, Q);
+    q5_zero(Qb);
+    qmul_b(Q, ab[0], ob1, Qb, abb[0]);
+    qmat_b<2, 0, 0>(G, Qb, Bg);
+    qmat<1, 1, 0>(G, Q);
+    q5_zero(Qb);
+    qmul_b(Q, ab[1], ob1, Qb, abb[1]);
+    qmat_b<1, 1, 0>(G, Qb, Bg);
+    qmat<1, 0, 1>(G, Q);
+    q5_zero(Qb);
+    qmul_b(Q, ab[2], ob1, Qb, abb[2]);
+    qmat_b<1, 0, 1>(G, Qb, Bg);
+    // Av = solve(-pv)
     {
         T bA[5], bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
-        Padv<0>(G, ab, bA);
 #pragma unroll
-        for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
+        for (int j = 0; j < 5; ++j) bA[j] = -pv[j];
         slope_solve_b(bA, U0, V0, W0, lam0, K, Av, Avb, bAb, U0b, V0b, W0b, lam0b);
 #pragma unroll
-        for (int j = 0; j < 5; ++j) bAb[j] = -bAb[j];
-        Padv_b<0>(G, ab, bAb, Bg, abb);
+        for (int j = 0; j < 5; ++j) pvb[j] -= bAb[j];
     }
+    // pv = qadv<0>(G, ab)
+    qmul_b(Q1, ab[0], pvb, Qb1, abb[0]);
+    qmat_b<1, 0, 0>(G, Qb1, Bg);
+    qmat<0, 1, 0>(G, Q);
+    q5_zero(Qb);
+    qmul_b(Q, ab[1], pvb, Qb, abb[1]);
+    qmat_b<0, 1, 0>(G, Qb, Bg);
+    qmat<0, 0, 1>(G, Q);
+    q5_zero(Qb);
+    qmul_b(Q, ab[2], pvb, Qb, abb[2]);
+    qmat_b<0, 0, 1>(G, Qb, Bg);
     // ab[m] = solve(bab[m] / r0)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {

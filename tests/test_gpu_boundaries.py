@@ -4,7 +4,8 @@ Lid-driven cavity with isothermal no-slip walls (the paper's cavity setup at sma
 no-slip walls with a moving wall, far field by Riemann invariants (subsonic and supersonic free
 streams carrying a density wave), and zero-gradient ends with reflective side walls (the paper's
 shock-tube setup, with the first-order fallback).  Both sides take the oracle's step sizes; FP64 bar:
-relative L-infinity per component <= 1e-12 (momentum components sharing max |rho U|).
+relative L-infinity per component <= 1e-12 (momentum components sharing max |rho U|); FP32-mixed
+bar 1e-4 (the cavities' momentum on the lid's scale rho u_lid).
 """
 import math
 
@@ -90,7 +91,12 @@ def test_boundary_conditions_match_oracle(gks, name):
     host = gks.HostMesh(mesh)
     scale = np.abs(ref).max(axis=1)
     scale[1:4] = scale[1:4].max()
-    for prec, tol in ((gks.FP64, 1e-12), (gks.FP32_MIXED, 1e-4)):
+    # FP32 rounds the cavity's momentum on the scale of the lid's (rho u_lid), not of the small
+    # momentum that has developed after a few steps
+    scale32 = scale.copy()
+    if name.startswith("cavity"):
+        scale32[1:4] = max(scale[1], 1.0 * 0.15)
+    for prec, tol, sc in ((gks.FP64, 1e-12, scale), (gks.FP32_MIXED, 1e-4, scale32)):
         sol = gks.Solver(host, gks.params(precision=prec, bc=gbc, **kw))
         Q = sol.upload(host.to_internal(Q0))
         for dt in dts:
@@ -98,7 +104,7 @@ def test_boundary_conditions_match_oracle(gks, name):
         sol.poll()
         torch.cuda.synchronize()
         got = host.to_external(Q.cpu().numpy())
-        err = np.abs(got - ref).max(axis=1) / scale
+        err = np.abs(got - ref).max(axis=1) / sc
         print(name, "FP64" if prec == gks.FP64 else "FP32-mixed", "relative Linf per component:", err, flush=True)
         assert (err <= tol).all(), err
         if kw.get("fallback"):
