@@ -86,11 +86,10 @@ __host__ __device__ __forceinline__ double sqrt_t<double>(double x) { return sqr
 template <>
 __host__ __device__ __forceinline__ float sqrt_t<float>(float x) { return sqrtf(x); }
 
-// Full-space v, w, internal moments (shared by full and half-space sets of one state).
+// Full-space v, w, internal moments (shared by full and half-space sets of one state); h = 1 / (2 lambda).
 template <typename T>
-__host__ __device__ __forceinline__ void mom_common(Mom<T> &m, T V, T W, T lam, T K)
+__host__ __device__ __forceinline__ void mom_common(Mom<T> &m, T V, T W, T h, T K)
 {
-    const T h = T(0.5) / lam;
     m.v[0] = T(1);
     m.v[1] = V;
     recur6(m.v, V, h);
@@ -102,22 +101,56 @@ __host__ __device__ __forceinline__ void mom_common(Mom<T> &m, T V, T W, T lam, 
 }
 
 template <typename T>
-__host__ __device__ __forceinline__ void mom_full_u(Mom<T> &m, T U, T lam)
+__host__ __device__ __forceinline__ void mom_full_u(Mom<T> &m, T U, T h)
 {
     m.u[0] = T(1);
     m.u[1] = U;
-    recur7(m.u, U, T(0.5) / lam);
+    recur7(m.u, U, h);
 }
 
-// sign = +1: u > 0, -1: u < 0
-template <typename T>
-__host__ __device__ __forceinline__ void mom_half_u(Mom<T> &m, T U, T lam, T sign)
+// erfc(x): for |x| < 1 from the Maclaurin series of erf (erf x = 2/sqrt(pi) sum_n (-1)^n x^(2n+1) /
+// (n! (2n+1)), Abramowitz & Stegun 7.1.5), truncated where the next term is below the type's rounding
+// (the coefficients are that formula, evaluated by the compiler); beyond, the library's erfc.
+constexpr double erf_series_coef(int n)
 {
-    const T sl = sqrt_t(lam);
-    const T e = exp_t(-lam * U * U) / (T(2) * sqrt_t(T(M_PI) * lam));
-    m.u[0] = T(0.5) * erfc_t(-sign * sl * U);
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return (n % 2 ? -1.0 : 1.0) / (f * (2 * n + 1));
+}
+
+// the library's erfc out of line: lanes that need it are rare, and inlined it would hold registers
+// across the whole flux
+template <typename T>
+__host__ __device__ __attribute__((noinline)) T erfc_outline(T x)
+{
+    return erfc_t(x);
+}
+
+template <typename T>
+__host__ __device__ __forceinline__ T erfc_half(T x)
+{
+    constexpr int N = sizeof(T) == 8 ? 18 : 10;  // |term N+1| < 5e-18 (FP64), 1e-9 (FP32) for |x| < 1
+    if (x < T(1) && x > T(-1)) {
+        const T z = x * x;
+        T s = T(erf_series_coef(N));
+#pragma unroll
+        for (int n = N - 1; n >= 0; --n) s = s * z + T(erf_series_coef(n));
+        return T(1) - T(M_2_SQRTPI) * x * s;
+    }
+    return erfc_outline(x);
+}
+
+// sign = +1: u > 0, -1: u < 0.  One square root gives both sqrt(lambda) and its inverse:
+// sqrt(2 h) = 1 / sqrt(lambda).
+template <typename T>
+__host__ __device__ __forceinline__ void mom_half_u(Mom<T> &m, T U, T lam, T h, T sign)
+{
+    const T isl = sqrt_t(T(2) * h);
+    const T sl = lam * isl;
+    const T e = exp_t(-lam * U * U) * (T(0.25 * M_2_SQRTPI) * isl);  // exp(-lambda U^2) / (2 sqrt(pi lambda))
+    m.u[0] = T(0.5) * erfc_half(-sign * sl * U);
     m.u[1] = U * m.u[0] + sign * e;
-    recur7(m.u, U, T(0.5) / lam);
+    recur7(m.u, U, h);
 }
 
 // The symmetric moment matrix Q = <u^k v^l w^n psi psi^T> of one moment set, upper triangle by
@@ -206,11 +239,11 @@ __host__ __device__ __forceinline__ void qadv(const Mom<T> &M, const T a[3][5], 
 
 // Closed-form solution of <psi psi^T> a = b for a Maxwellian (U, V, W, lambda).
 template <typename T>
-__host__ __device__ __forceinline__ void slope_solve(const T b[5], T U, T V, T W, T lam, T K, T a[5])
+__host__ __device__ __forceinline__ void slope_solve(const T b[5], T U, T V, T W, T lam, T h, T K, T a[5])
 {
-    // 1 / (2 lambda) is the moments' recursion factor and 1 / (K + 3) a constant of the launch:
-    // both are shared, no division of its own
-    const T q = U * U + V * V + W * W + (K + T(3)) * (T(0.5) / lam);
+    // h = 1 / (2 lambda) is the moments' recursion factor and 1 / (K + 3) a constant of the launch:
+    // no division of its own
+    const T q = U * U + V * V + W * W + (K + T(3)) * h;
     const T R2 = b[1] - U * b[0], R3 = b[2] - V * b[0], R4 = b[3] - W * b[0];
     const T R5 = T(2) * b[4] - q * b[0];
     a[4] = T(4) * lam * lam * (T(1) / (K + T(3))) * (R5 - T(2) * (U * R2 + V * R3 + W * R4));
@@ -222,7 +255,7 @@ __host__ __device__ __forceinline__ void slope_solve(const T b[5], T U, T V, T W
 
 // primitive variables; returns false for a non-physical state
 template <typename T>
-__host__ __device__ __forceinline__ bool to_prim(const T q[5], T gam, T &rho, T &U, T &V, T &W, T &lam, T &p)
+__host__ __device__ __forceinline__ bool to_prim(const T q[5], T gam, T &rho, T &U, T &V, T &W, T &lam, T &p, T &h)
 {
     rho = q[0];
     const T ir = T(1) / rho;
@@ -231,6 +264,7 @@ __host__ __device__ __forceinline__ bool to_prim(const T q[5], T gam, T &rho, T 
     W = q[3] * ir;
     p = (gam - T(1)) * (q[4] - T(0.5) * rho * (U * U + V * V + W * W));
     lam = rho / (T(2) * p);
+    h = p * ir;  // 1 / (2 lambda)
     return rho > T(0) && p > T(0);
 }
 
@@ -281,13 +315,13 @@ __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5
                                                    FluxAcc<T, PR> &A, int side)
 {
     const T K = fp.K;
-    T rho, U, V, W, lam, p;
-    const bool ok = to_prim(q, fp.gamma, rho, U, V, W, lam, p);
+    T rho, U, V, W, lam, p, h;
+    const bool ok = to_prim(q, fp.gamma, rho, U, V, W, lam, p, h);
     A.p[side] = p;
     if (!ok) return false;
     Mom<T> M;
-    mom_common(M, V, W, lam, K);
-    if constexpr (!SM) mom_full_u(M, U, lam);
+    mom_common(M, V, W, h, K);
+    if constexpr (!SM) mom_full_u(M, U, h);
     // spatial slopes <a_m> = dQ/dn_m / rho, time slope from <a_1 u + a_2 v + a_3 w + A> = 0
     T a[3][5], Ab[5];
     const T ir = T(1) / rho;
@@ -296,17 +330,17 @@ __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5
         T b[5];
 #pragma unroll
         for (int j = 0; j < 5; ++j) b[j] = dq[m][j] * ir;
-        slope_solve(b, U, V, W, lam, K, a[m]);
+        slope_solve(b, U, V, W, lam, h, K, a[m]);
     }
     if constexpr (!SM) {
         T b[5];
         qadv<0>(M, a, b);
 #pragma unroll
         for (int j = 0; j < 5; ++j) b[j] = -b[j];
-        slope_solve(b, U, V, W, lam, K, Ab);
+        slope_solve(b, U, V, W, lam, h, K, Ab);
     }
     // half-space moments of u replace the full ones; each moment matrix serves every slope
-    mom_half_u(M, U, lam, sign);
+    mom_half_u(M, U, lam, h, sign);
     T t[5];
     Q5<T> Q;
     qmat<0, 0, 0>(M, Q);
@@ -357,11 +391,11 @@ template <typename T, bool PR, bool SM = false, bool PL = true>
 __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T dt, const FluxParams<T> &fp, T out[10])
 {
     const T K = fp.K;
-    T r0, U0, V0, W0, lam0, p0;
-    const bool ok = to_prim(A.q0, fp.gamma, r0, U0, V0, W0, lam0, p0);
+    T r0, U0, V0, W0, lam0, p0, h0;
+    const bool ok = to_prim(A.q0, fp.gamma, r0, U0, V0, W0, lam0, p0, h0);
     Mom<T> G;
-    mom_common(G, V0, W0, lam0, K);
-    mom_full_u(G, U0, lam0);
+    mom_common(G, V0, W0, h0, K);
+    mom_full_u(G, U0, h0);
     T ab[3][5], Ab[5];
     const T ir0 = T(1) / r0;
 #pragma unroll
@@ -369,7 +403,7 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
         T b[5];
 #pragma unroll
         for (int j = 0; j < 5; ++j) b[j] = A.bab[m][j] * ir0;
-        slope_solve(b, U0, V0, W0, lam0, K, ab[m]);
+        slope_solve(b, U0, V0, W0, lam0, h0, K, ab[m]);
     }
     // qadv<0>(G, ab): the time slope's right-hand side (negated) and, with PR, a heat-flux moment
     T pv[5];
@@ -385,7 +419,7 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
         T b[5];
 #pragma unroll
         for (int j = 0; j < 5; ++j) b[j] = -pv[j];
-        slope_solve(b, U0, V0, W0, lam0, K, Ab);
+        slope_solve(b, U0, V0, W0, lam0, h0, K, Ab);
     }
     // collision time
     const T dp = (A.p[0] - A.p[1]) / (A.p[0] + A.p[1]);
@@ -393,7 +427,7 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
     // viscosity at the interface temperature T0 = p0 / rho0 = 1 / (2 lambda0) (power law when asked)
     T mu = fp.mu;
     if constexpr (PL)
-        if (fp.viscous && fp.mu_power != T(0)) mu *= pow_t(T(0.5) / lam0 * fp.iT_ref, fp.mu_power);
+        if (fp.viscous && fp.mu_power != T(0)) mu *= pow_t(h0 * fp.iT_ref, fp.mu_power);
     const T tau = fp.viscous ? mu / p0 + fp.tau_C * jump : fp.tau_eps * dt + fp.tau_C * jump;
     T M0[5], Ma[5], MA[5];
 #pragma unroll
@@ -421,6 +455,12 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
     }
     T Fd[2][5];
     const T itau = T(1) / tau;
+    // exp(-dt / tau) = eta^2 and 1 - exp(-dt / tau) = om (1 + eta) for eta = exp(-dt / (2 tau)), om = 1 - eta
+    T eta_h = T(0), om_h = T(0);
+    if constexpr (!SM) {
+        eta_h = exp_t(T(-0.5) * dt * itau);
+        om_h = -expm1_t(T(-0.5) * dt * itau);
+    }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const T d = s == 0 ? T(0.5) * dt : dt;
@@ -430,8 +470,8 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
             T2 = -tau * d;
             T3 = T(0.5) * d * d - tau * d;
         } else {
-            const T eta = exp_t(-d * itau);
-            const T om = -expm1_t(-d * itau);
+            const T eta = s == 0 ? eta_h : eta_h * eta_h;
+            const T om = s == 0 ? om_h : om_h * (T(1) + eta_h);
             T1 = d - tau * om;
             T2 = T(2) * tau * tau * om - tau * d * (T(1) + eta);
             T3 = T(0.5) * d * d - tau * d + tau * tau * om;

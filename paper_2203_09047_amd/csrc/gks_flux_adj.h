@@ -47,50 +47,49 @@ __host__ __device__ __forceinline__ void recur_b(const T *m, T *mb, T U, T h, T 
     }
 }
 
-// reverse of mom_common: v, w, s moments -> V, W, lambda
+// reverse of mom_common: v, w, s moments -> V, W, lambda (h = 1 / (2 lambda): dh/dlambda = -2 h^2)
 template <typename T>
-__host__ __device__ __forceinline__ void mom_common_b(const Mom<T> &M, MomB<T> &B, T V, T W, T lam, T K, T &Vb, T &Wb,
+__host__ __device__ __forceinline__ void mom_common_b(const Mom<T> &M, MomB<T> &B, T V, T W, T h, T K, T &Vb, T &Wb,
                                                       T &lamb)
 {
-    const T h = T(0.5) / lam;
     T hb = K * B.s1 + T(2) * K * (K + T(2)) * h * B.s2;
     recur_b<6>(M.v, B.v, V, h, Vb, hb);
     Vb += B.v[1];
     recur_b<6>(M.w, B.w, W, h, Wb, hb);
     Wb += B.w[1];
-    lamb += -hb * h / lam;
+    lamb += T(-2) * hb * h * h;
 }
 
 template <typename T>
-__host__ __device__ __forceinline__ void mom_full_u_b(const Mom<T> &M, MomB<T> &B, T U, T lam, T &Ub, T &lamb)
+__host__ __device__ __forceinline__ void mom_full_u_b(const Mom<T> &M, MomB<T> &B, T U, T h, T &Ub, T &lamb)
 {
-    const T h = T(0.5) / lam;
     T hb = T(0);
     recur_b<7>(M.u, B.u, U, h, Ub, hb);
     Ub += B.u[1];
-    lamb += -hb * h / lam;
+    lamb += T(-2) * hb * h * h;
 }
 
 template <typename T>
-__host__ __device__ __forceinline__ void mom_half_u_b(const Mom<T> &M, MomB<T> &B, T U, T lam, T sign, T &Ub, T &lamb)
+__host__ __device__ __forceinline__ void mom_half_u_b(const Mom<T> &M, MomB<T> &B, T U, T lam, T h, T sign, T &Ub,
+                                                      T &lamb)
 {
-    const T h = T(0.5) / lam;
     T hb = T(0);
     recur_b<7>(M.u, B.u, U, h, Ub, hb);
-    lamb += -hb * h / lam;
-    const T sl = sqrt_t(lam);
+    lamb += T(-2) * hb * h * h;
+    const T isl = sqrt_t(T(2) * h);  // 1 / sqrt(lambda)
+    const T sl = lam * isl;
     const T g = exp_t(-lam * U * U);
-    const T e = g / (T(2) * sqrt_t(T(M_PI) * lam));
+    const T ip = T(0.5 * M_2_SQRTPI);  // 1 / sqrt(pi)
+    const T e = g * (T(0.5) * ip * isl);
     // u1 = U u0 + sign e
     Ub += M.u[0] * B.u[1];
     const T u0b = B.u[0] + U * B.u[1];
     const T eb = sign * B.u[1];
     Ub += eb * e * (T(-2) * lam * U);
-    lamb += eb * e * (-U * U - T(0.5) / lam);
+    lamb += eb * e * (-U * U - h);
     // u0 = erfc(-sign sqrt(lam) U) / 2
-    const T ip = T(1) / sqrt_t(T(M_PI));
     Ub += u0b * sign * sl * g * ip;
-    lamb += u0b * sign * U * g * ip / (T(2) * sl);
+    lamb += u0b * sign * U * g * ip * (T(0.5) * isl);
 }
 
 template <typename T>
@@ -101,13 +100,14 @@ __host__ __device__ __forceinline__ T dot5(const T *a, const T *b)
 
 // reverse of slope_solve: a_b -> b_b and state cotangents (a: the forward result)
 template <typename T>
-__host__ __device__ __forceinline__ void slope_solve_b(const T b[5], T U, T V, T W, T lam, T K, const T a[5],
+__host__ __device__ __forceinline__ void slope_solve_b(const T b[5], T U, T V, T W, T lam, T h, T K, const T a[5],
                                                        const T ab_in[5], T bb[5], T &Ub, T &Vb, T &Wb, T &lamb)
 {
-    const T q = U * U + V * V + W * W + (K + T(3)) / (T(2) * lam);
+    const T iK3 = T(1) / (K + T(3));  // a constant of the launch
+    const T q = U * U + V * V + W * W + (K + T(3)) * h;
     const T R2 = b[1] - U * b[0], R3 = b[2] - V * b[0], R4 = b[3] - W * b[0];
     const T R5 = T(2) * b[4] - q * b[0];
-    const T c = T(4) * lam * lam / (K + T(3));
+    const T c = T(4) * lam * lam * iK3;
     const T X = R5 - T(2) * (U * R2 + V * R3 + W * R4);
     T ab[5] = {ab_in[0], ab_in[1], ab_in[2], ab_in[3], ab_in[4]};
     T qb = T(0), R2b = T(0), R3b = T(0), R4b = T(0), R5b = T(0), cb = T(0);
@@ -144,7 +144,7 @@ __host__ __device__ __forceinline__ void slope_solve_b(const T b[5], T U, T V, T
     Vb += T(-2) * R3 * Xb;
     R4b += T(-2) * W * Xb;
     Wb += T(-2) * R4 * Xb;
-    lamb += T(8) * lam / (K + T(3)) * cb;
+    lamb += T(8) * lam * iK3 * cb;
     // R5 = 2 b4 - q b0
     bb[4] += T(2) * R5b;
     qb += -b[0] * R5b;
@@ -163,7 +163,7 @@ __host__ __device__ __forceinline__ void slope_solve_b(const T b[5], T U, T V, T
     Ub += T(2) * U * qb;
     Vb += T(2) * V * qb;
     Wb += T(2) * W * qb;
-    lamb += -(K + T(3)) / (T(2) * lam * lam) * qb;
+    lamb += T(-2) * (K + T(3)) * h * h * qb;
 }
 
 // Reverses of the moment-matrix products.  A matrix's cotangent Qb (same symmetric layout) gathers
@@ -269,16 +269,17 @@ __host__ __device__ __forceinline__ void qmat_b(const Mom<T> &M, const Q5<T> &Qb
 template <typename T>
 __host__ __device__ __forceinline__ void to_prim_b(const T q[5], T gam, T rhob, T Ub, T Vb, T Wb, T lamb, T pb, T qb[5])
 {
-    T rho, U, V, W, lam, p;
-    to_prim(q, gam, rho, U, V, W, lam, p);
-    rhob += lamb / (T(2) * p);
-    pb += -lamb * lam / p;
+    T rho, U, V, W, lam, p, h;
+    to_prim(q, gam, rho, U, V, W, lam, p, h);
+    const T ir = T(1) / rho;
+    // lambda = rho / (2 p): d/drho = lambda / rho, d/dp = -lambda / p = -2 lambda^2 / rho
+    rhob += lamb * lam * ir;
+    pb += T(-2) * lamb * lam * lam * ir;
     qb[4] += (gam - T(1)) * pb;
     rhob += -(gam - T(1)) * pb * T(0.5) * (U * U + V * V + W * W);
     Ub += -(gam - T(1)) * pb * rho * U;
     Vb += -(gam - T(1)) * pb * rho * V;
     Wb += -(gam - T(1)) * pb * rho * W;
-    const T ir = T(1) / rho;
     qb[1] += Ub * ir;
     qb[2] += Vb * ir;
     qb[3] += Wb * ir;
@@ -339,28 +340,28 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
         for (int j = 0; j < 5; ++j) o[j] = get(slot + j);
     };
     const T K = fp.K;
-    T rho, U, V, W, lam, p;
-    to_prim(q, fp.gamma, rho, U, V, W, lam, p);
+    T rho, U, V, W, lam, p, h;
+    to_prim(q, fp.gamma, rho, U, V, W, lam, p, h);
     const T ir = T(1) / rho;
     Mom<T> M;
-    mom_common(M, V, W, lam, K);
-    mom_full_u(M, U, lam);
+    mom_common(M, V, W, h, K);
+    mom_full_u(M, U, h);
     T a[3][5], Av[5];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         T bm[5];
 #pragma unroll
         for (int j = 0; j < 5; ++j) bm[j] = dq[m][j] * ir;
-        slope_solve(bm, U, V, W, lam, K, a[m]);
+        slope_solve(bm, U, V, W, lam, h, K, a[m]);
     }
     {
         T bA[5];
         qadv<0>(M, a, bA);
 #pragma unroll
         for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
-        slope_solve(bA, U, V, W, lam, K, Av);
+        slope_solve(bA, U, V, W, lam, h, K, Av);
     }
-    mom_half_u(M, U, lam, sign);
+    mom_half_u(M, U, lam, h, sign);
 
     T rhob = T(0), Ub = T(0), Vb = T(0), Wb = T(0), lamb = T(0);
     MomB<T> B;
@@ -441,10 +442,10 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
         qmat_b<0, 0, 1>(M, Qb, B);
     }
     // half-space u moments done: their cotangents go to U and lambda, then the full set returns
-    mom_half_u_b(M, B, U, lam, sign, Ub, lamb);
+    mom_half_u_b(M, B, U, lam, h, sign, Ub, lamb);
 #pragma unroll
     for (int k = 0; k < 7; ++k) B.u[k] = T(0);
-    mom_full_u(M, U, lam);
+    mom_full_u(M, U, h);
     // Av = solve(-qadv<0>(M, a))
     {
         T bA[5];
@@ -452,7 +453,7 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
 #pragma unroll
         for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
         T bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
-        slope_solve_b(bA, U, V, W, lam, K, Av, Avb, bAb, Ub, Vb, Wb, lamb);
+        slope_solve_b(bA, U, V, W, lam, h, K, Av, Avb, bAb, Ub, Vb, Wb, lamb);
 #pragma unroll
         for (int j = 0; j < 5; ++j) bAb[j] = -bAb[j];
         qmat<1, 0, 0>(M, Q);
@@ -474,25 +475,24 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
         T bm[5], bmb[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int j = 0; j < 5; ++j) bm[j] = dq[m][j] * ir;
-        slope_solve_b(bm, U, V, W, lam, K, a[m], ab[m], bmb, Ub, Vb, Wb, lamb);
+        slope_solve_b(bm, U, V, W, lam, h, K, a[m], ab[m], bmb, Ub, Vb, Wb, lamb);
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
             dqb[m][j] += bmb[j] * ir;
             rhob += -bmb[j] * bm[j] * ir;
         }
     }
-    mom_full_u_b(M, B, U, lam, Ub, lamb);
-    mom_common_b(M, B, V, W, lam, K, Vb, Wb, lamb);
+    mom_full_u_b(M, B, U, h, Ub, lamb);
+    mom_common_b(M, B, V, W, h, K, Vb, Wb, lamb);
     to_prim_b(q, fp.gamma, rhob, Ub, Vb, Wb, lamb, get(kSlotP + side), qb);
 }
 
 // T coefficients of the time integrals over [0, d] and their derivatives in tau
+// (eta = exp(-d / tau), om = 1 - eta, itau = 1 / tau)
 template <typename T>
-__host__ __device__ __forceinline__ void tcoef(T d, T tau, T Tc[5], T dT[5])
+__host__ __device__ __forceinline__ void tcoef(T d, T tau, T itau, T eta, T om, T Tc[5], T dT[5])
 {
-    const T eta = exp_t(-d / tau);
-    const T om = -expm1_t(-d / tau);
-    const T deta = eta * d / (tau * tau);
+    const T deta = eta * d * itau * itau;
     const T dom = -deta;
     Tc[0] = d - tau * om;
     Tc[1] = T(2) * tau * tau * om - tau * d * (T(1) + eta);
@@ -522,11 +522,11 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
                                        Put put)
 {
     const T K = fp.K;
-    T r0, U0, V0, W0, lam0, p0;
-    to_prim(A.q0, fp.gamma, r0, U0, V0, W0, lam0, p0);
+    T r0, U0, V0, W0, lam0, p0, h0;
+    to_prim(A.q0, fp.gamma, r0, U0, V0, W0, lam0, p0, h0);
     Mom<T> G;
-    mom_common(G, V0, W0, lam0, K);
-    mom_full_u(G, U0, lam0);
+    mom_common(G, V0, W0, h0, K);
+    mom_full_u(G, U0, h0);
     const T ir0 = T(1) / r0;
     T ab[3][5], Av[5];
 #pragma unroll
@@ -534,7 +534,7 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         T bm[5];
 #pragma unroll
         for (int j = 0; j < 5; ++j) bm[j] = A.bab[m][j] * ir0;
-        slope_solve(bm, U0, V0, W0, lam0, K, ab[m]);
+        slope_solve(bm, U0, V0, W0, lam0, h0, K, ab[m]);
     }
     T pv[5];  // qadv<0>(G, ab): the time slope's right-hand side (negated), with PR a heat-flux moment
     qadv<0>(G, ab, pv);
@@ -542,7 +542,7 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         T bA[5];
 #pragma unroll
         for (int j = 0; j < 5; ++j) bA[j] = -pv[j];
-        slope_solve(bA, U0, V0, W0, lam0, K, Av);
+        slope_solve(bA, U0, V0, W0, lam0, h0, K, Av);
     }
     const T dp = (A.p[0] - A.p[1]) / (A.p[0] + A.p[1]);
     const T adp = dp < T(0) ? -dp : dp;
@@ -550,8 +550,13 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
     // time coefficients of F(dt/2) (s = 0) and F(dt) (s = 1), their tau derivatives, and the
     // cotangents of F(dt/2), F(dt) from out = (4 F(dt/2) - F(dt)) / dt, 4 (F(dt) - 2 F(dt/2)) / dt^2
     T Tc[2][5], dT[2][5], Fb[2][5];
-    tcoef(T(0.5) * dt, tau, Tc[0], dT[0]);
-    tcoef(dt, tau, Tc[1], dT[1]);
+    {
+        // the integration lengths dt / 2 and dt: exp(-dt / tau) = eta^2, 1 - exp(-dt / tau) = om (1 + eta)
+        const T itau = T(1) / tau;
+        const T eta = exp_t(T(-0.5) * dt * itau), om = -expm1_t(T(-0.5) * dt * itau);
+        tcoef(T(0.5) * dt, tau, itau, eta, om, Tc[0], dT[0]);
+        tcoef(dt, tau, itau, eta * eta, om * (T(1) + eta), Tc[1], dT[1]);
+    }
     const T idt = T(1) / dt;
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
@@ -677,9 +682,10 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
     {
         const T sp = A.p[0] + A.p[1];
         const T dpb = fp.tau_C * dt * sgn_t(dp) * taub;
-        put(kSlotP + 0, dpb * T(2) * A.p[1] / (sp * sp));
-        put(kSlotP + 1, -dpb * T(2) * A.p[0] / (sp * sp));
-        if (fp.viscous) p0b += -fp.mu / (p0 * p0) * taub;
+        const T isp = T(1) / sp;
+        put(kSlotP + 0, dpb * T(2) * A.p[1] * isp * isp);
+        put(kSlotP + 1, -dpb * T(2) * A.p[0] * isp * isp);
+        if (fp.viscous) p0b += -fp.mu / p0 * (T(2) * lam0 * ir0) * taub;  // 1 / p0 = 2 lambda0 / r0
     }
     // moment vectors of g0: cotangents r0 (T_k(dt/2) Fb_0 + T_k(dt) Fb_1), and r0 c_k e for W
     MomB<T> Bg;
@@ -739,7 +745,7 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         T bA[5], bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int j = 0; j < 5; ++j) bA[j] = -pv[j];
-        slope_solve_b(bA, U0, V0, W0, lam0, K, Av, Avb, bAb, U0b, V0b, W0b, lam0b);
+        slope_solve_b(bA, U0, V0, W0, lam0, h0, K, Av, Avb, bAb, U0b, V0b, W0b, lam0b);
 #pragma unroll
         for (int j = 0; j < 5; ++j) pvb[j] -= bAb[j];
     }
@@ -760,15 +766,15 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         T bm[5], bmb[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int j = 0; j < 5; ++j) bm[j] = A.bab[m][j] * ir0;
-        slope_solve_b(bm, U0, V0, W0, lam0, K, ab[m], abb[m], bmb, U0b, V0b, W0b, lam0b);
+        slope_solve_b(bm, U0, V0, W0, lam0, h0, K, ab[m], abb[m], bmb, U0b, V0b, W0b, lam0b);
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
             put(kSlotBab + 5 * m + j, bmb[j] * ir0);
             r0b += -bmb[j] * bm[j] * ir0;
         }
     }
-    mom_full_u_b(G, Bg, U0, lam0, U0b, lam0b);
-    mom_common_b(G, Bg, V0, W0, lam0, K, V0b, W0b, lam0b);
+    mom_full_u_b(G, Bg, U0, h0, U0b, lam0b);
+    mom_common_b(G, Bg, V0, W0, h0, K, V0b, W0b, lam0b);
     // g_0's own conserved variables, plus (PR) their appearance in W with T_4
     T q0b[5];
     {
