@@ -237,6 +237,36 @@ __host__ __device__ __forceinline__ void qadv(const Mom<T> &M, const T a[3][5], 
     qmul_add(Q, a[2], o);
 }
 
+// (1/rho) sum_m dF_m/dn_m: the divergence of the Euler fluxes F_m along the frame's axes from the
+// derivatives dq[m] of the conserved variables (E = q[4]; gam = (K + 5) / (K + 3)).  For a Maxwellian
+// it equals qadv<0> of the slopes <psi psi^T> a_m = dq[m] / rho, since <u_m psi dg/dn_m> = dF_m/dn_m:
+// the right-hand side of the compatibility condition that gives the time slope, at a fraction of
+// the moment-matrix cost.
+template <typename T>
+__host__ __device__ __forceinline__ void euler_div(T rho, T ir, T U, T V, T W, T p, T E, T gam, const T dq[3][5], T o[5])
+{
+    const T u[3] = {U, V, W};
+    const T g1 = gam - T(1);
+    const T k2 = T(0.5) * (U * U + V * V + W * W);
+    const T H = E + p;
+    T f[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const T *d = dq[m];
+        T du[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) du[k] = (d[1 + k] - u[k] * d[0]) * ir;
+        const T dp = g1 * (d[4] - (U * d[1] + V * d[2] + W * d[3]) + k2 * d[0]);
+        f[0] += d[1 + m];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) f[1 + k] += d[1 + m] * u[k] + rho * u[m] * du[k];
+        f[1 + m] += dp;
+        f[4] += du[m] * H + u[m] * (d[4] + dp);
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) o[j] = f[j] * ir;
+}
+
 // Closed-form solution of <psi psi^T> a = b for a Maxwellian (U, V, W, lambda).
 template <typename T>
 __host__ __device__ __forceinline__ void slope_solve(const T b[5], T U, T V, T W, T lam, T h, T K, T a[5])
@@ -321,7 +351,6 @@ __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5
     if (!ok) return false;
     Mom<T> M;
     mom_common(M, V, W, h, K);
-    if constexpr (!SM) mom_full_u(M, U, h);
     // spatial slopes <a_m> = dQ/dn_m / rho, time slope from <a_1 u + a_2 v + a_3 w + A> = 0
     T a[3][5], Ab[5];
     const T ir = T(1) / rho;
@@ -334,12 +363,12 @@ __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5
     }
     if constexpr (!SM) {
         T b[5];
-        qadv<0>(M, a, b);
+        euler_div(rho, ir, U, V, W, p, q[4], fp.gamma, dq, b);
 #pragma unroll
         for (int j = 0; j < 5; ++j) b[j] = -b[j];
         slope_solve(b, U, V, W, lam, h, K, Ab);
     }
-    // half-space moments of u replace the full ones; each moment matrix serves every slope
+    // the half-space moments of u; each moment matrix serves every slope
     mom_half_u(M, U, lam, h, sign);
     T t[5];
     Q5<T> Q;
@@ -407,15 +436,10 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
     }
     // qadv<0>(G, ab): the time slope's right-hand side (negated) and, with PR, a heat-flux moment
     T pv[5];
+    euler_div(r0, ir0, U0, V0, W0, p0, A.q0[4], fp.gamma, A.bab, pv);
     Q5<T> Q1;  // <u psi psi^T> of g_0
     qmat<1, 0, 0>(G, Q1);
     {
-        Q5<T> Q;
-        qmul(Q1, ab[0], pv);
-        qmat<0, 1, 0>(G, Q);
-        qmul_add(Q, ab[1], pv);
-        qmat<0, 0, 1>(G, Q);
-        qmul_add(Q, ab[2], pv);
         T b[5];
 #pragma unroll
         for (int j = 0; j < 5; ++j) b[j] = -pv[j];

@@ -265,6 +265,81 @@ __host__ __device__ __forceinline__ void qmat_b(const Mom<T> &M, const Q5<T> &Qb
     B.w[n + 4] += b04 * v[0];
 }
 
+// reverse of euler_div (o: its forward result): o_b -> cotangents of rho, U, V, W, p, E and dq
+// (accumulated).  The per-direction intermediates are formed again in another association than the
+// forward's, so that the compiler does not keep the forward's alive until here.
+template <typename T>
+__host__ __device__ __forceinline__ void euler_div_b(T rho, T ir, T U, T V, T W, T p, T E, T gam, const T dq[3][5],
+                                                     const T o[5], const T ob[5], T &rhob, T &Ub, T &Vb, T &Wb,
+                                                     T &pb, T &Eb, T dqb[3][5])
+{
+    const T u[3] = {U, V, W};
+    const T g1 = gam - T(1);
+    const T k2 = T(0.5) * (U * U + V * V + W * W);
+    const T H = E + p;
+    T fb[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) fb[j] = ob[j] * ir;
+    // o = f / rho: the cotangent of 1 / rho is ob . f = rho (ob . o)
+    T irb = rho * (ob[0] * o[0] + ob[1] * o[1] + ob[2] * o[2] + ob[3] * o[3] + ob[4] * o[4]);
+    T ub[3] = {T(0), T(0), T(0)}, Hb = T(0), k2b = T(0);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const T *d = dq[m];
+        T *db = dqb[m];
+        const T d0i = d[0] * ir;
+        T du[3], dub[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) du[k] = d[1 + k] * ir - u[k] * d0i;
+        const T dp = g1 * (d[4] + k2 * d[0] - (U * d[1] + V * d[2] + W * d[3]));
+        // f4 += du_m H + u_m (d4 + dp)
+        dub[0] = dub[1] = dub[2] = T(0);
+        dub[m] += fb[4] * H;
+        Hb += fb[4] * du[m];
+        ub[m] += fb[4] * (d[4] + dp);
+        db[4] += fb[4] * u[m];
+        T dpb = fb[4] * u[m];
+        // f_{1+m} += dp
+        dpb += fb[1 + m];
+        // f_{1+k} += d_{1+m} u_k + rho u_m du_k
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            db[1 + m] += fb[1 + k] * u[k];
+            ub[k] += fb[1 + k] * d[1 + m];
+            rhob += fb[1 + k] * u[m] * du[k];
+            ub[m] += fb[1 + k] * rho * du[k];
+            dub[k] += fb[1 + k] * rho * u[m];
+        }
+        // f0 += d_{1+m}
+        db[1 + m] += fb[0];
+        // dp = g1 (d4 - u . d_{1..3} + k2 d0)
+        db[4] += g1 * dpb;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            ub[k] += -g1 * dpb * d[1 + k];
+            db[1 + k] += -g1 * dpb * u[k];
+        }
+        k2b += g1 * dpb * d[0];
+        db[0] += g1 * dpb * k2;
+        // du_k = (d_{1+k} - u_k d0) / rho
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            db[1 + k] += dub[k] * ir;
+            ub[k] += -dub[k] * d0i;
+            db[0] += -dub[k] * u[k] * ir;
+            irb += dub[k] * du[k] * rho;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ub[k] += k2b * u[k];
+    Eb += Hb;
+    pb += Hb;
+    rhob += -irb * ir * ir;
+    Ub += ub[0];
+    Vb += ub[1];
+    Wb += ub[2];
+}
+
 // reverse of to_prim
 template <typename T>
 __host__ __device__ __forceinline__ void to_prim_b(const T q[5], T gam, T rhob, T Ub, T Vb, T Wb, T lamb, T pb, T qb[5])
@@ -345,7 +420,6 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
     const T ir = T(1) / rho;
     Mom<T> M;
     mom_common(M, V, W, h, K);
-    mom_full_u(M, U, h);
     T a[3][5], Av[5];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -356,7 +430,7 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
     }
     {
         T bA[5];
-        qadv<0>(M, a, bA);
+        euler_div(rho, ir, U, V, W, p, q[4], fp.gamma, dq, bA);
 #pragma unroll
         for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
         slope_solve(bA, U, V, W, lam, h, K, Av);
@@ -441,34 +515,10 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
         rhob += ir * q5_dot(Q, Qb);
         qmat_b<0, 0, 1>(M, Qb, B);
     }
-    // half-space u moments done: their cotangents go to U and lambda, then the full set returns
+    // half-space u moments done: their cotangents go to U and lambda, the v, w and internal
+    // moments' to V, W and lambda (the time slope's right-hand side uses no moments)
     mom_half_u_b(M, B, U, lam, h, sign, Ub, lamb);
-#pragma unroll
-    for (int k = 0; k < 7; ++k) B.u[k] = T(0);
-    mom_full_u(M, U, h);
-    // Av = solve(-qadv<0>(M, a))
-    {
-        T bA[5];
-        qadv<0>(M, a, bA);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) bA[j] = -bA[j];
-        T bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
-        slope_solve_b(bA, U, V, W, lam, h, K, Av, Avb, bAb, Ub, Vb, Wb, lamb);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) bAb[j] = -bAb[j];
-        qmat<1, 0, 0>(M, Q);
-        q5_zero(Qb);
-        qmul_b(Q, a[0], bAb, Qb, ab[0]);
-        qmat_b<1, 0, 0>(M, Qb, B);
-        qmat<0, 1, 0>(M, Q);
-        q5_zero(Qb);
-        qmul_b(Q, a[1], bAb, Qb, ab[1]);
-        qmat_b<0, 1, 0>(M, Qb, B);
-        qmat<0, 0, 1>(M, Q);
-        q5_zero(Qb);
-        qmul_b(Q, a[2], bAb, Qb, ab[2]);
-        qmat_b<0, 0, 1>(M, Qb, B);
-    }
+    mom_common_b(M, B, V, W, h, K, Vb, Wb, lamb);
     // a[m] = solve(dq[m] / rho)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -482,9 +532,21 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
             rhob += -bmb[j] * bm[j] * ir;
         }
     }
-    mom_full_u_b(M, B, U, h, Ub, lamb);
-    mom_common_b(M, B, V, W, h, K, Vb, Wb, lamb);
-    to_prim_b(q, fp.gamma, rhob, Ub, Vb, Wb, lamb, get(kSlotP + side), qb);
+    // Av = solve(-euler_div(q, dq))
+    T pb = get(kSlotP + side), Eb = T(0);
+    {
+        T ed[5], bA[5];
+        euler_div(rho, ir, U, V, W, p, q[4], fp.gamma, dq, ed);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) bA[j] = -ed[j];
+        T bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
+        slope_solve_b(bA, U, V, W, lam, h, K, Av, Avb, bAb, Ub, Vb, Wb, lamb);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) bAb[j] = -bAb[j];
+        euler_div_b(rho, ir, U, V, W, p, q[4], fp.gamma, dq, ed, bAb, rhob, Ub, Vb, Wb, pb, Eb, dqb);
+    }
+    to_prim_b(q, fp.gamma, rhob, Ub, Vb, Wb, lamb, pb, qb);
+    qb[4] += Eb;
 }
 
 // T coefficients of the time integrals over [0, d] and their derivatives in tau
@@ -537,7 +599,7 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         slope_solve(bm, U0, V0, W0, lam0, h0, K, ab[m]);
     }
     T pv[5];  // qadv<0>(G, ab): the time slope's right-hand side (negated), with PR a heat-flux moment
-    qadv<0>(G, ab, pv);
+    euler_div(r0, ir0, U0, V0, W0, p0, A.q0[4], fp.gamma, A.bab, pv);
     {
         T bA[5];
 #pragma unroll
@@ -696,8 +758,8 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         Avb[j] = T(0);
         abb[0][j] = abb[1][j] = abb[2][j] = T(0);
     }
-    // g_0's moment matrices, each reversed once: <u psi psi^T> serves <u psi> (ob0), <u (Av . psi) psi>
-    // (ob2) and the a[0] term of qadv<0>(G, ab) (pvb: the time slope's and, with PR, W's cotangent)
+    // g_0's moment matrices, each reversed once: <u psi psi^T> serves <u psi> (ob0) and
+    // <u (Av . psi) psi> (ob2); pvb is the cotangent of pv (the time slope's and, with PR, W's)
     T ob0[5], ob1[5], ob2[5], pvb[5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
@@ -749,17 +811,14 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
 #pragma unroll
         for (int j = 0; j < 5; ++j) pvb[j] -= bAb[j];
     }
-    // pv = qadv<0>(G, ab)
-    qmul_b(Q1, ab[0], pvb, Qb1, abb[0]);
     qmat_b<1, 0, 0>(G, Qb1, Bg);
-    qmat<0, 1, 0>(G, Q);
-    q5_zero(Qb);
-    qmul_b(Q, ab[1], pvb, Qb, abb[1]);
-    qmat_b<0, 1, 0>(G, Qb, Bg);
-    qmat<0, 0, 1>(G, Q);
-    q5_zero(Qb);
-    qmul_b(Q, ab[2], pvb, Qb, abb[2]);
-    qmat_b<0, 0, 1>(G, Qb, Bg);
+    // pv = euler_div(q0, bab): its cotangents of bab join the slopes' below
+    T E0b = T(0), babb[3][5];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) babb[m][j] = T(0);
+    euler_div_b(r0, ir0, U0, V0, W0, p0, A.q0[4], fp.gamma, A.bab, pv, pvb, r0b, U0b, V0b, W0b, p0b, E0b, babb);
     // ab[m] = solve(bab[m] / r0)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -769,7 +828,7 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         slope_solve_b(bm, U0, V0, W0, lam0, h0, K, ab[m], abb[m], bmb, U0b, V0b, W0b, lam0b);
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            put(kSlotBab + 5 * m + j, bmb[j] * ir0);
+            put(kSlotBab + 5 * m + j, bmb[j] * ir0 + babb[m][j]);
             r0b += -bmb[j] * bm[j] * ir0;
         }
     }
@@ -783,6 +842,7 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         for (int j = 0; j < 5; ++j) q0b[j] = c3 * e[j];
     }
     to_prim_b(A.q0, fp.gamma, r0b, U0b, V0b, W0b, lam0b, p0b, q0b);
+    q0b[4] += E0b;
 #pragma unroll
     for (int j = 0; j < 5; ++j) put(kSlotQ0 + j, q0b[j]);
 }
