@@ -237,7 +237,24 @@ __host__ __device__ __forceinline__ void qadv(const Mom<T> &M, const T a[3][5], 
     qmul_add(Q, a[2], o);
 }
 
-// (1/rho) sum_m dF_m/dn_m: the divergence of the Euler fluxes F_m along the frame's axes from the
+// F_m'(W) d added to f: the Jacobian of the Euler flux F_m along the frame's axis m applied to an
+// increment d of the conserved variables (u = (U, V, W), g1 = gamma - 1, k2 = |u|^2 / 2, H = E + p).
+template <typename T>
+__host__ __device__ __forceinline__ void euler_jac_add(int m, T rho, T ir, const T u[3], T g1, T k2, T H, const T d[5],
+                                                       T f[5])
+{
+    T du[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) du[k] = (d[1 + k] - u[k] * d[0]) * ir;
+    const T dp = g1 * (d[4] - (u[0] * d[1] + u[1] * d[2] + u[2] * d[3]) + k2 * d[0]);
+    f[0] += d[1 + m];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[1 + k] += d[1 + m] * u[k] + rho * u[m] * du[k];
+    f[1 + m] += dp;
+    f[4] += du[m] * H + u[m] * (d[4] + dp);
+}
+
+// (1/rho) sum_m dF_m/dn_m: the divergence of the Euler fluxes along the frame's axes from the
 // derivatives dq[m] of the conserved variables (E = q[4]; gam = (K + 5) / (K + 3)).  For a Maxwellian
 // it equals qadv<0> of the slopes <psi psi^T> a_m = dq[m] / rho, since <u_m psi dg/dn_m> = dF_m/dn_m:
 // the right-hand side of the compatibility condition that gives the time slope, at a fraction of
@@ -246,23 +263,10 @@ template <typename T>
 __host__ __device__ __forceinline__ void euler_div(T rho, T ir, T U, T V, T W, T p, T E, T gam, const T dq[3][5], T o[5])
 {
     const T u[3] = {U, V, W};
-    const T g1 = gam - T(1);
-    const T k2 = T(0.5) * (U * U + V * V + W * W);
-    const T H = E + p;
     T f[5] = {T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        const T *d = dq[m];
-        T du[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) du[k] = (d[1 + k] - u[k] * d[0]) * ir;
-        const T dp = g1 * (d[4] - (U * d[1] + V * d[2] + W * d[3]) + k2 * d[0]);
-        f[0] += d[1 + m];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) f[1 + k] += d[1 + m] * u[k] + rho * u[m] * du[k];
-        f[1 + m] += dp;
-        f[4] += du[m] * H + u[m] * (d[4] + dp);
-    }
+    for (int m = 0; m < 3; ++m)
+        euler_jac_add(m, rho, ir, u, gam - T(1), T(0.5) * (U * U + V * V + W * W), E + p, dq[m], f);
 #pragma unroll
     for (int j = 0; j < 5; ++j) o[j] = f[j] * ir;
 }
@@ -425,7 +429,7 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
     Mom<T> G;
     mom_common(G, V0, W0, h0, K);
     mom_full_u(G, U0, h0);
-    T ab[3][5], Ab[5];
+    T ab[3][5];
     const T ir0 = T(1) / r0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -434,17 +438,9 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
         for (int j = 0; j < 5; ++j) b[j] = A.bab[m][j] * ir0;
         slope_solve(b, U0, V0, W0, lam0, h0, K, ab[m]);
     }
-    // qadv<0>(G, ab): the time slope's right-hand side (negated) and, with PR, a heat-flux moment
+    // qadv<0>(G, ab): the negated right-hand side of g_0's time slope Ab (<psi psi^T> Ab = -pv)
     T pv[5];
     euler_div(r0, ir0, U0, V0, W0, p0, A.q0[4], fp.gamma, A.bab, pv);
-    Q5<T> Q1;  // <u psi psi^T> of g_0
-    qmat<1, 0, 0>(G, Q1);
-    {
-        T b[5];
-#pragma unroll
-        for (int j = 0; j < 5; ++j) b[j] = -pv[j];
-        slope_solve(b, U0, V0, W0, lam0, h0, K, Ab);
-    }
     // collision time
     const T dp = (A.p[0] - A.p[1]) / (A.p[0] + A.p[1]);
     const T jump = (dp < T(0) ? -dp : dp) * dt;
@@ -453,29 +449,32 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
     if constexpr (PL)
         if (fp.viscous && fp.mu_power != T(0)) mu *= pow_t(h0 * fp.iT_ref, fp.mu_power);
     const T tau = fp.viscous ? mu / p0 + fp.tau_C * jump : fp.tau_eps * dt + fp.tau_C * jump;
-    T M0[5], Ma[5], MA[5];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) M0[j] = Q1.e[j];
-    qmul(Q1, Ab, MA);
+    // <u psi> of g_0 is its Euler flux along n1 over r0, and <u (Ab . psi) psi> that flux's Jacobian
+    // applied to <psi psi^T> Ab = -pv (d/dt of <u psi g_0>); with PR, <psi> = W_0 / r0 and
+    // <(Ab . psi) psi> = -pv
+    T M0[5], Ma[5], MA[5] = {T(0), T(0), T(0), T(0), T(0)};
     {
-        Q5<T> Q;
-        qmat<2, 0, 0>(G, Q);
-        qmul(Q, ab[0], Ma);
-        qmat<1, 1, 0>(G, Q);
-        qmul_add(Q, ab[1], Ma);
-        qmat<1, 0, 1>(G, Q);
-        qmul_add(Q, ab[2], Ma);
+        const T E0 = A.q0[4];
+        M0[0] = U0;
+        M0[1] = U0 * U0 + h0;
+        M0[2] = U0 * V0;
+        M0[3] = U0 * W0;
+        M0[4] = U0 * (E0 * ir0 + h0);
+        const T u0[3] = {U0, V0, W0};
+        T npv[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) npv[j] = -pv[j];
+        euler_jac_add(0, r0, ir0, u0, fp.gamma - T(1), T(0.5) * (U0 * U0 + V0 * V0 + W0 * W0), E0 + p0, npv, MA);
     }
+    qadv<1>(G, ab, Ma);
     T W0m[PR ? 5 : 1], Wam[PR ? 5 : 1], WAm[PR ? 5 : 1];
     if constexpr (PR) {
-        Q5<T> Q;
-        qmat<0, 0, 0>(G, Q);
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            W0m[j] = Q.e[j];
+            W0m[j] = A.q0[j] * ir0;
             Wam[j] = pv[j];
+            WAm[j] = -pv[j];
         }
-        qmul(Q, Ab, WAm);
     }
     T Fd[2][5];
     const T itau = T(1) / tau;

@@ -265,18 +265,78 @@ __host__ __device__ __forceinline__ void qmat_b(const Mom<T> &M, const Q5<T> &Qb
     B.w[n + 4] += b04 * v[0];
 }
 
+// reverse of euler_jac_add along axis m: fb (the cotangent of f) -> cotangents of d (accumulated
+// into db) and of rho, u, H, k2 and 1/rho.  The intermediates are formed again in another
+// association than the forward's, so that the compiler does not keep the forward's alive until here.
+template <typename T>
+__host__ __device__ __forceinline__ void euler_jac_add_b(int m, T rho, T ir, const T u[3], T g1, T k2, T H,
+                                                         const T d[5], const T fb[5], T db[5], T &rhob, T ub[3],
+                                                         T &Hb, T &k2b, T &irb)
+{
+    const T d0i = d[0] * ir;
+    T du[3], dub[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) du[k] = d[1 + k] * ir - u[k] * d0i;
+    const T dp = g1 * (d[4] + k2 * d[0] - (u[0] * d[1] + u[1] * d[2] + u[2] * d[3]));
+    // f4 += du_m H + u_m (d4 + dp)
+    dub[m] += fb[4] * H;
+    Hb += fb[4] * du[m];
+    ub[m] += fb[4] * (d[4] + dp);
+    db[4] += fb[4] * u[m];
+    T dpb = fb[4] * u[m];
+    // f_{1+m} += dp
+    dpb += fb[1 + m];
+    // f_{1+k} += d_{1+m} u_k + rho u_m du_k
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        db[1 + m] += fb[1 + k] * u[k];
+        ub[k] += fb[1 + k] * d[1 + m];
+        rhob += fb[1 + k] * u[m] * du[k];
+        ub[m] += fb[1 + k] * rho * du[k];
+        dub[k] += fb[1 + k] * rho * u[m];
+    }
+    // f0 += d_{1+m}
+    db[1 + m] += fb[0];
+    // dp = g1 (d4 - u . d_{1..3} + k2 d0)
+    db[4] += g1 * dpb;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        ub[k] += -g1 * dpb * d[1 + k];
+        db[1 + k] += -g1 * dpb * u[k];
+    }
+    k2b += g1 * dpb * d[0];
+    db[0] += g1 * dpb * k2;
+    // du_k = (d_{1+k} - u_k d0) / rho
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        db[1 + k] += dub[k] * ir;
+        ub[k] += -dub[k] * d0i;
+        db[0] += -dub[k] * u[k] * ir;
+        irb += dub[k] * du[k] * rho;
+    }
+}
+
+// the cotangents of u, H = E + p, k2 = |u|^2 / 2 and 1/rho to those of U, V, W, E, p and rho
+template <typename T>
+__host__ __device__ __forceinline__ void euler_state_b(T ir, const T u[3], const T ub[3], T Hb, T k2b, T irb, T &rhob,
+                                                       T &Ub, T &Vb, T &Wb, T &pb, T &Eb)
+{
+    Ub += ub[0] + k2b * u[0];
+    Vb += ub[1] + k2b * u[1];
+    Wb += ub[2] + k2b * u[2];
+    Eb += Hb;
+    pb += Hb;
+    rhob += -irb * ir * ir;
+}
+
 // reverse of euler_div (o: its forward result): o_b -> cotangents of rho, U, V, W, p, E and dq
-// (accumulated).  The per-direction intermediates are formed again in another association than the
-// forward's, so that the compiler does not keep the forward's alive until here.
+// (accumulated)
 template <typename T>
 __host__ __device__ __forceinline__ void euler_div_b(T rho, T ir, T U, T V, T W, T p, T E, T gam, const T dq[3][5],
                                                      const T o[5], const T ob[5], T &rhob, T &Ub, T &Vb, T &Wb,
                                                      T &pb, T &Eb, T dqb[3][5])
 {
     const T u[3] = {U, V, W};
-    const T g1 = gam - T(1);
-    const T k2 = T(0.5) * (U * U + V * V + W * W);
-    const T H = E + p;
     T fb[5];
 #pragma unroll
     for (int j = 0; j < 5; ++j) fb[j] = ob[j] * ir;
@@ -284,60 +344,10 @@ __host__ __device__ __forceinline__ void euler_div_b(T rho, T ir, T U, T V, T W,
     T irb = rho * (ob[0] * o[0] + ob[1] * o[1] + ob[2] * o[2] + ob[3] * o[3] + ob[4] * o[4]);
     T ub[3] = {T(0), T(0), T(0)}, Hb = T(0), k2b = T(0);
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        const T *d = dq[m];
-        T *db = dqb[m];
-        const T d0i = d[0] * ir;
-        T du[3], dub[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) du[k] = d[1 + k] * ir - u[k] * d0i;
-        const T dp = g1 * (d[4] + k2 * d[0] - (U * d[1] + V * d[2] + W * d[3]));
-        // f4 += du_m H + u_m (d4 + dp)
-        dub[0] = dub[1] = dub[2] = T(0);
-        dub[m] += fb[4] * H;
-        Hb += fb[4] * du[m];
-        ub[m] += fb[4] * (d[4] + dp);
-        db[4] += fb[4] * u[m];
-        T dpb = fb[4] * u[m];
-        // f_{1+m} += dp
-        dpb += fb[1 + m];
-        // f_{1+k} += d_{1+m} u_k + rho u_m du_k
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            db[1 + m] += fb[1 + k] * u[k];
-            ub[k] += fb[1 + k] * d[1 + m];
-            rhob += fb[1 + k] * u[m] * du[k];
-            ub[m] += fb[1 + k] * rho * du[k];
-            dub[k] += fb[1 + k] * rho * u[m];
-        }
-        // f0 += d_{1+m}
-        db[1 + m] += fb[0];
-        // dp = g1 (d4 - u . d_{1..3} + k2 d0)
-        db[4] += g1 * dpb;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            ub[k] += -g1 * dpb * d[1 + k];
-            db[1 + k] += -g1 * dpb * u[k];
-        }
-        k2b += g1 * dpb * d[0];
-        db[0] += g1 * dpb * k2;
-        // du_k = (d_{1+k} - u_k d0) / rho
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            db[1 + k] += dub[k] * ir;
-            ub[k] += -dub[k] * d0i;
-            db[0] += -dub[k] * u[k] * ir;
-            irb += dub[k] * du[k] * rho;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) ub[k] += k2b * u[k];
-    Eb += Hb;
-    pb += Hb;
-    rhob += -irb * ir * ir;
-    Ub += ub[0];
-    Vb += ub[1];
-    Wb += ub[2];
+    for (int m = 0; m < 3; ++m)
+        euler_jac_add_b(m, rho, ir, u, gam - T(1), T(0.5) * (U * U + V * V + W * W), E + p, dq[m], fb, dqb[m], rhob,
+                        ub, Hb, k2b, irb);
+    euler_state_b(ir, u, ub, Hb, k2b, irb, rhob, Ub, Vb, Wb, pb, Eb);
 }
 
 // reverse of to_prim
@@ -590,7 +600,7 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
     mom_common(G, V0, W0, h0, K);
     mom_full_u(G, U0, h0);
     const T ir0 = T(1) / r0;
-    T ab[3][5], Av[5];
+    T ab[3][5];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         T bm[5];
@@ -598,14 +608,10 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         for (int j = 0; j < 5; ++j) bm[j] = A.bab[m][j] * ir0;
         slope_solve(bm, U0, V0, W0, lam0, h0, K, ab[m]);
     }
-    T pv[5];  // qadv<0>(G, ab): the time slope's right-hand side (negated), with PR a heat-flux moment
+    T pv[5];  // qadv<0>(G, ab): the negated right-hand side of g_0's time slope
     euler_div(r0, ir0, U0, V0, W0, p0, A.q0[4], fp.gamma, A.bab, pv);
-    {
-        T bA[5];
-#pragma unroll
-        for (int j = 0; j < 5; ++j) bA[j] = -pv[j];
-        slope_solve(bA, U0, V0, W0, lam0, h0, K, Av);
-    }
+    const T E0 = A.q0[4], g1 = fp.gamma - T(1);
+    const T u0[3] = {U0, V0, W0};
     const T dp = (A.p[0] - A.p[1]) / (A.p[0] + A.p[1]);
     const T adp = dp < T(0) ? -dp : dp;
     const T tau = fp.viscous ? fp.mu / p0 + fp.tau_C * adp * dt : fp.tau_eps * dt + fp.tau_C * adp * dt;
@@ -690,28 +696,36 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         }
     };
     {
+        // g_0's moment vectors as in finish_flux: <u psi> = (its Euler flux along n1) / r0,
+        // <u (Ab . psi) psi> = that flux's Jacobian applied to -pv, <u (ab . u psi) psi> = qadv<1>;
+        // with PR <psi> = q0 / r0, qadv<0> = pv and <(Ab . psi) psi> = -pv
         T X[5];
-        Q5<T> Q;
-        qmat<1, 0, 0>(G, Q);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) X[j] = Q.e[j];
+        X[0] = U0;
+        X[1] = U0 * U0 + h0;
+        X[2] = U0 * V0;
+        X[3] = U0 * W0;
+        X[4] = U0 * (E0 * ir0 + h0);
         fterm(X, 0, r0);
         r0b += Tc[0][0] * dot5(Fb[0], X) + Tc[1][0] * dot5(Fb[1], X);
-        qmul(Q, Av, X);
+        T npv[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            npv[j] = -pv[j];
+            X[j] = T(0);
+        }
+        euler_jac_add(0, r0, ir0, u0, g1, T(0.5) * U2, E0 + p0, npv, X);
         fterm(X, 2, r0);
         r0b += Tc[0][2] * dot5(Fb[0], X) + Tc[1][2] * dot5(Fb[1], X);
         qadv<1>(G, ab, X);
         fterm(X, 1, r0);
         r0b += Tc[0][1] * dot5(Fb[0], X) + Tc[1][1] * dot5(Fb[1], X);
         if constexpr (PR) {
-            qmat<0, 0, 0>(G, Q);
 #pragma unroll
-            for (int j = 0; j < 5; ++j) X[j] = Q.e[j];
+            for (int j = 0; j < 5; ++j) X[j] = A.q0[j] * ir0;
             wterm(X, 0, r0);
             r0b += (Tc[0][0] * w[0] + Tc[1][0] * w[1]) * dot5(e, X);
-            qmul(Q, Av, X);
-            wterm(X, 2, r0);
-            r0b += (Tc[0][2] * w[0] + Tc[1][2] * w[1]) * dot5(e, X);
+            wterm(npv, 2, r0);
+            r0b += (Tc[0][2] * w[0] + Tc[1][2] * w[1]) * dot5(e, npv);
             wterm(pv, 1, r0);
             r0b += (Tc[0][1] * w[0] + Tc[1][1] * w[1]) * dot5(e, pv);
         }
@@ -752,44 +766,55 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
     // moment vectors of g0: cotangents r0 (T_k(dt/2) Fb_0 + T_k(dt) Fb_1), and r0 c_k e for W
     MomB<T> Bg;
     momb_zero(Bg);
-    T abb[3][5], Avb[5];
+    T abb[3][5];
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        Avb[j] = T(0);
-        abb[0][j] = abb[1][j] = abb[2][j] = T(0);
-    }
-    // g_0's moment matrices, each reversed once: <u psi psi^T> serves <u psi> (ob0) and
-    // <u (Av . psi) psi> (ob2); pvb is the cotangent of pv (the time slope's and, with PR, W's)
-    T ob0[5], ob1[5], ob2[5], pvb[5];
+    for (int j = 0; j < 5; ++j) abb[0][j] = abb[1][j] = abb[2][j] = T(0);
+    T ob0[5], ob1[5], ob2[5], pvb[5], q0d[5], E0b = T(0);
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
         ob0[j] = r0 * (Tc[0][0] * Fb[0][j] + Tc[1][0] * Fb[1][j]);
         ob1[j] = r0 * (Tc[0][1] * Fb[0][j] + Tc[1][1] * Fb[1][j]);
         ob2[j] = r0 * (Tc[0][2] * Fb[0][j] + Tc[1][2] * Fb[1][j]);
-        pvb[j] = T(0);
+        pvb[j] = q0d[j] = T(0);
     }
-    Q5<T> Q, Qb, Q1, Qb1;
     if constexpr (PR) {
+        // W's <psi> = q0 / r0 (cotangent c0 e), qadv<0> = pv (c1 e), <(Ab . psi) psi> = -pv (c2 e)
         const T c0 = r0 * (Tc[0][0] * w[0] + Tc[1][0] * w[1]);
         const T c1 = r0 * (Tc[0][1] * w[0] + Tc[1][1] * w[1]);
         const T c2 = r0 * (Tc[0][2] * w[0] + Tc[1][2] * w[1]);
-        T o2[5];
+        T sq = T(0);
 #pragma unroll
         for (int j = 0; j < 5; ++j) {
-            o2[j] = c2 * e[j];
-            pvb[j] = c1 * e[j];
+            pvb[j] = (c1 - c2) * e[j];
+            q0d[j] = c0 * e[j] * ir0;
+            sq += c0 * e[j] * A.q0[j];
         }
-        qmat<0, 0, 0>(G, Q);
-        q5_zero(Qb);
-        qcol0_b(c0, e, Qb);
-        qmul_b(Q, Av, o2, Qb, Avb);
-        qmat_b<0, 0, 0>(G, Qb, Bg);
+        r0b += -sq * ir0 * ir0;
     }
-    qmat<1, 0, 0>(G, Q1);
-    q5_zero(Qb1);
-    qcol0_b(T(1), ob0, Qb1);
-    qmul_b(Q1, Av, ob2, Qb1, Avb);
+    // <u psi> = (U0, U0^2 + h0, U0 V0, U0 W0, U0 (E0 / r0 + h0)), h0 = p0 / r0
+    {
+        U0b += ob0[0] + T(2) * U0 * ob0[1] + V0 * ob0[2] + W0 * ob0[3] + (E0 * ir0 + h0) * ob0[4];
+        V0b += U0 * ob0[2];
+        W0b += U0 * ob0[3];
+        const T hb = ob0[1] + U0 * ob0[4];
+        E0b += U0 * ir0 * ob0[4];
+        r0b += -U0 * E0 * ir0 * ir0 * ob0[4];
+        p0b += hb * ir0;
+        r0b += -hb * h0 * ir0;
+    }
+    // <u (Ab . psi) psi> = F_n'(W0) (-pv)
+    {
+        T npv[5], npvb[5] = {T(0), T(0), T(0), T(0), T(0)}, ub[3] = {T(0), T(0), T(0)};
+        T Hb = T(0), k2b = T(0), irb = T(0);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) npv[j] = -pv[j];
+        euler_jac_add_b(0, r0, ir0, u0, g1, T(0.5) * U2, E0 + p0, npv, ob2, npvb, r0b, ub, Hb, k2b, irb);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) pvb[j] -= npvb[j];
+        euler_state_b(ir0, u0, ub, Hb, k2b, irb, r0b, U0b, V0b, W0b, p0b, E0b);
+    }
     // qadv<1>(G, ab)
+    Q5<T> Q, Qb;
     qmat<2, 0, 0>(G, Q);
     q5_zero(Qb);
     qmul_b(Q, ab[0], ob1, Qb, abb[0]);
@@ -802,23 +827,13 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
     q5_zero(Qb);
     qmul_b(Q, ab[2], ob1, Qb, abb[2]);
     qmat_b<1, 0, 1>(G, Qb, Bg);
-    // Av = solve(-pv)
-    {
-        T bA[5], bAb[5] = {T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll
-        for (int j = 0; j < 5; ++j) bA[j] = -pv[j];
-        slope_solve_b(bA, U0, V0, W0, lam0, h0, K, Av, Avb, bAb, U0b, V0b, W0b, lam0b);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) pvb[j] -= bAb[j];
-    }
-    qmat_b<1, 0, 0>(G, Qb1, Bg);
     // pv = euler_div(q0, bab): its cotangents of bab join the slopes' below
-    T E0b = T(0), babb[3][5];
+    T babb[3][5];
 #pragma unroll
     for (int m = 0; m < 3; ++m)
 #pragma unroll
         for (int j = 0; j < 5; ++j) babb[m][j] = T(0);
-    euler_div_b(r0, ir0, U0, V0, W0, p0, A.q0[4], fp.gamma, A.bab, pv, pvb, r0b, U0b, V0b, W0b, p0b, E0b, babb);
+    euler_div_b(r0, ir0, U0, V0, W0, p0, E0, fp.gamma, A.bab, pv, pvb, r0b, U0b, V0b, W0b, p0b, E0b, babb);
     // ab[m] = solve(bab[m] / r0)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -843,6 +858,8 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
     }
     to_prim_b(A.q0, fp.gamma, r0b, U0b, V0b, W0b, lam0b, p0b, q0b);
     q0b[4] += E0b;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) q0b[j] += q0d[j];
 #pragma unroll
     for (int j = 0; j < 5; ++j) put(kSlotQ0 + j, q0b[j]);
 }
