@@ -1297,13 +1297,28 @@ __global__ void __launch_bounds__(kBlock) k_flux_adj_b(DevMesh m, const double *
 #pragma unroll
     for (int j = 0; j < 50; ++j) cb[j] = 0.0;
     side_state_b(X, Y, Z, n3, qb, dqb, cb);
+    // the quad's sums, each lane keeping the ones it stores (j = 4 r + g): an exchange with lane
+    // g ^ 1 keeps the values of j's parity, one with lane g ^ 2 those of j mod 4.  Every sum is
+    // (v0 + v1) + (v2 + v3) up to the order of the two operands of an addition: bitwise the same on
+    // whichever lane forms it, and the same as a full quad sum.
+    const bool odd = (g & 1) != 0, hi = (g & 2) != 0;
+    double h[25], k[13];
 #pragma unroll
-    for (int j = 0; j < 50; ++j) cb[j] = quad_sum(cb[j]);
+    for (int i = 0; i < 25; ++i) {
+        const double send = odd ? cb[2 * i] : cb[2 * i + 1];
+        h[i] = (odd ? cb[2 * i + 1] : cb[2 * i]) + dpp_f64<kDppQuadXor1>(send);
+    }
+#pragma unroll
+    for (int r = 0; r < 12; ++r) {
+        const double send = hi ? h[2 * r] : h[2 * r + 1];
+        k[r] = (hi ? h[2 * r + 1] : h[2 * r]) + dpp_f64<kDppQuadXor2>(send);
+    }
+    k[12] = h[24] + dpp_f64<kDppQuadXor2>(h[24]);  // j = 48 + g, stored by g < 2
     if (live) {
         double *dst = cbf + (size_t)100 * f + 50 * side;
 #pragma unroll
-        for (int j = 0; j < 50; ++j)
-            if ((j & 3) == g) dst[j] = cb[j];
+        for (int r = 0; r < 12; ++r) dst[4 * r + g] = k[r];
+        if (g < 2) dst[48 + g] = k[12];
     }
 }
 
