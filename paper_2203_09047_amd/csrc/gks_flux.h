@@ -222,6 +222,23 @@ __host__ __device__ __forceinline__ void qcol0_axpy(const Q5<T> &Q, T s, T y[5])
     y[4] += s * Q.e[4];
 }
 
+// o += <u^k x (a . psi) psi> for x = v (DIR = 2) or w (DIR = 3), from Qa = <u^k (a . psi) psi> and
+// P = <u^k psi>.  x is a Gaussian of mean X and variance h in every moment set (also the half-space
+// ones), so <x f(x)> = X <f> + h <df/dx> (Stein's identity) with d(psi)/dx = e_DIR + x e_4:
+//   o_j += X Qa_j + h (a_DIR + a_4 X) P_j,  o_DIR += h (Qa_0 + h a_4 P_0),
+//   o_4 += h (<u^k x (a . psi)> + h a_4 P_0 X),  <u^k x (a . psi)> = X Qa_0 + h P_0 (a_DIR + a_4 X).
+template <int DIR, typename T>
+__host__ __device__ __forceinline__ void stein_add(const T Qa[5], const T P[5], T X, T h, const T a[5], T o[5])
+{
+    const T c = a[DIR] + a[4] * X;
+    const T hc = h * c;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) o[j] += X * Qa[j] + hc * P[j];
+    const T ha4u = h * a[4] * P[0];
+    o[DIR] += h * (Qa[0] + ha4u);
+    o[4] += h * (X * Qa[0] + hc * P[0] + ha4u * X);
+}
+
 // <u^k (a_1 . psi u + a_2 . psi v + a_3 . psi w) psi> for the three spatial slopes a (k = 0: the
 // compatibility condition's right-hand side; k = 1: the flux) =
 // <u^(k+1) psi psi^T> a_1 + <u^k v psi psi^T> a_2 + <u^k w psi psi^T> a_3
@@ -372,43 +389,46 @@ __host__ __device__ __forceinline__ bool side_pass(const T q[5], const T dq[3][5
         for (int j = 0; j < 5; ++j) b[j] = -b[j];
         slope_solve(b, U, V, W, lam, h, K, Ab);
     }
-    // the half-space moments of u; each moment matrix serves every slope
+    // the half-space moments of u; each moment matrix serves every slope, and the v and w terms of
+    // qadv come from the <psi psi^T> and <u psi psi^T> products by Stein's identity
     mom_half_u(M, U, lam, h, sign);
-    T t[5];
+    T t[5], P0[5], t1[5], t2[5];
     Q5<T> Q;
     qmat<0, 0, 0>(M, Q);
-    qcol0_axpy(Q, rho, A.q0);
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        qmul(Q, a[m], t);
-        axpy5(A.bab[m], rho, t);
-    }
+    for (int j = 0; j < 5; ++j) P0[j] = Q.e[j];
+    axpy5(A.q0, rho, P0);
+    qmul(Q, a[0], t);
+    axpy5(A.bab[0], rho, t);
+    qmul(Q, a[1], t1);
+    axpy5(A.bab[1], rho, t1);
+    qmul(Q, a[2], t2);
+    axpy5(A.bab[2], rho, t2);
     if constexpr (SM) return true;
     if constexpr (PR) {
         qmul(Q, Ab, t);
         axpy5(A.WhA, rho, t);
     }
-    T wa[5];  // qadv<0> of the half-space set (PR)
+    T P1[5], ma[5], wa[5];  // qadv<1> and (PR) qadv<0> of the half-space set
     qmat<1, 0, 0>(M, Q);
-    qcol0_axpy(Q, rho, A.Mh);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) P1[j] = Q.e[j];
+    axpy5(A.Mh, rho, P1);
     qmul(Q, Ab, t);
     axpy5(A.MhA, rho, t);
-    if constexpr (PR) qmul(Q, a[0], wa);
-    T ma[5];  // qadv<1> of the half-space set
-    qmat<2, 0, 0>(M, Q);
-    qmul(Q, a[0], ma);
-    qmat<1, 1, 0>(M, Q);
-    qmul_add(Q, a[1], ma);
-    qmat<1, 0, 1>(M, Q);
-    qmul_add(Q, a[2], ma);
-    axpy5(A.Mha, rho, ma);
     if constexpr (PR) {
-        qmat<0, 1, 0>(M, Q);
-        qmul_add(Q, a[1], wa);
-        qmat<0, 0, 1>(M, Q);
-        qmul_add(Q, a[2], wa);
+        qmul(Q, a[0], wa);
+        stein_add<2>(t1, P0, V, h, a[1], wa);
+        stein_add<3>(t2, P0, W, h, a[2], wa);
         axpy5(A.Wha, rho, wa);
     }
+    qmul(Q, a[1], t1);
+    qmul(Q, a[2], t2);
+    qmat<2, 0, 0>(M, Q);
+    qmul(Q, a[0], ma);
+    stein_add<2>(t1, P1, V, h, a[1], ma);
+    stein_add<3>(t2, P1, W, h, a[2], ma);
+    axpy5(A.Mha, rho, ma);
     return true;
 }
 

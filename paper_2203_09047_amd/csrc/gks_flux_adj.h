@@ -458,7 +458,9 @@ __host__ __device__ void side_pass_b(const T q[5], const T dq[3][5], T sign, con
     }
     // Every half-space accumulation is rho times a moment-matrix product; the matrix's cotangent
     // gathers the rho-scaled slot cotangents of all its products, and rho's cotangent is
-    // sum(Q Qb) / rho.
+    // sum(Q Qb) / rho.  (side_pass forms the v and w terms of qadv by Stein's identity; here they
+    // keep their own matrices, the same function: reversed through Stein's identity this pass
+    // needs more registers than the lane has.)
     T g[5], s[5], sw[5];
     auto scaled = [&](int slot, T o[5]) {
         ld(slot, g);
