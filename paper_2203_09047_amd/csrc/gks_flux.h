@@ -239,6 +239,21 @@ __host__ __device__ __forceinline__ void stein_add(const T Qa[5], const T P[5], 
     o[4] += h * (X * Qa[0] + hc * P[0] + ha4u * X);
 }
 
+// o += <u^2 (a . psi) psi> of a full-space set (u Gaussian of mean U and variance h) from
+// Q1a = <u (a . psi) psi>, B = <(a . psi) psi>, P1 = <u psi>, P2 = <u^2 psi>: Stein's identity in u
+// on u (a . psi) psi_j, whose u-derivative has the extra term (a . psi) psi_j:
+//   o_j += U Q1a_j + h (B_j + [j = 1] Q1a_0 + [j = 4] s2 + a_1 P1_j + a_4 P2_j),
+//   s2 = <u^2 (a . psi)> = U Q1a_0 + h (B_0 + a_1 P1_0 + a_4 P2_0).
+template <typename T>
+__host__ __device__ __forceinline__ void stein_u2_add(const T Q1a[5], const T B[5], const T P1[5], const T P2[5], T U,
+                                                      T h, const T a[5], T o[5])
+{
+#pragma unroll
+    for (int j = 0; j < 5; ++j) o[j] += U * Q1a[j] + h * (B[j] + a[1] * P1[j] + a[4] * P2[j]);
+    o[1] += h * Q1a[0];
+    o[4] += h * (U * Q1a[0] + h * (B[0] + a[1] * P1[0] + a[4] * P2[0]));
+}
+
 // <u^k (a_1 . psi u + a_2 . psi v + a_3 . psi w) psi> for the three spatial slopes a (k = 0: the
 // compatibility condition's right-hand side; k = 1: the flux) =
 // <u^(k+1) psi psi^T> a_1 + <u^k v psi psi^T> a_2 + <u^k w psi psi^T> a_3
@@ -446,9 +461,6 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
     const T K = fp.K;
     T r0, U0, V0, W0, lam0, p0, h0;
     const bool ok = to_prim(A.q0, fp.gamma, r0, U0, V0, W0, lam0, p0, h0);
-    Mom<T> G;
-    mom_common(G, V0, W0, h0, K);
-    mom_full_u(G, U0, h0);
     T ab[3][5];
     const T ir0 = T(1) / r0;
 #pragma unroll
@@ -472,7 +484,7 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
     // <u psi> of g_0 is its Euler flux along n1 over r0, and <u (Ab . psi) psi> that flux's Jacobian
     // applied to <psi psi^T> Ab = -pv (d/dt of <u psi g_0>); with PR, <psi> = W_0 / r0 and
     // <(Ab . psi) psi> = -pv
-    T M0[5], Ma[5], MA[5] = {T(0), T(0), T(0), T(0), T(0)};
+    T M0[5], Ma[5] = {T(0), T(0), T(0), T(0), T(0)}, MA[5] = {T(0), T(0), T(0), T(0), T(0)};
     {
         const T E0 = A.q0[4];
         M0[0] = U0;
@@ -486,7 +498,30 @@ __host__ __device__ __forceinline__ bool finish_flux(const FluxAcc<T, PR> &A, T 
         for (int j = 0; j < 5; ++j) npv[j] = -pv[j];
         euler_jac_add(0, r0, ir0, u0, fp.gamma - T(1), T(0.5) * (U0 * U0 + V0 * V0 + W0 * W0), E0 + p0, npv, MA);
     }
-    qadv<1>(G, ab, Ma);
+    // <u (ab . u psi) psi> = qadv<1> of g_0 by Stein's identity in u, v and w (g_0 is Gaussian in
+    // each), from <psi psi^T> ab[m] = bab[m] / r0, <psi> = W_0 / r0, <u psi> = M0 and <u^2 psi>
+    {
+        T Pw[5], P2[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) Pw[j] = A.q0[j] * ir0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) P2[j] = U0 * M0[j] + h0 * Pw[j];
+        P2[1] += h0 * U0;
+        P2[4] += h0 * (U0 * U0 + h0);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            T B[5], Q1a[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int j = 0; j < 5; ++j) B[j] = A.bab[m][j] * ir0;
+            stein_add<1>(B, Pw, U0, h0, ab[m], Q1a);  // <u (ab[m] . psi) psi>
+            if (m == 0)
+                stein_u2_add(Q1a, B, M0, P2, U0, h0, ab[0], Ma);
+            else if (m == 1)
+                stein_add<2>(Q1a, M0, V0, h0, ab[1], Ma);
+            else
+                stein_add<3>(Q1a, M0, W0, h0, ab[2], Ma);
+        }
+    }
     T W0m[PR ? 5 : 1], Wam[PR ? 5 : 1], WAm[PR ? 5 : 1];
     if constexpr (PR) {
 #pragma unroll

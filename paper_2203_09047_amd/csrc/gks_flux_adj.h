@@ -265,6 +265,88 @@ __host__ __device__ __forceinline__ void qmat_b(const Mom<T> &M, const Q5<T> &Qb
     B.w[n + 4] += b04 * v[0];
 }
 
+// reverse of stein_add: ob (the cotangent of o) -> cotangents of Qa, P, X, h and a (accumulated);
+// od += ob . (the term stein_add adds to o)
+template <int DIR, typename T>
+__host__ __device__ __forceinline__ void stein_add_b(const T Qa[5], const T P[5], T X, T h, const T a[5], const T ob[5],
+                                                     T Qab[5], T Pb[5], T &Xb, T &hb, T ab[5], T &od)
+{
+    const T c = a[DIR] + a[4] * X;
+    const T hc = h * c;
+    const T ha4u = h * a[4] * P[0];
+    T S = T(0), R = T(0);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        S += ob[j] * P[j];
+        R += ob[j] * Qa[j];
+        Qab[j] += X * ob[j];
+        Pb[j] += hc * ob[j];
+    }
+    // o_j += X Qa_j + hc P_j
+    Xb += R;
+    T hcb = S;
+    // o_DIR += h (Qa_0 + ha4u)
+    hb += ob[DIR] * (Qa[0] + ha4u);
+    Qab[0] += h * ob[DIR];
+    T ha4ub = h * ob[DIR];
+    // o_4 += h z, z = X Qa_0 + hc P_0 + ha4u X
+    const T z = X * Qa[0] + hc * P[0] + ha4u * X;
+    od += X * R + hc * S + h * (ob[DIR] * (Qa[0] + ha4u) + ob[4] * z);
+    hb += ob[4] * z;
+    const T zb = h * ob[4];
+    Xb += zb * (Qa[0] + ha4u);
+    Qab[0] += zb * X;
+    hcb += zb * P[0];
+    Pb[0] += zb * hc;
+    ha4ub += zb * X;
+    // ha4u = h a_4 P_0, hc = h c, c = a_DIR + a_4 X
+    hb += ha4ub * a[4] * P[0] + hcb * c;
+    ab[4] += ha4ub * h * P[0];
+    Pb[0] += ha4ub * h * a[4];
+    const T cb = hcb * h;
+    ab[DIR] += cb;
+    ab[4] += cb * X;
+    Xb += cb * a[4];
+}
+
+// reverse of stein_u2_add: ob -> cotangents of Q1a, B, P1, P2, U, h and a (accumulated)
+template <typename T>
+__host__ __device__ __forceinline__ void stein_u2_add_b(const T Q1a[5], const T B[5], const T P1[5], const T P2[5], T U,
+                                                        T h, const T a[5], const T ob[5], T Q1ab[5], T Bb[5],
+                                                        T P1b[5], T P2b[5], T &Ub, T &hb, T ab[5])
+{
+    T S1 = T(0), S2 = T(0);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        Q1ab[j] += U * ob[j];
+        Bb[j] += h * ob[j];
+        P1b[j] += h * a[1] * ob[j];
+        P2b[j] += h * a[4] * ob[j];
+        Ub += ob[j] * Q1a[j];
+        hb += ob[j] * (B[j] + a[1] * P1[j] + a[4] * P2[j]);
+        S1 += ob[j] * P1[j];
+        S2 += ob[j] * P2[j];
+    }
+    ab[1] += h * S1;
+    ab[4] += h * S2;
+    // o_1 += h Q1a_0
+    hb += ob[1] * Q1a[0];
+    Q1ab[0] += h * ob[1];
+    // o_4 += h s2, s2 = U Q1a_0 + h c0, c0 = B_0 + a_1 P1_0 + a_4 P2_0
+    const T c0 = B[0] + a[1] * P1[0] + a[4] * P2[0];
+    hb += ob[4] * (U * Q1a[0] + h * c0);
+    const T s2b = h * ob[4];
+    Ub += s2b * Q1a[0];
+    Q1ab[0] += s2b * U;
+    hb += s2b * c0;
+    const T c0b = s2b * h;
+    Bb[0] += c0b;
+    ab[1] += c0b * P1[0];
+    P1b[0] += c0b * a[1];
+    ab[4] += c0b * P2[0];
+    P2b[0] += c0b * a[4];
+}
+
 // reverse of euler_jac_add along axis m: fb (the cotangent of f) -> cotangents of d (accumulated
 // into db) and of rho, u, H, k2 and 1/rho.  The intermediates are formed again in another
 // association than the forward's, so that the compiler does not keep the forward's alive until here.
@@ -598,9 +680,6 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
     const T K = fp.K;
     T r0, U0, V0, W0, lam0, p0, h0;
     to_prim(A.q0, fp.gamma, r0, U0, V0, W0, lam0, p0, h0);
-    Mom<T> G;
-    mom_common(G, V0, W0, h0, K);
-    mom_full_u(G, U0, h0);
     const T ir0 = T(1) / r0;
     T ab[3][5];
 #pragma unroll
@@ -718,7 +797,32 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         euler_jac_add(0, r0, ir0, u0, g1, T(0.5) * U2, E0 + p0, npv, X);
         fterm(X, 2, r0);
         r0b += Tc[0][2] * dot5(Fb[0], X) + Tc[1][2] * dot5(Fb[1], X);
-        qadv<1>(G, ab, X);
+        // qadv<1> of g_0 by Stein chains, as in finish_flux
+        T M0v[5] = {U0, U0 * U0 + h0, U0 * V0, U0 * W0, U0 * (E0 * ir0 + h0)};
+#pragma unroll
+        for (int j = 0; j < 5; ++j) X[j] = T(0);
+        {
+            T Pw[5], P2[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) Pw[j] = A.q0[j] * ir0;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) P2[j] = U0 * M0v[j] + h0 * Pw[j];
+            P2[1] += h0 * U0;
+            P2[4] += h0 * (U0 * U0 + h0);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                T B[5], Q1a[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+                for (int j = 0; j < 5; ++j) B[j] = A.bab[m][j] * ir0;
+                stein_add<1>(B, Pw, U0, h0, ab[m], Q1a);
+                if (m == 0)
+                    stein_u2_add(Q1a, B, M0v, P2, U0, h0, ab[0], X);
+                else if (m == 1)
+                    stein_add<2>(Q1a, M0v, V0, h0, ab[1], X);
+                else
+                    stein_add<3>(Q1a, M0v, W0, h0, ab[2], X);
+            }
+        }
         fterm(X, 1, r0);
         r0b += Tc[0][1] * dot5(Fb[0], X) + Tc[1][1] * dot5(Fb[1], X);
         if constexpr (PR) {
@@ -766,9 +870,11 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         if (fp.viscous) p0b += -fp.mu / p0 * (T(2) * lam0 * ir0) * taub;  // 1 / p0 = 2 lambda0 / r0
     }
     // moment vectors of g0: cotangents r0 (T_k(dt/2) Fb_0 + T_k(dt) Fb_1), and r0 c_k e for W
-    MomB<T> Bg;
-    momb_zero(Bg);
-    T abb[3][5];
+    T abb[3][5], babb[3][5];
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) babb[m][j] = T(0);
 #pragma unroll
     for (int j = 0; j < 5; ++j) abb[0][j] = abb[1][j] = abb[2][j] = T(0);
     T ob0[5], ob1[5], ob2[5], pvb[5], q0d[5], E0b = T(0);
@@ -793,8 +899,68 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         }
         r0b += -sq * ir0 * ir0;
     }
+    // qadv<1> of g_0 (Stein chains in u, v, w from bab / r0, W0 / r0, <u psi>, <u^2 psi>), reversed:
+    // its cotangent of <u psi> joins ob0's below
+    T M0b[5] = {T(0), T(0), T(0), T(0), T(0)};
+    {
+        const T M0v[5] = {U0, U0 * U0 + h0, U0 * V0, U0 * W0, U0 * (E0 * ir0 + h0)};
+        T Pw[5], P2[5], Pwb[5] = {T(0), T(0), T(0), T(0), T(0)}, P2b[5] = {T(0), T(0), T(0), T(0), T(0)};
+        T hb = T(0), od = T(0);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) Pw[j] = A.q0[j] * ir0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) P2[j] = U0 * M0v[j] + h0 * Pw[j];
+        P2[1] += h0 * U0;
+        P2[4] += h0 * (U0 * U0 + h0);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            T B[5], Q1a[5] = {T(0), T(0), T(0), T(0), T(0)};
+            T Q1ab[5] = {T(0), T(0), T(0), T(0), T(0)}, Bb[5] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int j = 0; j < 5; ++j) B[j] = A.bab[m][j] * ir0;
+            stein_add<1>(B, Pw, U0, h0, ab[m], Q1a);
+            if (m == 0)
+                stein_u2_add_b(Q1a, B, M0v, P2, U0, h0, ab[0], ob1, Q1ab, Bb, M0b, P2b, U0b, hb, abb[0]);
+            else if (m == 1)
+                stein_add_b<2>(Q1a, M0v, V0, h0, ab[1], ob1, Q1ab, M0b, V0b, hb, abb[1], od);
+            else
+                stein_add_b<3>(Q1a, M0v, W0, h0, ab[2], ob1, Q1ab, M0b, W0b, hb, abb[2], od);
+            stein_add_b<1>(B, Pw, U0, h0, ab[m], Q1ab, Bb, Pwb, U0b, hb, abb[m], od);
+            // B = bab[m] / r0
+            T sb = T(0);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                babb[m][j] += Bb[j] * ir0;
+                sb += Bb[j] * B[j];
+            }
+            r0b += -sb * ir0;
+        }
+        // P2_j = U0 M0_j + h0 Pw_j (+ h0 U0 at j = 1, + h0 (U0^2 + h0) at j = 4)
+        T sp = T(0);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            U0b += P2b[j] * M0v[j];
+            M0b[j] += U0 * P2b[j];
+            hb += P2b[j] * Pw[j];
+            Pwb[j] += h0 * P2b[j];
+        }
+        hb += P2b[1] * U0 + P2b[4] * (U0 * U0 + T(2) * h0);
+        U0b += P2b[1] * h0 + P2b[4] * T(2) * U0 * h0;
+        // Pw = q0 / r0
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            q0d[j] += Pwb[j] * ir0;
+            sp += Pwb[j] * Pw[j];
+        }
+        r0b += -sp * ir0;
+        // h0 = p0 / r0
+        p0b += hb * ir0;
+        r0b += -hb * h0 * ir0;
+    }
     // <u psi> = (U0, U0^2 + h0, U0 V0, U0 W0, U0 (E0 / r0 + h0)), h0 = p0 / r0
     {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) ob0[j] += M0b[j];
         U0b += ob0[0] + T(2) * U0 * ob0[1] + V0 * ob0[2] + W0 * ob0[3] + (E0 * ir0 + h0) * ob0[4];
         V0b += U0 * ob0[2];
         W0b += U0 * ob0[3];
@@ -815,26 +981,7 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
         for (int j = 0; j < 5; ++j) pvb[j] -= npvb[j];
         euler_state_b(ir0, u0, ub, Hb, k2b, irb, r0b, U0b, V0b, W0b, p0b, E0b);
     }
-    // qadv<1>(G, ab)
-    Q5<T> Q, Qb;
-    qmat<2, 0, 0>(G, Q);
-    q5_zero(Qb);
-    qmul_b(Q, ab[0], ob1, Qb, abb[0]);
-    qmat_b<2, 0, 0>(G, Qb, Bg);
-    qmat<1, 1, 0>(G, Q);
-    q5_zero(Qb);
-    qmul_b(Q, ab[1], ob1, Qb, abb[1]);
-    qmat_b<1, 1, 0>(G, Qb, Bg);
-    qmat<1, 0, 1>(G, Q);
-    q5_zero(Qb);
-    qmul_b(Q, ab[2], ob1, Qb, abb[2]);
-    qmat_b<1, 0, 1>(G, Qb, Bg);
     // pv = euler_div(q0, bab): its cotangents of bab join the slopes' below
-    T babb[3][5];
-#pragma unroll
-    for (int m = 0; m < 3; ++m)
-#pragma unroll
-        for (int j = 0; j < 5; ++j) babb[m][j] = T(0);
     euler_div_b(r0, ir0, U0, V0, W0, p0, E0, fp.gamma, A.bab, pv, pvb, r0b, U0b, V0b, W0b, p0b, E0b, babb);
     // ab[m] = solve(bab[m] / r0)
 #pragma unroll
@@ -849,8 +996,6 @@ __host__ __device__ void finish_flux_b(const FluxAcc<T, PR> &A, T dt, const Flux
             r0b += -bmb[j] * bm[j] * ir0;
         }
     }
-    mom_full_u_b(G, Bg, U0, h0, U0b, lam0b);
-    mom_common_b(G, Bg, V0, W0, h0, K, V0b, W0b, lam0b);
     // g_0's own conserved variables, plus (PR) their appearance in W with T_4
     T q0b[5];
     {
