@@ -378,10 +378,11 @@ gks_status gks_gp_flux_batch(int64_t n, const double *ql, const double *dql, con
 
 /*
  * Testing aid for the FP64 flux of periodic meshes without the fallback (the
- * flux of Section 3.2 at the Gauss points of Eq. flux-qud).  That kernel stages
- * the coefficients of the cells owning a chunk of faces in a window of up to 92
+ * flux of Section 3.2 at the Gauss points of Eq. flux-qud) and for the first
+ * kernel of its reverse in gks_adjoint_step.  Those kernels stage the
+ * coefficients of the cells owning a chunk of faces in a window of up to 92
  * consecutive cells in device shared memory (faces are sorted by owner) and
- * reads an owner beyond the window from memory directly.  cells in [0, 92]
+ * read an owner beyond the window from memory directly.  cells in [0, 92]
  * narrows the window of this mesh handle (0: every owner read directly), so
  * that tests can run the direct path; the results are bitwise the same for every
  * value.  Default 92.  GKS_EINVAL for a null handle or a value outside the range.

@@ -18,6 +18,11 @@ HIPCC_FLAGS = [
     # packed FP32 instructions stay off in every HIP build of this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
+# the kernels' source only: no loop-invariant hoisting after instruction selection.  In the flux
+# kernels' loops over chunks it lifts dozens of FP64 constants and parameter-derived values out of
+# the loop, each then held in registers (or spilled) across the whole flux evaluation.  (hipcc
+# passes -mllvm options to the host compilation as well, so the host preprocessor is compiled apart.)
+DEVICE_FLAGS = ["-mllvm", "-disable-machine-licm"]
 
 
 def hipcc() -> str:
@@ -28,10 +33,20 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I" + os.path.join(ROOT, "include"), "-o", LIB + ".tmp", *SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    inc = "-I" + os.path.join(ROOT, "include")
+    prep_o, dev_o = LIB + ".prep.o", LIB + ".dev.o"
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    steps = [
+        [hipcc(), "-O3", "-std=c++17", "-fPIC", "-fopenmp", inc, "-c", "-o", prep_o, SOURCES[1]],
+        [hipcc(), *flags, *DEVICE_FLAGS, inc, "-c", "-o", dev_o, SOURCES[0]],
+        [hipcc(), *HIPCC_FLAGS, "-o", LIB + ".tmp", dev_o, prep_o],
+    ]
+    for cmd in steps:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+    os.remove(prep_o)
+    os.remove(dev_o)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

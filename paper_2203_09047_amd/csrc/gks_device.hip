@@ -1140,98 +1140,175 @@ static size_t adj_layout(int64_t n, int64_t nf, int64_t nnz, AdjWork *w, char *b
 
 // reverse of the flux, part 1 (lane per face Gauss point): both half-space passes forward,
 // then the reverse of the interface equilibrium, its slopes, the collision time, the time
-// integrals and the rotation/weighting, down to the half-space accumulators.  Alone on its SIMD a
-// wave would wait for each load, so all cell cotangents are loaded in one group, and the
-// neighbour's coefficients travel from memory into shared memory (global_load_lds, 16 B per lane
-// and instruction, lane L writing bytes [16 L, 16 L + 16) of each 1 KiB row) while the owner's
-// side is computed.
+// integrals and the rotation/weighting, down to the half-space accumulators.  The kernel runs
+// 1 wave/SIMD, so it walks chunks of Gauss points the way k_flux_chunked does (one block per CU,
+// the same shared-memory rows: the next chunk's neighbour coefficients and geometry per wave, an
+// owner window per block, all by global_load_lds while the current chunk computes, and the
+// neighbour's side first, as there).  A chunk's cell cotangents and volumes are requested after
+// the neighbour's side pass and used after the owner's.
 template <bool PR>
 __global__ void __launch_bounds__(kBlock) k_flux_adj_a(DevMesh m, const double *__restrict__ coeff,
                                                        const double *__restrict__ dt_dev, const double *__restrict__ lp,
                                                        const double *__restrict__ ls, double cL1, double cL2, double cD1,
-                                                       double cD2, FluxParams<double> fp, double *__restrict__ abuf)
+                                                       double cD2, FluxParams<double> fp, double *__restrict__ abuf,
+                                                       int chunk, int win_cells)
 {
-    __shared__ __attribute__((aligned(16))) char sco[(kBlock / 64) * kPfRows * 1024];
+    __shared__ __attribute__((aligned(16))) char pf[kFluxLds];
     typedef __attribute__((address_space(3))) void *lds_ptr;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const int f = t >> 2;
-    if (f >= m.nf) return;
-    const double dt = dt_dev[0];
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int nf4 = 4 * m.nf;
-    const int o = m.owner[f], nb = m.nbr[f];
     const int n = m.n;
+    const int b0 = (int)min((int64_t)blk * chunk, (int64_t)nf4), b1 = min(b0 + chunk, nf4);
+    const double dt = dt_dev[0];
     const int lane = (int)threadIdx.x & 63;
-    char *wco = sco + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) * (kPfRows * 1024);
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // wave-uniform
+    char *cbuf = pf + wv * kPfWaveBytes;
+    char *gbuf = cbuf + kPfRows * 1024;
+    char *win = pf + (kBlock / 64) * kPfWaveBytes;
+    const size_t coeff_last = (size_t)400 * n - 16;  // last 16-byte piece of the coefficients
+    auto face_of = [&](int t) { return min(t >> 2, m.nf - 1); };  // tail lanes shadow the last face
+    auto tt_of = [&](int t) { return 4 * face_of(t) + (t & 3); };
+    // the same row layout as k_flux_chunked's
+    auto prefetch = [&](int cbase, int nb) {
+        const double *src = coeff + (size_t)50 * nb;
 #pragma unroll
-    for (int k = 0; k < kPfRows; ++k)
-        __builtin_amdgcn_global_load_lds(coeff + (size_t)50 * nb + 2 * k, (lds_ptr)(wco + 1024 * k), 16, 0, 0);
-    // every load that needs only the two cell indices, in one group: cell cotangents (the second
-    // set read from lp again when there is none, unused then), volumes, geometry, the owner's
-    // coefficients
-    const double *ls_or_lp = ls ? ls : lp;
-    double po[5], pn[5], so[5], sn[5];
+        for (int k = 0; k < kPfRows; ++k) __builtin_amdgcn_global_load_lds(src + 2 * k, (lds_ptr)(cbuf + k * 1024), 16, 0, 0);
+        const int tg = tt_of(cbase + 64 * wv + 2 * (lane & 31));
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        po[c] = lp[(size_t)c * n + o];
-        pn[c] = lp[(size_t)c * n + nb];
-        so[c] = ls_or_lp[(size_t)c * n + o];
-        sn[c] = ls_or_lp[(size_t)c * n + nb];
-    }
-    const double vo = m.vol[o], vnb = m.vol[nb];
-    double geo[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) geo[q] = m.fgeo[(size_t)q * nf4 + t];
-    double cl[50];
-    load_cell(coeff + (size_t)50 * o, cl);
-    const double io = 1.0 / vo, inb = 1.0 / vnb;
-    double outb[10];
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-        double Lo = cL1 * po[c], Ln = cL1 * pn[c];
-        double Do = cD1 * po[c], Dn = cD1 * pn[c];
-        if (ls) {
-            Lo += cL2 * so[c];
-            Ln += cL2 * sn[c];
-            Do += cD2 * so[c];
-            Dn += cD2 * sn[c];
+        for (int k = 0; k < kGeoRows; ++k) {
+            const int q = min(2 * k + (lane >> 5), 8);
+            __builtin_amdgcn_global_load_lds(m.fgeo + (size_t)q * nf4 + tg, (lds_ptr)(gbuf + k * 1024), 16, 0, 0);
         }
-        outb[c] = dt * (-Lo * io + Ln * inb);
-        outb[5 + c] = dt * dt * (-Do * io + Dn * inb);
+    };
+    auto prefetch_win = [&](int w0) {
+#pragma unroll
+        for (int k = 0; k < kWinRows / 4; ++k) {
+            const int r = 4 * k + wv;
+            const size_t off = min((size_t)400 * w0 + (size_t)(1024 * r + 16 * lane), coeff_last);
+            __builtin_amdgcn_global_load_lds(reinterpret_cast<const char *>(coeff) + off, (lds_ptr)(win + r * 1024), 16, 0, 0);
+        }
+    };
+    int own = 0, nbc = 0, nb1 = 0, w0 = 0;  // this chunk's owner, neighbour and window; the next chunk's neighbour
+    if (b0 < b1) {
+        const int t0 = b0 + (int)threadIdx.x;
+        own = m.owner[face_of(t0)];
+        nbc = m.nbr[face_of(t0)];
+        w0 = m.owner[face_of(b0)];
+        prefetch(b0, nbc);
+        prefetch_win(w0);
+        nb1 = m.nbr[face_of(t0 + kBlock)];
     }
-    double n3[3][3];
-    const double area = local_frame(geo[6], geo[7], geo[8], n3);
-    FluxAcc<double, PR> A;
-    acc_zero(A);
-    {
-        double q[5], dq[3][5];
-        side_state(cl, nullptr, geo[0], geo[1], geo[2], n3, q, dq);
-        side_pass<double, PR>(q, dq, 1.0, fp, A, 0);
-    }
-    {
-        double q[5], dq[3][5], c[50];
-        // the neighbour's rows have landed (vmcnt covers the shared-memory loads)
+    const double *ls_or_lp = ls ? ls : lp;  // the second set read from lp again when there is none, unused then
+    for (int base = b0; base < b1; base += kBlock) {  // uniform over the block
+        const int t = base + (int)threadIdx.x;
+        // tail lanes (t >= b1, only in the last chunk of the grid) compute the Gauss point they
+        // shadow, bit for bit as its own lane does, and store the same values to its slots: a
+        // conditional store would keep the whole reverse pass's registers live across branches
+        const int tt = tt_of(t);
+        // the parameters pass through an empty asm each chunk, so that values derived from them are
+        // formed where they are used instead of being held in registers across the loop
+        FluxParams<double> fpl = fp;
+        double dtl = dt;
+        asm volatile("" : "+s"(fpl.gamma), "+s"(fpl.K), "+s"(fpl.mu), "+s"(fpl.Pr), "+s"(fpl.tau_eps), "+s"(fpl.tau_C),
+                     "+s"(dtl));
+        // this wave's rows and indices have landed (vmcnt covers the shared-memory loads) ...
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        // ... and so have every wave's rows of the owner window
+        __syncthreads();
+        double geo[9], cr[50];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) geo[q] = *reinterpret_cast<const double *>(gbuf + (q >> 1) * 1024 + (q & 1) * 512 + 8 * lane);
 #pragma unroll
         for (int k = 0; k < kPfRows; ++k) {
-            const double2 v = *reinterpret_cast<const double2 *>(wco + 1024 * k + 16 * lane);
-            c[2 * k] = v.x;
-            c[2 * k + 1] = v.y;
+            const double2 v = *reinterpret_cast<const double2 *>(cbuf + k * 1024 + 16 * lane);
+            cr[2 * k] = v.x;
+            cr[2 * k + 1] = v.y;
         }
-        side_state(c, nullptr, geo[3], geo[4], geo[5], n3, q, dq);
-        side_pass<double, PR>(q, dq, -1.0, fp, A, 1);
-    }
-    // rotation back and weighting: out = area R^T F
-    double Fb[10];
+        // read before the next chunk's rows overwrite them
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        const int own_n = m.owner[face_of(t + kBlock)];
+        const int w0_n = m.owner[face_of(base + kBlock)];
+        const int nb2 = m.nbr[face_of(t + 2 * kBlock)];
+        // issued unconditionally (after the last chunk they fetch the last face's rows again, unused),
+        // as in k_flux_chunked
+        prefetch(base + kBlock, nb1);
+        double n3[3][3];
+        const double area = local_frame(geo[6], geo[7], geo[8], n3);
+        FluxAcc<double, PR> A;
+        acc_zero(A);
+        {
+            double q[5], dq[3][5];
+            side_state(cr, nullptr, geo[3], geo[4], geo[5], n3, q, dq);
+            side_pass<double, PR>(q, dq, -1.0, fpl, A, 1);
+        }
+        // the chunk's cell cotangents and volumes, used after the owner's side pass
+        double po[5], pn[5], so[5], sn[5];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        Fb[5 * s] = area * outb[5 * s];
-        Fb[5 * s + 4] = area * outb[5 * s + 4];
+        for (int c = 0; c < 5; ++c) {
+            po[c] = lp[(size_t)c * n + own];
+            pn[c] = lp[(size_t)c * n + nbc];
+            so[c] = ls_or_lp[(size_t)c * n + own];
+            sn[c] = ls_or_lp[(size_t)c * n + nbc];
+        }
+        const double vo = m.vol[own], vnb = m.vol[nbc];
+        {
+            double q[5], dq[3][5], cl[50];
+            const int idx = own - w0;  // >= 0: owners do not decrease along the faces
+            // (as in k_flux_chunked: one unconditional shared-memory read, a rare overwrite from memory)
+            const char *src = win + 400 * min(idx, kWinCells - 1);
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            Fb[5 * s + 1 + k] =
-                area * (outb[5 * s + 1] * n3[k][0] + outb[5 * s + 2] * n3[k][1] + outb[5 * s + 3] * n3[k][2]);
+            for (int k = 0; k < kPfRows; ++k) {
+                const double2 v = *reinterpret_cast<const double2 *>(src + 16 * k);
+                cl[2 * k] = v.x;
+                cl[2 * k + 1] = v.y;
+            }
+            if (idx >= win_cells) {
+                const volatile double *g = coeff + (size_t)50 * own;
+#pragma unroll
+                for (int q = 0; q < 50; ++q) cl[q] = g[q];
+            }
+            // every wave has read the window before the next chunk's rows overwrite it
+            __syncthreads();
+            prefetch_win(w0_n);
+            side_state(cl, nullptr, geo[0], geo[1], geo[2], n3, q, dq);
+            side_pass<double, PR>(q, dq, 1.0, fpl, A, 0);
+        }
+        const double io = 1.0 / vo, inb = 1.0 / vnb;
+        double outb[10];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            double Lo = cL1 * po[c], Ln = cL1 * pn[c];
+            double Do = cD1 * po[c], Dn = cD1 * pn[c];
+            if (ls) {
+                Lo += cL2 * so[c];
+                Ln += cL2 * sn[c];
+                Do += cD2 * so[c];
+                Dn += cD2 * sn[c];
+            }
+            outb[c] = dtl * (-Lo * io + Ln * inb);
+            outb[5 + c] = dtl * dtl * (-Do * io + Dn * inb);
+        }
+        // rotation back and weighting: out = area R^T F
+        double Fb[10];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            Fb[5 * s] = area * outb[5 * s];
+            Fb[5 * s + 4] = area * outb[5 * s + 4];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                Fb[5 * s + 1 + k] =
+                    area * (outb[5 * s + 1] * n3[k][0] + outb[5 * s + 2] * n3[k][1] + outb[5 * s + 3] * n3[k][2]);
+        }
+        finish_flux_b<double, PR>(A, dtl, fpl, Fb, [&](int slot, double v) {
+            abuf[(size_t)slot * nf4 + tt] = v;
+        });
+        own = own_n;
+        nbc = nb1;
+        w0 = w0_n;
+        nb1 = nb2;
     }
-    finish_flux_b<double, PR>(A, dt, fp, Fb, [&](int slot, double v) { abuf[(size_t)slot * nf4 + t] = v; });
+    // no shared-memory load may still be in flight when the block's shared memory is released
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
 // reverse of the flux, part 2 (lane per face Gauss point and side): the reverse of that
@@ -2332,12 +2409,19 @@ static gks_status launch_vjp(gks_mesh *m, const double *Qe, const double *coeff_
     const FluxParams<double> fp = flux_params<double>(p);
     {
         ProfScope ps(m, GKS_K_FLUX_ADJ, st);
-        const unsigned ga = grid_for(4 * m->nf, kBlock), gb = grid_for(8 * m->nf, kBlock);
+        const unsigned gb = grid_for(8 * m->nf, kBlock);
+        // part 1 walks chunks of Gauss points, one block per compute unit (as the chunked flux)
+        const int64_t ncu = m->n_cu;
+        const int64_t nf4 = 4 * (int64_t)m->nf;
+        const int64_t per = ((nf4 + ncu * kBlock - 1) / (ncu * kBlock)) * kBlock;
+        const int na = (int)((nf4 + per - 1) / per);
         if (pr) {
-            k_flux_adj_a<true><<<ga, kBlock, 0, st>>>(m->d, coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.abuf);
+            k_flux_adj_a<true><<<na, kBlock, 0, st>>>(m->d, coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.abuf,
+                                                      (int)per, m->flux_win);
             k_flux_adj_b<true><<<gb, kBlock, 0, st>>>(m->d, coeff, fp, aw.abuf, aw.cbf);
         } else {
-            k_flux_adj_a<false><<<ga, kBlock, 0, st>>>(m->d, coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.abuf);
+            k_flux_adj_a<false><<<na, kBlock, 0, st>>>(m->d, coeff, dt_dev, lp, ls, cL1, cL2, cD1, cD2, fp, aw.abuf,
+                                                       (int)per, m->flux_win);
             k_flux_adj_b<false><<<gb, kBlock, 0, st>>>(m->d, coeff, fp, aw.abuf, aw.cbf);
         }
     }

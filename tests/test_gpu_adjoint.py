@@ -318,6 +318,51 @@ def test_adjoint_step_matches_the_oracle_tangent(gks, kind, viscous):
         assert err <= 1e-10
 
 
+@pytest.mark.parametrize("kind,N,viscous,tau_C", [("hybrid", 14, True, 1.0), ("tet", 12, False, 0.0)])
+def test_adjoint_step_over_several_chunks_and_owner_window_paths(gks, kind, N, viscous, tau_C):
+    """The flux reverse's first kernel walks chunks of 256 Gauss points per block (these lattices give
+    each block 3 and 2 chunks, the last block a ragged one) with the owners' coefficients in a
+    window of consecutive cells in shared memory and an owner beyond it read from memory: narrowing
+    the window (92 cells by default) sends every lane, or all but the first owner's, down the direct
+    path, with the same arithmetic, so the adjoint steps agree bitwise; and against the oracle's
+    tangent to 1e-10 along random directions.
+
+    The Kuhn lattice runs with tau_C = 0: its Taylor-Green field is symmetric about planes through
+    Gauss points, where the two reconstructed pressures agree up to rounding, so the sign of
+    p_l - p_r in the collision time's |p_l - p_r| term (the derivative there) is rounding noise in
+    either code; with tau_C = 1 the adjoint and the tangent differ by about 1e-3 there."""
+    import torch
+
+    print(f"case: adjoint step chunks and windows {kind} N={N} viscous={viscous} tau_C={tau_C}", flush=True)
+    mesh, Q0, host, sol = _setup(gks, kind, N, viscous, tau_C=tau_C)
+    kw = dict(viscous=viscous, mu=5e-3, Pr=0.72 if viscous else 1.0, tau_C=tau_C)
+    o, T = oracle.Oracle(mesh, oracle.params(**kw)), oracle.Tangent(mesh, oracle.params(**kw))
+    dt = o.timestep(Q0)
+    Qn = host.to_internal(Q0)
+    rng = np.random.default_rng(41)
+    lam1 = rng.standard_normal(Qn.shape)
+    Q = sol.upload(Qn)
+    Qs = torch.empty_like(Q)
+    sol.step(Q, dt, Q_star=Qs)
+    dtt = torch.tensor([dt], dtype=torch.float64, device=Q.device)
+    outs = {}
+    for cells in (92, 7, 1, 0):
+        sol.set_flux_window(cells)
+        outs[cells] = sol.adjoint_step(sol.upload(Qn), Qs, dtt, sol.upload(lam1)).cpu().numpy()
+    sol.set_flux_window(92)
+    sol.poll()
+    for cells in (7, 1, 0):
+        assert np.array_equal(outs[cells], outs[92]), cells
+    lam, lam1e = host.to_external(outs[92]), host.to_external(lam1)
+    for trial in range(2):
+        v = rng.standard_normal(Q0.shape) * np.abs(Q0).max(axis=1, keepdims=True)
+        _, Tv = T.step(Q0, v, dt)
+        want, got = float((lam1e * Tv).sum()), float((lam * v).sum())
+        err = abs(got - want) / abs(want)
+        print(trial, want, got, err, flush=True)
+        assert err <= 1e-10
+
+
 def test_rollout_gradient_matches_the_oracle_tangent(gks):
     """Checkpointed rollout (hybrid N = 5, Taylor-Green Mach 0.5, Euler, 12 steps, checkpoints every
     5, tau_C = 1): the kinetic-energy gradient along random directions against the oracle's tangent
