@@ -1399,18 +1399,21 @@ __global__ void __launch_bounds__(kBlock) k_flux_adj_b(DevMesh m, const double *
     }
 }
 
-// per cell: sum of its face sides' coefficient cotangents, F_p order
+// per cell: sum of its face sides' coefficient cotangents, F_p order; a lane per cell and pair of
+// coefficients (16-byte loads and stores: face-side records and cell rows are 400 bytes)
 __global__ void __launch_bounds__(kBlock) k_cbar_gather(DevMesh m, const double *__restrict__ cbf, double *__restrict__ cbc)
 {
     const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    const int i = t / 50, j = t - 50 * (t / 50);
+    const int i = t / 25, j = 2 * (t - 25 * (t / 25));
     if (i >= m.n) return;
-    double s = 0.0;
+    double sx = 0.0, sy = 0.0;
     for (int p = m.cf_ptr[i]; p < m.cf_ptr[i + 1]; ++p) {
         const int code = m.cf_idx[p];
-        s += cbf[(size_t)100 * (code >> 1) + 50 * (code & 1) + j];
+        const double2 v = *reinterpret_cast<const double2 *>(cbf + (size_t)100 * (code >> 1) + 50 * (code & 1) + j);
+        sx += v.x;
+        sy += v.y;
     }
-    cbc[(size_t)50 * i + j] = s;
+    *reinterpret_cast<double2 *>(cbc + (size_t)50 * i + j) = make_double2(sx, sy);
 }
 
 // reverse of the reconstruction: quad of lanes per (cell, component)
@@ -2427,7 +2430,7 @@ static gks_status launch_vjp(gks_mesh *m, const double *Qe, const double *coeff_
     }
     {
         ProfScope ps(m, GKS_K_GATHER_ADJ, st);
-        k_cbar_gather<<<grid_for(50 * m->n, kBlock), kBlock, 0, st>>>(m->d, aw.cbf, aw.cbc);
+        k_cbar_gather<<<grid_for(25 * m->n, kBlock), kBlock, 0, st>>>(m->d, aw.cbf, aw.cbc);
     }
     {
         ProfScope ps(m, GKS_K_RECONSTRUCT_ADJ, st);
